@@ -1,0 +1,161 @@
+"""Benchmark: Louvain local moving with weighted Misra-Gries sketches on one MI355X.
+
+Workload (default): Louvain, MG sketch k=8 (Algorithm 1) vs the exact table, on an
+R-MAT graph with 2^20 vertices and 16 * 2^20 undirected edge samples
+(a, b, c = 0.57, 0.19, 0.19; self-loops dropped, duplicates collapsed, weights
+uniform in [1, 8]; ~31.4M CSR entries).  One step = one whole louvain_run (every
+local-moving sweep of every pass, renumbering and aggregation) on the graph
+already resident in HBM.
+
+Prints one JSON line.  `value` = local-move edges/s of the whole job: CSR entries
+streamed by local-moving sweeps divided by the wall time of the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "local-move edges/s (sketch vs exact), batched p99 latency, equal modularity"
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def class_bytes(g, L: int, k: int):
+    """Algorithmic bytes of one level-0 sweep per kernel class (reads + writes that
+    the method must make; the second pass over a row counts as on-chip):
+      per CSR entry 12 B (index 4, weight 4, gathered C[j] 4);
+      single rows: per vertex 28 B (list 4, offsets 8, C 4, C_new 4, K 4, Sigma_d 4);
+      chunks: per chunk 16 + 8k B (owner/list 8, cstart 8, sketch 8k) + 4 B flag;
+      merge: per long row 28 B + per chunk 8k + 4 B (sketch and flag reads)."""
+    deg = np.diff(g.offsets)
+    single = deg <= L
+    e_single = int(deg[single].sum())
+    n_single = int(single.sum())
+    e_multi = int(deg[~single].sum())
+    nch = int(((deg[~single] + L - 1) // L).sum())
+    n_multi = int((~single).sum())
+    return [12 * e_single + 28 * n_single,
+            12 * e_multi + (20 + 8 * k) * nch,
+            28 * n_multi + (8 * k + 4) * nch]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--exact-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2411_02268_amd as mg
+    from paper_2411_02268_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    mg.lib()
+    t0 = time.time()
+    g = synth.rmat(scale=20, edge_factor=16, seed=2)
+    gen_s = time.time() - t0
+    print(f"[bench] graph n={g.n} nnz={g.nnz} W={g.total_weight()} generated in {gen_s:.1f}s",
+          file=sys.stderr, flush=True)
+    dg = mg.to_device(g)
+    k, L = 8, 128
+
+    def run(mode, steps, warm):
+        for _ in range(warm):
+            mg.louvain(dg, mode=mode, k=k, chunk_len=L)
+        torch.cuda.synchronize()
+        stats = []
+        a = time.perf_counter()
+        for _ in range(steps):
+            lab, st = mg.louvain(dg, mode=mode, k=k, chunk_len=L)
+            stats.append(st)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        return lab, stats, b - a
+
+    lab, stats, secs = run(mg.MODE_ALG1, args.steps, args.warmup)
+    edges = sum(s["edges_scanned"] for s in stats)
+    value = edges / secs
+    q_mg = mg.modularity(dg, lab)
+    print(f"[bench] MG k=8: {args.steps} steps in {secs:.3f}s, {value/1e9:.3f} G edges/s, "
+          f"Q={q_mg:.6f}", file=sys.stderr, flush=True)
+
+    # dominant level-0 kernel class, its live HIP-event time, algorithmic bytes
+    ms = np.zeros(3)
+    sweeps = 0
+    for s in stats:
+        ms += np.array(s["ms_l0_kernel"])
+        sweeps += s["l0_sweeps"]
+    cb = class_bytes(g, L, k)
+    dom = int(np.argmax(ms))
+    names = ["k_move_single (rows of one chunk)", "k_move_chunks (chunk sketches)",
+             "k_move_multi (merge tree + second pass)"]
+    per_launch_ms = ms[dom] / max(sweeps, 1)
+    achieved = cb[dom] / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    sweep_ms = ms.sum() / max(sweeps, 1)
+    sweep_gbs = sum(cb) / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
+
+    lab_x, stats_x, secs_x = run(mg.MODE_EXACT, args.exact_steps, 1)
+    edges_x = sum(s["edges_scanned"] for s in stats_x)
+    q_x = mg.modularity(dg, lab_x)
+    print(f"[bench] exact: {args.exact_steps} steps in {secs_x:.3f}s, "
+          f"{edges_x/secs_x/1e9:.3f} G edges/s, Q={q_x:.6f}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        threads = os.cpu_count() or 1
+        a = time.perf_counter()
+        reps, e_cpu = 0, 0
+        while reps < 3 or time.perf_counter() - a < 10.0:
+            _, est = oracle.louvain(g, mode=oracle.MODE_ALG1, k=k, chunk_len=L, threads=threads)
+            e_cpu += est.edges_scanned
+            reps += 1
+            if time.perf_counter() - a > 30.0:
+                break
+        cs = time.perf_counter() - a
+        cpu = {"value": e_cpu / cs, "unit": "edges/s", "cores": threads, "kind": "oracle",
+               "sample": f"whole MG k=8 Louvain run on the same R-MAT 2^20 graph, {reps} runs "
+                         f"({cs:.1f}s), OpenMP threads={threads}"}
+        print(f"[bench] oracle: {reps} runs in {cs:.1f}s -> {e_cpu/cs/1e9:.3f} G edges/s",
+              file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "louvain-mg-k8-rmat20", "graph": "R-MAT scale 20, edge factor 16, "
+                   "a/b/c=0.57/0.19/0.19, weights U[1,8], seed 2", "n": g.n, "nnz": g.nnz,
+                   "k": k, "chunk_len": L, "algorithm": "louvain", "parallelism": "single-gpu"},
+        "modularity": {"mg": q_mg, "exact": q_x, "ratio": q_mg / q_x if q_x else None},
+        "exact": {"value": edges_x / secs_x, "unit": "edges/s",
+                  "ms_per_step": secs_x / args.exact_steps * 1e3},
+        "stats": {"iterations": stats[-1]["iterations"], "passes": stats[-1]["passes"],
+                  "communities": stats[-1]["communities"], "ms_local_move": stats[-1]["ms_local_move"],
+                  "ms_aggregate": stats[-1]["ms_aggregate"], "ms_total": stats[-1]["ms_total"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": names[dom],
+                     "ms_per_launch": per_launch_ms, "bytes_per_launch": cb[dom],
+                     "sweep": {"ms": sweep_ms, "bytes": sum(cb), "GBs": sweep_gbs,
+                               "class_ms": (ms / max(sweeps, 1)).tolist(), "class_bytes": cb}},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

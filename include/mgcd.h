@@ -1,0 +1,163 @@
+/*
+ * mgcd.h -- C ABI of the MI355X (gfx950) community-detection library built on
+ * weighted Misra-Gries (MG) sketches (Sahu, arXiv 2411.02268).
+ *
+ * Every entry point works on an undirected graph in CSR form whose arrays live in
+ * device memory (the caller's allocation, e.g. PyTorch).  All work is ordered on
+ * the caller's HIP stream (passed as `void *`, a hipStream_t).  The library never
+ * allocates device memory in these calls: the caller passes one workspace buffer
+ * of at least mgcd_workspace_bytes() bytes.  Calls that use different workspaces
+ * and streams may run concurrently; calls that share a workspace must not.
+ *
+ * Return codes: MGCD_OK (0) or a negative error; mgcd_last_error() then returns a
+ * message (thread-local).  No C++ exception crosses this boundary.
+ */
+#ifndef MGCD_H
+#define MGCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MGCD_OK = 0,
+  MGCD_E_ARG = -1,         /* null pointer, bad size or bad parameter value        */
+  MGCD_E_GRAPH = -2,       /* the CSR failed validation (only with validate=1)      */
+  MGCD_E_OVERFLOW = -3,    /* total edge weight W >= 2^31                           */
+  MGCD_E_WORKSPACE = -4,   /* workspace smaller than mgcd_workspace_bytes()         */
+  MGCD_E_HIP = -5,         /* a HIP runtime call failed                             */
+  MGCD_E_UNSUPPORTED = -6  /* k, mode or algorithm not built                        */
+};
+
+/* Sketch update rule used by local moving, refinement and aggregation. */
+enum {
+  MGCD_MODE_EXACT = 0,  /* exact per-vertex table (the hashtable of Section 4, Fig. 1) */
+  MGCD_MODE_ALG1 = 1,   /* Algorithm 1, conditional subtraction (Appendix A.1)       */
+  MGCD_MODE_UNCOND = 2, /* unconditional subtraction (Section 4.1, first variant)    */
+  MGCD_MODE_STD = 3     /* textbook weighted MG (subtract min(w, smallest value))     */
+};
+
+enum { MGCD_ALGO_LPA = 0, MGCD_ALGO_LOUVAIN = 1, MGCD_ALGO_LEIDEN = 2 };
+
+/* An undirected graph G = (V, E, w) (Section 3).  Every undirected edge {i, j}
+ * appears as the entries i->j and j->i with equal weight; a self-loop appears once.
+ * Layout: offsets[n+1] int64 (offsets[0] = 0, non-decreasing, offsets[n] = nnz);
+ * indices[nnz] int32 in [0, n); weights[nnz] uint32 >= 1.  Device pointers, read
+ * only.  The sum W of all weights (= 2m) must be below 2^31. */
+typedef struct {
+  int32_t n;
+  int32_t reserved;
+  int64_t nnz;
+  const int64_t *offsets;
+  const int32_t *indices;
+  const uint32_t *weights;
+} mgcd_csr;
+
+typedef struct {
+  int32_t mode;           /* MGCD_MODE_*                                              */
+  int32_t k;              /* sketch slots for moving/refinement: 1, 2, 4, 8 or 16     */
+  int32_t k_aggregate;    /* sketch slots for aggregation: 1, 2, 4, 8 or 16           */
+  int32_t max_iterations; /* synchronous sweeps per pass (LPA: in total)              */
+  int32_t max_passes;     /* Louvain/Leiden passes (levels)                            */
+  int32_t validate;       /* 1: check the CSR on the device first (MGCD_E_GRAPH)      */
+  int64_t chunk_len;      /* L: streams longer than L are sketched in chunks of L
+                             positions, then merged (changes results; >= 1)          */
+  double tolerance;       /* LPA: stop when <= tolerance*n labels change; Louvain/
+                             Leiden: stop a pass when the summed gain of all
+                             positive moves, as a modularity change, is <= tolerance */
+  double tolerance_drop;  /* tolerance is divided by this after every pass           */
+  double aggregation_tolerance; /* stop when a pass keeps more than this fraction of
+                                   its vertices                                    */
+} mgcd_params;
+
+typedef struct {
+  int32_t iterations;     /* local-moving sweeps run, all passes                      */
+  int32_t passes;         /* levels run                                               */
+  int32_t communities;    /* communities in the output                                */
+  int32_t reserved;
+  int64_t edges_scanned;  /* CSR entries streamed by local-moving sweeps              */
+  int64_t moved_last;     /* vertices that moved in the last sweep                    */
+  float ms_local_move;    /* device time in local-moving sweeps                       */
+  float ms_refine;        /* device time in Leiden refinement                         */
+  float ms_aggregate;     /* device time in renumbering and aggregation               */
+  float ms_total;         /* device time of the whole call                            */
+  /* Level-0 local-moving sweeps, device time per kernel class (HIP events on the
+     call's stream): rows of one chunk (MG) or short rows (exact); chunk sketches
+     (MG) or LDS tables (exact); merge + second pass of long rows (MG) or global
+     tables (exact). */
+  int32_t l0_sweeps;
+  int32_t reserved2;
+  float ms_l0_kernel[3];
+  float reserved3;
+} mgcd_stats;
+
+/* Defaults for an algorithm: MG Algorithm 1, k = 8 (LPA, Louvain) or 16 (Leiden),
+ * L = 128, 20 sweeps, 10 passes, tolerance 0.05 (LPA) or 0.01, drop 10,
+ * aggregation tolerance 0.8, validate 0. */
+void mgcd_default_params(int32_t algo, mgcd_params *p);
+
+/* Workspace bytes for one run of `algo` on a graph of n vertices and nnz entries. */
+size_t mgcd_workspace_bytes(int32_t algo, int32_t n, int64_t nnz, const mgcd_params *p);
+
+/* Label Propagation (Section 3.5) with MG sketches (Section 4.3): every vertex
+ * takes the label of largest total edge weight among its neighbours (self
+ * excluded; candidates from a k-slot sketch, weights from a second pass; ties to
+ * the lowest label); synchronous sweeps until at most tolerance*n labels change or
+ * max_iterations sweeps.  communities_out: device int32[n], canonical labels
+ * (communities numbered 0.. in order of their smallest vertex).  stats: host, may be
+ * NULL.  The call returns after synchronising the stream. */
+int lpa_run(const mgcd_csr *g, const mgcd_params *p, int32_t *communities_out, void *ws,
+            size_t ws_bytes, mgcd_stats *stats, void *stream);
+
+/* Louvain (Section 3.3) with MG local moving and MG aggregation (Section 4.1,
+ * Figs. 2-3); gains by Eq. 2 in exact integer form.  Arguments as lpa_run. */
+int louvain_run(const mgcd_csr *g, const mgcd_params *p, int32_t *communities_out, void *ws,
+                size_t ws_bytes, mgcd_stats *stats, void *stream);
+
+/* Leiden (Section 3.4) with MG local moving, MG refinement and symmetric MG
+ * aggregation (Section 4.2).  Arguments as lpa_run. */
+int leiden_run(const mgcd_csr *g, const mgcd_params *p, int32_t *communities_out, void *ws,
+               size_t ws_bytes, mgcd_stats *stats, void *stream);
+
+/* Modularity Q of a membership (Section 3.2, Eq. 1), summing over CSR entries
+ * (a self-loop entry counts once; 2m = W).  communities: device int32[n], values
+ * in [0, n).  q: host.  Synchronises the stream. */
+int modularity(const mgcd_csr *g, const int32_t *communities, double *q, void *ws,
+               size_t ws_bytes, void *stream);
+
+/* One synchronous local-moving sweep (the hot path on its own, for iteration-level
+ * checks).  algo: MGCD_ALGO_LPA or MGCD_ALGO_LOUVAIN.  C: device int32[n], the
+ * current membership (values in [0, n)).  C_new: device int32[n] receives the
+ * moves allowed by `direction` (-1: to lower ids only, +1: higher only, 0: all).
+ * gain: device int64[n] or NULL, the integer gain W(K_ic-K_id)-K_i(K_i+S_c-S_d) of
+ * each vertex's best move (Louvain; 0 when none).  counters (host, may be NULL):
+ * [moved, proposals, sum of gains].  Sigma/size are derived from C. */
+int mgcd_move_sweep(const mgcd_csr *g, const mgcd_params *p, int32_t algo, const int32_t *C,
+                    int32_t direction, int32_t *C_new, int64_t *gain, int64_t *counters,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* Leiden refinement on its own (Section 4.2): bound: device int32[n]; R: device
+ * int32[n] receives each vertex's sub-community (a vertex id). */
+int mgcd_refine(const mgcd_csr *g, const mgcd_params *p, const int32_t *bound, int32_t *R,
+                void *ws, size_t ws_bytes, void *stream);
+
+/* Aggregation on its own (Section 4.1 Fig. 3, Section 4.2): D: device int32[n]
+ * dense membership in [0, m).  The aggregated CSR is written to out_offsets
+ * (device int64[m+1]), out_indices and out_weights (device, capacity nnz entries;
+ * the aggregate never has more entries than the input).  *out_nnz (host) receives
+ * its entry count.  symmetric: 1 for Leiden's symmetric aggregation. */
+int mgcd_aggregate(const mgcd_csr *g, const mgcd_params *p, const int32_t *D, int32_t m,
+                   int32_t symmetric, int64_t *out_offsets, int32_t *out_indices,
+                   uint32_t *out_weights, int64_t *out_nnz, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char *mgcd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -151,9 +151,9 @@ def weighted_degree(g) -> np.ndarray:
 
 def move_sweep(g, algo, C, mode=MODE_ALG1, k=8, chunk_len=128, bound=None, K=None, Sigma=None,
                size=None, W=None, direction=0):
-    """One synchronous sweep.  Returns (C_new, gain): C_new holds the moves allowed
-    by ``direction`` (-1 lower ids only, +1 higher ids only, 0 all); gain holds the
-    integer gain of every vertex's best move."""
+    """One synchronous sweep.  Returns (C_new, gain): for Louvain moves C_new holds
+    the moves allowed by ``direction`` (-1 lower ids only, +1 higher ids only, 0 all);
+    gain holds the integer gain of every vertex's best move."""
     off, idx, w = _csr(g)
     n = off.shape[0] - 1
     C = np.ascontiguousarray(C, dtype=np.int32)

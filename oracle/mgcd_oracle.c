@@ -500,7 +500,7 @@ int oracle_move_sweep(int32_t n, const int64_t *off, const int32_t *idx, const u
   graph_t g = {n, off[n], (int64_t *)off, (int32_t *)idx, (uint32_t *)w, 0};
   sweep_t s = {&g, algo, mode, k, chunk_len, C, bound, K, Sigma, size, W};
   sweep(&s, Cnew, gain);
-  apply_direction(n, C, Cnew, direction);
+  if (algo == OR_ALGO_MOVE) apply_direction(n, C, Cnew, direction);
   return 0;
 }
 

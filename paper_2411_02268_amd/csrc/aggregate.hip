@@ -1,0 +1,714 @@
+// Renumbering and aggregation (Section 4.1 Fig. 3, Section 4.2), modularity
+// (Section 3.2 Eq. 1), canonical labels, weighted degrees and CSR validation.
+//
+// Aggregation streams community c's members in ascending vertex id, each row in
+// CSR order with self-loops, keys D[j].  MG mode sketches that stream with the same
+// chunk-then-merge schedule as local moving and keeps the positive slots, sorted by
+// key, as the super-vertex row (no second pass).  Exact mode sorts all (D[i], D[j])
+// pairs and sums runs.  Leiden adds the reverse of every kept pair and keeps, per
+// ordered pair, the larger of the two values.
+#include "aggregate.hpp"
+#include "move.hpp"
+#include "primitives.hpp"
+#include "sketch.hpp"
+
+namespace mgcd {
+
+static unsigned grid_for(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, BLOCK); }
+
+// ---- small per-vertex kernels ---------------------------------------------------------
+
+__global__ void k_zero_u32(uint32_t *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+static void zero_u32(uint32_t *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_zero_u32<<<grid_for(n), BLOCK, 0, st>>>(p, n);
+  MGCD_LAUNCHED();
+}
+
+__global__ void k_flag_used(const int32_t *C, int32_t n, uint32_t *used) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) used[C[i]] = 1u;
+}
+
+__global__ void k_dense_map(const int32_t *C, const int64_t *dense, int32_t n, int32_t *D) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) D[i] = (int32_t)dense[C[i]];
+}
+
+int32_t renumber(const int32_t *C, int32_t n, int32_t *D, Arena &a, hipStream_t st) {
+  if (n == 0) return 0;
+  size_t mk = a.mark();
+  uint32_t *used = a.take<uint32_t>(n);
+  int64_t *dense = a.take<int64_t>(n + 1);
+  zero_u32(used, n, st);
+  k_flag_used<<<grid_for(n), BLOCK, 0, st>>>(C, n, used);
+  MGCD_LAUNCHED();
+  scan_u32_i64(used, dense, n, dense + n, a, st);
+  k_dense_map<<<grid_for(n), BLOCK, 0, st>>>(C, dense, n, D);
+  MGCD_LAUNCHED();
+  int64_t m = 0;
+  MGCD_HIP(hipMemcpyAsync(&m, dense + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  a.release(mk);
+  return (int32_t)m;
+}
+
+__global__ void k_group_sums(const int32_t *D, const uint32_t *K, uint32_t *Kout, int32_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) atomicAdd(&Kout[D[i]], K[i]);
+}
+
+void launch_group_sums(const int32_t *D, const uint32_t *K, uint32_t *Kout, int32_t n, int32_t m,
+                       hipStream_t st) {
+  zero_u32(Kout, m, st);
+  if (n <= 0) return;
+  k_group_sums<<<grid_for(n), BLOCK, 0, st>>>(D, K, Kout, n);
+  MGCD_LAUNCHED();
+}
+
+__global__ void k_compose(const int32_t *in, const int32_t *map, int32_t *out, int32_t n) {
+  int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v < n) out[v] = map[in[v]];
+}
+
+void launch_compose(const int32_t *in, const int32_t *map, int32_t *out, int32_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_compose<<<grid_for(n), BLOCK, 0, st>>>(in, map, out, n);
+  MGCD_LAUNCHED();
+}
+
+__global__ void k_scatter_labels(const int32_t *map, const int32_t *val, int32_t *out, int32_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) out[map[i]] = val[i];
+}
+
+void launch_scatter_labels(const int32_t *map, const int32_t *val, int32_t *out, int32_t n,
+                           hipStream_t st) {
+  if (n <= 0) return;
+  k_scatter_labels<<<grid_for(n), BLOCK, 0, st>>>(map, val, out, n);
+  MGCD_LAUNCHED();
+}
+
+// One wave per vertex: K_i = sum of its row's weights (Section 3); W = sum of K.
+__global__ void __launch_bounds__(BLOCK)
+    k_degrees(Graph g, uint32_t *K, unsigned long long *W) {
+  __shared__ unsigned long long lw[4];
+  int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+  uint64_t s = 0;
+  if (i < g.n) {
+    for (int64_t e = g.off[i] + lane_id(); e < g.off[i + 1]; e += WAVE) s += g.w[e];
+    s = wave_sum(s);
+    if (lane_id() == 0) K[i] = (uint32_t)s;
+  }
+  if (lane_id() == 0) lw[threadIdx.x / WAVE] = i < g.n ? s : 0;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(W, lw[0] + lw[1] + lw[2] + lw[3]);
+}
+
+void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, hipStream_t st) {
+  launch_zero_u64(W, 1, st);
+  if (g.n <= 0) return;
+  k_degrees<<<(unsigned)ceil_div(g.n, 4), BLOCK, 0, st>>>(g, K, W);
+  MGCD_LAUNCHED();
+}
+
+// ---- canonical labels ----------------------------------------------------------------
+
+__global__ void k_min_member(const int32_t *C, int32_t n, int32_t *minv) {
+  int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v < n) atomicMin(&minv[C[v]], (int32_t)v);
+}
+__global__ void k_is_first(const int32_t *C, const int32_t *minv, int32_t n, uint32_t *first) {
+  int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v < n) first[v] = minv[C[v]] == (int32_t)v ? 1u : 0u;
+}
+__global__ void k_canon(const int32_t *C, const int32_t *minv, const int64_t *rank, int32_t n,
+                        int32_t *out) {
+  int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v < n) out[v] = (int32_t)rank[minv[C[v]]];
+}
+__global__ void k_fill_max(int32_t *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) p[i] = 0x7FFFFFFF;
+}
+
+int32_t canonical(const int32_t *C, int32_t n, int32_t *out, Arena &a, hipStream_t st) {
+  if (n == 0) return 0;
+  size_t mk = a.mark();
+  int32_t *minv = a.take<int32_t>(n);
+  uint32_t *first = a.take<uint32_t>(n);
+  int64_t *rank = a.take<int64_t>((int64_t)n + 1);
+  k_fill_max<<<grid_for(n), BLOCK, 0, st>>>(minv, n);
+  MGCD_LAUNCHED();
+  k_min_member<<<grid_for(n), BLOCK, 0, st>>>(C, n, minv);
+  MGCD_LAUNCHED();
+  k_is_first<<<grid_for(n), BLOCK, 0, st>>>(C, minv, n, first);
+  MGCD_LAUNCHED();
+  scan_u32_i64(first, rank, n, rank + n, a, st);
+  k_canon<<<grid_for(n), BLOCK, 0, st>>>(C, minv, rank, n, out);
+  MGCD_LAUNCHED();
+  int64_t m = 0;
+  MGCD_HIP(hipMemcpyAsync(&m, rank + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  a.release(mk);
+  return (int32_t)m;
+}
+
+// ---- modularity ------------------------------------------------------------------------
+
+// One wave per vertex: intra-community weight of its row.
+__global__ void __launch_bounds__(BLOCK)
+    k_intra(Graph g, const int32_t *C, unsigned long long *terms) {
+  __shared__ unsigned long long lw[4];
+  int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+  uint64_t s = 0;
+  if (i < g.n) {
+    int32_t ci = C[i];
+    for (int64_t e = g.off[i] + lane_id(); e < g.off[i + 1]; e += WAVE)
+      s += C[g.idx[e]] == ci ? g.w[e] : 0u;
+    s = wave_sum(s);
+  }
+  if (lane_id() == 0) lw[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&terms[0], lw[0] + lw[1] + lw[2] + lw[3]);
+}
+
+__global__ void k_comm_tot(const int32_t *C, const uint32_t *K, int32_t n, uint32_t *tot) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) atomicAdd(&tot[C[i]], K[i]);
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    k_sum_squares(const uint32_t *tot, int32_t n, unsigned long long *terms) {
+  __shared__ unsigned long long lw[4];
+  int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  unsigned long long x = c < n ? (unsigned long long)tot[c] : 0ull;
+  unsigned long long s = block_sum(x * x, lw);
+  if (threadIdx.x == 0) atomicAdd(&terms[1], s);
+}
+
+__global__ void k_zero2(unsigned long long *p) {
+  p[0] = 0;
+  p[1] = 0;
+}
+
+void modularity_terms(const Graph &g, const int32_t *C, const uint32_t *K, unsigned long long *terms,
+                      Arena &a, hipStream_t st) {
+  k_zero2<<<1, 1, 0, st>>>(terms);
+  MGCD_LAUNCHED();
+  if (g.n == 0) return;
+  size_t mk = a.mark();
+  uint32_t *tot = a.take<uint32_t>(g.n);
+  zero_u32(tot, g.n, st);
+  k_intra<<<(unsigned)ceil_div(g.n, 4), BLOCK, 0, st>>>(g, C, terms);
+  MGCD_LAUNCHED();
+  k_comm_tot<<<grid_for(g.n), BLOCK, 0, st>>>(C, K, g.n, tot);
+  MGCD_LAUNCHED();
+  k_sum_squares<<<grid_for(g.n), BLOCK, 0, st>>>(tot, g.n, terms);
+  MGCD_LAUNCHED();
+  a.release(mk);
+}
+
+// ---- validation --------------------------------------------------------------------------
+
+__global__ void k_check_labels(const int32_t *C, int64_t n, int64_t limit, unsigned long long *flag) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n && (C[i] < 0 || (int64_t)C[i] >= limit)) atomicOr(flag, 1ull);
+}
+
+void launch_check_labels(const int32_t *C, int64_t n, int64_t limit, unsigned long long *flag,
+                         hipStream_t st) {
+  launch_zero_u64(flag, 1, st);
+  if (n <= 0) return;
+  k_check_labels<<<grid_for(n), BLOCK, 0, st>>>(C, n, limit, flag);
+  MGCD_LAUNCHED();
+}
+
+__global__ void k_validate_rows(Graph g, unsigned long long *flags) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i > g.n) return;
+  bool bad = false;
+  if (i == 0) bad |= g.off[0] != 0;
+  if (i == g.n) bad |= g.off[g.n] != g.nnz;
+  if (i < g.n) bad |= g.off[i + 1] < g.off[i];
+  if (bad) atomicOr(&flags[0], 1ull);
+}
+
+__global__ void k_validate_entries(Graph g, unsigned long long *flags) {
+  int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (e >= g.nnz) return;
+  int32_t j = g.idx[e];
+  if (j < 0 || j >= g.n || g.w[e] == 0) atomicOr(&flags[0], 2ull);
+}
+
+void launch_validate(const Graph &g, unsigned long long *flags, hipStream_t st) {
+  k_validate_rows<<<grid_for((int64_t)g.n + 1), BLOCK, 0, st>>>(g, flags);
+  MGCD_LAUNCHED();
+  if (g.nnz > 0) {
+    k_validate_entries<<<grid_for(g.nnz), BLOCK, 0, st>>>(g, flags);
+    MGCD_LAUNCHED();
+  }
+}
+
+// ---- aggregation: member order and community streams ------------------------------------
+
+__global__ void k_member_keys(const int32_t *D, int32_t n, uint64_t *key, uint32_t *val) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) {
+    key[i] = (uint64_t)(uint32_t)D[i];
+    val[i] = (uint32_t)i;
+  }
+}
+
+// mstart[c] = first position of community c in the sorted member list.
+__global__ void k_member_bounds(const uint64_t *ks, int32_t n, int32_t m, int32_t *mstart) {
+  int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (t < n) {
+    uint32_t c = (uint32_t)ks[t];
+    if (t == 0 || (uint32_t)ks[t - 1] != c) mstart[c] = (int32_t)t;
+  }
+  if (t == 0) mstart[m] = n;
+}
+
+__global__ void k_member_deg(const int64_t *off, const uint32_t *mem, int32_t n, uint32_t *mdeg) {
+  int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (t < n) {
+    uint32_t i = mem[t];
+    mdeg[t] = (uint32_t)(off[i + 1] - off[i]);
+  }
+}
+
+__global__ void k_comm_keys(const int32_t *mstart, const int64_t *P, int32_t m, int64_t L,
+                            uint64_t *key, uint32_t *val, unsigned long long *cnt) {
+  int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= m) return;
+  int64_t len = P[mstart[c + 1]] - P[mstart[c]];
+  int b = 0;
+  while (b < 63 && (len >> b) != 0) ++b;
+  bool single = len <= L;
+  key[c] = single ? (uint64_t)(64 - b) : 255ull;
+  val[c] = (uint32_t)c;
+  atomicAdd(&cnt[single ? 0 : 1], 1ull);
+}
+
+__global__ void k_comm_chunks(const int32_t *mstart, const int64_t *P, const int32_t *multi,
+                              int64_t nmulti, int64_t L, int64_t *nch) {
+  int64_t x = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (x >= nmulti) return;
+  int32_t c = multi[x];
+  int64_t len = P[mstart[c + 1]] - P[mstart[c]];
+  nch[x] = (len + L - 1) / L;
+}
+
+__global__ void k_comm_owner(const int64_t *cstart, int64_t nmulti, int32_t *owner) {
+  int64_t x = blockIdx.x;
+  if (x >= nmulti) return;
+  for (int64_t q = cstart[x] + threadIdx.x; q < cstart[x + 1]; q += BLOCK) owner[q] = (int32_t)x;
+}
+
+__global__ void k_u32_to_i32(const uint32_t *v, int32_t *out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) out[i] = (int32_t)v[i];
+}
+
+struct AggStreams {
+  Graph g;
+  const int32_t *D;
+  const uint32_t *mem;    // members sorted by community, ascending id within one
+  const int32_t *mstart;  // [m+1]
+  const int64_t *P;       // [n+1] stream position of each member's row
+};
+
+// Stream positions [p0, p1) of community c into the sketch.
+template <int K, int MODE>
+__device__ inline void stream_range(const AggStreams &s, int32_t c, int64_t p0, int64_t p1,
+                                    RegSketch<K, MODE> &sk) {
+  // member t holding position p0: the last t in [mstart[c], mstart[c+1]) with P[t] <= p0
+  int32_t lo = s.mstart[c], hi = s.mstart[c + 1] - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (s.P[mid] <= p0) lo = mid; else hi = mid - 1;
+  }
+  int32_t t = lo;
+  int64_t p = p0;
+  while (p < p1) {
+    const uint32_t i = s.mem[t];
+    const int64_t rb = s.g.off[i];
+    const int64_t row_end = s.P[t + 1];
+    const int64_t stop = row_end < p1 ? row_end : p1;
+    for (int64_t e = rb + (p - s.P[t]); p < stop; ++e, ++p)
+      sk.update((uint32_t)s.D[s.g.idx[e]], s.g.w[e]);
+    ++t;
+  }
+}
+
+template <int K>
+__device__ inline void write_row(uint32_t (&k)[K], uint32_t (&v)[K], int32_t c, Pair *rows,
+                                 uint32_t *rcount) {
+#pragma unroll
+  for (int p = 0; p < K; ++p) k[p] = v[p] > 0 ? k[p] : EMPTY;
+  sort_by_key<K>(k, v);
+  uint32_t x = 0;
+#pragma unroll
+  for (int p = 0; p < K; ++p)
+    if (k[p] != EMPTY) rows[(int64_t)c * K + x++] = Pair{k[p], v[p]};
+  rcount[c] = x;
+}
+
+template <int K, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_agg_single(AggStreams s, const int32_t *list, int64_t count, Pair *rows, uint32_t *rcount) {
+  int64_t x = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (x >= count) return;
+  const int32_t c = list[x];
+  RegSketch<K, MODE> sk;
+  sk.reset();
+  const int64_t p0 = s.P[s.mstart[c]], p1 = s.P[s.mstart[c + 1]];
+  if (p1 > p0) stream_range<K, MODE>(s, c, p0, p1, sk);
+  write_row<K>(sk.key, sk.val, c, rows, rcount);
+}
+
+template <int K, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_agg_chunks(AggStreams s, const int32_t *multi, const int32_t *owner, const int64_t *cstart,
+                 int64_t nchunks, int64_t L, Pair *skbuf) {
+  int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (q >= nchunks) return;
+  const int32_t x = owner[q];
+  const int32_t c = multi[x];
+  const int64_t base = s.P[s.mstart[c]], end = s.P[s.mstart[c + 1]];
+  const int64_t p0 = base + (q - cstart[x]) * L;
+  const int64_t p1 = p0 + L < end ? p0 + L : end;
+  RegSketch<K, MODE> sk;
+  sk.reset();
+  stream_range<K, MODE>(s, c, p0, p1, sk);
+  sk.finalize();
+#pragma unroll
+  for (int p = 0; p < K; ++p) skbuf[q * K + p] = Pair{sk.key[p], sk.val[p]};
+}
+
+template <int K>
+__global__ void __launch_bounds__(BLOCK)
+    k_agg_multi(const int32_t *multi, const int64_t *cstart, Pair *skbuf, Pair *rows, uint32_t *rcount) {
+  __shared__ Pair lds[BLOCK * K];
+  const int32_t x = blockIdx.x;
+  const int32_t c = multi[x];
+  tree_reduce<K>(skbuf, cstart[x], cstart[x + 1] - cstart[x], lds);
+  if (threadIdx.x == 0) {
+    uint32_t k[K], v[K];
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      k[p] = lds[p].key;
+      v[p] = lds[p].val;
+    }
+    write_row<K>(k, v, c, rows, rcount);
+  }
+}
+
+// rows (K slots per community, rcount used) -> CSR
+__global__ void k_compact_rows(const Pair *rows, const uint32_t *rcount, const int64_t *off, int32_t m,
+                               int k, int32_t *idx, uint32_t *w) {
+  int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= m) return;
+  int64_t o = off[c];
+  for (uint32_t x = 0; x < rcount[c]; ++x) {
+    Pair p = rows[c * k + x];
+    idx[o + x] = (int32_t)p.key;
+    w[o + x] = p.val;
+  }
+}
+
+// Leiden: emit every kept pair forward and, off the diagonal, reversed.
+__global__ void k_emit_counts(const Pair *rows, const uint32_t *rcount, int32_t m, int k, uint32_t *ec) {
+  int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= m) return;
+  uint32_t e = 0;
+  for (uint32_t x = 0; x < rcount[c]; ++x) e += rows[c * k + x].key == (uint32_t)c ? 1u : 2u;
+  ec[c] = e;
+}
+
+__global__ void k_emit(const Pair *rows, const uint32_t *rcount, const int64_t *epos, int32_t m, int k,
+                       int b, uint64_t *key, uint32_t *val) {
+  int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= m) return;
+  int64_t o = epos[c];
+  for (uint32_t x = 0; x < rcount[c]; ++x) {
+    Pair p = rows[c * k + x];
+    key[o] = ((uint64_t)c << b) | p.key;
+    val[o++] = p.val;
+    if (p.key != (uint32_t)c) {
+      key[o] = ((uint64_t)p.key << b) | (uint64_t)c;
+      val[o++] = p.val;
+    }
+  }
+}
+
+// Sorted (row, col) keys: run heads (first entry of each distinct key).
+__global__ void k_heads(const uint64_t *ks, int64_t n, uint32_t *head) {
+  int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (e < n) head[e] = (e == 0 || ks[e - 1] != ks[e]) ? 1u : 0u;
+}
+
+// Runs have at most two entries (forward and reversed): keep the larger value.
+__global__ void k_dedupe_max(const uint64_t *ks, const uint32_t *vs, const uint32_t *head,
+                             const int64_t *rid, int64_t n, int b, int32_t *idx, uint32_t *w,
+                             uint32_t *rowcnt) {
+  int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (e >= n || !head[e]) return;
+  uint32_t v = vs[e];
+  if (e + 1 < n && ks[e + 1] == ks[e]) v = vs[e + 1] > v ? vs[e + 1] : v;
+  int64_t u = rid[e];
+  uint64_t mask = (b >= 64) ? ~0ull : ((1ull << b) - 1);
+  idx[u] = (int32_t)(ks[e] & mask);
+  w[u] = v;
+  atomicAdd(&rowcnt[(uint32_t)(ks[e] >> b)], 1u);
+}
+
+// Exact aggregation: one key (D[i], D[j]) per CSR entry; the row by binary search.
+__global__ void k_exact_keys(Graph g, const int32_t *D, int b, uint64_t *key, uint32_t *val) {
+  int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (e >= g.nnz) return;
+  int32_t lo = 0, hi = g.n - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (g.off[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  key[e] = ((uint64_t)(uint32_t)D[lo] << b) | (uint64_t)(uint32_t)D[g.idx[e]];
+  val[e] = g.w[e];
+}
+
+// Sum the weights of each run of equal keys: in-wave segmented sums, one atomic
+// per run segment of a wave.
+__global__ void __launch_bounds__(BLOCK)
+    k_run_sums(const uint64_t *ks, const uint32_t *vs, const int64_t *rid, int64_t n, int b,
+               int32_t *idx, uint32_t *w, uint32_t *rowcnt) {
+  int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const bool valid = e < n;
+  const uint64_t key = valid ? ks[e] : ~0ull;
+  const bool head = valid && (e == 0 || ks[e - 1] != key);
+  const int lane = lane_id();
+  uint64_t incl = wave_inclusive_scan((uint64_t)(valid ? vs[e] : 0u));
+  const uint64_t hm = __ballot(head) | 1ull;  // a wave's first lane starts a segment
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+  const int start = 63 - __clzll(hm & upto);
+  const uint64_t before = __shfl(incl, start > 0 ? start - 1 : 0);
+  const bool next_head = lane == 63 || ((hm >> (lane + 1)) & 1ull) || e + 1 >= n;
+  if (valid) {
+    int64_t u = rid[e] + (head ? 0 : -1);
+    if (head) {
+      uint64_t mask = (1ull << b) - 1;
+      idx[u] = (int32_t)(key & mask);
+      atomicAdd(&rowcnt[(uint32_t)(key >> b)], 1u);
+    }
+    if (next_head) atomicAdd(&w[u], (uint32_t)(incl - (start > 0 ? before : 0ull)));
+  }
+}
+
+// ---- aggregation driver -----------------------------------------------------------------
+
+template <int K, int MODE>
+static void agg_mg(const AggStreams &s, const int32_t *single, int64_t nsingle, const int32_t *multi,
+                   int64_t nmulti, const int64_t *cstart, const int32_t *owner, int64_t nchunks,
+                   int64_t L, Pair *skbuf, Pair *rows, uint32_t *rcount, hipStream_t st) {
+  if (nsingle > 0) {
+    k_agg_single<K, MODE><<<grid_for(nsingle), BLOCK, 0, st>>>(s, single, nsingle, rows, rcount);
+    MGCD_LAUNCHED();
+  }
+  if (nmulti > 0) {
+    k_agg_chunks<K, MODE><<<grid_for(nchunks), BLOCK, 0, st>>>(s, multi, owner, cstart, nchunks, L, skbuf);
+    MGCD_LAUNCHED();
+    k_agg_multi<K><<<(unsigned)nmulti, BLOCK, 0, st>>>(multi, cstart, skbuf, rows, rcount);
+    MGCD_LAUNCHED();
+  }
+}
+
+template <int MODE>
+static void agg_mg_k(int k, const AggStreams &s, const int32_t *single, int64_t nsingle,
+                     const int32_t *multi, int64_t nmulti, const int64_t *cstart, const int32_t *owner,
+                     int64_t nchunks, int64_t L, Pair *skbuf, Pair *rows, uint32_t *rcount,
+                     hipStream_t st) {
+  switch (k) {
+    case 1: agg_mg<1, MODE>(s, single, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case 2: agg_mg<2, MODE>(s, single, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case 4: agg_mg<4, MODE>(s, single, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case 8: agg_mg<8, MODE>(s, single, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case 16: agg_mg<16, MODE>(s, single, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    default: throw Error(-6, "k_aggregate must be 1, 2, 4, 8 or 16");
+  }
+}
+
+static int64_t read_i64(const int64_t *p, hipStream_t st) {
+  int64_t h = 0;
+  MGCD_HIP(hipMemcpyAsync(&h, p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  return h;
+}
+
+// CSR offsets from per-row counts.
+static void offsets_from_counts(const uint32_t *rowcnt, int32_t m, int64_t *out_off, Arena &a,
+                                hipStream_t st) {
+  scan_u32_i64(rowcnt, out_off, m, out_off + m, a, st);
+}
+
+static int64_t aggregate_exact(const Graph &g, const int32_t *D, int32_t m, int64_t *out_off,
+                               int32_t *out_idx, uint32_t *out_w, Arena &a, hipStream_t st) {
+  const int64_t E = g.nnz;
+  const int b = bits_for((uint64_t)(m > 1 ? m - 1 : 1));
+  uint32_t *rowcnt = a.take<uint32_t>(m);
+  zero_u32(rowcnt, m, st);
+  if (E == 0) {
+    offsets_from_counts(rowcnt, m, out_off, a, st);
+    return 0;
+  }
+  uint64_t *k0 = a.take<uint64_t>(E), *k1 = a.take<uint64_t>(E);
+  uint32_t *v0 = a.take<uint32_t>(E), *v1 = a.take<uint32_t>(E);
+  uint32_t *head = a.take<uint32_t>(E);
+  int64_t *rid = a.take<int64_t>(E + 1);
+  k_exact_keys<<<grid_for(E), BLOCK, 0, st>>>(g, D, b, k0, v0);
+  MGCD_LAUNCHED();
+  bool flip = radix_sort_pairs(k0, v0, k1, v1, E, 2 * b, a, st);
+  const uint64_t *ks = flip ? k1 : k0;
+  const uint32_t *vs = flip ? v1 : v0;
+  k_heads<<<grid_for(E), BLOCK, 0, st>>>(ks, E, head);
+  MGCD_LAUNCHED();
+  scan_u32_i64(head, rid, E, rid + E, a, st);
+  int64_t R = read_i64(rid + E, st);
+  zero_u32(out_w, R, st);
+  k_run_sums<<<grid_for(E), BLOCK, 0, st>>>(ks, vs, rid, E, b, out_idx, out_w, rowcnt);
+  MGCD_LAUNCHED();
+  offsets_from_counts(rowcnt, m, out_off, a, st);
+  return R;
+}
+
+int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, int64_t L,
+                  int symmetric, int64_t *out_off, int32_t *out_idx, uint32_t *out_w, Arena &a,
+                  hipStream_t st) {
+  const int32_t n = g.n;
+  size_t mk = a.mark();
+  if (mode == MODE_EXACT) {
+    int64_t r = aggregate_exact(g, D, m, out_off, out_idx, out_w, a, st);
+    a.release(mk);
+    return r;
+  }
+  // members in ascending id within each community (stable radix sort by D)
+  uint64_t *k0 = a.take<uint64_t>(n), *k1 = a.take<uint64_t>(n);
+  uint32_t *v0 = a.take<uint32_t>(n), *v1 = a.take<uint32_t>(n);
+  k_member_keys<<<grid_for(n), BLOCK, 0, st>>>(D, n, k0, v0);
+  MGCD_LAUNCHED();
+  bool flip = radix_sort_pairs(k0, v0, k1, v1, n, bits_for((uint64_t)(m > 1 ? m - 1 : 1)), a, st);
+  const uint64_t *ks = flip ? k1 : k0;
+  const uint32_t *mem = flip ? v1 : v0;
+  int32_t *mstart = a.take<int32_t>((int64_t)m + 1);
+  k_member_bounds<<<grid_for(n), BLOCK, 0, st>>>(ks, n, m, mstart);
+  MGCD_LAUNCHED();
+  uint32_t *mdeg = a.take<uint32_t>(n);
+  int64_t *P = a.take<int64_t>((int64_t)n + 1);
+  k_member_deg<<<grid_for(n), BLOCK, 0, st>>>(g.off, mem, n, mdeg);
+  MGCD_LAUNCHED();
+  scan_u32_i64(mdeg, P, n, P + n, a, st);
+  // communities: short streams (one lane each) vs long ones (chunks + merge tree)
+  unsigned long long *cnt = a.take<unsigned long long>(2);
+  launch_zero_u64(cnt, 2, st);
+  uint64_t *ck0 = a.take<uint64_t>(m), *ck1 = a.take<uint64_t>(m);
+  uint32_t *cv0 = a.take<uint32_t>(m), *cv1 = a.take<uint32_t>(m);
+  k_comm_keys<<<grid_for(m), BLOCK, 0, st>>>(mstart, P, m, L, ck0, cv0, cnt);
+  MGCD_LAUNCHED();
+  bool cf = radix_sort_pairs(ck0, cv0, ck1, cv1, m, 8, a, st);
+  int32_t *corder = a.take<int32_t>(m);
+  k_u32_to_i32<<<grid_for(m), BLOCK, 0, st>>>(cf ? cv1 : cv0, corder, m);
+  MGCD_LAUNCHED();
+  unsigned long long hc[2];
+  MGCD_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  const int64_t nsingle = (int64_t)hc[0], nmulti = (int64_t)hc[1];
+  int32_t *multi = corder + nsingle;
+  int64_t *cstart = nullptr, nchunks = 0;
+  int32_t *owner = nullptr;
+  Pair *skbuf = nullptr;
+  if (nmulti > 0) {
+    int64_t *nch = a.take<int64_t>(nmulti);
+    cstart = a.take<int64_t>(nmulti + 1);
+    k_comm_chunks<<<grid_for(nmulti), BLOCK, 0, st>>>(mstart, P, multi, nmulti, L, nch);
+    MGCD_LAUNCHED();
+    scan_i64(nch, cstart, nmulti, cstart + nmulti, a, st);
+    nchunks = read_i64(cstart + nmulti, st);
+    owner = a.take<int32_t>(nchunks);
+    k_comm_owner<<<(unsigned)nmulti, BLOCK, 0, st>>>(cstart, nmulti, owner);
+    MGCD_LAUNCHED();
+    skbuf = a.take<Pair>(nchunks * k);
+  }
+  Pair *rows = a.take<Pair>((int64_t)m * k);
+  uint32_t *rcount = a.take<uint32_t>(m);
+  AggStreams s{g, D, mem, mstart, P};
+  switch (mode) {
+    case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, corder, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, corder, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case MODE_STD: agg_mg_k<MODE_STD>(k, s, corder, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    default: throw Error(-6, "unknown sketch mode");
+  }
+  int64_t total = 0;
+  if (!symmetric) {
+    offsets_from_counts(rcount, m, out_off, a, st);
+    k_compact_rows<<<grid_for(m), BLOCK, 0, st>>>(rows, rcount, out_off, m, k, out_idx, out_w);
+    MGCD_LAUNCHED();
+    total = read_i64(out_off + m, st);
+  } else {
+    uint32_t *ec = a.take<uint32_t>(m);
+    int64_t *epos = a.take<int64_t>((int64_t)m + 1);
+    k_emit_counts<<<grid_for(m), BLOCK, 0, st>>>(rows, rcount, m, k, ec);
+    MGCD_LAUNCHED();
+    scan_u32_i64(ec, epos, m, epos + m, a, st);
+    const int64_t E2 = read_i64(epos + m, st);
+    const int b = bits_for((uint64_t)(m > 1 ? m - 1 : 1));
+    uint64_t *e0 = a.take<uint64_t>(E2), *e1 = a.take<uint64_t>(E2);
+    uint32_t *w0 = a.take<uint32_t>(E2), *w1 = a.take<uint32_t>(E2);
+    k_emit<<<grid_for(m), BLOCK, 0, st>>>(rows, rcount, epos, m, k, b, e0, w0);
+    MGCD_LAUNCHED();
+    bool ef = radix_sort_pairs(e0, w0, e1, w1, E2, 2 * b, a, st);
+    const uint64_t *sk = ef ? e1 : e0;
+    const uint32_t *sv = ef ? w1 : w0;
+    uint32_t *head = a.take<uint32_t>(E2);
+    int64_t *rid = a.take<int64_t>(E2 + 1);
+    uint32_t *rowcnt = a.take<uint32_t>(m);
+    zero_u32(rowcnt, m, st);
+    if (E2 > 0) {
+      k_heads<<<grid_for(E2), BLOCK, 0, st>>>(sk, E2, head);
+      MGCD_LAUNCHED();
+      scan_u32_i64(head, rid, E2, rid + E2, a, st);
+      k_dedupe_max<<<grid_for(E2), BLOCK, 0, st>>>(sk, sv, head, rid, E2, b, out_idx, out_w, rowcnt);
+      MGCD_LAUNCHED();
+    }
+    offsets_from_counts(rowcnt, m, out_off, a, st);
+    total = read_i64(out_off + m, st);
+  }
+  a.release(mk);
+  return total;
+}
+
+size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
+  size_t b = 0;
+  if (mode == MODE_EXACT) {
+    b += (size_t)nnz * (8 + 8 + 4 + 4 + 4 + 8) + 8192;
+    b += radix_sort_ws_bytes(nnz) + scan_ws_bytes(nnz) + (size_t)n * 4 + 4096;
+    return b + 64 * 1024;
+  }
+  b += (size_t)n * (8 + 8 + 4 + 4) + 4096;          // member sort buffers
+  b += radix_sort_ws_bytes(n) + 4096;
+  b += (size_t)(n + 1) * (4 + 4 + 8) + 4096;        // mstart, mdeg, P
+  b += scan_ws_bytes(n + 1) + 4096;
+  b += (size_t)n * (8 + 8 + 4 + 4 + 4) + 4096;      // community sort, order
+  int64_t chunks = nnz / (L > 0 ? L : 1) + n + 1;
+  b += (size_t)(n + 1) * 16 + (size_t)chunks * (4 + (size_t)k * sizeof(Pair)) + 8192;
+  b += (size_t)n * k * sizeof(Pair) + (size_t)n * 4 + 4096;  // rows, rcount
+  // symmetric: emit buffers (<= 2 k n entries), sort, heads
+  int64_t e2 = 2 * (int64_t)n * k;
+  b += (size_t)n * (4 + 8 + 4) + (size_t)e2 * (8 + 8 + 4 + 4 + 4 + 8) + 16384;
+  b += radix_sort_ws_bytes(e2) + scan_ws_bytes(e2);
+  return b + 64 * 1024;
+}
+
+}  // namespace mgcd

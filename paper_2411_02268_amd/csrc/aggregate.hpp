@@ -1,0 +1,47 @@
+// Renumbering, aggregation, modularity and small per-vertex kernels (aggregate.hip).
+#pragma once
+#include "common.hpp"
+
+namespace mgcd {
+
+// dense[c] for every used id c of C (ascending old id); D[i] = dense[C[i]]; returns m.
+int32_t renumber(const int32_t *C, int32_t n, int32_t *D, Arena &a, hipStream_t st);
+
+// Aggregated graph of g under the dense membership D (values in [0, m)).
+// out_off: [m+1]; out_idx/out_w: capacity g.nnz.  Returns the entry count.
+// Louvain (symmetric=0): a community's row is the sketch (or exact sums) of the
+// stream of its members' rows, members in ascending id.  Leiden (symmetric=1): the
+// kept pairs in both directions, weight max(v_st, v_ts).
+int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, int64_t L,
+                  int symmetric, int64_t *out_off, int32_t *out_idx, uint32_t *out_w, Arena &a,
+                  hipStream_t st);
+size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L);
+
+// K'[c] = sum of K[i] over D[i] == c.
+void launch_group_sums(const int32_t *D, const uint32_t *K, uint32_t *Kout, int32_t n, int32_t m,
+                       hipStream_t st);
+// out[v] = map[in[v]] for v < n (in may alias out).
+void launch_compose(const int32_t *in, const int32_t *map, int32_t *out, int32_t n, hipStream_t st);
+// out[map[i]] = val[i]  (all i with the same map[i] write the same value).
+void launch_scatter_labels(const int32_t *map, const int32_t *val, int32_t *out, int32_t n,
+                           hipStream_t st);
+
+// K[i] = row sums (uint32) and *W = their total (device uint64).
+void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, hipStream_t st);
+
+// Canonical labels: communities numbered in order of their smallest vertex.
+// Returns the number of communities (synchronises the stream).
+int32_t canonical(const int32_t *C, int32_t n, int32_t *out, Arena &a, hipStream_t st);
+
+// Integers of Eq. 1: I = weight of intra-community entries, S2 = sum of Sigma_c^2.
+void modularity_terms(const Graph &g, const int32_t *C, const uint32_t *K,
+                      unsigned long long *terms /* device [2] */, Arena &a, hipStream_t st);
+
+// *flag = 1 when some C[i] (i < n) lies outside [0, limit).
+void launch_check_labels(const int32_t *C, int64_t n, int64_t limit, unsigned long long *flag,
+                         hipStream_t st);
+
+// Validation of a CSR; sets flags[0] when something is wrong.
+void launch_validate(const Graph &g, unsigned long long *flags, hipStream_t st);
+
+}  // namespace mgcd

@@ -1,0 +1,115 @@
+// Shared device and host helpers of the MI355X (gfx950) community-detection library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace mgcd {
+
+constexpr uint32_t EMPTY = 0xFFFFFFFFu;  // key of a fresh sketch slot; never a community id
+constexpr int WAVE = 64;                 // CDNA wavefront width
+constexpr int BLOCK = 256;               // four waves per workgroup
+
+enum Algo : int { ALGO_LPA = 0, ALGO_MOVE = 1, ALGO_REFINE = 2 };
+enum Mode : int { MODE_EXACT = 0, MODE_ALG1 = 1, MODE_UNCOND = 2, MODE_STD = 3 };
+
+// A CSR graph in device memory (Section 3): rows are the out-entries of a vertex.
+struct Graph {
+  int32_t n;
+  int64_t nnz;
+  const int64_t *off;
+  const int32_t *idx;
+  const uint32_t *w;
+};
+
+struct Pair {
+  uint32_t key;
+  uint32_t val;
+};
+
+// ---- errors (host) -------------------------------------------------------------
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define MGCD_HIP(x)                                                                     \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      throw ::mgcd::Error(-5, std::string(#x) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+#define MGCD_LAUNCHED() MGCD_HIP(hipGetLastError())
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline int bits_for(uint64_t maxval) {  // bits needed to hold values <= maxval
+  int b = 0;
+  while (b < 64 && (maxval >> b) != 0) ++b;
+  return b;
+}
+
+// ---- bump allocator over the caller's workspace (host) ---------------------------
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0, used = 0, peak = 0;
+  bool dry = false;  // sizing pass: count bytes only
+  template <typename T>
+  T *take(int64_t count) {
+    size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    size_t start = (used + 255) & ~(size_t)255;
+    size_t end = start + bytes;
+    if (end > peak) peak = end;
+    if (!dry && end > cap)
+      throw Error(-4, "workspace too small: need more than " + std::to_string(end) + " bytes");
+    used = end;
+    return dry ? nullptr : reinterpret_cast<T *>(base + start);
+  }
+  size_t mark() const { return used; }
+  void release(size_t m) { used = m; }
+};
+
+// ---- wave helpers (device) -------------------------------------------------------
+__device__ inline int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+
+__device__ inline uint64_t lanemask_lt() {
+  int l = lane_id();
+  return l == 0 ? 0ull : ((~0ull) >> (64 - l));
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <typename T>
+__device__ inline T wave_inclusive_scan(T v) {
+  int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    T u = __shfl_up(v, o);
+    if (l >= o) v += u;
+  }
+  return v;
+}
+
+// Sum over a 256-thread block; every thread gets the total.
+template <typename T>
+__device__ inline T block_sum(T v, T *lds4) {
+  v = wave_sum(v);
+  int w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane_id() == 0) lds4[w] = v;
+  __syncthreads();
+  T t = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+  __syncthreads();
+  return t;
+}
+
+}  // namespace mgcd

@@ -1,0 +1,502 @@
+// Host drivers of LPA, Louvain and Leiden and the C ABI declared in include/mgcd.h.
+//
+// Louvain pass (Section 3.3, Section 4.1): synchronous local-moving sweeps until no
+// vertex has a positive-gain move, the summed gain of those moves is at most the
+// tolerance, or max_iterations; sweep t applies only moves to lower community ids
+// (t even) or higher ids (t odd), which keeps pairs of vertices from swapping
+// forever.  Then communities are renumbered densely (ascending old id) and, unless
+// the pass kept more than aggregation_tolerance of its vertices or was the last,
+// aggregated into super-vertices whose weighted degree is the exact sum of their
+// members' (the total weight W stays the input's).  Leiden (Section 4.2) adds one
+// refinement sweep inside each community, aggregates the refined partition
+// symmetrically and starts the next pass from the (renumbered) communities.
+#include <chrono>
+#include <cstring>
+#include <string>
+
+#include "../../include/mgcd.h"
+#include "aggregate.hpp"
+#include "move.hpp"
+#include "primitives.hpp"
+
+namespace mgcd {
+
+static thread_local std::string g_last_error;
+
+// Per-kernel-class device time of level-0 sweeps.
+struct ClassTimer {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  ClassTimer() {
+    for (auto &e : ev) MGCD_HIP(hipEventCreate(&e));
+  }
+  ~ClassTimer() {
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void add(mgcd_stats &s) {  // after the sweep has completed
+    for (int q = 0; q < 3; ++q) {
+      float ms = 0;
+      MGCD_HIP(hipEventElapsedTime(&ms, ev[q], ev[q + 1]));
+      s.ms_l0_kernel[q] += ms;
+    }
+    s.l0_sweeps += 1;
+  }
+};
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t st;
+  explicit Timer(hipStream_t s) : st(s) {
+    MGCD_HIP(hipEventCreate(&a));
+    MGCD_HIP(hipEventCreate(&b));
+  }
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  void start() { MGCD_HIP(hipEventRecord(a, st)); }
+  float stop() {  // synchronises
+    MGCD_HIP(hipEventRecord(b, st));
+    MGCD_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    MGCD_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  }
+};
+
+static void check_params(const mgcd_params *p) {
+  if (!p) throw Error(MGCD_E_ARG, "params is null");
+  if (p->mode < 0 || p->mode > 3) throw Error(MGCD_E_UNSUPPORTED, "unknown sketch mode");
+  auto okk = [](int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16; };
+  if (p->mode != MGCD_MODE_EXACT && (!okk(p->k) || !okk(p->k_aggregate)))
+    throw Error(MGCD_E_UNSUPPORTED, "k and k_aggregate must be 1, 2, 4, 8 or 16");
+  if (p->chunk_len < 1) throw Error(MGCD_E_ARG, "chunk_len must be >= 1");
+  if (p->max_iterations < 1 || p->max_passes < 1) throw Error(MGCD_E_ARG, "iteration limits must be >= 1");
+  if (!(p->tolerance >= 0.0) || !(p->tolerance_drop > 0.0) || !(p->aggregation_tolerance >= 0.0))
+    throw Error(MGCD_E_ARG, "bad tolerance");
+}
+
+static Graph view(const mgcd_csr *g) {
+  if (!g) throw Error(MGCD_E_ARG, "graph is null");
+  if (g->n < 0 || g->nnz < 0) throw Error(MGCD_E_ARG, "negative graph size");
+  if (g->n > 0 && (!g->offsets)) throw Error(MGCD_E_ARG, "offsets is null");
+  if (g->nnz > 0 && (!g->indices || !g->weights)) throw Error(MGCD_E_ARG, "indices/weights null");
+  return Graph{g->n, g->nnz, g->offsets, g->indices, g->weights};
+}
+
+template <typename T>
+static T read_dev(const T *p, hipStream_t st) {
+  T h{};
+  MGCD_HIP(hipMemcpyAsync(&h, p, sizeof(T), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  return h;
+}
+
+// Degrees, W, optional validation.  Returns W.
+static uint64_t prepare(const Graph &g, const mgcd_params *p, uint32_t *K, Arena &a, hipStream_t st) {
+  unsigned long long *scr = a.take<unsigned long long>(2);
+  if (p && p->validate) {
+    launch_zero_u64(scr, 2, st);
+    launch_validate(g, scr, st);
+    if (read_dev(scr, st) != 0) throw Error(MGCD_E_GRAPH, "CSR failed validation");
+  }
+  launch_degrees(g, K, scr + 1, st);
+  uint64_t W = read_dev(scr + 1, st);
+  if (W >= (1ull << 31)) throw Error(MGCD_E_OVERFLOW, "total edge weight must be below 2^31");
+  return W;
+}
+
+static void require_labels(const int32_t *C, int64_t n, int64_t limit, Arena &a, hipStream_t st,
+                           const char *what) {
+  unsigned long long *flag = a.take<unsigned long long>(1);
+  launch_check_labels(C, n, limit, flag, st);
+  if (read_dev(flag, st) != 0) throw Error(MGCD_E_ARG, std::string(what) + " has values out of range");
+}
+
+struct Counts {
+  unsigned long long moved, prop, sumG;
+};
+
+static Counts read_counts(const unsigned long long *ctr, hipStream_t st) {
+  unsigned long long h[3];
+  MGCD_HIP(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  return Counts{h[0], h[1], h[2]};
+}
+
+// ---- LPA ------------------------------------------------------------------------------
+
+static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Arena &a, hipStream_t st,
+                    mgcd_stats *stats) {
+  check_params(p);
+  Graph g = view(gin);
+  const int32_t n = g.n;
+  Timer total(st), lm(st);
+  total.start();
+  uint32_t *K = a.take<uint32_t>(n);
+  prepare(g, p, K, a, st);
+  int32_t *Ca = a.take<int32_t>(n), *Cb = a.take<int32_t>(n);
+  unsigned long long *ctr = a.take<unsigned long long>(4);
+  launch_iota(Ca, n, st);
+  Schedule sch;
+  build_schedule(g, p->mode, p->k, p->chunk_len, sch, a, st);
+  mgcd_stats s{};
+  float ms_lm = 0;
+  ClassTimer ct;
+  for (int it = 0; it < p->max_iterations && n > 0; ++it) {
+    launch_zero_u64(ctr, 3, st);
+    SweepArgs args{g, Ca, nullptr, K, nullptr, 0, 0, Cb, nullptr, ctr};
+    lm.start();
+    launch_sweep(args, sch, ALGO_LPA, p->mode, p->k, p->chunk_len, st, ct.ev);
+    ms_lm += lm.stop();
+    ct.add(s);
+    Counts c = read_counts(ctr, st);
+    std::swap(Ca, Cb);
+    s.iterations += 1;
+    s.edges_scanned += g.nnz;
+    s.moved_last = (int64_t)c.moved;
+    if ((double)c.moved <= p->tolerance * (double)n) break;
+  }
+  s.communities = canonical(Ca, n, out, a, st);
+  s.passes = 1;
+  s.ms_local_move = ms_lm;
+  s.ms_total = total.stop();
+  if (stats) *stats = s;
+}
+
+// ---- Louvain / Leiden -------------------------------------------------------------------
+
+static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Arena &a,
+                       hipStream_t st, mgcd_stats *stats) {
+  check_params(p);
+  Graph g0 = view(gin);
+  const int32_t n = g0.n;
+  const int64_t nnz = g0.nnz;
+  Timer total(st), tm(st);
+  total.start();
+  mgcd_stats s{};
+  uint32_t *Kbuf[2] = {a.take<uint32_t>(n), a.take<uint32_t>(n)};
+  const uint64_t W = prepare(g0, p, Kbuf[0], a, st);
+  int32_t *top = a.take<int32_t>(n);
+  int32_t *Ca = a.take<int32_t>(n), *Cb = a.take<int32_t>(n);
+  int32_t *D = a.take<int32_t>(n), *Dc = a.take<int32_t>(n);
+  uint32_t *Sig = a.take<uint32_t>(n);
+  int32_t *size = a.take<int32_t>(n);
+  int32_t *prop = leiden ? a.take<int32_t>(n) : nullptr;
+  int32_t *nprop = leiden ? a.take<int32_t>(n) : nullptr;
+  int32_t *from = leiden ? a.take<int32_t>(n) : nullptr;
+  unsigned long long *ctr = a.take<unsigned long long>(4);
+  struct Slot {
+    int64_t *off;
+    int32_t *idx;
+    uint32_t *w;
+  } slot[2];
+  for (int q = 0; q < 2; ++q) {
+    slot[q].off = a.take<int64_t>((int64_t)n + 1);
+    slot[q].idx = a.take<int32_t>(nnz);
+    slot[q].w = a.take<uint32_t>(nnz);
+  }
+  launch_iota(top, n, st);
+  launch_iota(Ca, n, st);
+  Graph cur = g0;
+  int kcur = 0, next_slot = 0;
+  double tol = p->tolerance;
+  float ms_lm = 0, ms_ref = 0, ms_agg = 0;
+  const double WW = (double)W * (double)W;
+  ClassTimer ct;
+  for (int pass = 0; pass < p->max_passes && n > 0; ++pass) {
+    const int32_t nl = cur.n;
+    uint32_t *K = Kbuf[kcur];
+    s.passes += 1;
+    size_t mark = a.mark();
+    Schedule sch;
+    tm.start();
+    build_schedule(cur, p->mode, p->k, p->chunk_len, sch, a, st);
+    if (!leiden) launch_iota(Ca, nl, st);
+    launch_community_totals(Ca, K, Sig, size, nl, st);
+    ms_lm += tm.stop();
+    for (int it = 0; it < p->max_iterations; ++it) {
+      launch_zero_u64(ctr, 3, st);
+      SweepArgs args{cur, Ca, nullptr, K, Sig, W, (it % 2 == 0) ? -1 : 1, Cb, nullptr, ctr};
+      tm.start();
+      launch_sweep(args, sch, ALGO_MOVE, p->mode, p->k, p->chunk_len, st, pass == 0 ? ct.ev : nullptr);
+      ms_lm += tm.stop();
+      if (pass == 0) ct.add(s);
+      Counts c = read_counts(ctr, st);
+      s.iterations += 1;
+      s.edges_scanned += cur.nnz;
+      s.moved_last = (int64_t)c.moved;
+      if (c.prop == 0) break;
+      launch_apply_moves(Ca, Cb, K, Sig, size, nl, st);
+      std::swap(Ca, Cb);
+      if (2.0 * (double)c.sumG <= tol * WW) break;
+    }
+    int32_t m;
+    bool last;
+    if (leiden) {
+      tm.start();
+      SweepArgs r{cur, nullptr, Ca, K, K, W, 0, prop, nullptr, ctr};
+      launch_zero_u64(ctr, 3, st);
+      launch_sweep(r, sch, ALGO_REFINE, p->mode, p->k, p->chunk_len, st);
+      launch_refine_accept(prop, nprop, from, Cb, nl, st);  // Cb <- refined R
+      ms_ref += tm.stop();
+      a.release(mark);
+      tm.start();
+      m = renumber(Cb, nl, D, a, st);
+      last = pass == p->max_passes - 1 || (double)m > p->aggregation_tolerance * (double)nl;
+      if (last) {
+        launch_compose(top, Ca, top, n, st);  // final community of every input vertex
+        ms_agg += tm.stop();
+        break;
+      }
+      renumber(Ca, nl, Dc, a, st);
+      launch_compose(top, D, top, n, st);
+    } else {
+      a.release(mark);
+      tm.start();
+      m = renumber(Ca, nl, D, a, st);
+      launch_compose(top, D, top, n, st);
+      last = pass == p->max_passes - 1 || (double)m > p->aggregation_tolerance * (double)nl;
+      if (last) {
+        ms_agg += tm.stop();
+        break;
+      }
+    }
+    Slot &sl = slot[next_slot];
+    int64_t nnz2 = aggregate(cur, D, m, p->mode, p->k_aggregate, p->chunk_len, leiden ? 1 : 0, sl.off,
+                             sl.idx, sl.w, a, st);
+    launch_group_sums(D, K, Kbuf[1 - kcur], nl, m, st);
+    if (leiden) {
+      launch_scatter_labels(D, Dc, Cb, nl, st);  // super-vertex starts in its community
+      std::swap(Ca, Cb);
+    }
+    ms_agg += tm.stop();
+    cur = Graph{m, nnz2, sl.off, sl.idx, sl.w};
+    next_slot = 1 - next_slot;
+    kcur = 1 - kcur;
+    tol /= p->tolerance_drop;
+  }
+  s.communities = canonical(top, n, out, a, st);
+  s.ms_local_move = ms_lm;
+  s.ms_refine = ms_ref;
+  s.ms_aggregate = ms_agg;
+  s.ms_total = total.stop();
+  if (stats) *stats = s;
+}
+
+// ---- workspace ---------------------------------------------------------------------------
+
+static size_t workspace_bytes(int32_t algo, int32_t n, int64_t nnz, const mgcd_params *p) {
+  const int mode = p->mode;
+  const int64_t L = p->chunk_len > 0 ? p->chunk_len : 1;
+  size_t fixed = (size_t)n * 4 * 16 + 64 * 1024;
+  if (algo != MGCD_ALGO_LPA) fixed += 2 * ((size_t)(n + 1) * 8 + (size_t)nnz * 8) + 4096;
+  size_t sched = schedule_ws_bytes(n, nnz, mode, p->k, L);
+  size_t agg = algo == MGCD_ALGO_LPA ? 0 : aggregate_ws_bytes(n, nnz, mode, p->k_aggregate, L);
+  size_t misc = (size_t)n * (4 + 4 + 8 + 8) + scan_ws_bytes((int64_t)n + 1) + 16 * 1024;
+  size_t phase = sched > agg ? sched : agg;
+  return fixed + phase + misc + (1u << 20);
+}
+
+}  // namespace mgcd
+
+// ---- C ABI ---------------------------------------------------------------------------------
+
+using namespace mgcd;
+
+template <typename F>
+static int guarded(F &&f) {
+  try {
+    g_last_error.clear();
+    f();
+    return MGCD_OK;
+  } catch (const Error &e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return MGCD_E_ARG;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return MGCD_E_ARG;
+  }
+}
+
+static Arena make_arena(void *ws, size_t bytes) {
+  if (!ws && bytes) throw Error(MGCD_E_ARG, "workspace is null");
+  Arena a;
+  a.base = (char *)ws;
+  a.cap = bytes;
+  return a;
+}
+
+extern "C" {
+
+void mgcd_default_params(int32_t algo, mgcd_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->mode = MGCD_MODE_ALG1;
+  p->k = algo == MGCD_ALGO_LEIDEN ? 16 : 8;
+  p->k_aggregate = p->k;
+  p->max_iterations = 20;
+  p->max_passes = 10;
+  p->validate = 0;
+  p->chunk_len = 128;
+  p->tolerance = algo == MGCD_ALGO_LPA ? 0.05 : 0.01;
+  p->tolerance_drop = 10.0;
+  p->aggregation_tolerance = 0.8;
+}
+
+size_t mgcd_workspace_bytes(int32_t algo, int32_t n, int64_t nnz, const mgcd_params *p) {
+  mgcd_params d;
+  if (!p) {
+    mgcd_default_params(algo, &d);
+    p = &d;
+  }
+  return workspace_bytes(algo, n < 0 ? 0 : n, nnz < 0 ? 0 : nnz, p);
+}
+
+static int run_checked(int32_t algo, const mgcd_csr *g, const mgcd_params *p, int32_t *out, void *ws,
+                       size_t ws_bytes, mgcd_stats *stats, void *stream) {
+  return guarded([&] {
+    if (!g || !p) throw Error(MGCD_E_ARG, "null argument");
+    if (g->n > 0 && !out) throw Error(MGCD_E_ARG, "communities_out is null");
+    check_params(p);
+    size_t need = workspace_bytes(algo, g->n, g->nnz, p);
+    if (ws_bytes < need)
+      throw Error(MGCD_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    Arena a = make_arena(ws, ws_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    if (algo == MGCD_ALGO_LPA)
+      run_lpa(g, p, out, a, st, stats);
+    else
+      run_levels(algo == MGCD_ALGO_LEIDEN, g, p, out, a, st, stats);
+  });
+}
+
+int lpa_run(const mgcd_csr *g, const mgcd_params *p, int32_t *out, void *ws, size_t ws_bytes,
+            mgcd_stats *stats, void *stream) {
+  return run_checked(MGCD_ALGO_LPA, g, p, out, ws, ws_bytes, stats, stream);
+}
+
+int louvain_run(const mgcd_csr *g, const mgcd_params *p, int32_t *out, void *ws, size_t ws_bytes,
+                mgcd_stats *stats, void *stream) {
+  return run_checked(MGCD_ALGO_LOUVAIN, g, p, out, ws, ws_bytes, stats, stream);
+}
+
+int leiden_run(const mgcd_csr *g, const mgcd_params *p, int32_t *out, void *ws, size_t ws_bytes,
+               mgcd_stats *stats, void *stream) {
+  return run_checked(MGCD_ALGO_LEIDEN, g, p, out, ws, ws_bytes, stats, stream);
+}
+
+int modularity(const mgcd_csr *gin, const int32_t *C, double *q, void *ws, size_t ws_bytes,
+               void *stream) {
+  return guarded([&] {
+    if (!q) throw Error(MGCD_E_ARG, "q is null");
+    Graph g = view(gin);
+    if (g.n > 0 && !C) throw Error(MGCD_E_ARG, "communities is null");
+    size_t need = (size_t)g.n * 8 + 64 * 1024;
+    if (ws_bytes < need) throw Error(MGCD_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    if (g.n == 0) {
+      *q = 0.0;
+      return;
+    }
+    Arena a = make_arena(ws, ws_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    require_labels(C, g.n, g.n, a, st, "communities");
+    uint32_t *K = a.take<uint32_t>(g.n);
+    unsigned long long *Wd = a.take<unsigned long long>(1);
+    unsigned long long *terms = a.take<unsigned long long>(2);
+    launch_degrees(g, K, Wd, st);
+    modularity_terms(g, C, K, terms, a, st);
+    unsigned long long h[2];
+    MGCD_HIP(hipMemcpyAsync(h, terms, sizeof(h), hipMemcpyDeviceToHost, st));
+    uint64_t W = read_dev(Wd, st);
+    if (W == 0) {
+      *q = 0.0;
+      return;
+    }
+    const double Wd_ = (double)W;
+    *q = (double)h[0] / Wd_ - (double)h[1] / (Wd_ * Wd_);
+  });
+}
+
+int mgcd_move_sweep(const mgcd_csr *gin, const mgcd_params *p, int32_t algo, const int32_t *C,
+                    int32_t direction, int32_t *C_new, int64_t *gain, int64_t *counters, void *ws,
+                    size_t ws_bytes, void *stream) {
+  return guarded([&] {
+    check_params(p);
+    Graph g = view(gin);
+    if (algo != MGCD_ALGO_LPA && algo != MGCD_ALGO_LOUVAIN) throw Error(MGCD_E_ARG, "algo must be LPA or LOUVAIN");
+    if (g.n > 0 && (!C || !C_new)) throw Error(MGCD_E_ARG, "membership is null");
+    size_t need = workspace_bytes(MGCD_ALGO_LPA, g.n, g.nnz, p);
+    if (ws_bytes < need) throw Error(MGCD_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    Arena a = make_arena(ws, ws_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    require_labels(C, g.n, g.n, a, st, "C");
+    uint32_t *K = a.take<uint32_t>(g.n);
+    uint64_t W = prepare(g, p, K, a, st);
+    uint32_t *Sig = a.take<uint32_t>(g.n);
+    int32_t *size = a.take<int32_t>(g.n);
+    unsigned long long *ctr = a.take<unsigned long long>(4);
+    launch_community_totals(C, K, Sig, size, g.n, st);
+    Schedule sch;
+    build_schedule(g, p->mode, p->k, p->chunk_len, sch, a, st);
+    launch_zero_u64(ctr, 3, st);
+    SweepArgs args{g, C, nullptr, K, Sig, W, direction < 0 ? -1 : direction > 0 ? 1 : 0, C_new, gain, ctr};
+    launch_sweep(args, sch, algo == MGCD_ALGO_LPA ? ALGO_LPA : ALGO_MOVE, p->mode, p->k, p->chunk_len, st);
+    Counts c = read_counts(ctr, st);
+    if (counters) {
+      counters[0] = (int64_t)c.moved;
+      counters[1] = (int64_t)c.prop;
+      counters[2] = (int64_t)c.sumG;
+    }
+  });
+}
+
+int mgcd_refine(const mgcd_csr *gin, const mgcd_params *p, const int32_t *bound, int32_t *R, void *ws,
+                size_t ws_bytes, void *stream) {
+  return guarded([&] {
+    check_params(p);
+    Graph g = view(gin);
+    if (g.n > 0 && (!bound || !R)) throw Error(MGCD_E_ARG, "bound or R is null");
+    size_t need = workspace_bytes(MGCD_ALGO_LPA, g.n, g.nnz, p);
+    if (ws_bytes < need) throw Error(MGCD_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    Arena a = make_arena(ws, ws_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *K = a.take<uint32_t>(g.n);
+    uint64_t W = prepare(g, p, K, a, st);
+    int32_t *prop = a.take<int32_t>(g.n), *nprop = a.take<int32_t>(g.n), *from = a.take<int32_t>(g.n);
+    unsigned long long *ctr = a.take<unsigned long long>(4);
+    Schedule sch;
+    build_schedule(g, p->mode, p->k, p->chunk_len, sch, a, st);
+    launch_zero_u64(ctr, 3, st);
+    SweepArgs r{g, nullptr, bound, K, K, W, 0, prop, nullptr, ctr};
+    launch_sweep(r, sch, ALGO_REFINE, p->mode, p->k, p->chunk_len, st);
+    launch_refine_accept(prop, nprop, from, R, g.n, st);
+    MGCD_HIP(hipStreamSynchronize(st));
+  });
+}
+
+int mgcd_aggregate(const mgcd_csr *gin, const mgcd_params *p, const int32_t *D, int32_t m,
+                   int32_t symmetric, int64_t *out_off, int32_t *out_idx, uint32_t *out_w,
+                   int64_t *out_nnz, void *ws, size_t ws_bytes, void *stream) {
+  return guarded([&] {
+    check_params(p);
+    Graph g = view(gin);
+    if (m < 0 || m > g.n) throw Error(MGCD_E_ARG, "m out of range");
+    if (!out_off || (g.nnz > 0 && (!out_idx || !out_w)) || !out_nnz) throw Error(MGCD_E_ARG, "null output");
+    size_t need = aggregate_ws_bytes(g.n, g.nnz, p->mode, p->k_aggregate, p->chunk_len) + 64 * 1024;
+    if (ws_bytes < need) throw Error(MGCD_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    Arena a = make_arena(ws, ws_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    require_labels(D, g.n, m, a, st, "D");
+    *out_nnz = aggregate(g, D, m, p->mode, p->k_aggregate, p->chunk_len, symmetric ? 1 : 0, out_off,
+                         out_idx, out_w, a, st);
+    MGCD_HIP(hipStreamSynchronize(st));
+  });
+}
+
+const char *mgcd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,719 @@
+// Local-moving sweeps: LPA iterations (Section 4.3), Louvain/Leiden local moving
+// (Sections 4.1-4.2, Fig. 2) and Leiden refinement, with the weighted Misra-Gries
+// sketch (Appendix A.1, Algorithm 1) or an exact table (Section 4, Fig. 1).
+//
+// Per vertex i with current community d = C[i]:
+//   pass 1  stream the row (self excluded; refinement: same bound only), key C[j],
+//           into a K-slot sketch; rows longer than L positions are cut into chunks
+//           of L, each sketched from empty, then merged pairwise left to right,
+//           level by level (odd last moves up);
+//   pass 2  exact K_{i->c} of every positive slot and K_{i->d} (skipped when the
+//           sketch lost no weight: its values are then exact and complete);
+//   decide  LPA: largest K_{i->c}, lowest c on ties.  Louvain/Leiden: largest
+//           G = W (K_ic - K_id) - K_i (K_i + Sigma_c - Sigma_d) (Eq. 2 times W^2/2),
+//           c != d, G > 0, lowest c on ties; applied only in the sweep's direction.
+//
+// Mapping on CDNA: a row that fits one chunk is streamed by one lane with the
+// sketch in VGPRs (vertices ordered heavy-first so a wave's lanes have similar
+// trip counts); each chunk of a longer row is one lane's stream, and one workgroup
+// per long row merges its chunk sketches in LDS and runs pass 2 with coalesced,
+// block-strided reads.
+#include "move.hpp"
+#include "primitives.hpp"
+#include "sketch.hpp"
+
+namespace mgcd {
+
+// ---- decision ---------------------------------------------------------------------
+
+struct Counters {
+  uint32_t moved = 0, prop = 0;
+  uint64_t sumG = 0;
+};
+
+template <int ALGO>
+__device__ inline int32_t community_of_self(const SweepArgs &a, int32_t i) {
+  return ALGO == ALGO_REFINE ? i : a.C[i];
+}
+
+// Evaluate one candidate community c with exact linking weight kc; keep the best.
+template <int ALGO>
+__device__ inline void consider(const SweepArgs &a, int32_t d, int64_t Ki, int64_t Sd, uint32_t kd,
+                                int32_t c, uint32_t kc, int32_t &best, int64_t &bestG) {
+  if (ALGO == ALGO_LPA) {
+    int64_t G = (int64_t)kc;
+    if (best < 0 || G > bestG || (G == bestG && c < best)) {
+      best = c;
+      bestG = G;
+    }
+  } else {
+    if (c == d) return;
+    int64_t G = (int64_t)a.W * ((int64_t)kc - (int64_t)kd) -
+                Ki * (Ki + (int64_t)a.Sig[c] - Sd);
+    if (G > 0 && (best < 0 || G > bestG || (G == bestG && c < best))) {
+      best = c;
+      bestG = G;
+    }
+  }
+}
+
+template <int ALGO>
+__device__ inline void finish(const SweepArgs &a, int32_t i, int32_t d, int32_t best, int64_t bestG,
+                              Counters &ct) {
+  int32_t target = d;
+  if (ALGO == ALGO_LPA) {
+    if (best >= 0) target = best;
+  } else if (best >= 0) {
+    ct.prop += 1;
+    ct.sumG += (uint64_t)bestG;
+    bool ok = a.dir == 0 || (a.dir < 0 ? best < d : best > d);
+    if (ok) target = best;
+  }
+  a.Cnew[i] = target;
+  ct.moved += target != d;
+  if (ALGO != ALGO_LPA && a.gain) a.gain[i] = best >= 0 ? bestG : 0;
+}
+
+__device__ inline void flush_counters(const SweepArgs &a, Counters ct) {
+  __shared__ unsigned long long red[3][4];
+  unsigned long long m = wave_sum((unsigned long long)ct.moved);
+  unsigned long long p = wave_sum((unsigned long long)ct.prop);
+  unsigned long long g = wave_sum((unsigned long long)ct.sumG);
+  int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    red[0][w] = m;
+    red[1][w] = p;
+    red[2][w] = g;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long s = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] +
+                           red[threadIdx.x][3];
+    if (s) atomicAdd(&a.ctr[threadIdx.x], s);
+  }
+}
+
+// Key of entry (i -> j) in the stream of vertex i, or EMPTY when Algorithm 1's
+// early exits skip it (self-loop; refinement across bounds).
+template <int ALGO>
+__device__ inline uint32_t stream_key(const SweepArgs &a, int32_t i, int32_t j, int32_t bi) {
+  if (j == i) return EMPTY;
+  if (ALGO == ALGO_REFINE) return a.bound[j] == bi ? (uint32_t)j : EMPTY;
+  return (uint32_t)a.C[j];
+}
+
+// ---- MG: rows that fit one chunk (thread per vertex) --------------------------------
+
+template <int K, int ALGO, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_move_single(SweepArgs a, const int32_t *__restrict__ list, int64_t count) {
+  Counters ct;
+  int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (t < count) {
+    const int32_t i = list[t];
+    const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
+    const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
+    const int32_t d = community_of_self<ALGO>(a, i);
+    RegSketch<K, MODE> s;
+    s.reset();
+    for (int64_t e = lo; e < hi; ++e) {
+      uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
+      if (c != EMPTY) s.update(c, a.g.w[e]);
+    }
+    s.finalize();
+    uint32_t ex[K];
+    uint32_t kd = 0;
+    if (!s.lossy) {
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+        ex[p] = s.val[p];
+        kd += s.key[p] == (uint32_t)d ? s.val[p] : 0u;
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < K; ++p) ex[p] = 0;
+      for (int64_t e = lo; e < hi; ++e) {
+        uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
+        if (c == EMPTY) continue;
+        uint32_t w = a.g.w[e];
+#pragma unroll
+        for (int p = 0; p < K; ++p) ex[p] += s.key[p] == c ? w : 0u;
+        kd += c == (uint32_t)d ? w : 0u;
+      }
+    }
+    int32_t best = -1;
+    int64_t bestG = 0;
+    const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+    const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+#pragma unroll
+    for (int p = 0; p < K; ++p)
+      if (s.key[p] != EMPTY) consider<ALGO>(a, d, Ki, Sd, kd, (int32_t)s.key[p], ex[p], best, bestG);
+    finish<ALGO>(a, i, d, best, bestG, ct);
+  }
+  flush_counters(a, ct);
+}
+
+// ---- MG: long rows -----------------------------------------------------------------
+
+// One lane per chunk of L positions of a long row: Algorithm 1 from an empty sketch.
+template <int K, int ALGO, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_move_chunks(SweepArgs a, const int32_t *__restrict__ multi, const int32_t *__restrict__ owner,
+                  const int64_t *__restrict__ cstart, int64_t nchunks, int64_t L, Pair *sk,
+                  uint32_t *skflag) {
+  int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (q >= nchunks) return;
+  const int32_t m = owner[q];
+  const int32_t i = multi[m];
+  const int64_t c = q - cstart[m];
+  const int64_t rlo = a.g.off[i], rhi = a.g.off[i + 1];
+  const int64_t lo = rlo + c * L;
+  const int64_t hi = lo + L < rhi ? lo + L : rhi;
+  const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
+  RegSketch<K, MODE> s;
+  s.reset();
+  for (int64_t e = lo; e < hi; ++e) {
+    uint32_t key = stream_key<ALGO>(a, i, a.g.idx[e], bi);
+    if (key != EMPTY) s.update(key, a.g.w[e]);
+  }
+  s.finalize();
+#pragma unroll
+  for (int p = 0; p < K; ++p) sk[q * K + p] = Pair{s.key[p], s.val[p]};
+  skflag[q] = s.lossy ? 1u : 0u;
+}
+
+// One workgroup per long row: merge its chunk sketches, pass 2 over the row with
+// block-strided (coalesced) reads, decide.
+template <int K, int ALGO>
+__global__ void __launch_bounds__(BLOCK)
+    k_move_multi(SweepArgs a, const int32_t *__restrict__ multi, const int64_t *__restrict__ cstart,
+                 Pair *sk, const uint32_t *__restrict__ skflag) {
+  __shared__ Pair lds[BLOCK * K];
+  __shared__ uint32_t red[K + 1][4];
+  __shared__ int flag_any;
+  const int t = threadIdx.x;
+  const int32_t m = blockIdx.x;
+  const int32_t i = multi[m];
+  const int64_t cb = cstart[m], nc = cstart[m + 1] - cb;
+  if (t == 0) flag_any = 0;
+  __syncthreads();
+  bool f = false;
+  for (int64_t q = t; q < nc; q += BLOCK) f |= skflag[cb + q] != 0;
+  if (f) flag_any = 1;
+  bool lossy = tree_reduce<K>(sk, cb, nc, lds);
+  lossy |= flag_any != 0;  // flag_any settled by the barriers inside tree_reduce
+  uint32_t key[K], ex[K];
+#pragma unroll
+  for (int p = 0; p < K; ++p) {
+    Pair x = lds[p];
+    key[p] = x.val > 0 ? x.key : EMPTY;
+    ex[p] = x.val;
+  }
+  const int32_t d = community_of_self<ALGO>(a, i);
+  uint32_t kd = 0;
+  if (!lossy) {
+#pragma unroll
+    for (int p = 0; p < K; ++p) kd += key[p] == (uint32_t)d ? ex[p] : 0u;
+  } else {
+    const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
+    const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
+#pragma unroll
+    for (int p = 0; p < K; ++p) ex[p] = 0;
+    for (int64_t e = lo + t; e < hi; e += BLOCK) {
+      uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
+      if (c == EMPTY) continue;
+      uint32_t w = a.g.w[e];
+#pragma unroll
+      for (int p = 0; p < K; ++p) ex[p] += key[p] == c ? w : 0u;
+      kd += c == (uint32_t)d ? w : 0u;
+    }
+    const int wv = t / WAVE;
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      uint32_t s = wave_sum(ex[p]);
+      if (lane_id() == 0) red[p][wv] = s;
+    }
+    uint32_t s = wave_sum(kd);
+    if (lane_id() == 0) red[K][wv] = s;
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < K; ++p) ex[p] = red[p][0] + red[p][1] + red[p][2] + red[p][3];
+    kd = red[K][0] + red[K][1] + red[K][2] + red[K][3];
+  }
+  if (t == 0) {
+    Counters ct;
+    int32_t best = -1;
+    int64_t bestG = 0;
+    const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+    const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+#pragma unroll
+    for (int p = 0; p < K; ++p)
+      if (key[p] != EMPTY) consider<ALGO>(a, d, Ki, Sd, kd, (int32_t)key[p], ex[p], best, bestG);
+    finish<ALGO>(a, i, d, best, bestG, ct);
+    if (ct.moved) atomicAdd(&a.ctr[0], (unsigned long long)ct.moved);
+    if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
+    if (ct.sumG) atomicAdd(&a.ctr[2], (unsigned long long)ct.sumG);
+  }
+}
+
+// ---- exact mode ----------------------------------------------------------------------
+
+// Rows of at most EXACT_T0 entries: one lane per vertex; K_{i->c} of each distinct
+// key, summed at its first occurrence in the row.
+template <int ALGO>
+__global__ void __launch_bounds__(BLOCK)
+    k_exact_small(SweepArgs a, const int32_t *__restrict__ list, int64_t count) {
+  Counters ct;
+  int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (t < count) {
+    const int32_t i = list[t];
+    const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
+    const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
+    const int32_t d = community_of_self<ALGO>(a, i);
+    uint32_t kd = 0;
+    for (int64_t e = lo; e < hi; ++e)
+      kd += stream_key<ALGO>(a, i, a.g.idx[e], bi) == (uint32_t)d ? a.g.w[e] : 0u;
+    int32_t best = -1;
+    int64_t bestG = 0;
+    const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+    const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+    for (int64_t e = lo; e < hi; ++e) {
+      uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
+      if (c == EMPTY) continue;
+      bool first = true;
+      for (int64_t f = lo; f < e && first; ++f) first = stream_key<ALGO>(a, i, a.g.idx[f], bi) != c;
+      if (!first) continue;
+      uint32_t kc = 0;
+      for (int64_t f = e; f < hi; ++f) kc += stream_key<ALGO>(a, i, a.g.idx[f], bi) == c ? a.g.w[f] : 0u;
+      consider<ALGO>(a, d, Ki, Sd, kd, (int32_t)c, kc, best, bestG);
+    }
+    finish<ALGO>(a, i, d, best, bestG, ct);
+  }
+  flush_counters(a, ct);
+}
+
+__device__ inline uint32_t hash_slot(uint32_t c, uint32_t mask) {
+  return (c * 0x9E3779B1u) & mask;  // Fibonacci hashing, low bits
+}
+
+// A table slot filled by other threads' atomics: global tables are read at device
+// scope (past the CU's L1), LDS tables directly.
+template <bool GLOBAL>
+__device__ inline Pair load_slot(Pair *p) {
+  if constexpr (GLOBAL) {
+    uint32_t k = __hip_atomic_load(&p->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t v = __hip_atomic_load(&p->val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return Pair{k, v};
+  } else {
+    return *p;
+  }
+}
+
+// Workgroup per vertex with an open-addressing table (linear probing) in LDS
+// (CAP slots) or, when GLOBAL, in this vertex's region of global memory.
+template <int ALGO, int CAP, bool GLOBAL>
+__global__ void __launch_bounds__(BLOCK)
+    k_exact_table(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
+                  Pair *htab) {
+  __shared__ Pair ltab[GLOBAL ? 1 : CAP];
+  __shared__ uint32_t kd_s;
+  __shared__ int32_t bc[4];
+  __shared__ int64_t bg[4];
+  const int t = threadIdx.x;
+  const int32_t i = list[blockIdx.x];
+  const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
+  Pair *tab;
+  uint32_t cap;
+  if (GLOBAL) {
+    tab = htab + hbase[blockIdx.x];
+    cap = (uint32_t)(hbase[blockIdx.x + 1] - hbase[blockIdx.x]);
+  } else {
+    tab = ltab;
+    cap = CAP;
+  }
+  for (uint32_t x = t; x < cap; x += BLOCK) tab[x] = Pair{EMPTY, 0u};
+  if (t == 0) kd_s = 0;
+  if (GLOBAL) __threadfence();
+  __syncthreads();
+  const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
+  const uint32_t mask = cap - 1;
+  for (int64_t e = lo + t; e < hi; e += BLOCK) {
+    uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
+    if (c == EMPTY) continue;
+    uint32_t w = a.g.w[e];
+    uint32_t h = hash_slot(c, mask);
+    while (true) {
+      uint32_t prev = atomicCAS(&tab[h].key, EMPTY, c);
+      if (prev == EMPTY || prev == c) {
+        atomicAdd(&tab[h].val, w);
+        break;
+      }
+      h = (h + 1) & mask;
+    }
+  }
+  if (GLOBAL) __threadfence();
+  __syncthreads();
+  const int32_t d = community_of_self<ALGO>(a, i);
+  for (uint32_t x = t; x < cap; x += BLOCK) {
+    Pair p = load_slot<GLOBAL>(&tab[x]);
+    if (p.key == (uint32_t)d) kd_s = p.val;
+  }
+  __syncthreads();
+  const uint32_t kd = kd_s;
+  int32_t best = -1;
+  int64_t bestG = 0;
+  const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+  const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+  for (uint32_t x = t; x < cap; x += BLOCK) {
+    Pair p = load_slot<GLOBAL>(&tab[x]);
+    if (p.key != EMPTY) consider<ALGO>(a, d, Ki, Sd, kd, (int32_t)p.key, p.val, best, bestG);
+  }
+  // block arg-max: larger gain first, then lower community id
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    int32_t ob = __shfl_xor(best, o);
+    int64_t og = __shfl_xor(bestG, o);
+    bool take = ob >= 0 && (best < 0 || og > bestG || (og == bestG && ob < best));
+    best = take ? ob : best;
+    bestG = take ? og : bestG;
+  }
+  if (lane_id() == 0) {
+    bc[t / WAVE] = best;
+    bg[t / WAVE] = bestG;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int q = 1; q < 4; ++q) {
+      bool take = bc[q] >= 0 && (best < 0 || bg[q] > bestG || (bg[q] == bestG && bc[q] < best));
+      best = take ? bc[q] : best;
+      bestG = take ? bg[q] : bestG;
+    }
+    Counters ct;
+    finish<ALGO>(a, i, d, best, bestG, ct);
+    if (ct.moved) atomicAdd(&a.ctr[0], (unsigned long long)ct.moved);
+    if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
+    if (ct.sumG) atomicAdd(&a.ctr[2], (unsigned long long)ct.sumG);
+  }
+}
+
+// ---- schedule ------------------------------------------------------------------------
+
+__global__ void k_schedule_keys(const int64_t *off, int32_t n, int mode, int64_t L, uint64_t *key,
+                                uint32_t *val, unsigned long long *cnt) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  int64_t deg = off[i + 1] - off[i];
+  int b = 0;
+  while (b < 63 && (deg >> b) != 0) ++b;  // bits of deg
+  uint64_t k;
+  if (mode == MODE_EXACT) {
+    int tier = deg <= EXACT_T0 ? 0 : deg <= EXACT_T1 ? 1 : deg <= EXACT_T2 ? 2 : 3;
+    k = tier == 0 ? (uint64_t)(64 - b) : (uint64_t)(128 + tier);
+    atomicAdd(&cnt[tier], 1ull);
+  } else {
+    bool single = deg <= L;
+    k = single ? (uint64_t)(64 - b) : 255ull;  // heavy rows first
+    atomicAdd(&cnt[single ? 0 : 1], 1ull);
+  }
+  key[i] = k;
+  val[i] = (uint32_t)i;
+}
+
+__global__ void k_chunk_counts(const int64_t *off, const int32_t *multi, int64_t nmulti, int64_t L,
+                               int64_t *nch) {
+  int64_t m = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (m >= nmulti) return;
+  int32_t i = multi[m];
+  nch[m] = (off[i + 1] - off[i] + L - 1) / L;
+}
+
+__global__ void k_chunk_owner(const int64_t *cstart, int64_t nmulti, int32_t *owner) {
+  int64_t m = blockIdx.x;
+  if (m >= nmulti) return;
+  for (int64_t q = cstart[m] + threadIdx.x; q < cstart[m + 1]; q += BLOCK) owner[q] = (int32_t)m;
+}
+
+__global__ void k_hash_caps(const int64_t *off, const int32_t *list, int64_t count, int64_t *cap) {
+  int64_t m = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (m >= count) return;
+  int32_t i = list[m];
+  int64_t need = 2 * (off[i + 1] - off[i]);
+  int64_t c = 1;
+  while (c < need) c <<= 1;
+  cap[m] = c;
+}
+
+__global__ void k_u32_from_u64(const uint32_t *v, int32_t *out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) out[i] = (int32_t)v[i];
+}
+
+static unsigned grid_for(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, BLOCK); }
+
+size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
+  size_t b = 0;
+  b += (size_t)n * (8 + 4) * 2 + 4096;         // sort keys/values, two buffers
+  b += radix_sort_ws_bytes(n) + 4096;
+  b += (size_t)n * 4 + 1024;                   // ordered list
+  if (mode == MODE_EXACT) {
+    b += (size_t)(n + 1) * 8 + scan_ws_bytes(n) + 1024;  // hash bases
+    b += (size_t)(4 * nnz + 64) * sizeof(Pair) + 1024;  // tables: cap <= 4*deg
+  } else {
+    int64_t chunks = nnz / (L > 0 ? L : 1) + n + 1;
+    b += (size_t)(n + 1) * 8 * 2 + scan_ws_bytes(n) + 2048;  // counts, cstart
+    b += (size_t)chunks * (4 + 4 + (size_t)k * sizeof(Pair)) + 4096;
+  }
+  return b + 64 * 1024;
+}
+
+void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Arena &a,
+                    hipStream_t st) {
+  const int32_t n = g.n;
+  s = Schedule{};
+  if (n == 0) return;
+  unsigned long long *cnt = a.take<unsigned long long>(4);
+  uint64_t *k0 = a.take<uint64_t>(n);
+  uint32_t *v0 = a.take<uint32_t>(n);
+  uint64_t *k1 = a.take<uint64_t>(n);
+  uint32_t *v1 = a.take<uint32_t>(n);
+  int32_t *order = a.take<int32_t>(n);
+  launch_zero_u64(cnt, 4, st);
+  k_schedule_keys<<<grid_for(n), BLOCK, 0, st>>>(g.off, n, mode, L, k0, v0, cnt);
+  MGCD_LAUNCHED();
+  bool flip = radix_sort_pairs(k0, v0, k1, v1, n, 8, a, st);
+  k_u32_from_u64<<<grid_for(n), BLOCK, 0, st>>>(flip ? v1 : v0, order, n);
+  MGCD_LAUNCHED();
+  unsigned long long h[4];
+  MGCD_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  if (mode == MODE_EXACT) {
+    int64_t pos = 0;
+    for (int q = 0; q < 4; ++q) {
+      s.tier[q] = order + pos;
+      s.ntier[q] = (int64_t)h[q];
+      pos += (int64_t)h[q];
+    }
+    if (s.ntier[3] > 0) {
+      int64_t c3 = s.ntier[3];
+      s.hbase = a.take<int64_t>(c3 + 1);
+      int64_t *caps = a.take<int64_t>(c3);
+      k_hash_caps<<<grid_for(c3), BLOCK, 0, st>>>(g.off, s.tier[3], c3, caps);
+      MGCD_LAUNCHED();
+      scan_i64(caps, s.hbase, c3, s.hbase + c3, a, st);
+      int64_t tot = 0;
+      MGCD_HIP(hipMemcpyAsync(&tot, s.hbase + c3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      MGCD_HIP(hipStreamSynchronize(st));
+      s.htab = a.take<Pair>(tot);
+    }
+    return;
+  }
+  s.single = order;
+  s.nsingle = (int64_t)h[0];
+  s.multi = order + s.nsingle;
+  s.nmulti = (int64_t)h[1];
+  if (s.nmulti > 0) {
+    int64_t *nch = a.take<int64_t>(s.nmulti);
+    s.cstart = a.take<int64_t>(s.nmulti + 1);
+    k_chunk_counts<<<grid_for(s.nmulti), BLOCK, 0, st>>>(g.off, s.multi, s.nmulti, L, nch);
+    MGCD_LAUNCHED();
+    scan_i64(nch, s.cstart, s.nmulti, s.cstart + s.nmulti, a, st);
+    MGCD_HIP(hipMemcpyAsync(&s.nchunks, s.cstart + s.nmulti, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+    s.owner = a.take<int32_t>(s.nchunks);
+    k_chunk_owner<<<(unsigned)s.nmulti, BLOCK, 0, st>>>(s.cstart, s.nmulti, s.owner);
+    MGCD_LAUNCHED();
+    s.sk = a.take<Pair>(s.nchunks * k);
+    s.skflag = a.take<uint32_t>(s.nchunks);
+  }
+}
+
+// ---- launch -------------------------------------------------------------------------
+
+static inline void mark(hipEvent_t *ev, int i, hipStream_t st) {
+  if (ev) MGCD_HIP(hipEventRecord(ev[i], st));
+}
+
+template <int K, int ALGO, int MODE>
+static void sweep_mg(const SweepArgs &a, const Schedule &s, int64_t L, hipStream_t st, hipEvent_t *ev) {
+  mark(ev, 0, st);
+  if (s.nsingle > 0) {
+    k_move_single<K, ALGO, MODE><<<grid_for(s.nsingle), BLOCK, 0, st>>>(a, s.single, s.nsingle);
+    MGCD_LAUNCHED();
+  }
+  mark(ev, 1, st);
+  if (s.nmulti > 0) {
+    k_move_chunks<K, ALGO, MODE><<<grid_for(s.nchunks), BLOCK, 0, st>>>(
+        a, s.multi, s.owner, s.cstart, s.nchunks, L, s.sk, s.skflag);
+    MGCD_LAUNCHED();
+  }
+  mark(ev, 2, st);
+  if (s.nmulti > 0) {
+    k_move_multi<K, ALGO><<<(unsigned)s.nmulti, BLOCK, 0, st>>>(a, s.multi, s.cstart, s.sk, s.skflag);
+    MGCD_LAUNCHED();
+  }
+  mark(ev, 3, st);
+}
+
+template <int ALGO>
+static void sweep_exact(const SweepArgs &a, const Schedule &s, hipStream_t st, hipEvent_t *ev) {
+  mark(ev, 0, st);
+  if (s.ntier[0] > 0) {
+    k_exact_small<ALGO><<<grid_for(s.ntier[0]), BLOCK, 0, st>>>(a, s.tier[0], s.ntier[0]);
+    MGCD_LAUNCHED();
+  }
+  mark(ev, 1, st);
+  if (s.ntier[1] > 0) {
+    k_exact_table<ALGO, 1024, false><<<(unsigned)s.ntier[1], BLOCK, 0, st>>>(a, s.tier[1], nullptr, nullptr);
+    MGCD_LAUNCHED();
+  }
+  if (s.ntier[2] > 0) {
+    k_exact_table<ALGO, 8192, false><<<(unsigned)s.ntier[2], BLOCK, 0, st>>>(a, s.tier[2], nullptr, nullptr);
+    MGCD_LAUNCHED();
+  }
+  mark(ev, 2, st);
+  if (s.ntier[3] > 0) {
+    k_exact_table<ALGO, 1, true><<<(unsigned)s.ntier[3], BLOCK, 0, st>>>(a, s.tier[3], s.hbase, s.htab);
+    MGCD_LAUNCHED();
+  }
+  mark(ev, 3, st);
+}
+
+template <int ALGO, int MODE>
+static void sweep_k(const SweepArgs &a, const Schedule &s, int k, int64_t L, hipStream_t st,
+                    hipEvent_t *ev) {
+  switch (k) {
+    case 1: sweep_mg<1, ALGO, MODE>(a, s, L, st, ev); break;
+    case 2: sweep_mg<2, ALGO, MODE>(a, s, L, st, ev); break;
+    case 4: sweep_mg<4, ALGO, MODE>(a, s, L, st, ev); break;
+    case 8: sweep_mg<8, ALGO, MODE>(a, s, L, st, ev); break;
+    case 16: sweep_mg<16, ALGO, MODE>(a, s, L, st, ev); break;
+    default: throw Error(-6, "k must be 1, 2, 4, 8 or 16");
+  }
+}
+
+template <int ALGO>
+static void sweep_algo(const SweepArgs &a, const Schedule &s, int mode, int k, int64_t L,
+                       hipStream_t st, hipEvent_t *ev) {
+  switch (mode) {
+    case MODE_EXACT: sweep_exact<ALGO>(a, s, st, ev); break;
+    case MODE_ALG1: sweep_k<ALGO, MODE_ALG1>(a, s, k, L, st, ev); break;
+    case MODE_UNCOND: sweep_k<ALGO, MODE_UNCOND>(a, s, k, L, st, ev); break;
+    case MODE_STD: sweep_k<ALGO, MODE_STD>(a, s, k, L, st, ev); break;
+    default: throw Error(-6, "unknown sketch mode");
+  }
+}
+
+void launch_sweep(const SweepArgs &a, const Schedule &s, int algo, int mode, int k, int64_t L,
+                  hipStream_t st, hipEvent_t *ev) {
+  switch (algo) {
+    case ALGO_LPA: sweep_algo<ALGO_LPA>(a, s, mode, k, L, st, ev); break;
+    case ALGO_MOVE: sweep_algo<ALGO_MOVE>(a, s, mode, k, L, st, ev); break;
+    case ALGO_REFINE: sweep_algo<ALGO_REFINE>(a, s, mode, k, L, st, ev); break;
+    default: throw Error(-1, "unknown sweep");
+  }
+}
+
+// ---- bookkeeping kernels ---------------------------------------------------------------
+
+__global__ void k_apply_moves(const int32_t *Cold, const int32_t *Cnew, const uint32_t *K, uint32_t *Sig,
+                              int32_t *size, int32_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  int32_t d = Cold[i], c = Cnew[i];
+  if (c == d) return;
+  uint32_t k = K[i];
+  atomicSub(&Sig[d], k);
+  atomicAdd(&Sig[c], k);
+  atomicSub(&size[d], 1);
+  atomicAdd(&size[c], 1);
+}
+
+void launch_apply_moves(const int32_t *Cold, const int32_t *Cnew, const uint32_t *K, uint32_t *Sig,
+                        int32_t *size, int32_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_apply_moves<<<grid_for(n), BLOCK, 0, st>>>(Cold, Cnew, K, Sig, size, n);
+  MGCD_LAUNCHED();
+}
+
+__global__ void k_zero_totals(uint32_t *Sig, int32_t *size, int32_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) {
+    Sig[i] = 0;
+    size[i] = 0;
+  }
+}
+
+__global__ void k_totals(const int32_t *C, const uint32_t *K, uint32_t *Sig, int32_t *size, int32_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  atomicAdd(&Sig[C[i]], K[i]);
+  atomicAdd(&size[C[i]], 1);
+}
+
+void launch_community_totals(const int32_t *C, const uint32_t *K, uint32_t *Sig, int32_t *size,
+                             int32_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_zero_totals<<<grid_for(n), BLOCK, 0, st>>>(Sig, size, n);
+  MGCD_LAUNCHED();
+  k_totals<<<grid_for(n), BLOCK, 0, st>>>(C, K, Sig, size, n);
+  MGCD_LAUNCHED();
+}
+
+__global__ void k_count_proposals(const int32_t *prop, int32_t *nprop, int32_t *from, int32_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  int32_t t = prop[i];
+  if (t != (int32_t)i) {
+    atomicAdd(&nprop[t], 1);
+    from[t] = (int32_t)i;  // read only where exactly one vertex proposed t
+  }
+}
+
+__global__ void k_accept(const int32_t *prop, const int32_t *nprop, const int32_t *from, int32_t *R,
+                         int32_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  int32_t t = prop[i];
+  bool ok = t != (int32_t)i &&
+            (nprop[i] == 0 || (nprop[i] == 1 && from[i] == t && t < (int32_t)i));
+  R[i] = ok ? t : (int32_t)i;
+}
+
+void launch_refine_accept(const int32_t *prop, int32_t *nprop, int32_t *from, int32_t *R, int32_t n,
+                          hipStream_t st) {
+  if (n <= 0) return;
+  launch_fill_i32(nprop, 0, n, st);
+  k_count_proposals<<<grid_for(n), BLOCK, 0, st>>>(prop, nprop, from, n);
+  MGCD_LAUNCHED();
+  k_accept<<<grid_for(n), BLOCK, 0, st>>>(prop, nprop, from, R, n);
+  MGCD_LAUNCHED();
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_iota(int32_t *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill_i32<<<grid_for(n), BLOCK, 0, st>>>(p, v, n);
+  MGCD_LAUNCHED();
+}
+void launch_iota(int32_t *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_iota<<<grid_for(n), BLOCK, 0, st>>>(p, n);
+  MGCD_LAUNCHED();
+}
+void launch_zero_u64(unsigned long long *p, int n, hipStream_t st) {
+  k_zero_u64<<<1, 64, 0, st>>>(p, n);
+  MGCD_LAUNCHED();
+}
+
+}  // namespace mgcd

@@ -1,0 +1,67 @@
+// Local-moving sweeps (host launchers; kernels in move.hip).
+#pragma once
+#include "common.hpp"
+
+namespace mgcd {
+
+// Everything one synchronous sweep reads and writes.
+struct SweepArgs {
+  Graph g;
+  const int32_t *C;      // membership before the sweep (unused by refinement: keys are j)
+  const int32_t *bound;  // refinement only: the local-moving community C_B
+  const uint32_t *K;     // weighted degree of every vertex
+  const uint32_t *Sig;   // Sigma of every community (refinement: K itself)
+  uint64_t W;            // total edge weight 2m
+  int32_t dir;           // -1 lower ids only, +1 higher ids only, 0 any
+  int32_t *Cnew;         // new membership (refinement: proposed target)
+  int64_t *gain;         // optional: gain of each vertex's best move
+  unsigned long long *ctr;  // [moved, proposals, sum of gains] (device)
+};
+
+// Per-level work lists, built once per level by build_schedule.
+struct Schedule {
+  // MG mode
+  int32_t *single = nullptr;  // vertices whose row fits one chunk (deg <= L), heavy first
+  int64_t nsingle = 0;
+  int32_t *multi = nullptr;   // vertices with deg > L, ascending id
+  int64_t nmulti = 0;
+  int64_t *cstart = nullptr;  // [nmulti+1] first chunk of each multi vertex
+  int32_t *owner = nullptr;   // [nchunks] multi index of each chunk
+  int64_t nchunks = 0;
+  Pair *sk = nullptr;         // [nchunks * k] chunk sketches
+  uint32_t *skflag = nullptr; // [nchunks] chunk lost weight
+  // exact mode
+  int32_t *tier[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t ntier[4] = {0, 0, 0, 0};
+  int64_t *hbase = nullptr;   // [ntier[3]+1] global hash region of each tier-3 vertex
+  Pair *htab = nullptr;
+};
+
+// exact-mode tiers: degree <= 32 | <= 512 | <= 4096 | larger
+constexpr int64_t EXACT_T0 = 32, EXACT_T1 = 512, EXACT_T2 = 4096;
+
+void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Arena &a,
+                    hipStream_t st);
+size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L);
+
+// One sweep of `algo` (ALGO_LPA / ALGO_MOVE / ALGO_REFINE) over all vertices.
+// ev (optional, 4 events): recorded before the first kernel class and after each
+// of the three classes, for per-class timing.
+void launch_sweep(const SweepArgs &a, const Schedule &s, int algo, int mode, int k, int64_t L,
+                  hipStream_t st, hipEvent_t *ev = nullptr);
+
+// Sigma[c] -= K_i, Sigma[c'] += K_i and sizes for every vertex that moved.
+void launch_apply_moves(const int32_t *Cold, const int32_t *Cnew, const uint32_t *K, uint32_t *Sig,
+                        int32_t *size, int32_t n, hipStream_t st);
+// Sigma and sizes of a membership from scratch.
+void launch_community_totals(const int32_t *C, const uint32_t *K, uint32_t *Sig, int32_t *size,
+                             int32_t n, hipStream_t st);
+// Leiden refinement acceptance: R[i] = prop[i] unless a vertex other than the target
+// proposed i, or the target proposed i and has the higher id.
+void launch_refine_accept(const int32_t *prop, int32_t *nprop, int32_t *from, int32_t *R, int32_t n,
+                          hipStream_t st);
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+void launch_iota(int32_t *p, int64_t n, hipStream_t st);
+void launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
+
+}  // namespace mgcd

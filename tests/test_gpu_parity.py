@@ -1,0 +1,234 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on the
+same seeded inputs.  Labels, moves, gains and aggregated graphs must be bit-exact;
+modularity must agree to a relative 1e-9.  Run on an MI355X only."""
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_02268_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"exact": 0, "alg1": 1, "uncond": 2, "std": 3}
+
+
+@pytest.fixture(scope="module")
+def mg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_02268_amd as m
+    m.lib()
+    return m
+
+
+def _t(x, dev="cuda"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).to(dev)
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def q_close(a, b):
+    return abs(a - b) <= 1e-9 * max(abs(b), 1e-300) + 1e-15
+
+
+GRAPHS = {
+    "er200": lambda: synth.random_small(200, 0.06, 8, seed=1, loops=True),
+    "er120dense": lambda: synth.random_small(120, 0.3, 8, seed=2),
+    "rmat11": lambda: synth.rmat(scale=11, edge_factor=8, seed=3),
+    "cl12": lambda: synth.chung_lu(n=1 << 12, avg_deg=24, seed=4),
+    "planted": lambda: synth.planted_exact(n_comm=8, comm_size=60, seed=5)[0],
+}
+_cache = {}
+
+
+def graph(name):
+    if name not in _cache:
+        _cache[name] = GRAPHS[name]()
+    return _cache[name]
+
+
+# ---------------------------------------------------------------------------------
+# one sweep
+# ---------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("gname", ["er200", "er120dense", "rmat11", "cl12"])
+@pytest.mark.parametrize("mode", ["exact", "alg1", "uncond", "std"])
+@pytest.mark.parametrize("k,L", [(1, 128), (4, 7), (8, 128), (8, 16), (16, 5)])
+def test_sweep_parity(mg, gname, mode, k, L):
+    g = graph(gname)
+    dg = mg.to_device(g)
+    rng = np.random.default_rng(zlib.crc32(f"{gname}-{mode}-{k}-{L}".encode()))
+    C = rng.integers(0, max(2, g.n // 5), size=g.n).astype(np.int32)
+    for algo, oalgo in ((mg.ALGO_LPA, oracle.ALGO_LPA), (mg.ALGO_LOUVAIN, oracle.ALGO_MOVE)):
+        for direction in (-1, 0, 1):
+            Cn, gain, ctr = mg.move_sweep(dg, algo, _t(C), direction, mode=MODES[mode], k=k,
+                                          chunk_len=L)
+            eC, eg = oracle.move_sweep(g, oalgo, C, mode=MODES[mode], k=k, chunk_len=L,
+                                       direction=direction)
+            assert np.array_equal(_np(Cn), eC), (algo, direction)
+            if algo == mg.ALGO_LOUVAIN:
+                assert np.array_equal(_np(gain), eg)
+                assert ctr == [int((eC != C).sum()), int((eg > 0).sum()), int(eg.sum())]
+            else:
+                assert ctr[0] == int((eC != C).sum())
+
+
+@pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12"])
+@pytest.mark.parametrize("mode,k,L", [("exact", 8, 128), ("alg1", 2, 9), ("alg1", 16, 128),
+                                      ("std", 4, 6)])
+def test_refine_parity(mg, gname, mode, k, L):
+    g = graph(gname)
+    dg = mg.to_device(g)
+    rng = np.random.default_rng(11)
+    bound = rng.integers(0, max(2, g.n // 40), size=g.n).astype(np.int32)
+    R = mg.refine(dg, _t(bound), mode=MODES[mode], k=k, chunk_len=L)
+    eR = oracle.refine(g, bound, mode=MODES[mode], k=k, chunk_len=L)
+    assert np.array_equal(_np(R), eR)
+
+
+@pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12", "planted"])
+@pytest.mark.parametrize("mode,k,L", [("exact", 8, 128), ("alg1", 1, 128), ("alg1", 4, 11),
+                                      ("alg1", 8, 128), ("alg1", 16, 40), ("uncond", 8, 64)])
+@pytest.mark.parametrize("symmetric", [False, True])
+def test_aggregate_parity(mg, gname, mode, k, L, symmetric):
+    g = graph(gname)
+    dg = mg.to_device(g)
+    rng = np.random.default_rng(5)
+    C = rng.integers(0, max(2, g.n // 7), size=g.n)
+    u, D = np.unique(C, return_inverse=True)
+    m = len(u)
+    off, idx, w = mg.aggregate(dg, _t(D), m, symmetric, mode=MODES[mode], k=k, chunk_len=L)
+    e = oracle.aggregate(g, D.astype(np.int32), m, mode=MODES[mode], k=k, chunk_len=L,
+                         symmetric=symmetric)
+    assert np.array_equal(off, e.offsets)
+    assert np.array_equal(idx, e.indices)
+    assert np.array_equal(w, e.weights)
+
+
+# ---------------------------------------------------------------------------------
+# whole runs
+# ---------------------------------------------------------------------------------
+
+RUNS = [
+    ("lpa", "exact", 8, 128), ("lpa", "alg1", 8, 128), ("lpa", "alg1", 2, 6), ("lpa", "std", 4, 128),
+    ("louvain", "exact", 8, 128), ("louvain", "alg1", 8, 128), ("louvain", "alg1", 16, 9),
+    ("louvain", "uncond", 4, 128), ("louvain", "std", 8, 32), ("louvain", "alg1", 1, 128),
+    ("leiden", "exact", 16, 128), ("leiden", "alg1", 16, 128), ("leiden", "alg1", 8, 10),
+    ("leiden", "std", 4, 128),
+]
+
+
+@pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12", "planted"])
+@pytest.mark.parametrize("algo,mode,k,L", RUNS)
+def test_run_parity(mg, gname, algo, mode, k, L):
+    g = graph(gname)
+    dg = mg.to_device(g)
+    kw = dict(mode=MODES[mode], k=k, chunk_len=L)
+    lab, st = getattr(mg, algo)(dg, **kw)
+    elab, est = getattr(oracle, algo)(g, **kw)
+    lab = _np(lab)
+    assert np.array_equal(lab, elab)
+    assert st["iterations"] == est.iterations and st["passes"] == est.passes
+    assert st["communities"] == est.communities
+    assert st["edges_scanned"] == est.edges_scanned
+    q = mg.modularity(dg, _t(lab))
+    assert q_close(q, oracle.modularity(g, elab))
+
+
+def test_edge_cases(mg):
+    import torch
+    # isolated vertices, a self-loop only vertex, one edge
+    g = synth.from_edges(6, [(0, 1)], self_loops={4: 3})
+    dg = mg.to_device(g)
+    for algo in ("lpa", "louvain", "leiden"):
+        for mode in (0, 1):
+            lab, st = getattr(mg, algo)(dg, mode=mode, k=4)
+            elab, est = getattr(oracle, algo)(g, mode=mode, k=4)
+            assert np.array_equal(_np(lab), elab)
+    # K2 oscillates under synchronous LPA until the sweep cap
+    k2 = mg.to_device(synth.from_edges(2, [(0, 1)]))
+    lab, st = mg.lpa(k2, mode=0)
+    assert st["iterations"] == 20 and list(_np(lab)) == [0, 1]
+    # one vertex without edges
+    one = mg.to_device(synth.from_edges(1, []))
+    lab, st = mg.louvain(one)
+    assert list(_np(lab)) == [0]
+    # total weight at 2^31 is rejected
+    big = synth.from_edges(2, [(0, 1)], weights=[1 << 30])
+    with pytest.raises(mg.MgcdError) as ei:
+        mg.louvain(mg.to_device(big))
+    assert ei.value.code == -3
+    # validation catches an index out of range
+    bad = synth.from_edges(3, [(0, 1), (1, 2)])
+    bad.indices = bad.indices.copy()
+    bad.indices[0] = 7
+    with pytest.raises(mg.MgcdError) as ei:
+        mg.lpa(mg.to_device(bad), validate=1)
+    assert ei.value.code == -2
+    # unsupported k
+    with pytest.raises(mg.MgcdError) as ei:
+        mg.louvain(mg.to_device(synth.from_edges(3, [(0, 1)])), k=3)
+    assert ei.value.code == -6
+    # labels out of range are rejected before any indexing
+    with pytest.raises(mg.MgcdError):
+        mg.modularity(dg, torch.full((6,), 9, dtype=torch.int32, device="cuda"))
+
+
+def test_workspace_too_small(mg):
+    import ctypes as ct
+    import torch
+    g = mg.to_device(synth.random_small(50, 0.1, 3, seed=9))
+    p = mg.params(mg.ALGO_LOUVAIN)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    d = g.desc()
+    rc = mg.lib().louvain_run(ct.byref(d), ct.byref(p), out.data_ptr(), ws.data_ptr(), 1024, None,
+                              mg._stream())
+    assert rc == -4
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_modularity_parity(mg, seed):
+    g = synth.rmat(scale=12, edge_factor=8, seed=20 + seed)
+    rng = np.random.default_rng(seed)
+    C = rng.integers(0, 50, size=g.n).astype(np.int32)
+    q = mg.modularity(mg.to_device(g), _t(C))
+    assert q_close(q, oracle.modularity(g, C))
+
+
+# ---------------------------------------------------------------------------------
+# the configured workloads
+# ---------------------------------------------------------------------------------
+
+def test_planted_lpa_config(mg):
+    """LPA, MG k=8, planted partition 20 x 500, 12 intra + 4 inter edges, <= 20 sweeps."""
+    g, truth = synth.planted_exact()
+    dg = mg.to_device(g)
+    for mode in (1, 0):
+        lab, st = mg.lpa(dg, mode=mode, k=8)
+        elab, est = oracle.lpa(g, mode=mode, k=8)
+        assert np.array_equal(_np(lab), elab)
+        assert st["iterations"] == est.iterations <= 20
+
+
+def test_rmat20_louvain_config(mg):
+    """Louvain MG k=8 on the R-MAT 2^20 graph (~31M CSR entries), the benchmarked
+    workload: labels bit-exact with the oracle."""
+    g = synth.rmat()
+    dg = mg.to_device(g)
+    lab, st = mg.louvain(dg, mode=1, k=8)
+    elab, est = oracle.louvain(g, mode=1, k=8)
+    assert np.array_equal(_np(lab), elab)
+    assert st["iterations"] == est.iterations and st["passes"] == est.passes
+    assert q_close(mg.modularity(dg, lab), oracle.modularity(g, elab))
+    # exact mode: one full-size sweep against the oracle (the full exact run is slow on CPU)
+    C = np.arange(g.n, dtype=np.int32)
+    Cn, gain, ctr = mg.move_sweep(dg, mg.ALGO_LOUVAIN, _t(C), -1, mode=0)
+    eC, eg = oracle.move_sweep(g, oracle.ALGO_MOVE, C, mode=0, direction=-1)
+    assert np.array_equal(_np(Cn), eC) and np.array_equal(_np(gain), eg)

@@ -31,19 +31,18 @@ def class_bytes(g, L: int, k: int):
     """Algorithmic bytes of one level-0 sweep per kernel class (reads + writes that
     the method must make; the second pass over a row counts as on-chip):
       per CSR entry 12 B (index 4, weight 4, gathered C[j] 4);
-      single rows: per vertex 28 B (list 4, offsets 8, C 4, C_new 4, K 4, Sigma_d 4);
-      chunks: per chunk 16 + 8k B (owner/list 8, cstart 8, sketch 8k) + 4 B flag;
-      merge: per long row 28 B + per chunk 8k + 4 B (sketch and flag reads)."""
+      per decided vertex 28 B (list 4, offsets 8, C 4, C_new 4, K 4, Sigma_d 4);
+      rows longer than 64 chunks also write and re-read 8k + 4 B per chunk sketch
+      and use 20 B of chunk table per chunk.
+    Class 0: rows of more than 64 chunks (k_move_chunks + k_move_multi).
+    Class 1: every other row (k_move_rows).  Class 2: unused (0)."""
     deg = np.diff(g.offsets)
-    single = deg <= L
-    e_single = int(deg[single].sum())
-    n_single = int(single.sum())
-    e_multi = int(deg[~single].sum())
-    nch = int(((deg[~single] + L - 1) // L).sum())
-    n_multi = int((~single).sum())
-    return [12 * e_single + 28 * n_single,
-            12 * e_multi + (20 + 8 * k) * nch,
-            28 * n_multi + (8 * k + 4) * nch]
+    nch = (deg + L - 1) // L
+    big = nch > 64
+    c0 = (12 * int(deg[big].sum()) + 28 * int(big.sum())
+          + (20 + 2 * (8 * k + 4)) * int(nch[big].sum()))
+    c1 = 12 * int(deg[~big].sum()) + 28 * int((~big).sum())
+    return [c0, c1, 0]
 
 
 def main():
@@ -101,8 +100,9 @@ def main():
         sweeps += s["l0_sweeps"]
     cb = class_bytes(g, L, k)
     dom = int(np.argmax(ms))
-    names = ["k_move_single (rows of one chunk)", "k_move_chunks (chunk sketches)",
-             "k_move_multi (merge tree + second pass)"]
+    names = ["k_move_chunks + k_move_multi (rows of more than 64 chunks)",
+             "k_move_rows (rows of up to 64 chunks: sketch, merge tree, second pass, decision)",
+             "unused"]
     per_launch_ms = ms[dom] / max(sweeps, 1)
     achieved = cb[dom] / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     sweep_ms = ms.sum() / max(sweeps, 1)

@@ -93,18 +93,23 @@ void launch_scatter_labels(const int32_t *map, const int32_t *val, int32_t *out,
   MGCD_LAUNCHED();
 }
 
-// One wave per vertex: K_i = sum of its row's weights (Section 3); W = sum of K.
+// Grid-stride waves over vertices: K_i = sum of row i's weights (Section 3), lanes
+// striding the row; W = sum of K with one atomic per workgroup.
+constexpr int ROW_BLOCKS = 2048;
+
 __global__ void __launch_bounds__(BLOCK)
     k_degrees(Graph g, uint32_t *K, unsigned long long *W) {
   __shared__ unsigned long long lw[4];
-  int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
-  uint64_t s = 0;
-  if (i < g.n) {
+  const int64_t waves = (int64_t)gridDim.x * 4;
+  uint64_t tot = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE; i < g.n; i += waves) {
+    uint64_t s = 0;
     for (int64_t e = g.off[i] + lane_id(); e < g.off[i + 1]; e += WAVE) s += g.w[e];
     s = wave_sum(s);
     if (lane_id() == 0) K[i] = (uint32_t)s;
+    tot += s;
   }
-  if (lane_id() == 0) lw[threadIdx.x / WAVE] = i < g.n ? s : 0;
+  if (lane_id() == 0) lw[threadIdx.x / WAVE] = tot;
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(W, lw[0] + lw[1] + lw[2] + lw[3]);
 }
@@ -112,7 +117,8 @@ __global__ void __launch_bounds__(BLOCK)
 void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, hipStream_t st) {
   launch_zero_u64(W, 1, st);
   if (g.n <= 0) return;
-  k_degrees<<<(unsigned)ceil_div(g.n, 4), BLOCK, 0, st>>>(g, K, W);
+  int64_t blocks = ceil_div(g.n, 4);
+  k_degrees<<<(unsigned)(blocks < ROW_BLOCKS ? blocks : ROW_BLOCKS), BLOCK, 0, st>>>(g, K, W);
   MGCD_LAUNCHED();
 }
 
@@ -160,19 +166,21 @@ int32_t canonical(const int32_t *C, int32_t n, int32_t *out, Arena &a, hipStream
 
 // ---- modularity ------------------------------------------------------------------------
 
-// One wave per vertex: intra-community weight of its row.
+// Grid-stride waves over vertices: weight of the intra-community entries.
 __global__ void __launch_bounds__(BLOCK)
     k_intra(Graph g, const int32_t *C, unsigned long long *terms) {
   __shared__ unsigned long long lw[4];
-  int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
-  uint64_t s = 0;
-  if (i < g.n) {
-    int32_t ci = C[i];
+  const int64_t waves = (int64_t)gridDim.x * 4;
+  uint64_t tot = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE; i < g.n; i += waves) {
+    const int32_t ci = C[i];
+    uint64_t s = 0;
     for (int64_t e = g.off[i] + lane_id(); e < g.off[i + 1]; e += WAVE)
       s += C[g.idx[e]] == ci ? g.w[e] : 0u;
-    s = wave_sum(s);
+    tot += s;
   }
-  if (lane_id() == 0) lw[threadIdx.x / WAVE] = s;
+  tot = wave_sum(tot);
+  if (lane_id() == 0) lw[threadIdx.x / WAVE] = tot;
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&terms[0], lw[0] + lw[1] + lw[2] + lw[3]);
 }
@@ -204,7 +212,8 @@ void modularity_terms(const Graph &g, const int32_t *C, const uint32_t *K, unsig
   size_t mk = a.mark();
   uint32_t *tot = a.take<uint32_t>(g.n);
   zero_u32(tot, g.n, st);
-  k_intra<<<(unsigned)ceil_div(g.n, 4), BLOCK, 0, st>>>(g, C, terms);
+  int64_t rb = ceil_div(g.n, 4);
+  k_intra<<<(unsigned)(rb < ROW_BLOCKS ? rb : ROW_BLOCKS), BLOCK, 0, st>>>(g, C, terms);
   MGCD_LAUNCHED();
   k_comm_tot<<<grid_for(g.n), BLOCK, 0, st>>>(C, K, g.n, tot);
   MGCD_LAUNCHED();
@@ -282,17 +291,29 @@ __global__ void k_member_deg(const int64_t *off, const uint32_t *mem, int32_t n,
   }
 }
 
-__global__ void k_comm_keys(const int32_t *mstart, const int64_t *P, int32_t m, int64_t L,
-                            uint64_t *key, uint32_t *val, unsigned long long *cnt) {
+__global__ void __launch_bounds__(BLOCK)
+    k_comm_keys(const int32_t *mstart, const int64_t *P, int32_t m, int64_t L, uint64_t *key,
+                uint32_t *val, unsigned long long *cnt) {
+  __shared__ unsigned long long bc[2];
+  if (threadIdx.x < 2) bc[threadIdx.x] = 0;
+  __syncthreads();
   int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= m) return;
-  int64_t len = P[mstart[c + 1]] - P[mstart[c]];
-  int b = 0;
-  while (b < 63 && (len >> b) != 0) ++b;
-  bool single = len <= L;
-  key[c] = single ? (uint64_t)(64 - b) : 255ull;
-  val[c] = (uint32_t)c;
-  atomicAdd(&cnt[single ? 0 : 1], 1ull);
+  int cat = -1;
+  if (c < m) {
+    int64_t len = P[mstart[c + 1]] - P[mstart[c]];
+    int b = 0;
+    while (b < 63 && (len >> b) != 0) ++b;
+    bool single = len <= L;
+    key[c] = single ? (uint64_t)(64 - b) : 255ull;
+    val[c] = (uint32_t)c;
+    cat = single ? 0 : 1;
+  }
+  for (int q = 0; q < 2; ++q) {
+    uint64_t mk = __ballot(cat == q);
+    if (lane_id() == 0 && mk) atomicAdd(&bc[q], (unsigned long long)__popcll(mk));
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 && bc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], bc[threadIdx.x]);
 }
 
 __global__ void k_comm_chunks(const int32_t *mstart, const int64_t *P, const int32_t *multi,

@@ -13,11 +13,13 @@
 //           G = W (K_ic - K_id) - K_i (K_i + Sigma_c - Sigma_d) (Eq. 2 times W^2/2),
 //           c != d, G > 0, lowest c on ties; applied only in the sweep's direction.
 //
-// Mapping on CDNA: a row that fits one chunk is streamed by one lane with the
-// sketch in VGPRs (vertices ordered heavy-first so a wave's lanes have similar
-// trip counts); each chunk of a longer row is one lane's stream, and one workgroup
-// per long row merges its chunk sketches in LDS and runs pass 2 with coalesced,
-// block-strided reads.
+// Mapping on CDNA: every chunk is one lane's stream with the sketch in VGPRs.  A
+// row of at most 64 chunks occupies 2^b adjacent lanes of one wave (b = 0 for a
+// row of one chunk; rows of one chunk ordered heavy-first so a wave's lanes have
+// similar trip counts); its chunk sketches are merged with cross-lane shuffles and
+// the same lanes run pass 2.  Rows of more than 64 chunks write chunk sketches to
+// scratch and one workgroup per row merges them in LDS and runs pass 2 with
+// block-strided (coalesced) reads.
 #include "move.hpp"
 #include "primitives.hpp"
 #include "sketch.hpp"
@@ -102,55 +104,30 @@ __device__ inline uint32_t stream_key(const SweepArgs &a, int32_t i, int32_t j, 
   return (uint32_t)a.C[j];
 }
 
-// ---- MG: rows that fit one chunk (thread per vertex) --------------------------------
-
-template <int K, int ALGO, int MODE>
-__global__ void __launch_bounds__(BLOCK)
-    k_move_single(SweepArgs a, const int32_t *__restrict__ list, int64_t count) {
-  Counters ct;
-  int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (t < count) {
-    const int32_t i = list[t];
-    const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
-    const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
-    const int32_t d = community_of_self<ALGO>(a, i);
-    RegSketch<K, MODE> s;
-    s.reset();
-    for (int64_t e = lo; e < hi; ++e) {
-      uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
-      if (c != EMPTY) s.update(c, a.g.w[e]);
-    }
-    s.finalize();
-    uint32_t ex[K];
-    uint32_t kd = 0;
-    if (!s.lossy) {
+// Stream entries [lo, hi) of row i (stride 1) into f(key, weight), skipped entries
+// dropped.  Four entries per step: their index and weight loads, then their four
+// label gathers, are all in flight before the first update.
+template <int ALGO, typename F>
+__device__ inline void for_each_entry(const SweepArgs &a, int32_t i, int32_t bi, int64_t lo,
+                                      int64_t hi, F &&f, int64_t stride = 1) {
+  int64_t e = lo;
+  for (; e + 3 * stride < hi; e += 4 * stride) {
+    int32_t j[4];
+    uint32_t w[4], c[4];
 #pragma unroll
-      for (int p = 0; p < K; ++p) {
-        ex[p] = s.val[p];
-        kd += s.key[p] == (uint32_t)d ? s.val[p] : 0u;
-      }
-    } else {
+    for (int u = 0; u < 4; ++u) j[u] = a.g.idx[e + u * stride];
 #pragma unroll
-      for (int p = 0; p < K; ++p) ex[p] = 0;
-      for (int64_t e = lo; e < hi; ++e) {
-        uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
-        if (c == EMPTY) continue;
-        uint32_t w = a.g.w[e];
+    for (int u = 0; u < 4; ++u) w[u] = a.g.w[e + u * stride];
 #pragma unroll
-        for (int p = 0; p < K; ++p) ex[p] += s.key[p] == c ? w : 0u;
-        kd += c == (uint32_t)d ? w : 0u;
-      }
-    }
-    int32_t best = -1;
-    int64_t bestG = 0;
-    const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
-    const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+    for (int u = 0; u < 4; ++u) c[u] = stream_key<ALGO>(a, i, j[u], bi);
 #pragma unroll
-    for (int p = 0; p < K; ++p)
-      if (s.key[p] != EMPTY) consider<ALGO>(a, d, Ki, Sd, kd, (int32_t)s.key[p], ex[p], best, bestG);
-    finish<ALGO>(a, i, d, best, bestG, ct);
+    for (int u = 0; u < 4; ++u)
+      if (c[u] != EMPTY) f(c[u], w[u]);
   }
-  flush_counters(a, ct);
+  for (; e < hi; e += stride) {
+    uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
+    if (c != EMPTY) f(c, a.g.w[e]);
+  }
 }
 
 // ---- MG: long rows -----------------------------------------------------------------
@@ -172,10 +149,7 @@ __global__ void __launch_bounds__(BLOCK)
   const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
   RegSketch<K, MODE> s;
   s.reset();
-  for (int64_t e = lo; e < hi; ++e) {
-    uint32_t key = stream_key<ALGO>(a, i, a.g.idx[e], bi);
-    if (key != EMPTY) s.update(key, a.g.w[e]);
-  }
+  for_each_entry<ALGO>(a, i, bi, lo, hi, [&](uint32_t c, uint32_t w) { s.update(c, w); });
   s.finalize();
 #pragma unroll
   for (int p = 0; p < K; ++p) sk[q * K + p] = Pair{s.key[p], s.val[p]};
@@ -219,14 +193,11 @@ __global__ void __launch_bounds__(BLOCK)
     const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
 #pragma unroll
     for (int p = 0; p < K; ++p) ex[p] = 0;
-    for (int64_t e = lo + t; e < hi; e += BLOCK) {
-      uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
-      if (c == EMPTY) continue;
-      uint32_t w = a.g.w[e];
+    for_each_entry<ALGO>(a, i, bi, lo + t, hi, [&](uint32_t c, uint32_t w) {
 #pragma unroll
       for (int p = 0; p < K; ++p) ex[p] += key[p] == c ? w : 0u;
       kd += c == (uint32_t)d ? w : 0u;
-    }
+    }, BLOCK);
     const int wv = t / WAVE;
 #pragma unroll
     for (int p = 0; p < K; ++p) {
@@ -254,6 +225,104 @@ __global__ void __launch_bounds__(BLOCK)
     if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
     if (ct.sumG) atomicAdd(&a.ctr[2], (unsigned long long)ct.sumG);
   }
+}
+
+// ---- MG: every row of at most 64 chunks, one launch ---------------------------------
+
+// Rows are grouped in buckets by P = 2^b lanes per row (P >= the row's chunk count;
+// b = 0 for rows of one chunk), 64/P rows per wave, heaviest bucket first in the
+// grid.  Lane q of a row streams chunk q with the sketch in VGPRs; chunk sketches
+// are merged by the fixed tree with cross-lane shuffles (node j of level l lives in
+// lane j*2^l, its right partner 2^l lanes up); the row's P lanes then run pass 2
+// over the row (stride P, four loads in flight) and reduce with xor-shuffles inside
+// their aligned segment; lane 0 of the segment decides.
+struct Buckets {
+  int64_t wave_begin[7];  // waves of bucket b: [wave_begin[b], wave_end[b]); b = 6 comes first
+  int64_t wave_end[7];    // wave_end[0] is the total
+  const int32_t *rows[7];
+  int64_t nrows[7];
+};
+
+template <int K, int ALGO, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_move_rows(SweepArgs a, Buckets bk, int64_t L) {
+  const int lane = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
+  // buckets are laid out in the grid from b = 6 down to b = 0 (wave-uniform)
+  int b = 6;
+  while (b > 0 && wave >= bk.wave_end[b]) --b;
+  const int logp = b;
+  const int P = 1 << logp;
+  const int q = lane & (P - 1);
+  const int base_lane = lane & ~(P - 1);
+  const int64_t r = (wave - bk.wave_begin[b]) * (WAVE >> logp) + (lane >> logp);
+  const bool valid = wave < bk.wave_end[0] && r < bk.nrows[b];
+  const int32_t i = valid ? bk.rows[b][r] : 0;
+  const int64_t lo = valid ? a.g.off[i] : 0, hi = valid ? a.g.off[i + 1] : 0;
+  const int64_t nc = (hi - lo + L - 1) / L;
+  const int32_t bi = (ALGO == ALGO_REFINE && valid) ? a.bound[i] : 0;
+  RegSketch<K, MODE> s;
+  s.reset();
+  if (q < nc) {
+    const int64_t clo = lo + q * L;
+    const int64_t chi = clo + L < hi ? clo + L : hi;
+    for_each_entry<ALGO>(a, i, bi, clo, chi, [&](uint32_t c, uint32_t w) { s.update(c, w); });
+  }
+  s.finalize();
+  bool lossy = s.lossy;
+  for (int l = 0; l < logp; ++l) {
+    const int stride = 1 << l;
+    uint32_t bk_[K], bv_[K];
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      bk_[p] = __shfl_down(s.key[p], stride);
+      bv_[p] = __shfl_down(s.val[p], stride);
+    }
+    const int64_t c_l = (nc + stride - 1) >> l;  // nodes at level l
+    const bool left = (q & ((2 << l) - 1)) == 0;
+    if (left && (int64_t)(q >> l) + 1 < c_l) lossy |= merge_sketch<K>(s.key, s.val, bk_, bv_);
+  }
+  uint32_t key[K], ex[K];
+#pragma unroll
+  for (int p = 0; p < K; ++p) {
+    uint32_t kk = __shfl(s.key[p], base_lane);
+    uint32_t vv = __shfl(s.val[p], base_lane);
+    key[p] = vv > 0 ? kk : EMPTY;
+    ex[p] = vv;
+  }
+  const uint64_t lm = __ballot(lossy);
+  const uint64_t seg = P == 64 ? lm : (lm >> base_lane) & ((1ull << P) - 1);
+  const int32_t d = valid ? community_of_self<ALGO>(a, i) : 0;
+  uint32_t kd = 0;
+  if (seg == 0) {
+#pragma unroll
+    for (int p = 0; p < K; ++p) kd += key[p] == (uint32_t)d ? ex[p] : 0u;
+  } else {
+#pragma unroll
+    for (int p = 0; p < K; ++p) ex[p] = 0;
+    for_each_entry<ALGO>(a, i, bi, lo + q, hi, [&](uint32_t c, uint32_t w) {
+#pragma unroll
+      for (int p = 0; p < K; ++p) ex[p] += key[p] == c ? w : 0u;
+      kd += c == (uint32_t)d ? w : 0u;
+    }, P);
+    for (int o = P / 2; o > 0; o >>= 1) {
+#pragma unroll
+      for (int p = 0; p < K; ++p) ex[p] += __shfl_xor(ex[p], o);
+      kd += __shfl_xor(kd, o);
+    }
+  }
+  Counters ct;
+  if (valid && q == 0) {
+    int32_t best = -1;
+    int64_t bestG = 0;
+    const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+    const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+#pragma unroll
+    for (int p = 0; p < K; ++p)
+      if (key[p] != EMPTY) consider<ALGO>(a, d, Ki, Sd, kd, (int32_t)key[p], ex[p], best, bestG);
+    finish<ALGO>(a, i, d, best, bestG, ct);
+  }
+  flush_counters(a, ct);
 }
 
 // ---- exact mode ----------------------------------------------------------------------
@@ -398,25 +467,49 @@ __global__ void __launch_bounds__(BLOCK)
 
 // ---- schedule ------------------------------------------------------------------------
 
-__global__ void k_schedule_keys(const int64_t *off, int32_t n, int mode, int64_t L, uint64_t *key,
-                                uint32_t *val, unsigned long long *cnt) {
+// Category of every vertex for this level's schedule, and per-category counts
+// (wave ballots, then one atomic per category and workgroup).
+//   MG:    0 = row fits one chunk (sort key: heavy first), 1 + b = a long row of at
+//          most 2^b <= 64 chunks (b = 1..6), 7 = longer rows;
+//   exact: tiers 0..3 by degree.
+constexpr int NCAT = 8;
+
+__global__ void __launch_bounds__(BLOCK)
+    k_schedule_keys(const int64_t *off, int32_t n, int mode, int64_t L, uint64_t *key, uint32_t *val,
+                    unsigned long long *cnt) {
+  __shared__ unsigned long long bc[NCAT];
+  if (threadIdx.x < NCAT) bc[threadIdx.x] = 0;
+  __syncthreads();
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= n) return;
-  int64_t deg = off[i + 1] - off[i];
-  int b = 0;
-  while (b < 63 && (deg >> b) != 0) ++b;  // bits of deg
-  uint64_t k;
-  if (mode == MODE_EXACT) {
-    int tier = deg <= EXACT_T0 ? 0 : deg <= EXACT_T1 ? 1 : deg <= EXACT_T2 ? 2 : 3;
-    k = tier == 0 ? (uint64_t)(64 - b) : (uint64_t)(128 + tier);
-    atomicAdd(&cnt[tier], 1ull);
-  } else {
-    bool single = deg <= L;
-    k = single ? (uint64_t)(64 - b) : 255ull;  // heavy rows first
-    atomicAdd(&cnt[single ? 0 : 1], 1ull);
+  int cat = -1;
+  if (i < n) {
+    int64_t deg = off[i + 1] - off[i];
+    int b = 0;
+    while (b < 63 && (deg >> b) != 0) ++b;  // bits of deg
+    uint64_t k;
+    if (mode == MODE_EXACT) {
+      cat = deg <= EXACT_T0 ? 0 : deg <= EXACT_T1 ? 1 : deg <= EXACT_T2 ? 2 : 3;
+      k = cat == 0 ? (uint64_t)(64 - b) : (uint64_t)(128 + cat);
+    } else if (deg <= L) {
+      cat = 0;
+      k = (uint64_t)(64 - b);  // heavy rows first
+    } else {
+      int64_t nc = (deg + L - 1) / L;
+      int lp = 0;
+      while ((1ll << lp) < nc) ++lp;
+      cat = lp <= 6 ? lp : 7;
+      k = 200ull + (uint64_t)cat;
+    }
+    key[i] = k;
+    val[i] = (uint32_t)i;
   }
-  key[i] = k;
-  val[i] = (uint32_t)i;
+#pragma unroll
+  for (int q = 0; q < NCAT; ++q) {
+    uint64_t m = __ballot(cat == q);
+    if (lane_id() == 0 && m) atomicAdd(&bc[q], (unsigned long long)__popcll(m));
+  }
+  __syncthreads();
+  if (threadIdx.x < NCAT && bc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], bc[threadIdx.x]);
 }
 
 __global__ void k_chunk_counts(const int64_t *off, const int32_t *multi, int64_t nmulti, int64_t L,
@@ -471,19 +564,19 @@ void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Are
   const int32_t n = g.n;
   s = Schedule{};
   if (n == 0) return;
-  unsigned long long *cnt = a.take<unsigned long long>(4);
+  unsigned long long *cnt = a.take<unsigned long long>(NCAT);
   uint64_t *k0 = a.take<uint64_t>(n);
   uint32_t *v0 = a.take<uint32_t>(n);
   uint64_t *k1 = a.take<uint64_t>(n);
   uint32_t *v1 = a.take<uint32_t>(n);
   int32_t *order = a.take<int32_t>(n);
-  launch_zero_u64(cnt, 4, st);
+  launch_zero_u64(cnt, NCAT, st);
   k_schedule_keys<<<grid_for(n), BLOCK, 0, st>>>(g.off, n, mode, L, k0, v0, cnt);
   MGCD_LAUNCHED();
   bool flip = radix_sort_pairs(k0, v0, k1, v1, n, 8, a, st);
   k_u32_from_u64<<<grid_for(n), BLOCK, 0, st>>>(flip ? v1 : v0, order, n);
   MGCD_LAUNCHED();
-  unsigned long long h[4];
+  unsigned long long h[NCAT];
   MGCD_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
   MGCD_HIP(hipStreamSynchronize(st));
   if (mode == MODE_EXACT) {
@@ -507,10 +600,17 @@ void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Are
     }
     return;
   }
+  int64_t pos = 0;
   s.single = order;
   s.nsingle = (int64_t)h[0];
-  s.multi = order + s.nsingle;
-  s.nmulti = (int64_t)h[1];
+  pos = s.nsingle;
+  for (int b = 1; b <= 6; ++b) {
+    s.packed[b] = order + pos;
+    s.npacked[b] = (int64_t)h[b];
+    pos += (int64_t)h[b];
+  }
+  s.multi = order + pos;
+  s.nmulti = (int64_t)h[7];
   if (s.nmulti > 0) {
     int64_t *nch = a.take<int64_t>(s.nmulti);
     s.cstart = a.take<int64_t>(s.nmulti + 1);
@@ -536,21 +636,30 @@ static inline void mark(hipEvent_t *ev, int i, hipStream_t st) {
 template <int K, int ALGO, int MODE>
 static void sweep_mg(const SweepArgs &a, const Schedule &s, int64_t L, hipStream_t st, hipEvent_t *ev) {
   mark(ev, 0, st);
-  if (s.nsingle > 0) {
-    k_move_single<K, ALGO, MODE><<<grid_for(s.nsingle), BLOCK, 0, st>>>(a, s.single, s.nsingle);
-    MGCD_LAUNCHED();
-  }
-  mark(ev, 1, st);
+  // rows of more than 64 chunks: chunk sketches to scratch, then one workgroup per row
   if (s.nmulti > 0) {
     k_move_chunks<K, ALGO, MODE><<<grid_for(s.nchunks), BLOCK, 0, st>>>(
         a, s.multi, s.owner, s.cstart, s.nchunks, L, s.sk, s.skflag);
     MGCD_LAUNCHED();
-  }
-  mark(ev, 2, st);
-  if (s.nmulti > 0) {
     k_move_multi<K, ALGO><<<(unsigned)s.nmulti, BLOCK, 0, st>>>(a, s.multi, s.cstart, s.sk, s.skflag);
     MGCD_LAUNCHED();
   }
+  mark(ev, 1, st);
+  Buckets bk{};
+  int64_t w = 0;
+  for (int b = 6; b >= 0; --b) {
+    const int64_t rows = b == 0 ? s.nsingle : s.npacked[b];
+    bk.rows[b] = b == 0 ? s.single : s.packed[b];
+    bk.nrows[b] = rows;
+    bk.wave_begin[b] = w;
+    w += ceil_div(rows << b, WAVE);
+    bk.wave_end[b] = w;
+  }
+  if (w > 0) {
+    k_move_rows<K, ALGO, MODE><<<(unsigned)ceil_div(w, BLOCK / WAVE), BLOCK, 0, st>>>(a, bk, L);
+    MGCD_LAUNCHED();
+  }
+  mark(ev, 2, st);
   mark(ev, 3, st);
 }
 

@@ -23,7 +23,9 @@ struct Schedule {
   // MG mode
   int32_t *single = nullptr;  // vertices whose row fits one chunk (deg <= L), heavy first
   int64_t nsingle = 0;
-  int32_t *multi = nullptr;   // vertices with deg > L, ascending id
+  int32_t *packed[7] = {};    // [b] long rows of at most 2^b chunks (b = 1..6)
+  int64_t npacked[7] = {};
+  int32_t *multi = nullptr;   // rows of more than 64 chunks, ascending id
   int64_t nmulti = 0;
   int64_t *cstart = nullptr;  // [nmulti+1] first chunk of each multi vertex
   int32_t *owner = nullptr;   // [nchunks] multi index of each chunk

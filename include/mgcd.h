@@ -46,7 +46,8 @@ enum { MGCD_ALGO_LPA = 0, MGCD_ALGO_LOUVAIN = 1, MGCD_ALGO_LEIDEN = 2 };
  * appears as the entries i->j and j->i with equal weight; a self-loop appears once.
  * Layout: offsets[n+1] int64 (offsets[0] = 0, non-decreasing, offsets[n] = nnz);
  * indices[nnz] int32 in [0, n); weights[nnz] uint32 >= 1.  Device pointers, read
- * only.  The sum W of all weights (= 2m) must be below 2^31. */
+ * only; indices and weights 16-byte aligned (MGCD_E_ARG otherwise).  The sum W of
+ * all weights (= 2m) must be below 2^31. */
 typedef struct {
   int32_t n;
   int32_t reserved;
@@ -122,6 +123,9 @@ int louvain_run(const mgcd_csr *g, const mgcd_params *p, int32_t *communities_ou
 int leiden_run(const mgcd_csr *g, const mgcd_params *p, int32_t *communities_out, void *ws,
                size_t ws_bytes, mgcd_stats *stats, void *stream);
 
+/* Workspace bytes of modularity() for a graph of n vertices and nnz entries. */
+size_t mgcd_modularity_workspace_bytes(int32_t n, int64_t nnz);
+
 /* Modularity Q of a membership (Section 3.2, Eq. 1), summing over CSR entries
  * (a self-loop entry counts once; 2m = W).  communities: device int32[n], values
  * in [0, n).  q: host.  Synchronises the stream. */
@@ -153,6 +157,35 @@ int mgcd_aggregate(const mgcd_csr *g, const mgcd_params *p, const int32_t *D, in
                    int32_t symmetric, int64_t *out_offsets, int32_t *out_indices,
                    uint32_t *out_weights, int64_t *out_nnz, void *ws, size_t ws_bytes,
                    void *stream);
+
+/* Per-graph statistics of a batched run. */
+typedef struct {
+  int32_t iterations;     /* local-moving sweeps in which the graph took part         */
+  int32_t passes;
+  int32_t communities;
+  int32_t reserved;
+  int64_t edges_scanned;
+  int64_t moved_last;
+} mgcd_graph_stats;
+
+/* Workspace bytes of a batched run over `count` graphs with total_n vertices and
+ * total_nnz entries in all. */
+size_t mgcd_workspace_bytes_batched(int32_t algo, int32_t count, int64_t total_n,
+                                    int64_t total_nnz, const mgcd_params *p);
+
+/* Batched LPA / Louvain: `count` independent graphs (graphs: host array of
+ * descriptors of device CSRs) run together, one launch per sweep for all of them,
+ * as one disjoint union with per-graph total weight, counters, convergence and
+ * pass control.  Every graph's labels equal those of its own lpa_run/louvain_run
+ * with the same parameters.  communities_out: host array of `count` device int32
+ * arrays (n_g each).  per_graph: host array of `count` (may be NULL); total: host
+ * (may be NULL).  Total vertices must be below 2^31.  Synchronises the stream. */
+int lpa_run_batched(const mgcd_csr *graphs, int32_t count, const mgcd_params *p,
+                    int32_t *const *communities_out, void *ws, size_t ws_bytes,
+                    mgcd_graph_stats *per_graph, mgcd_stats *total, void *stream);
+int louvain_run_batched(const mgcd_csr *graphs, int32_t count, const mgcd_params *p,
+                        int32_t *const *communities_out, void *ws, size_t ws_bytes,
+                        mgcd_graph_stats *per_graph, mgcd_stats *total, void *stream);
 
 /* Message of the last error on this thread ("" if none). */
 const char *mgcd_last_error(void);

@@ -54,6 +54,14 @@ class Stats(ct.Structure):
         return d
 
 
+class GraphStats(ct.Structure):
+    _fields_ = [("iterations", ct.c_int32), ("passes", ct.c_int32), ("communities", ct.c_int32),
+                ("reserved", ct.c_int32), ("edges_scanned", ct.c_int64), ("moved_last", ct.c_int64)]
+
+    def asdict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 class CSRDesc(ct.Structure):
     _fields_ = [("n", ct.c_int32), ("reserved", ct.c_int32), ("nnz", ct.c_int64),
                 ("offsets", ct.c_void_p), ("indices", ct.c_void_p), ("weights", ct.c_void_p)]
@@ -79,6 +87,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [ct.POINTER(CSRDesc), ct.POINTER(Params), P, P, sz, ct.POINTER(Stats), P]
             f.restype = ct.c_int
+        L.mgcd_modularity_workspace_bytes.argtypes = [i32, i64]
+        L.mgcd_modularity_workspace_bytes.restype = sz
         L.modularity.argtypes = [ct.POINTER(CSRDesc), P, ct.POINTER(ct.c_double), P, sz, P]
         L.modularity.restype = ct.c_int
         L.mgcd_move_sweep.argtypes = [ct.POINTER(CSRDesc), ct.POINTER(Params), i32, P, i32, P, P, P,
@@ -89,6 +99,13 @@ def lib():
         L.mgcd_aggregate.argtypes = [ct.POINTER(CSRDesc), ct.POINTER(Params), P, i32, i32, P, P, P,
                                      ct.POINTER(ct.c_int64), P, sz, P]
         L.mgcd_aggregate.restype = ct.c_int
+        L.mgcd_workspace_bytes_batched.argtypes = [i32, i32, i64, i64, ct.POINTER(Params)]
+        L.mgcd_workspace_bytes_batched.restype = sz
+        for name in ("lpa_run_batched", "louvain_run_batched"):
+            f = getattr(L, name)
+            f.argtypes = [ct.POINTER(CSRDesc), i32, ct.POINTER(Params), ct.POINTER(ct.c_void_p), P,
+                          sz, ct.POINTER(GraphStats), ct.POINTER(Stats), P]
+            f.restype = ct.c_int
         L.mgcd_last_error.argtypes = []
         L.mgcd_last_error.restype = ct.c_char_p
         _lib = L
@@ -182,7 +199,8 @@ def leiden(g: DeviceGraph, **kw):
 
 def modularity(g: DeviceGraph, labels) -> float:
     import torch
-    ws = torch.empty(g.n * 8 + 64 * 1024, dtype=torch.uint8, device=g.offsets.device)
+    nbytes = int(lib().mgcd_modularity_workspace_bytes(g.n, g.nnz))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=g.offsets.device)
     q = ct.c_double()
     d = g.desc()
     _check(lib().modularity(ct.byref(d), labels.data_ptr(), ct.byref(q), ws.data_ptr(),
@@ -232,3 +250,26 @@ def aggregate(g: DeviceGraph, D, m: int, symmetric: bool = False, **kw):
     k = nnz.value
     return (off.cpu().numpy(), idx[:k].cpu().numpy(),
             w[:k].cpu().numpy().view(np.uint32))
+
+
+def run_batched(algo: int, graphs, **kw):
+    """Run LPA (ALGO_LPA) or Louvain (ALGO_LOUVAIN) on many device graphs together.
+    Returns (labels per graph, stats per graph, total stats)."""
+    import torch
+    count = len(graphs)
+    p = params(algo, **kw)
+    dev = graphs[0].offsets.device if count else torch.device("cuda")
+    outs = [torch.empty(max(g.n, 1), dtype=torch.int32, device=dev) for g in graphs]
+    descs = (CSRDesc * max(count, 1))(*[g.desc() for g in graphs])
+    ptrs = (ct.c_void_p * max(count, 1))(*[o.data_ptr() for o in outs])
+    N = sum(g.n for g in graphs)
+    E = sum(g.nnz for g in graphs)
+    nbytes = int(lib().mgcd_workspace_bytes_batched(algo, count, N, E, ct.byref(p)))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    gst = (GraphStats * max(count, 1))()
+    tot = Stats()
+    name = "lpa_run_batched" if algo == ALGO_LPA else "louvain_run_batched"
+    _check(getattr(lib(), name)(descs, count, ct.byref(p), ptrs, ws.data_ptr(), nbytes, gst,
+                                ct.byref(tot), _stream()))
+    return ([o[:g.n] for o, g in zip(outs, graphs)], [gst[i].asdict() for i in range(count)],
+            tot.asdict())

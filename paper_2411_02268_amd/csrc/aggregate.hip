@@ -29,26 +29,29 @@ static void zero_u32(uint32_t *p, int64_t n, hipStream_t st) {
   MGCD_LAUNCHED();
 }
 
-__global__ void k_flag_used(const int32_t *C, int32_t n, uint32_t *used) {
+__global__ void k_flag_used(const int32_t *C, int32_t n, uint32_t *used, const int32_t *gid,
+                            const uint8_t *keep) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i < n) used[C[i]] = 1u;
+  if (i < n && (!gid || keep[gid[i]])) used[C[i]] = 1u;
 }
 
-__global__ void k_dense_map(const int32_t *C, const int64_t *dense, int32_t n, int32_t *D) {
+__global__ void k_dense_map(const int32_t *C, const int64_t *dense, int32_t n, int32_t *D,
+                            const int32_t *gid, const uint8_t *keep) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i < n) D[i] = (int32_t)dense[C[i]];
+  if (i < n) D[i] = (!gid || keep[gid[i]]) ? (int32_t)dense[C[i]] : -1;
 }
 
-int32_t renumber(const int32_t *C, int32_t n, int32_t *D, Arena &a, hipStream_t st) {
+int32_t renumber(const int32_t *C, int32_t n, int32_t *D, Arena &a, hipStream_t st,
+                 const int32_t *gid, const uint8_t *keep, int64_t *dense_out) {
   if (n == 0) return 0;
   size_t mk = a.mark();
   uint32_t *used = a.take<uint32_t>(n);
-  int64_t *dense = a.take<int64_t>(n + 1);
+  int64_t *dense = dense_out ? dense_out : a.take<int64_t>((int64_t)n + 1);
   zero_u32(used, n, st);
-  k_flag_used<<<grid_for(n), BLOCK, 0, st>>>(C, n, used);
+  k_flag_used<<<grid_for(n), BLOCK, 0, st>>>(C, n, used, gid, keep);
   MGCD_LAUNCHED();
   scan_u32_i64(used, dense, n, dense + n, a, st);
-  k_dense_map<<<grid_for(n), BLOCK, 0, st>>>(C, dense, n, D);
+  k_dense_map<<<grid_for(n), BLOCK, 0, st>>>(C, dense, n, D, gid, keep);
   MGCD_LAUNCHED();
   int64_t m = 0;
   MGCD_HIP(hipMemcpyAsync(&m, dense + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -59,7 +62,7 @@ int32_t renumber(const int32_t *C, int32_t n, int32_t *D, Arena &a, hipStream_t 
 
 __global__ void k_group_sums(const int32_t *D, const uint32_t *K, uint32_t *Kout, int32_t n) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i < n) atomicAdd(&Kout[D[i]], K[i]);
+  if (i < n && D[i] >= 0) atomicAdd(&Kout[D[i]], K[i]);
 }
 
 void launch_group_sums(const int32_t *D, const uint32_t *K, uint32_t *Kout, int32_t n, int32_t m,
@@ -83,7 +86,7 @@ void launch_compose(const int32_t *in, const int32_t *map, int32_t *out, int32_t
 
 __global__ void k_scatter_labels(const int32_t *map, const int32_t *val, int32_t *out, int32_t n) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i < n) out[map[i]] = val[i];
+  if (i < n && map[i] >= 0) out[map[i]] = val[i];
 }
 
 void launch_scatter_labels(const int32_t *map, const int32_t *val, int32_t *out, int32_t n,
@@ -93,40 +96,42 @@ void launch_scatter_labels(const int32_t *map, const int32_t *val, int32_t *out,
   MGCD_LAUNCHED();
 }
 
-// Grid-stride waves over vertices: K_i = sum of row i's weights (Section 3), lanes
-// striding the row; W = sum of K with one atomic per workgroup.
+// K_i = sum of row i's weights (Section 3) as the difference of an exclusive prefix
+// sum of all weights at the row bounds; W = the total.
 constexpr int ROW_BLOCKS = 2048;
 
-__global__ void __launch_bounds__(BLOCK)
-    k_degrees(Graph g, uint32_t *K, unsigned long long *W) {
-  __shared__ unsigned long long lw[4];
-  const int64_t waves = (int64_t)gridDim.x * 4;
-  uint64_t tot = 0;
-  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE; i < g.n; i += waves) {
-    uint64_t s = 0;
-    for (int64_t e = g.off[i] + lane_id(); e < g.off[i + 1]; e += WAVE) s += g.w[e];
-    s = wave_sum(s);
-    if (lane_id() == 0) K[i] = (uint32_t)s;
-    tot += s;
-  }
-  if (lane_id() == 0) lw[threadIdx.x / WAVE] = tot;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(W, lw[0] + lw[1] + lw[2] + lw[3]);
+__global__ void k_row_sums(const int64_t *off, const int64_t *ps, int32_t n, uint32_t *K) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) K[i] = (uint32_t)(ps[off[i + 1]] - ps[off[i]]);
 }
 
-void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, hipStream_t st) {
-  launch_zero_u64(W, 1, st);
-  if (g.n <= 0) return;
-  int64_t blocks = ceil_div(g.n, 4);
-  k_degrees<<<(unsigned)(blocks < ROW_BLOCKS ? blocks : ROW_BLOCKS), BLOCK, 0, st>>>(g, K, W);
+__global__ void k_copy_total(const int64_t *src, unsigned long long *dst) {
+  *dst = (unsigned long long)*src;
+}
+
+size_t degrees_ws_bytes(int64_t nnz) { return (size_t)(nnz + 1) * 8 + scan_ws_bytes(nnz) + 4096; }
+
+void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, Arena &a, hipStream_t st) {
+  size_t mk = a.mark();
+  int64_t *ps = a.take<int64_t>(g.nnz + 1);
+  scan_u32_i64(g.w, ps, g.nnz, ps + g.nnz, a, st);
+  if (g.n > 0) {
+    k_row_sums<<<grid_for(g.n), BLOCK, 0, st>>>(g.off, ps, g.n, K);
+    MGCD_LAUNCHED();
+  }
+  k_copy_total<<<1, 1, 0, st>>>(ps + g.nnz, W);
   MGCD_LAUNCHED();
+  a.release(mk);
 }
 
 // ---- canonical labels ----------------------------------------------------------------
 
 __global__ void k_min_member(const int32_t *C, int32_t n, int32_t *minv) {
   int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (v < n) atomicMin(&minv[C[v]], (int32_t)v);
+  if (v < n) {
+    int32_t *m = &minv[C[v]];
+    if (*m > (int32_t)v) atomicMin(m, (int32_t)v);  // skip the atomic once a smaller id won
+  }
 }
 __global__ void k_is_first(const int32_t *C, const int32_t *minv, int32_t n, uint32_t *first) {
   int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -265,22 +270,24 @@ void launch_validate(const Graph &g, unsigned long long *flags, hipStream_t st) 
 
 // ---- aggregation: member order and community streams ------------------------------------
 
-__global__ void k_member_keys(const int32_t *D, int32_t n, uint64_t *key, uint32_t *val) {
+// Sort keys of the members: their community, or m for a vertex left out (D < 0).
+__global__ void k_member_keys(const int32_t *D, int32_t n, int32_t m, uint64_t *key, uint32_t *val) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (i < n) {
-    key[i] = (uint64_t)(uint32_t)D[i];
+    key[i] = D[i] >= 0 ? (uint64_t)(uint32_t)D[i] : (uint64_t)m;
     val[i] = (uint32_t)i;
   }
 }
 
-// mstart[c] = first position of community c in the sorted member list.
+// mstart[c] = first position of community c in the sorted member list (every c < m
+// has members); mstart[m] = number of members that belong to some community.
 __global__ void k_member_bounds(const uint64_t *ks, int32_t n, int32_t m, int32_t *mstart) {
   int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (t < n) {
-    uint32_t c = (uint32_t)ks[t];
-    if (t == 0 || (uint32_t)ks[t - 1] != c) mstart[c] = (int32_t)t;
-  }
-  if (t == 0) mstart[m] = n;
+  if (t >= n) return;
+  const uint64_t c = ks[t];
+  const bool first = t == 0 || ks[t - 1] != c;
+  if (first) mstart[c] = (int32_t)t;  // c <= m; c == m marks the first left-out vertex
+  if (t == n - 1 && c < (uint64_t)m) mstart[m] = n;
 }
 
 __global__ void k_member_deg(const int64_t *off, const uint32_t *mem, int32_t n, uint32_t *mdeg) {
@@ -291,29 +298,38 @@ __global__ void k_member_deg(const int64_t *off, const uint32_t *mem, int32_t n,
   }
 }
 
+// Category of every community stream: b = log2 of the lanes it needs (0..6, at
+// most 64 chunks; sort key heavy first within b = 0) or 7 = longer.
 __global__ void __launch_bounds__(BLOCK)
     k_comm_keys(const int32_t *mstart, const int64_t *P, int32_t m, int64_t L, uint64_t *key,
                 uint32_t *val, unsigned long long *cnt) {
-  __shared__ unsigned long long bc[2];
-  if (threadIdx.x < 2) bc[threadIdx.x] = 0;
+  __shared__ unsigned long long bc[8];
+  if (threadIdx.x < 8) bc[threadIdx.x] = 0;
   __syncthreads();
   int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   int cat = -1;
   if (c < m) {
     int64_t len = P[mstart[c + 1]] - P[mstart[c]];
-    int b = 0;
-    while (b < 63 && (len >> b) != 0) ++b;
-    bool single = len <= L;
-    key[c] = single ? (uint64_t)(64 - b) : 255ull;
+    if (len <= L) {
+      int b = 0;
+      while (b < 63 && (len >> b) != 0) ++b;
+      cat = 0;
+      key[c] = (uint64_t)(64 - b);
+    } else {
+      int64_t nc = (len + L - 1) / L;
+      int lp = 0;
+      while ((1ll << lp) < nc) ++lp;
+      cat = lp <= 6 ? lp : 7;
+      key[c] = 200ull + (uint64_t)cat;
+    }
     val[c] = (uint32_t)c;
-    cat = single ? 0 : 1;
   }
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < 8; ++q) {
     uint64_t mk = __ballot(cat == q);
     if (lane_id() == 0 && mk) atomicAdd(&bc[q], (unsigned long long)__popcll(mk));
   }
   __syncthreads();
-  if (threadIdx.x < 2 && bc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], bc[threadIdx.x]);
+  if (threadIdx.x < 8 && bc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], bc[threadIdx.x]);
 }
 
 __global__ void k_comm_chunks(const int32_t *mstart, const int64_t *P, const int32_t *multi,
@@ -342,7 +358,13 @@ struct AggStreams {
   const uint32_t *mem;    // members sorted by community, ascending id within one
   const int32_t *mstart;  // [m+1]
   const int64_t *P;       // [n+1] stream position of each member's row
+  const int64_t *rs;      // [n] CSR offset of each member's row (off[mem[t]])
 };
+
+__global__ void k_row_starts(const int64_t *off, const uint32_t *mem, int32_t n, int64_t *rs) {
+  int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (t < n) rs[t] = off[mem[t]];
+}
 
 // Stream positions [p0, p1) of community c into the sketch.
 template <int K, int MODE>
@@ -357,14 +379,75 @@ __device__ inline void stream_range(const AggStreams &s, int32_t c, int64_t p0, 
   int32_t t = lo;
   int64_t p = p0;
   while (p < p1) {
-    const uint32_t i = s.mem[t];
-    const int64_t rb = s.g.off[i];
+    const int64_t rb = s.rs[t];
     const int64_t row_end = s.P[t + 1];
     const int64_t stop = row_end < p1 ? row_end : p1;
-    for (int64_t e = rb + (p - s.P[t]); p < stop; ++e, ++p)
-      sk.update((uint32_t)s.D[s.g.idx[e]], s.g.w[e]);
+    int64_t e = rb + (p - s.P[t]);
+    for (; p + 4 <= stop; p += 4, e += 4) {  // four entries in flight
+      int32_t j[4];
+      uint32_t w[4], c[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) j[u] = __builtin_nontemporal_load(s.g.idx + e + u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w[u] = __builtin_nontemporal_load(s.g.w + e + u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c[u] = (uint32_t)s.D[j[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sk.update(c[u], w[u]);
+    }
+    for (; p < stop; ++e, ++p) sk.update((uint32_t)s.D[s.g.idx[e]], s.g.w[e]);
     ++t;
   }
+}
+
+// Communities whose stream has at most 64 chunks: P = 2^b adjacent lanes per
+// community (P >= its chunk count), lane q sketches chunk q, the chunk sketches are
+// merged by the fixed tree with cross-lane shuffles and lane 0 writes the row.
+struct AggBuckets {
+  int64_t wave_begin[7];
+  int64_t wave_end[7];
+  const int32_t *comm[7];
+  int64_t ncomm[7];
+};
+
+template <int K>
+__device__ inline void write_row(uint32_t (&k)[K], uint32_t (&v)[K], int32_t c, Pair *rows,
+                                 uint32_t *rcount);
+
+template <int K, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_agg_rows(AggStreams s, AggBuckets bk, int64_t L, Pair *rows, uint32_t *rcount) {
+  const int lane = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
+  int b = 6;
+  while (b > 0 && wave >= bk.wave_end[b]) --b;
+  const int logp = b;
+  const int q = lane & ((1 << logp) - 1);
+  const int64_t r = (wave - bk.wave_begin[b]) * (WAVE >> logp) + (lane >> logp);
+  const bool valid = wave < bk.wave_end[0] && r < bk.ncomm[b];
+  const int32_t c = valid ? bk.comm[b][r] : 0;
+  const int64_t base = valid ? s.P[s.mstart[c]] : 0, end = valid ? s.P[s.mstart[c + 1]] : 0;
+  const int64_t nc = (end - base + L - 1) / L;
+  RegSketch<K, MODE> sk;
+  sk.reset();
+  if (q < nc) {
+    const int64_t p0 = base + q * L;
+    stream_range<K, MODE>(s, c, p0, p0 + L < end ? p0 + L : end, sk);
+  }
+  sk.finalize();
+  for (int l = 0; l < logp; ++l) {
+    const int stride = 1 << l;
+    uint32_t bk_[K], bv_[K];
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      bk_[p] = __shfl_down(sk.key[p], stride);
+      bv_[p] = __shfl_down(sk.val[p], stride);
+    }
+    const int64_t c_l = (nc + stride - 1) >> l;
+    const bool left = (q & ((2 << l) - 1)) == 0;
+    if (left && (int64_t)(q >> l) + 1 < c_l) merge_sketch<K>(sk.key, sk.val, bk_, bv_);
+  }
+  if (valid && q == 0) write_row<K>(sk.key, sk.val, c, rows, rcount);
 }
 
 template <int K>
@@ -378,19 +461,6 @@ __device__ inline void write_row(uint32_t (&k)[K], uint32_t (&v)[K], int32_t c, 
   for (int p = 0; p < K; ++p)
     if (k[p] != EMPTY) rows[(int64_t)c * K + x++] = Pair{k[p], v[p]};
   rcount[c] = x;
-}
-
-template <int K, int MODE>
-__global__ void __launch_bounds__(BLOCK)
-    k_agg_single(AggStreams s, const int32_t *list, int64_t count, Pair *rows, uint32_t *rcount) {
-  int64_t x = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (x >= count) return;
-  const int32_t c = list[x];
-  RegSketch<K, MODE> sk;
-  sk.reset();
-  const int64_t p0 = s.P[s.mstart[c]], p1 = s.P[s.mstart[c + 1]];
-  if (p1 > p0) stream_range<K, MODE>(s, c, p0, p1, sk);
-  write_row<K>(sk.key, sk.val, c, rows, rcount);
 }
 
 template <int K, int MODE>
@@ -490,16 +560,25 @@ __global__ void k_dedupe_max(const uint64_t *ks, const uint32_t *vs, const uint3
 }
 
 // Exact aggregation: one key (D[i], D[j]) per CSR entry; the row by binary search.
-__global__ void k_exact_keys(Graph g, const int32_t *D, int b, uint64_t *key, uint32_t *val) {
+// Entries of left-out rows (D < 0) get the key 2^(2b) - 1... sorted past every
+// real key, and are not counted in *kept.
+__global__ void k_exact_keys(Graph g, const int32_t *D, int b, uint64_t *key, uint32_t *val,
+                             unsigned long long *kept) {
   int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (e >= g.nnz) return;
-  int32_t lo = 0, hi = g.n - 1;
-  while (lo < hi) {
-    int32_t mid = (lo + hi + 1) >> 1;
-    if (g.off[mid] <= e) lo = mid; else hi = mid - 1;
+  bool in = false;
+  if (e < g.nnz) {
+    int32_t lo = 0, hi = g.n - 1;
+    while (lo < hi) {
+      int32_t mid = (lo + hi + 1) >> 1;
+      if (g.off[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    in = D[lo] >= 0;
+    key[e] = in ? ((uint64_t)(uint32_t)D[lo] << b) | (uint64_t)(uint32_t)D[g.idx[e]]
+                : ((1ull << (2 * b)) - 1);
+    val[e] = g.w[e];
   }
-  key[e] = ((uint64_t)(uint32_t)D[lo] << b) | (uint64_t)(uint32_t)D[g.idx[e]];
-  val[e] = g.w[e];
+  uint64_t m = __ballot(in);
+  if (lane_id() == 0 && m) atomicAdd(kept, (unsigned long long)__popcll(m));
 }
 
 // Sum the weights of each run of equal keys: in-wave segmented sums, one atomic
@@ -532,32 +611,31 @@ __global__ void __launch_bounds__(BLOCK)
 // ---- aggregation driver -----------------------------------------------------------------
 
 template <int K, int MODE>
-static void agg_mg(const AggStreams &s, const int32_t *single, int64_t nsingle, const int32_t *multi,
+static void agg_mg(const AggStreams &s, const AggBuckets &bk, int64_t waves, const int32_t *multi,
                    int64_t nmulti, const int64_t *cstart, const int32_t *owner, int64_t nchunks,
                    int64_t L, Pair *skbuf, Pair *rows, uint32_t *rcount, hipStream_t st) {
-  if (nsingle > 0) {
-    k_agg_single<K, MODE><<<grid_for(nsingle), BLOCK, 0, st>>>(s, single, nsingle, rows, rcount);
-    MGCD_LAUNCHED();
-  }
   if (nmulti > 0) {
     k_agg_chunks<K, MODE><<<grid_for(nchunks), BLOCK, 0, st>>>(s, multi, owner, cstart, nchunks, L, skbuf);
     MGCD_LAUNCHED();
     k_agg_multi<K><<<(unsigned)nmulti, BLOCK, 0, st>>>(multi, cstart, skbuf, rows, rcount);
     MGCD_LAUNCHED();
   }
+  if (waves > 0) {
+    k_agg_rows<K, MODE><<<(unsigned)ceil_div(waves, BLOCK / WAVE), BLOCK, 0, st>>>(s, bk, L, rows, rcount);
+    MGCD_LAUNCHED();
+  }
 }
 
 template <int MODE>
-static void agg_mg_k(int k, const AggStreams &s, const int32_t *single, int64_t nsingle,
-                     const int32_t *multi, int64_t nmulti, const int64_t *cstart, const int32_t *owner,
-                     int64_t nchunks, int64_t L, Pair *skbuf, Pair *rows, uint32_t *rcount,
-                     hipStream_t st) {
+static void agg_mg_k(int k, const AggStreams &s, const AggBuckets &bk, int64_t waves, const int32_t *multi,
+                     int64_t nmulti, const int64_t *cstart, const int32_t *owner, int64_t nchunks, int64_t L,
+                     Pair *skbuf, Pair *rows, uint32_t *rcount, hipStream_t st) {
   switch (k) {
-    case 1: agg_mg<1, MODE>(s, single, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case 2: agg_mg<2, MODE>(s, single, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case 4: agg_mg<4, MODE>(s, single, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case 8: agg_mg<8, MODE>(s, single, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case 16: agg_mg<16, MODE>(s, single, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case 1: agg_mg<1, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case 2: agg_mg<2, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case 4: agg_mg<4, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case 8: agg_mg<8, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case 16: agg_mg<16, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
     default: throw Error(-6, "k_aggregate must be 1, 2, 4, 8 or 16");
   }
 }
@@ -577,21 +655,31 @@ static void offsets_from_counts(const uint32_t *rowcnt, int32_t m, int64_t *out_
 
 static int64_t aggregate_exact(const Graph &g, const int32_t *D, int32_t m, int64_t *out_off,
                                int32_t *out_idx, uint32_t *out_w, Arena &a, hipStream_t st) {
-  const int64_t E = g.nnz;
-  const int b = bits_for((uint64_t)(m > 1 ? m - 1 : 1));
+  const int64_t E0 = g.nnz;
+  const int b = bits_for((uint64_t)m);  // room for the left-out key
   uint32_t *rowcnt = a.take<uint32_t>(m);
   zero_u32(rowcnt, m, st);
+  if (E0 == 0) {
+    offsets_from_counts(rowcnt, m, out_off, a, st);
+    return 0;
+  }
+  uint64_t *k0 = a.take<uint64_t>(E0), *k1 = a.take<uint64_t>(E0);
+  uint32_t *v0 = a.take<uint32_t>(E0), *v1 = a.take<uint32_t>(E0);
+  uint32_t *head = a.take<uint32_t>(E0);
+  int64_t *rid = a.take<int64_t>(E0 + 1);
+  unsigned long long *kept = a.take<unsigned long long>(1);
+  launch_zero_u64(kept, 1, st);
+  k_exact_keys<<<grid_for(E0), BLOCK, 0, st>>>(g, D, b, k0, v0, kept);
+  MGCD_LAUNCHED();
+  bool flip = radix_sort_pairs(k0, v0, k1, v1, E0, 2 * b, a, st);
+  unsigned long long hk = 0;
+  MGCD_HIP(hipMemcpyAsync(&hk, kept, sizeof(hk), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  const int64_t E = (int64_t)hk;
   if (E == 0) {
     offsets_from_counts(rowcnt, m, out_off, a, st);
     return 0;
   }
-  uint64_t *k0 = a.take<uint64_t>(E), *k1 = a.take<uint64_t>(E);
-  uint32_t *v0 = a.take<uint32_t>(E), *v1 = a.take<uint32_t>(E);
-  uint32_t *head = a.take<uint32_t>(E);
-  int64_t *rid = a.take<int64_t>(E + 1);
-  k_exact_keys<<<grid_for(E), BLOCK, 0, st>>>(g, D, b, k0, v0);
-  MGCD_LAUNCHED();
-  bool flip = radix_sort_pairs(k0, v0, k1, v1, E, 2 * b, a, st);
   const uint64_t *ks = flip ? k1 : k0;
   const uint32_t *vs = flip ? v1 : v0;
   k_heads<<<grid_for(E), BLOCK, 0, st>>>(ks, E, head);
@@ -618,9 +706,9 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   // members in ascending id within each community (stable radix sort by D)
   uint64_t *k0 = a.take<uint64_t>(n), *k1 = a.take<uint64_t>(n);
   uint32_t *v0 = a.take<uint32_t>(n), *v1 = a.take<uint32_t>(n);
-  k_member_keys<<<grid_for(n), BLOCK, 0, st>>>(D, n, k0, v0);
+  k_member_keys<<<grid_for(n), BLOCK, 0, st>>>(D, n, m, k0, v0);
   MGCD_LAUNCHED();
-  bool flip = radix_sort_pairs(k0, v0, k1, v1, n, bits_for((uint64_t)(m > 1 ? m - 1 : 1)), a, st);
+  bool flip = radix_sort_pairs(k0, v0, k1, v1, n, bits_for((uint64_t)m), a, st);
   const uint64_t *ks = flip ? k1 : k0;
   const uint32_t *mem = flip ? v1 : v0;
   int32_t *mstart = a.take<int32_t>((int64_t)m + 1);
@@ -632,8 +720,8 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   MGCD_LAUNCHED();
   scan_u32_i64(mdeg, P, n, P + n, a, st);
   // communities: short streams (one lane each) vs long ones (chunks + merge tree)
-  unsigned long long *cnt = a.take<unsigned long long>(2);
-  launch_zero_u64(cnt, 2, st);
+  unsigned long long *cnt = a.take<unsigned long long>(8);
+  launch_zero_u64(cnt, 8, st);
   uint64_t *ck0 = a.take<uint64_t>(m), *ck1 = a.take<uint64_t>(m);
   uint32_t *cv0 = a.take<uint32_t>(m), *cv1 = a.take<uint32_t>(m);
   k_comm_keys<<<grid_for(m), BLOCK, 0, st>>>(mstart, P, m, L, ck0, cv0, cnt);
@@ -642,11 +730,25 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   int32_t *corder = a.take<int32_t>(m);
   k_u32_to_i32<<<grid_for(m), BLOCK, 0, st>>>(cf ? cv1 : cv0, corder, m);
   MGCD_LAUNCHED();
-  unsigned long long hc[2];
+  unsigned long long hc[8];
   MGCD_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
   MGCD_HIP(hipStreamSynchronize(st));
-  const int64_t nsingle = (int64_t)hc[0], nmulti = (int64_t)hc[1];
-  int32_t *multi = corder + nsingle;
+  AggBuckets bk{};
+  int64_t pos = 0, waves = 0;
+  const int32_t *bucket_rows[7];
+  for (int b = 0; b <= 6; ++b) {
+    bucket_rows[b] = corder + pos;
+    pos += (int64_t)hc[b];
+  }
+  for (int b = 6; b >= 0; --b) {  // heaviest bucket first in the grid
+    bk.comm[b] = bucket_rows[b];
+    bk.ncomm[b] = (int64_t)hc[b];
+    bk.wave_begin[b] = waves;
+    waves += ceil_div((int64_t)hc[b] << b, WAVE);
+    bk.wave_end[b] = waves;
+  }
+  const int64_t nmulti = (int64_t)hc[7];
+  int32_t *multi = corder + pos;
   int64_t *cstart = nullptr, nchunks = 0;
   int32_t *owner = nullptr;
   Pair *skbuf = nullptr;
@@ -664,11 +766,14 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   }
   Pair *rows = a.take<Pair>((int64_t)m * k);
   uint32_t *rcount = a.take<uint32_t>(m);
-  AggStreams s{g, D, mem, mstart, P};
+  int64_t *rs = a.take<int64_t>(n);
+  k_row_starts<<<grid_for(n), BLOCK, 0, st>>>(g.off, mem, n, rs);
+  MGCD_LAUNCHED();
+  AggStreams s{g, D, mem, mstart, P, rs};
   switch (mode) {
-    case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, corder, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, corder, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case MODE_STD: agg_mg_k<MODE_STD>(k, s, corder, nsingle, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case MODE_STD: agg_mg_k<MODE_STD>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
     default: throw Error(-6, "unknown sketch mode");
   }
   int64_t total = 0;
@@ -721,7 +826,7 @@ size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
   b += radix_sort_ws_bytes(n) + 4096;
   b += (size_t)(n + 1) * (4 + 4 + 8) + 4096;        // mstart, mdeg, P
   b += scan_ws_bytes(n + 1) + 4096;
-  b += (size_t)n * (8 + 8 + 4 + 4 + 4) + 4096;      // community sort, order
+  b += (size_t)n * (8 + 8 + 4 + 4 + 4 + 8) + 4096;  // community sort, order, row starts
   int64_t chunks = nnz / (L > 0 ? L : 1) + n + 1;
   b += (size_t)(n + 1) * 16 + (size_t)chunks * (4 + (size_t)k * sizeof(Pair)) + 8192;
   b += (size_t)n * k * sizeof(Pair) + (size_t)n * 4 + 4096;  // rows, rcount

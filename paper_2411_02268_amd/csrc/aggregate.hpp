@@ -5,9 +5,15 @@
 namespace mgcd {
 
 // dense[c] for every used id c of C (ascending old id); D[i] = dense[C[i]]; returns m.
-int32_t renumber(const int32_t *C, int32_t n, int32_t *D, Arena &a, hipStream_t st);
+// Batched runs: only vertices whose graph has keep[gid[i]] count; the others get
+// D[i] = -1.  dense_out (optional, n+1 entries) receives the exclusive prefix of the
+// used flags (dense_out[c] = new id of c; dense_out[n] = m).
+int32_t renumber(const int32_t *C, int32_t n, int32_t *D, Arena &a, hipStream_t st,
+                 const int32_t *gid = nullptr, const uint8_t *keep = nullptr,
+                 int64_t *dense_out = nullptr);
 
-// Aggregated graph of g under the dense membership D (values in [0, m)).
+// Aggregated graph of g under the dense membership D (values in [0, m), or -1 for a
+// vertex left out, together with its whole row).
 // out_off: [m+1]; out_idx/out_w: capacity g.nnz.  Returns the entry count.
 // Louvain (symmetric=0): a community's row is the sketch (or exact sums) of the
 // stream of its members' rows, members in ascending id.  Leiden (symmetric=1): the
@@ -26,8 +32,10 @@ void launch_compose(const int32_t *in, const int32_t *map, int32_t *out, int32_t
 void launch_scatter_labels(const int32_t *map, const int32_t *val, int32_t *out, int32_t n,
                            hipStream_t st);
 
-// K[i] = row sums (uint32) and *W = their total (device uint64).
-void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, hipStream_t st);
+// K[i] = row sums (uint32) and *W = their total (device uint64).  Uses nnz + 1
+// int64 of transient workspace.
+void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, Arena &a, hipStream_t st);
+size_t degrees_ws_bytes(int64_t nnz);
 
 // Canonical labels: communities numbered in order of their smallest vertex.
 // Returns the number of communities (synchronises the stream).

@@ -1,0 +1,507 @@
+// Batched runs: many graphs processed together as one disjoint union.
+//
+// The graphs are packed into one CSR (vertex ids shifted by each graph's vertex
+// base); every sweep is one launch over all of them.  Everything that decides a
+// graph's course is kept per graph: its total weight W (Eq. 2), its moved /
+// proposal / gain counters, its convergence, its last pass.  A graph that has
+// converged stays frozen while the others continue, and a graph that finishes is
+// written out and dropped from later levels.  Because communities never cross
+// graphs and the union preserves every graph's id order (ties, stream order,
+// member order), each graph's labels equal those of its own single run.
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/mgcd.h"
+#include "aggregate.hpp"
+#include "batch.hpp"
+#include "move.hpp"
+#include "primitives.hpp"
+
+namespace mgcd {
+
+static unsigned grid_for(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, BLOCK); }
+
+struct DevDesc {
+  const int64_t *off;
+  const int32_t *idx;
+  const uint32_t *w;
+  int32_t *out;
+  int64_t n, nnz, vbase, ebase;
+};
+
+// graph y0 + blockIdx.y; x covers that graph's vertices and entries.
+__global__ void k_pack(const DevDesc *d, int32_t y0, int64_t *off, int32_t *idx, uint32_t *w,
+                       int32_t *gid) {
+  const DevDesc g = d[y0 + blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < g.n; v += stride) {
+    off[g.vbase + v] = g.ebase + g.off[v];
+    gid[g.vbase + v] = y0 + (int32_t)blockIdx.y;
+  }
+  for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < g.nnz; e += stride) {
+    idx[g.ebase + e] = (int32_t)(g.vbase + g.idx[e]);
+    w[g.ebase + e] = g.w[e];
+  }
+}
+
+__global__ void k_set_last_offset(int64_t *off, int64_t n, int64_t E) { off[n] = E; }
+
+// Per-graph sums of K (vertices of one graph are contiguous: a wave whose lanes all
+// belong to one graph adds once).
+__global__ void k_graph_weights(const uint32_t *K, const int32_t *gid, int64_t n, unsigned long long *Wg) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const bool in = i < n;
+  const int32_t g = in ? gid[i] : -1;
+  const unsigned long long k = in ? K[i] : 0;
+  const int32_t g0 = __shfl(g, 0);
+  if (__ballot(in && g != g0) == 0) {
+    unsigned long long s = wave_sum(k);
+    if (lane_id() == 0 && g0 >= 0 && s) atomicAdd(&Wg[g0], s);
+  } else if (in && k) {
+    atomicAdd(&Wg[g], k);
+  }
+}
+
+__global__ void k_u64_to_u32(const unsigned long long *a, uint32_t *b, int32_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) b[i] = (uint32_t)a[i];
+}
+
+// top[v] = D[top[v]] for input vertices whose graph is selected (sel[gid0[v]]).
+__global__ void k_compose_sel(int32_t *top, const int32_t *D, const int32_t *gid0, const uint8_t *sel,
+                              int64_t n) {
+  int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v < n && sel[gid0[v]]) top[v] = D[top[v]];
+}
+
+// Canonical labels of the selected graphs, written to each graph's own output:
+// communities numbered in order of their smallest vertex (within the graph).
+__global__ void k_min_sel(const int32_t *lab, const int32_t *gid0, const uint8_t *sel, int64_t n,
+                          int32_t *minv) {
+  int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v < n && sel[gid0[v]]) atomicMin(&minv[lab[v]], (int32_t)v);
+}
+__global__ void k_first_sel(const int32_t *lab, const int32_t *gid0, const uint8_t *sel,
+                            const int32_t *minv, int64_t n, uint32_t *first) {
+  int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v < n) first[v] = (sel[gid0[v]] && minv[lab[v]] == (int32_t)v) ? 1u : 0u;
+}
+__global__ void k_write_sel(const int32_t *lab, const int32_t *gid0, const uint8_t *sel,
+                            const int32_t *minv, const int64_t *rank, const DevDesc *d, int64_t n) {
+  int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v >= n) return;
+  const int32_t g = gid0[v];
+  if (!sel[g]) return;
+  const DevDesc dg = d[g];
+  dg.out[v - dg.vbase] = (int32_t)(rank[minv[lab[v]]] - rank[dg.vbase]);
+}
+__global__ void k_fill_i32v(int32_t *p, int32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_gather_i64(const int64_t *src, const int64_t *pos, int64_t *dst, int32_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) dst[i] = src[pos[i]];
+}
+// graph id of every vertex of the next level: graph g owns [base[g], base[g] + cnt[g]).
+__global__ void k_gid_ranges(const int64_t *base, const int64_t *cnt, int32_t y0, int32_t count,
+                             int32_t *gid) {
+  const int32_t g = y0 + (int32_t)blockIdx.y;
+  if (g >= count) return;
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < cnt[g]; v += (int64_t)gridDim.x * BLOCK)
+    gid[base[g] + v] = g;
+}
+
+struct Batch {
+  int32_t count;
+  int64_t N, E;
+  std::vector<int64_t> vb, eb, n, nnz;  // host: input bases and sizes
+  DevDesc *ddesc;
+  int32_t *gid0;
+  uint8_t *sel_d;
+};
+
+static void copy_h2d(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  MGCD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+  MGCD_HIP(hipStreamSynchronize(st));  // the host buffer may go away
+}
+
+static void set_sel(Batch &b, const std::vector<uint8_t> &sel, hipStream_t st) {
+  copy_h2d(b.sel_d, sel.data(), sel.size(), st);
+}
+
+// Write canonical labels for the graphs marked in `sel` from lab (level ids of the
+// input vertices).  Returns per-graph community counts through `comms`.
+static void write_selected(Batch &b, const int32_t *lab, const std::vector<uint8_t> &sel,
+                           std::vector<int64_t> &comms, Arena &a, hipStream_t st) {
+  size_t mk = a.mark();
+  const int64_t N = b.N;
+  int32_t *minv = a.take<int32_t>(N);
+  uint32_t *first = a.take<uint32_t>(N);
+  int64_t *rank = a.take<int64_t>(N + 1);
+  set_sel(b, sel, st);
+  k_fill_i32v<<<grid_for(N), BLOCK, 0, st>>>(minv, 0x7FFFFFFF, N);
+  MGCD_LAUNCHED();
+  k_min_sel<<<grid_for(N), BLOCK, 0, st>>>(lab, b.gid0, b.sel_d, N, minv);
+  MGCD_LAUNCHED();
+  k_first_sel<<<grid_for(N), BLOCK, 0, st>>>(lab, b.gid0, b.sel_d, minv, N, first);
+  MGCD_LAUNCHED();
+  scan_u32_i64(first, rank, N, rank + N, a, st);
+  k_write_sel<<<grid_for(N), BLOCK, 0, st>>>(lab, b.gid0, b.sel_d, minv, rank, b.ddesc, N);
+  MGCD_LAUNCHED();
+  // community count of graph g = rank[vb[g+1]] - rank[vb[g]]
+  std::vector<int64_t> pos(b.count + 1);
+  for (int32_t g = 0; g <= b.count; ++g) pos[g] = b.vb[g];
+  int64_t *pos_d = a.take<int64_t>(b.count + 1);
+  int64_t *val_d = a.take<int64_t>(b.count + 1);
+  copy_h2d(pos_d, pos.data(), pos.size() * sizeof(int64_t), st);
+  k_gather_i64<<<grid_for(b.count + 1), BLOCK, 0, st>>>(rank, pos_d, val_d, b.count + 1);
+  MGCD_LAUNCHED();
+  std::vector<int64_t> val(b.count + 1);
+  MGCD_HIP(hipMemcpyAsync(val.data(), val_d, val.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  for (int32_t g = 0; g < b.count; ++g)
+    if (sel[g]) comms[g] = val[g + 1] - val[g];
+  a.release(mk);
+}
+
+static std::vector<unsigned long long> read_gctr(const unsigned long long *gctr, int32_t count,
+                                                 hipStream_t st) {
+  std::vector<unsigned long long> h(3 * (size_t)count);
+  MGCD_HIP(hipMemcpyAsync(h.data(), gctr, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  return h;
+}
+
+static void zero_gctr(unsigned long long *gctr, int32_t count, hipStream_t st) {
+  MGCD_HIP(hipMemsetAsync(gctr, 0, 3 * (size_t)count * sizeof(unsigned long long), st));
+}
+
+void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_params *p,
+                 int32_t *const *outs, Arena &a, hipStream_t st, mgcd_graph_stats *gstats,
+                 mgcd_stats *total) {
+  Batch b;
+  b.count = count;
+  b.vb.assign(count + 1, 0);
+  b.eb.assign(count + 1, 0);
+  b.n.assign(count, 0);
+  b.nnz.assign(count, 0);
+  for (int32_t g = 0; g < count; ++g) {
+    const mgcd_csr &c = graphs[g];
+    if (c.n < 0 || c.nnz < 0) throw Error(MGCD_E_ARG, "negative graph size");
+    if (c.n > 0 && (!c.offsets || !outs[g])) throw Error(MGCD_E_ARG, "null graph or output");
+    if (c.nnz > 0 && (!c.indices || !c.weights)) throw Error(MGCD_E_ARG, "null graph arrays");
+    b.n[g] = c.n;
+    b.nnz[g] = c.nnz;
+    b.vb[g + 1] = b.vb[g] + c.n;
+    b.eb[g + 1] = b.eb[g] + c.nnz;
+  }
+  b.N = b.vb[count];
+  b.E = b.eb[count];
+  if (b.N >= (1ll << 31)) throw Error(MGCD_E_ARG, "batched vertex total must be below 2^31");
+  const int32_t N = (int32_t)b.N;
+  const int64_t E = b.E;
+  Timer total_t(st), tm(st);
+  total_t.start();
+
+  // pack the union
+  std::vector<DevDesc> hd(count);
+  int64_t max_items = 1;
+  for (int32_t g = 0; g < count; ++g) {
+    hd[g] = DevDesc{graphs[g].offsets, graphs[g].indices, graphs[g].weights, outs[g], b.n[g], b.nnz[g],
+                    b.vb[g], b.eb[g]};
+    max_items = std::max<int64_t>(max_items, std::max(b.n[g], b.nnz[g]));
+  }
+  b.ddesc = a.take<DevDesc>(count);
+  copy_h2d(b.ddesc, hd.data(), hd.size() * sizeof(DevDesc), st);
+  b.gid0 = a.take<int32_t>(N);
+  b.sel_d = a.take<uint8_t>(count);
+  uint8_t *active_d = a.take<uint8_t>(count);
+  unsigned long long *gctr = a.take<unsigned long long>(3 * (int64_t)count);
+  unsigned long long *Wg64 = a.take<unsigned long long>(count);
+  uint32_t *Wg = a.take<uint32_t>(count);
+  int64_t *uoff = a.take<int64_t>((int64_t)N + 1);
+  int32_t *uidx = a.take<int32_t>(E);
+  uint32_t *uw = a.take<uint32_t>(E);
+  for (int32_t y0 = 0; y0 < count; y0 += 65535) {
+    const int32_t ny = std::min<int32_t>(65535, count - y0);
+    dim3 grid((unsigned)std::min<int64_t>(ceil_div(max_items, BLOCK), 4096), (unsigned)ny);
+    k_pack<<<grid, BLOCK, 0, st>>>(b.ddesc, y0, uoff, uidx, uw, b.gid0);
+    MGCD_LAUNCHED();
+  }
+  k_set_last_offset<<<1, 1, 0, st>>>(uoff, N, E);
+  MGCD_LAUNCHED();
+  Graph U{N, E, uoff, uidx, uw};
+  if (p->validate) {
+    unsigned long long *flag = a.take<unsigned long long>(1);
+    launch_zero_u64(flag, 1, st);
+    launch_validate(U, flag, st);
+    unsigned long long hf = 0;
+    MGCD_HIP(hipMemcpyAsync(&hf, flag, sizeof(hf), hipMemcpyDeviceToHost, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+    if (hf) throw Error(MGCD_E_GRAPH, "a CSR failed validation");
+  }
+  uint32_t *Kbuf[2] = {a.take<uint32_t>(N), a.take<uint32_t>(N)};
+  {
+    unsigned long long *Wtot = a.take<unsigned long long>(1);
+    launch_degrees(U, Kbuf[0], Wtot, a, st);
+    MGCD_HIP(hipMemsetAsync(Wg64, 0, count * sizeof(unsigned long long), st));
+    if (N > 0) {
+      k_graph_weights<<<grid_for(N), BLOCK, 0, st>>>(Kbuf[0], b.gid0, N, Wg64);
+      MGCD_LAUNCHED();
+    }
+    std::vector<unsigned long long> hw(count);
+    MGCD_HIP(hipMemcpyAsync(hw.data(), Wg64, count * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+    for (int32_t g = 0; g < count; ++g)
+      if (hw[g] >= (1ull << 31)) throw Error(MGCD_E_OVERFLOW, "graph " + std::to_string(g) + ": total edge weight must be below 2^31");
+    k_u64_to_u32<<<grid_for(count), BLOCK, 0, st>>>(Wg64, Wg, count);
+    MGCD_LAUNCHED();
+  }
+  std::vector<uint64_t> W(count);
+  {
+    std::vector<unsigned long long> hw(count);
+    MGCD_HIP(hipMemcpyAsync(hw.data(), Wg64, count * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+    for (int32_t g = 0; g < count; ++g) W[g] = hw[g];
+  }
+
+  std::vector<mgcd_graph_stats> gs(count);
+  for (auto &x : gs) x = mgcd_graph_stats{};
+  std::vector<int64_t> comms(count, 0);
+  std::vector<uint8_t> finished(count, 0), active(count, 0), sel(count, 0);
+  for (int32_t g = 0; g < count; ++g) finished[g] = b.n[g] == 0;
+  int32_t *Ca = a.take<int32_t>(N), *Cb = a.take<int32_t>(N);
+  mgcd_stats s{};
+  float ms_lm = 0, ms_agg = 0;
+
+  if (algo == MGCD_ALGO_LPA) {
+    launch_iota(Ca, N, st);
+    Schedule sch;
+    build_schedule(U, p->mode, p->k, p->chunk_len, sch, a, st);
+    for (int32_t g = 0; g < count; ++g) active[g] = !finished[g];
+    copy_h2d(active_d, active.data(), count, st);
+    for (int it = 0; it < p->max_iterations && N > 0; ++it) {
+      zero_gctr(gctr, count, st);
+      SweepArgs args{U, Ca, nullptr, Kbuf[0], nullptr, 0, 0, Cb, nullptr, gctr};
+      args.gid = b.gid0;
+      args.Wg = Wg;
+      args.active = active_d;
+      args.gctr = gctr;
+      tm.start();
+      launch_sweep(args, sch, ALGO_LPA, p->mode, p->k, p->chunk_len, st);
+      ms_lm += tm.stop();
+      auto h = read_gctr(gctr, count, st);
+      std::swap(Ca, Cb);
+      s.iterations += 1;
+      bool any = false;
+      for (int32_t g = 0; g < count; ++g) {
+        if (!active[g]) continue;
+        gs[g].iterations += 1;
+        gs[g].edges_scanned += b.nnz[g];
+        gs[g].moved_last = (int64_t)h[3 * g];
+        s.edges_scanned += b.nnz[g];
+        if ((double)h[3 * g] <= p->tolerance * (double)b.n[g]) active[g] = 0;
+        any |= active[g] != 0;
+      }
+      copy_h2d(active_d, active.data(), count, st);
+      if (!any) break;
+    }
+    for (int32_t g = 0; g < count; ++g) sel[g] = !finished[g];
+    write_selected(b, Ca, sel, comms, a, st);
+    for (int32_t g = 0; g < count; ++g) {
+      gs[g].passes = b.n[g] > 0 ? 1 : 0;
+      gs[g].communities = (int32_t)comms[g];
+    }
+    s.passes = 1;
+  } else {
+    // Louvain: all unfinished graphs move through the levels together
+    int32_t *top = a.take<int32_t>(N);
+    int32_t *D = a.take<int32_t>(N);
+    int32_t *gid_cur = a.take<int32_t>(N);
+    int32_t *gid_next = a.take<int32_t>(N);
+    uint32_t *Sig = a.take<uint32_t>(N);
+    int32_t *size = a.take<int32_t>(N);
+    int64_t *dense = a.take<int64_t>((int64_t)N + 1);
+    int64_t *nb_d = a.take<int64_t>(count + 1);
+    int64_t *nc_d = a.take<int64_t>(count + 1);
+    int64_t *tmp_d = a.take<int64_t>(count + 1);
+    struct Slot {
+      int64_t *off;
+      int32_t *idx;
+      uint32_t *w;
+    } slot[2];
+    for (int q = 0; q < 2; ++q) {
+      slot[q].off = a.take<int64_t>((int64_t)N + 1);
+      slot[q].idx = a.take<int32_t>(E);
+      slot[q].w = a.take<uint32_t>(E);
+    }
+    launch_iota(top, N, st);
+    MGCD_HIP(hipMemcpyAsync(gid_cur, b.gid0, (size_t)N * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    std::vector<int64_t> vb_cur(b.vb.begin(), b.vb.end() - 1), n_cur(b.n), nnz_cur(b.nnz);
+    Graph cur = U;
+    int kcur = 0, next_slot = 0;
+    double tol = p->tolerance;
+    for (int pass = 0; pass < p->max_passes; ++pass) {
+      bool any_left = false;
+      for (int32_t g = 0; g < count; ++g) any_left |= !finished[g];
+      if (!any_left) break;
+      const int32_t nl = cur.n;
+      uint32_t *K = Kbuf[kcur];
+      s.passes += 1;
+      size_t mark = a.mark();
+      tm.start();
+      Schedule sch;
+      build_schedule(cur, p->mode, p->k, p->chunk_len, sch, a, st);
+      launch_iota(Ca, nl, st);
+      launch_community_totals(Ca, K, Sig, size, nl, st);
+      ms_lm += tm.stop();
+      for (int32_t g = 0; g < count; ++g) {
+        active[g] = !finished[g];
+        if (!finished[g]) gs[g].passes += 1;
+      }
+      copy_h2d(active_d, active.data(), count, st);
+      for (int it = 0; it < p->max_iterations; ++it) {
+        zero_gctr(gctr, count, st);
+        SweepArgs args{cur, Ca, nullptr, K, Sig, 0, (it % 2 == 0) ? -1 : 1, Cb, nullptr, gctr};
+        args.gid = gid_cur;
+        args.Wg = Wg;
+        args.active = active_d;
+        args.gctr = gctr;
+        tm.start();
+        launch_sweep(args, sch, ALGO_MOVE, p->mode, p->k, p->chunk_len, st);
+        ms_lm += tm.stop();
+        auto h = read_gctr(gctr, count, st);
+        s.iterations += 1;
+        launch_apply_moves(Ca, Cb, K, Sig, size, nl, st);
+        std::swap(Ca, Cb);
+        bool any = false;
+        for (int32_t g = 0; g < count; ++g) {
+          if (!active[g]) continue;
+          gs[g].iterations += 1;
+          gs[g].edges_scanned += nnz_cur[g];
+          gs[g].moved_last = (int64_t)h[3 * g];
+          s.edges_scanned += nnz_cur[g];
+          const double WW = (double)W[g] * (double)W[g];
+          if (h[3 * g + 1] == 0 || 2.0 * (double)h[3 * g + 2] <= tol * WW) active[g] = 0;
+          any |= active[g] != 0;
+        }
+        copy_h2d(active_d, active.data(), count, st);
+        if (!any) break;
+      }
+      a.release(mark);
+      tm.start();
+      // renumber over the unfinished graphs and decide who stops here
+      for (int32_t g = 0; g < count; ++g) sel[g] = !finished[g];
+      set_sel(b, sel, st);
+      renumber(Ca, nl, D, a, st, gid_cur, b.sel_d, dense);
+      std::vector<int64_t> pos(count + 1);
+      for (int32_t g = 0; g < count; ++g) pos[g] = vb_cur[g];
+      pos[count] = nl;
+      copy_h2d(tmp_d, pos.data(), pos.size() * sizeof(int64_t), st);
+      k_gather_i64<<<grid_for(count + 1), BLOCK, 0, st>>>(dense, tmp_d, nb_d, count + 1);
+      MGCD_LAUNCHED();
+      std::vector<int64_t> db(count + 1);
+      MGCD_HIP(hipMemcpyAsync(db.data(), nb_d, db.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      MGCD_HIP(hipStreamSynchronize(st));
+      std::vector<uint8_t> stop(count, 0);
+      bool cont = false;
+      for (int32_t g = 0; g < count; ++g) {
+        if (finished[g]) continue;
+        const int64_t m = db[g + 1] - db[g];  // graph g's communities (a contiguous id range)
+        stop[g] = pass == p->max_passes - 1 || (double)m > p->aggregation_tolerance * (double)n_cur[g];
+        cont |= !stop[g];
+      }
+      // graphs that stop: compose their labels with this renumbering and write them
+      set_sel(b, stop, st);
+      k_compose_sel<<<grid_for(N), BLOCK, 0, st>>>(top, D, b.gid0, b.sel_d, N);
+      MGCD_LAUNCHED();
+      write_selected(b, top, stop, comms, a, st);
+      for (int32_t g = 0; g < count; ++g)
+        if (stop[g]) {
+          finished[g] = 1;
+          gs[g].communities = (int32_t)comms[g];
+        }
+      if (!cont) {
+        ms_agg += tm.stop();
+        break;
+      }
+      // renumber again over the graphs that go on, compose, aggregate
+      for (int32_t g = 0; g < count; ++g) sel[g] = !finished[g];
+      set_sel(b, sel, st);
+      const int32_t m = renumber(Ca, nl, D, a, st, gid_cur, b.sel_d, dense);
+      k_compose_sel<<<grid_for(N), BLOCK, 0, st>>>(top, D, b.gid0, b.sel_d, N);
+      MGCD_LAUNCHED();
+      k_gather_i64<<<grid_for(count + 1), BLOCK, 0, st>>>(dense, tmp_d, nb_d, count + 1);
+      MGCD_LAUNCHED();
+      MGCD_HIP(hipMemcpyAsync(db.data(), nb_d, db.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      MGCD_HIP(hipStreamSynchronize(st));
+      auto &sl = slot[next_slot];
+      const int64_t nnz2 = aggregate(cur, D, m, p->mode, p->k_aggregate, p->chunk_len, 0, sl.off, sl.idx,
+                                     sl.w, a, st);
+      launch_group_sums(D, K, Kbuf[1 - kcur], nl, m, st);
+      // next level: graph g owns [db[g], db[g+1]) (empty when finished)
+      std::vector<int64_t> cnt(count + 1, 0), base(count + 1, 0);
+      for (int32_t g = 0; g < count; ++g) {
+        base[g] = db[g];
+        cnt[g] = finished[g] ? 0 : db[g + 1] - db[g];
+        vb_cur[g] = db[g];
+        n_cur[g] = cnt[g];
+      }
+      copy_h2d(nb_d, base.data(), base.size() * sizeof(int64_t), st);
+      copy_h2d(nc_d, cnt.data(), cnt.size() * sizeof(int64_t), st);
+      int64_t maxc = 1;
+      for (int32_t g = 0; g < count; ++g) maxc = std::max(maxc, cnt[g]);
+      for (int32_t y0 = 0; y0 < count; y0 += 65535) {
+        const int32_t ny = std::min<int32_t>(65535, count - y0);
+        dim3 grid((unsigned)std::min<int64_t>(ceil_div(maxc, BLOCK), 4096), (unsigned)ny);
+        k_gid_ranges<<<grid, BLOCK, 0, st>>>(nb_d, nc_d, y0, count, gid_next);
+        MGCD_LAUNCHED();
+      }
+      // entries per graph at the next level
+      std::vector<int64_t> pos2(count + 1);
+      for (int32_t g = 0; g < count; ++g) pos2[g] = db[g];
+      pos2[count] = m;
+      copy_h2d(tmp_d, pos2.data(), pos2.size() * sizeof(int64_t), st);
+      k_gather_i64<<<grid_for(count + 1), BLOCK, 0, st>>>(sl.off, tmp_d, nb_d, count + 1);
+      MGCD_LAUNCHED();
+      std::vector<int64_t> eb2(count + 1);
+      MGCD_HIP(hipMemcpyAsync(eb2.data(), nb_d, eb2.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      MGCD_HIP(hipStreamSynchronize(st));
+      for (int32_t g = 0; g < count; ++g) nnz_cur[g] = finished[g] ? 0 : eb2[g + 1] - eb2[g];
+      std::swap(gid_cur, gid_next);
+      ms_agg += tm.stop();
+      cur = Graph{m, nnz2, sl.off, sl.idx, sl.w};
+      next_slot = 1 - next_slot;
+      kcur = 1 - kcur;
+      tol /= p->tolerance_drop;
+    }
+  }
+  for (int32_t g = 0; g < count; ++g) {
+    if (b.n[g] == 0) gs[g] = mgcd_graph_stats{};
+    s.communities += gs[g].communities;
+  }
+  s.ms_local_move = ms_lm;
+  s.ms_aggregate = ms_agg;
+  s.ms_total = total_t.stop();
+  if (gstats)
+    for (int32_t g = 0; g < count; ++g) gstats[g] = gs[g];
+  if (total) *total = s;
+}
+
+size_t batched_workspace_bytes(int32_t algo, int32_t count, int64_t N, int64_t E, const mgcd_params *p) {
+  const int64_t L = p->chunk_len > 0 ? p->chunk_len : 1;
+  size_t b = (size_t)count * (sizeof(DevDesc) + 64) + 64 * 1024;
+  b += (size_t)(N + 1) * 8 + (size_t)E * 8;                 // union
+  b += (size_t)N * 4 * 14 + (size_t)(N + 1) * 8;             // per-vertex state
+  if (algo != MGCD_ALGO_LPA) b += 2 * ((size_t)(N + 1) * 8 + (size_t)E * 8);  // level slots
+  size_t sched = schedule_ws_bytes((int32_t)N, E, p->mode, p->k, L);
+  size_t agg = algo == MGCD_ALGO_LPA ? 0 : aggregate_ws_bytes((int32_t)N, E, p->mode, p->k_aggregate, L);
+  size_t misc = (size_t)N * (4 + 4 + 8 + 8) + scan_ws_bytes(N + 1) + 64 * 1024;
+  size_t phase = sched > agg ? sched : agg;
+  phase = phase > degrees_ws_bytes(E) ? phase : degrees_ws_bytes(E);
+  return b + phase + misc + (1u << 20);
+}
+
+}  // namespace mgcd

@@ -73,6 +73,28 @@ struct Arena {
   void release(size_t m) { used = m; }
 };
 
+// ---- device time of a stretch of stream work (host) --------------------------------
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t st;
+  explicit Timer(hipStream_t s) : st(s) {
+    MGCD_HIP(hipEventCreate(&a));
+    MGCD_HIP(hipEventCreate(&b));
+  }
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  void start() { MGCD_HIP(hipEventRecord(a, st)); }
+  float stop() {  // synchronises
+    MGCD_HIP(hipEventRecord(b, st));
+    MGCD_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    MGCD_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  }
+};
+
 // ---- wave helpers (device) -------------------------------------------------------
 __device__ inline int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
 

@@ -16,6 +16,7 @@
 
 #include "../../include/mgcd.h"
 #include "aggregate.hpp"
+#include "batch.hpp"
 #include "move.hpp"
 #include "primitives.hpp"
 
@@ -43,27 +44,6 @@ struct ClassTimer {
   }
 };
 
-struct Timer {
-  hipEvent_t a = nullptr, b = nullptr;
-  hipStream_t st;
-  explicit Timer(hipStream_t s) : st(s) {
-    MGCD_HIP(hipEventCreate(&a));
-    MGCD_HIP(hipEventCreate(&b));
-  }
-  ~Timer() {
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-  }
-  void start() { MGCD_HIP(hipEventRecord(a, st)); }
-  float stop() {  // synchronises
-    MGCD_HIP(hipEventRecord(b, st));
-    MGCD_HIP(hipEventSynchronize(b));
-    float ms = 0;
-    MGCD_HIP(hipEventElapsedTime(&ms, a, b));
-    return ms;
-  }
-};
-
 static void check_params(const mgcd_params *p) {
   if (!p) throw Error(MGCD_E_ARG, "params is null");
   if (p->mode < 0 || p->mode > 3) throw Error(MGCD_E_UNSUPPORTED, "unknown sketch mode");
@@ -81,6 +61,8 @@ static Graph view(const mgcd_csr *g) {
   if (g->n < 0 || g->nnz < 0) throw Error(MGCD_E_ARG, "negative graph size");
   if (g->n > 0 && (!g->offsets)) throw Error(MGCD_E_ARG, "offsets is null");
   if (g->nnz > 0 && (!g->indices || !g->weights)) throw Error(MGCD_E_ARG, "indices/weights null");
+  if ((((uintptr_t)g->indices) | ((uintptr_t)g->weights)) & 15)
+    throw Error(MGCD_E_ARG, "indices and weights must be 16-byte aligned");
   return Graph{g->n, g->nnz, g->offsets, g->indices, g->weights};
 }
 
@@ -100,7 +82,7 @@ static uint64_t prepare(const Graph &g, const mgcd_params *p, uint32_t *K, Arena
     launch_validate(g, scr, st);
     if (read_dev(scr, st) != 0) throw Error(MGCD_E_GRAPH, "CSR failed validation");
   }
-  launch_degrees(g, K, scr + 1, st);
+  launch_degrees(g, K, scr + 1, a, st);
   uint64_t W = read_dev(scr + 1, st);
   if (W >= (1ull << 31)) throw Error(MGCD_E_OVERFLOW, "total edge weight must be below 2^31");
   return W;
@@ -294,7 +276,9 @@ static size_t workspace_bytes(int32_t algo, int32_t n, int64_t nnz, const mgcd_p
   size_t sched = schedule_ws_bytes(n, nnz, mode, p->k, L);
   size_t agg = algo == MGCD_ALGO_LPA ? 0 : aggregate_ws_bytes(n, nnz, mode, p->k_aggregate, L);
   size_t misc = (size_t)n * (4 + 4 + 8 + 8) + scan_ws_bytes((int64_t)n + 1) + 16 * 1024;
+  size_t degrees = degrees_ws_bytes(nnz);
   size_t phase = sched > agg ? sched : agg;
+  phase = phase > degrees ? phase : degrees;
   return fixed + phase + misc + (1u << 20);
 }
 
@@ -389,13 +373,17 @@ int leiden_run(const mgcd_csr *g, const mgcd_params *p, int32_t *out, void *ws, 
   return run_checked(MGCD_ALGO_LEIDEN, g, p, out, ws, ws_bytes, stats, stream);
 }
 
+size_t mgcd_modularity_workspace_bytes(int32_t n, int64_t nnz) {
+  return (size_t)(n > 0 ? n : 0) * 16 + degrees_ws_bytes(nnz > 0 ? nnz : 0) + 64 * 1024;
+}
+
 int modularity(const mgcd_csr *gin, const int32_t *C, double *q, void *ws, size_t ws_bytes,
                void *stream) {
   return guarded([&] {
     if (!q) throw Error(MGCD_E_ARG, "q is null");
     Graph g = view(gin);
     if (g.n > 0 && !C) throw Error(MGCD_E_ARG, "communities is null");
-    size_t need = (size_t)g.n * 8 + 64 * 1024;
+    size_t need = mgcd_modularity_workspace_bytes(g.n, g.nnz);
     if (ws_bytes < need) throw Error(MGCD_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
     if (g.n == 0) {
       *q = 0.0;
@@ -407,7 +395,7 @@ int modularity(const mgcd_csr *gin, const int32_t *C, double *q, void *ws, size_
     uint32_t *K = a.take<uint32_t>(g.n);
     unsigned long long *Wd = a.take<unsigned long long>(1);
     unsigned long long *terms = a.take<unsigned long long>(2);
-    launch_degrees(g, K, Wd, st);
+    launch_degrees(g, K, Wd, a, st);
     modularity_terms(g, C, K, terms, a, st);
     unsigned long long h[2];
     MGCD_HIP(hipMemcpyAsync(h, terms, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -495,6 +483,50 @@ int mgcd_aggregate(const mgcd_csr *gin, const mgcd_params *p, const int32_t *D, 
                          out_idx, out_w, a, st);
     MGCD_HIP(hipStreamSynchronize(st));
   });
+}
+
+size_t mgcd_workspace_bytes_batched(int32_t algo, int32_t count, int64_t total_n, int64_t total_nnz,
+                                    const mgcd_params *p) {
+  mgcd_params d;
+  if (!p) {
+    mgcd_default_params(algo, &d);
+    p = &d;
+  }
+  return batched_workspace_bytes(algo, count < 0 ? 0 : count, total_n < 0 ? 0 : total_n,
+                                 total_nnz < 0 ? 0 : total_nnz, p);
+}
+
+static int run_batched_checked(int32_t algo, const mgcd_csr *graphs, int32_t count, const mgcd_params *p,
+                               int32_t *const *outs, void *ws, size_t ws_bytes, mgcd_graph_stats *gs,
+                               mgcd_stats *total, void *stream) {
+  return guarded([&] {
+    if (!graphs || !outs || count < 0) throw Error(MGCD_E_ARG, "null argument");
+    check_params(p);
+    int64_t N = 0, E = 0;
+    for (int32_t g = 0; g < count; ++g) {
+      N += graphs[g].n;
+      E += graphs[g].nnz;
+      if ((((uintptr_t)graphs[g].indices) | ((uintptr_t)graphs[g].weights)) & 15)
+        throw Error(MGCD_E_ARG, "indices and weights must be 16-byte aligned");
+    }
+    if (N >= (1ll << 31)) throw Error(MGCD_E_ARG, "batched vertex total must be below 2^31");
+    size_t need = batched_workspace_bytes(algo, count, N, E, p);
+    if (ws_bytes < need) throw Error(MGCD_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    Arena a = make_arena(ws, ws_bytes);
+    if (count == 0) return;
+    run_batched(algo, graphs, count, p, outs, a, (hipStream_t)stream, gs, total);
+  });
+}
+
+int lpa_run_batched(const mgcd_csr *graphs, int32_t count, const mgcd_params *p, int32_t *const *outs,
+                    void *ws, size_t ws_bytes, mgcd_graph_stats *gs, mgcd_stats *total, void *stream) {
+  return run_batched_checked(MGCD_ALGO_LPA, graphs, count, p, outs, ws, ws_bytes, gs, total, stream);
+}
+
+int louvain_run_batched(const mgcd_csr *graphs, int32_t count, const mgcd_params *p, int32_t *const *outs,
+                        void *ws, size_t ws_bytes, mgcd_graph_stats *gs, mgcd_stats *total,
+                        void *stream) {
+  return run_batched_checked(MGCD_ALGO_LOUVAIN, graphs, count, p, outs, ws, ws_bytes, gs, total, stream);
 }
 
 const char *mgcd_last_error(void) { return g_last_error.c_str(); }

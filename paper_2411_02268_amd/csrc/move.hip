@@ -39,9 +39,19 @@ __device__ inline int32_t community_of_self(const SweepArgs &a, int32_t i) {
 }
 
 // Evaluate one candidate community c with exact linking weight kc; keep the best.
+// Total weight W of vertex i's graph.
+__device__ inline uint64_t weight_of(const SweepArgs &a, int32_t i) {
+  return a.gid ? (uint64_t)a.Wg[a.gid[i]] : a.W;
+}
+
+// Batched runs: a vertex of a graph that no longer moves keeps its community.
+__device__ inline bool frozen(const SweepArgs &a, int32_t i) {
+  return a.gid && !a.active[a.gid[i]];
+}
+
 template <int ALGO>
-__device__ inline void consider(const SweepArgs &a, int32_t d, int64_t Ki, int64_t Sd, uint32_t kd,
-                                int32_t c, uint32_t kc, int32_t &best, int64_t &bestG) {
+__device__ inline void consider(const SweepArgs &a, int64_t W, int32_t d, int64_t Ki, int64_t Sd,
+                                uint32_t kd, int32_t c, uint32_t kc, int32_t &best, int64_t &bestG) {
   if (ALGO == ALGO_LPA) {
     int64_t G = (int64_t)kc;
     if (best < 0 || G > bestG || (G == bestG && c < best)) {
@@ -50,7 +60,7 @@ __device__ inline void consider(const SweepArgs &a, int32_t d, int64_t Ki, int64
     }
   } else {
     if (c == d) return;
-    int64_t G = (int64_t)a.W * ((int64_t)kc - (int64_t)kd) -
+    int64_t G = W * ((int64_t)kc - (int64_t)kd) -
                 Ki * (Ki + (int64_t)a.Sig[c] - Sd);
     if (G > 0 && (best < 0 || G > bestG || (G == bestG && c < best))) {
       best = c;
@@ -66,14 +76,26 @@ __device__ inline void finish(const SweepArgs &a, int32_t i, int32_t d, int32_t 
   if (ALGO == ALGO_LPA) {
     if (best >= 0) target = best;
   } else if (best >= 0) {
-    ct.prop += 1;
-    ct.sumG += (uint64_t)bestG;
+    if (!a.gctr) {
+      ct.prop += 1;
+      ct.sumG += (uint64_t)bestG;
+    }
     bool ok = a.dir == 0 || (a.dir < 0 ? best < d : best > d);
     if (ok) target = best;
   }
   a.Cnew[i] = target;
-  ct.moved += target != d;
   if (ALGO != ALGO_LPA && a.gain) a.gain[i] = best >= 0 ? bestG : 0;
+  if (a.gctr) {  // batched: per-graph counters (the block counters stay zero)
+    unsigned long long *gc = a.gctr + 3 * (int64_t)a.gid[i];
+    if (target != d) atomicAdd(&gc[0], 1ull);
+    if (ALGO != ALGO_LPA && best >= 0) {
+      atomicAdd(&gc[1], 1ull);
+      atomicAdd(&gc[2], (unsigned long long)bestG);
+    }
+    ct = Counters{};
+    return;
+  }
+  ct.moved += target != d;
 }
 
 __device__ inline void flush_counters(const SweepArgs &a, Counters ct) {
@@ -104,29 +126,56 @@ __device__ inline uint32_t stream_key(const SweepArgs &a, int32_t i, int32_t j, 
   return (uint32_t)a.C[j];
 }
 
-// Stream entries [lo, hi) of row i (stride 1) into f(key, weight), skipped entries
-// dropped.  Four entries per step: their index and weight loads, then their four
-// label gathers, are all in flight before the first update.
+// Stream entries lo, lo+stride, ... < hi of row i into f(key, weight), skipped
+// entries dropped.  Four entries per step: their index and weight loads, then their
+// four label gathers, are all in flight before the first update.  With stride 1 the
+// loads are 16-byte vector loads once the position is 4-aligned.
+// Row data is streamed with non-temporal loads so that it does not evict the
+// gathered community labels C[j] from L2.
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+__device__ inline int32_t ld_idx(const int32_t *p) { return __builtin_nontemporal_load(p); }
+__device__ inline uint32_t ld_w(const uint32_t *p) { return __builtin_nontemporal_load(p); }
+__device__ inline v4i32 ld4(const void *p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const v4i32 *>(p));
+}
+
 template <int ALGO, typename F>
 __device__ inline void for_each_entry(const SweepArgs &a, int32_t i, int32_t bi, int64_t lo,
                                       int64_t hi, F &&f, int64_t stride = 1) {
   int64_t e = lo;
-  for (; e + 3 * stride < hi; e += 4 * stride) {
-    int32_t j[4];
-    uint32_t w[4], c[4];
+  if (stride == 1) {
+    for (; e < hi && (e & 3); ++e) {
+      uint32_t c = stream_key<ALGO>(a, i, ld_idx(a.g.idx + e), bi);
+      if (c != EMPTY) f(c, ld_w(a.g.w + e));
+    }
+    for (; e + 4 <= hi; e += 4) {
+      const v4i32 j = ld4(a.g.idx + e);
+      const v4i32 w = ld4(a.g.w + e);
+      const uint32_t c0 = stream_key<ALGO>(a, i, j.x, bi), c1 = stream_key<ALGO>(a, i, j.y, bi);
+      const uint32_t c2 = stream_key<ALGO>(a, i, j.z, bi), c3 = stream_key<ALGO>(a, i, j.w, bi);
+      if (c0 != EMPTY) f(c0, (uint32_t)w.x);
+      if (c1 != EMPTY) f(c1, (uint32_t)w.y);
+      if (c2 != EMPTY) f(c2, (uint32_t)w.z);
+      if (c3 != EMPTY) f(c3, (uint32_t)w.w);
+    }
+  } else {
+    for (; e + 3 * stride < hi; e += 4 * stride) {
+      int32_t j[4];
+      uint32_t w[4], c[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) j[u] = a.g.idx[e + u * stride];
+      for (int u = 0; u < 4; ++u) j[u] = ld_idx(a.g.idx + e + u * stride);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) w[u] = a.g.w[e + u * stride];
+      for (int u = 0; u < 4; ++u) w[u] = ld_w(a.g.w + e + u * stride);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) c[u] = stream_key<ALGO>(a, i, j[u], bi);
+      for (int u = 0; u < 4; ++u) c[u] = stream_key<ALGO>(a, i, j[u], bi);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (c[u] != EMPTY) f(c[u], w[u]);
+      for (int u = 0; u < 4; ++u)
+        if (c[u] != EMPTY) f(c[u], w[u]);
+    }
   }
   for (; e < hi; e += stride) {
-    uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
-    if (c != EMPTY) f(c, a.g.w[e]);
+    uint32_t c = stream_key<ALGO>(a, i, ld_idx(a.g.idx + e), bi);
+    if (c != EMPTY) f(c, ld_w(a.g.w + e));
   }
 }
 
@@ -149,7 +198,8 @@ __global__ void __launch_bounds__(BLOCK)
   const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
   RegSketch<K, MODE> s;
   s.reset();
-  for_each_entry<ALGO>(a, i, bi, lo, hi, [&](uint32_t c, uint32_t w) { s.update(c, w); });
+  if (!frozen(a, i))
+    for_each_entry<ALGO>(a, i, bi, lo, hi, [&](uint32_t c, uint32_t w) { s.update(c, w); });
   s.finalize();
 #pragma unroll
   for (int p = 0; p < K; ++p) sk[q * K + p] = Pair{s.key[p], s.val[p]};
@@ -169,6 +219,10 @@ __global__ void __launch_bounds__(BLOCK)
   const int32_t m = blockIdx.x;
   const int32_t i = multi[m];
   const int64_t cb = cstart[m], nc = cstart[m + 1] - cb;
+  if (frozen(a, i)) {  // block-uniform
+    if (t == 0) a.Cnew[i] = community_of_self<ALGO>(a, i);
+    return;
+  }
   if (t == 0) flag_any = 0;
   __syncthreads();
   bool f = false;
@@ -215,11 +269,12 @@ __global__ void __launch_bounds__(BLOCK)
     Counters ct;
     int32_t best = -1;
     int64_t bestG = 0;
-    const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+    const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
+  const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
     const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
 #pragma unroll
     for (int p = 0; p < K; ++p)
-      if (key[p] != EMPTY) consider<ALGO>(a, d, Ki, Sd, kd, (int32_t)key[p], ex[p], best, bestG);
+      if (key[p] != EMPTY) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)key[p], ex[p], best, bestG);
     finish<ALGO>(a, i, d, best, bestG, ct);
     if (ct.moved) atomicAdd(&a.ctr[0], (unsigned long long)ct.moved);
     if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
@@ -256,8 +311,10 @@ __global__ void __launch_bounds__(BLOCK)
   const int q = lane & (P - 1);
   const int base_lane = lane & ~(P - 1);
   const int64_t r = (wave - bk.wave_begin[b]) * (WAVE >> logp) + (lane >> logp);
-  const bool valid = wave < bk.wave_end[0] && r < bk.nrows[b];
-  const int32_t i = valid ? bk.rows[b][r] : 0;
+  const bool listed = wave < bk.wave_end[0] && r < bk.nrows[b];
+  const int32_t i = listed ? bk.rows[b][r] : 0;
+  const bool valid = listed && !frozen(a, i);
+  if (listed && !valid && q == 0) a.Cnew[i] = community_of_self<ALGO>(a, i);
   const int64_t lo = valid ? a.g.off[i] : 0, hi = valid ? a.g.off[i + 1] : 0;
   const int64_t nc = (hi - lo + L - 1) / L;
   const int32_t bi = (ALGO == ALGO_REFINE && valid) ? a.bound[i] : 0;
@@ -315,11 +372,12 @@ __global__ void __launch_bounds__(BLOCK)
   if (valid && q == 0) {
     int32_t best = -1;
     int64_t bestG = 0;
-    const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+    const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
+  const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
     const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
 #pragma unroll
     for (int p = 0; p < K; ++p)
-      if (key[p] != EMPTY) consider<ALGO>(a, d, Ki, Sd, kd, (int32_t)key[p], ex[p], best, bestG);
+      if (key[p] != EMPTY) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)key[p], ex[p], best, bestG);
     finish<ALGO>(a, i, d, best, bestG, ct);
   }
   flush_counters(a, ct);
@@ -334,7 +392,9 @@ __global__ void __launch_bounds__(BLOCK)
     k_exact_small(SweepArgs a, const int32_t *__restrict__ list, int64_t count) {
   Counters ct;
   int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (t < count) {
+  if (t < count && frozen(a, list[t])) {
+    a.Cnew[list[t]] = community_of_self<ALGO>(a, list[t]);
+  } else if (t < count) {
     const int32_t i = list[t];
     const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
     const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
@@ -344,7 +404,8 @@ __global__ void __launch_bounds__(BLOCK)
       kd += stream_key<ALGO>(a, i, a.g.idx[e], bi) == (uint32_t)d ? a.g.w[e] : 0u;
     int32_t best = -1;
     int64_t bestG = 0;
-    const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+    const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
+  const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
     const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
     for (int64_t e = lo; e < hi; ++e) {
       uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
@@ -354,7 +415,7 @@ __global__ void __launch_bounds__(BLOCK)
       if (!first) continue;
       uint32_t kc = 0;
       for (int64_t f = e; f < hi; ++f) kc += stream_key<ALGO>(a, i, a.g.idx[f], bi) == c ? a.g.w[f] : 0u;
-      consider<ALGO>(a, d, Ki, Sd, kd, (int32_t)c, kc, best, bestG);
+      consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)c, kc, best, bestG);
     }
     finish<ALGO>(a, i, d, best, bestG, ct);
   }
@@ -390,6 +451,10 @@ __global__ void __launch_bounds__(BLOCK)
   __shared__ int64_t bg[4];
   const int t = threadIdx.x;
   const int32_t i = list[blockIdx.x];
+  if (frozen(a, i)) {  // block-uniform
+    if (t == 0) a.Cnew[i] = community_of_self<ALGO>(a, i);
+    return;
+  }
   const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
   Pair *tab;
   uint32_t cap;
@@ -431,11 +496,12 @@ __global__ void __launch_bounds__(BLOCK)
   const uint32_t kd = kd_s;
   int32_t best = -1;
   int64_t bestG = 0;
+  const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
   const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
   const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
   for (uint32_t x = t; x < cap; x += BLOCK) {
     Pair p = load_slot<GLOBAL>(&tab[x]);
-    if (p.key != EMPTY) consider<ALGO>(a, d, Ki, Sd, kd, (int32_t)p.key, p.val, best, bestG);
+    if (p.key != EMPTY) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)p.key, p.val, best, bestG);
   }
   // block arg-max: larger gain first, then lower community id
 #pragma unroll

@@ -16,6 +16,13 @@ struct SweepArgs {
   int32_t *Cnew;         // new membership (refinement: proposed target)
   int64_t *gain;         // optional: gain of each vertex's best move
   unsigned long long *ctr;  // [moved, proposals, sum of gains] (device)
+  // Batched runs (many graphs as one disjoint union): graph of every vertex, its
+  // graph's total weight, whether that graph still moves, per-graph counters
+  // [3 * graph + {moved, proposals, sum of gains}].  Null for a single graph.
+  const int32_t *gid = nullptr;
+  const uint32_t *Wg = nullptr;
+  const uint8_t *active = nullptr;
+  unsigned long long *gctr = nullptr;
 };
 
 // Per-level work lists, built once per level by build_schedule.

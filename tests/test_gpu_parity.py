@@ -232,3 +232,42 @@ def test_rmat20_louvain_config(mg):
     Cn, gain, ctr = mg.move_sweep(dg, mg.ALGO_LOUVAIN, _t(C), -1, mode=0)
     eC, eg = oracle.move_sweep(g, oracle.ALGO_MOVE, C, mode=0, direction=-1)
     assert np.array_equal(_np(Cn), eC) and np.array_equal(_np(gain), eg)
+
+
+# ---------------------------------------------------------------------------------
+# batched runs
+# ---------------------------------------------------------------------------------
+
+def _batch_graphs():
+    gs = []
+    rng = np.random.default_rng(77)
+    for q in range(14):
+        n = int(rng.integers(60, 1500))
+        gs.append(synth.planted_uneven(n, 20, 200, 6, 4, rng)[0])
+    gs.append(synth.rmat(scale=10, edge_factor=8, seed=78))
+    gs.append(synth.from_edges(5, []))            # isolated vertices only
+    gs.append(synth.from_edges(0, []))            # empty graph
+    gs.append(synth.chung_lu(n=1 << 11, avg_deg=20, seed=79))
+    gs.append(synth.from_edges(2, [(0, 1)]))      # K2
+    return gs
+
+
+@pytest.mark.parametrize("algo", ["lpa", "louvain"])
+@pytest.mark.parametrize("mode,k,L", [("alg1", 8, 128), ("alg1", 4, 16), ("exact", 8, 128)])
+def test_batched_equals_solo(mg, algo, mode, k, L):
+    gs = _batch_graphs()
+    dgs = [mg.to_device(g) for g in gs]
+    kw = dict(mode=MODES[mode], k=k, chunk_len=L)
+    code = mg.ALGO_LPA if algo == "lpa" else mg.ALGO_LOUVAIN
+    labs, gst, tot = mg.run_batched(code, dgs, **kw)
+    for g, dg, lab, st in zip(gs, dgs, labs, gst):
+        if g.n == 0:
+            assert lab.numel() == 0
+            continue
+        solo, sst = getattr(mg, algo)(dg, **kw)
+        assert np.array_equal(_np(lab), _np(solo))
+        assert st["iterations"] == sst["iterations"] and st["passes"] == sst["passes"]
+        assert st["communities"] == sst["communities"]
+        assert st["edges_scanned"] == sst["edges_scanned"]
+        elab, est = getattr(oracle, algo)(g, **kw)
+        assert np.array_equal(_np(lab), elab)

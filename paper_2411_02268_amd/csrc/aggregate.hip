@@ -415,7 +415,7 @@ __device__ inline void write_row(uint32_t (&k)[K], uint32_t (&v)[K], int32_t c, 
                                  uint32_t *rcount);
 
 template <int K, int MODE>
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
     k_agg_rows(AggStreams s, AggBuckets bk, int64_t L, Pair *rows, uint32_t *rcount) {
   const int lane = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(BLOCK)
 }
 
 template <int K>
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
     k_agg_multi(const int32_t *multi, const int64_t *cstart, Pair *skbuf, Pair *rows, uint32_t *rcount) {
   __shared__ Pair lds[BLOCK * K];
   const int32_t x = blockIdx.x;

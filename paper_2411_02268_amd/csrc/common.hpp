@@ -45,6 +45,10 @@ struct Error : std::runtime_error {
 
 #define MGCD_LAUNCHED() MGCD_HIP(hipGetLastError())
 
+// Kernels that hold a K-slot sketch per lane in registers: at K = 16 two waves per
+// SIMD leave room for the sketch and its merge partner without spilling.
+#define MGCD_SKETCH_OCCUPANCY(K) __attribute__((amdgpu_waves_per_eu(1, (K) >= 16 ? 2 : 8)))
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 inline int bits_for(uint64_t maxval) {  // bits needed to hold values <= maxval

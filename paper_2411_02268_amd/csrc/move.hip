@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(BLOCK)
 // One workgroup per long row: merge its chunk sketches, pass 2 over the row with
 // block-strided (coalesced) reads, decide.
 template <int K, int ALGO>
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
     k_move_multi(SweepArgs a, const int32_t *__restrict__ multi, const int64_t *__restrict__ cstart,
                  Pair *sk, const uint32_t *__restrict__ skflag) {
   __shared__ Pair lds[BLOCK * K];
@@ -286,22 +286,34 @@ __global__ void __launch_bounds__(BLOCK)
 
 // Rows are grouped in buckets by P = 2^b lanes per row (P >= the row's chunk count;
 // b = 0 for rows of one chunk), 64/P rows per wave, heaviest bucket first in the
-// grid.  Lane q of a row streams chunk q with the sketch in VGPRs; chunk sketches
-// are merged by the fixed tree with cross-lane shuffles (node j of level l lives in
-// lane j*2^l, its right partner 2^l lanes up); the row's P lanes then run pass 2
-// over the row (stride P, four loads in flight) and reduce with xor-shuffles inside
-// their aligned segment; lane 0 of the segment decides.
-struct Buckets {
-  int64_t wave_begin[7];  // waves of bucket b: [wave_begin[b], wave_end[b]); b = 6 comes first
-  int64_t wave_end[7];    // wave_end[0] is the total
-  const int32_t *rows[7];
-  int64_t nrows[7];
-};
+// grid.  Lane q of a row owns chunk q.
+//   pass 1: the wave stages its lanes' chunks through LDS in windows of 16
+//           positions: 16 lanes load 16 consecutive entries of one chunk (64-byte
+//           segments instead of 64 scattered lines per load), gather the keys
+//           C[j], write them to a key stream for pass 2 and to LDS; then every lane
+//           folds its own 16 staged entries into its VGPR sketch;
+//   merge:  chunk sketches merged by the fixed tree with cross-lane shuffles (node
+//           j of level l lives in lane j*2^l, its right partner 2^l lanes up);
+//   pass 2: the row's P lanes read keys (no second gather) and weights with
+//           stride P and reduce with xor-shuffles inside their aligned segment;
+//   lane 0 of the segment decides.
+constexpr int WIN = 16;        // staged positions per lane and window
+constexpr int WSTRIDE = WIN + 1;  // odd LDS row stride: conflict-free lane reads
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int K, int ALGO, int MODE>
-__global__ void __launch_bounds__(BLOCK)
-    k_move_rows(SweepArgs a, Buckets bk, int64_t L) {
+__global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
+    k_move_rows(SweepArgs a, const Buckets *__restrict__ bkp, int64_t L, uint32_t *keybuf) {
+  const Buckets &bk = *bkp;
+  __shared__ uint32_t skey[BLOCK / WAVE][WAVE * WSTRIDE];
+  __shared__ uint32_t swt[BLOCK / WAVE][WAVE * WSTRIDE];
   const int lane = lane_id();
+  const int wv = threadIdx.x / WAVE;
   const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
   // buckets are laid out in the grid from b = 6 down to b = 0 (wave-uniform)
   int b = 6;
@@ -318,12 +330,54 @@ __global__ void __launch_bounds__(BLOCK)
   const int64_t lo = valid ? a.g.off[i] : 0, hi = valid ? a.g.off[i + 1] : 0;
   const int64_t nc = (hi - lo + L - 1) / L;
   const int32_t bi = (ALGO == ALGO_REFINE && valid) ? a.bound[i] : 0;
+  // this lane's chunk [clo, chi)
+  const int64_t clo = lo + q * L;
+  const int64_t chi = q < nc ? (clo + L < hi ? clo + L : hi) : clo;
+  int64_t maxlen = chi - clo;
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    int64_t x = __shfl_xor(maxlen, o);
+    maxlen = x > maxlen ? x : maxlen;
+  }
   RegSketch<K, MODE> s;
   s.reset();
-  if (q < nc) {
-    const int64_t clo = lo + q * L;
-    const int64_t chi = clo + L < hi ? clo + L : hi;
-    for_each_entry<ALGO>(a, i, bi, clo, chi, [&](uint32_t c, uint32_t w) { s.update(c, w); });
+  uint32_t *const kl = skey[wv];
+  uint32_t *const wl = swt[wv];
+  for (int64_t s0 = 0; s0 < maxlen; s0 += WIN) {
+    // stage: round rr covers the chunks of lanes 4rr .. 4rr+3, 16 positions each
+#pragma unroll
+    for (int half = 0; half < 4; ++half) {
+      int32_t jj[4];
+      uint32_t ww[4];
+      int64_t ee[4];
+      int32_t ii[4], bb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int src = (half * 4 + u) * 4 + (lane >> 4);
+        const int64_t e = __shfl(clo, src) + s0 + (lane & 15);
+        const int64_t end = __shfl(chi, src);
+        ii[u] = __shfl(i, src);
+        bb[u] = __shfl(bi, src);
+        ee[u] = e < end ? e : -1;
+        jj[u] = ee[u] >= 0 ? __builtin_nontemporal_load(a.g.idx + e) : -1;
+        ww[u] = ee[u] >= 0 ? __builtin_nontemporal_load(a.g.w + e) : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int src = (half * 4 + u) * 4 + (lane >> 4);
+        const uint32_t key = ee[u] >= 0 ? stream_key<ALGO>(a, ii[u], jj[u], bb[u]) : EMPTY;
+        if (ee[u] >= 0) keybuf[ee[u]] = key;
+        kl[src * WSTRIDE + (lane & 15)] = key;
+        wl[src * WSTRIDE + (lane & 15)] = ww[u];
+      }
+    }
+    wave_sync();
+#pragma unroll 4
+    for (int t = 0; t < WIN; ++t) {
+      const uint32_t key = kl[lane * WSTRIDE + t];
+      if (key != EMPTY) s.update(key, wl[lane * WSTRIDE + t]);
+    }
+    wave_sync();
   }
   s.finalize();
   bool lossy = s.lossy;
@@ -357,11 +411,27 @@ __global__ void __launch_bounds__(BLOCK)
   } else {
 #pragma unroll
     for (int p = 0; p < K; ++p) ex[p] = 0;
-    for_each_entry<ALGO>(a, i, bi, lo + q, hi, [&](uint32_t c, uint32_t w) {
+    // pass 2 over the stashed keys: no second gather
+    int64_t e = lo + q;
+    for (; e + 3 * P < hi; e += 4 * P) {
+      uint32_t c[4], w[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c[u] = __builtin_nontemporal_load(keybuf + e + u * P);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w[u] = __builtin_nontemporal_load(a.g.w + e + u * P);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int p = 0; p < K; ++p) ex[p] += key[p] == c[u] ? w[u] : 0u;
+        kd += c[u] == (uint32_t)d ? w[u] : 0u;
+      }
+    }
+    for (; e < hi; e += P) {
+      const uint32_t c = keybuf[e], w = a.g.w[e];
 #pragma unroll
       for (int p = 0; p < K; ++p) ex[p] += key[p] == c ? w : 0u;
       kd += c == (uint32_t)d ? w : 0u;
-    }, P);
+    }
     for (int o = P / 2; o > 0; o >>= 1) {
 #pragma unroll
       for (int p = 0; p < K; ++p) ex[p] += __shfl_xor(ex[p], o);
@@ -373,7 +443,7 @@ __global__ void __launch_bounds__(BLOCK)
     int32_t best = -1;
     int64_t bestG = 0;
     const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
-  const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+    const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
     const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
 #pragma unroll
     for (int p = 0; p < K; ++p)
@@ -619,6 +689,7 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
     b += (size_t)(4 * nnz + 64) * sizeof(Pair) + 1024;  // tables: cap <= 4*deg
   } else {
     int64_t chunks = nnz / (L > 0 ? L : 1) + n + 1;
+    b += (size_t)nnz * 4 + 1024;                            // key stream
     b += (size_t)(n + 1) * 8 * 2 + scan_ws_bytes(n) + 2048;  // counts, cstart
     b += (size_t)chunks * (4 + 4 + (size_t)k * sizeof(Pair)) + 4096;
   }
@@ -666,6 +737,7 @@ void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Are
     }
     return;
   }
+  s.keybuf = a.take<uint32_t>(g.nnz);
   int64_t pos = 0;
   s.single = order;
   s.nsingle = (int64_t)h[0];
@@ -677,6 +749,22 @@ void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Are
   }
   s.multi = order + pos;
   s.nmulti = (int64_t)h[7];
+  {  // bucket table of k_move_rows, heaviest bucket first in the grid
+    Buckets bk{};
+    int64_t w = 0;
+    for (int b = 6; b >= 0; --b) {
+      const int64_t rows = b == 0 ? s.nsingle : s.npacked[b];
+      bk.rows[b] = b == 0 ? s.single : s.packed[b];
+      bk.nrows[b] = rows;
+      bk.wave_begin[b] = w;
+      w += ceil_div(rows << b, WAVE);
+      bk.wave_end[b] = w;
+    }
+    s.row_waves = w;
+    s.buckets = a.take<Buckets>(1);
+    MGCD_HIP(hipMemcpyAsync(s.buckets, &bk, sizeof(bk), hipMemcpyHostToDevice, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+  }
   if (s.nmulti > 0) {
     int64_t *nch = a.take<int64_t>(s.nmulti);
     s.cstart = a.take<int64_t>(s.nmulti + 1);
@@ -711,18 +799,9 @@ static void sweep_mg(const SweepArgs &a, const Schedule &s, int64_t L, hipStream
     MGCD_LAUNCHED();
   }
   mark(ev, 1, st);
-  Buckets bk{};
-  int64_t w = 0;
-  for (int b = 6; b >= 0; --b) {
-    const int64_t rows = b == 0 ? s.nsingle : s.npacked[b];
-    bk.rows[b] = b == 0 ? s.single : s.packed[b];
-    bk.nrows[b] = rows;
-    bk.wave_begin[b] = w;
-    w += ceil_div(rows << b, WAVE);
-    bk.wave_end[b] = w;
-  }
-  if (w > 0) {
-    k_move_rows<K, ALGO, MODE><<<(unsigned)ceil_div(w, BLOCK / WAVE), BLOCK, 0, st>>>(a, bk, L);
+  if (s.row_waves > 0) {
+    k_move_rows<K, ALGO, MODE><<<(unsigned)ceil_div(s.row_waves, BLOCK / WAVE), BLOCK, 0, st>>>(
+        a, s.buckets, L, s.keybuf);
     MGCD_LAUNCHED();
   }
   mark(ev, 2, st);

@@ -25,6 +25,14 @@ struct SweepArgs {
   unsigned long long *gctr = nullptr;
 };
 
+// Row buckets of the main sweep kernel: rows needing 2^b lanes (b = 0..6).
+struct Buckets {
+  int64_t wave_begin[7];  // waves of bucket b: [wave_begin[b], wave_end[b]); b = 6 comes first
+  int64_t wave_end[7];    // wave_end[0] is the total
+  const int32_t *rows[7];
+  int64_t nrows[7];
+};
+
 // Per-level work lists, built once per level by build_schedule.
 struct Schedule {
   // MG mode
@@ -37,6 +45,9 @@ struct Schedule {
   int64_t *cstart = nullptr;  // [nmulti+1] first chunk of each multi vertex
   int32_t *owner = nullptr;   // [nchunks] multi index of each chunk
   int64_t nchunks = 0;
+  Buckets *buckets = nullptr; // device copy of the bucket table
+  int64_t row_waves = 0;
+  uint32_t *keybuf = nullptr; // [nnz] keys C[j] gathered in pass 1, read by pass 2
   Pair *sk = nullptr;         // [nchunks * k] chunk sketches
   uint32_t *skflag = nullptr; // [nchunks] chunk lost weight
   // exact mode

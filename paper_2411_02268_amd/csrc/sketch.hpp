@@ -128,9 +128,12 @@ struct RegSketch {
 // values of equal keys; if more than K keys are positive, subtract the (K+1)-th
 // largest value from all and keep the positive ones.  Slots with value 0 are empty.
 // Returns true when the threshold step removed weight.  Output in a (K slots).
+// Always inlined: as a call its slot arrays would live in scratch memory.
 template <int K>
-__device__ inline bool merge_sketch(uint32_t (&ak)[K], uint32_t (&av)[K], const uint32_t (&bk)[K],
-                                    uint32_t (&bv)[K]) {
+__device__ __attribute__((always_inline)) inline bool merge_sketch(uint32_t (&ak)[K],
+                                                                  uint32_t (&av)[K],
+                                                                  const uint32_t (&bk)[K],
+                                                                  uint32_t (&bv)[K]) {
 #pragma unroll
   for (int y = 0; y < K; ++y) {
 #pragma unroll

@@ -405,37 +405,61 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
   const uint64_t seg = P == 64 ? lm : (lm >> base_lane) & ((1ull << P) - 1);
   const int32_t d = valid ? community_of_self<ALGO>(a, i) : 0;
   uint32_t kd = 0;
-  if (seg == 0) {
+  const bool need2 = seg != 0;  // same for all lanes of a row
+  if (!need2) {
 #pragma unroll
     for (int p = 0; p < K; ++p) kd += key[p] == (uint32_t)d ? ex[p] : 0u;
   } else {
 #pragma unroll
     for (int p = 0; p < K; ++p) ex[p] = 0;
-    // pass 2 over the stashed keys: no second gather
-    int64_t e = lo + q;
-    for (; e + 3 * P < hi; e += 4 * P) {
-      uint32_t c[4], w[4];
+  }
+  // pass 2 over the stashed keys (no second gather), staged like pass 1; rows whose
+  // sketch was exact take no part
+  const int64_t chi2 = need2 ? chi : clo;
+  int64_t maxlen2 = chi2 - clo;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) c[u] = __builtin_nontemporal_load(keybuf + e + u * P);
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    int64_t x = __shfl_xor(maxlen2, o);
+    maxlen2 = x > maxlen2 ? x : maxlen2;
+  }
+  for (int64_t s0 = 0; s0 < maxlen2; s0 += WIN) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) w[u] = __builtin_nontemporal_load(a.g.w + e + u * P);
+    for (int half = 0; half < 4; ++half) {
+      uint32_t cc[4], ww[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
+        const int src = (half * 4 + u) * 4 + (lane >> 4);
+        const int64_t e = __shfl(clo, src) + s0 + (lane & 15);
+        const bool ok = e < __shfl(chi2, src);
+        cc[u] = ok ? __builtin_nontemporal_load(keybuf + e) : EMPTY;
+        ww[u] = ok ? __builtin_nontemporal_load(a.g.w + e) : 0u;
+      }
 #pragma unroll
-        for (int p = 0; p < K; ++p) ex[p] += key[p] == c[u] ? w[u] : 0u;
-        kd += c[u] == (uint32_t)d ? w[u] : 0u;
+      for (int u = 0; u < 4; ++u) {
+        const int src = (half * 4 + u) * 4 + (lane >> 4);
+        kl[src * WSTRIDE + (lane & 15)] = cc[u];
+        wl[src * WSTRIDE + (lane & 15)] = ww[u];
       }
     }
-    for (; e < hi; e += P) {
-      const uint32_t c = keybuf[e], w = a.g.w[e];
+    wave_sync();
+#pragma unroll 4
+    for (int t = 0; t < WIN; ++t) {
+      const uint32_t c = kl[lane * WSTRIDE + t], w = wl[lane * WSTRIDE + t];
 #pragma unroll
       for (int p = 0; p < K; ++p) ex[p] += key[p] == c ? w : 0u;
       kd += c == (uint32_t)d ? w : 0u;
     }
+    wave_sync();
+  }
+  if (maxlen2 > 0) {
     for (int o = P / 2; o > 0; o >>= 1) {
 #pragma unroll
-      for (int p = 0; p < K; ++p) ex[p] += __shfl_xor(ex[p], o);
-      kd += __shfl_xor(kd, o);
+      for (int p = 0; p < K; ++p) {
+        const uint32_t x = __shfl_xor(ex[p], o);
+        ex[p] += need2 ? x : 0u;
+      }
+      const uint32_t x = __shfl_xor(kd, o);
+      kd += need2 ? x : 0u;
     }
   }
   Counters ct;

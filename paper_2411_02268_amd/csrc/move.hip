@@ -126,101 +126,228 @@ __device__ inline uint32_t stream_key(const SweepArgs &a, int32_t i, int32_t j, 
   return (uint32_t)a.C[j];
 }
 
-// Stream entries lo, lo+stride, ... < hi of row i into f(key, weight), skipped
-// entries dropped.  Four entries per step: their index and weight loads, then their
-// four label gathers, are all in flight before the first update.  With stride 1 the
-// loads are 16-byte vector loads once the position is 4-aligned.
-// Row data is streamed with non-temporal loads so that it does not evict the
-// gathered community labels C[j] from L2.
-typedef int v4i32 __attribute__((ext_vector_type(4)));
-__device__ inline int32_t ld_idx(const int32_t *p) { return __builtin_nontemporal_load(p); }
-__device__ inline uint32_t ld_w(const uint32_t *p) { return __builtin_nontemporal_load(p); }
-__device__ inline v4i32 ld4(const void *p) {
-  return __builtin_nontemporal_load(reinterpret_cast<const v4i32 *>(p));
-}
-
-template <int ALGO, typename F>
-__device__ inline void for_each_entry(const SweepArgs &a, int32_t i, int32_t bi, int64_t lo,
-                                      int64_t hi, F &&f, int64_t stride = 1) {
-  int64_t e = lo;
-  if (stride == 1) {
-    for (; e < hi && (e & 3); ++e) {
-      uint32_t c = stream_key<ALGO>(a, i, ld_idx(a.g.idx + e), bi);
-      if (c != EMPTY) f(c, ld_w(a.g.w + e));
-    }
-    for (; e + 4 <= hi; e += 4) {
-      const v4i32 j = ld4(a.g.idx + e);
-      const v4i32 w = ld4(a.g.w + e);
-      const uint32_t c0 = stream_key<ALGO>(a, i, j.x, bi), c1 = stream_key<ALGO>(a, i, j.y, bi);
-      const uint32_t c2 = stream_key<ALGO>(a, i, j.z, bi), c3 = stream_key<ALGO>(a, i, j.w, bi);
-      if (c0 != EMPTY) f(c0, (uint32_t)w.x);
-      if (c1 != EMPTY) f(c1, (uint32_t)w.y);
-      if (c2 != EMPTY) f(c2, (uint32_t)w.z);
-      if (c3 != EMPTY) f(c3, (uint32_t)w.w);
-    }
-  } else {
-    for (; e + 3 * stride < hi; e += 4 * stride) {
-      int32_t j[4];
-      uint32_t w[4], c[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) j[u] = ld_idx(a.g.idx + e + u * stride);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) w[u] = ld_w(a.g.w + e + u * stride);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) c[u] = stream_key<ALGO>(a, i, j[u], bi);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (c[u] != EMPTY) f(c[u], w[u]);
-    }
-  }
-  for (; e < hi; e += stride) {
-    uint32_t c = stream_key<ALGO>(a, i, ld_idx(a.g.idx + e), bi);
-    if (c != EMPTY) f(c, ld_w(a.g.w + e));
-  }
-}
-
 // ---- MG: long rows -----------------------------------------------------------------
 
-// One lane per chunk of L positions of a long row: Algorithm 1 from an empty sketch.
+constexpr int WIN = 16;        // staged positions per lane and window
+constexpr int WROW = 2 * WIN + 4;  // words per lane row: WIN (key, weight) pairs + pad; rows
+                                   // are 16-byte aligned and 8 consecutive lanes' rows start
+                                   // in distinct 4-bank groups (conflict-free 128-bit reads)
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Stage positions s0 .. s0+WIN-1 of every lane's chunk [clo, chi) of row i into the
+// wave's LDS window win (WAVE * WROW words, (key, weight) pairs).  Round r serves
+// the chunks of lanes 4r .. 4r+3, 16 lanes per chunk loading 16 consecutive entries
+// (64-byte segments instead of 64 scattered lines per load); the loads of 8 rounds
+// are in flight together.  GATHER: the keys are C[j] (with Algorithm 1's skips)
+// and are also written to the key stream; otherwise they are read from the key
+// stream.  Positions past a chunk's end stage (EMPTY, 0).
+template <int ALGO, bool GATHER>
+__device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i, int32_t bi,
+                                    int64_t clo, int64_t chi, int64_t s0, uint32_t *keybuf) {
+  constexpr int G = GATHER ? 8 : WIN;  // rounds per group of loads in flight
+  const int lane = lane_id();
+#pragma unroll
+  for (int g0 = 0; g0 < WIN; g0 += G) {
+    uint32_t kk[G], ww[G];
+    uint32_t ok = 0;
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const int src = (g0 + r) * 4 + (lane >> 4);
+      const int64_t e = __shfl(clo, src) + s0 + (lane & 15);
+      const bool v = e < __shfl(chi, src);
+      ok |= v ? 1u << r : 0u;
+      const int64_t es = v ? e : 0;
+      kk[r] = GATHER ? (uint32_t)__builtin_nontemporal_load(a.g.idx + es)
+                     : __builtin_nontemporal_load(keybuf + es);
+      ww[r] = __builtin_nontemporal_load(a.g.w + es);
+    }
+    if (GATHER) {
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const int src = (g0 + r) * 4 + (lane >> 4);
+        const int32_t ii = __shfl(i, src);
+        const int32_t bb = __shfl(bi, src);
+        const bool v = (ok >> r) & 1u;
+        const int32_t j = v ? (int32_t)kk[r] : 0;
+        uint32_t c;
+        if (ALGO == ALGO_REFINE)
+          c = a.bound[j] == bb ? (uint32_t)j : EMPTY;
+        else
+          c = (uint32_t)a.C[j];
+        kk[r] = (v && j != ii) ? c : EMPTY;  // self-loops are skipped
+      }
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const int src = (g0 + r) * 4 + (lane >> 4);
+        const int64_t e = __shfl(clo, src) + s0 + (lane & 15);
+        if ((ok >> r) & 1u) keybuf[e] = kk[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const int src = (g0 + r) * 4 + (lane >> 4);
+      const bool v = (ok >> r) & 1u;
+      typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+      v2u pr;
+      pr.x = v ? kk[r] : EMPTY;
+      pr.y = v ? ww[r] : 0u;
+      *reinterpret_cast<v2u *>(win + src * WROW + 2 * (lane & 15)) = pr;
+    }
+  }
+}
+
+// This lane's WIN staged keys and weights, read with 128-bit LDS loads.
+__device__ inline void read_window(const uint32_t *win, uint32_t (&kk)[WIN], uint32_t (&ww)[WIN]) {
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+  const v4u *p = reinterpret_cast<const v4u *>(win + lane_id() * WROW);
+#pragma unroll
+  for (int q = 0; q < WIN / 2; ++q) {
+    const v4u x = p[q];
+    kk[2 * q] = x.x;
+    ww[2 * q] = x.y;
+    kk[2 * q + 1] = x.z;
+    ww[2 * q + 1] = x.w;
+  }
+}
+
+// Pass 1 of Algorithm 1 over this lane's chunk [clo, chi) of row i: windows staged
+// by stage_window, then every lane folds its own 16 staged entries into its VGPR
+// sketch.  Every lane of the wave must call this; an idle lane passes an empty
+// chunk.
+template <int K, int ALGO, int MODE, bool GATHER = true>
+__device__ inline void staged_sketch(const SweepArgs &a, RegSketch<K, MODE> &s, uint32_t *win,
+                                     int32_t i, int32_t bi, int64_t clo, int64_t chi,
+                                     uint32_t *keybuf) {
+  int64_t maxlen = chi - clo;
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    int64_t x = __shfl_xor(maxlen, o);
+    maxlen = x > maxlen ? x : maxlen;
+  }
+  for (int64_t s0 = 0; s0 < maxlen; s0 += WIN) {
+    stage_window<ALGO, GATHER>(a, win, i, bi, clo, chi, s0, keybuf);
+    wave_sync();
+    uint32_t kk[WIN], ww[WIN];
+    read_window(win, kk, ww);
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < WIN; ++t)
+      if (kk[t] != EMPTY) s.update(kk[t], ww[t]);
+  }
+}
+
+// Rows of more than 64 chunks ("long rows") go through five launches, each with
+// enough independent work to fill the chip:
+//   k_long_keys    one wave per chunk: gather the keys C[j] into the key stream;
+//   k_long_chunks  one lane per chunk: Algorithm 1 from an empty sketch over the
+//                  staged keys (no gather in the dependent chain);
+//   k_long_merge   one workgroup per row: the fixed merge tree over its chunk
+//                  sketches; a row whose sketch lost no weight is decided here;
+//   k_long_count   one wave per chunk of a lossy row: pass 2 against the row's
+//                  candidates, partial counts per chunk;
+//   k_long_decide  one workgroup per lossy row: sum the partial counts, decide.
+
+// Chunk q of a long row: its row, its bounds and whether it is active.
+struct LongChunk {
+  int32_t m, i;
+  int64_t lo, hi;
+  bool active;
+};
+
+__device__ inline LongChunk long_chunk(const SweepArgs &a, const int32_t *multi,
+                                       const int32_t *owner, const int64_t *cstart, int64_t q,
+                                       int64_t nchunks, int64_t L) {
+  LongChunk c{0, 0, 0, 0, false};
+  if (q >= nchunks) return c;
+  c.m = owner[q];
+  c.i = multi[c.m];
+  if (frozen(a, c.i)) return c;
+  const int64_t rhi = a.g.off[c.i + 1];
+  c.lo = a.g.off[c.i] + (q - cstart[c.m]) * L;
+  c.hi = c.lo + L < rhi ? c.lo + L : rhi;
+  c.active = true;
+  return c;
+}
+
+template <int ALGO>
+__global__ void __launch_bounds__(BLOCK)
+    k_long_keys(SweepArgs a, const int32_t *__restrict__ multi, const int32_t *__restrict__ owner,
+                const int64_t *__restrict__ cstart, int64_t nchunks, int64_t L, uint32_t *keybuf) {
+  const int64_t q = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
+  const LongChunk c = long_chunk(a, multi, owner, cstart, q, nchunks, L);
+  if (!c.active) return;
+  const int32_t bi = ALGO == ALGO_REFINE ? a.bound[c.i] : 0;
+  int64_t e = c.lo + lane_id();
+  for (; e + 3 * WAVE < c.hi; e += 4 * WAVE) {
+    int32_t j[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) j[u] = __builtin_nontemporal_load(a.g.idx + e + u * WAVE);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) keybuf[e + u * WAVE] = stream_key<ALGO>(a, c.i, j[u], bi);
+  }
+  for (; e < c.hi; e += WAVE) keybuf[e] = stream_key<ALGO>(a, c.i, a.g.idx[e], bi);
+}
+
 template <int K, int ALGO, int MODE>
 __global__ void __launch_bounds__(BLOCK)
-    k_move_chunks(SweepArgs a, const int32_t *__restrict__ multi, const int32_t *__restrict__ owner,
+    k_long_chunks(SweepArgs a, const int32_t *__restrict__ multi, const int32_t *__restrict__ owner,
                   const int64_t *__restrict__ cstart, int64_t nchunks, int64_t L, Pair *sk,
-                  uint32_t *skflag) {
-  int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (q >= nchunks) return;
-  const int32_t m = owner[q];
-  const int32_t i = multi[m];
-  const int64_t c = q - cstart[m];
-  const int64_t rlo = a.g.off[i], rhi = a.g.off[i + 1];
-  const int64_t lo = rlo + c * L;
-  const int64_t hi = lo + L < rhi ? lo + L : rhi;
-  const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
+                  uint32_t *skflag, uint32_t *keybuf) {
+  __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
+  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const LongChunk c = long_chunk(a, multi, owner, cstart, q, nchunks, L);
+  const int wv = threadIdx.x / WAVE;
   RegSketch<K, MODE> s;
   s.reset();
-  if (!frozen(a, i))
-    for_each_entry<ALGO>(a, i, bi, lo, hi, [&](uint32_t c, uint32_t w) { s.update(c, w); });
+  staged_sketch<K, ALGO, MODE, false>(a, s, swin[wv], c.i, 0, c.lo,
+                                      c.active ? c.hi : c.lo, keybuf);
   s.finalize();
+  if (q >= nchunks) return;
 #pragma unroll
   for (int p = 0; p < K; ++p) sk[q * K + p] = Pair{s.key[p], s.val[p]};
   skflag[q] = s.lossy ? 1u : 0u;
 }
 
-// One workgroup per long row: merge its chunk sketches, pass 2 over the row with
-// block-strided (coalesced) reads, decide.
+// Choose the best candidate of row i and record the move (one thread).
+template <int K, int ALGO>
+__device__ inline void decide_long(const SweepArgs &a, int32_t i, int32_t d, const uint32_t (&key)[K],
+                                   const uint32_t (&ex)[K], uint32_t kd) {
+  Counters ct;
+  int32_t best = -1;
+  int64_t bestG = 0;
+  const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
+  const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+  const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+#pragma unroll
+  for (int p = 0; p < K; ++p)
+    if (key[p] != EMPTY) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)key[p], ex[p], best, bestG);
+  finish<ALGO>(a, i, d, best, bestG, ct);
+  if (ct.moved) atomicAdd(&a.ctr[0], (unsigned long long)ct.moved);
+  if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
+  if (ct.sumG) atomicAdd(&a.ctr[2], (unsigned long long)ct.sumG);
+}
+
+// cflag[m]: 0 decided here (exact sketch), 1 lossy (candidates in cand), 2 frozen.
 template <int K, int ALGO>
 __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
-    k_move_multi(SweepArgs a, const int32_t *__restrict__ multi, const int64_t *__restrict__ cstart,
-                 Pair *sk, const uint32_t *__restrict__ skflag) {
+    k_long_merge(SweepArgs a, const int32_t *__restrict__ multi, const int64_t *__restrict__ cstart,
+                 Pair *sk, const uint32_t *__restrict__ skflag, Pair *cand, uint32_t *cflag) {
   __shared__ Pair lds[BLOCK * K];
-  __shared__ uint32_t red[K + 1][4];
   __shared__ int flag_any;
   const int t = threadIdx.x;
   const int32_t m = blockIdx.x;
   const int32_t i = multi[m];
   const int64_t cb = cstart[m], nc = cstart[m + 1] - cb;
   if (frozen(a, i)) {  // block-uniform
-    if (t == 0) a.Cnew[i] = community_of_self<ALGO>(a, i);
+    if (t == 0) {
+      a.Cnew[i] = community_of_self<ALGO>(a, i);
+      cflag[m] = 2;
+    }
     return;
   }
   if (t == 0) flag_any = 0;
@@ -229,57 +356,114 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
   for (int64_t q = t; q < nc; q += BLOCK) f |= skflag[cb + q] != 0;
   if (f) flag_any = 1;
   bool lossy = tree_reduce<K>(sk, cb, nc, lds);
-  lossy |= flag_any != 0;  // flag_any settled by the barriers inside tree_reduce
+  lossy |= flag_any != 0;  // settled by the barriers inside tree_reduce
+  if (lossy) {
+    if (t < K) cand[(int64_t)m * K + t] = lds[t];
+    if (t == 0) cflag[m] = 1;
+    return;
+  }
+  if (t == 0) {
+    cflag[m] = 0;
+    uint32_t key[K], ex[K];
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      const Pair x = lds[p];
+      key[p] = x.val > 0 ? x.key : EMPTY;
+      ex[p] = x.val;
+    }
+    const int32_t d = community_of_self<ALGO>(a, i);
+    uint32_t kd = 0;
+#pragma unroll
+    for (int p = 0; p < K; ++p) kd += key[p] == (uint32_t)d ? ex[p] : 0u;
+    decide_long<K, ALGO>(a, i, d, key, ex, kd);
+  }
+}
+
+// part[q * (K + 1) + p] = weight of chunk q's entries with key cand[p];
+// part[q * (K + 1) + K] = weight of those in the row's own community.
+template <int K, int ALGO>
+__global__ void __launch_bounds__(BLOCK)
+    k_long_count(SweepArgs a, const int32_t *__restrict__ multi, const int32_t *__restrict__ owner,
+                 const int64_t *__restrict__ cstart, int64_t nchunks, int64_t L,
+                 const Pair *__restrict__ cand, const uint32_t *__restrict__ cflag,
+                 const uint32_t *__restrict__ keybuf, uint32_t *part) {
+  const int64_t q = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
+  if (q >= nchunks) return;
+  const int32_t m = owner[q];
+  if (cflag[m] != 1) return;
+  const LongChunk c = long_chunk(a, multi, owner, cstart, q, nchunks, L);
+  const int32_t d = community_of_self<ALGO>(a, c.i);
+  uint32_t key[K], ex[K], kd = 0;
+#pragma unroll
+  for (int p = 0; p < K; ++p) {
+    const Pair x = cand[(int64_t)m * K + p];
+    key[p] = x.val > 0 ? x.key : EMPTY;
+    ex[p] = 0;
+  }
+  int64_t e = c.lo + lane_id();
+  for (; e + 3 * WAVE < c.hi; e += 4 * WAVE) {
+    uint32_t cc[4], w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cc[u] = __builtin_nontemporal_load(keybuf + e + u * WAVE);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = __builtin_nontemporal_load(a.g.w + e + u * WAVE);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int p = 0; p < K; ++p) ex[p] += key[p] == cc[u] ? w[u] : 0u;
+      kd += cc[u] == (uint32_t)d ? w[u] : 0u;
+    }
+  }
+  for (; e < c.hi; e += WAVE) {
+    const uint32_t cc = keybuf[e], w = a.g.w[e];
+#pragma unroll
+    for (int p = 0; p < K; ++p) ex[p] += key[p] == cc ? w : 0u;
+    kd += cc == (uint32_t)d ? w : 0u;
+  }
+#pragma unroll
+  for (int p = 0; p < K; ++p) ex[p] = wave_sum(ex[p]);
+  kd = wave_sum(kd);
+  const int l = lane_id();
+  uint32_t mine = kd;
+#pragma unroll
+  for (int p = 0; p < K; ++p) mine = l == p ? ex[p] : mine;
+  if (l <= K) part[q * (K + 1) + l] = mine;
+}
+
+template <int K, int ALGO>
+__global__ void __launch_bounds__(BLOCK)
+    k_long_decide(SweepArgs a, const int32_t *__restrict__ multi, const int64_t *__restrict__ cstart,
+                  const Pair *__restrict__ cand, const uint32_t *__restrict__ cflag,
+                  const uint32_t *__restrict__ part) {
+  __shared__ uint32_t red[K + 1][BLOCK / WAVE];
+  const int32_t m = blockIdx.x;
+  if (cflag[m] != 1) return;  // block-uniform
+  const int t = threadIdx.x;
+  const int64_t cb = cstart[m], ce = cstart[m + 1];
+  uint32_t sum[K + 1];
+#pragma unroll
+  for (int p = 0; p <= K; ++p) sum[p] = 0;
+  for (int64_t q = cb + t; q < ce; q += BLOCK) {
+#pragma unroll
+    for (int p = 0; p <= K; ++p) sum[p] += part[q * (K + 1) + p];
+  }
+#pragma unroll
+  for (int p = 0; p <= K; ++p) {
+    const uint32_t v = wave_sum(sum[p]);
+    if (lane_id() == 0) red[p][t / WAVE] = v;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  const int32_t i = multi[m];
   uint32_t key[K], ex[K];
 #pragma unroll
   for (int p = 0; p < K; ++p) {
-    Pair x = lds[p];
+    const Pair x = cand[(int64_t)m * K + p];
     key[p] = x.val > 0 ? x.key : EMPTY;
-    ex[p] = x.val;
+    ex[p] = red[p][0] + red[p][1] + red[p][2] + red[p][3];
   }
-  const int32_t d = community_of_self<ALGO>(a, i);
-  uint32_t kd = 0;
-  if (!lossy) {
-#pragma unroll
-    for (int p = 0; p < K; ++p) kd += key[p] == (uint32_t)d ? ex[p] : 0u;
-  } else {
-    const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
-    const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
-#pragma unroll
-    for (int p = 0; p < K; ++p) ex[p] = 0;
-    for_each_entry<ALGO>(a, i, bi, lo + t, hi, [&](uint32_t c, uint32_t w) {
-#pragma unroll
-      for (int p = 0; p < K; ++p) ex[p] += key[p] == c ? w : 0u;
-      kd += c == (uint32_t)d ? w : 0u;
-    }, BLOCK);
-    const int wv = t / WAVE;
-#pragma unroll
-    for (int p = 0; p < K; ++p) {
-      uint32_t s = wave_sum(ex[p]);
-      if (lane_id() == 0) red[p][wv] = s;
-    }
-    uint32_t s = wave_sum(kd);
-    if (lane_id() == 0) red[K][wv] = s;
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < K; ++p) ex[p] = red[p][0] + red[p][1] + red[p][2] + red[p][3];
-    kd = red[K][0] + red[K][1] + red[K][2] + red[K][3];
-  }
-  if (t == 0) {
-    Counters ct;
-    int32_t best = -1;
-    int64_t bestG = 0;
-    const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
-  const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
-    const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
-#pragma unroll
-    for (int p = 0; p < K; ++p)
-      if (key[p] != EMPTY) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)key[p], ex[p], best, bestG);
-    finish<ALGO>(a, i, d, best, bestG, ct);
-    if (ct.moved) atomicAdd(&a.ctr[0], (unsigned long long)ct.moved);
-    if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
-    if (ct.sumG) atomicAdd(&a.ctr[2], (unsigned long long)ct.sumG);
-  }
+  const uint32_t kd = red[K][0] + red[K][1] + red[K][2] + red[K][3];
+  decide_long<K, ALGO>(a, i, community_of_self<ALGO>(a, i), key, ex, kd);
 }
 
 // ---- MG: every row of at most 64 chunks, one launch ---------------------------------
@@ -287,31 +471,18 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
 // Rows are grouped in buckets by P = 2^b lanes per row (P >= the row's chunk count;
 // b = 0 for rows of one chunk), 64/P rows per wave, heaviest bucket first in the
 // grid.  Lane q of a row owns chunk q.
-//   pass 1: the wave stages its lanes' chunks through LDS in windows of 16
-//           positions: 16 lanes load 16 consecutive entries of one chunk (64-byte
-//           segments instead of 64 scattered lines per load), gather the keys
-//           C[j], write them to a key stream for pass 2 and to LDS; then every lane
-//           folds its own 16 staged entries into its VGPR sketch;
+//   pass 1: staged_sketch over the lane's chunk (keys also go to the key stream);
 //   merge:  chunk sketches merged by the fixed tree with cross-lane shuffles (node
 //           j of level l lives in lane j*2^l, its right partner 2^l lanes up);
-//   pass 2: the row's P lanes read keys (no second gather) and weights with
-//           stride P and reduce with xor-shuffles inside their aligned segment;
+//   pass 2: only rows whose sketch lost weight: the same LDS windows over the key
+//           stream (no second gather) and the weights, each lane counting its own
+//           chunk, then xor-shuffles inside the row's aligned segment;
 //   lane 0 of the segment decides.
-constexpr int WIN = 16;        // staged positions per lane and window
-constexpr int WSTRIDE = WIN + 1;  // odd LDS row stride: conflict-free lane reads
-
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <int K, int ALGO, int MODE>
 __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
     k_move_rows(SweepArgs a, const Buckets *__restrict__ bkp, int64_t L, uint32_t *keybuf) {
   const Buckets &bk = *bkp;
-  __shared__ uint32_t skey[BLOCK / WAVE][WAVE * WSTRIDE];
-  __shared__ uint32_t swt[BLOCK / WAVE][WAVE * WSTRIDE];
+  __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
   const int lane = lane_id();
   const int wv = threadIdx.x / WAVE;
   const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
@@ -333,52 +504,10 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
   // this lane's chunk [clo, chi)
   const int64_t clo = lo + q * L;
   const int64_t chi = q < nc ? (clo + L < hi ? clo + L : hi) : clo;
-  int64_t maxlen = chi - clo;
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    int64_t x = __shfl_xor(maxlen, o);
-    maxlen = x > maxlen ? x : maxlen;
-  }
   RegSketch<K, MODE> s;
   s.reset();
-  uint32_t *const kl = skey[wv];
-  uint32_t *const wl = swt[wv];
-  for (int64_t s0 = 0; s0 < maxlen; s0 += WIN) {
-    // stage: round rr covers the chunks of lanes 4rr .. 4rr+3, 16 positions each
-#pragma unroll
-    for (int half = 0; half < 4; ++half) {
-      int32_t jj[4];
-      uint32_t ww[4];
-      int64_t ee[4];
-      int32_t ii[4], bb[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int src = (half * 4 + u) * 4 + (lane >> 4);
-        const int64_t e = __shfl(clo, src) + s0 + (lane & 15);
-        const int64_t end = __shfl(chi, src);
-        ii[u] = __shfl(i, src);
-        bb[u] = __shfl(bi, src);
-        ee[u] = e < end ? e : -1;
-        jj[u] = ee[u] >= 0 ? __builtin_nontemporal_load(a.g.idx + e) : -1;
-        ww[u] = ee[u] >= 0 ? __builtin_nontemporal_load(a.g.w + e) : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int src = (half * 4 + u) * 4 + (lane >> 4);
-        const uint32_t key = ee[u] >= 0 ? stream_key<ALGO>(a, ii[u], jj[u], bb[u]) : EMPTY;
-        if (ee[u] >= 0) keybuf[ee[u]] = key;
-        kl[src * WSTRIDE + (lane & 15)] = key;
-        wl[src * WSTRIDE + (lane & 15)] = ww[u];
-      }
-    }
-    wave_sync();
-#pragma unroll 4
-    for (int t = 0; t < WIN; ++t) {
-      const uint32_t key = kl[lane * WSTRIDE + t];
-      if (key != EMPTY) s.update(key, wl[lane * WSTRIDE + t]);
-    }
-    wave_sync();
-  }
+  uint32_t *const win = swin[wv];
+  staged_sketch<K, ALGO, MODE>(a, s, win, i, bi, clo, chi, keybuf);
   s.finalize();
   bool lossy = s.lossy;
   for (int l = 0; l < logp; ++l) {
@@ -423,33 +552,18 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
     maxlen2 = x > maxlen2 ? x : maxlen2;
   }
   for (int64_t s0 = 0; s0 < maxlen2; s0 += WIN) {
-#pragma unroll
-    for (int half = 0; half < 4; ++half) {
-      uint32_t cc[4], ww[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int src = (half * 4 + u) * 4 + (lane >> 4);
-        const int64_t e = __shfl(clo, src) + s0 + (lane & 15);
-        const bool ok = e < __shfl(chi2, src);
-        cc[u] = ok ? __builtin_nontemporal_load(keybuf + e) : EMPTY;
-        ww[u] = ok ? __builtin_nontemporal_load(a.g.w + e) : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int src = (half * 4 + u) * 4 + (lane >> 4);
-        kl[src * WSTRIDE + (lane & 15)] = cc[u];
-        wl[src * WSTRIDE + (lane & 15)] = ww[u];
-      }
-    }
+    stage_window<ALGO, false>(a, win, i, bi, clo, chi2, s0, keybuf);
     wave_sync();
-#pragma unroll 4
+    uint32_t kk[WIN], ww[WIN];
+    read_window(win, kk, ww);
+    wave_sync();
+#pragma unroll
     for (int t = 0; t < WIN; ++t) {
-      const uint32_t c = kl[lane * WSTRIDE + t], w = wl[lane * WSTRIDE + t];
+      const uint32_t c = kk[t], w = ww[t];
 #pragma unroll
       for (int p = 0; p < K; ++p) ex[p] += key[p] == c ? w : 0u;
       kd += c == (uint32_t)d ? w : 0u;
     }
-    wave_sync();
   }
   if (maxlen2 > 0) {
     for (int o = P / 2; o > 0; o >>= 1) {
@@ -715,7 +829,8 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
     int64_t chunks = nnz / (L > 0 ? L : 1) + n + 1;
     b += (size_t)nnz * 4 + 1024;                            // key stream
     b += (size_t)(n + 1) * 8 * 2 + scan_ws_bytes(n) + 2048;  // counts, cstart
-    b += (size_t)chunks * (4 + 4 + (size_t)k * sizeof(Pair)) + 4096;
+    b += (size_t)chunks * (4 + 4 + (size_t)k * sizeof(Pair) + (size_t)(k + 1) * 4) + 4096;
+    b += (size_t)n * ((size_t)k * sizeof(Pair) + 4) + 2048;  // long-row candidates, flags
   }
   return b + 64 * 1024;
 }
@@ -802,6 +917,9 @@ void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Are
     MGCD_LAUNCHED();
     s.sk = a.take<Pair>(s.nchunks * k);
     s.skflag = a.take<uint32_t>(s.nchunks);
+    s.part = a.take<uint32_t>(s.nchunks * (k + 1));
+    s.cand = a.take<Pair>(s.nmulti * k);
+    s.cflag = a.take<uint32_t>(s.nmulti);
   }
 }
 
@@ -814,12 +932,23 @@ static inline void mark(hipEvent_t *ev, int i, hipStream_t st) {
 template <int K, int ALGO, int MODE>
 static void sweep_mg(const SweepArgs &a, const Schedule &s, int64_t L, hipStream_t st, hipEvent_t *ev) {
   mark(ev, 0, st);
-  // rows of more than 64 chunks: chunk sketches to scratch, then one workgroup per row
+  // rows of more than 64 chunks
   if (s.nmulti > 0) {
-    k_move_chunks<K, ALGO, MODE><<<grid_for(s.nchunks), BLOCK, 0, st>>>(
-        a, s.multi, s.owner, s.cstart, s.nchunks, L, s.sk, s.skflag);
+    const unsigned wave_grid = (unsigned)ceil_div(s.nchunks, BLOCK / WAVE);
+    k_long_keys<ALGO><<<wave_grid, BLOCK, 0, st>>>(a, s.multi, s.owner, s.cstart, s.nchunks, L,
+                                                   s.keybuf);
     MGCD_LAUNCHED();
-    k_move_multi<K, ALGO><<<(unsigned)s.nmulti, BLOCK, 0, st>>>(a, s.multi, s.cstart, s.sk, s.skflag);
+    k_long_chunks<K, ALGO, MODE><<<grid_for(s.nchunks), BLOCK, 0, st>>>(
+        a, s.multi, s.owner, s.cstart, s.nchunks, L, s.sk, s.skflag, s.keybuf);
+    MGCD_LAUNCHED();
+    k_long_merge<K, ALGO><<<(unsigned)s.nmulti, BLOCK, 0, st>>>(a, s.multi, s.cstart, s.sk,
+                                                                s.skflag, s.cand, s.cflag);
+    MGCD_LAUNCHED();
+    k_long_count<K, ALGO><<<wave_grid, BLOCK, 0, st>>>(a, s.multi, s.owner, s.cstart, s.nchunks, L,
+                                                       s.cand, s.cflag, s.keybuf, s.part);
+    MGCD_LAUNCHED();
+    k_long_decide<K, ALGO><<<(unsigned)s.nmulti, BLOCK, 0, st>>>(a, s.multi, s.cstart, s.cand,
+                                                                 s.cflag, s.part);
     MGCD_LAUNCHED();
   }
   mark(ev, 1, st);

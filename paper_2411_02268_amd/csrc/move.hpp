@@ -50,6 +50,9 @@ struct Schedule {
   uint32_t *keybuf = nullptr; // [nnz] keys C[j] gathered in pass 1, read by pass 2
   Pair *sk = nullptr;         // [nchunks * k] chunk sketches
   uint32_t *skflag = nullptr; // [nchunks] chunk lost weight
+  uint32_t *part = nullptr;   // [nchunks * (k+1)] pass-2 counts per chunk of a lossy long row
+  Pair *cand = nullptr;       // [nmulti * k] merged candidates of each long row
+  uint32_t *cflag = nullptr;  // [nmulti] 0 decided, 1 lossy, 2 frozen
   // exact mode
   int32_t *tier[4] = {nullptr, nullptr, nullptr, nullptr};
   int64_t ntier[4] = {0, 0, 0, 0};

@@ -28,20 +28,22 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 
 def class_bytes(g, L: int, k: int):
-    """Algorithmic bytes of one level-0 sweep per kernel class (reads + writes that
-    the method must make; the second pass over a row counts as on-chip):
+    """Algorithmic bytes of one level-0 MG sweep per kernel class (reads and writes
+    the method must make; a second pass over a row of at most 64 chunks counts as
+    on-chip, a second pass over a longer row re-reads its keys and weights):
       per CSR entry 12 B (index 4, weight 4, gathered C[j] 4);
       per decided vertex 28 B (list 4, offsets 8, C 4, C_new 4, K 4, Sigma_d 4);
-      rows longer than 64 chunks also write and re-read 8k + 4 B per chunk sketch
-      and use 20 B of chunk table per chunk.
-    Class 0: rows of more than 64 chunks (k_move_chunks + k_move_multi).
-    Class 1: every other row (k_move_rows).  Class 2: unused (0)."""
+      rows of more than 64 chunks: one sketch of 8k + 4 B per group of 64 chunks,
+      written by class 0 and read by class 1; class 1 re-reads their entries'
+      keys and weights (8 B) and writes and reads 4 (k + 1) B of counts per chunk.
+    Class 0: the main sweep kernel (k_move_rows).  Class 1: long-row merge, second
+    pass and decision (k_long_merge, k_long_count, k_long_decide).  Class 2: 0."""
     deg = np.diff(g.offsets)
     nch = (deg + L - 1) // L
     big = nch > 64
-    c0 = (12 * int(deg[big].sum()) + 28 * int(big.sum())
-          + (20 + 2 * (8 * k + 4)) * int(nch[big].sum()))
-    c1 = 12 * int(deg[~big].sum()) + 28 * int((~big).sum())
+    groups = int(((nch[big] + 63) // 64).sum())
+    c0 = 12 * int(deg.sum()) + 28 * g.n + (8 * k + 4) * groups
+    c1 = (8 * k + 4) * groups + 8 * int(deg[big].sum()) + 2 * 4 * (k + 1) * int(nch[big].sum())
     return [c0, c1, 0]
 
 
@@ -100,8 +102,9 @@ def main():
         sweeps += s["l0_sweeps"]
     cb = class_bytes(g, L, k)
     dom = int(np.argmax(ms))
-    names = ["k_move_chunks + k_move_multi (rows of more than 64 chunks)",
-             "k_move_rows (rows of up to 64 chunks: sketch, merge tree, second pass, decision)",
+    names = ["k_move_rows (every row: staged sketch, merge tree, second pass, decision; "
+             "chunk sketches of rows longer than 64 chunks)",
+             "k_long_merge + k_long_count + k_long_decide (rows longer than 64 chunks)",
              "unused"]
     per_launch_ms = ms[dom] / max(sweeps, 1)
     achieved = cb[dom] / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0

@@ -86,9 +86,10 @@ typedef struct {
   float ms_aggregate;     /* device time in renumbering and aggregation               */
   float ms_total;         /* device time of the whole call                            */
   /* Level-0 local-moving sweeps, device time per kernel class (HIP events on the
-     call's stream): rows of one chunk (MG) or short rows (exact); chunk sketches
-     (MG) or LDS tables (exact); merge + second pass of long rows (MG) or global
-     tables (exact). */
+     call's stream).  MG: [0] the main sweep kernel (every row, plus the chunk
+     sketches of rows longer than 64 chunks), [1] the merge, second pass and
+     decision of those long rows, [2] unused.  Exact: [0] rows of at most 32
+     entries, [1] LDS hash tables, [2] global hash tables. */
   int32_t l0_sweeps;
   int32_t reserved2;
   float ms_l0_kernel[3];

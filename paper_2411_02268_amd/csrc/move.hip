@@ -244,10 +244,13 @@ __device__ inline void staged_sketch(const SweepArgs &a, RegSketch<K, MODE> &s, 
 // Rows of more than 64 chunks ("long rows") go through five launches, each with
 // enough independent work to fill the chip:
 //   k_long_keys    one wave per chunk: gather the keys C[j] into the key stream;
-//   k_long_chunks  one lane per chunk: Algorithm 1 from an empty sketch over the
-//                  staged keys (no gather in the dependent chain);
-//   k_long_merge   one workgroup per row: the fixed merge tree over its chunk
-//                  sketches; a row whose sketch lost no weight is decided here;
+//   k_long_chunks  one lane per chunk, one wave per aligned group of 64 chunks:
+//                  Algorithm 1 from an empty sketch over the staged keys (no
+//                  gather in the dependent chain), then the first six levels of
+//                  the fixed merge tree with shuffles;
+//   k_long_merge   one workgroup per row: the rest of the fixed merge tree over
+//                  its group roots; a row whose sketch lost no weight is decided
+//                  here;
 //   k_long_count   one wave per chunk of a lossy row: pass 2 against the row's
 //                  candidates, partial counts per chunk;
 //   k_long_decide  one workgroup per lossy row: sum the partial counts, decide.
@@ -274,43 +277,51 @@ __device__ inline LongChunk long_chunk(const SweepArgs &a, const int32_t *multi,
   return c;
 }
 
-template <int ALGO>
-__global__ void __launch_bounds__(BLOCK)
-    k_long_keys(SweepArgs a, const int32_t *__restrict__ multi, const int32_t *__restrict__ owner,
-                const int64_t *__restrict__ cstart, int64_t nchunks, int64_t L, uint32_t *keybuf) {
-  const int64_t q = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
-  const LongChunk c = long_chunk(a, multi, owner, cstart, q, nchunks, L);
-  if (!c.active) return;
-  const int32_t bi = ALGO == ALGO_REFINE ? a.bound[c.i] : 0;
-  int64_t e = c.lo + lane_id();
-  for (; e + 3 * WAVE < c.hi; e += 4 * WAVE) {
-    int32_t j[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) j[u] = __builtin_nontemporal_load(a.g.idx + e + u * WAVE);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) keybuf[e + u * WAVE] = stream_key<ALGO>(a, c.i, j[u], bi);
-  }
-  for (; e < c.hi; e += WAVE) keybuf[e] = stream_key<ALGO>(a, c.i, a.g.idx[e], bi);
-}
-
+// Wave w takes the aligned group of 64 chunks gstart[m] .. of its long row m (lane
+// = chunk within the group): Algorithm 1 over the staged entries (keys gathered
+// and written to the key stream), then the first six levels of the fixed merge
+// tree with cross-lane shuffles; lane 0 writes the group's root.
 template <int K, int ALGO, int MODE>
-__global__ void __launch_bounds__(BLOCK)
-    k_long_chunks(SweepArgs a, const int32_t *__restrict__ multi, const int32_t *__restrict__ owner,
-                  const int64_t *__restrict__ cstart, int64_t nchunks, int64_t L, Pair *sk,
-                  uint32_t *skflag, uint32_t *keybuf) {
-  __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
-  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const LongChunk c = long_chunk(a, multi, owner, cstart, q, nchunks, L);
-  const int wv = threadIdx.x / WAVE;
+__device__ inline void long_group(const SweepArgs &a, const Buckets &bk, int64_t L,
+                                  uint32_t *keybuf, uint32_t *win, int64_t w) {
+  const int lane = lane_id();
+  const int32_t m = bk.gowner[w];
+  const int32_t i = bk.multi[m];
+  const int64_t nc = bk.cstart[m + 1] - bk.cstart[m];
+  const int64_t q = (w - bk.gstart[m]) * WAVE + lane;  // chunk index within the row
+  const bool active = q < nc && !frozen(a, i);
+  int64_t lo = 0, hi = 0;
+  if (active) {
+    const int64_t rhi = a.g.off[i + 1];
+    lo = a.g.off[i] + q * L;
+    hi = lo + L < rhi ? lo + L : rhi;
+  }
+  const int32_t bi = (ALGO == ALGO_REFINE && active) ? a.bound[i] : 0;
   RegSketch<K, MODE> s;
   s.reset();
-  staged_sketch<K, ALGO, MODE, false>(a, s, swin[wv], c.i, 0, c.lo,
-                                      c.active ? c.hi : c.lo, keybuf);
+  staged_sketch<K, ALGO, MODE>(a, s, win, i, bi, lo, hi, keybuf);
   s.finalize();
-  if (q >= nchunks) return;
+  bool lossy = s.lossy;
+#pragma unroll 1
+  for (int l = 0; l < 6; ++l) {
+    const int stride = 1 << l;
+    uint32_t bk_[K], bv_[K];
 #pragma unroll
-  for (int p = 0; p < K; ++p) sk[q * K + p] = Pair{s.key[p], s.val[p]};
-  skflag[q] = s.lossy ? 1u : 0u;
+    for (int p = 0; p < K; ++p) {
+      bk_[p] = __shfl_down(s.key[p], stride);
+      bv_[p] = __shfl_down(s.val[p], stride);
+    }
+    const int64_t c_l = (nc + stride - 1) >> l;  // nodes at level l
+    const bool left = (lane & ((2 << l) - 1)) == 0;
+    if (left && (q >> l) + 1 < c_l) lossy |= merge_sketch<K>(s.key, s.val, bk_, bv_);
+  }
+  const bool any = __ballot(lossy) != 0;
+  if (lane == 0) {
+#pragma unroll
+    for (int p = 0; p < K; ++p)
+      bk.sk[w * K + p] = Pair{s.val[p] > 0 ? s.key[p] : EMPTY, s.val[p]};
+    bk.skflag[w] = any ? 1u : 0u;
+  }
 }
 
 // Choose the best candidate of row i and record the move (one thread).
@@ -335,14 +346,14 @@ __device__ inline void decide_long(const SweepArgs &a, int32_t i, int32_t d, con
 // cflag[m]: 0 decided here (exact sketch), 1 lossy (candidates in cand), 2 frozen.
 template <int K, int ALGO>
 __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
-    k_long_merge(SweepArgs a, const int32_t *__restrict__ multi, const int64_t *__restrict__ cstart,
+    k_long_merge(SweepArgs a, const int32_t *__restrict__ multi, const int64_t *__restrict__ gstart,
                  Pair *sk, const uint32_t *__restrict__ skflag, Pair *cand, uint32_t *cflag) {
   __shared__ Pair lds[BLOCK * K];
   __shared__ int flag_any;
   const int t = threadIdx.x;
   const int32_t m = blockIdx.x;
   const int32_t i = multi[m];
-  const int64_t cb = cstart[m], nc = cstart[m + 1] - cb;
+  const int64_t cb = gstart[m], nc = gstart[m + 1] - cb;  // group roots of the row
   if (frozen(a, i)) {  // block-uniform
     if (t == 0) {
       a.Cnew[i] = community_of_self<ALGO>(a, i);
@@ -479,13 +490,9 @@ __global__ void __launch_bounds__(BLOCK)
 //           chunk, then xor-shuffles inside the row's aligned segment;
 //   lane 0 of the segment decides.
 template <int K, int ALGO, int MODE>
-__global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
-    k_move_rows(SweepArgs a, const Buckets *__restrict__ bkp, int64_t L, uint32_t *keybuf) {
-  const Buckets &bk = *bkp;
-  __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
+__device__ inline void row_work(const SweepArgs &a, const Buckets &bk, int64_t L, uint32_t *keybuf,
+                                uint32_t *win, int64_t wave, Counters &ct) {
   const int lane = lane_id();
-  const int wv = threadIdx.x / WAVE;
-  const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
   // buckets are laid out in the grid from b = 6 down to b = 0 (wave-uniform)
   int b = 6;
   while (b > 0 && wave >= bk.wave_end[b]) --b;
@@ -506,7 +513,6 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
   const int64_t chi = q < nc ? (clo + L < hi ? clo + L : hi) : clo;
   RegSketch<K, MODE> s;
   s.reset();
-  uint32_t *const win = swin[wv];
   staged_sketch<K, ALGO, MODE>(a, s, win, i, bi, clo, chi, keybuf);
   s.finalize();
   bool lossy = s.lossy;
@@ -576,7 +582,6 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
       kd += need2 ? x : 0u;
     }
   }
-  Counters ct;
   if (valid && q == 0) {
     int32_t best = -1;
     int64_t bestG = 0;
@@ -588,6 +593,23 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
       if (key[p] != EMPTY) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)key[p], ex[p], best, bestG);
     finish<ALGO>(a, i, d, best, bestG, ct);
   }
+}
+
+// The main sweep kernel: the first bk.ngroups waves sketch the groups of 64 chunks
+// of long rows (their merge, pass 2 and decision follow in k_long_*), the rest
+// take the row buckets.
+template <int K, int ALGO, int MODE>
+__global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
+    k_move_rows(SweepArgs a, const Buckets *__restrict__ bkp, int64_t L, uint32_t *keybuf) {
+  const Buckets &bk = *bkp;
+  __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
+  uint32_t *const win = swin[threadIdx.x / WAVE];
+  const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
+  Counters ct;
+  if (wave < bk.ngroups)
+    long_group<K, ALGO, MODE>(a, bk, L, keybuf, win, wave);
+  else
+    row_work<K, ALGO, MODE>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
   flush_counters(a, ct);
 }
 
@@ -794,6 +816,12 @@ __global__ void k_chunk_counts(const int64_t *off, const int32_t *multi, int64_t
   nch[m] = (off[i + 1] - off[i] + L - 1) / L;
 }
 
+__global__ void k_group_counts(const int64_t *cstart, int64_t nmulti, int64_t *ng) {
+  int64_t m = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (m >= nmulti) return;
+  ng[m] = (cstart[m + 1] - cstart[m] + WAVE - 1) / WAVE;
+}
+
 __global__ void k_chunk_owner(const int64_t *cstart, int64_t nmulti, int32_t *owner) {
   int64_t m = blockIdx.x;
   if (m >= nmulti) return;
@@ -830,6 +858,7 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
     b += (size_t)nnz * 4 + 1024;                            // key stream
     b += (size_t)(n + 1) * 8 * 2 + scan_ws_bytes(n) + 2048;  // counts, cstart
     b += (size_t)chunks * (4 + 4 + (size_t)k * sizeof(Pair) + (size_t)(k + 1) * 4) + 4096;
+    b += (size_t)(n + 1) * 8 * 2 + scan_ws_bytes(n) + 2048;  // group counts, gstart
     b += (size_t)n * ((size_t)k * sizeof(Pair) + 4) + 2048;  // long-row candidates, flags
   }
   return b + 64 * 1024;
@@ -888,6 +917,33 @@ void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Are
   }
   s.multi = order + pos;
   s.nmulti = (int64_t)h[7];
+  if (s.nmulti > 0) {
+    int64_t *nch = a.take<int64_t>(s.nmulti);
+    s.cstart = a.take<int64_t>(s.nmulti + 1);
+    k_chunk_counts<<<grid_for(s.nmulti), BLOCK, 0, st>>>(g.off, s.multi, s.nmulti, L, nch);
+    MGCD_LAUNCHED();
+    scan_i64(nch, s.cstart, s.nmulti, s.cstart + s.nmulti, a, st);
+    MGCD_HIP(hipMemcpyAsync(&s.nchunks, s.cstart + s.nmulti, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+    s.owner = a.take<int32_t>(s.nchunks);
+    k_chunk_owner<<<(unsigned)s.nmulti, BLOCK, 0, st>>>(s.cstart, s.nmulti, s.owner);
+    MGCD_LAUNCHED();
+    int64_t *ng = a.take<int64_t>(s.nmulti);
+    s.gstart = a.take<int64_t>(s.nmulti + 1);
+    k_group_counts<<<grid_for(s.nmulti), BLOCK, 0, st>>>(s.cstart, s.nmulti, ng);
+    MGCD_LAUNCHED();
+    scan_i64(ng, s.gstart, s.nmulti, s.gstart + s.nmulti, a, st);
+    MGCD_HIP(hipMemcpyAsync(&s.ngroups, s.gstart + s.nmulti, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+    s.gowner = a.take<int32_t>(s.ngroups);
+    k_chunk_owner<<<(unsigned)s.nmulti, BLOCK, 0, st>>>(s.gstart, s.nmulti, s.gowner);
+    MGCD_LAUNCHED();
+    s.sk = a.take<Pair>(s.ngroups * k);
+    s.skflag = a.take<uint32_t>(s.ngroups);
+    s.part = a.take<uint32_t>(s.nchunks * (k + 1));
+    s.cand = a.take<Pair>(s.nmulti * k);
+    s.cflag = a.take<uint32_t>(s.nmulti);
+  }
   {  // bucket table of k_move_rows, heaviest bucket first in the grid
     Buckets bk{};
     int64_t w = 0;
@@ -900,26 +956,16 @@ void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Are
       bk.wave_end[b] = w;
     }
     s.row_waves = w;
+    bk.ngroups = s.ngroups;
+    bk.multi = s.multi;
+    bk.gowner = s.gowner;
+    bk.gstart = s.gstart;
+    bk.cstart = s.cstart;
+    bk.sk = s.sk;
+    bk.skflag = s.skflag;
     s.buckets = a.take<Buckets>(1);
     MGCD_HIP(hipMemcpyAsync(s.buckets, &bk, sizeof(bk), hipMemcpyHostToDevice, st));
     MGCD_HIP(hipStreamSynchronize(st));
-  }
-  if (s.nmulti > 0) {
-    int64_t *nch = a.take<int64_t>(s.nmulti);
-    s.cstart = a.take<int64_t>(s.nmulti + 1);
-    k_chunk_counts<<<grid_for(s.nmulti), BLOCK, 0, st>>>(g.off, s.multi, s.nmulti, L, nch);
-    MGCD_LAUNCHED();
-    scan_i64(nch, s.cstart, s.nmulti, s.cstart + s.nmulti, a, st);
-    MGCD_HIP(hipMemcpyAsync(&s.nchunks, s.cstart + s.nmulti, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    MGCD_HIP(hipStreamSynchronize(st));
-    s.owner = a.take<int32_t>(s.nchunks);
-    k_chunk_owner<<<(unsigned)s.nmulti, BLOCK, 0, st>>>(s.cstart, s.nmulti, s.owner);
-    MGCD_LAUNCHED();
-    s.sk = a.take<Pair>(s.nchunks * k);
-    s.skflag = a.take<uint32_t>(s.nchunks);
-    s.part = a.take<uint32_t>(s.nchunks * (k + 1));
-    s.cand = a.take<Pair>(s.nmulti * k);
-    s.cflag = a.take<uint32_t>(s.nmulti);
   }
 }
 
@@ -932,29 +978,23 @@ static inline void mark(hipEvent_t *ev, int i, hipStream_t st) {
 template <int K, int ALGO, int MODE>
 static void sweep_mg(const SweepArgs &a, const Schedule &s, int64_t L, hipStream_t st, hipEvent_t *ev) {
   mark(ev, 0, st);
-  // rows of more than 64 chunks
-  if (s.nmulti > 0) {
-    const unsigned wave_grid = (unsigned)ceil_div(s.nchunks, BLOCK / WAVE);
-    k_long_keys<ALGO><<<wave_grid, BLOCK, 0, st>>>(a, s.multi, s.owner, s.cstart, s.nchunks, L,
-                                                   s.keybuf);
-    MGCD_LAUNCHED();
-    k_long_chunks<K, ALGO, MODE><<<grid_for(s.nchunks), BLOCK, 0, st>>>(
-        a, s.multi, s.owner, s.cstart, s.nchunks, L, s.sk, s.skflag, s.keybuf);
-    MGCD_LAUNCHED();
-    k_long_merge<K, ALGO><<<(unsigned)s.nmulti, BLOCK, 0, st>>>(a, s.multi, s.cstart, s.sk,
-                                                                s.skflag, s.cand, s.cflag);
-    MGCD_LAUNCHED();
-    k_long_count<K, ALGO><<<wave_grid, BLOCK, 0, st>>>(a, s.multi, s.owner, s.cstart, s.nchunks, L,
-                                                       s.cand, s.cflag, s.keybuf, s.part);
-    MGCD_LAUNCHED();
-    k_long_decide<K, ALGO><<<(unsigned)s.nmulti, BLOCK, 0, st>>>(a, s.multi, s.cstart, s.cand,
-                                                                 s.cflag, s.part);
+  const int64_t waves = s.ngroups + s.row_waves;
+  if (waves > 0) {
+    k_move_rows<K, ALGO, MODE><<<(unsigned)ceil_div(waves, BLOCK / WAVE), BLOCK, 0, st>>>(
+        a, s.buckets, L, s.keybuf);
     MGCD_LAUNCHED();
   }
   mark(ev, 1, st);
-  if (s.row_waves > 0) {
-    k_move_rows<K, ALGO, MODE><<<(unsigned)ceil_div(s.row_waves, BLOCK / WAVE), BLOCK, 0, st>>>(
-        a, s.buckets, L, s.keybuf);
+  // long rows: rest of the merge tree, pass 2, decision
+  if (s.nmulti > 0) {
+    k_long_merge<K, ALGO><<<(unsigned)s.nmulti, BLOCK, 0, st>>>(a, s.multi, s.gstart, s.sk,
+                                                                s.skflag, s.cand, s.cflag);
+    MGCD_LAUNCHED();
+    k_long_count<K, ALGO><<<(unsigned)ceil_div(s.nchunks, BLOCK / WAVE), BLOCK, 0, st>>>(
+        a, s.multi, s.owner, s.cstart, s.nchunks, L, s.cand, s.cflag, s.keybuf, s.part);
+    MGCD_LAUNCHED();
+    k_long_decide<K, ALGO><<<(unsigned)s.nmulti, BLOCK, 0, st>>>(a, s.multi, s.cstart, s.cand,
+                                                                 s.cflag, s.part);
     MGCD_LAUNCHED();
   }
   mark(ev, 2, st);

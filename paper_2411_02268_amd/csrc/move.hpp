@@ -26,11 +26,20 @@ struct SweepArgs {
 };
 
 // Row buckets of the main sweep kernel: rows needing 2^b lanes (b = 0..6).
+// The grid of the main sweep kernel: first one wave per group of 64 chunks of the
+// long rows (more than 64 chunks), then the row buckets.
 struct Buckets {
-  int64_t wave_begin[7];  // waves of bucket b: [wave_begin[b], wave_end[b]); b = 6 comes first
-  int64_t wave_end[7];    // wave_end[0] is the total
+  int64_t wave_begin[7];  // row waves of bucket b: [wave_begin[b], wave_end[b]), counted
+  int64_t wave_end[7];    // after the long-row groups; b = 6 first; wave_end[0] = total
   const int32_t *rows[7];
   int64_t nrows[7];
+  int64_t ngroups;        // long-row groups (their waves come first)
+  const int32_t *multi;   // long rows
+  const int32_t *gowner;  // [ngroups] long row of each group
+  const int64_t *gstart;  // [nmulti+1] first group of each long row
+  const int64_t *cstart;  // [nmulti+1] first chunk of each long row
+  Pair *sk;               // [ngroups * k] group roots
+  uint32_t *skflag;       // [ngroups] group lost weight
 };
 
 // Per-level work lists, built once per level by build_schedule.
@@ -48,8 +57,11 @@ struct Schedule {
   Buckets *buckets = nullptr; // device copy of the bucket table
   int64_t row_waves = 0;
   uint32_t *keybuf = nullptr; // [nnz] keys C[j] gathered in pass 1, read by pass 2
-  Pair *sk = nullptr;         // [nchunks * k] chunk sketches
-  uint32_t *skflag = nullptr; // [nchunks] chunk lost weight
+  int64_t *gstart = nullptr;  // [nmulti+1] first group of 64 chunks of each multi vertex
+  int32_t *gowner = nullptr;  // [ngroups] multi index of each group
+  int64_t ngroups = 0;
+  Pair *sk = nullptr;         // [ngroups * k] merged sketch of each group of 64 chunks
+  uint32_t *skflag = nullptr; // [ngroups] some sketch or merge of the group lost weight
   uint32_t *part = nullptr;   // [nchunks * (k+1)] pass-2 counts per chunk of a lossy long row
   Pair *cand = nullptr;       // [nmulti * k] merged candidates of each long row
   uint32_t *cflag = nullptr;  // [nmulti] 0 decided, 1 lossy, 2 frozen

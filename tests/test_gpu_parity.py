@@ -59,7 +59,8 @@ def graph(name):
 
 @pytest.mark.parametrize("gname", ["er200", "er120dense", "rmat11", "cl12"])
 @pytest.mark.parametrize("mode", ["exact", "alg1", "uncond", "std"])
-@pytest.mark.parametrize("k,L", [(1, 128), (4, 7), (8, 128), (8, 16), (16, 5)])
+# L = 1 and 2 give rows of several aligned groups of 64 chunks on the R-MAT graph
+@pytest.mark.parametrize("k,L", [(1, 128), (4, 7), (8, 128), (8, 16), (16, 5), (8, 2), (4, 1)])
 def test_sweep_parity(mg, gname, mode, k, L):
     g = graph(gname)
     dg = mg.to_device(g)

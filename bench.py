@@ -26,6 +26,25 @@ sys.path.insert(0, ROOT)
 METRIC = "local-move edges/s (sketch vs exact), batched p99 latency, equal modularity"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 
+# HBM bytes of one level-0 k_move_rows launch on this workload, from FETCH_SIZE and
+# WRITE_SIZE (rocprofv3 --pmc, one counter per run) scaled by what the counters read
+# for a 512 MiB device copy (FETCH x 2.0, WRITE x 1.0); the commands and figures are in
+# profiles/k_move_rows_rmat20_counters.md.  Valid only for the kernel sources they were
+# taken on: SOURCES_SHA256 is checked at run time, and traffic is reported as null when
+# the sources differ.
+TRAFFIC_BYTES = 2407623648
+TRAFFIC_SOURCES = ["csrc/move.hip", "csrc/move.hpp", "csrc/sketch.hpp", "csrc/common.hpp"]
+TRAFFIC_SOURCES_SHA256 = "7278a4d716c06c9f043e22245dc1f4ff6bafe891c0bc9c047d28aef9b03bbdc0"
+
+
+def sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2411_02268_amd", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def class_bytes(g, L: int, k: int):
     """Algorithmic bytes of one level-0 MG sweep per kernel class (reads and writes
@@ -54,6 +73,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--exact-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="finish with three 512 MiB device-to-device copies, the reference "
+                         "kernel for scaling FETCH_SIZE / WRITE_SIZE counters to bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -111,11 +133,24 @@ def main():
     sweep_ms = ms.sum() / max(sweeps, 1)
     sweep_gbs = sum(cb) / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
 
-    lab_x, stats_x, secs_x = run(mg.MODE_EXACT, args.exact_steps, 1)
-    edges_x = sum(s["edges_scanned"] for s in stats_x)
-    q_x = mg.modularity(dg, lab_x)
-    print(f"[bench] exact: {args.exact_steps} steps in {secs_x:.3f}s, "
-          f"{edges_x/secs_x/1e9:.3f} G edges/s, Q={q_x:.6f}", file=sys.stderr, flush=True)
+    exact = None
+    q_x = None
+    if args.exact_steps > 0:
+        lab_x, stats_x, secs_x = run(mg.MODE_EXACT, args.exact_steps, 1)
+        edges_x = sum(s["edges_scanned"] for s in stats_x)
+        q_x = mg.modularity(dg, lab_x)
+        exact = {"value": edges_x / secs_x, "unit": "edges/s",
+                 "ms_per_step": secs_x / args.exact_steps * 1e3}
+        print(f"[bench] exact: {args.exact_steps} steps in {secs_x:.3f}s, "
+              f"{edges_x/secs_x/1e9:.3f} G edges/s, Q={q_x:.6f}", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -137,6 +172,9 @@ def main():
         print(f"[bench] oracle: {reps} runs in {cs:.1f}s -> {e_cpu/cs/1e9:.3f} G edges/s",
               file=sys.stderr, flush=True)
 
+    traffic = None
+    if dom == 0 and sources_sha256() == TRAFFIC_SOURCES_SHA256:
+        traffic = TRAFFIC_BYTES
     out = {
         "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3, "higher_is_better": True,
@@ -145,13 +183,12 @@ def main():
                    "a/b/c=0.57/0.19/0.19, weights U[1,8], seed 2", "n": g.n, "nnz": g.nnz,
                    "k": k, "chunk_len": L, "algorithm": "louvain", "parallelism": "single-gpu"},
         "modularity": {"mg": q_mg, "exact": q_x, "ratio": q_mg / q_x if q_x else None},
-        "exact": {"value": edges_x / secs_x, "unit": "edges/s",
-                  "ms_per_step": secs_x / args.exact_steps * 1e3},
+        "exact": exact,
         "stats": {"iterations": stats[-1]["iterations"], "passes": stats[-1]["passes"],
                   "communities": stats[-1]["communities"], "ms_local_move": stats[-1]["ms_local_move"],
                   "ms_aggregate": stats[-1]["ms_aggregate"], "ms_total": stats[-1]["ms_total"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": names[dom],
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": names[dom],
                      "ms_per_launch": per_launch_ms, "bytes_per_launch": cb[dom],
                      "sweep": {"ms": sweep_ms, "bytes": sum(cb), "GBs": sweep_gbs,
                                "class_ms": (ms / max(sweeps, 1)).tolist(), "class_bytes": cb}},

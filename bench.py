@@ -66,6 +66,90 @@ def class_bytes(g, L: int, k: int):
     return [c0, c1, 0]
 
 
+def serving_leg(mg, torch, requests: int, slots: int, budget_gb: float, seed: int = 5):
+    """Louvain MG k=8 requests on R-MAT graphs of 2^14..2^21 vertices (scale uniform,
+    average degree 16, weights [1, 8]) arriving as a Poisson stream, served by
+    mg.Server under a device-memory budget.  One graph per scale (seed 500 + scale) is
+    generated once and every request of that scale reuses it.  Capacities are measured
+    closed-loop (all requests queued at once): mu_plain with one slot (a FIFO of plain
+    per-graph launches), mu_batched with `slots` slots.  Latency = completion minus
+    submission (server clock).  Every served result is compared with the plain launch's
+    labels on the device (bit-identical, hence equal modularity)."""
+    import threading
+    from paper_2411_02268_amd import synth
+    scales = list(range(14, 22))
+    t0 = time.time()
+    pool = {s: mg.to_device(synth.rmat(scale=s, edge_factor=8, seed=500 + s)) for s in scales}
+    print(f"[bench] serving pool generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    solo, svc, q = {}, {}, {}
+    for s, dg in pool.items():
+        mg.louvain(dg)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        lab, st = mg.louvain(dg)
+        torch.cuda.synchronize()
+        svc[s] = time.perf_counter() - a
+        solo[s] = (lab, st)
+        q[s] = mg.modularity(dg, lab)
+    rng = np.random.default_rng(seed)
+    req_scales = rng.integers(14, 22, size=requests)
+    unit_gaps = rng.exponential(1.0, size=requests)
+    budget = int(budget_gb * (1 << 30))
+    same = [True]
+
+    def run(nslots, rate):
+        arrivals = np.zeros(requests) if rate is None else np.cumsum(unit_gaps / rate)
+        tickets = [None] * requests
+        ready = threading.Semaphore(0)
+        out = [None] * requests
+        with mg.Server(mg.ALGO_LOUVAIN, budget, slots=nslots) as srv:
+            def waiter():
+                for k in range(requests):
+                    ready.acquire()
+                    lab, st, tm = srv.wait(tickets[k])
+                    ok = bool(torch.equal(lab, solo[int(req_scales[k])][0]))
+                    out[k] = (tm, st["edges_scanned"], ok)
+            th = threading.Thread(target=waiter)
+            th.start()
+            start = time.perf_counter()
+            for k in range(requests):
+                delay = start + arrivals[k] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[k] = srv.submit(pool[int(req_scales[k])])
+                ready.release()
+            th.join()
+            peak = srv.info()["peak_bytes"]
+        lat = np.array([o[0][2] - o[0][0] for o in out])
+        t_first = min(o[0][0] for o in out)
+        t_last = max(o[0][2] for o in out)
+        edges = sum(o[1] for o in out)
+        same[0] &= all(o[2] for o in out)
+        return {"slots": nslots, "rate_rps": rate, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+                "throughput_rps": requests / (t_last - t_first),
+                "edges_per_s": edges / (t_last - t_first), "peak_arena_GB": peak / 2**30}
+
+    cap_plain = run(1, None)
+    cap_batched = run(slots, None)
+    mu_p, mu_b = cap_plain["throughput_rps"], cap_batched["throughput_rps"]
+    res = {
+        "requests": requests, "algorithm": "louvain", "k": 8, "budget_GB": budget_gb,
+        "scales": "2^14..2^21 vertices, uniform in the exponent; one pooled graph per scale",
+        "modularity_by_scale": {str(s): q[s] for s in scales},
+        "plain_service_ms_by_scale": {str(s): svc[s] * 1e3 for s in scales},
+        "capacity": {"plain": cap_plain, "batched": cap_batched},
+        "at_0.8_mu_plain": {"plain": run(1, 0.8 * mu_p), "batched": run(slots, 0.8 * mu_p)},
+        "at_0.8_mu_batched": {"batched": run(slots, 0.8 * mu_b)},
+    }
+    res["labels_identical_to_plain"] = same[0]
+    for key in ("at_0.8_mu_plain", "at_0.8_mu_batched"):
+        for mode, r in res[key].items():
+            print(f"[bench] serving {key} {mode}: rate {r['rate_rps']:.1f}/s p50 {r['p50_ms']:.2f} ms "
+                  f"p99 {r['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +157,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--exact-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="finish with three 512 MiB device-to-device copies, the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -144,6 +231,10 @@ def main():
         print(f"[bench] exact: {args.exact_steps} steps in {secs_x:.3f}s, "
               f"{edges_x/secs_x/1e9:.3f} G edges/s, Q={q_x:.6f}", file=sys.stderr, flush=True)
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = serving_leg(mg, torch, args.serve_requests, args.serve_slots, 64.0)
+
     if args.calibrate_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -193,6 +284,7 @@ def main():
                      "sweep": {"ms": sweep_ms, "bytes": sum(cb), "GBs": sweep_gbs,
                                "class_ms": (ms / max(sweeps, 1)).tolist(), "class_bytes": cb}},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out))
 

@@ -188,6 +188,50 @@ int louvain_run_batched(const mgcd_csr *graphs, int32_t count, const mgcd_params
                         int32_t *const *communities_out, void *ws, size_t ws_bytes,
                         mgcd_graph_stats *per_graph, mgcd_stats *total, void *stream);
 
+/* ---- serving: continuous batching of independent requests ------------------------
+ *
+ * A server runs whole lpa/louvain/leiden calls for a stream of graphs that arrive
+ * over time.  It owns `slots` worker threads, each with its own HIP stream (default
+ * priority) on the device that is current at creation, and carves each request's
+ * workspace out of one caller-provided device arena (first fit, 256-byte aligned).
+ * Requests are admitted in arrival order: the oldest waiting request starts as soon
+ * as a slot is free and the arena has a free block of mgcd_workspace_bytes() for it,
+ * so requests that arrive while others run are admitted as slots and memory free up,
+ * and the work of admitted requests overlaps on the device.  A request's result is
+ * identical to the same call made alone (each call is deterministic and shares no
+ * state with the others).
+ *
+ * mgcd_server_create: arena = device pointer, 256-byte aligned, arena_bytes long,
+ *   owned by the caller and untouched by anyone else until mgcd_server_destroy
+ *   returns; slots in [1, 64]; algo MGCD_ALGO_*; params copied (NULL = defaults).
+ *   *out receives the server.  Errors: MGCD_E_ARG, MGCD_E_UNSUPPORTED, MGCD_E_HIP.
+ * mgcd_server_submit: g (host struct, copied; its device arrays and
+ *   communities_out must stay valid and unmodified until the request is done, and
+ *   the arrays must already hold their contents: the server's streams do not wait
+ *   on the caller's stream).
+ *   *ticket receives the request's id.  MGCD_E_WORKSPACE if the request's
+ *   workspace exceeds the whole arena.  Never blocks on the device.
+ * mgcd_server_poll: *state = 0 waiting for admission, 1 running, 2 done.
+ * mgcd_server_wait: blocks until the request is done and returns its call's return
+ *   code (its message through mgcd_last_error on this thread); stats (host, may be
+ *   NULL) as the call filled it; times (host, may be NULL) = seconds since server
+ *   creation of [submission, admission, completion].  The ticket is then released
+ *   (a second wait or poll on it returns MGCD_E_ARG).
+ * mgcd_server_info: counts of waiting and running requests, arena bytes in use and
+ *   the peak (host pointers, each may be NULL).
+ * mgcd_server_destroy: runs every submitted request to completion, joins the
+ *   workers and destroys their streams; results not yet collected are dropped. */
+typedef struct mgcd_server mgcd_server;
+int mgcd_server_create(void *arena, size_t arena_bytes, int32_t slots, int32_t algo,
+                       const mgcd_params *p, mgcd_server **out);
+int mgcd_server_submit(mgcd_server *s, const mgcd_csr *g, int32_t *communities_out,
+                       int64_t *ticket);
+int mgcd_server_poll(mgcd_server *s, int64_t ticket, int32_t *state);
+int mgcd_server_wait(mgcd_server *s, int64_t ticket, mgcd_stats *stats, double *times);
+int mgcd_server_info(mgcd_server *s, int64_t *waiting, int64_t *running, size_t *bytes_in_use,
+                     size_t *peak_bytes);
+int mgcd_server_destroy(mgcd_server *s);
+
 /* Message of the last error on this thread ("" if none). */
 const char *mgcd_last_error(void);
 

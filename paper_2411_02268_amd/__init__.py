@@ -106,6 +106,19 @@ def lib():
             f.argtypes = [ct.POINTER(CSRDesc), i32, ct.POINTER(Params), ct.POINTER(ct.c_void_p), P,
                           sz, ct.POINTER(GraphStats), ct.POINTER(Stats), P]
             f.restype = ct.c_int
+        L.mgcd_server_create.argtypes = [P, sz, i32, i32, ct.POINTER(Params), ct.POINTER(P)]
+        L.mgcd_server_create.restype = ct.c_int
+        L.mgcd_server_submit.argtypes = [P, ct.POINTER(CSRDesc), P, ct.POINTER(i64)]
+        L.mgcd_server_submit.restype = ct.c_int
+        L.mgcd_server_poll.argtypes = [P, i64, ct.POINTER(i32)]
+        L.mgcd_server_poll.restype = ct.c_int
+        L.mgcd_server_wait.argtypes = [P, i64, ct.POINTER(Stats), ct.POINTER(ct.c_double)]
+        L.mgcd_server_wait.restype = ct.c_int
+        L.mgcd_server_info.argtypes = [P, ct.POINTER(i64), ct.POINTER(i64), ct.POINTER(sz),
+                                       ct.POINTER(sz)]
+        L.mgcd_server_info.restype = ct.c_int
+        L.mgcd_server_destroy.argtypes = [P]
+        L.mgcd_server_destroy.restype = ct.c_int
         L.mgcd_last_error.argtypes = []
         L.mgcd_last_error.restype = ct.c_char_p
         _lib = L
@@ -273,3 +286,63 @@ def run_batched(algo: int, graphs, **kw):
                                 ct.byref(tot), _stream()))
     return ([o[:g.n] for o, g in zip(outs, graphs)], [gst[i].asdict() for i in range(count)],
             tot.asdict())
+
+
+class Server:
+    """Continuous-batching server over the library's mgcd_server_* calls: `slots`
+    worker streams run whole calls of `algo` for submitted graphs, each in a block of
+    one device arena of `arena_bytes`.  submit() returns a ticket; wait() returns
+    (labels, stats, (t_submit, t_start, t_end)) with times in seconds since creation."""
+
+    def __init__(self, algo: int, arena_bytes: int, slots: int = 4, device: str = "cuda", **kw):
+        import torch
+        self.algo = algo
+        self.p = params(algo, **kw)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        self.device = self.arena.device
+        self._h = ct.c_void_p()
+        self._held = {}
+        _check(lib().mgcd_server_create(self.arena.data_ptr(), int(arena_bytes), int(slots), algo,
+                                        ct.byref(self.p), ct.byref(self._h)))
+
+    def submit(self, g: DeviceGraph) -> int:
+        import torch
+        out = torch.empty(max(g.n, 1), dtype=torch.int32, device=self.device)
+        torch.cuda.current_stream().synchronize()  # the graph and out exist before the server reads
+        t = ct.c_int64()
+        d = g.desc()
+        _check(lib().mgcd_server_submit(self._h, ct.byref(d), out.data_ptr(), ct.byref(t)))
+        self._held[t.value] = (g, out)
+        return t.value
+
+    def poll(self, ticket: int) -> str:
+        s = ct.c_int32()
+        _check(lib().mgcd_server_poll(self._h, ticket, ct.byref(s)))
+        return ("waiting", "running", "done")[s.value]
+
+    def wait(self, ticket: int):
+        st = Stats()
+        tm = (ct.c_double * 3)()
+        rc = lib().mgcd_server_wait(self._h, ticket, ct.byref(st), tm)
+        g, out = self._held.pop(ticket)
+        _check(rc)
+        return out[:g.n], st.asdict(), (tm[0], tm[1], tm[2])
+
+    def info(self) -> dict:
+        w, r = ct.c_int64(), ct.c_int64()
+        u, pk = ct.c_size_t(), ct.c_size_t()
+        _check(lib().mgcd_server_info(self._h, ct.byref(w), ct.byref(r), ct.byref(u), ct.byref(pk)))
+        return {"waiting": w.value, "running": r.value, "bytes_in_use": u.value, "peak_bytes": pk.value}
+
+    def close(self):
+        if self._h:
+            rc = lib().mgcd_server_destroy(self._h)
+            self._h = ct.c_void_p()
+            self._held.clear()
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -51,6 +51,9 @@ struct Error : std::runtime_error {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Sets the calling thread's message returned by mgcd_last_error().
+void set_last_error(const std::string &msg);
+
 inline int bits_for(uint64_t maxval) {  // bits needed to hold values <= maxval
   int b = 0;
   while (b < 64 && (maxval >> b) != 0) ++b;

@@ -24,6 +24,8 @@ namespace mgcd {
 
 static thread_local std::string g_last_error;
 
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
 // Per-kernel-class device time of level-0 sweeps.
 struct ClassTimer {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};

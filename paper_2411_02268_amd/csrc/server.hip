@@ -1,0 +1,257 @@
+// Serving (continuous batching): worker threads with their own streams run whole
+// calls for a queue of requests, each in a block of one caller-provided arena.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "common.hpp"
+#include "mgcd.h"
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+struct Request {
+  int64_t ticket = 0;
+  mgcd_csr g{};
+  int32_t *out = nullptr;
+  size_t need = 0;
+  int state = 0;  // 0 waiting, 1 running, 2 done
+  int rc = MGCD_OK;
+  std::string err;
+  mgcd_stats stats{};
+  double t_submit = 0, t_start = 0, t_end = 0;
+};
+
+// First-fit allocator over [0, cap) with coalescing of free neighbours.
+struct BlockAllocator {
+  std::map<size_t, size_t> free_;  // offset -> size
+  size_t used = 0, peak = 0;
+  explicit BlockAllocator(size_t cap) {
+    if (cap) free_[0] = cap;
+  }
+  bool take(size_t bytes, size_t *off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t at = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      used += bytes;
+      if (used > peak) peak = used;
+      return true;
+    }
+    return false;
+  }
+  void give(size_t off, size_t bytes) {
+    used -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+int run_call(int32_t algo, const mgcd_csr *g, const mgcd_params *p, int32_t *out, void *ws,
+             size_t bytes, mgcd_stats *stats, hipStream_t st) {
+  switch (algo) {
+    case MGCD_ALGO_LPA: return lpa_run(g, p, out, ws, bytes, stats, st);
+    case MGCD_ALGO_LOUVAIN: return louvain_run(g, p, out, ws, bytes, stats, st);
+    default: return leiden_run(g, p, out, ws, bytes, stats, st);
+  }
+}
+
+}  // namespace
+
+struct mgcd_server {
+  char *arena = nullptr;
+  int32_t algo = 0;
+  mgcd_params params{};
+  int device = 0;
+  BlockAllocator blocks{0};
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;
+  std::mutex mu;
+  std::condition_variable cv_admit, cv_done;
+  std::deque<std::shared_ptr<Request>> waiting;
+  std::unordered_map<int64_t, std::shared_ptr<Request>> tickets;
+  int64_t next_ticket = 1;
+  int64_t running = 0;
+  bool stopping = false;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  // The oldest waiting request can start: a free block exists for it.
+  bool head_fits(size_t *off) {
+    return !waiting.empty() && blocks.take(waiting.front()->need, off);
+  }
+
+  void work(int slot) {
+    (void)hipSetDevice(device);
+    hipStream_t st = streams[slot];
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      size_t off = 0;
+      cv_admit.wait(lk, [&] { return (stopping && waiting.empty()) || head_fits(&off); });
+      if (waiting.empty()) break;  // stopping and drained
+      std::shared_ptr<Request> r = waiting.front();
+      waiting.pop_front();
+      r->state = 1;
+      r->t_start = now();
+      ++running;
+      lk.unlock();
+      const int rc = run_call(algo, &r->g, &params, r->out, arena + off, r->need, &r->stats, st);
+      std::string err = rc == MGCD_OK ? std::string() : std::string(mgcd_last_error());
+      lk.lock();
+      blocks.give(off, r->need);
+      r->rc = rc;
+      r->err = std::move(err);
+      r->t_end = now();
+      r->state = 2;
+      --running;
+      cv_done.notify_all();
+      cv_admit.notify_all();  // freed memory may admit the next request
+    }
+  }
+};
+
+static int fail(int code, const char *msg) {
+  mgcd::set_last_error(msg);
+  return code;
+}
+
+extern "C" {
+
+int mgcd_server_create(void *arena, size_t arena_bytes, int32_t slots, int32_t algo,
+                       const mgcd_params *p, mgcd_server **out) {
+  if (!out) return fail(MGCD_E_ARG, "out is null");
+  *out = nullptr;
+  if (!arena || arena_bytes == 0) return fail(MGCD_E_ARG, "arena is empty");
+  if (((uintptr_t)arena % ALIGN) != 0) return fail(MGCD_E_ARG, "arena must be 256-byte aligned");
+  if (slots < 1 || slots > 64) return fail(MGCD_E_ARG, "slots must be in [1, 64]");
+  if (algo < MGCD_ALGO_LPA || algo > MGCD_ALGO_LEIDEN) return fail(MGCD_E_UNSUPPORTED, "unknown algorithm");
+  auto s = std::make_unique<mgcd_server>();
+  s->arena = (char *)arena;
+  s->algo = algo;
+  if (p)
+    s->params = *p;
+  else
+    mgcd_default_params(algo, &s->params);
+  s->blocks = BlockAllocator(arena_bytes / ALIGN * ALIGN);
+  if (hipGetDevice(&s->device) != hipSuccess) return fail(MGCD_E_HIP, "hipGetDevice failed");
+  mgcd::set_last_error("");
+  for (int q = 0; q < slots; ++q) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+      return fail(MGCD_E_HIP, "hipStreamCreateWithFlags failed");
+    }
+    s->streams.push_back(st);
+  }
+  for (int q = 0; q < slots; ++q) s->workers.emplace_back([srv = s.get(), q] { srv->work(q); });
+  *out = s.release();
+  return MGCD_OK;
+}
+
+int mgcd_server_submit(mgcd_server *s, const mgcd_csr *g, int32_t *communities_out,
+                       int64_t *ticket) {
+  if (!s || !g || !ticket) return fail(MGCD_E_ARG, "null argument");
+  if (g->n < 0 || g->nnz < 0) return fail(MGCD_E_ARG, "negative size");
+  if (g->n > 0 && !communities_out) return fail(MGCD_E_ARG, "communities_out is null");
+  auto r = std::make_shared<Request>();
+  r->g = *g;
+  r->out = communities_out;
+  const size_t need = mgcd_workspace_bytes(s->algo, g->n, g->nnz, &s->params);
+  r->need = need < ALIGN ? ALIGN : (need + ALIGN - 1) / ALIGN * ALIGN;
+  std::lock_guard<std::mutex> lk(s->mu);
+  size_t cap = 0;
+  for (auto &b : s->blocks.free_) cap += b.second;
+  cap += s->blocks.used;
+  if (r->need > cap) return fail(MGCD_E_WORKSPACE, "request needs more than the whole arena");
+  if (s->stopping) return fail(MGCD_E_ARG, "server is shutting down");
+  r->ticket = s->next_ticket++;
+  r->t_submit = s->now();
+  s->tickets[r->ticket] = r;
+  s->waiting.push_back(r);
+  *ticket = r->ticket;
+  s->cv_admit.notify_all();
+  return MGCD_OK;
+}
+
+int mgcd_server_poll(mgcd_server *s, int64_t ticket, int32_t *state) {
+  if (!s || !state) return fail(MGCD_E_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return fail(MGCD_E_ARG, "unknown ticket");
+  *state = it->second->state;
+  return MGCD_OK;
+}
+
+int mgcd_server_wait(mgcd_server *s, int64_t ticket, mgcd_stats *stats, double *times) {
+  if (!s) return fail(MGCD_E_ARG, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return fail(MGCD_E_ARG, "unknown ticket");
+  std::shared_ptr<Request> r = it->second;
+  s->cv_done.wait(lk, [&] { return r->state == 2; });
+  s->tickets.erase(ticket);
+  if (stats) *stats = r->stats;
+  if (times) {
+    times[0] = r->t_submit;
+    times[1] = r->t_start;
+    times[2] = r->t_end;
+  }
+  if (r->rc != MGCD_OK) mgcd::set_last_error(r->err);
+  return r->rc;
+}
+
+int mgcd_server_info(mgcd_server *s, int64_t *waiting, int64_t *running, size_t *bytes_in_use,
+                     size_t *peak_bytes) {
+  if (!s) return fail(MGCD_E_ARG, "null server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (waiting) *waiting = (int64_t)s->waiting.size();
+  if (running) *running = s->running;
+  if (bytes_in_use) *bytes_in_use = s->blocks.used;
+  if (peak_bytes) *peak_bytes = s->blocks.peak;
+  return MGCD_OK;
+}
+
+int mgcd_server_destroy(mgcd_server *s) {
+  if (!s) return MGCD_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+  }
+  s->cv_admit.notify_all();
+  for (auto &t : s->workers) t.join();
+  int rc = MGCD_OK;
+  for (hipStream_t st : s->streams)
+    if (hipStreamDestroy(st) != hipSuccess) rc = fail(MGCD_E_HIP, "hipStreamDestroy failed");
+  delete s;
+  return rc;
+}
+
+}  // extern "C"

@@ -72,6 +72,17 @@ typedef struct {
   double tolerance_drop;  /* tolerance is divided by this after every pass           */
   double aggregation_tolerance; /* stop when a pass keeps more than this fraction of
                                    its vertices                                    */
+  /* Schedule only: these choose which kernel and lane mapping takes a row and never
+     change results.  0 selects the default. */
+  int32_t row_lanes;      /* most lanes (chunks) a row takes in the row buckets: a
+                             power of two up to 64 (default 64); rows of more chunks
+                             take the long-row path                                  */
+  int32_t exact_small;    /* exact mode: rows of at most this many entries use one
+                             lane each (default 32)                                  */
+  int32_t exact_lds;      /* exact mode: rows up to this use a 1024-slot LDS table
+                             (default and maximum 512)                               */
+  int32_t exact_lds_big;  /* exact mode: rows up to this use an 8192-slot LDS table
+                             (default and maximum 4096); longer rows a global table  */
 } mgcd_params;
 
 typedef struct {

@@ -37,7 +37,9 @@ class Params(ct.Structure):
                 ("max_iterations", ct.c_int32), ("max_passes", ct.c_int32),
                 ("validate", ct.c_int32), ("chunk_len", ct.c_int64),
                 ("tolerance", ct.c_double), ("tolerance_drop", ct.c_double),
-                ("aggregation_tolerance", ct.c_double)]
+                ("aggregation_tolerance", ct.c_double), ("row_lanes", ct.c_int32),
+                ("exact_small", ct.c_int32), ("exact_lds", ct.c_int32),
+                ("exact_lds_big", ct.c_int32)]
 
 
 class Stats(ct.Structure):

@@ -279,7 +279,7 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
   if (algo == MGCD_ALGO_LPA) {
     launch_iota(Ca, N, st);
     Schedule sch;
-    build_schedule(U, p->mode, p->k, p->chunk_len, sch, a, st);
+    build_schedule(U, sched_params(p), sch, a, st);
     for (int32_t g = 0; g < count; ++g) active[g] = !finished[g];
     copy_h2d(active_d, active.data(), count, st);
     for (int it = 0; it < p->max_iterations && N > 0; ++it) {
@@ -353,7 +353,7 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
       size_t mark = a.mark();
       tm.start();
       Schedule sch;
-      build_schedule(cur, p->mode, p->k, p->chunk_len, sch, a, st);
+      build_schedule(cur, sched_params(p), sch, a, st);
       launch_iota(Ca, nl, st);
       launch_community_totals(Ca, K, Sig, size, nl, st);
       ms_lm += tm.stop();

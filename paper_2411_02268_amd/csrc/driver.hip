@@ -56,6 +56,14 @@ static void check_params(const mgcd_params *p) {
   if (p->max_iterations < 1 || p->max_passes < 1) throw Error(MGCD_E_ARG, "iteration limits must be >= 1");
   if (!(p->tolerance >= 0.0) || !(p->tolerance_drop > 0.0) || !(p->aggregation_tolerance >= 0.0))
     throw Error(MGCD_E_ARG, "bad tolerance");
+  const int rl = p->row_lanes;
+  if (rl < 0 || rl > 64 || (rl & (rl - 1)) != 0)
+    throw Error(MGCD_E_ARG, "row_lanes must be 0 or a power of two up to 64");
+  if (p->exact_small < 0 || p->exact_lds < 0 || p->exact_lds_big < 0)
+    throw Error(MGCD_E_ARG, "exact tier bounds must be >= 0");
+  const SchedParams sp = sched_params(p);
+  if (sp.exact_t1 > EXACT_T1_MAX || sp.exact_t2 > EXACT_T2_MAX)
+    throw Error(MGCD_E_ARG, "exact tier bounds must be at most 512 (exact_lds) and 4096 (exact_lds_big)");
 }
 
 static Graph view(const mgcd_csr *g) {
@@ -123,7 +131,7 @@ static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Are
   unsigned long long *ctr = a.take<unsigned long long>(4);
   launch_iota(Ca, n, st);
   Schedule sch;
-  build_schedule(g, p->mode, p->k, p->chunk_len, sch, a, st);
+  build_schedule(g, sched_params(p), sch, a, st);
   mgcd_stats s{};
   float ms_lm = 0;
   ClassTimer ct;
@@ -195,7 +203,7 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
     size_t mark = a.mark();
     Schedule sch;
     tm.start();
-    build_schedule(cur, p->mode, p->k, p->chunk_len, sch, a, st);
+    build_schedule(cur, sched_params(p), sch, a, st);
     if (!leiden) launch_iota(Ca, nl, st);
     launch_community_totals(Ca, K, Sig, size, nl, st);
     ms_lm += tm.stop();
@@ -431,7 +439,7 @@ int mgcd_move_sweep(const mgcd_csr *gin, const mgcd_params *p, int32_t algo, con
     unsigned long long *ctr = a.take<unsigned long long>(4);
     launch_community_totals(C, K, Sig, size, g.n, st);
     Schedule sch;
-    build_schedule(g, p->mode, p->k, p->chunk_len, sch, a, st);
+    build_schedule(g, sched_params(p), sch, a, st);
     launch_zero_u64(ctr, 3, st);
     SweepArgs args{g, C, nullptr, K, Sig, W, direction < 0 ? -1 : direction > 0 ? 1 : 0, C_new, gain, ctr};
     launch_sweep(args, sch, algo == MGCD_ALGO_LPA ? ALGO_LPA : ALGO_MOVE, p->mode, p->k, p->chunk_len, st);
@@ -459,7 +467,7 @@ int mgcd_refine(const mgcd_csr *gin, const mgcd_params *p, const int32_t *bound,
     int32_t *prop = a.take<int32_t>(g.n), *nprop = a.take<int32_t>(g.n), *from = a.take<int32_t>(g.n);
     unsigned long long *ctr = a.take<unsigned long long>(4);
     Schedule sch;
-    build_schedule(g, p->mode, p->k, p->chunk_len, sch, a, st);
+    build_schedule(g, sched_params(p), sch, a, st);
     launch_zero_u64(ctr, 3, st);
     SweepArgs r{g, nullptr, bound, K, K, W, 0, prop, nullptr, ctr};
     launch_sweep(r, sch, ALGO_REFINE, p->mode, p->k, p->chunk_len, st);

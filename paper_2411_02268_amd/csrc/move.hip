@@ -615,7 +615,7 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
 
 // ---- exact mode ----------------------------------------------------------------------
 
-// Rows of at most EXACT_T0 entries: one lane per vertex; K_{i->c} of each distinct
+// Exact mode, the shortest rows (tier 0): one lane per vertex; K_{i->c} of each distinct
 // key, summed at its first occurrence in the row.
 template <int ALGO>
 __global__ void __launch_bounds__(BLOCK)
@@ -771,8 +771,10 @@ __global__ void __launch_bounds__(BLOCK)
 constexpr int NCAT = 8;
 
 __global__ void __launch_bounds__(BLOCK)
-    k_schedule_keys(const int64_t *off, int32_t n, int mode, int64_t L, uint64_t *key, uint32_t *val,
+    k_schedule_keys(const int64_t *off, int32_t n, SchedParams sp, uint64_t *key, uint32_t *val,
                     unsigned long long *cnt) {
+  const int mode = sp.mode;
+  const int64_t L = sp.L;
   __shared__ unsigned long long bc[NCAT];
   if (threadIdx.x < NCAT) bc[threadIdx.x] = 0;
   __syncthreads();
@@ -784,7 +786,7 @@ __global__ void __launch_bounds__(BLOCK)
     while (b < 63 && (deg >> b) != 0) ++b;  // bits of deg
     uint64_t k;
     if (mode == MODE_EXACT) {
-      cat = deg <= EXACT_T0 ? 0 : deg <= EXACT_T1 ? 1 : deg <= EXACT_T2 ? 2 : 3;
+      cat = deg <= sp.exact_t0 ? 0 : deg <= sp.exact_t1 ? 1 : deg <= sp.exact_t2 ? 2 : 3;
       k = cat == 0 ? (uint64_t)(64 - b) : (uint64_t)(128 + cat);
     } else if (deg <= L) {
       cat = 0;
@@ -793,7 +795,7 @@ __global__ void __launch_bounds__(BLOCK)
       int64_t nc = (deg + L - 1) / L;
       int lp = 0;
       while ((1ll << lp) < nc) ++lp;
-      cat = lp <= 6 ? lp : 7;
+      cat = lp <= sp.row_lanes_log2 ? lp : 7;
       k = 200ull + (uint64_t)cat;
     }
     key[i] = k;
@@ -864,8 +866,9 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
   return b + 64 * 1024;
 }
 
-void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Arena &a,
-                    hipStream_t st) {
+void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a, hipStream_t st) {
+  const int mode = sp.mode, k = sp.k;
+  const int64_t L = sp.L;
   const int32_t n = g.n;
   s = Schedule{};
   if (n == 0) return;
@@ -876,7 +879,7 @@ void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Are
   uint32_t *v1 = a.take<uint32_t>(n);
   int32_t *order = a.take<int32_t>(n);
   launch_zero_u64(cnt, NCAT, st);
-  k_schedule_keys<<<grid_for(n), BLOCK, 0, st>>>(g.off, n, mode, L, k0, v0, cnt);
+  k_schedule_keys<<<grid_for(n), BLOCK, 0, st>>>(g.off, n, sp, k0, v0, cnt);
   MGCD_LAUNCHED();
   bool flip = radix_sort_pairs(k0, v0, k1, v1, n, 8, a, st);
   k_u32_from_u64<<<grid_for(n), BLOCK, 0, st>>>(flip ? v1 : v0, order, n);

@@ -1,6 +1,7 @@
 // Local-moving sweeps (host launchers; kernels in move.hip).
 #pragma once
 #include "common.hpp"
+#include "mgcd.h"
 
 namespace mgcd {
 
@@ -72,11 +73,42 @@ struct Schedule {
   Pair *htab = nullptr;
 };
 
-// exact-mode tiers: degree <= 32 | <= 512 | <= 4096 | larger
-constexpr int64_t EXACT_T0 = 32, EXACT_T1 = 512, EXACT_T2 = 4096;
+// What a level's schedule depends on.  mode, k and L change results; the rest only
+// changes which kernel and mapping takes a row (results never change):
+//   row_lanes_log2: rows of more than 2^row_lanes_log2 chunks (at most 64) take the
+//                   long-row path;
+//   exact_t0/t1/t2: exact mode, rows of at most t0 entries use one lane each, at most
+//                   t1 (<= 512) the 1024-slot LDS table, at most t2 (<= 4096) the
+//                   8192-slot LDS table, longer rows a global table.
+struct SchedParams {
+  int mode = MODE_ALG1;
+  int k = 8;
+  int64_t L = 128;
+  int row_lanes_log2 = 6;
+  int64_t exact_t0 = 32, exact_t1 = 512, exact_t2 = 4096;
+};
+constexpr int64_t EXACT_T1_MAX = 512, EXACT_T2_MAX = 4096;
 
-void build_schedule(const Graph &g, int mode, int k, int64_t L, Schedule &s, Arena &a,
-                    hipStream_t st);
+void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a, hipStream_t st);
+
+// The schedule parameters of a call (0 in a schedule field selects its default).
+inline SchedParams sched_params(const mgcd_params *p) {
+  SchedParams sp;
+  sp.mode = p->mode;
+  sp.k = p->k;
+  sp.L = p->chunk_len;
+  if (p->row_lanes > 0) {
+    int b = 0;
+    while ((1 << b) < p->row_lanes) ++b;
+    sp.row_lanes_log2 = b;
+  }
+  if (p->exact_small > 0) sp.exact_t0 = p->exact_small;
+  if (p->exact_lds > 0) sp.exact_t1 = p->exact_lds;
+  if (p->exact_lds_big > 0) sp.exact_t2 = p->exact_lds_big;
+  if (sp.exact_t1 < sp.exact_t0) sp.exact_t1 = sp.exact_t0;
+  if (sp.exact_t2 < sp.exact_t1) sp.exact_t2 = sp.exact_t1;
+  return sp;
+}
 size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L);
 
 // One sweep of `algo` (ALGO_LPA / ALGO_MOVE / ALGO_REFINE) over all vertices.

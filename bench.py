@@ -150,6 +150,59 @@ def serving_leg(mg, torch, requests: int, slots: int, budget_gb: float, seed: in
     return res
 
 
+def batched_leg(mg, torch, count: int, nmax: float, workers: int):
+    """LPA and Louvain (MG) on `count` planted-partition graphs (vertex counts
+    log-uniform in [1e3, nmax], communities log-uniform in [20, 2000], intra:inter
+    degree 12:4, weight 1; graph g seeded 4000 + g) in one batched call, against the
+    plain per-graph launches of the same graphs.  k and the schedule knobs come from
+    the autotuner on a 32-graph sample (batched).  Labels of the batched call must
+    equal the plain launches' (bit-identical, hence equal modularity)."""
+    from paper_2411_02268_amd import autotune, synth
+    t0 = time.time()
+    graphs = synth.planted_batch(count=count, nmax=nmax, workers=workers)
+    dgs = [mg.to_device(g) for g in graphs]
+    del graphs
+    N = sum(g.n for g in dgs)
+    E = sum(g.nnz for g in dgs)
+    print(f"[bench] batch of {count} graphs: n={N} nnz={E}, built in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    sample = dgs[:: max(1, count // 32)][:32]
+    out = {"graphs": count, "n": N, "nnz": E, "nmax": nmax}
+    for name, algo, fn in (("lpa", mg.ALGO_LPA, mg.lpa), ("louvain", mg.ALGO_LOUVAIN, mg.louvain)):
+        tuned = autotune.tune(mg, sample, algo, repeats=1, batched=True)
+        kw = autotune.run_kwargs(tuned)
+        mg.run_batched(algo, dgs, **kw)  # warm-up
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        labs, per, tot = mg.run_batched(algo, dgs, **kw)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - a
+        fn(dgs[0], **kw)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        same = True
+        plain_labels = []
+        for g in dgs:
+            lab, _ = fn(g, **kw)
+            plain_labels.append(lab)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - a
+        for x, y in zip(labs, plain_labels):
+            same &= bool(torch.equal(x, y))
+        qs = [mg.modularity(g, lab) for g, lab in zip(sample, labs[:: max(1, count // 32)][:32])]
+        edges = sum(p["edges_scanned"] for p in per)
+        out[name] = {"k": tuned["k"], "row_lanes": tuned["row_lanes"],
+                     "quality_rule_met": tuned["report"]["quality_met"],
+                     "batched_s": t_batch, "plain_s": t_plain, "speedup": t_plain / t_batch,
+                     "batched_edges_per_s": edges / t_batch, "labels_identical_to_plain": same,
+                     "mean_Q_sample": float(np.mean(qs))}
+        print(f"[bench] batched {name}: k={tuned['k']} batch {t_batch*1e3:.1f} ms vs plain "
+              f"{t_plain*1e3:.1f} ms ({t_plain/t_batch:.2f}x), identical={same}",
+              file=sys.stderr, flush=True)
+        del labs, plain_labels
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +213,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving leg (0 skips it)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--batch-graphs", type=int, default=1024,
+                    help="graphs of the batched leg (0 skips it)")
+    ap.add_argument("--batch-nmax", type=float, default=2e5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="finish with three 512 MiB device-to-device copies, the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -235,6 +291,11 @@ def main():
     if args.serve_requests > 0:
         serving = serving_leg(mg, torch, args.serve_requests, args.serve_slots, 64.0)
 
+    batched = None
+    if args.batch_graphs > 0:
+        batched = batched_leg(mg, torch, args.batch_graphs, args.batch_nmax,
+                              min(16, os.cpu_count() or 1))
+
     if args.calibrate_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -285,6 +346,7 @@ def main():
                                "class_ms": (ms / max(sweeps, 1)).tolist(), "class_bytes": cb}},
         "cpu_baseline": cpu,
         "serving": serving,
+        "batched": batched,
     }
     print(json.dumps(out))
 

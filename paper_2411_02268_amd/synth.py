@@ -79,18 +79,22 @@ def csr_from_undirected(n: int, u: np.ndarray, v: np.ndarray, w: np.ndarray | No
     lo = np.minimum(u, v)
     hi = np.maximum(u, v)
     if w is None:
+        # unique pairs, both directions, sorted by (row, column); the weight is a
+        # symmetric hash of the pair, so it is computed after sorting
         key = np.unique(lo * n + hi)
-        lo, hi = key // n, key % n
-        ww = pair_weights(lo, hi, seed, wmax)
+        both = np.concatenate([key, (key % n) * n + key // n])
+        both.sort()
+        src, dst = both // n, both % n
+        wt = pair_weights(np.minimum(src, dst), np.maximum(src, dst), seed, wmax)
     else:
         w = np.asarray(w, dtype=np.uint32)[keep]
         key, first = np.unique(lo * n + hi, return_index=True)
         lo, hi, ww = key // n, key % n, w[first]
-    src = np.concatenate([lo, hi])
-    dst = np.concatenate([hi, lo])
-    wt = np.concatenate([ww, ww])
-    order = np.argsort(src * n + dst, kind="stable")
-    src, dst, wt = src[order], dst[order], wt[order]
+        src = np.concatenate([lo, hi])
+        dst = np.concatenate([hi, lo])
+        wt = np.concatenate([ww, ww])
+        order = np.argsort(src * n + dst, kind="stable")
+        src, dst, wt = src[order], dst[order], wt[order]
     counts = np.bincount(src, minlength=n).astype(np.int64)
     offsets = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=offsets[1:])
@@ -143,7 +147,7 @@ def planted_exact(n_comm: int = 20, comm_size: int = 500, half_intra: int = 6,
         t2 = np.empty(n, dtype=np.int32)
         t2[perm] = truth
         truth = t2
-    g = csr_from_undirected(n, u, v, np.ones(u.shape[0], dtype=np.uint32))
+    g = csr_from_undirected(n, u, v, wmax=1)
     return g, truth
 
 
@@ -288,19 +292,27 @@ def planted_uneven(n: int, cmin: int, cmax: int, d_in_half: int, d_out: int,
     u, v = perm[u], perm[v]
     t2 = np.empty(n, dtype=np.int32)
     t2[perm] = truth
-    return csr_from_undirected(n, u, v, np.ones(u.shape[0], dtype=np.uint32)), t2
+    return csr_from_undirected(n, u, v, wmax=1), t2
+
+
+def _planted_one(args):
+    seed, nmin, nmax, cmin, cmax = args
+    rng = np.random.default_rng(seed)
+    n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+    return planted_uneven(n, cmin, cmax, 6, 4, rng)[0]
 
 
 def planted_batch(count: int = 4096, nmin: float = 1e3, nmax: float = 2e5, cmin: int = 20,
-                  cmax: int = 2000, base_seed: int = 4000):
+                  cmax: int = 2000, base_seed: int = 4000, workers: int = 1):
     """`count` planted graphs; graph g uses seed base_seed + g and has a vertex count
-    log-uniform in [nmin, nmax] with intra:inter degree 12:4."""
-    out = []
-    for g in range(count):
-        rng = np.random.default_rng(base_seed + g)
-        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
-        out.append(planted_uneven(n, cmin, cmax, 6, 4, rng)[0])
-    return out
+    log-uniform in [nmin, nmax] with intra:inter degree 12:4.  workers > 1 builds the
+    graphs in that many fresh processes (same result)."""
+    jobs = [(base_seed + g, nmin, nmax, cmin, cmax) for g in range(count)]
+    if workers <= 1:
+        return [_planted_one(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_planted_one, jobs, chunksize=max(1, count // (8 * workers)))
 
 
 # ----------------------------------------------------------------------------------

@@ -1,10 +1,13 @@
-"""Benchmark: Louvain local moving with weighted Misra-Gries sketches on one MI355X.
+"""Benchmark: community detection with weighted Misra-Gries sketches on one MI355X.
 
-Workload (default): Louvain, MG sketch k=8 (Algorithm 1) vs the exact table, on an
-R-MAT graph with 2^20 vertices and 16 * 2^20 undirected edge samples
-(a, b, c = 0.57, 0.19, 0.19; self-loops dropped, duplicates collapsed, weights
-uniform in [1, 8]; ~31.4M CSR entries).  One step = one whole louvain_run (every
-local-moving sweep of every pass, renumbering and aggregation) on the graph
+Default workload (louvain-mg-k8-rmat20): Louvain, MG sketch k=8 (Algorithm 1) vs the
+exact table, on an R-MAT graph with 2^20 vertices and 16 * 2^20 undirected edge
+samples (a, b, c = 0.57, 0.19, 0.19; self-loops dropped, duplicates collapsed,
+weights uniform in [1, 8]; ~31.4M CSR entries), plus a serving leg (Poisson stream of
+R-MAT requests) and a batched leg (planted graphs, autotuned).  Other workloads:
+leiden-mg-k16-cl24 (Leiden k=16 on a 2^24-vertex Chung-Lu graph) and
+lpa-mg-k8-planted (LPA on the 10,000-vertex planted partition).  One step = one whole
+run (every sweep of every pass, refinement, renumbering and aggregation) on the graph
 already resident in HBM.
 
 Prints one JSON line.  `value` = local-move edges/s of the whole job: CSR entries
@@ -203,18 +206,43 @@ def batched_leg(mg, torch, count: int, nmax: float, workers: int):
     return out
 
 
+WORKLOADS = {
+    # name: (algorithm, k, graph description, generator)
+    "louvain-mg-k8-rmat20": (
+        "louvain", 8, "R-MAT scale 20, edge factor 16, a/b/c=0.57/0.19/0.19, weights U[1,8], seed 2",
+        lambda synth: synth.rmat(scale=20, edge_factor=16, seed=2)),
+    "leiden-mg-k16-cl24": (
+        "leiden", 16, "Chung-Lu 2^24 vertices, mean degree 32, exponent 2.1, weights U[1,4], seed 3",
+        lambda synth: synth.chung_lu(n=1 << 24, avg_deg=32, seed=3)),
+    "lpa-mg-k8-planted": (
+        "lpa", 8, "planted partition 20 x 500, 12 intra + 4 inter edges per vertex, weight 1, seed 1",
+        lambda synth: synth.planted_exact(n_comm=20, comm_size=500, seed=1)[0]),
+}
+DEFAULT_WORKLOAD = "louvain-mg-k8-rmat20"
+
+
+def host_threads() -> int:
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--exact-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=2000,
-                    help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--serve-requests", type=int, default=None,
+                    help="requests of the serving leg (0 skips it; default 2000 with the "
+                         "default workload, else 0)")
     ap.add_argument("--serve-slots", type=int, default=4)
-    ap.add_argument("--batch-graphs", type=int, default=1024,
-                    help="graphs of the batched leg (0 skips it)")
+    ap.add_argument("--batch-graphs", type=int, default=None,
+                    help="graphs of the batched leg (0 skips it; default 1024 with the "
+                         "default workload, else 0)")
     ap.add_argument("--batch-nmax", type=float, default=2e5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="finish with three 512 MiB device-to-device copies, the reference "
@@ -224,6 +252,11 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see the sharding notes in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    default = args.workload == DEFAULT_WORKLOAD
+    if args.serve_requests is None:
+        args.serve_requests = 2000 if default else 0
+    if args.batch_graphs is None:
+        args.batch_graphs = 1024 if default else 0
 
     import torch
     import paper_2411_02268_amd as mg
@@ -231,22 +264,24 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     mg.lib()
+    algo_name, k, graph_desc, gen = WORKLOADS[args.workload]
+    L = 128
+    fn = {"lpa": mg.lpa, "louvain": mg.louvain, "leiden": mg.leiden}[algo_name]
     t0 = time.time()
-    g = synth.rmat(scale=20, edge_factor=16, seed=2)
+    g = gen(synth)
     gen_s = time.time() - t0
-    print(f"[bench] graph n={g.n} nnz={g.nnz} W={g.total_weight()} generated in {gen_s:.1f}s",
-          file=sys.stderr, flush=True)
+    print(f"[bench] {args.workload}: graph n={g.n} nnz={g.nnz} W={g.total_weight()} generated in "
+          f"{gen_s:.1f}s", file=sys.stderr, flush=True)
     dg = mg.to_device(g)
-    k, L = 8, 128
 
     def run(mode, steps, warm):
         for _ in range(warm):
-            mg.louvain(dg, mode=mode, k=k, chunk_len=L)
+            fn(dg, mode=mode, k=k, chunk_len=L)
         torch.cuda.synchronize()
         stats = []
         a = time.perf_counter()
         for _ in range(steps):
-            lab, st = mg.louvain(dg, mode=mode, k=k, chunk_len=L)
+            lab, st = fn(dg, mode=mode, k=k, chunk_len=L)
             stats.append(st)
         torch.cuda.synchronize()
         b = time.perf_counter()
@@ -256,7 +291,7 @@ def main():
     edges = sum(s["edges_scanned"] for s in stats)
     value = edges / secs
     q_mg = mg.modularity(dg, lab)
-    print(f"[bench] MG k=8: {args.steps} steps in {secs:.3f}s, {value/1e9:.3f} G edges/s, "
+    print(f"[bench] MG k={k}: {args.steps} steps in {secs:.3f}s, {value/1e9:.3f} G edges/s, "
           f"Q={q_mg:.6f}", file=sys.stderr, flush=True)
 
     # dominant level-0 kernel class, its live HIP-event time, algorithmic bytes
@@ -294,7 +329,7 @@ def main():
     batched = None
     if args.batch_graphs > 0:
         batched = batched_leg(mg, torch, args.batch_graphs, args.batch_nmax,
-                              min(16, os.cpu_count() or 1))
+                              min(16, host_threads()))
 
     if args.calibrate_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
@@ -308,37 +343,50 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        threads = os.cpu_count() or 1
+        threads = host_threads()
         a = time.perf_counter()
         reps, e_cpu = 0, 0
-        while reps < 3 or time.perf_counter() - a < 10.0:
-            _, est = oracle.louvain(g, mode=oracle.MODE_ALG1, k=k, chunk_len=L, threads=threads)
-            e_cpu += est.edges_scanned
-            reps += 1
-            if time.perf_counter() - a > 30.0:
-                break
+        if g.nnz <= 100_000_000:
+            ofn = {"lpa": oracle.lpa, "louvain": oracle.louvain, "leiden": oracle.leiden}[algo_name]
+            while reps < 3 or time.perf_counter() - a < 10.0:
+                _, est = ofn(g, mode=oracle.MODE_ALG1, k=k, chunk_len=L, threads=threads)
+                e_cpu += est.edges_scanned
+                reps += 1
+                if time.perf_counter() - a > 30.0:
+                    break
+            sample = f"whole MG k={k} {algo_name} runs on the same graph"
+        else:
+            C0 = np.arange(g.n, dtype=np.int32)
+            oalgo = oracle.ALGO_LPA if algo_name == "lpa" else oracle.ALGO_MOVE
+            while reps < 1 or time.perf_counter() - a < 10.0:
+                oracle.move_sweep(g, oalgo, C0, mode=oracle.MODE_ALG1, k=k, chunk_len=L)
+                e_cpu += g.nnz
+                reps += 1
+                if time.perf_counter() - a > 30.0:
+                    break
+            sample = (f"level-0 MG k={k} local-moving sweeps from singletons on the same graph "
+                      f"(a whole run exceeds the time bound)")
         cs = time.perf_counter() - a
         cpu = {"value": e_cpu / cs, "unit": "edges/s", "cores": threads, "kind": "oracle",
-               "sample": f"whole MG k=8 Louvain run on the same R-MAT 2^20 graph, {reps} runs "
-                         f"({cs:.1f}s), OpenMP threads={threads}"}
-        print(f"[bench] oracle: {reps} runs in {cs:.1f}s -> {e_cpu/cs/1e9:.3f} G edges/s",
+               "sample": f"{sample}, {reps} repetitions ({cs:.1f}s), OpenMP threads={threads}"}
+        print(f"[bench] oracle: {reps} reps in {cs:.1f}s -> {e_cpu/cs/1e9:.3f} G edges/s",
               file=sys.stderr, flush=True)
 
     traffic = None
-    if dom == 0 and sources_sha256() == TRAFFIC_SOURCES_SHA256:
+    if default and dom == 0 and sources_sha256() == TRAFFIC_SOURCES_SHA256:
         traffic = TRAFFIC_BYTES
+    st_last = stats[-1]
     out = {
         "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": "louvain-mg-k8-rmat20", "graph": "R-MAT scale 20, edge factor 16, "
-                   "a/b/c=0.57/0.19/0.19, weights U[1,8], seed 2", "n": g.n, "nnz": g.nnz,
-                   "k": k, "chunk_len": L, "algorithm": "louvain", "parallelism": "single-gpu"},
+        "config": {"workload": args.workload, "graph": graph_desc, "n": g.n, "nnz": g.nnz,
+                   "k": k, "chunk_len": L, "algorithm": algo_name, "parallelism": "single-gpu"},
         "modularity": {"mg": q_mg, "exact": q_x, "ratio": q_mg / q_x if q_x else None},
         "exact": exact,
-        "stats": {"iterations": stats[-1]["iterations"], "passes": stats[-1]["passes"],
-                  "communities": stats[-1]["communities"], "ms_local_move": stats[-1]["ms_local_move"],
-                  "ms_aggregate": stats[-1]["ms_aggregate"], "ms_total": stats[-1]["ms_total"]},
+        "stats": {key: st_last[key] for key in ("iterations", "passes", "communities",
+                                                 "ms_local_move", "ms_refine", "ms_aggregate",
+                                                 "ms_total")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": names[dom],
                      "ms_per_launch": per_launch_ms, "bytes_per_launch": cb[dom],

@@ -11,6 +11,7 @@
 #include "move.hpp"
 #include "primitives.hpp"
 #include "sketch.hpp"
+#include "wave_sketch.hpp"
 
 namespace mgcd {
 
@@ -610,6 +611,70 @@ __global__ void __launch_bounds__(BLOCK)
 
 // ---- aggregation driver -----------------------------------------------------------------
 
+// K = 32 or 64: one wave per community holds a WaveSketch (slot p in lane p).  The
+// community's stream (members in ascending id, each row in CSR order) is loaded 64
+// entries at a time and folded in stream order; every L positions the chunk sketch
+// goes into the fixed merge tree.  The row is the positive slots sorted by key: each
+// lane's rank is the number of smaller keys, found by scanning the 64 lanes.
+template <int K, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_agg_wave(AggStreams s, const int32_t *__restrict__ comms, int64_t ncomm, int64_t L,
+               Pair *rows, uint32_t *rcount) {
+  __shared__ uint32_t sstack[BLOCK / WAVE][WDEPTH * 2 * WAVE];
+  const int lane = lane_id();
+  const int64_t r = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
+  if (r >= ncomm) return;
+  const int32_t c = comms[r];
+  WaveSketch<K, MODE> sk;
+  sk.reset();
+  WaveTree<K> tree{sstack[threadIdx.x / WAVE]};
+  int64_t left = L;  // positions left in the current chunk
+  const int32_t t1 = s.mstart[c + 1];
+  for (int32_t t = s.mstart[c]; t < t1; ++t) {
+    const int64_t rb = s.rs[t], len = s.P[t + 1] - s.P[t];
+    for (int64_t q0 = 0; q0 < len; q0 += WAVE) {
+      const int64_t q = q0 + lane;
+      const bool v = q < len;
+      const int32_t j = v ? __builtin_nontemporal_load(s.g.idx + rb + q) : 0;
+      const uint32_t w = v ? __builtin_nontemporal_load(s.g.w + rb + q) : 0u;
+      const uint32_t key = v ? (uint32_t)s.D[j] : EMPTY;
+      const int nb = len - q0 < WAVE ? (int)(len - q0) : WAVE;
+      for (int u = 0; u < nb; ++u) {
+        sk.update(lane_value(key, u), lane_value(w, u));
+        if (--left == 0) {  // end of a chunk
+          sk.finalize();
+          tree.push(sk.key, sk.val);
+          sk.reset();
+          left = L;
+        }
+      }
+    }
+  }
+  if (left != L) {  // the last, partial chunk
+    sk.finalize();
+    tree.push(sk.key, sk.val);
+  }
+  uint32_t ck, cv;
+  tree.result(ck, cv);
+  uint32_t rank = 0;
+  for (int u = 0; u < WAVE; ++u) rank += lane_value(ck, u) < ck ? 1u : 0u;
+  const uint64_t pos = __ballot(cv > 0);
+  if (cv > 0) rows[(int64_t)c * K + rank] = Pair{ck, cv};
+  if (lane == 0) rcount[c] = (uint32_t)__popcll(pos);
+}
+
+template <int K, int MODE>
+static void agg_wave(const AggStreams &s, const int32_t *comms, int64_t ncomm, int64_t L, Pair *rows,
+                     uint32_t *rcount, hipStream_t st) {
+  if (s.g.nnz / L >= (int64_t)1 << WDEPTH)
+    throw Error(-6, "streams of 2^31 chunks or more are not supported with k >= 32");
+  if (ncomm > 0) {
+    k_agg_wave<K, MODE><<<(unsigned)ceil_div(ncomm, BLOCK / WAVE), BLOCK, 0, st>>>(s, comms, ncomm, L,
+                                                                                  rows, rcount);
+    MGCD_LAUNCHED();
+  }
+}
+
 template <int K, int MODE>
 static void agg_mg(const AggStreams &s, const AggBuckets &bk, int64_t waves, const int32_t *multi,
                    int64_t nmulti, const int64_t *cstart, const int32_t *owner, int64_t nchunks,
@@ -629,14 +694,17 @@ static void agg_mg(const AggStreams &s, const AggBuckets &bk, int64_t waves, con
 template <int MODE>
 static void agg_mg_k(int k, const AggStreams &s, const AggBuckets &bk, int64_t waves, const int32_t *multi,
                      int64_t nmulti, const int64_t *cstart, const int32_t *owner, int64_t nchunks, int64_t L,
-                     Pair *skbuf, Pair *rows, uint32_t *rcount, hipStream_t st) {
+                     Pair *skbuf, Pair *rows, uint32_t *rcount, const int32_t *all, int64_t m,
+                     hipStream_t st) {
   switch (k) {
+    case 32: agg_wave<32, MODE>(s, all, m, L, rows, rcount, st); break;
+    case 64: agg_wave<64, MODE>(s, all, m, L, rows, rcount, st); break;
     case 1: agg_mg<1, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
     case 2: agg_mg<2, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
     case 4: agg_mg<4, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
     case 8: agg_mg<8, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
     case 16: agg_mg<16, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    default: throw Error(-6, "k_aggregate must be 1, 2, 4, 8 or 16");
+    default: throw Error(-6, "k_aggregate must be 1, 2, 4, 8, 16, 32 or 64");
   }
 }
 
@@ -771,9 +839,9 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   MGCD_LAUNCHED();
   AggStreams s{g, D, mem, mstart, P, rs};
   switch (mode) {
-    case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case MODE_STD: agg_mg_k<MODE_STD>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, st); break;
+    case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, st); break;
+    case MODE_STD: agg_mg_k<MODE_STD>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, st); break;
     default: throw Error(-6, "unknown sketch mode");
   }
   int64_t total = 0;
@@ -831,7 +899,7 @@ size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
   b += (size_t)(n + 1) * 16 + (size_t)chunks * (4 + (size_t)k * sizeof(Pair)) + 8192;
   b += (size_t)n * k * sizeof(Pair) + (size_t)n * 4 + 4096;  // rows, rcount
   // symmetric: emit buffers (<= 2 k n entries), sort, heads
-  int64_t e2 = 2 * (int64_t)n * k;
+  int64_t e2 = 2 * ((int64_t)n * k < nnz ? (int64_t)n * k : nnz);  // rows hold <= their stream
   b += (size_t)n * (4 + 8 + 4) + (size_t)e2 * (8 + 8 + 4 + 4 + 4 + 8) + 16384;
   b += radix_sort_ws_bytes(e2) + scan_ws_bytes(e2);
   return b + 64 * 1024;

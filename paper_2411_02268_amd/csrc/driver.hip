@@ -49,9 +49,9 @@ struct ClassTimer {
 static void check_params(const mgcd_params *p) {
   if (!p) throw Error(MGCD_E_ARG, "params is null");
   if (p->mode < 0 || p->mode > 3) throw Error(MGCD_E_UNSUPPORTED, "unknown sketch mode");
-  auto okk = [](int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16; };
+  auto okk = [](int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16 || k == 32 || k == 64; };
   if (p->mode != MGCD_MODE_EXACT && (!okk(p->k) || !okk(p->k_aggregate)))
-    throw Error(MGCD_E_UNSUPPORTED, "k and k_aggregate must be 1, 2, 4, 8 or 16");
+    throw Error(MGCD_E_UNSUPPORTED, "k and k_aggregate must be 1, 2, 4, 8, 16, 32 or 64");
   if (p->chunk_len < 1) throw Error(MGCD_E_ARG, "chunk_len must be >= 1");
   if (p->max_iterations < 1 || p->max_passes < 1) throw Error(MGCD_E_ARG, "iteration limits must be >= 1");
   if (!(p->tolerance >= 0.0) || !(p->tolerance_drop > 0.0) || !(p->aggregation_tolerance >= 0.0))

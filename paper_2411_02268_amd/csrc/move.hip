@@ -23,6 +23,7 @@
 #include "move.hpp"
 #include "primitives.hpp"
 #include "sketch.hpp"
+#include "wave_sketch.hpp"
 
 namespace mgcd {
 
@@ -613,6 +614,110 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
   flush_counters(a, ct);
 }
 
+// ---- MG with K = 32 or 64: one wave per row -------------------------------------------
+
+// Rows longer than 32 entries when K is 32 or 64 (shorter rows cannot lose weight
+// under Algorithm 1 or the textbook rule and take the exact one-lane kernel).  One
+// wave per row holds a WaveSketch (slot p in lane p).  Pass 1: the row is loaded 64
+// entries at a time (coalesced index and weight loads, 64 label gathers in flight,
+// keys written to the key stream) and folded in stream order, one wave-uniform item
+// at a time; every L positions the chunk sketch goes into the fixed merge tree
+// (WaveTree).  Pass 2 (lossy rows only): the key stream again, each item added to the
+// lane whose candidate matches.  Decision: every lane scores its candidate, a
+// butterfly keeps the best (lowest id on ties), lane 0 records it.
+template <int K, int ALGO, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_wave_rows(SweepArgs a, const int32_t *__restrict__ rows, int64_t nrows, int64_t L,
+                uint32_t *keybuf) {
+  __shared__ uint32_t sstack[BLOCK / WAVE][WDEPTH * 2 * WAVE];
+  const int lane = lane_id();
+  const int64_t r = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
+  Counters ct;
+  const bool listed = r < nrows;
+  const int32_t i = listed ? rows[r] : 0;
+  const bool valid = listed && !frozen(a, i);
+  if (listed && !valid && lane == 0) a.Cnew[i] = community_of_self<ALGO>(a, i);
+  if (valid) {
+    const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
+    const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
+    const int32_t d = community_of_self<ALGO>(a, i);
+    WaveSketch<K, MODE> s;
+    s.reset();
+    WaveTree<K> tree{sstack[threadIdx.x / WAVE]};
+    bool lossy = false;
+    int64_t left = L;  // positions left in the current chunk
+    for (int64_t e0 = lo; e0 < hi; e0 += WAVE) {
+      const int64_t e = e0 + lane;
+      const bool v = e < hi;
+      const int32_t j = v ? __builtin_nontemporal_load(a.g.idx + e) : 0;
+      const uint32_t w = v ? __builtin_nontemporal_load(a.g.w + e) : 0u;
+      uint32_t key = EMPTY;
+      if (v) {
+        key = stream_key<ALGO>(a, i, j, bi);
+        keybuf[e] = key;
+      }
+      const int nb = hi - e0 < WAVE ? (int)(hi - e0) : WAVE;
+      for (int t = 0; t < nb; ++t) {
+        const uint32_t c = lane_value(key, t);
+        if (c != EMPTY) s.update(c, lane_value(w, t));
+        if (--left == 0) {  // end of a chunk
+          lossy |= s.lossy;
+          s.finalize();
+          tree.push(s.key, s.val);
+          s.reset();
+          left = L;
+        }
+      }
+    }
+    if (left != L) {  // the last, partial chunk
+      lossy |= s.lossy;
+      s.finalize();
+      tree.push(s.key, s.val);
+    }
+    uint32_t ck, cv;
+    tree.result(ck, cv);
+    lossy |= tree.lossy;
+    uint32_t kd = 0;
+    if (!lossy) {
+      kd = wave_sum(ck == (uint32_t)d ? cv : 0u);
+    } else {
+      cv = 0;
+      for (int64_t e0 = lo; e0 < hi; e0 += WAVE) {
+        const int64_t e = e0 + lane;
+        const bool v = e < hi;
+        const uint32_t key = v ? __builtin_nontemporal_load(keybuf + e) : EMPTY;
+        const uint32_t w = v ? __builtin_nontemporal_load(a.g.w + e) : 0u;
+        kd += key == (uint32_t)d ? w : 0u;
+        const int nb = hi - e0 < WAVE ? (int)(hi - e0) : WAVE;
+        for (int t = 0; t < nb; ++t) {
+          const uint32_t c = lane_value(key, t);
+          if (c != EMPTY && ck == c) cv += lane_value(w, t);
+        }
+      }
+      kd = wave_sum(kd);
+    }
+    int32_t best = -1;
+    int64_t bestG = 0;
+    if (ck != EMPTY) {
+      const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
+      const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+      const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+      consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)ck, cv, best, bestG);
+    }
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const int32_t b2 = __shfl_xor(best, o);
+      const int64_t g2 = __shfl_xor(bestG, o);
+      if (b2 >= 0 && (best < 0 || g2 > bestG || (g2 == bestG && b2 < best))) {
+        best = b2;
+        bestG = g2;
+      }
+    }
+    if (lane == 0) finish<ALGO>(a, i, d, best, bestG, ct);
+  }
+  flush_counters(a, ct);
+}
+
 // ---- exact mode ----------------------------------------------------------------------
 
 // Exact mode, the shortest rows (tier 0): one lane per vertex; K_{i->c} of each distinct
@@ -788,6 +893,9 @@ __global__ void __launch_bounds__(BLOCK)
     if (mode == MODE_EXACT) {
       cat = deg <= sp.exact_t0 ? 0 : deg <= sp.exact_t1 ? 1 : deg <= sp.exact_t2 ? 2 : 3;
       k = cat == 0 ? (uint64_t)(64 - b) : (uint64_t)(128 + cat);
+    } else if (sp.wave) {  // K = 32 / 64: short rows exact, the rest one wave each
+      cat = deg <= sp.exact_t0 ? 0 : 1;
+      k = (uint64_t)(cat * 64 + 64 - b);  // heavy rows first in each tier
     } else if (deg <= L) {
       cat = 0;
       k = (uint64_t)(64 - b);  // heavy rows first
@@ -887,6 +995,14 @@ void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a
   unsigned long long h[NCAT];
   MGCD_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
   MGCD_HIP(hipStreamSynchronize(st));
+  if (sp.wave) {
+    s.tier[0] = order;
+    s.ntier[0] = (int64_t)h[0];
+    s.tier[1] = order + h[0];
+    s.ntier[1] = (int64_t)h[1];
+    s.keybuf = a.take<uint32_t>(g.nnz);
+    return;
+  }
   if (mode == MODE_EXACT) {
     int64_t pos = 0;
     for (int q = 0; q < 4; ++q) {
@@ -1028,16 +1144,37 @@ static void sweep_exact(const SweepArgs &a, const Schedule &s, hipStream_t st, h
   mark(ev, 3, st);
 }
 
+template <int K, int ALGO, int MODE>
+static void sweep_wave(const SweepArgs &a, const Schedule &s, int64_t L, hipStream_t st, hipEvent_t *ev) {
+  mark(ev, 0, st);
+  if (s.ntier[0] > 0) {  // rows that cannot lose weight: the exact one-lane kernel
+    k_exact_small<ALGO><<<grid_for(s.ntier[0]), BLOCK, 0, st>>>(a, s.tier[0], s.ntier[0]);
+    MGCD_LAUNCHED();
+  }
+  mark(ev, 1, st);
+  if (a.g.nnz / L >= (int64_t)1 << WDEPTH)
+    throw Error(-6, "rows of 2^31 chunks or more are not supported with k >= 32");
+  if (s.ntier[1] > 0) {
+    k_wave_rows<K, ALGO, MODE><<<(unsigned)ceil_div(s.ntier[1], BLOCK / WAVE), BLOCK, 0, st>>>(
+        a, s.tier[1], s.ntier[1], L, s.keybuf);
+    MGCD_LAUNCHED();
+  }
+  mark(ev, 2, st);
+  mark(ev, 3, st);
+}
+
 template <int ALGO, int MODE>
 static void sweep_k(const SweepArgs &a, const Schedule &s, int k, int64_t L, hipStream_t st,
                     hipEvent_t *ev) {
   switch (k) {
+    case 32: sweep_wave<32, ALGO, MODE>(a, s, L, st, ev); break;
+    case 64: sweep_wave<64, ALGO, MODE>(a, s, L, st, ev); break;
     case 1: sweep_mg<1, ALGO, MODE>(a, s, L, st, ev); break;
     case 2: sweep_mg<2, ALGO, MODE>(a, s, L, st, ev); break;
     case 4: sweep_mg<4, ALGO, MODE>(a, s, L, st, ev); break;
     case 8: sweep_mg<8, ALGO, MODE>(a, s, L, st, ev); break;
     case 16: sweep_mg<16, ALGO, MODE>(a, s, L, st, ev); break;
-    default: throw Error(-6, "k must be 1, 2, 4, 8 or 16");
+    default: throw Error(-6, "k must be 1, 2, 4, 8, 16, 32 or 64");
   }
 }
 

@@ -86,6 +86,8 @@ struct SchedParams {
   int64_t L = 128;
   int row_lanes_log2 = 6;
   int64_t exact_t0 = 32, exact_t1 = 512, exact_t2 = 4096;
+  bool wave = false;  // K = 32 / 64: rows of at most exact_t0 entries exact, the rest one
+                      // wave each
 };
 constexpr int64_t EXACT_T1_MAX = 512, EXACT_T2_MAX = 4096;
 
@@ -107,6 +109,13 @@ inline SchedParams sched_params(const mgcd_params *p) {
   if (p->exact_lds_big > 0) sp.exact_t2 = p->exact_lds_big;
   if (sp.exact_t1 < sp.exact_t0) sp.exact_t1 = sp.exact_t0;
   if (sp.exact_t2 < sp.exact_t1) sp.exact_t2 = sp.exact_t1;
+  if (p->mode != MGCD_MODE_EXACT && p->k > 16) {
+    // a stream of at most 32 items cannot lose weight in a sketch of >= 32 slots under
+    // Algorithm 1 or the textbook rule (a free slot is always left); the unconditional
+    // rule subtracts on every miss, so it takes the sketch for every row
+    sp.wave = true;
+    sp.exact_t0 = p->mode == MGCD_MODE_UNCOND ? 0 : 32;
+  }
   return sp;
 }
 size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L);

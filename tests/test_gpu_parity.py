@@ -60,7 +60,8 @@ def graph(name):
 @pytest.mark.parametrize("gname", ["er200", "er120dense", "rmat11", "cl12"])
 @pytest.mark.parametrize("mode", ["exact", "alg1", "uncond", "std"])
 # L = 1 and 2 give rows of several aligned groups of 64 chunks on the R-MAT graph
-@pytest.mark.parametrize("k,L", [(1, 128), (4, 7), (8, 128), (8, 16), (16, 5), (8, 2), (4, 1)])
+@pytest.mark.parametrize("k,L", [(1, 128), (4, 7), (8, 128), (8, 16), (16, 5), (8, 2), (4, 1),
+                                 (32, 128), (64, 16), (64, 3), (32, 1)])
 def test_sweep_parity(mg, gname, mode, k, L):
     g = graph(gname)
     dg = mg.to_device(g)
@@ -82,7 +83,8 @@ def test_sweep_parity(mg, gname, mode, k, L):
 
 @pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12"])
 @pytest.mark.parametrize("mode,k,L", [("exact", 8, 128), ("alg1", 2, 9), ("alg1", 16, 128),
-                                      ("std", 4, 6)])
+                                      ("std", 4, 6), ("alg1", 64, 128), ("std", 32, 7),
+                                      ("uncond", 64, 20)])
 def test_refine_parity(mg, gname, mode, k, L):
     g = graph(gname)
     dg = mg.to_device(g)
@@ -95,7 +97,9 @@ def test_refine_parity(mg, gname, mode, k, L):
 
 @pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12", "planted"])
 @pytest.mark.parametrize("mode,k,L", [("exact", 8, 128), ("alg1", 1, 128), ("alg1", 4, 11),
-                                      ("alg1", 8, 128), ("alg1", 16, 40), ("uncond", 8, 64)])
+                                      ("alg1", 8, 128), ("alg1", 16, 40), ("uncond", 8, 64),
+                                      ("alg1", 64, 128), ("alg1", 32, 5), ("std", 64, 9),
+                                      ("uncond", 32, 64)])
 @pytest.mark.parametrize("symmetric", [False, True])
 def test_aggregate_parity(mg, gname, mode, k, L, symmetric):
     g = graph(gname)
@@ -122,6 +126,8 @@ RUNS = [
     ("louvain", "uncond", 4, 128), ("louvain", "std", 8, 32), ("louvain", "alg1", 1, 128),
     ("leiden", "exact", 16, 128), ("leiden", "alg1", 16, 128), ("leiden", "alg1", 8, 10),
     ("leiden", "std", 4, 128),
+    ("leiden", "alg1", 64, 128), ("louvain", "alg1", 32, 16), ("lpa", "alg1", 64, 5),
+    ("leiden", "uncond", 32, 128), ("louvain", "std", 64, 128),
 ]
 
 
@@ -254,7 +260,8 @@ def _batch_graphs():
 
 
 @pytest.mark.parametrize("algo", ["lpa", "louvain"])
-@pytest.mark.parametrize("mode,k,L", [("alg1", 8, 128), ("alg1", 4, 16), ("exact", 8, 128)])
+@pytest.mark.parametrize("mode,k,L", [("alg1", 8, 128), ("alg1", 4, 16), ("exact", 8, 128),
+                                      ("alg1", 32, 16), ("alg1", 64, 128)])
 def test_batched_equals_solo(mg, algo, mode, k, L):
     gs = _batch_graphs()
     dgs = [mg.to_device(g) for g in gs]

@@ -214,6 +214,12 @@ WORKLOADS = {
     "leiden-mg-k16-cl24": (
         "leiden", 16, "Chung-Lu 2^24 vertices, mean degree 32, exponent 2.1, weights U[1,4], seed 3",
         lambda synth: synth.chung_lu(n=1 << 24, avg_deg=32, seed=3)),
+    "leiden-mg-k64-cl24": (
+        "leiden", 64, "Chung-Lu 2^24 vertices, mean degree 32, exponent 2.1, weights U[1,4], seed 3",
+        lambda synth: synth.chung_lu(n=1 << 24, avg_deg=32, seed=3)),
+    "louvain-mg-k64-rmat20": (
+        "louvain", 64, "R-MAT scale 20, edge factor 16, a/b/c=0.57/0.19/0.19, weights U[1,8], seed 2",
+        lambda synth: synth.rmat(scale=20, edge_factor=16, seed=2)),
     "lpa-mg-k8-planted": (
         "lpa", 8, "planted partition 20 x 500, 12 intra + 4 inter edges per vertex, weight 1, seed 1",
         lambda synth: synth.planted_exact(n_comm=20, comm_size=500, seed=1)[0]),

@@ -622,16 +622,16 @@ __global__ void __launch_bounds__(BLOCK)
                Pair *rows, uint32_t *rcount) {
   __shared__ uint32_t sstack[BLOCK / WAVE][WDEPTH * 2 * WAVE];
   const int lane = lane_id();
-  const int64_t r = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
+  const int64_t r = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
   if (r >= ncomm) return;
-  const int32_t c = comms[r];
+  const int32_t c = uniform(comms[r]);
   WaveSketch<K, MODE> sk;
   sk.reset();
   WaveTree<K> tree{sstack[threadIdx.x / WAVE]};
   int64_t left = L;  // positions left in the current chunk
-  const int32_t t1 = s.mstart[c + 1];
-  for (int32_t t = s.mstart[c]; t < t1; ++t) {
-    const int64_t rb = s.rs[t], len = s.P[t + 1] - s.P[t];
+  const int32_t t1 = uniform(s.mstart[c + 1]);
+  for (int32_t t = uniform(s.mstart[c]); t < t1; ++t) {
+    const int64_t rb = uniform(s.rs[t]), len = uniform(s.P[t + 1] - s.P[t]);
     for (int64_t q0 = 0; q0 < len; q0 += WAVE) {
       const int64_t q = q0 + lane;
       const bool v = q < len;

@@ -105,6 +105,19 @@ struct Timer {
 // ---- wave helpers (device) -------------------------------------------------------
 __device__ inline int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
 
+// A value that is the same in every lane, moved to a scalar register so that the
+// compiler treats what depends on it as wave-uniform (scalar branches and loops).
+__device__ inline int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint32_t uniform(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)v);
+}
+__device__ inline int64_t uniform(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ inline uint64_t lanemask_lt() {
   int l = lane_id();
   return l == 0 ? 0ull : ((~0ull) >> (64 - l));

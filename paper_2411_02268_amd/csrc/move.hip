@@ -631,16 +631,16 @@ __global__ void __launch_bounds__(BLOCK)
                 uint32_t *keybuf) {
   __shared__ uint32_t sstack[BLOCK / WAVE][WDEPTH * 2 * WAVE];
   const int lane = lane_id();
-  const int64_t r = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
+  const int64_t r = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
   Counters ct;
   const bool listed = r < nrows;
-  const int32_t i = listed ? rows[r] : 0;
+  const int32_t i = listed ? uniform(rows[r]) : 0;
   const bool valid = listed && !frozen(a, i);
   if (listed && !valid && lane == 0) a.Cnew[i] = community_of_self<ALGO>(a, i);
   if (valid) {
-    const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
-    const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
-    const int32_t d = community_of_self<ALGO>(a, i);
+    const int64_t lo = uniform(a.g.off[i]), hi = uniform(a.g.off[i + 1]);
+    const int32_t bi = ALGO == ALGO_REFINE ? uniform(a.bound[i]) : 0;
+    const int32_t d = uniform(community_of_self<ALGO>(a, i));
     WaveSketch<K, MODE> s;
     s.reset();
     WaveTree<K> tree{sstack[threadIdx.x / WAVE]};
@@ -720,27 +720,78 @@ __global__ void __launch_bounds__(BLOCK)
 
 // ---- exact mode ----------------------------------------------------------------------
 
-// Exact mode, the shortest rows (tier 0): one lane per vertex; K_{i->c} of each distinct
-// key, summed at its first occurrence in the row.
+// A row of at most ES entries: keys and weights gathered once into registers, then
+// every distinct key summed at its first occurrence (static indices, unrolled).
+template <int ALGO, int ES>
+__device__ inline void exact_row_regs(const SweepArgs &a, int32_t i, int32_t bi, int64_t lo,
+                                      int64_t hi, int32_t d, Counters &ct) {
+  uint32_t ks[ES], ws[ES];
+#pragma unroll
+  for (int t = 0; t < ES; ++t) {
+    const bool v = lo + t < hi;
+    const int32_t j = v ? a.g.idx[lo + t] : 0;
+    ws[t] = v ? a.g.w[lo + t] : 0u;
+    ks[t] = v ? stream_key<ALGO>(a, i, j, bi) : EMPTY;
+  }
+  uint32_t kd = 0;
+#pragma unroll
+  for (int t = 0; t < ES; ++t) kd += ks[t] == (uint32_t)d ? ws[t] : 0u;
+  int32_t best = -1;
+  int64_t bestG = 0;
+  const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
+  const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+  const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+#pragma unroll
+  for (int t = 0; t < ES; ++t) {
+    const uint32_t c = ks[t];
+    bool first = c != EMPTY;
+#pragma unroll
+    for (int u = 0; u < t; ++u) first &= ks[u] != c;
+    uint32_t kc = 0;
+#pragma unroll
+    for (int u = t; u < ES; ++u) kc += ks[u] == c ? ws[u] : 0u;
+    if (first) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)c, kc, best, bestG);
+  }
+  finish<ALGO>(a, i, d, best, bestG, ct);
+}
+
+// Exact mode, the shortest rows (tier 0): one lane per vertex; K_{i->c} of each
+// distinct key, summed at its first occurrence in the row.  Rows of at most 32
+// entries keep the row in registers (the unroll depth follows the longest row of
+// the wave); longer tier-0 rows (a raised exact_small) re-read the row.
 template <int ALGO>
 __global__ void __launch_bounds__(BLOCK)
     k_exact_small(SweepArgs a, const int32_t *__restrict__ list, int64_t count) {
   Counters ct;
   int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (t < count && frozen(a, list[t])) {
-    a.Cnew[list[t]] = community_of_self<ALGO>(a, list[t]);
-  } else if (t < count) {
-    const int32_t i = list[t];
-    const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
-    const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
-    const int32_t d = community_of_self<ALGO>(a, i);
+  const bool listed = t < count;
+  const int32_t i = listed ? list[t] : 0;
+  const bool live = listed && !frozen(a, i);
+  if (listed && !live) a.Cnew[i] = community_of_self<ALGO>(a, i);
+  const int64_t lo = live ? a.g.off[i] : 0, hi = live ? a.g.off[i + 1] : 0;
+  int64_t maxdeg = hi - lo;
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int64_t x = __shfl_xor(maxdeg, o);
+    maxdeg = x > maxdeg ? x : maxdeg;
+  }
+  maxdeg = uniform(maxdeg);
+  const int32_t bi = (ALGO == ALGO_REFINE && live) ? a.bound[i] : 0;
+  const int32_t d = live ? community_of_self<ALGO>(a, i) : 0;
+  if (maxdeg <= 8) {
+    if (live) exact_row_regs<ALGO, 8>(a, i, bi, lo, hi, d, ct);
+  } else if (maxdeg <= 16) {
+    if (live) exact_row_regs<ALGO, 16>(a, i, bi, lo, hi, d, ct);
+  } else if (maxdeg <= 32) {
+    if (live) exact_row_regs<ALGO, 32>(a, i, bi, lo, hi, d, ct);
+  } else if (live) {
     uint32_t kd = 0;
     for (int64_t e = lo; e < hi; ++e)
       kd += stream_key<ALGO>(a, i, a.g.idx[e], bi) == (uint32_t)d ? a.g.w[e] : 0u;
     int32_t best = -1;
     int64_t bestG = 0;
     const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
-  const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+    const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
     const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
     for (int64_t e = lo; e < hi; ++e) {
       uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);

@@ -309,8 +309,10 @@ __global__ void __launch_bounds__(BLOCK)
   __syncthreads();
   int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   int cat = -1;
+  int64_t lmax = 0;
   if (c < m) {
     int64_t len = P[mstart[c + 1]] - P[mstart[c]];
+    lmax = len;
     if (len <= L) {
       int b = 0;
       while (b < 63 && (len >> b) != 0) ++b;
@@ -331,6 +333,12 @@ __global__ void __launch_bounds__(BLOCK)
   }
   __syncthreads();
   if (threadIdx.x < 8 && bc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], bc[threadIdx.x]);
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int64_t x = __shfl_xor(lmax, o);
+    lmax = x > lmax ? x : lmax;
+  }
+  if (lane_id() == 0 && lmax > 0) atomicMax(&cnt[8], (unsigned long long)lmax);  // longest stream
 }
 
 __global__ void k_comm_chunks(const int32_t *mstart, const int64_t *P, const int32_t *multi,
@@ -616,18 +624,18 @@ __global__ void __launch_bounds__(BLOCK)
 // entries at a time and folded in stream order; every L positions the chunk sketch
 // goes into the fixed merge tree.  The row is the positive slots sorted by key: each
 // lane's rank is the number of smaller keys, found by scanning the 64 lanes.
-template <int K, int MODE>
+template <int K, int MODE, int DEPTH>
 __global__ void __launch_bounds__(BLOCK)
     k_agg_wave(AggStreams s, const int32_t *__restrict__ comms, int64_t ncomm, int64_t L,
                Pair *rows, uint32_t *rcount) {
-  __shared__ uint32_t sstack[BLOCK / WAVE][WDEPTH * 2 * WAVE];
+  __shared__ uint32_t sstack[BLOCK / WAVE][DEPTH * 2 * WAVE];
   const int lane = lane_id();
   const int64_t r = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
   if (r >= ncomm) return;
   const int32_t c = uniform(comms[r]);
   WaveSketch<K, MODE> sk;
   sk.reset();
-  WaveTree<K> tree{sstack[threadIdx.x / WAVE]};
+  WaveTree<K, DEPTH> tree{sstack[threadIdx.x / WAVE]};
   int64_t left = L;  // positions left in the current chunk
   const int32_t t1 = uniform(s.mstart[c + 1]);
   for (int32_t t = uniform(s.mstart[c]); t < t1; ++t) {
@@ -665,12 +673,13 @@ __global__ void __launch_bounds__(BLOCK)
 
 template <int K, int MODE>
 static void agg_wave(const AggStreams &s, const int32_t *comms, int64_t ncomm, int64_t L, Pair *rows,
-                     uint32_t *rcount, hipStream_t st) {
-  if (s.g.nnz / L >= (int64_t)1 << WDEPTH)
-    throw Error(-6, "streams of 2^31 chunks or more are not supported with k >= 32");
+                     uint32_t *rcount, int64_t max_len, hipStream_t st) {
   if (ncomm > 0) {
-    k_agg_wave<K, MODE><<<(unsigned)ceil_div(ncomm, BLOCK / WAVE), BLOCK, 0, st>>>(s, comms, ncomm, L,
-                                                                                  rows, rcount);
+    const unsigned grid = (unsigned)ceil_div(ncomm, BLOCK / WAVE);
+    if (wave_depth_for(max_len, L) == WDEPTH_SHALLOW)
+      k_agg_wave<K, MODE, WDEPTH_SHALLOW><<<grid, BLOCK, 0, st>>>(s, comms, ncomm, L, rows, rcount);
+    else
+      k_agg_wave<K, MODE, WDEPTH><<<grid, BLOCK, 0, st>>>(s, comms, ncomm, L, rows, rcount);
     MGCD_LAUNCHED();
   }
 }
@@ -695,10 +704,10 @@ template <int MODE>
 static void agg_mg_k(int k, const AggStreams &s, const AggBuckets &bk, int64_t waves, const int32_t *multi,
                      int64_t nmulti, const int64_t *cstart, const int32_t *owner, int64_t nchunks, int64_t L,
                      Pair *skbuf, Pair *rows, uint32_t *rcount, const int32_t *all, int64_t m,
-                     hipStream_t st) {
+                     int64_t max_len, hipStream_t st) {
   switch (k) {
-    case 32: agg_wave<32, MODE>(s, all, m, L, rows, rcount, st); break;
-    case 64: agg_wave<64, MODE>(s, all, m, L, rows, rcount, st); break;
+    case 32: agg_wave<32, MODE>(s, all, m, L, rows, rcount, max_len, st); break;
+    case 64: agg_wave<64, MODE>(s, all, m, L, rows, rcount, max_len, st); break;
     case 1: agg_mg<1, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
     case 2: agg_mg<2, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
     case 4: agg_mg<4, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
@@ -788,8 +797,8 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   MGCD_LAUNCHED();
   scan_u32_i64(mdeg, P, n, P + n, a, st);
   // communities: short streams (one lane each) vs long ones (chunks + merge tree)
-  unsigned long long *cnt = a.take<unsigned long long>(8);
-  launch_zero_u64(cnt, 8, st);
+  unsigned long long *cnt = a.take<unsigned long long>(9);
+  launch_zero_u64(cnt, 9, st);
   uint64_t *ck0 = a.take<uint64_t>(m), *ck1 = a.take<uint64_t>(m);
   uint32_t *cv0 = a.take<uint32_t>(m), *cv1 = a.take<uint32_t>(m);
   k_comm_keys<<<grid_for(m), BLOCK, 0, st>>>(mstart, P, m, L, ck0, cv0, cnt);
@@ -798,7 +807,7 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   int32_t *corder = a.take<int32_t>(m);
   k_u32_to_i32<<<grid_for(m), BLOCK, 0, st>>>(cf ? cv1 : cv0, corder, m);
   MGCD_LAUNCHED();
-  unsigned long long hc[8];
+  unsigned long long hc[9];
   MGCD_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
   MGCD_HIP(hipStreamSynchronize(st));
   AggBuckets bk{};
@@ -839,9 +848,9 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   MGCD_LAUNCHED();
   AggStreams s{g, D, mem, mstart, P, rs};
   switch (mode) {
-    case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, st); break;
-    case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, st); break;
-    case MODE_STD: agg_mg_k<MODE_STD>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, st); break;
+    case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, (int64_t)hc[8], st); break;
+    case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, (int64_t)hc[8], st); break;
+    case MODE_STD: agg_mg_k<MODE_STD>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, (int64_t)hc[8], st); break;
     default: throw Error(-6, "unknown sketch mode");
   }
   int64_t total = 0;

@@ -625,11 +625,11 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
 // (WaveTree).  Pass 2 (lossy rows only): the key stream again, each item added to the
 // lane whose candidate matches.  Decision: every lane scores its candidate, a
 // butterfly keeps the best (lowest id on ties), lane 0 records it.
-template <int K, int ALGO, int MODE>
+template <int K, int ALGO, int MODE, int DEPTH>
 __global__ void __launch_bounds__(BLOCK)
     k_wave_rows(SweepArgs a, const int32_t *__restrict__ rows, int64_t nrows, int64_t L,
                 uint32_t *keybuf) {
-  __shared__ uint32_t sstack[BLOCK / WAVE][WDEPTH * 2 * WAVE];
+  __shared__ uint32_t sstack[BLOCK / WAVE][DEPTH * 2 * WAVE];
   const int lane = lane_id();
   const int64_t r = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
   Counters ct;
@@ -643,7 +643,7 @@ __global__ void __launch_bounds__(BLOCK)
     const int32_t d = uniform(community_of_self<ALGO>(a, i));
     WaveSketch<K, MODE> s;
     s.reset();
-    WaveTree<K> tree{sstack[threadIdx.x / WAVE]};
+    WaveTree<K, DEPTH> tree{sstack[threadIdx.x / WAVE]};
     bool lossy = false;
     int64_t left = L;  // positions left in the current chunk
     for (int64_t e0 = lo; e0 < hi; e0 += WAVE) {
@@ -936,8 +936,10 @@ __global__ void __launch_bounds__(BLOCK)
   __syncthreads();
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   int cat = -1;
+  int64_t dmax = 0;
   if (i < n) {
     int64_t deg = off[i + 1] - off[i];
+    dmax = deg;
     int b = 0;
     while (b < 63 && (deg >> b) != 0) ++b;  // bits of deg
     uint64_t k;
@@ -967,6 +969,12 @@ __global__ void __launch_bounds__(BLOCK)
   }
   __syncthreads();
   if (threadIdx.x < NCAT && bc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], bc[threadIdx.x]);
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int64_t x = __shfl_xor(dmax, o);
+    dmax = x > dmax ? x : dmax;
+  }
+  if (lane_id() == 0 && dmax > 0) atomicMax(&cnt[NCAT], (unsigned long long)dmax);  // longest row
 }
 
 __global__ void k_chunk_counts(const int64_t *off, const int32_t *multi, int64_t nmulti, int64_t L,
@@ -1031,21 +1039,22 @@ void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a
   const int32_t n = g.n;
   s = Schedule{};
   if (n == 0) return;
-  unsigned long long *cnt = a.take<unsigned long long>(NCAT);
+  unsigned long long *cnt = a.take<unsigned long long>(NCAT + 1);
   uint64_t *k0 = a.take<uint64_t>(n);
   uint32_t *v0 = a.take<uint32_t>(n);
   uint64_t *k1 = a.take<uint64_t>(n);
   uint32_t *v1 = a.take<uint32_t>(n);
   int32_t *order = a.take<int32_t>(n);
-  launch_zero_u64(cnt, NCAT, st);
+  launch_zero_u64(cnt, NCAT + 1, st);
   k_schedule_keys<<<grid_for(n), BLOCK, 0, st>>>(g.off, n, sp, k0, v0, cnt);
   MGCD_LAUNCHED();
   bool flip = radix_sort_pairs(k0, v0, k1, v1, n, 8, a, st);
   k_u32_from_u64<<<grid_for(n), BLOCK, 0, st>>>(flip ? v1 : v0, order, n);
   MGCD_LAUNCHED();
-  unsigned long long h[NCAT];
+  unsigned long long h[NCAT + 1];
   MGCD_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
   MGCD_HIP(hipStreamSynchronize(st));
+  s.maxdeg = (int64_t)h[NCAT];
   if (sp.wave) {
     s.tier[0] = order;
     s.ntier[0] = (int64_t)h[0];
@@ -1203,11 +1212,13 @@ static void sweep_wave(const SweepArgs &a, const Schedule &s, int64_t L, hipStre
     MGCD_LAUNCHED();
   }
   mark(ev, 1, st);
-  if (a.g.nnz / L >= (int64_t)1 << WDEPTH)
-    throw Error(-6, "rows of 2^31 chunks or more are not supported with k >= 32");
   if (s.ntier[1] > 0) {
-    k_wave_rows<K, ALGO, MODE><<<(unsigned)ceil_div(s.ntier[1], BLOCK / WAVE), BLOCK, 0, st>>>(
-        a, s.tier[1], s.ntier[1], L, s.keybuf);
+    const unsigned grid = (unsigned)ceil_div(s.ntier[1], BLOCK / WAVE);
+    if (wave_depth_for(s.maxdeg, L) == WDEPTH_SHALLOW)
+      k_wave_rows<K, ALGO, MODE, WDEPTH_SHALLOW><<<grid, BLOCK, 0, st>>>(a, s.tier[1], s.ntier[1], L,
+                                                                         s.keybuf);
+    else
+      k_wave_rows<K, ALGO, MODE, WDEPTH><<<grid, BLOCK, 0, st>>>(a, s.tier[1], s.ntier[1], L, s.keybuf);
     MGCD_LAUNCHED();
   }
   mark(ev, 2, st);

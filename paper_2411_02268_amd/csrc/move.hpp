@@ -55,6 +55,7 @@ struct Schedule {
   int64_t *cstart = nullptr;  // [nmulti+1] first chunk of each multi vertex
   int32_t *owner = nullptr;   // [nchunks] multi index of each chunk
   int64_t nchunks = 0;
+  int64_t maxdeg = 0;          // longest row
   Buckets *buckets = nullptr; // device copy of the bucket table
   int64_t row_waves = 0;
   uint32_t *keybuf = nullptr; // [nnz] keys C[j] gathered in pass 1, read by pass 2

@@ -151,16 +151,22 @@ __device__ inline bool wave_merge(uint32_t &ak, uint32_t &av, uint32_t bk, uint3
 }
 
 // The fixed merge tree over a stream's chunk sketches, kept as a binary counter:
-// level l of `stack` (LDS, WDEPTH levels of 2 x 64 words) holds the merged sketch of
+// level l of `stack` (LDS, DEPTH levels of 2 x 64 words) holds the merged sketch of
 // the last complete aligned run of 2^l chunks.  push() merges a finished chunk
 // sketch in (left operand = the older run); result() merges the pending runs from
 // the right, which is the order of the level-by-level tree with an odd last node
-// carried up.
-constexpr int WDEPTH = 31;
+// carried up.  A stream of fewer than 2^DEPTH chunks fits.
+constexpr int WDEPTH_SHALLOW = 12, WDEPTH = 31;
 
-template <int K>
+// Stack depth for streams of at most max_len positions cut into chunks of L.
+inline int wave_depth_for(int64_t max_len, int64_t L) {
+  const int64_t chunks = (max_len + L - 1) / L;
+  return chunks < ((int64_t)1 << WDEPTH_SHALLOW) ? WDEPTH_SHALLOW : WDEPTH;
+}
+
+template <int K, int DEPTH>
 struct WaveTree {
-  uint32_t *stack;  // this wave's LDS: WDEPTH * 2 * WAVE words
+  uint32_t *stack;  // this wave's LDS: DEPTH * 2 * WAVE words
   uint32_t mask = 0;  // occupied levels (wave-uniform)
   bool lossy = false;
 
@@ -193,7 +199,7 @@ struct WaveTree {
     k = EMPTY;
     v = 0;
     bool have = false;
-    for (int l = 0; l < WDEPTH; ++l) {
+    for (int l = 0; l < DEPTH; ++l) {
       if (!((mask >> l) & 1u)) continue;
       uint32_t lk, lv;
       get(l, lk, lv);

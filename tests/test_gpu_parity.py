@@ -279,3 +279,26 @@ def test_batched_equals_solo(mg, algo, mode, k, L):
         assert st["edges_scanned"] == sst["edges_scanned"]
         elab, est = getattr(oracle, algo)(g, **kw)
         assert np.array_equal(_np(lab), elab)
+
+
+@pytest.mark.parametrize("k", [32, 64])
+def test_wave_sketch_deep_merge_tree(mg, k):
+    """A hub row of 6,000 entries with L = 1 needs a merge tree of more than 4,096
+    chunk sketches (the deep stack); its sweep and aggregation match the oracle."""
+    rng = np.random.default_rng(31)
+    n = 6001
+    edges = [(0, v) for v in range(1, n)]
+    edges += [(int(u), int(v)) for u, v in rng.integers(1, n, size=(3000, 2)) if u != v]
+    w = rng.integers(1, 9, size=len(edges)).astype(np.uint32)
+    g = synth.from_edges(n, edges, w)
+    dg = mg.to_device(g)
+    C = rng.integers(0, 300, size=n).astype(np.int32)
+    for algo, oalgo in ((mg.ALGO_LPA, oracle.ALGO_LPA), (mg.ALGO_LOUVAIN, oracle.ALGO_MOVE)):
+        Cn, gain, _ = mg.move_sweep(dg, algo, _t(C), 0, mode=mg.MODE_ALG1, k=k, chunk_len=1)
+        eC, eg = oracle.move_sweep(g, oalgo, C, mode=oracle.MODE_ALG1, k=k, chunk_len=1)
+        assert np.array_equal(_np(Cn), eC)
+    u, D = np.unique(rng.integers(0, 40, size=n), return_inverse=True)
+    off, idx, ww = mg.aggregate(dg, _t(D), len(u), False, mode=mg.MODE_ALG1, k=k, chunk_len=1)
+    e = oracle.aggregate(g, D.astype(np.int32), len(u), mode=oracle.MODE_ALG1, k=k, chunk_len=1)
+    assert np.array_equal(off, e.offsets) and np.array_equal(idx, e.indices)
+    assert np.array_equal(ww, e.weights)

@@ -83,6 +83,9 @@ typedef struct {
                              (default and maximum 512)                               */
   int32_t exact_lds_big;  /* exact mode: rows up to this use an 8192-slot LDS table
                              (default and maximum 4096); longer rows a global table  */
+  int32_t direct_launch;  /* batched runs: 0 (default) issues each level's sweeps as
+                             one captured HIP graph, 1 launches them one by one      */
+  int32_t reserved_params;
 } mgcd_params;
 
 typedef struct {

@@ -39,7 +39,8 @@ class Params(ct.Structure):
                 ("tolerance", ct.c_double), ("tolerance_drop", ct.c_double),
                 ("aggregation_tolerance", ct.c_double), ("row_lanes", ct.c_int32),
                 ("exact_small", ct.c_int32), ("exact_lds", ct.c_int32),
-                ("exact_lds_big", ct.c_int32)]
+                ("exact_lds_big", ct.c_int32), ("direct_launch", ct.c_int32),
+                ("reserved_params", ct.c_int32)]
 
 
 class Stats(ct.Structure):

@@ -166,16 +166,141 @@ static void write_selected(Batch &b, const int32_t *lab, const std::vector<uint8
   a.release(mk);
 }
 
-static std::vector<unsigned long long> read_gctr(const unsigned long long *gctr, int32_t count,
-                                                 hipStream_t st) {
-  std::vector<unsigned long long> h(3 * (size_t)count);
-  MGCD_HIP(hipMemcpyAsync(h.data(), gctr, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-  MGCD_HIP(hipStreamSynchronize(st));
-  return h;
+// After a sweep, per graph on the device: a graph still moving counts the sweep
+// (stat = {sweeps, entries streamed, movers of its last sweep}) and stops when its
+// rule says so -- LPA: movers <= tol * n_g; Louvain: no positive move, or
+// 2 * (summed gain) <= tol * W_g^2 -- and its counters are cleared for the next sweep.
+// The same double-precision tests the single-graph driver makes on the host.
+template <int ALGO>
+__global__ void k_batch_converge(unsigned long long *gctr, uint8_t *active, long long *stat,
+                                 const int64_t *nent, const int64_t *nvert,
+                                 const unsigned long long *Wg64, double tol, int32_t count) {
+  const int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (g >= count) return;
+  unsigned long long *c = gctr + 3 * g;
+  const unsigned long long moved = c[0], prop = c[1], sumG = c[2];
+  c[0] = c[1] = c[2] = 0;
+  if (!active[g]) return;
+  stat[3 * g] += 1;
+  stat[3 * g + 1] += nent[g];
+  stat[3 * g + 2] = (long long)moved;
+  bool stop;
+  if (ALGO == ALGO_LPA) {
+    stop = (double)moved <= tol * (double)nvert[g];
+  } else {
+    const double WW = (double)Wg64[g] * (double)Wg64[g];
+    stop = prop == 0 || 2.0 * (double)sumG <= tol * WW;
+  }
+  if (stop) active[g] = 0;
 }
 
-static void zero_gctr(unsigned long long *gctr, int32_t count, hipStream_t st) {
-  MGCD_HIP(hipMemsetAsync(gctr, 0, 3 * (size_t)count * sizeof(unsigned long long), st));
+// One level's local-moving sweeps for every graph of the batch, each sweep followed
+// by the per-graph bookkeeping on the device, so no sweep waits for the host.  The
+// sweeps are issued in segments of SEG (even, so the two label buffers and the sweep
+// directions repeat); by default one segment is captured as a HIP graph and that
+// graph is launched again for every segment.  Between segments the host reads the
+// per-graph flags once and stops when no graph is still moving; a graph that has
+// stopped stays frozen (its vertices keep their labels) in the rest of its segment.
+// Returns with the caller's stream synchronised; C[0] then holds the labels.
+constexpr int SEG = 4;
+
+struct LevelSweeps {
+  int algo;             // ALGO_LPA or ALGO_MOVE
+  Graph g;
+  int32_t *C[2];
+  uint32_t *K, *Sig;
+  int32_t *size;
+  int32_t *gid;
+  uint32_t *Wg;
+  unsigned long long *Wg64;
+  uint8_t *active;
+  unsigned long long *gctr;
+  long long *stat;
+  const int64_t *nent, *nvert;
+  int32_t count;
+  double tol;
+};
+
+// A stream of the library's own to record graphs on (the caller's stream may be the
+// legacy default stream, which cannot be captured); destroyed with the call.
+struct CaptureStream {
+  hipStream_t s = nullptr;
+  hipStream_t get() {
+    if (!s) MGCD_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
+  }
+  ~CaptureStream() {
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+static void level_sweeps(LevelSweeps &L, const mgcd_params *p, const Schedule &sch,
+                         CaptureStream *capture, hipStream_t st) {
+  // sweeps it0 .. it0+n-1 on stream s (label buffers swapped after each)
+  auto issue = [&](int it0, int n, hipStream_t s) {
+    for (int it = it0; it < it0 + n; ++it) {
+      const int dir = L.algo == ALGO_LPA ? 0 : (it % 2 == 0 ? -1 : 1);
+      SweepArgs args{L.g, L.C[0], nullptr, L.K, L.Sig, 0, dir, L.C[1], nullptr, L.gctr};
+      args.gid = L.gid;
+      args.Wg = L.Wg;
+      args.active = L.active;
+      args.gctr = L.gctr;
+      launch_sweep(args, sch, L.algo, p->mode, p->k, p->chunk_len, s);
+      if (L.algo != ALGO_LPA) launch_apply_moves(L.C[0], L.C[1], L.K, L.Sig, L.size, L.g.n, s);
+      if (L.algo == ALGO_LPA)
+        k_batch_converge<ALGO_LPA><<<grid_for(L.count), BLOCK, 0, s>>>(
+            L.gctr, L.active, L.stat, L.nent, L.nvert, L.Wg64, L.tol, L.count);
+      else
+        k_batch_converge<ALGO_MOVE><<<grid_for(L.count), BLOCK, 0, s>>>(
+            L.gctr, L.active, L.stat, L.nent, L.nvert, L.Wg64, L.tol, L.count);
+      MGCD_LAUNCHED();
+      std::swap(L.C[0], L.C[1]);
+    }
+  };
+  std::vector<uint8_t> flags(L.count);
+  auto any_moving = [&]() {
+    MGCD_HIP(hipMemcpyAsync(flags.data(), L.active, L.count, hipMemcpyDeviceToHost, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+    for (uint8_t f : flags)
+      if (f) return true;
+    return false;
+  };
+  const int total = p->max_iterations;
+  int done = 0;
+  bool moving = true;
+  if (capture && total >= SEG) {
+    hipStream_t cs = capture->get();
+    hipGraph_t graph = nullptr;
+    MGCD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    in_capture = true;
+    try {
+      issue(0, SEG, cs);
+    } catch (...) {
+      in_capture = false;
+      (void)hipStreamEndCapture(cs, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    in_capture = false;
+    MGCD_HIP(hipStreamEndCapture(cs, &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    while (e == hipSuccess && moving && done + SEG <= total) {
+      e = hipGraphLaunch(exec, st);  // on the caller's stream, after its earlier work
+      done += SEG;
+      if (e == hipSuccess) moving = any_moving();
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    MGCD_HIP(e);
+  }
+  while (moving && done < total) {
+    const int n = std::min(SEG, total - done);
+    issue(done, n, st);
+    done += n;
+    moving = any_moving();
+  }
+  MGCD_HIP(hipStreamSynchronize(st));
 }
 
 void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_params *p,
@@ -276,37 +401,47 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
   mgcd_stats s{};
   float ms_lm = 0, ms_agg = 0;
 
+  CaptureStream cstream;
+  CaptureStream *capture = p->direct_launch == 0 ? &cstream : nullptr;
+  long long *stat = a.take<long long>(3 * (int64_t)count);
+  int64_t *nent_d = a.take<int64_t>(count);
+  int64_t *nvert_d = a.take<int64_t>(count);
+  // per-level stats from the device: sweeps, entries, movers per graph
+  auto collect = [&](const std::vector<uint8_t> &was_active) {
+    std::vector<long long> h(3 * (size_t)count);
+    MGCD_HIP(hipMemcpyAsync(h.data(), stat, h.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+    long long sweeps = 0;
+    for (int32_t g = 0; g < count; ++g) {
+      if (!was_active[g] || h[3 * g] == 0) continue;
+      gs[g].iterations += (int32_t)h[3 * g];
+      gs[g].edges_scanned += h[3 * g + 1];
+      gs[g].moved_last = h[3 * g + 2];
+      s.edges_scanned += h[3 * g + 1];
+      sweeps = std::max(sweeps, h[3 * g]);
+    }
+    s.iterations += (int32_t)sweeps;
+  };
+
   if (algo == MGCD_ALGO_LPA) {
     launch_iota(Ca, N, st);
     Schedule sch;
     build_schedule(U, sched_params(p), sch, a, st);
     for (int32_t g = 0; g < count; ++g) active[g] = !finished[g];
     copy_h2d(active_d, active.data(), count, st);
-    for (int it = 0; it < p->max_iterations && N > 0; ++it) {
-      zero_gctr(gctr, count, st);
-      SweepArgs args{U, Ca, nullptr, Kbuf[0], nullptr, 0, 0, Cb, nullptr, gctr};
-      args.gid = b.gid0;
-      args.Wg = Wg;
-      args.active = active_d;
-      args.gctr = gctr;
+    copy_h2d(nent_d, b.nnz.data(), count * sizeof(int64_t), st);
+    copy_h2d(nvert_d, b.n.data(), count * sizeof(int64_t), st);
+    launch_zero_u64((unsigned long long *)stat, 3 * count, st);
+    launch_zero_u64(gctr, 3 * count, st);
+    if (N > 0 && p->max_iterations > 0) {
+      LevelSweeps lv{ALGO_LPA, U, {Ca, Cb}, Kbuf[0], nullptr, nullptr, b.gid0, Wg, Wg64,
+                     active_d, gctr, stat, nent_d, nvert_d, count, p->tolerance};
       tm.start();
-      launch_sweep(args, sch, ALGO_LPA, p->mode, p->k, p->chunk_len, st);
+      level_sweeps(lv, p, sch, capture, st);
       ms_lm += tm.stop();
-      auto h = read_gctr(gctr, count, st);
-      std::swap(Ca, Cb);
-      s.iterations += 1;
-      bool any = false;
-      for (int32_t g = 0; g < count; ++g) {
-        if (!active[g]) continue;
-        gs[g].iterations += 1;
-        gs[g].edges_scanned += b.nnz[g];
-        gs[g].moved_last = (int64_t)h[3 * g];
-        s.edges_scanned += b.nnz[g];
-        if ((double)h[3 * g] <= p->tolerance * (double)b.n[g]) active[g] = 0;
-        any |= active[g] != 0;
-      }
-      copy_h2d(active_d, active.data(), count, st);
-      if (!any) break;
+      Ca = lv.C[0];
+      Cb = lv.C[1];
+      collect(active);
     }
     for (int32_t g = 0; g < count; ++g) sel[g] = !finished[g];
     write_selected(b, Ca, sel, comms, a, st);
@@ -362,33 +497,19 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
         if (!finished[g]) gs[g].passes += 1;
       }
       copy_h2d(active_d, active.data(), count, st);
-      for (int it = 0; it < p->max_iterations; ++it) {
-        zero_gctr(gctr, count, st);
-        SweepArgs args{cur, Ca, nullptr, K, Sig, 0, (it % 2 == 0) ? -1 : 1, Cb, nullptr, gctr};
-        args.gid = gid_cur;
-        args.Wg = Wg;
-        args.active = active_d;
-        args.gctr = gctr;
+      copy_h2d(nent_d, nnz_cur.data(), count * sizeof(int64_t), st);
+      copy_h2d(nvert_d, n_cur.data(), count * sizeof(int64_t), st);
+      launch_zero_u64((unsigned long long *)stat, 3 * count, st);
+      launch_zero_u64(gctr, 3 * count, st);
+      {
+        LevelSweeps lv{ALGO_MOVE, cur, {Ca, Cb}, K, Sig, size, gid_cur, Wg, Wg64,
+                       active_d, gctr, stat, nent_d, nvert_d, count, tol};
         tm.start();
-        launch_sweep(args, sch, ALGO_MOVE, p->mode, p->k, p->chunk_len, st);
+        level_sweeps(lv, p, sch, capture, st);
         ms_lm += tm.stop();
-        auto h = read_gctr(gctr, count, st);
-        s.iterations += 1;
-        launch_apply_moves(Ca, Cb, K, Sig, size, nl, st);
-        std::swap(Ca, Cb);
-        bool any = false;
-        for (int32_t g = 0; g < count; ++g) {
-          if (!active[g]) continue;
-          gs[g].iterations += 1;
-          gs[g].edges_scanned += nnz_cur[g];
-          gs[g].moved_last = (int64_t)h[3 * g];
-          s.edges_scanned += nnz_cur[g];
-          const double WW = (double)W[g] * (double)W[g];
-          if (h[3 * g + 1] == 0 || 2.0 * (double)h[3 * g + 2] <= tol * WW) active[g] = 0;
-          any |= active[g] != 0;
-        }
-        copy_h2d(active_d, active.data(), count, st);
-        if (!any) break;
+        Ca = lv.C[0];
+        Cb = lv.C[1];
+        collect(active);
       }
       a.release(mark);
       tm.start();

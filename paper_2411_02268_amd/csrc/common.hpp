@@ -43,7 +43,14 @@ struct Error : std::runtime_error {
       throw ::mgcd::Error(-5, std::string(#x) + ": " + hipGetErrorString(e_));          \
   } while (0)
 
-#define MGCD_LAUNCHED() MGCD_HIP(hipGetLastError())
+// Set while this thread records work into a HIP graph: the runtime refuses
+// hipGetLastError then, and launch errors surface when the capture ends instead.
+inline thread_local bool in_capture = false;
+
+#define MGCD_LAUNCHED()                                      \
+  do {                                                       \
+    if (!::mgcd::in_capture) MGCD_HIP(hipGetLastError());    \
+  } while (0)
 
 // Kernels that hold a K-slot sketch per lane in registers: at K = 16 two waves per
 // SIMD leave room for the sketch and its merge partner without spilling.

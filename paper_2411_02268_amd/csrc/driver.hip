@@ -59,6 +59,7 @@ static void check_params(const mgcd_params *p) {
   const int rl = p->row_lanes;
   if (rl < 0 || rl > 64 || (rl & (rl - 1)) != 0)
     throw Error(MGCD_E_ARG, "row_lanes must be 0 or a power of two up to 64");
+  if (p->direct_launch != 0 && p->direct_launch != 1) throw Error(MGCD_E_ARG, "direct_launch must be 0 or 1");
   if (p->exact_small < 0 || p->exact_lds < 0 || p->exact_lds_big < 0)
     throw Error(MGCD_E_ARG, "exact tier bounds must be >= 0");
   const SchedParams sp = sched_params(p);

@@ -260,14 +260,19 @@ def _batch_graphs():
 
 
 @pytest.mark.parametrize("algo", ["lpa", "louvain"])
-@pytest.mark.parametrize("mode,k,L", [("alg1", 8, 128), ("alg1", 4, 16), ("exact", 8, 128),
-                                      ("alg1", 32, 16), ("alg1", 64, 128)])
-def test_batched_equals_solo(mg, algo, mode, k, L):
+@pytest.mark.parametrize("mode,k,L,direct", [("alg1", 8, 128, 0), ("alg1", 4, 16, 0),
+                                             ("exact", 8, 128, 0), ("alg1", 32, 16, 0),
+                                             ("alg1", 64, 128, 0), ("alg1", 8, 128, 1),
+                                             ("exact", 8, 128, 1)])
+def test_batched_equals_solo(mg, algo, mode, k, L, direct):
     gs = _batch_graphs()
     dgs = [mg.to_device(g) for g in gs]
     kw = dict(mode=MODES[mode], k=k, chunk_len=L)
     code = mg.ALGO_LPA if algo == "lpa" else mg.ALGO_LOUVAIN
-    labs, gst, tot = mg.run_batched(code, dgs, **kw)
+    labs, gst, tot = mg.run_batched(code, dgs, direct_launch=direct, **kw)
+    again, _, _ = mg.run_batched(code, dgs, direct_launch=direct, **kw)  # a second call agrees
+    for x, y in zip(labs, again):
+        assert np.array_equal(_np(x), _np(y))
     for g, dg, lab, st in zip(gs, dgs, labs, gst):
         if g.n == 0:
             assert lab.numel() == 0

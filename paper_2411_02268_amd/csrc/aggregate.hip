@@ -892,7 +892,7 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   return total;
 }
 
-size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
+size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L, bool symmetric) {
   size_t b = 0;
   if (mode == MODE_EXACT) {
     b += (size_t)nnz * (8 + 8 + 4 + 4 + 4 + 8) + 8192;
@@ -904,13 +904,18 @@ size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
   b += (size_t)(n + 1) * (4 + 4 + 8) + 4096;        // mstart, mdeg, P
   b += scan_ws_bytes(n + 1) + 4096;
   b += (size_t)n * (8 + 8 + 4 + 4 + 4 + 8) + 4096;  // community sort, order, row starts
-  int64_t chunks = nnz / (L > 0 ? L : 1) + n + 1;
-  b += (size_t)(n + 1) * 16 + (size_t)chunks * (4 + (size_t)k * sizeof(Pair)) + 8192;
+  // streams of more than 64 chunks: at most nnz / (64 L) of them, at most
+  // nnz / L + that many chunks
+  const int64_t Lc = L > 0 ? L : 1;
+  const int64_t nm = nnz / (64 * Lc) + 1, chunks = nnz / Lc + nm + 1;
+  b += (size_t)(nm + 1) * 16 + scan_ws_bytes(nm) + (size_t)chunks * (4 + (size_t)k * sizeof(Pair)) + 8192;
   b += (size_t)n * k * sizeof(Pair) + (size_t)n * 4 + 4096;  // rows, rcount
-  // symmetric: emit buffers (<= 2 k n entries), sort, heads
-  int64_t e2 = 2 * ((int64_t)n * k < nnz ? (int64_t)n * k : nnz);  // rows hold <= their stream
-  b += (size_t)n * (4 + 8 + 4) + (size_t)e2 * (8 + 8 + 4 + 4 + 4 + 8) + 16384;
-  b += radix_sort_ws_bytes(e2) + scan_ws_bytes(e2);
+  if (symmetric) {
+    // emit buffers (rows hold at most their stream: <= 2 min(k n, nnz) entries), sort, heads
+    int64_t e2 = 2 * ((int64_t)n * k < nnz ? (int64_t)n * k : nnz);
+    b += (size_t)n * (4 + 8 + 4) + (size_t)e2 * (8 + 8 + 4 + 4 + 4 + 8) + 16384;
+    b += radix_sort_ws_bytes(e2) + scan_ws_bytes(e2);
+  }
   return b + 64 * 1024;
 }
 

@@ -21,7 +21,7 @@ int32_t renumber(const int32_t *C, int32_t n, int32_t *D, Arena &a, hipStream_t 
 int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, int64_t L,
                   int symmetric, int64_t *out_off, int32_t *out_idx, uint32_t *out_w, Arena &a,
                   hipStream_t st);
-size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L);
+size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L, bool symmetric);
 
 // K'[c] = sum of K[i] over D[i] == c.
 void launch_group_sums(const int32_t *D, const uint32_t *K, uint32_t *Kout, int32_t n, int32_t m,

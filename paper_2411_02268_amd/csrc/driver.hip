@@ -285,7 +285,7 @@ static size_t workspace_bytes(int32_t algo, int32_t n, int64_t nnz, const mgcd_p
   size_t fixed = (size_t)n * 4 * 16 + 64 * 1024;
   if (algo != MGCD_ALGO_LPA) fixed += 2 * ((size_t)(n + 1) * 8 + (size_t)nnz * 8) + 4096;
   size_t sched = schedule_ws_bytes(n, nnz, mode, p->k, L);
-  size_t agg = algo == MGCD_ALGO_LPA ? 0 : aggregate_ws_bytes(n, nnz, mode, p->k_aggregate, L);
+  size_t agg = algo == MGCD_ALGO_LPA ? 0 : aggregate_ws_bytes(n, nnz, mode, p->k_aggregate, L, algo == MGCD_ALGO_LEIDEN);
   size_t misc = (size_t)n * (4 + 4 + 8 + 8) + scan_ws_bytes((int64_t)n + 1) + 16 * 1024;
   size_t degrees = degrees_ws_bytes(nnz);
   size_t phase = sched > agg ? sched : agg;
@@ -485,7 +485,7 @@ int mgcd_aggregate(const mgcd_csr *gin, const mgcd_params *p, const int32_t *D, 
     Graph g = view(gin);
     if (m < 0 || m > g.n) throw Error(MGCD_E_ARG, "m out of range");
     if (!out_off || (g.nnz > 0 && (!out_idx || !out_w)) || !out_nnz) throw Error(MGCD_E_ARG, "null output");
-    size_t need = aggregate_ws_bytes(g.n, g.nnz, p->mode, p->k_aggregate, p->chunk_len) + 64 * 1024;
+    size_t need = aggregate_ws_bytes(g.n, g.nnz, p->mode, p->k_aggregate, p->chunk_len, symmetric != 0) + 64 * 1024;
     if (ws_bytes < need) throw Error(MGCD_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
     Arena a = make_arena(ws, ws_bytes);
     hipStream_t st = (hipStream_t)stream;

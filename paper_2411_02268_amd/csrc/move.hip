@@ -1023,12 +1023,17 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
     b += (size_t)(n + 1) * 8 + scan_ws_bytes(n) + 1024;  // hash bases
     b += (size_t)(4 * nnz + 64) * sizeof(Pair) + 1024;  // tables: cap <= 4*deg
   } else {
-    int64_t chunks = nnz / (L > 0 ? L : 1) + n + 1;
-    b += (size_t)nnz * 4 + 1024;                            // key stream
-    b += (size_t)(n + 1) * 8 * 2 + scan_ws_bytes(n) + 2048;  // counts, cstart
-    b += (size_t)chunks * (4 + 4 + (size_t)k * sizeof(Pair) + (size_t)(k + 1) * 4) + 4096;
-    b += (size_t)(n + 1) * 8 * 2 + scan_ws_bytes(n) + 2048;  // group counts, gstart
-    b += (size_t)n * ((size_t)k * sizeof(Pair) + 4) + 2048;  // long-row candidates, flags
+    // a long row has more than one chunk, so more than L entries: at most nnz / L
+    // long rows, at most 2 nnz / L + 1 of their chunks, and groups of 64 chunks at
+    // most chunks / 64 + long rows
+    const int64_t Lc = L > 0 ? L : 1;
+    const int64_t nl = nnz / Lc + 1, cl = 2 * (nnz / Lc) + 2, gl = cl / 64 + nl + 1;
+    b += (size_t)nnz * 4 + 1024;                                     // key stream
+    b += (size_t)(nl + 1) * 8 * 2 + scan_ws_bytes(nl) + 2048;        // chunk counts, cstart
+    b += (size_t)cl * (4 + (size_t)(k + 1) * 4) + 4096;              // owner, pass-2 counts
+    b += (size_t)(nl + 1) * 8 * 2 + scan_ws_bytes(nl) + 2048;        // group counts, gstart
+    b += (size_t)gl * (4 + (size_t)k * sizeof(Pair) + 4) + 4096;     // gowner, roots, flags
+    b += (size_t)nl * ((size_t)k * sizeof(Pair) + 4) + 2048;         // candidates, flags
   }
   return b + 64 * 1024;
 }

@@ -268,8 +268,15 @@ def aggregate(g: DeviceGraph, D, m: int, symmetric: bool = False, **kw):
             w[:k].cpu().numpy().view(np.uint32))
 
 
-def run_batched(algo: int, graphs, **kw):
+def batched_workspace_bytes(algo: int, graphs, **kw) -> int:
+    p = params(algo, **kw)
+    return int(lib().mgcd_workspace_bytes_batched(algo, len(graphs), sum(g.n for g in graphs),
+                                                  sum(g.nnz for g in graphs), ct.byref(p)))
+
+
+def run_batched(algo: int, graphs, workspace=None, **kw):
     """Run LPA (ALGO_LPA) or Louvain (ALGO_LOUVAIN) on many device graphs together.
+    `workspace` (optional): a device uint8 tensor of at least batched_workspace_bytes.
     Returns (labels per graph, stats per graph, total stats)."""
     import torch
     count = len(graphs)
@@ -281,7 +288,11 @@ def run_batched(algo: int, graphs, **kw):
     N = sum(g.n for g in graphs)
     E = sum(g.nnz for g in graphs)
     nbytes = int(lib().mgcd_workspace_bytes_batched(algo, count, N, E, ct.byref(p)))
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if workspace is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    else:
+        ws = workspace
+        nbytes = int(ws.numel())
     gst = (GraphStats * max(count, 1))()
     tot = Stats()
     name = "lpa_run_batched" if algo == ALGO_LPA else "louvain_run_batched"

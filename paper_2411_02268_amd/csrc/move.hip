@@ -1351,8 +1351,9 @@ __global__ void k_iota(int32_t *p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (i < n) p[i] = (int32_t)i;
 }
-__global__ void k_zero_u64(unsigned long long *p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+__global__ void k_zero_u64(unsigned long long *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
@@ -1365,8 +1366,9 @@ void launch_iota(int32_t *p, int64_t n, hipStream_t st) {
   k_iota<<<grid_for(n), BLOCK, 0, st>>>(p, n);
   MGCD_LAUNCHED();
 }
-void launch_zero_u64(unsigned long long *p, int n, hipStream_t st) {
-  k_zero_u64<<<1, 64, 0, st>>>(p, n);
+void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_zero_u64<<<grid_for(n), BLOCK, 0, st>>>(p, n);
   MGCD_LAUNCHED();
 }
 

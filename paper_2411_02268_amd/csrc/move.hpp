@@ -139,6 +139,6 @@ void launch_refine_accept(const int32_t *prop, int32_t *nprop, int32_t *from, in
                           hipStream_t st);
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 void launch_iota(int32_t *p, int64_t n, hipStream_t st);
-void launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
+void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st);
 
 }  // namespace mgcd

@@ -307,3 +307,24 @@ def test_wave_sketch_deep_merge_tree(mg, k):
     e = oracle.aggregate(g, D.astype(np.int32), len(u), mode=oracle.MODE_ALG1, k=k, chunk_len=1)
     assert np.array_equal(off, e.offsets) and np.array_equal(idx, e.indices)
     assert np.array_equal(ww, e.weights)
+
+
+@pytest.mark.parametrize("algo", ["lpa", "louvain"])
+def test_batched_many_graphs_dirty_workspace(mg, algo):
+    """More graphs than one wave of counters, in a workspace full of garbage: every
+    per-graph counter and statistic must start from zero (regression: a clear that
+    covered only 64 entries)."""
+    import torch
+    gs = [synth.planted_uneven(n, 20, 200, 6, 4, np.random.default_rng(900 + n))[0]
+          for n in range(300, 300 + 45 * 37, 37)]
+    dgs = [mg.to_device(g) for g in gs]
+    code = mg.ALGO_LPA if algo == "lpa" else mg.ALGO_LOUVAIN
+    kw = dict(mode=mg.MODE_ALG1, k=8, chunk_len=16)
+    nbytes = mg.batched_workspace_bytes(code, dgs, **kw)
+    ws = torch.full((nbytes,), 0xA7, dtype=torch.uint8, device="cuda")
+    labs, gst, tot = mg.run_batched(code, dgs, workspace=ws, **kw)
+    for dg, lab, st in zip(dgs, labs, gst):
+        solo, sst = getattr(mg, algo)(dg, **kw)
+        assert np.array_equal(_np(lab), _np(solo))
+        for key in ("iterations", "passes", "communities", "edges_scanned", "moved_last"):
+            assert st[key] == sst[key], key

@@ -11,6 +11,7 @@
 #include "move.hpp"
 #include "primitives.hpp"
 #include "sketch.hpp"
+#include "staging.hpp"
 #include "wave_sketch.hpp"
 
 namespace mgcd {
@@ -368,7 +369,74 @@ struct AggStreams {
   const int32_t *mstart;  // [m+1]
   const int64_t *P;       // [n+1] stream position of each member's row
   const int64_t *rs;      // [n] CSR offset of each member's row (off[mem[t]])
+  const uint32_t *skey;   // [positions] the streams laid out contiguously: key D[j]
+  const uint32_t *sw;     //             and weight of every position
 };
+
+// Stream position of every vertex's row (-1: the vertex is in no community).
+__global__ void k_row_pos(const uint32_t *mem, const int64_t *P, int32_t nmem, int64_t *rowpos) {
+  int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (t < nmem) rowpos[mem[t]] = P[t];
+}
+
+// Lay the community streams out contiguously: entry e of row i goes to position
+// rowpos[i] + (e - off[i]) with key D[j] and its weight.  A workgroup takes SF_TILE
+// consecutive entries (balanced whatever the row lengths): the rows spanning the
+// tile are found once (binary search), their offsets staged in LDS, and each entry
+// finds its row there; a tile spanning more rows than fit searches the offsets in
+// global memory instead.
+constexpr int SF_ITEMS = 8, SF_TILE = BLOCK * SF_ITEMS, SF_ROWS = SF_TILE;
+
+__device__ inline int32_t row_of_entry(const int64_t *off, int32_t lo, int32_t hi, int64_t e) {
+  // the largest r in [lo, hi] with off[r] <= e (the last of equal offsets: a row
+  // holding e, not an empty one before it)
+  while (lo < hi) {
+    const int32_t mid = (int32_t)(((int64_t)lo + hi + 1) >> 1);
+    if (off[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    k_agg_streamify(Graph g, const int32_t *D, const int64_t *rowpos, uint32_t *skey, uint32_t *sw) {
+  __shared__ int64_t soff[SF_ROWS + 1];
+  __shared__ int32_t sr[2];
+  const int64_t e0 = (int64_t)blockIdx.x * SF_TILE;
+  const int64_t e1 = e0 + SF_TILE < g.nnz ? e0 + SF_TILE : g.nnz;
+  if (threadIdx.x == 0) sr[0] = row_of_entry(g.off, 0, g.n - 1, e0);
+  if (threadIdx.x == 1) sr[1] = row_of_entry(g.off, 0, g.n - 1, e1 - 1);
+  __syncthreads();
+  const int32_t r0 = sr[0], r1 = sr[1];
+  const int32_t nr = r1 - r0 + 1;
+  const bool staged = nr <= SF_ROWS;
+  if (staged)
+    for (int32_t k = threadIdx.x; k <= nr; k += BLOCK) soff[k] = g.off[r0 + k];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < SF_ITEMS; ++q) {
+    const int64_t e = e0 + (int64_t)q * BLOCK + threadIdx.x;
+    if (e >= e1) break;
+    int32_t r;
+    int64_t rb;
+    if (staged) {
+      int32_t lo = 0, hi = nr - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (soff[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      r = r0 + lo;
+      rb = soff[lo];
+    } else {
+      r = row_of_entry(g.off, r0, r1, e);
+      rb = g.off[r];
+    }
+    const int64_t p = rowpos[r];
+    if (p < 0) continue;
+    const int64_t pos = p + (e - rb);
+    skey[pos] = (uint32_t)D[__builtin_nontemporal_load(g.idx + e)];
+    sw[pos] = __builtin_nontemporal_load(g.w + e);
+  }
+}
 
 __global__ void k_row_starts(const int64_t *off, const uint32_t *mem, int32_t n, int64_t *rs) {
   int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -376,39 +444,6 @@ __global__ void k_row_starts(const int64_t *off, const uint32_t *mem, int32_t n,
 }
 
 // Stream positions [p0, p1) of community c into the sketch.
-template <int K, int MODE>
-__device__ inline void stream_range(const AggStreams &s, int32_t c, int64_t p0, int64_t p1,
-                                    RegSketch<K, MODE> &sk) {
-  // member t holding position p0: the last t in [mstart[c], mstart[c+1]) with P[t] <= p0
-  int32_t lo = s.mstart[c], hi = s.mstart[c + 1] - 1;
-  while (lo < hi) {
-    int32_t mid = (lo + hi + 1) >> 1;
-    if (s.P[mid] <= p0) lo = mid; else hi = mid - 1;
-  }
-  int32_t t = lo;
-  int64_t p = p0;
-  while (p < p1) {
-    const int64_t rb = s.rs[t];
-    const int64_t row_end = s.P[t + 1];
-    const int64_t stop = row_end < p1 ? row_end : p1;
-    int64_t e = rb + (p - s.P[t]);
-    for (; p + 4 <= stop; p += 4, e += 4) {  // four entries in flight
-      int32_t j[4];
-      uint32_t w[4], c[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) j[u] = __builtin_nontemporal_load(s.g.idx + e + u);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) w[u] = __builtin_nontemporal_load(s.g.w + e + u);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) c[u] = (uint32_t)s.D[j[u]];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) sk.update(c[u], w[u]);
-    }
-    for (; p < stop; ++e, ++p) sk.update((uint32_t)s.D[s.g.idx[e]], s.g.w[e]);
-    ++t;
-  }
-}
-
 // Communities whose stream has at most 64 chunks: P = 2^b adjacent lanes per
 // community (P >= its chunk count), lane q sketches chunk q, the chunk sketches are
 // merged by the fixed tree with cross-lane shuffles and lane 0 writes the row.
@@ -426,6 +461,7 @@ __device__ inline void write_row(uint32_t (&k)[K], uint32_t (&v)[K], int32_t c, 
 template <int K, int MODE>
 __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
     k_agg_rows(AggStreams s, AggBuckets bk, int64_t L, Pair *rows, uint32_t *rcount) {
+  __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
   const int lane = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
   int b = 6;
@@ -439,10 +475,9 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
   const int64_t nc = (end - base + L - 1) / L;
   RegSketch<K, MODE> sk;
   sk.reset();
-  if (q < nc) {
-    const int64_t p0 = base + q * L;
-    stream_range<K, MODE>(s, c, p0, p0 + L < end ? p0 + L : end, sk);
-  }
+  const int64_t p0 = base + q * L;
+  const int64_t p1 = q < nc ? (p0 + L < end ? p0 + L : end) : p0;
+  staged_fold<K, MODE>(sk, swin[threadIdx.x / WAVE], p0, p1, s.skey, s.sw);
   sk.finalize();
   for (int l = 0; l < logp; ++l) {
     const int stride = 1 << l;
@@ -476,16 +511,20 @@ template <int K, int MODE>
 __global__ void __launch_bounds__(BLOCK)
     k_agg_chunks(AggStreams s, const int32_t *multi, const int32_t *owner, const int64_t *cstart,
                  int64_t nchunks, int64_t L, Pair *skbuf) {
+  __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
   int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (q >= nchunks) return;
-  const int32_t x = owner[q];
-  const int32_t c = multi[x];
-  const int64_t base = s.P[s.mstart[c]], end = s.P[s.mstart[c + 1]];
-  const int64_t p0 = base + (q - cstart[x]) * L;
-  const int64_t p1 = p0 + L < end ? p0 + L : end;
+  int64_t p0 = 0, p1 = 0;
+  if (q < nchunks) {
+    const int32_t x = owner[q];
+    const int32_t c = multi[x];
+    const int64_t base = s.P[s.mstart[c]], end = s.P[s.mstart[c + 1]];
+    p0 = base + (q - cstart[x]) * L;
+    p1 = p0 + L < end ? p0 + L : end;
+  }
   RegSketch<K, MODE> sk;
   sk.reset();
-  stream_range<K, MODE>(s, c, p0, p1, sk);
+  staged_fold<K, MODE>(sk, swin[threadIdx.x / WAVE], p0, p1, s.skey, s.sw);
+  if (q >= nchunks) return;
   sk.finalize();
 #pragma unroll
   for (int p = 0; p < K; ++p) skbuf[q * K + p] = Pair{sk.key[p], sk.val[p]};
@@ -637,24 +676,20 @@ __global__ void __launch_bounds__(BLOCK)
   sk.reset();
   WaveTree<K, DEPTH> tree{sstack[threadIdx.x / WAVE]};
   int64_t left = L;  // positions left in the current chunk
-  const int32_t t1 = uniform(s.mstart[c + 1]);
-  for (int32_t t = uniform(s.mstart[c]); t < t1; ++t) {
-    const int64_t rb = uniform(s.rs[t]), len = uniform(s.P[t + 1] - s.P[t]);
-    for (int64_t q0 = 0; q0 < len; q0 += WAVE) {
-      const int64_t q = q0 + lane;
-      const bool v = q < len;
-      const int32_t j = v ? __builtin_nontemporal_load(s.g.idx + rb + q) : 0;
-      const uint32_t w = v ? __builtin_nontemporal_load(s.g.w + rb + q) : 0u;
-      const uint32_t key = v ? (uint32_t)s.D[j] : EMPTY;
-      const int nb = len - q0 < WAVE ? (int)(len - q0) : WAVE;
-      for (int u = 0; u < nb; ++u) {
-        sk.update(lane_value(key, u), lane_value(w, u));
-        if (--left == 0) {  // end of a chunk
-          sk.finalize();
-          tree.push(sk.key, sk.val);
-          sk.reset();
-          left = L;
-        }
+  const int64_t base = uniform(s.P[s.mstart[c]]), end = uniform(s.P[s.mstart[c + 1]]);
+  for (int64_t q0 = base; q0 < end; q0 += WAVE) {
+    const int64_t q = q0 + lane;
+    const bool v = q < end;
+    const uint32_t key = v ? __builtin_nontemporal_load(s.skey + q) : EMPTY;
+    const uint32_t w = v ? __builtin_nontemporal_load(s.sw + q) : 0u;
+    const int nb = end - q0 < WAVE ? (int)(end - q0) : WAVE;
+    for (int u = 0; u < nb; ++u) {
+      sk.update(lane_value(key, u), lane_value(w, u));
+      if (--left == 0) {  // end of a chunk
+        sk.finalize();
+        tree.push(sk.key, sk.val);
+        sk.reset();
+        left = L;
       }
     }
   }
@@ -715,6 +750,24 @@ static void agg_mg_k(int k, const AggStreams &s, const AggBuckets &bk, int64_t w
     case 16: agg_mg<16, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
     default: throw Error(-6, "k_aggregate must be 1, 2, 4, 8, 16, 32 or 64");
   }
+}
+
+static int32_t read_i32(const int32_t *p, hipStream_t st) {
+  int32_t h = 0;
+  MGCD_HIP(hipMemcpyAsync(&h, p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  return h;
+}
+
+__global__ void k_fill_i64(int64_t *p, int64_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill_i64<<<grid_for(n), BLOCK, 0, st>>>(p, v, n);
+  MGCD_LAUNCHED();
 }
 
 static int64_t read_i64(const int64_t *p, hipStream_t st) {
@@ -846,7 +899,21 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   int64_t *rs = a.take<int64_t>(n);
   k_row_starts<<<grid_for(n), BLOCK, 0, st>>>(g.off, mem, n, rs);
   MGCD_LAUNCHED();
-  AggStreams s{g, D, mem, mstart, P, rs};
+  int64_t *rowpos = a.take<int64_t>(n);
+  launch_fill_i64(rowpos, -1, n, st);
+  const int32_t nmem = read_i32(mstart + m, st);
+  if (nmem > 0) {
+    k_row_pos<<<grid_for(nmem), BLOCK, 0, st>>>(mem, P, nmem, rowpos);
+    MGCD_LAUNCHED();
+  }
+  const int64_t npos = read_i64(P + n, st);  // positions of all streams
+  uint32_t *skey = a.take<uint32_t>(npos);
+  uint32_t *sw = a.take<uint32_t>(npos);
+  if (g.nnz > 0) {
+    k_agg_streamify<<<(unsigned)ceil_div(g.nnz, SF_TILE), BLOCK, 0, st>>>(g, D, rowpos, skey, sw);
+    MGCD_LAUNCHED();
+  }
+  AggStreams s{g, D, mem, mstart, P, rs, skey, sw};
   switch (mode) {
     case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, (int64_t)hc[8], st); break;
     case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, (int64_t)hc[8], st); break;
@@ -910,6 +977,7 @@ size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L, bo
   const int64_t nm = nnz / (64 * Lc) + 1, chunks = nnz / Lc + nm + 1;
   b += (size_t)(nm + 1) * 16 + scan_ws_bytes(nm) + (size_t)chunks * (4 + (size_t)k * sizeof(Pair)) + 8192;
   b += (size_t)n * k * sizeof(Pair) + (size_t)n * 4 + 4096;  // rows, rcount
+  b += (size_t)nnz * 8 + (size_t)n * 8 + 4096;               // laid-out streams, row positions
   if (symmetric) {
     // emit buffers (rows hold at most their stream: <= 2 min(k n, nnz) entries), sort, heads
     int64_t e2 = 2 * ((int64_t)n * k < nnz ? (int64_t)n * k : nnz);

@@ -23,6 +23,7 @@
 #include "move.hpp"
 #include "primitives.hpp"
 #include "sketch.hpp"
+#include "staging.hpp"
 #include "wave_sketch.hpp"
 
 namespace mgcd {
@@ -129,28 +130,18 @@ __device__ inline uint32_t stream_key(const SweepArgs &a, int32_t i, int32_t j, 
 
 // ---- MG: long rows -----------------------------------------------------------------
 
-constexpr int WIN = 16;        // staged positions per lane and window
-constexpr int WROW = 2 * WIN + 4;  // words per lane row: WIN (key, weight) pairs + pad; rows
-                                   // are 16-byte aligned and 8 consecutive lanes' rows start
-                                   // in distinct 4-bank groups (conflict-free 128-bit reads)
-
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Stage positions s0 .. s0+WIN-1 of every lane's chunk [clo, chi) of row i into the
-// wave's LDS window win (WAVE * WROW words, (key, weight) pairs).  Round r serves
-// the chunks of lanes 4r .. 4r+3, 16 lanes per chunk loading 16 consecutive entries
-// (64-byte segments instead of 64 scattered lines per load); the loads of 8 rounds
-// are in flight together.  GATHER: the keys are C[j] (with Algorithm 1's skips)
-// and are also written to the key stream; otherwise they are read from the key
-// stream.  Positions past a chunk's end stage (EMPTY, 0).
+// wave's LDS window (staging.hpp).  GATHER: the keys are C[j] (with Algorithm 1's
+// skips), gathered with the loads of 8 rounds in flight, and are also written to the
+// key stream; otherwise they are read from the key stream.
 template <int ALGO, bool GATHER>
 __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i, int32_t bi,
                                     int64_t clo, int64_t chi, int64_t s0, uint32_t *keybuf) {
-  constexpr int G = GATHER ? 8 : WIN;  // rounds per group of loads in flight
+  if constexpr (!GATHER) {
+    stage_pairs(win, clo, chi, s0, keybuf, a.g.w);
+    return;
+  }
+  constexpr int G = 8;  // rounds per group of loads in flight
   const int lane = lane_id();
 #pragma unroll
   for (int g0 = 0; g0 < WIN; g0 += G) {
@@ -163,11 +154,10 @@ __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i
       const bool v = e < __shfl(chi, src);
       ok |= v ? 1u << r : 0u;
       const int64_t es = v ? e : 0;
-      kk[r] = GATHER ? (uint32_t)__builtin_nontemporal_load(a.g.idx + es)
-                     : __builtin_nontemporal_load(keybuf + es);
+      kk[r] = (uint32_t)__builtin_nontemporal_load(a.g.idx + es);
       ww[r] = __builtin_nontemporal_load(a.g.w + es);
     }
-    if (GATHER) {
+    {
 #pragma unroll
       for (int r = 0; r < G; ++r) {
         const int src = (g0 + r) * 4 + (lane >> 4);
@@ -191,28 +181,9 @@ __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i
     }
 #pragma unroll
     for (int r = 0; r < G; ++r) {
-      const int src = (g0 + r) * 4 + (lane >> 4);
       const bool v = (ok >> r) & 1u;
-      typedef uint32_t v2u __attribute__((ext_vector_type(2)));
-      v2u pr;
-      pr.x = v ? kk[r] : EMPTY;
-      pr.y = v ? ww[r] : 0u;
-      *reinterpret_cast<v2u *>(win + src * WROW + 2 * (lane & 15)) = pr;
+      put_pair(win, (g0 + r) * 4 + (lane >> 4), v ? kk[r] : EMPTY, v ? ww[r] : 0u);
     }
-  }
-}
-
-// This lane's WIN staged keys and weights, read with 128-bit LDS loads.
-__device__ inline void read_window(const uint32_t *win, uint32_t (&kk)[WIN], uint32_t (&ww)[WIN]) {
-  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-  const v4u *p = reinterpret_cast<const v4u *>(win + lane_id() * WROW);
-#pragma unroll
-  for (int q = 0; q < WIN / 2; ++q) {
-    const v4u x = p[q];
-    kk[2 * q] = x.x;
-    ww[2 * q] = x.y;
-    kk[2 * q + 1] = x.z;
-    ww[2 * q + 1] = x.w;
   }
 }
 
@@ -242,16 +213,11 @@ __device__ inline void staged_sketch(const SweepArgs &a, RegSketch<K, MODE> &s, 
   }
 }
 
-// Rows of more than 64 chunks ("long rows") go through five launches, each with
-// enough independent work to fill the chip:
-//   k_long_keys    one wave per chunk: gather the keys C[j] into the key stream;
-//   k_long_chunks  one lane per chunk, one wave per aligned group of 64 chunks:
-//                  Algorithm 1 from an empty sketch over the staged keys (no
-//                  gather in the dependent chain), then the first six levels of
-//                  the fixed merge tree with shuffles;
-//   k_long_merge   one workgroup per row: the rest of the fixed merge tree over
-//                  its group roots; a row whose sketch lost no weight is decided
-//                  here;
+// Rows of more than 64 chunks ("long rows"): the main sweep kernel sketches their
+// chunks, one wave per aligned group of 64 chunks (long_group), and merges each
+// group with the first six levels of the fixed tree; then
+//   k_long_merge   one workgroup per row: the rest of the fixed merge tree over its
+//                  group roots; a row whose sketch lost no weight is decided here;
 //   k_long_count   one wave per chunk of a lossy row: pass 2 against the row's
 //                  candidates, partial counts per chunk;
 //   k_long_decide  one workgroup per lossy row: sum the partial counts, decide.

@@ -334,12 +334,21 @@ __global__ void __launch_bounds__(BLOCK)
   }
   __syncthreads();
   if (threadIdx.x < 8 && bc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], bc[threadIdx.x]);
+  // block maximum, then one atomic per block, skipped when it cannot raise the value
+  __shared__ unsigned long long bmax[BLOCK / WAVE];
 #pragma unroll
   for (int o = WAVE / 2; o > 0; o >>= 1) {
     const int64_t x = __shfl_xor(lmax, o);
     lmax = x > lmax ? x : lmax;
   }
-  if (lane_id() == 0 && lmax > 0) atomicMax(&cnt[8], (unsigned long long)lmax);  // longest stream
+  if (lane_id() == 0) bmax[threadIdx.x / WAVE] = (unsigned long long)lmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long mx = bmax[0];
+    for (int q = 1; q < BLOCK / WAVE; ++q) mx = bmax[q] > mx ? bmax[q] : mx;
+    if (mx > 0 && mx > __hip_atomic_load(&cnt[8], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&cnt[8], mx);
+  }  // longest stream
 }
 
 __global__ void k_comm_chunks(const int32_t *mstart, const int64_t *P, const int32_t *multi,
@@ -349,6 +358,11 @@ __global__ void k_comm_chunks(const int32_t *mstart, const int64_t *P, const int
   int32_t c = multi[x];
   int64_t len = P[mstart[c + 1]] - P[mstart[c]];
   nch[x] = (len + L - 1) / L;
+}
+
+__global__ void k_comm_groups(const int64_t *cstart, int64_t nmulti, int64_t *ng) {
+  int64_t x = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (x < nmulti) ng[x] = (cstart[x + 1] - cstart[x] + WAVE - 1) / WAVE;
 }
 
 __global__ void k_comm_owner(const int64_t *cstart, int64_t nmulti, int32_t *owner) {
@@ -507,36 +521,65 @@ __device__ inline void write_row(uint32_t (&k)[K], uint32_t (&v)[K], int32_t c, 
   rcount[c] = x;
 }
 
+// Streams of more than 64 chunks.
+struct AggLong {
+  const int32_t *multi;   // [nmulti] such communities
+  int64_t nmulti;
+  const int64_t *cstart;  // [nmulti+1] first chunk of each
+  const int64_t *gstart;  // [nmulti+1] first group of 64 chunks of each
+  const int32_t *gowner;  // [ngroups] community index (into multi) of each group
+  int64_t ngroups;
+  Pair *skbuf;            // [ngroups * K] group roots
+};
+
+// Wave w takes the aligned group of 64 chunks gstart[x] .. of long stream x (lane =
+// chunk within the group): the staged fold of each chunk, then the first six
+// levels of the fixed merge tree with shuffles; lane 0 writes the group's root.
 template <int K, int MODE>
-__global__ void __launch_bounds__(BLOCK)
-    k_agg_chunks(AggStreams s, const int32_t *multi, const int32_t *owner, const int64_t *cstart,
-                 int64_t nchunks, int64_t L, Pair *skbuf) {
+__global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
+    k_agg_chunks(AggStreams s, AggLong lg, int64_t L) {
   __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
-  int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  int64_t p0 = 0, p1 = 0;
-  if (q < nchunks) {
-    const int32_t x = owner[q];
-    const int32_t c = multi[x];
-    const int64_t base = s.P[s.mstart[c]], end = s.P[s.mstart[c + 1]];
-    p0 = base + (q - cstart[x]) * L;
-    p1 = p0 + L < end ? p0 + L : end;
-  }
+  const int64_t w = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
+  if (w >= lg.ngroups) return;
+  const int lane = lane_id();
+  const int32_t x = lg.gowner[w];
+  const int32_t c = lg.multi[x];
+  const int64_t nc = lg.cstart[x + 1] - lg.cstart[x];
+  const int64_t q = (w - lg.gstart[x]) * WAVE + lane;  // chunk index within the stream
+  const int64_t base = s.P[s.mstart[c]], end = s.P[s.mstart[c + 1]];
+  const int64_t p0 = base + q * L;
+  const int64_t p1 = q < nc ? (p0 + L < end ? p0 + L : end) : p0;
   RegSketch<K, MODE> sk;
   sk.reset();
   staged_fold<K, MODE>(sk, swin[threadIdx.x / WAVE], p0, p1, s.skey, s.sw);
-  if (q >= nchunks) return;
   sk.finalize();
+#pragma unroll 1
+  for (int l = 0; l < 6; ++l) {
+    const int stride = 1 << l;
+    uint32_t bk_[K], bv_[K];
 #pragma unroll
-  for (int p = 0; p < K; ++p) skbuf[q * K + p] = Pair{sk.key[p], sk.val[p]};
+    for (int p = 0; p < K; ++p) {
+      bk_[p] = __shfl_down(sk.key[p], stride);
+      bv_[p] = __shfl_down(sk.val[p], stride);
+    }
+    const int64_t c_l = (nc + stride - 1) >> l;  // nodes at level l
+    const bool left = (lane & ((2 << l) - 1)) == 0;
+    if (left && (q >> l) + 1 < c_l) merge_sketch<K>(sk.key, sk.val, bk_, bv_);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int p = 0; p < K; ++p)
+      lg.skbuf[w * K + p] = Pair{sk.val[p] > 0 ? sk.key[p] : EMPTY, sk.val[p]};
+  }
 }
 
 template <int K>
 __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
-    k_agg_multi(const int32_t *multi, const int64_t *cstart, Pair *skbuf, Pair *rows, uint32_t *rcount) {
+    k_agg_multi(AggLong lg, Pair *rows, uint32_t *rcount) {
   __shared__ Pair lds[BLOCK * K];
   const int32_t x = blockIdx.x;
-  const int32_t c = multi[x];
-  tree_reduce<K>(skbuf, cstart[x], cstart[x + 1] - cstart[x], lds);
+  const int32_t c = lg.multi[x];
+  tree_reduce<K>(lg.skbuf, lg.gstart[x], lg.gstart[x + 1] - lg.gstart[x], lds);  // group roots
   if (threadIdx.x == 0) {
     uint32_t k[K], v[K];
 #pragma unroll
@@ -720,13 +763,12 @@ static void agg_wave(const AggStreams &s, const int32_t *comms, int64_t ncomm, i
 }
 
 template <int K, int MODE>
-static void agg_mg(const AggStreams &s, const AggBuckets &bk, int64_t waves, const int32_t *multi,
-                   int64_t nmulti, const int64_t *cstart, const int32_t *owner, int64_t nchunks,
-                   int64_t L, Pair *skbuf, Pair *rows, uint32_t *rcount, hipStream_t st) {
-  if (nmulti > 0) {
-    k_agg_chunks<K, MODE><<<grid_for(nchunks), BLOCK, 0, st>>>(s, multi, owner, cstart, nchunks, L, skbuf);
+static void agg_mg(const AggStreams &s, const AggBuckets &bk, int64_t waves, const AggLong &lg,
+                   int64_t L, Pair *rows, uint32_t *rcount, hipStream_t st) {
+  if (lg.nmulti > 0) {
+    k_agg_chunks<K, MODE><<<(unsigned)ceil_div(lg.ngroups, BLOCK / WAVE), BLOCK, 0, st>>>(s, lg, L);
     MGCD_LAUNCHED();
-    k_agg_multi<K><<<(unsigned)nmulti, BLOCK, 0, st>>>(multi, cstart, skbuf, rows, rcount);
+    k_agg_multi<K><<<(unsigned)lg.nmulti, BLOCK, 0, st>>>(lg, rows, rcount);
     MGCD_LAUNCHED();
   }
   if (waves > 0) {
@@ -736,18 +778,17 @@ static void agg_mg(const AggStreams &s, const AggBuckets &bk, int64_t waves, con
 }
 
 template <int MODE>
-static void agg_mg_k(int k, const AggStreams &s, const AggBuckets &bk, int64_t waves, const int32_t *multi,
-                     int64_t nmulti, const int64_t *cstart, const int32_t *owner, int64_t nchunks, int64_t L,
-                     Pair *skbuf, Pair *rows, uint32_t *rcount, const int32_t *all, int64_t m,
+static void agg_mg_k(int k, const AggStreams &s, const AggBuckets &bk, int64_t waves, const AggLong &lg,
+                     int64_t L, Pair *rows, uint32_t *rcount, const int32_t *all, int64_t m,
                      int64_t max_len, hipStream_t st) {
   switch (k) {
     case 32: agg_wave<32, MODE>(s, all, m, L, rows, rcount, max_len, st); break;
     case 64: agg_wave<64, MODE>(s, all, m, L, rows, rcount, max_len, st); break;
-    case 1: agg_mg<1, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case 2: agg_mg<2, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case 4: agg_mg<4, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case 8: agg_mg<8, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
-    case 16: agg_mg<16, MODE>(s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, st); break;
+    case 1: agg_mg<1, MODE>(s, bk, waves, lg, L, rows, rcount, st); break;
+    case 2: agg_mg<2, MODE>(s, bk, waves, lg, L, rows, rcount, st); break;
+    case 4: agg_mg<4, MODE>(s, bk, waves, lg, L, rows, rcount, st); break;
+    case 8: agg_mg<8, MODE>(s, bk, waves, lg, L, rows, rcount, st); break;
+    case 16: agg_mg<16, MODE>(s, bk, waves, lg, L, rows, rcount, st); break;
     default: throw Error(-6, "k_aggregate must be 1, 2, 4, 8, 16, 32 or 64");
   }
 }
@@ -879,20 +920,25 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   }
   const int64_t nmulti = (int64_t)hc[7];
   int32_t *multi = corder + pos;
-  int64_t *cstart = nullptr, nchunks = 0;
-  int32_t *owner = nullptr;
-  Pair *skbuf = nullptr;
+  int64_t *cstart = nullptr;
+  AggLong lg{multi, nmulti, nullptr, nullptr, nullptr, 0, nullptr};
   if (nmulti > 0) {
     int64_t *nch = a.take<int64_t>(nmulti);
     cstart = a.take<int64_t>(nmulti + 1);
     k_comm_chunks<<<grid_for(nmulti), BLOCK, 0, st>>>(mstart, P, multi, nmulti, L, nch);
     MGCD_LAUNCHED();
     scan_i64(nch, cstart, nmulti, cstart + nmulti, a, st);
-    nchunks = read_i64(cstart + nmulti, st);
-    owner = a.take<int32_t>(nchunks);
-    k_comm_owner<<<(unsigned)nmulti, BLOCK, 0, st>>>(cstart, nmulti, owner);
+    // groups of 64 chunks per long stream
+    int64_t *ng = a.take<int64_t>(nmulti);
+    int64_t *gstart = a.take<int64_t>(nmulti + 1);
+    k_comm_groups<<<grid_for(nmulti), BLOCK, 0, st>>>(cstart, nmulti, ng);
     MGCD_LAUNCHED();
-    skbuf = a.take<Pair>(nchunks * k);
+    scan_i64(ng, gstart, nmulti, gstart + nmulti, a, st);
+    const int64_t ngroups = read_i64(gstart + nmulti, st);
+    int32_t *gowner = a.take<int32_t>(ngroups);
+    k_comm_owner<<<(unsigned)nmulti, BLOCK, 0, st>>>(gstart, nmulti, gowner);
+    MGCD_LAUNCHED();
+    lg = AggLong{multi, nmulti, cstart, gstart, gowner, ngroups, a.take<Pair>(ngroups * k)};
   }
   Pair *rows = a.take<Pair>((int64_t)m * k);
   uint32_t *rcount = a.take<uint32_t>(m);
@@ -915,9 +961,9 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   }
   AggStreams s{g, D, mem, mstart, P, rs, skey, sw};
   switch (mode) {
-    case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, (int64_t)hc[8], st); break;
-    case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, (int64_t)hc[8], st); break;
-    case MODE_STD: agg_mg_k<MODE_STD>(k, s, bk, waves, multi, nmulti, cstart, owner, nchunks, L, skbuf, rows, rcount, corder, m, (int64_t)hc[8], st); break;
+    case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, bk, waves, lg, L, rows, rcount, corder, m, (int64_t)hc[8], st); break;
+    case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, bk, waves, lg, L, rows, rcount, corder, m, (int64_t)hc[8], st); break;
+    case MODE_STD: agg_mg_k<MODE_STD>(k, s, bk, waves, lg, L, rows, rcount, corder, m, (int64_t)hc[8], st); break;
     default: throw Error(-6, "unknown sketch mode");
   }
   int64_t total = 0;

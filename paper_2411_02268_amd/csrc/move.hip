@@ -935,12 +935,21 @@ __global__ void __launch_bounds__(BLOCK)
   }
   __syncthreads();
   if (threadIdx.x < NCAT && bc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], bc[threadIdx.x]);
+  // block maximum, then one atomic per block, skipped when it cannot raise the value
+  __shared__ unsigned long long bmax[BLOCK / WAVE];
 #pragma unroll
   for (int o = WAVE / 2; o > 0; o >>= 1) {
     const int64_t x = __shfl_xor(dmax, o);
     dmax = x > dmax ? x : dmax;
   }
-  if (lane_id() == 0 && dmax > 0) atomicMax(&cnt[NCAT], (unsigned long long)dmax);  // longest row
+  if (lane_id() == 0) bmax[threadIdx.x / WAVE] = (unsigned long long)dmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long mx = bmax[0];
+    for (int q = 1; q < BLOCK / WAVE; ++q) mx = bmax[q] > mx ? bmax[q] : mx;
+    if (mx > 0 && mx > __hip_atomic_load(&cnt[NCAT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&cnt[NCAT], mx);
+  }  // longest row
 }
 
 __global__ void k_chunk_counts(const int64_t *off, const int32_t *multi, int64_t nmulti, int64_t L,

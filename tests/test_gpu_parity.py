@@ -99,7 +99,7 @@ def test_refine_parity(mg, gname, mode, k, L):
 @pytest.mark.parametrize("mode,k,L", [("exact", 8, 128), ("alg1", 1, 128), ("alg1", 4, 11),
                                       ("alg1", 8, 128), ("alg1", 16, 40), ("uncond", 8, 64),
                                       ("alg1", 64, 128), ("alg1", 32, 5), ("std", 64, 9),
-                                      ("uncond", 32, 64)])
+                                      ("uncond", 32, 64), ("alg1", 8, 1), ("std", 4, 2)])
 @pytest.mark.parametrize("symmetric", [False, True])
 def test_aggregate_parity(mg, gname, mode, k, L, symmetric):
     g = graph(gname)
@@ -286,10 +286,11 @@ def test_batched_equals_solo(mg, algo, mode, k, L, direct):
         assert np.array_equal(_np(lab), elab)
 
 
-@pytest.mark.parametrize("k", [32, 64])
+@pytest.mark.parametrize("k", [8, 16, 32, 64])
 def test_wave_sketch_deep_merge_tree(mg, k):
-    """A hub row of 6,000 entries with L = 1 needs a merge tree of more than 4,096
-    chunk sketches (the deep stack); its sweep and aggregation match the oracle."""
+    """A hub row of 6,000 entries with L = 1: a merge tree of more than 4,096 chunk
+    sketches (the deep stack of the wave sketch at k >= 32; about 94 groups of 64
+    chunks at k <= 16); its sweep and aggregation match the oracle."""
     rng = np.random.default_rng(31)
     n = 6001
     edges = [(0, v) for v in range(1, n)]

@@ -178,8 +178,8 @@ __global__ void k_batch_converge(unsigned long long *gctr, uint8_t *active, long
   const int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (g >= count) return;
   unsigned long long *c = gctr + 3 * g;
-  const unsigned long long moved = c[0], prop = c[1], sumG = c[2];
-  c[0] = c[1] = c[2] = 0;
+  const unsigned long long moved = atomicExch(&c[0], 0ull), prop = atomicExch(&c[1], 0ull),
+                           sumG = atomicExch(&c[2], 0ull);
   if (!active[g]) return;
   stat[3 * g] += 1;
   stat[3 * g + 1] += nent[g];

@@ -26,20 +26,28 @@ static thread_local std::string g_last_error;
 
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 
-// Per-kernel-class device time of level-0 sweeps.
+// Sweeps issued between two host reads of a level's device-side state: the stopping
+// rule is applied on the device after every sweep (LevelState), so a segment runs
+// without host round trips; sweeps issued after the rule fired leave every vertex
+// where it is.
+constexpr int SEG = 4;
+
+// Per-kernel-class device time of level-0 sweeps: four events per sweep of a segment.
 struct ClassTimer {
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[SEG][4] = {};
   ClassTimer() {
-    for (auto &e : ev) MGCD_HIP(hipEventCreate(&e));
+    for (auto &row : ev)
+      for (auto &e : row) MGCD_HIP(hipEventCreate(&e));
   }
   ~ClassTimer() {
-    for (auto &e : ev)
-      if (e) (void)hipEventDestroy(e);
+    for (auto &row : ev)
+      for (auto &e : row)
+        if (e) (void)hipEventDestroy(e);
   }
-  void add(mgcd_stats &s) {  // after the sweep has completed
+  void add(mgcd_stats &s, int j) {  // after sweep j of the segment has completed
     for (int q = 0; q < 3; ++q) {
       float ms = 0;
-      MGCD_HIP(hipEventElapsedTime(&ms, ev[q], ev[q + 1]));
+      MGCD_HIP(hipEventElapsedTime(&ms, ev[j][q], ev[j][q + 1]));
       s.ms_l0_kernel[q] += ms;
     }
     s.l0_sweeps += 1;
@@ -106,6 +114,11 @@ static void require_labels(const int32_t *C, int64_t n, int64_t limit, Arena &a,
   if (read_dev(flag, st) != 0) throw Error(MGCD_E_ARG, std::string(what) + " has values out of range");
 }
 
+// Runs the local-moving sweeps of one level: sweep(it, slot) issues sweep `it`
+// (slot: its place in the segment, for the level-0 events) and returns nothing;
+// the sweeps stop once the device-side stopping rule fired or after max_it sweeps.
+// Returns the level's state; class timings of the counted sweeps go to `ct` when
+// given.
 struct Counts {
   unsigned long long moved, prop, sumG;
 };
@@ -115,6 +128,23 @@ static Counts read_counts(const unsigned long long *ctr, hipStream_t st) {
   MGCD_HIP(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, st));
   MGCD_HIP(hipStreamSynchronize(st));
   return Counts{h[0], h[1], h[2]};
+}
+
+template <typename F>
+static LevelState run_sweeps(int max_it, LevelState *ls, hipStream_t st, ClassTimer *ct, mgcd_stats &s,
+                             F &&sweep) {
+  LevelState h{};
+  for (int it = 0; it < max_it;) {
+    const int seg = max_it - it < SEG ? max_it - it : SEG;
+    for (int j = 0; j < seg; ++j) sweep(it + j, j);
+    const uint32_t before = h.sweeps;
+    h = read_dev(ls, st);
+    if (ct)
+      for (uint32_t j = 0; j < h.sweeps - before; ++j) ct->add(s, (int)j);
+    it += seg;
+    if (h.halt) break;
+  }
+  return h;
 }
 
 // ---- LPA ------------------------------------------------------------------------------
@@ -133,23 +163,25 @@ static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Are
   launch_iota(Ca, n, st);
   Schedule sch;
   build_schedule(g, sched_params(p), sch, a, st);
+  LevelState *ls = a.take<LevelState>(1);
   mgcd_stats s{};
-  float ms_lm = 0;
   ClassTimer ct;
-  for (int it = 0; it < p->max_iterations && n > 0; ++it) {
-    launch_zero_u64(ctr, 3, st);
-    SweepArgs args{g, Ca, nullptr, K, nullptr, 0, 0, Cb, nullptr, ctr};
-    lm.start();
-    launch_sweep(args, sch, ALGO_LPA, p->mode, p->k, p->chunk_len, st, ct.ev);
-    ms_lm += lm.stop();
-    ct.add(s);
-    Counts c = read_counts(ctr, st);
-    std::swap(Ca, Cb);
-    s.iterations += 1;
-    s.edges_scanned += g.nnz;
-    s.moved_last = (int64_t)c.moved;
-    if ((double)c.moved <= p->tolerance * (double)n) break;
+  lm.start();
+  launch_zero_u64(ctr, 3, st);
+  launch_zero_state(ls, st);
+  if (n > 0) {
+    LevelState h = run_sweeps(p->max_iterations, ls, st, &ct, s, [&](int, int j) {
+      SweepArgs args{g, Ca, nullptr, K, nullptr, 0, 0, Cb, nullptr, ctr};
+      args.halt = &ls->halt;
+      launch_sweep(args, sch, ALGO_LPA, p->mode, p->k, p->chunk_len, st, ct.ev[j]);
+      launch_level_converge(ALGO_LPA, ctr, ls, g.nnz, n, p->tolerance, 0.0, st);
+      std::swap(Ca, Cb);  // a halted sweep copies C, so either buffer holds the result
+    });
+    s.iterations = h.sweeps;
+    s.edges_scanned = (int64_t)h.edges;
+    s.moved_last = (int64_t)h.moved_last;
   }
+  const float ms_lm = lm.stop();
   s.communities = canonical(Ca, n, out, a, st);
   s.passes = 1;
   s.ms_local_move = ms_lm;
@@ -179,6 +211,7 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
   int32_t *nprop = leiden ? a.take<int32_t>(n) : nullptr;
   int32_t *from = leiden ? a.take<int32_t>(n) : nullptr;
   unsigned long long *ctr = a.take<unsigned long long>(4);
+  LevelState *ls = a.take<LevelState>(1);
   struct Slot {
     int64_t *off;
     int32_t *idx;
@@ -207,23 +240,21 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
     build_schedule(cur, sched_params(p), sch, a, st);
     if (!leiden) launch_iota(Ca, nl, st);
     launch_community_totals(Ca, K, Sig, size, nl, st);
-    ms_lm += tm.stop();
-    for (int it = 0; it < p->max_iterations; ++it) {
-      launch_zero_u64(ctr, 3, st);
+    launch_zero_u64(ctr, 3, st);
+    launch_zero_state(ls, st);
+    LevelState h = run_sweeps(p->max_iterations, ls, st, pass == 0 ? &ct : nullptr, s, [&](int it, int j) {
       SweepArgs args{cur, Ca, nullptr, K, Sig, W, (it % 2 == 0) ? -1 : 1, Cb, nullptr, ctr};
-      tm.start();
-      launch_sweep(args, sch, ALGO_MOVE, p->mode, p->k, p->chunk_len, st, pass == 0 ? ct.ev : nullptr);
-      ms_lm += tm.stop();
-      if (pass == 0) ct.add(s);
-      Counts c = read_counts(ctr, st);
-      s.iterations += 1;
-      s.edges_scanned += cur.nnz;
-      s.moved_last = (int64_t)c.moved;
-      if (c.prop == 0) break;
+      args.halt = &ls->halt;
+      launch_sweep(args, sch, ALGO_MOVE, p->mode, p->k, p->chunk_len, st, pass == 0 ? ct.ev[j] : nullptr);
+      // a sweep without positive moves, or a halted one, leaves C_new equal to C
       launch_apply_moves(Ca, Cb, K, Sig, size, nl, st);
+      launch_level_converge(ALGO_MOVE, ctr, ls, cur.nnz, nl, tol, WW, st);
       std::swap(Ca, Cb);
-      if (2.0 * (double)c.sumG <= tol * WW) break;
-    }
+    });
+    ms_lm += tm.stop();
+    s.iterations += h.sweeps;
+    s.edges_scanned += (int64_t)h.edges;
+    s.moved_last = (int64_t)h.moved_last;
     int32_t m;
     bool last;
     if (leiden) {

@@ -48,7 +48,7 @@ __device__ inline uint64_t weight_of(const SweepArgs &a, int32_t i) {
 
 // Batched runs: a vertex of a graph that no longer moves keeps its community.
 __device__ inline bool frozen(const SweepArgs &a, int32_t i) {
-  return a.gid && !a.active[a.gid[i]];
+  return (a.halt && *a.halt) || (a.gid && !a.active[a.gid[i]]);
 }
 
 template <int ALGO>
@@ -1326,6 +1326,34 @@ __global__ void k_iota(int32_t *p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (i < n) p[i] = (int32_t)i;
 }
+__global__ void k_level_converge(int algo, unsigned long long *ctr, LevelState *ls, int64_t nnz,
+                                 int32_t n, double tol, double WW) {
+  // Read and clear in one atomic step: a plain load of these uniform addresses may
+  // become a scalar load, which a following vector store of 0 can overtake.
+  const unsigned long long moved = atomicExch(&ctr[0], 0ull), prop = atomicExch(&ctr[1], 0ull),
+                           sumG = atomicExch(&ctr[2], 0ull);
+  if (ls->halt) return;
+  ls->sweeps += 1;
+  ls->edges += (unsigned long long)nnz;
+  ls->moved_last = moved;
+  const bool stop = algo == ALGO_LPA ? (double)moved <= tol * (double)n
+                                     : prop == 0 || 2.0 * (double)sumG <= tol * WW;
+  if (stop) ls->halt = 1;
+}
+
+void launch_level_converge(int algo, unsigned long long *ctr, LevelState *ls, int64_t nnz, int32_t n,
+                           double tol, double WW, hipStream_t st) {
+  k_level_converge<<<1, 1, 0, st>>>(algo, ctr, ls, nnz, n, tol, WW);
+  MGCD_LAUNCHED();
+}
+
+__global__ void k_zero_state(LevelState *ls) { *ls = LevelState{0, 0, 0, 0}; }
+
+void launch_zero_state(LevelState *ls, hipStream_t st) {
+  k_zero_state<<<1, 1, 0, st>>>(ls);
+  MGCD_LAUNCHED();
+}
+
 __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (i < n) p[i] = 0;

@@ -24,7 +24,26 @@ struct SweepArgs {
   const uint32_t *Wg = nullptr;
   const uint8_t *active = nullptr;
   unsigned long long *gctr = nullptr;
+  // Single graph: a device flag; once set, every vertex keeps its community (the
+  // sweep only copies C to C_new).  Null: always move.
+  const uint32_t *halt = nullptr;
 };
+
+// A single graph's level, kept on the device so that sweeps need no host round trip:
+// set `halt` when the level's stopping rule fires; count sweeps, streamed entries
+// and the last sweep's movers.
+struct LevelState {
+  uint32_t halt;
+  uint32_t sweeps;
+  unsigned long long edges;
+  unsigned long long moved_last;
+};
+// After a sweep: apply the stopping rule of LPA (movers <= tol * n) or of Louvain
+// local moving (no positive move, or 2 * summed gain <= tol * W^2) to the counters
+// ctr, clear them, update the state.
+void launch_level_converge(int algo, unsigned long long *ctr, LevelState *ls, int64_t nnz, int32_t n,
+                           double tol, double WW, hipStream_t st);
+void launch_zero_state(LevelState *ls, hipStream_t st);
 
 // Row buckets of the main sweep kernel: rows needing 2^b lanes (b = 0..6).
 // The grid of the main sweep kernel: first one wave per group of 64 chunks of the

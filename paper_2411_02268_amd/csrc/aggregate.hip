@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(BLOCK)
   tot = wave_sum(tot);
   if (lane_id() == 0) lw[threadIdx.x / WAVE] = tot;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(&terms[0], lw[0] + lw[1] + lw[2] + lw[3]);
+  if (threadIdx.x == 0) atomicAdd(&terms[2 * spread_copy()], lw[0] + lw[1] + lw[2] + lw[3]);
 }
 
 __global__ void k_comm_tot(const int32_t *C, const uint32_t *K, int32_t n, uint32_t *tot) {
@@ -203,18 +203,12 @@ __global__ void __launch_bounds__(BLOCK)
   int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   unsigned long long x = c < n ? (unsigned long long)tot[c] : 0ull;
   unsigned long long s = block_sum(x * x, lw);
-  if (threadIdx.x == 0) atomicAdd(&terms[1], s);
-}
-
-__global__ void k_zero2(unsigned long long *p) {
-  p[0] = 0;
-  p[1] = 0;
+  if (threadIdx.x == 0 && s) atomicAdd(&terms[2 * spread_copy() + 1], s);
 }
 
 void modularity_terms(const Graph &g, const int32_t *C, const uint32_t *K, unsigned long long *terms,
                       Arena &a, hipStream_t st) {
-  k_zero2<<<1, 1, 0, st>>>(terms);
-  MGCD_LAUNCHED();
+  launch_zero_u64(terms, 2 * SPREAD, st);
   if (g.n == 0) return;
   size_t mk = a.mark();
   uint32_t *tot = a.take<uint32_t>(g.n);
@@ -333,6 +327,7 @@ __global__ void __launch_bounds__(BLOCK)
     if (lane_id() == 0 && mk) atomicAdd(&bc[q], (unsigned long long)__popcll(mk));
   }
   __syncthreads();
+  cnt += spread_copy() * 9;
   if (threadIdx.x < 8 && bc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], bc[threadIdx.x]);
   // block maximum, then one atomic per block, skipped when it cannot raise the value
   __shared__ unsigned long long bmax[BLOCK / WAVE];
@@ -395,11 +390,12 @@ __global__ void k_row_pos(const uint32_t *mem, const int64_t *P, int32_t nmem, i
 
 // Lay the community streams out contiguously: entry e of row i goes to position
 // rowpos[i] + (e - off[i]) with key D[j] and its weight.  A workgroup takes SF_TILE
-// consecutive entries (balanced whatever the row lengths): the rows spanning the
-// tile are found once (binary search), their offsets staged in LDS, and each entry
-// finds its row there; a tile spanning more rows than fit searches the offsets in
-// global memory instead.
-constexpr int SF_ITEMS = 8, SF_TILE = BLOCK * SF_ITEMS, SF_ROWS = SF_TILE;
+// consecutive entries (balanced whatever the row lengths).  The rows spanning the
+// tile are r0 .. r1 (two binary searches); every row r0 < r <= r1 marks its first
+// position in an LDS count array, whose inclusive prefix sum then gives each
+// entry's row as r0 + count (no per-entry search); entries are read and written in
+// coalesced order.
+constexpr int SF_ITEMS = 8, SF_TILE = BLOCK * SF_ITEMS;
 
 __device__ inline int32_t row_of_entry(const int64_t *off, int32_t lo, int32_t hi, int64_t e) {
   // the largest r in [lo, hi] with off[r] <= e (the last of equal offsets: a row
@@ -413,42 +409,51 @@ __device__ inline int32_t row_of_entry(const int64_t *off, int32_t lo, int32_t h
 
 __global__ void __launch_bounds__(BLOCK)
     k_agg_streamify(Graph g, const int32_t *D, const int64_t *rowpos, uint32_t *skey, uint32_t *sw) {
-  __shared__ int64_t soff[SF_ROWS + 1];
+  __shared__ uint32_t starts[SF_TILE];
+  __shared__ uint32_t wsum[BLOCK / WAVE];
   __shared__ int32_t sr[2];
   const int64_t e0 = (int64_t)blockIdx.x * SF_TILE;
   const int64_t e1 = e0 + SF_TILE < g.nnz ? e0 + SF_TILE : g.nnz;
+  for (int x = threadIdx.x; x < SF_TILE; x += BLOCK) starts[x] = 0;
   if (threadIdx.x == 0) sr[0] = row_of_entry(g.off, 0, g.n - 1, e0);
   if (threadIdx.x == 1) sr[1] = row_of_entry(g.off, 0, g.n - 1, e1 - 1);
   __syncthreads();
   const int32_t r0 = sr[0], r1 = sr[1];
-  const int32_t nr = r1 - r0 + 1;
-  const bool staged = nr <= SF_ROWS;
-  if (staged)
-    for (int32_t k = threadIdx.x; k <= nr; k += BLOCK) soff[k] = g.off[r0 + k];
+  // rows r0 < r <= r1 start inside the tile (off[r0 + 1] > e0, off[r1] <= e1 - 1)
+  for (int64_t r = (int64_t)r0 + 1 + threadIdx.x; r <= r1; r += BLOCK)
+    atomicAdd(&starts[g.off[r] - e0], 1u);
+  __syncthreads();
+  // inclusive prefix sum of the counts: thread t owns positions SF_ITEMS*t ..
+  const int t = threadIdx.x, w = t / WAVE;
+  uint32_t v[SF_ITEMS], run = 0;
+#pragma unroll
+  for (int q = 0; q < SF_ITEMS; ++q) {
+    v[q] = starts[t * SF_ITEMS + q];
+    run += v[q];
+  }
+  const uint32_t incl = wave_inclusive_scan(run);
+  if (lane_id() == WAVE - 1) wsum[w] = incl;
+  __syncthreads();
+  uint32_t acc = incl - run;
+  for (int q = 0; q < w; ++q) acc += wsum[q];
+#pragma unroll
+  for (int q = 0; q < SF_ITEMS; ++q) {
+    acc += v[q];
+    starts[t * SF_ITEMS + q] = acc;
+  }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < SF_ITEMS; ++q) {
-    const int64_t e = e0 + (int64_t)q * BLOCK + threadIdx.x;
-    if (e >= e1) break;
-    int32_t r;
-    int64_t rb;
-    if (staged) {
-      int32_t lo = 0, hi = nr - 1;
-      while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (soff[mid] <= e) lo = mid; else hi = mid - 1;
+    const int64_t e = e0 + (int64_t)q * BLOCK + t;
+    if (e < e1) {
+      const int32_t r = r0 + (int32_t)starts[e - e0];
+      const int64_t p = rowpos[r];
+      if (p >= 0) {
+        const int64_t pos = p + (e - g.off[r]);
+        skey[pos] = (uint32_t)D[__builtin_nontemporal_load(g.idx + e)];
+        sw[pos] = __builtin_nontemporal_load(g.w + e);
       }
-      r = r0 + lo;
-      rb = soff[lo];
-    } else {
-      r = row_of_entry(g.off, r0, r1, e);
-      rb = g.off[r];
     }
-    const int64_t p = rowpos[r];
-    if (p < 0) continue;
-    const int64_t pos = p + (e - rb);
-    skey[pos] = (uint32_t)D[__builtin_nontemporal_load(g.idx + e)];
-    sw[pos] = __builtin_nontemporal_load(g.w + e);
   }
 }
 
@@ -891,8 +896,8 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   MGCD_LAUNCHED();
   scan_u32_i64(mdeg, P, n, P + n, a, st);
   // communities: short streams (one lane each) vs long ones (chunks + merge tree)
-  unsigned long long *cnt = a.take<unsigned long long>(9);
-  launch_zero_u64(cnt, 9, st);
+  unsigned long long *cnt = a.take<unsigned long long>(SPREAD * 9);
+  launch_zero_u64(cnt, SPREAD * 9, st);
   uint64_t *ck0 = a.take<uint64_t>(m), *ck1 = a.take<uint64_t>(m);
   uint32_t *cv0 = a.take<uint32_t>(m), *cv1 = a.take<uint32_t>(m);
   k_comm_keys<<<grid_for(m), BLOCK, 0, st>>>(mstart, P, m, L, ck0, cv0, cnt);
@@ -902,7 +907,7 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   k_u32_to_i32<<<grid_for(m), BLOCK, 0, st>>>(cf ? cv1 : cv0, corder, m);
   MGCD_LAUNCHED();
   unsigned long long hc[9];
-  MGCD_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
+  read_spread(cnt, 8, hc, st);
   MGCD_HIP(hipStreamSynchronize(st));
   AggBuckets bk{};
   int64_t pos = 0, waves = 0;

@@ -41,9 +41,10 @@ size_t degrees_ws_bytes(int64_t nnz);
 // Returns the number of communities (synchronises the stream).
 int32_t canonical(const int32_t *C, int32_t n, int32_t *out, Arena &a, hipStream_t st);
 
-// Integers of Eq. 1: I = weight of intra-community entries, S2 = sum of Sigma_c^2.
+// Integers of Eq. 1: I = weight of intra-community entries, S2 = sum of Sigma_c^2,
+// accumulated in SPREAD copies: terms[2c] (parts of I) and terms[2c + 1] (parts of S2).
 void modularity_terms(const Graph &g, const int32_t *C, const uint32_t *K,
-                      unsigned long long *terms /* device [2] */, Arena &a, hipStream_t st);
+                      unsigned long long *terms /* device [2 * SPREAD] */, Arena &a, hipStream_t st);
 
 // *flag = 1 when some C[i] (i < n) lies outside [0, limit).
 void launch_check_labels(const int32_t *C, int64_t n, int64_t limit, unsigned long long *flag,

@@ -209,7 +209,6 @@ struct LevelSweeps {
   Graph g;
   int32_t *C[2];
   uint32_t *K, *Sig;
-  int32_t *size;
   int32_t *gid;
   uint32_t *Wg;
   unsigned long long *Wg64;
@@ -246,7 +245,7 @@ static void level_sweeps(LevelSweeps &L, const mgcd_params *p, const Schedule &s
       args.active = L.active;
       args.gctr = L.gctr;
       launch_sweep(args, sch, L.algo, p->mode, p->k, p->chunk_len, s);
-      if (L.algo != ALGO_LPA) launch_apply_moves(L.C[0], L.C[1], L.K, L.Sig, L.size, L.g.n, s);
+      if (L.algo != ALGO_LPA) launch_apply_moves(L.C[0], L.C[1], L.K, L.Sig, L.g.n, s);
       if (L.algo == ALGO_LPA)
         k_batch_converge<ALGO_LPA><<<grid_for(L.count), BLOCK, 0, s>>>(
             L.gctr, L.active, L.stat, L.nent, L.nvert, L.Wg64, L.tol, L.count);
@@ -434,7 +433,7 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
     launch_zero_u64((unsigned long long *)stat, 3 * count, st);
     launch_zero_u64(gctr, 3 * count, st);
     if (N > 0 && p->max_iterations > 0) {
-      LevelSweeps lv{ALGO_LPA, U, {Ca, Cb}, Kbuf[0], nullptr, nullptr, b.gid0, Wg, Wg64,
+      LevelSweeps lv{ALGO_LPA, U, {Ca, Cb}, Kbuf[0], nullptr, b.gid0, Wg, Wg64,
                      active_d, gctr, stat, nent_d, nvert_d, count, p->tolerance};
       tm.start();
       level_sweeps(lv, p, sch, capture, st);
@@ -457,7 +456,6 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
     int32_t *gid_cur = a.take<int32_t>(N);
     int32_t *gid_next = a.take<int32_t>(N);
     uint32_t *Sig = a.take<uint32_t>(N);
-    int32_t *size = a.take<int32_t>(N);
     int64_t *dense = a.take<int64_t>((int64_t)N + 1);
     int64_t *nb_d = a.take<int64_t>(count + 1);
     int64_t *nc_d = a.take<int64_t>(count + 1);
@@ -490,7 +488,7 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
       Schedule sch;
       build_schedule(cur, sched_params(p), sch, a, st);
       launch_iota(Ca, nl, st);
-      launch_community_totals(Ca, K, Sig, size, nl, st);
+      launch_community_totals(Ca, K, Sig, nl, st);
       ms_lm += tm.stop();
       for (int32_t g = 0; g < count; ++g) {
         active[g] = !finished[g];
@@ -502,7 +500,7 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
       launch_zero_u64((unsigned long long *)stat, 3 * count, st);
       launch_zero_u64(gctr, 3 * count, st);
       {
-        LevelSweeps lv{ALGO_MOVE, cur, {Ca, Cb}, K, Sig, size, gid_cur, Wg, Wg64,
+        LevelSweeps lv{ALGO_MOVE, cur, {Ca, Cb}, K, Sig, gid_cur, Wg, Wg64,
                        active_d, gctr, stat, nent_d, nvert_d, count, tol};
         tm.start();
         level_sweeps(lv, p, sch, capture, st);

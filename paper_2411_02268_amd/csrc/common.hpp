@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <vector>
 
 namespace mgcd {
 
@@ -146,6 +147,27 @@ __device__ inline T wave_inclusive_scan(T v) {
     if (l >= o) v += u;
   }
   return v;
+}
+
+// Totals that every block adds to one device counter go to one of SPREAD copies (by
+// block index), so the atomics of blocks that finish together do not serialise on a
+// single address; the reader adds up (or takes the maximum of) the copies.
+constexpr int SPREAD = 64;
+__device__ inline int spread_copy() { return (int)(blockIdx.x & (SPREAD - 1)); }
+
+// Host: fold SPREAD copies of (nsum counters, then one maximum), each copy nsum + 1
+// values, into out[0 .. nsum] (sums, then the maximum).  Synchronises st.
+inline void read_spread(const unsigned long long *dev, int nsum, unsigned long long *out,
+                        hipStream_t st) {
+  std::vector<unsigned long long> h((size_t)SPREAD * (nsum + 1));
+  MGCD_HIP(hipMemcpyAsync(h.data(), dev, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  for (int q = 0; q <= nsum; ++q) out[q] = 0;
+  for (int c = 0; c < SPREAD; ++c) {
+    const unsigned long long *x = h.data() + (size_t)c * (nsum + 1);
+    for (int q = 0; q < nsum; ++q) out[q] += x[q];
+    out[nsum] = x[nsum] > out[nsum] ? x[nsum] : out[nsum];
+  }
 }
 
 // Sum over a 256-thread block; every thread gets the total.

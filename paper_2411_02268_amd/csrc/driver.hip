@@ -174,7 +174,7 @@ static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Are
       SweepArgs args{g, Ca, nullptr, K, nullptr, 0, 0, Cb, nullptr, ctr};
       args.halt = &ls->halt;
       launch_sweep(args, sch, ALGO_LPA, p->mode, p->k, p->chunk_len, st, ct.ev[j]);
-      launch_level_converge(ALGO_LPA, ctr, ls, g.nnz, n, p->tolerance, 0.0, st);
+      launch_level_converge(ALGO_LPA, LevelRule{ctr, ls, g.nnz, n, p->tolerance, 0.0}, st);
       std::swap(Ca, Cb);  // a halted sweep copies C, so either buffer holds the result
     });
     s.iterations = h.sweeps;
@@ -206,7 +206,6 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
   int32_t *Ca = a.take<int32_t>(n), *Cb = a.take<int32_t>(n);
   int32_t *D = a.take<int32_t>(n), *Dc = a.take<int32_t>(n);
   uint32_t *Sig = a.take<uint32_t>(n);
-  int32_t *size = a.take<int32_t>(n);
   int32_t *prop = leiden ? a.take<int32_t>(n) : nullptr;
   int32_t *nprop = leiden ? a.take<int32_t>(n) : nullptr;
   int32_t *from = leiden ? a.take<int32_t>(n) : nullptr;
@@ -239,16 +238,17 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
     tm.start();
     build_schedule(cur, sched_params(p), sch, a, st);
     if (!leiden) launch_iota(Ca, nl, st);
-    launch_community_totals(Ca, K, Sig, size, nl, st);
+    launch_community_totals(Ca, K, Sig, nl, st);
     launch_zero_u64(ctr, 3, st);
     launch_zero_state(ls, st);
     LevelState h = run_sweeps(p->max_iterations, ls, st, pass == 0 ? &ct : nullptr, s, [&](int it, int j) {
       SweepArgs args{cur, Ca, nullptr, K, Sig, W, (it % 2 == 0) ? -1 : 1, Cb, nullptr, ctr};
       args.halt = &ls->halt;
       launch_sweep(args, sch, ALGO_MOVE, p->mode, p->k, p->chunk_len, st, pass == 0 ? ct.ev[j] : nullptr);
-      // a sweep without positive moves, or a halted one, leaves C_new equal to C
-      launch_apply_moves(Ca, Cb, K, Sig, size, nl, st);
-      launch_level_converge(ALGO_MOVE, ctr, ls, cur.nnz, nl, tol, WW, st);
+      // a sweep without positive moves, or a halted one, leaves C_new equal to C; the
+      // same launch applies the stopping rule to this sweep's counters
+      const LevelRule rule{ctr, ls, cur.nnz, nl, tol, WW};
+      launch_apply_moves(Ca, Cb, K, Sig, nl, st, &rule);
       std::swap(Ca, Cb);
     });
     ms_lm += tm.stop();
@@ -436,12 +436,16 @@ int modularity(const mgcd_csr *gin, const int32_t *C, double *q, void *ws, size_
     require_labels(C, g.n, g.n, a, st, "communities");
     uint32_t *K = a.take<uint32_t>(g.n);
     unsigned long long *Wd = a.take<unsigned long long>(1);
-    unsigned long long *terms = a.take<unsigned long long>(2);
+    unsigned long long *terms = a.take<unsigned long long>(2 * SPREAD);
     launch_degrees(g, K, Wd, a, st);
     modularity_terms(g, C, K, terms, a, st);
-    unsigned long long h[2];
-    MGCD_HIP(hipMemcpyAsync(h, terms, sizeof(h), hipMemcpyDeviceToHost, st));
+    unsigned long long ht[2 * SPREAD], h[2] = {0, 0};
+    MGCD_HIP(hipMemcpyAsync(ht, terms, sizeof(ht), hipMemcpyDeviceToHost, st));
     uint64_t W = read_dev(Wd, st);
+    for (int c = 0; c < SPREAD; ++c) {
+      h[0] += ht[2 * c];
+      h[1] += ht[2 * c + 1];
+    }
     if (W == 0) {
       *q = 0.0;
       return;
@@ -467,9 +471,8 @@ int mgcd_move_sweep(const mgcd_csr *gin, const mgcd_params *p, int32_t algo, con
     uint32_t *K = a.take<uint32_t>(g.n);
     uint64_t W = prepare(g, p, K, a, st);
     uint32_t *Sig = a.take<uint32_t>(g.n);
-    int32_t *size = a.take<int32_t>(g.n);
     unsigned long long *ctr = a.take<unsigned long long>(4);
-    launch_community_totals(C, K, Sig, size, g.n, st);
+    launch_community_totals(C, K, Sig, g.n, st);
     Schedule sch;
     build_schedule(g, sched_params(p), sch, a, st);
     launch_zero_u64(ctr, 3, st);

@@ -141,7 +141,7 @@ __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i
     stage_pairs(win, clo, chi, s0, keybuf, a.g.w);
     return;
   }
-  constexpr int G = 8;  // rounds per group of loads in flight
+  constexpr int G = WIN < 8 ? WIN : 8;  // rounds per group of loads in flight
   const int lane = lane_id();
 #pragma unroll
   for (int g0 = 0; g0 < WIN; g0 += G) {
@@ -149,8 +149,8 @@ __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i
     uint32_t ok = 0;
 #pragma unroll
     for (int r = 0; r < G; ++r) {
-      const int src = (g0 + r) * 4 + (lane >> 4);
-      const int64_t e = __shfl(clo, src) + s0 + (lane & 15);
+      const int src = (g0 + r) * SPR + lane / WIN;
+      const int64_t e = __shfl(clo, src) + s0 + lane % WIN;
       const bool v = e < __shfl(chi, src);
       ok |= v ? 1u << r : 0u;
       const int64_t es = v ? e : 0;
@@ -160,7 +160,7 @@ __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i
     {
 #pragma unroll
       for (int r = 0; r < G; ++r) {
-        const int src = (g0 + r) * 4 + (lane >> 4);
+        const int src = (g0 + r) * SPR + lane / WIN;
         const int32_t ii = __shfl(i, src);
         const int32_t bb = __shfl(bi, src);
         const bool v = (ok >> r) & 1u;
@@ -174,15 +174,15 @@ __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i
       }
 #pragma unroll
       for (int r = 0; r < G; ++r) {
-        const int src = (g0 + r) * 4 + (lane >> 4);
-        const int64_t e = __shfl(clo, src) + s0 + (lane & 15);
+        const int src = (g0 + r) * SPR + lane / WIN;
+        const int64_t e = __shfl(clo, src) + s0 + lane % WIN;
         if ((ok >> r) & 1u) keybuf[e] = kk[r];
       }
     }
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       const bool v = (ok >> r) & 1u;
-      put_pair(win, (g0 + r) * 4 + (lane >> 4), v ? kk[r] : EMPTY, v ? ww[r] : 0u);
+      put_pair(win, (g0 + r) * SPR + lane / WIN, v ? kk[r] : EMPTY, v ? ww[r] : 0u);
     }
   }
 }
@@ -934,6 +934,7 @@ __global__ void __launch_bounds__(BLOCK)
     if (lane_id() == 0 && m) atomicAdd(&bc[q], (unsigned long long)__popcll(m));
   }
   __syncthreads();
+  cnt += spread_copy() * (NCAT + 1);
   if (threadIdx.x < NCAT && bc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], bc[threadIdx.x]);
   // block maximum, then one atomic per block, skipped when it cannot raise the value
   __shared__ unsigned long long bmax[BLOCK / WAVE];
@@ -1019,21 +1020,20 @@ void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a
   const int32_t n = g.n;
   s = Schedule{};
   if (n == 0) return;
-  unsigned long long *cnt = a.take<unsigned long long>(NCAT + 1);
+  unsigned long long *cnt = a.take<unsigned long long>(SPREAD * (NCAT + 1));
   uint64_t *k0 = a.take<uint64_t>(n);
   uint32_t *v0 = a.take<uint32_t>(n);
   uint64_t *k1 = a.take<uint64_t>(n);
   uint32_t *v1 = a.take<uint32_t>(n);
   int32_t *order = a.take<int32_t>(n);
-  launch_zero_u64(cnt, NCAT + 1, st);
+  launch_zero_u64(cnt, SPREAD * (NCAT + 1), st);
   k_schedule_keys<<<grid_for(n), BLOCK, 0, st>>>(g.off, n, sp, k0, v0, cnt);
   MGCD_LAUNCHED();
   bool flip = radix_sort_pairs(k0, v0, k1, v1, n, 8, a, st);
   k_u32_from_u64<<<grid_for(n), BLOCK, 0, st>>>(flip ? v1 : v0, order, n);
   MGCD_LAUNCHED();
   unsigned long long h[NCAT + 1];
-  MGCD_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
-  MGCD_HIP(hipStreamSynchronize(st));
+  read_spread(cnt, NCAT, h, st);
   s.maxdeg = (int64_t)h[NCAT];
   if (sp.wave) {
     s.tier[0] = order;
@@ -1244,47 +1244,58 @@ void launch_sweep(const SweepArgs &a, const Schedule &s, int algo, int mode, int
 
 // ---- bookkeeping kernels ---------------------------------------------------------------
 
+__device__ inline void level_converge(int algo, const LevelRule &r) {
+  // Read and clear in one atomic step: a plain load of these uniform addresses may
+  // become a scalar load, which a following vector store of 0 can overtake.
+  unsigned long long *ctr = r.ctr;
+  const unsigned long long moved = atomicExch(&ctr[0], 0ull), prop = atomicExch(&ctr[1], 0ull),
+                           sumG = atomicExch(&ctr[2], 0ull);
+  LevelState *ls = r.ls;
+  if (ls->halt) return;
+  ls->sweeps += 1;
+  ls->edges += (unsigned long long)r.nnz;
+  ls->moved_last = moved;
+  const bool stop = algo == ALGO_LPA ? (double)moved <= r.tol * (double)r.n
+                                     : prop == 0 || 2.0 * (double)sumG <= r.tol * r.WW;
+  if (stop) ls->halt = 1;
+}
+
 __global__ void k_apply_moves(const int32_t *Cold, const int32_t *Cnew, const uint32_t *K, uint32_t *Sig,
-                              int32_t *size, int32_t n) {
+                              int32_t n, LevelRule rule) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (rule.ls && i == 0) level_converge(ALGO_MOVE, rule);  // the sweep's counters are final
   if (i >= n) return;
   int32_t d = Cold[i], c = Cnew[i];
   if (c == d) return;
   uint32_t k = K[i];
   atomicSub(&Sig[d], k);
   atomicAdd(&Sig[c], k);
-  atomicSub(&size[d], 1);
-  atomicAdd(&size[c], 1);
 }
 
 void launch_apply_moves(const int32_t *Cold, const int32_t *Cnew, const uint32_t *K, uint32_t *Sig,
-                        int32_t *size, int32_t n, hipStream_t st) {
-  if (n <= 0) return;
-  k_apply_moves<<<grid_for(n), BLOCK, 0, st>>>(Cold, Cnew, K, Sig, size, n);
+                        int32_t n, hipStream_t st, const LevelRule *rule) {
+  const LevelRule r = rule ? *rule : LevelRule{};
+  if (n <= 0 && !rule) return;
+  k_apply_moves<<<n > 0 ? grid_for(n) : 1, BLOCK, 0, st>>>(Cold, Cnew, K, Sig, n, r);
   MGCD_LAUNCHED();
 }
 
-__global__ void k_zero_totals(uint32_t *Sig, int32_t *size, int32_t n) {
+__global__ void k_zero_totals(uint32_t *Sig, int32_t n) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i < n) {
-    Sig[i] = 0;
-    size[i] = 0;
-  }
+  if (i < n) Sig[i] = 0;
 }
 
-__global__ void k_totals(const int32_t *C, const uint32_t *K, uint32_t *Sig, int32_t *size, int32_t n) {
+__global__ void k_totals(const int32_t *C, const uint32_t *K, uint32_t *Sig, int32_t n) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= n) return;
-  atomicAdd(&Sig[C[i]], K[i]);
-  atomicAdd(&size[C[i]], 1);
+  if (i < n) atomicAdd(&Sig[C[i]], K[i]);
 }
 
-void launch_community_totals(const int32_t *C, const uint32_t *K, uint32_t *Sig, int32_t *size,
-                             int32_t n, hipStream_t st) {
+void launch_community_totals(const int32_t *C, const uint32_t *K, uint32_t *Sig, int32_t n,
+                             hipStream_t st) {
   if (n <= 0) return;
-  k_zero_totals<<<grid_for(n), BLOCK, 0, st>>>(Sig, size, n);
+  k_zero_totals<<<grid_for(n), BLOCK, 0, st>>>(Sig, n);
   MGCD_LAUNCHED();
-  k_totals<<<grid_for(n), BLOCK, 0, st>>>(C, K, Sig, size, n);
+  k_totals<<<grid_for(n), BLOCK, 0, st>>>(C, K, Sig, n);
   MGCD_LAUNCHED();
 }
 
@@ -1326,24 +1337,10 @@ __global__ void k_iota(int32_t *p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (i < n) p[i] = (int32_t)i;
 }
-__global__ void k_level_converge(int algo, unsigned long long *ctr, LevelState *ls, int64_t nnz,
-                                 int32_t n, double tol, double WW) {
-  // Read and clear in one atomic step: a plain load of these uniform addresses may
-  // become a scalar load, which a following vector store of 0 can overtake.
-  const unsigned long long moved = atomicExch(&ctr[0], 0ull), prop = atomicExch(&ctr[1], 0ull),
-                           sumG = atomicExch(&ctr[2], 0ull);
-  if (ls->halt) return;
-  ls->sweeps += 1;
-  ls->edges += (unsigned long long)nnz;
-  ls->moved_last = moved;
-  const bool stop = algo == ALGO_LPA ? (double)moved <= tol * (double)n
-                                     : prop == 0 || 2.0 * (double)sumG <= tol * WW;
-  if (stop) ls->halt = 1;
-}
+__global__ void k_level_converge(int algo, LevelRule r) { level_converge(algo, r); }
 
-void launch_level_converge(int algo, unsigned long long *ctr, LevelState *ls, int64_t nnz, int32_t n,
-                           double tol, double WW, hipStream_t st) {
-  k_level_converge<<<1, 1, 0, st>>>(algo, ctr, ls, nnz, n, tol, WW);
+void launch_level_converge(int algo, const LevelRule &r, hipStream_t st) {
+  k_level_converge<<<1, 1, 0, st>>>(algo, r);
   MGCD_LAUNCHED();
 }
 

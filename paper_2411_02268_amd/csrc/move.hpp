@@ -38,11 +38,18 @@ struct LevelState {
   unsigned long long edges;
   unsigned long long moved_last;
 };
-// After a sweep: apply the stopping rule of LPA (movers <= tol * n) or of Louvain
-// local moving (no positive move, or 2 * summed gain <= tol * W^2) to the counters
-// ctr, clear them, update the state.
-void launch_level_converge(int algo, unsigned long long *ctr, LevelState *ls, int64_t nnz, int32_t n,
-                           double tol, double WW, hipStream_t st);
+// A level's stopping rule: LPA stops when movers <= tol * n, Louvain local moving
+// when no vertex has a positive move or 2 * summed gain <= tol * W^2 (WW = W^2).
+// The sweep counters ctr [moved, proposals, sum of gains] are read and cleared.
+struct LevelRule {
+  unsigned long long *ctr = nullptr;
+  LevelState *ls = nullptr;
+  int64_t nnz = 0;  // entries streamed per sweep
+  int32_t n = 0;
+  double tol = 0, WW = 0;
+};
+// After a sweep: apply the rule to the sweep's counters and update the state.
+void launch_level_converge(int algo, const LevelRule &r, hipStream_t st);
 void launch_zero_state(LevelState *ls, hipStream_t st);
 
 // Row buckets of the main sweep kernel: rows needing 2^b lanes (b = 0..6).
@@ -146,12 +153,14 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L);
 void launch_sweep(const SweepArgs &a, const Schedule &s, int algo, int mode, int k, int64_t L,
                   hipStream_t st, hipEvent_t *ev = nullptr);
 
-// Sigma[c] -= K_i, Sigma[c'] += K_i and sizes for every vertex that moved.
+// Sigma[c] -= K_i, Sigma[c'] += K_i for every vertex that moved from c to c'.  With
+// a rule, the same launch first applies the Louvain stopping rule of that level
+// (as launch_level_converge with ALGO_MOVE).
 void launch_apply_moves(const int32_t *Cold, const int32_t *Cnew, const uint32_t *K, uint32_t *Sig,
-                        int32_t *size, int32_t n, hipStream_t st);
-// Sigma and sizes of a membership from scratch.
-void launch_community_totals(const int32_t *C, const uint32_t *K, uint32_t *Sig, int32_t *size,
-                             int32_t n, hipStream_t st);
+                        int32_t n, hipStream_t st, const LevelRule *rule = nullptr);
+// Sigma of a membership from scratch.
+void launch_community_totals(const int32_t *C, const uint32_t *K, uint32_t *Sig, int32_t n,
+                             hipStream_t st);
 // Leiden refinement acceptance: R[i] = prop[i] unless a vertex other than the target
 // proposed i, or the target proposed i and has the higher id.
 void launch_refine_accept(const int32_t *prop, int32_t *nprop, int32_t *from, int32_t *R, int32_t n,

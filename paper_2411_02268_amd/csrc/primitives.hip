@@ -22,36 +22,35 @@ __global__ void __launch_bounds__(BLOCK) k_tile_sums(const Tin *in, int64_t n, i
   if (threadIdx.x == 0) sums[blockIdx.x] = acc;
 }
 
-// Each thread owns SCAN_ITEMS consecutive items; block-wide exclusive scan plus the
-// tile's offset.
+// Wave w of the tile scans its SCAN_ITEMS * WAVE consecutive items 64 at a time (one
+// coalesced load and store per round, a carry across rounds); the waves' totals give
+// their offsets within the tile, tile_off the tile's.
 template <typename Tin>
 __global__ void __launch_bounds__(BLOCK)
     k_tile_scan(const Tin *in, int64_t *out, int64_t n, const int64_t *tile_off, int64_t *total) {
-  __shared__ int64_t wtot[4];
-  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-  int64_t v[SCAN_ITEMS];
-  int64_t run = 0;
+  __shared__ int64_t wtot[BLOCK / WAVE];
+  const int w = threadIdx.x / WAVE, lane = lane_id();
+  const int64_t wbase = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)w * (SCAN_ITEMS * WAVE) + lane;
+  int64_t ex[SCAN_ITEMS];
+  int64_t carry = 0;
 #pragma unroll
   for (int r = 0; r < SCAN_ITEMS; ++r) {
-    int64_t i = base + r;
-    v[r] = i < n ? (int64_t)in[i] : 0;
-    run += v[r];
+    const int64_t i = wbase + (int64_t)r * WAVE;
+    const int64_t x = i < n ? (int64_t)in[i] : 0;
+    const int64_t incl = wave_inclusive_scan(x);
+    ex[r] = carry + incl - x;
+    carry += __shfl(incl, WAVE - 1);
   }
-  int64_t incl = wave_inclusive_scan(run);
-  int w = threadIdx.x / WAVE;
-  if (lane_id() == WAVE - 1) wtot[w] = incl;
+  if (lane == 0) wtot[w] = carry;
   __syncthreads();
-  int64_t woff = 0;
-  for (int q = 0; q < w; ++q) woff += wtot[q];
-  int64_t excl = (tile_off ? tile_off[blockIdx.x] : 0) + woff + incl - run;
+  int64_t off = tile_off ? tile_off[blockIdx.x] : 0;
+  for (int q = 0; q < w; ++q) off += wtot[q];
 #pragma unroll
   for (int r = 0; r < SCAN_ITEMS; ++r) {
-    int64_t i = base + r;
-    int64_t x = v[r];
-    if (i < n) out[i] = excl;
-    excl += x;
+    const int64_t i = wbase + (int64_t)r * WAVE;
+    if (i < n) out[i] = off + ex[r];
   }
-  if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == BLOCK - 1) *total = excl;
+  if (total && blockIdx.x == gridDim.x - 1 && w == BLOCK / WAVE - 1 && lane == 0) *total = off + carry;
 }
 
 template <typename Tin>

@@ -13,6 +13,8 @@ constexpr int WIN = 16;            // staged positions per lane and window
 constexpr int WROW = 2 * WIN + 4;  // words per lane row: WIN (key, weight) pairs + pad; rows
                                    // are 16-byte aligned and 8 consecutive lanes' rows start
                                    // in distinct 4-bank groups (conflict-free 128-bit reads)
+constexpr int SPR = WAVE / WIN;    // segments staged per load round (WIN lanes each); a
+                                   // window takes WIN rounds
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -25,12 +27,12 @@ __device__ inline void put_pair(uint32_t *win, int src, uint32_t k, uint32_t w) 
   v2u pr;
   pr.x = k;
   pr.y = w;
-  *reinterpret_cast<v2u *>(win + src * WROW + 2 * (lane_id() & 15)) = pr;
+  *reinterpret_cast<v2u *>(win + src * WROW + 2 * (lane_id() % WIN)) = pr;
 }
 
 // Stage positions s0 .. s0+WIN-1 of every lane's segment [lo, hi) of (keys, wts)
 // into the wave's window win (WAVE * WROW words): round r serves the segments of
-// lanes 4r .. 4r+3; all loads of the window are in flight together.  Positions past
+// lanes SPR*r .. SPR*r+SPR-1; all loads of the window are in flight together.  Positions past
 // a segment's end stage (EMPTY, 0).
 __device__ inline void stage_pairs(uint32_t *win, int64_t lo, int64_t hi, int64_t s0,
                                    const uint32_t *keys, const uint32_t *wts) {
@@ -39,8 +41,8 @@ __device__ inline void stage_pairs(uint32_t *win, int64_t lo, int64_t hi, int64_
   uint32_t ok = 0;
 #pragma unroll
   for (int r = 0; r < WIN; ++r) {
-    const int src = r * 4 + (lane >> 4);
-    const int64_t e = __shfl(lo, src) + s0 + (lane & 15);
+    const int src = r * SPR + lane / WIN;
+    const int64_t e = __shfl(lo, src) + s0 + lane % WIN;
     const bool v = e < __shfl(hi, src);
     ok |= v ? 1u << r : 0u;
     const int64_t es = v ? e : 0;
@@ -50,7 +52,7 @@ __device__ inline void stage_pairs(uint32_t *win, int64_t lo, int64_t hi, int64_
 #pragma unroll
   for (int r = 0; r < WIN; ++r) {
     const bool v = (ok >> r) & 1u;
-    put_pair(win, r * 4 + (lane >> 4), v ? kk[r] : EMPTY, v ? ww[r] : 0u);
+    put_pair(win, r * SPR + lane / WIN, v ? kk[r] : EMPTY, v ? ww[r] : 0u);
   }
 }
 

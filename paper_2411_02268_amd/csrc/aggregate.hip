@@ -98,30 +98,103 @@ void launch_scatter_labels(const int32_t *map, const int32_t *val, int32_t *out,
   MGCD_LAUNCHED();
 }
 
-// K_i = sum of row i's weights (Section 3) as the difference of an exclusive prefix
-// sum of all weights at the row bounds; W = the total.
 constexpr int ROW_BLOCKS = 2048;
 
-__global__ void k_row_sums(const int64_t *off, const int64_t *ps, int32_t n, uint32_t *K) {
-  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i < n) K[i] = (uint32_t)(ps[off[i + 1]] - ps[off[i]]);
+// K_i = sum of row i's weights (Section 3), W = their total.  A workgroup takes
+// DG_TILE consecutive entries: their weights are staged in LDS (coalesced loads) and
+// scanned there; every row meeting the tile takes the difference of the scan at its
+// bounds within the tile, stored when the row lies inside the tile and added
+// atomically (to a zeroed K) when it crosses a tile boundary.  Tile totals go to
+// SPREAD copies of W, folded by k_fold_total.
+constexpr int DG_ITEMS = 8, DG_TILE = BLOCK * DG_ITEMS;
+
+__device__ inline int32_t row_of_entry(const int64_t *off, int32_t lo, int32_t hi, int64_t e) {
+  // the largest r in [lo, hi] with off[r] <= e (the last of equal offsets: a row
+  // holding e, not an empty one before it)
+  while (lo < hi) {
+    const int32_t mid = (int32_t)(((int64_t)lo + hi + 1) >> 1);
+    if (off[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
-__global__ void k_copy_total(const int64_t *src, unsigned long long *dst) {
-  *dst = (unsigned long long)*src;
+__global__ void __launch_bounds__(BLOCK)
+    k_row_weight_sums(Graph g, uint32_t *K, unsigned long long *Wpart) {
+  __shared__ uint32_t ex[DG_TILE + 1];
+  __shared__ uint32_t wsum[BLOCK / WAVE];
+  __shared__ unsigned long long wtot[BLOCK / WAVE];
+  __shared__ int32_t sr[2];
+  const int t = threadIdx.x, w = t / WAVE;
+  const int64_t e0 = (int64_t)blockIdx.x * DG_TILE;
+  const int64_t e1 = e0 + DG_TILE < g.nnz ? e0 + DG_TILE : g.nnz;
+  if (t == 0) sr[0] = row_of_entry(g.off, 0, g.n - 1, e0);
+  if (t == 1) sr[1] = row_of_entry(g.off, 0, g.n - 1, e1 - 1);
+  unsigned long long tsum = 0;
+#pragma unroll
+  for (int q = 0; q < DG_ITEMS; ++q) {
+    const int x = q * BLOCK + t;
+    const uint32_t v = e0 + x < e1 ? __builtin_nontemporal_load(g.w + e0 + x) : 0u;
+    ex[x] = v;
+    tsum += v;
+  }
+  __syncthreads();
+  // exclusive prefix sums in place: thread t owns positions DG_ITEMS*t ..
+  uint32_t v[DG_ITEMS], run = 0;
+#pragma unroll
+  for (int q = 0; q < DG_ITEMS; ++q) {
+    v[q] = ex[t * DG_ITEMS + q];
+    run += v[q];
+  }
+  const uint32_t incl = wave_inclusive_scan(run);
+  tsum = wave_sum(tsum);
+  if (lane_id() == WAVE - 1) wsum[w] = incl;
+  if (lane_id() == 0) wtot[w] = tsum;
+  __syncthreads();
+  uint32_t acc = incl - run;
+  for (int q = 0; q < w; ++q) acc += wsum[q];
+#pragma unroll
+  for (int q = 0; q < DG_ITEMS; ++q) {
+    ex[t * DG_ITEMS + q] = acc;
+    acc += v[q];
+  }
+  if (t == BLOCK - 1) ex[DG_TILE] = acc;
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long total = 0;
+    for (int q = 0; q < BLOCK / WAVE; ++q) total += wtot[q];
+    if (total) atomicAdd(&Wpart[spread_copy()], total);
+  }
+  const int32_t r0 = sr[0], r1 = sr[1];
+  for (int64_t r = (int64_t)r0 + t; r <= r1; r += BLOCK) {
+    const int64_t lo = g.off[r], hi = g.off[r + 1];
+    const int64_t a = lo > e0 ? lo : e0, b = hi < e1 ? hi : e1;
+    if (b <= a) continue;  // empty row
+    const uint32_t part = ex[b - e0] - ex[a - e0];
+    if (lo >= e0 && hi <= e1)
+      K[r] = part;
+    else
+      atomicAdd(&K[r], part);
+  }
 }
 
-size_t degrees_ws_bytes(int64_t nnz) { return (size_t)(nnz + 1) * 8 + scan_ws_bytes(nnz) + 4096; }
+__global__ void k_fold_total(const unsigned long long *part, unsigned long long *W) {
+  const unsigned long long s = wave_sum(part[lane_id()]);  // one wave, SPREAD == WAVE
+  if (lane_id() == 0) *W = s;
+}
+
+size_t degrees_ws_bytes(int64_t) { return (size_t)SPREAD * 8 + 4096; }
 
 void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, Arena &a, hipStream_t st) {
+  static_assert(SPREAD == WAVE, "k_fold_total folds one copy per lane");
   size_t mk = a.mark();
-  int64_t *ps = a.take<int64_t>(g.nnz + 1);
-  scan_u32_i64(g.w, ps, g.nnz, ps + g.nnz, a, st);
-  if (g.n > 0) {
-    k_row_sums<<<grid_for(g.n), BLOCK, 0, st>>>(g.off, ps, g.n, K);
+  unsigned long long *part = a.take<unsigned long long>(SPREAD);
+  launch_zero_u64(part, SPREAD, st);
+  if (g.n > 0) zero_u32(K, g.n, st);
+  if (g.nnz > 0) {
+    k_row_weight_sums<<<(unsigned)ceil_div(g.nnz, DG_TILE), BLOCK, 0, st>>>(g, K, part);
     MGCD_LAUNCHED();
   }
-  k_copy_total<<<1, 1, 0, st>>>(ps + g.nnz, W);
+  k_fold_total<<<1, WAVE, 0, st>>>(part, W);
   MGCD_LAUNCHED();
   a.release(mk);
 }
@@ -388,43 +461,26 @@ __global__ void k_row_pos(const uint32_t *mem, const int64_t *P, int32_t nmem, i
   if (t < nmem) rowpos[mem[t]] = P[t];
 }
 
-// Lay the community streams out contiguously: entry e of row i goes to position
-// rowpos[i] + (e - off[i]) with key D[j] and its weight.  A workgroup takes SF_TILE
-// consecutive entries (balanced whatever the row lengths).  The rows spanning the
-// tile are r0 .. r1 (two binary searches); every row r0 < r <= r1 marks its first
-// position in an LDS count array, whose inclusive prefix sum then gives each
-// entry's row as r0 + count (no per-entry search); entries are read and written in
-// coalesced order.
+// Rows of a tile of consecutive CSR entries [e0, e1) (non-empty): the rows meeting
+// it are r0 .. r1 (two binary searches); every row r0 < r <= r1 marks its first
+// position in an LDS count array, whose inclusive prefix sum then gives the entry
+// at tile position x the row r0 + starts[x] (no per-entry search).  Whole-workgroup
+// call; returns r0.
 constexpr int SF_ITEMS = 8, SF_TILE = BLOCK * SF_ITEMS;
 
-__device__ inline int32_t row_of_entry(const int64_t *off, int32_t lo, int32_t hi, int64_t e) {
-  // the largest r in [lo, hi] with off[r] <= e (the last of equal offsets: a row
-  // holding e, not an empty one before it)
-  while (lo < hi) {
-    const int32_t mid = (int32_t)(((int64_t)lo + hi + 1) >> 1);
-    if (off[mid] <= e) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__global__ void __launch_bounds__(BLOCK)
-    k_agg_streamify(Graph g, const int32_t *D, const int64_t *rowpos, uint32_t *skey, uint32_t *sw) {
-  __shared__ uint32_t starts[SF_TILE];
+__device__ inline int32_t tile_rows(const Graph &g, int64_t e0, int64_t e1, uint32_t *starts) {
   __shared__ uint32_t wsum[BLOCK / WAVE];
   __shared__ int32_t sr[2];
-  const int64_t e0 = (int64_t)blockIdx.x * SF_TILE;
-  const int64_t e1 = e0 + SF_TILE < g.nnz ? e0 + SF_TILE : g.nnz;
-  for (int x = threadIdx.x; x < SF_TILE; x += BLOCK) starts[x] = 0;
-  if (threadIdx.x == 0) sr[0] = row_of_entry(g.off, 0, g.n - 1, e0);
-  if (threadIdx.x == 1) sr[1] = row_of_entry(g.off, 0, g.n - 1, e1 - 1);
+  const int t = threadIdx.x, w = t / WAVE;
+  for (int x = t; x < SF_TILE; x += BLOCK) starts[x] = 0;
+  if (t == 0) sr[0] = row_of_entry(g.off, 0, g.n - 1, e0);
+  if (t == 1) sr[1] = row_of_entry(g.off, 0, g.n - 1, e1 - 1);
   __syncthreads();
   const int32_t r0 = sr[0], r1 = sr[1];
   // rows r0 < r <= r1 start inside the tile (off[r0 + 1] > e0, off[r1] <= e1 - 1)
-  for (int64_t r = (int64_t)r0 + 1 + threadIdx.x; r <= r1; r += BLOCK)
-    atomicAdd(&starts[g.off[r] - e0], 1u);
+  for (int64_t r = (int64_t)r0 + 1 + t; r <= r1; r += BLOCK) atomicAdd(&starts[g.off[r] - e0], 1u);
   __syncthreads();
   // inclusive prefix sum of the counts: thread t owns positions SF_ITEMS*t ..
-  const int t = threadIdx.x, w = t / WAVE;
   uint32_t v[SF_ITEMS], run = 0;
 #pragma unroll
   for (int q = 0; q < SF_ITEMS; ++q) {
@@ -442,17 +498,42 @@ __global__ void __launch_bounds__(BLOCK)
     starts[t * SF_ITEMS + q] = acc;
   }
   __syncthreads();
+  return r0;
+}
+
+// Lay the community streams out contiguously: entry e of row i goes to position
+// rowpos[i] + (e - off[i]) with key D[j] and its weight.  A workgroup takes SF_TILE
+// consecutive entries (balanced whatever the row lengths), finds their rows with
+// tile_rows and reads and writes the entries in coalesced order.
+__global__ void __launch_bounds__(BLOCK)
+    k_agg_streamify(Graph g, const int32_t *D, const int64_t *rowpos, uint32_t *skey, uint32_t *sw) {
+  __shared__ uint32_t starts[SF_TILE];
+  const int t = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * SF_TILE;
+  const int64_t e1 = e0 + SF_TILE < g.nnz ? e0 + SF_TILE : g.nnz;
+  const int32_t r0 = tile_rows(g, e0, e1, starts);
+  // all loads and gathers are issued first (a position past the end reads entry e0),
+  // then the stores, so the gathers of the SF_ITEMS rounds are in flight together
+  int64_t pos[SF_ITEMS];
+  uint32_t key[SF_ITEMS], wt[SF_ITEMS];
 #pragma unroll
   for (int q = 0; q < SF_ITEMS; ++q) {
-    const int64_t e = e0 + (int64_t)q * BLOCK + t;
-    if (e < e1) {
-      const int32_t r = r0 + (int32_t)starts[e - e0];
-      const int64_t p = rowpos[r];
-      if (p >= 0) {
-        const int64_t pos = p + (e - g.off[r]);
-        skey[pos] = (uint32_t)D[__builtin_nontemporal_load(g.idx + e)];
-        sw[pos] = __builtin_nontemporal_load(g.w + e);
-      }
+    const int64_t x = (int64_t)q * BLOCK + t;
+    const bool v = e0 + x < e1;
+    const int64_t e = v ? e0 + x : e0;
+    const int32_t r = r0 + (int32_t)starts[v ? x : 0];
+    const int64_t p = rowpos[r];
+    // -1 (all ones) for a position past the end or a row in no community; an OR, not
+    // a select, so the load of off[r] is not moved into a branch of its own
+    pos[q] = (p + (e - g.off[r])) | ((v && p >= 0) ? 0 : -1);
+    key[q] = (uint32_t)D[__builtin_nontemporal_load(g.idx + e)];
+    wt[q] = __builtin_nontemporal_load(g.w + e);
+  }
+#pragma unroll
+  for (int q = 0; q < SF_ITEMS; ++q) {
+    if (pos[q] >= 0) {
+      skey[pos[q]] = key[q];
+      sw[pos[q]] = wt[q];
     }
   }
 }
@@ -655,26 +736,50 @@ __global__ void k_dedupe_max(const uint64_t *ks, const uint32_t *vs, const uint3
   atomicAdd(&rowcnt[(uint32_t)(ks[e] >> b)], 1u);
 }
 
-// Exact aggregation: one key (D[i], D[j]) per CSR entry; the row by binary search.
-// Entries of left-out rows (D < 0) get the key 2^(2b) - 1... sorted past every
-// real key, and are not counted in *kept.
-__global__ void k_exact_keys(Graph g, const int32_t *D, int b, uint64_t *key, uint32_t *val,
-                             unsigned long long *kept) {
-  int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  bool in = false;
-  if (e < g.nnz) {
-    int32_t lo = 0, hi = g.n - 1;
-    while (lo < hi) {
-      int32_t mid = (lo + hi + 1) >> 1;
-      if (g.off[mid] <= e) lo = mid; else hi = mid - 1;
-    }
-    in = D[lo] >= 0;
-    key[e] = in ? ((uint64_t)(uint32_t)D[lo] << b) | (uint64_t)(uint32_t)D[g.idx[e]]
-                : ((1ull << (2 * b)) - 1);
-    val[e] = g.w[e];
+// Exact aggregation: one key (D[i], D[j]) per CSR entry, SF_TILE entries per
+// workgroup with their rows from tile_rows.  Entries of left-out rows (D < 0) get
+// the key 2^(2b) - 1, sorted past every real key, and are not counted in kept
+// (SPREAD copies, by workgroup).
+__global__ void __launch_bounds__(BLOCK)
+    k_exact_keys(Graph g, const int32_t *D, int b, uint64_t *key, uint32_t *val,
+                 unsigned long long *kept) {
+  __shared__ uint32_t starts[SF_TILE];
+  __shared__ unsigned long long bk[BLOCK / WAVE];
+  const int t = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * SF_TILE;
+  const int64_t e1 = e0 + SF_TILE < g.nnz ? e0 + SF_TILE : g.nnz;
+  const int32_t r0 = tile_rows(g, e0, e1, starts);
+  const uint64_t left_out = (1ull << (2 * b)) - 1;
+  uint64_t ks[SF_ITEMS];
+  uint32_t vs[SF_ITEMS];
+  unsigned long long cnt = 0;
+#pragma unroll
+  for (int q = 0; q < SF_ITEMS; ++q) {
+    const int64_t x = (int64_t)q * BLOCK + t;
+    const bool v = e0 + x < e1;
+    const int64_t e = v ? e0 + x : e0;
+    const int32_t di = D[r0 + (int32_t)starts[v ? x : 0]];
+    const int32_t dj = D[__builtin_nontemporal_load(g.idx + e)];
+    const bool in = v && di >= 0;
+    cnt += in ? 1 : 0;
+    ks[q] = in ? ((uint64_t)(uint32_t)di << b) | (uint64_t)(uint32_t)dj : left_out;
+    vs[q] = __builtin_nontemporal_load(g.w + e);
   }
-  uint64_t m = __ballot(in);
-  if (lane_id() == 0 && m) atomicAdd(kept, (unsigned long long)__popcll(m));
+#pragma unroll
+  for (int q = 0; q < SF_ITEMS; ++q) {
+    const int64_t e = e0 + (int64_t)q * BLOCK + t;
+    if (e < e1) {
+      key[e] = ks[q];
+      val[e] = vs[q];
+    }
+  }
+  cnt = wave_sum(cnt);
+  if (lane_id() == 0) bk[t / WAVE] = cnt;
+  __syncthreads();
+  if (t == 0) {
+    const unsigned long long s = bk[0] + bk[1] + bk[2] + bk[3];
+    if (s) atomicAdd(&kept[2 * spread_copy()], s);
+  }
 }
 
 // Sum the weights of each run of equal keys: in-wave segmented sums, one atomic
@@ -843,15 +948,14 @@ static int64_t aggregate_exact(const Graph &g, const int32_t *D, int32_t m, int6
   uint32_t *v0 = a.take<uint32_t>(E0), *v1 = a.take<uint32_t>(E0);
   uint32_t *head = a.take<uint32_t>(E0);
   int64_t *rid = a.take<int64_t>(E0 + 1);
-  unsigned long long *kept = a.take<unsigned long long>(1);
-  launch_zero_u64(kept, 1, st);
-  k_exact_keys<<<grid_for(E0), BLOCK, 0, st>>>(g, D, b, k0, v0, kept);
+  unsigned long long *kept = a.take<unsigned long long>(2 * SPREAD);
+  launch_zero_u64(kept, 2 * SPREAD, st);
+  k_exact_keys<<<(unsigned)ceil_div(E0, SF_TILE), BLOCK, 0, st>>>(g, D, b, k0, v0, kept);
   MGCD_LAUNCHED();
   bool flip = radix_sort_pairs(k0, v0, k1, v1, E0, 2 * b, a, st);
-  unsigned long long hk = 0;
-  MGCD_HIP(hipMemcpyAsync(&hk, kept, sizeof(hk), hipMemcpyDeviceToHost, st));
-  MGCD_HIP(hipStreamSynchronize(st));
-  const int64_t E = (int64_t)hk;
+  unsigned long long hk[2];
+  read_spread(kept, 1, hk, st);
+  const int64_t E = (int64_t)hk[0];
   if (E == 0) {
     offsets_from_counts(rowcnt, m, out_off, a, st);
     return 0;

@@ -51,24 +51,45 @@ __device__ inline bool frozen(const SweepArgs &a, int32_t i) {
   return (a.halt && *a.halt) || (a.gid && !a.active[a.gid[i]]);
 }
 
+// Evaluate candidate c (present: it exists) with exact linking weight kc and
+// community total sc; keep the best.  Branch-free, so gathers feeding sc are issued
+// together rather than each inside a branch of its own.
+template <int ALGO>
+__device__ inline void consider_v(int64_t W, int32_t d, int64_t Ki, int64_t Sd, uint32_t kd, int32_t c,
+                                  uint32_t kc, uint32_t sc, bool present, int32_t &best, int64_t &bestG) {
+  int64_t G;
+  bool ok;
+  if (ALGO == ALGO_LPA) {
+    G = (int64_t)kc;
+    ok = present;
+  } else {
+    G = W * ((int64_t)kc - (int64_t)kd) - Ki * (Ki + (int64_t)sc - Sd);
+    ok = present && c != d && G > 0;
+  }
+  const bool better = ok && (best < 0 || G > bestG || (G == bestG && c < best));
+  best = better ? c : best;
+  bestG = better ? G : bestG;
+}
+
 template <int ALGO>
 __device__ inline void consider(const SweepArgs &a, int64_t W, int32_t d, int64_t Ki, int64_t Sd,
                                 uint32_t kd, int32_t c, uint32_t kc, int32_t &best, int64_t &bestG) {
-  if (ALGO == ALGO_LPA) {
-    int64_t G = (int64_t)kc;
-    if (best < 0 || G > bestG || (G == bestG && c < best)) {
-      best = c;
-      bestG = G;
-    }
-  } else {
-    if (c == d) return;
-    int64_t G = W * ((int64_t)kc - (int64_t)kd) -
-                Ki * (Ki + (int64_t)a.Sig[c] - Sd);
-    if (G > 0 && (best < 0 || G > bestG || (G == bestG && c < best))) {
-      best = c;
-      bestG = G;
-    }
-  }
+  const uint32_t sc = ALGO == ALGO_LPA ? 0u : a.Sig[c];
+  consider_v<ALGO>(W, d, Ki, Sd, kd, c, kc, sc, true, best, bestG);
+}
+
+// The best of K candidate slots (EMPTY: no candidate): the community totals of all
+// slots are gathered first (an absent slot reads Sigma_d), then scored.
+template <int K, int ALGO>
+__device__ inline void consider_slots(const SweepArgs &a, int64_t W, int32_t d, int64_t Ki, int64_t Sd,
+                                      uint32_t kd, const uint32_t (&key)[K], const uint32_t (&ex)[K],
+                                      int32_t &best, int64_t &bestG) {
+  uint32_t sc[K];
+#pragma unroll
+  for (int p = 0; p < K; ++p) sc[p] = ALGO == ALGO_LPA ? 0u : a.Sig[key[p] != EMPTY ? (int32_t)key[p] : d];
+#pragma unroll
+  for (int p = 0; p < K; ++p)
+    consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)key[p], ex[p], sc[p], key[p] != EMPTY, best, bestG);
 }
 
 template <int ALGO>
@@ -170,7 +191,10 @@ __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i
           c = a.bound[j] == bb ? (uint32_t)j : EMPTY;
         else
           c = (uint32_t)a.C[j];
-        kk[r] = (v && j != ii) ? c : EMPTY;  // self-loops are skipped
+        // self-loops are skipped.  The gathered value is used on every lane (OR with
+        // an all-ones mask instead of a select), so the compiler keeps the gathers of
+        // all rounds in flight instead of sinking each into a branch of its own.
+        kk[r] = c | ((v && j != ii) ? 0u : EMPTY);
       }
 #pragma unroll
       for (int r = 0; r < G; ++r) {
@@ -301,9 +325,7 @@ __device__ inline void decide_long(const SweepArgs &a, int32_t i, int32_t d, con
   const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
   const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
   const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
-#pragma unroll
-  for (int p = 0; p < K; ++p)
-    if (key[p] != EMPTY) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)key[p], ex[p], best, bestG);
+  consider_slots<K, ALGO>(a, W, d, Ki, Sd, kd, key, ex, best, bestG);
   finish<ALGO>(a, i, d, best, bestG, ct);
   if (ct.moved) atomicAdd(&a.ctr[0], (unsigned long long)ct.moved);
   if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
@@ -555,9 +577,7 @@ __device__ inline void row_work(const SweepArgs &a, const Buckets &bk, int64_t L
     const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
     const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
     const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
-#pragma unroll
-    for (int p = 0; p < K; ++p)
-      if (key[p] != EMPTY) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)key[p], ex[p], best, bestG);
+    consider_slots<K, ALGO>(a, W, d, Ki, Sd, kd, key, ex, best, bestG);
     finish<ALGO>(a, i, d, best, bestG, ct);
   }
 }
@@ -691,13 +711,24 @@ __global__ void __launch_bounds__(BLOCK)
 template <int ALGO, int ES>
 __device__ inline void exact_row_regs(const SweepArgs &a, int32_t i, int32_t bi, int64_t lo,
                                       int64_t hi, int32_t d, Counters &ct) {
+  // Every load is issued on every lane (an absent position reads a valid entry: the
+  // row's first, or entry 0 for an empty row; some row of the wave is non-empty) and
+  // its value masked afterwards, so the loads and gathers of all positions are in
+  // flight together.
   uint32_t ks[ES], ws[ES];
+  const int64_t safe = hi > lo ? lo : 0;
 #pragma unroll
   for (int t = 0; t < ES; ++t) {
     const bool v = lo + t < hi;
-    const int32_t j = v ? a.g.idx[lo + t] : 0;
-    ws[t] = v ? a.g.w[lo + t] : 0u;
-    ks[t] = v ? stream_key<ALGO>(a, i, j, bi) : EMPTY;
+    const int64_t e = v ? lo + t : safe;
+    const int32_t j = a.g.idx[e];
+    ws[t] = a.g.w[e] & (v ? ~0u : 0u);
+    uint32_t c;
+    if (ALGO == ALGO_REFINE)
+      c = a.bound[j] == bi ? (uint32_t)j : EMPTY;
+    else
+      c = (uint32_t)a.C[j];
+    ks[t] = c | ((v && j != i) ? 0u : EMPTY);  // self-loops are skipped
   }
   uint32_t kd = 0;
 #pragma unroll
@@ -707,6 +738,9 @@ __device__ inline void exact_row_regs(const SweepArgs &a, int32_t i, int32_t bi,
   const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
   const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
   const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+  uint32_t sc[ES];
+#pragma unroll
+  for (int t = 0; t < ES; ++t) sc[t] = ALGO == ALGO_LPA ? 0u : a.Sig[ks[t] != EMPTY ? (int32_t)ks[t] : d];
 #pragma unroll
   for (int t = 0; t < ES; ++t) {
     const uint32_t c = ks[t];
@@ -716,7 +750,7 @@ __device__ inline void exact_row_regs(const SweepArgs &a, int32_t i, int32_t bi,
     uint32_t kc = 0;
 #pragma unroll
     for (int u = t; u < ES; ++u) kc += ks[u] == c ? ws[u] : 0u;
-    if (first) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)c, kc, best, bestG);
+    consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)c, kc, sc[t], first, best, bestG);
   }
   finish<ALGO>(a, i, d, best, bestG, ct);
 }
@@ -744,7 +778,9 @@ __global__ void __launch_bounds__(BLOCK)
   maxdeg = uniform(maxdeg);
   const int32_t bi = (ALGO == ALGO_REFINE && live) ? a.bound[i] : 0;
   const int32_t d = live ? community_of_self<ALGO>(a, i) : 0;
-  if (maxdeg <= 8) {
+  if (maxdeg == 0) {
+    if (live) finish<ALGO>(a, i, d, -1, 0, ct);  // no neighbours: stay
+  } else if (maxdeg <= 8) {
     if (live) exact_row_regs<ALGO, 8>(a, i, bi, lo, hi, d, ct);
   } else if (maxdeg <= 16) {
     if (live) exact_row_regs<ALGO, 16>(a, i, bi, lo, hi, d, ct);
@@ -823,18 +859,38 @@ __global__ void __launch_bounds__(BLOCK)
   __syncthreads();
   const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
   const uint32_t mask = cap - 1;
-  for (int64_t e = lo + t; e < hi; e += BLOCK) {
-    uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
-    if (c == EMPTY) continue;
-    uint32_t w = a.g.w[e];
-    uint32_t h = hash_slot(c, mask);
-    while (true) {
-      uint32_t prev = atomicCAS(&tab[h].key, EMPTY, c);
-      if (prev == EMPTY || prev == c) {
-        atomicAdd(&tab[h].val, w);
-        break;
+  // four entries per thread and round: their loads and gathers are issued together
+  // (an absent entry reads the row's first and is masked), then inserted
+  constexpr int U = 4;
+  for (int64_t e0 = lo + t; e0 < hi; e0 += U * BLOCK) {
+    uint32_t cs[U], ws[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + (int64_t)u * BLOCK;
+      const bool v = e < hi;
+      const int64_t es = v ? e : lo;
+      const int32_t j = a.g.idx[es];
+      uint32_t c;
+      if (ALGO == ALGO_REFINE)
+        c = a.bound[j] == bi ? (uint32_t)j : EMPTY;
+      else
+        c = (uint32_t)a.C[j];
+      cs[u] = c | ((v && j != i) ? 0u : EMPTY);  // self-loops are skipped
+      ws[u] = a.g.w[es];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t c = cs[u];
+      if (c == EMPTY) continue;
+      uint32_t h = hash_slot(c, mask);
+      while (true) {
+        uint32_t prev = atomicCAS(&tab[h].key, EMPTY, c);
+        if (prev == EMPTY || prev == c) {
+          atomicAdd(&tab[h].val, ws[u]);
+          break;
+        }
+        h = (h + 1) & mask;
       }
-      h = (h + 1) & mask;
     }
   }
   if (GLOBAL) __threadfence();
@@ -853,7 +909,9 @@ __global__ void __launch_bounds__(BLOCK)
   const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
   for (uint32_t x = t; x < cap; x += BLOCK) {
     Pair p = load_slot<GLOBAL>(&tab[x]);
-    if (p.key != EMPTY) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)p.key, p.val, best, bestG);
+    const bool present = p.key != EMPTY;
+    const uint32_t sc = ALGO == ALGO_LPA ? 0u : a.Sig[present ? (int32_t)p.key : d];
+    consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)p.key, p.val, sc, present, best, bestG);
   }
   // block arg-max: larger gain first, then lower community id
 #pragma unroll

@@ -85,7 +85,13 @@ typedef struct {
                              (default and maximum 4096); longer rows a global table  */
   int32_t direct_launch;  /* batched runs: 0 (default) issues each level's sweeps as
                              one captured HIP graph, 1 launches them one by one      */
-  int32_t reserved_params;
+  /* Changes results: */
+  int32_t one_scan;       /* LPA only (Section 4.3, the "1-scan" variant): 1 decides
+                             every vertex from its sketch, taking the label with the
+                             largest accumulated value (ties: the lowest label) with
+                             no second pass; 0 (default) runs the second pass.
+                             Louvain/Leiden calls with 1 return MGCD_E_UNSUPPORTED;
+                             the exact mode is unaffected (its table is exact).     */
 } mgcd_params;
 
 typedef struct {

@@ -37,7 +37,8 @@ class _Params(ct.Structure):
                 ("max_iterations", ct.c_int32), ("max_passes", ct.c_int32),
                 ("threads", ct.c_int32), ("chunk_len", ct.c_int64),
                 ("tolerance", ct.c_double), ("tolerance_drop", ct.c_double),
-                ("aggregation_tolerance", ct.c_double)]
+                ("aggregation_tolerance", ct.c_double), ("one_scan", ct.c_int32),
+                ("reserved", ct.c_int32)]
 
 
 class _Stats(ct.Structure):
@@ -64,7 +65,7 @@ def lib():
         L.oracle_canonical.argtypes = [i32, P, P]
         L.oracle_canonical.restype = None
         L.oracle_move_sweep.argtypes = [i32, P, P, P, ct.c_int, ct.c_int, ct.c_int, i64, P, P, P, P,
-                                        P, i64, ct.c_int, P, P]
+                                        P, i64, ct.c_int, ct.c_int, P, P]
         L.oracle_move_sweep.restype = ct.c_int
         L.oracle_refine.argtypes = [i32, P, P, P, P, P, i64, ct.c_int, ct.c_int, i64, P]
         L.oracle_refine.restype = ct.c_int
@@ -150,10 +151,11 @@ def weighted_degree(g) -> np.ndarray:
 
 
 def move_sweep(g, algo, C, mode=MODE_ALG1, k=8, chunk_len=128, bound=None, K=None, Sigma=None,
-               size=None, W=None, direction=0):
+               size=None, W=None, direction=0, one_scan=0):
     """One synchronous sweep.  Returns (C_new, gain): for Louvain moves C_new holds
     the moves allowed by ``direction`` (-1 lower ids only, +1 higher ids only, 0 all);
-    gain holds the integer gain of every vertex's best move."""
+    gain holds the integer gain of every vertex's best move.  one_scan=1 (LPA): the
+    1-scan variant of Section 4.3, deciding from the sketch's values."""
     off, idx, w = _csr(g)
     n = off.shape[0] - 1
     C = np.ascontiguousarray(C, dtype=np.int32)
@@ -172,8 +174,8 @@ def move_sweep(g, algo, C, mode=MODE_ALG1, k=8, chunk_len=128, bound=None, K=Non
     Cn = np.zeros(n, dtype=np.int32)
     gain = np.zeros(n, dtype=np.int64)
     rc = lib().oracle_move_sweep(n, _p(off), _p(idx), _p(w), algo, mode, k, chunk_len, _p(C),
-                                 _p(bnd), _p(K), _p(Sigma), _p(size), int(W), direction, _p(Cn),
-                                 _p(gain))
+                                 _p(bnd), _p(K), _p(Sigma), _p(size), int(W), direction,
+                                 int(one_scan), _p(Cn), _p(gain))
     if rc:
         raise ValueError("bad sweep arguments")
     return Cn, gain
@@ -223,7 +225,7 @@ def modularity(g, C) -> float:
 
 DEFAULTS = dict(mode=MODE_ALG1, k=8, k_aggregate=None, chunk_len=128, max_iterations=20,
                 max_passes=10, tolerance=None, tolerance_drop=10.0, aggregation_tolerance=0.8,
-                threads=0)
+                threads=0, one_scan=0)
 
 
 def _params(algo: str, **kw) -> _Params:
@@ -235,7 +237,7 @@ def _params(algo: str, **kw) -> _Params:
         o["tolerance"] = 0.05 if algo == "lpa" else 1e-2
     return _Params(o["mode"], o["k"], o["k_aggregate"], o["max_iterations"], o["max_passes"],
                    o["threads"], o["chunk_len"], o["tolerance"], o["tolerance_drop"],
-                   o["aggregation_tolerance"])
+                   o["aggregation_tolerance"], o["one_scan"], 0)
 
 
 def _run(name: str, g, **kw):

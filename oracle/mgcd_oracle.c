@@ -386,6 +386,7 @@ typedef struct {
   const int64_t *Sig;    /* Sigma per community (C's ids) */
   const int32_t *size;   /* members per community */
   int64_t W;             /* total weight = 2m */
+  int one_scan;          /* LPA, 1-scan variant: decide from the sketch's values */
 } sweep_t;
 
 /* The best move of vertex i.  Returns the target (== C[i] if there is none) and
@@ -409,6 +410,21 @@ static int32_t decide_vertex(const sweep_t *s, int32_t i, uint32_t *kbuf, uint32
   int nc = s->mode == OR_MODE_EXACT ? exact_table(kbuf, wbuf, ubuf, n, cbuf)
                                     : stream_sketch(kbuf, wbuf, ubuf, n, s->mode, s->k, s->L, cbuf);
   if (nc == 0) return d;
+  if (s->algo == OR_ALGO_LPA && s->one_scan) {
+    /* The 1-scan variant of LPA (Section 4.3): no second pass; the label whose
+     * accumulated sketch value is largest (ties to the lowest label). */
+    int32_t best = -1;
+    int64_t bv = -1;
+    for (int x = 0; x < nc; ++x) {
+      int32_t c = (int32_t)cbuf[x].key;
+      int64_t v = (int64_t)cbuf[x].val;
+      if (v > bv || (v == bv && c < best)) {
+        bv = v;
+        best = c;
+      }
+    }
+    return best;
+  }
   /* pass 2: exact linking weights K_{i->c} of the candidates and K_{i->d} */
   int64_t Kid = 0;
   for (int x = 0; x < nc; ++x) cbuf[x].val = 0;
@@ -495,10 +511,10 @@ static int64_t apply_direction(int32_t n, const int32_t *C, int32_t *Cnew, int d
 int oracle_move_sweep(int32_t n, const int64_t *off, const int32_t *idx, const uint32_t *w, int algo,
                       int mode, int k, int64_t chunk_len, const int32_t *C, const int32_t *bound,
                       const int64_t *K, const int64_t *Sigma, const int32_t *size, int64_t W,
-                      int direction, int32_t *Cnew, int64_t *gain) {
+                      int direction, int one_scan, int32_t *Cnew, int64_t *gain) {
   if (k < 1 || k > KMAX || chunk_len < 1) return -1;
   graph_t g = {n, off[n], (int64_t *)off, (int32_t *)idx, (uint32_t *)w, 0};
-  sweep_t s = {&g, algo, mode, k, chunk_len, C, bound, K, Sigma, size, W};
+  sweep_t s = {&g, algo, mode, k, chunk_len, C, bound, K, Sigma, size, W, one_scan};
   sweep(&s, Cnew, gain);
   if (algo == OR_ALGO_MOVE) apply_direction(n, C, Cnew, direction);
   return 0;
@@ -522,7 +538,7 @@ static void refine(const graph_t *g, const int32_t *bound, const int64_t *K, int
     ones[i] = 1;
   }
   /* Sigma of a singleton sub-community is K of its vertex */
-  sweep_t s = {g, OR_ALGO_REFINE, mode, k, L, single, bound, K, K, ones, W};
+  sweep_t s = {g, OR_ALGO_REFINE, mode, k, L, single, bound, K, K, ones, W, 0};
   sweep(&s, prop, gain);
   for (int32_t i = 0; i < n; ++i)
     if (prop[i] != i) {
@@ -745,7 +761,8 @@ int oracle_lpa(int32_t n, const int64_t *off, const int32_t *idx, const uint32_t
   for (int32_t i = 0; i < n; ++i) C[i] = i;
   memset(st, 0, sizeof(*st));
   for (int it = 0; it < p->max_iterations; ++it) {
-    sweep_t s = {&g, OR_ALGO_LPA, p->mode, p->k, p->chunk_len, C, NULL, NULL, NULL, NULL, 0};
+    sweep_t s = {&g, OR_ALGO_LPA, p->mode, p->k, p->chunk_len, C, NULL, NULL, NULL, NULL, 0,
+                 p->one_scan};
     sweep(&s, Cn, gain);
     int64_t moved = 0;
     for (int32_t i = 0; i < n; ++i) moved += Cn[i] != C[i];
@@ -787,7 +804,7 @@ static void local_moving(const graph_t *g, const or_params *p, int64_t W, const 
       Sig[C[i]] += K[i];
       size[C[i]] += 1;
     }
-    sweep_t s = {g, OR_ALGO_MOVE, p->mode, p->k, p->chunk_len, C, NULL, K, Sig, size, W};
+    sweep_t s = {g, OR_ALGO_MOVE, p->mode, p->k, p->chunk_len, C, NULL, K, Sig, size, W, 0};
     sweep(&s, Cn, gain);
     int64_t proposed = 0;
     uint64_t sumG = 0;
@@ -817,6 +834,7 @@ int oracle_louvain(int32_t n, const int64_t *off, const int32_t *idx, const uint
                    const or_params *p, int32_t *labels, or_stats *st) {
   int rc = check_params(p);
   if (rc) return rc;
+  if (p->one_scan) return -6; /* the 1-scan variant is defined for LPA only */
   set_threads(p);
   memset(st, 0, sizeof(*st));
   graph_t g = {n, off[n], (int64_t *)off, (int32_t *)idx, (uint32_t *)w, 0};
@@ -873,6 +891,7 @@ int oracle_leiden(int32_t n, const int64_t *off, const int32_t *idx, const uint3
                   const or_params *p, int32_t *labels, or_stats *st) {
   int rc = check_params(p);
   if (rc) return rc;
+  if (p->one_scan) return -6; /* the 1-scan variant is defined for LPA only */
   set_threads(p);
   memset(st, 0, sizeof(*st));
   graph_t g = {n, off[n], (int64_t *)off, (int32_t *)idx, (uint32_t *)w, 0};

@@ -26,6 +26,8 @@ typedef struct {
   double tolerance;
   double tolerance_drop;
   double aggregation_tolerance;
+  int32_t one_scan; /* LPA only: 1 = the 1-scan variant (Section 4.3) */
+  int32_t reserved;
 } or_params;
 
 typedef struct {
@@ -45,7 +47,7 @@ void oracle_canonical(int32_t n, const int32_t *C, int32_t *out);
 int oracle_move_sweep(int32_t n, const int64_t *off, const int32_t *idx, const uint32_t *w, int algo,
                       int mode, int k, int64_t chunk_len, const int32_t *C, const int32_t *bound,
                       const int64_t *K, const int64_t *Sigma, const int32_t *size, int64_t W,
-                      int direction, int32_t *Cnew, int64_t *gain);
+                      int direction, int one_scan, int32_t *Cnew, int64_t *gain);
 int oracle_refine(int32_t n, const int64_t *off, const int32_t *idx, const uint32_t *w,
                   const int32_t *bound, const int64_t *K, int64_t W, int mode, int k,
                   int64_t chunk_len, int32_t *R);

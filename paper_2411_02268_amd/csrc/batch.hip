@@ -244,6 +244,7 @@ static void level_sweeps(LevelSweeps &L, const mgcd_params *p, const Schedule &s
       args.Wg = L.Wg;
       args.active = L.active;
       args.gctr = L.gctr;
+      args.one_scan = L.algo == ALGO_LPA ? p->one_scan : 0;
       launch_sweep(args, sch, L.algo, p->mode, p->k, p->chunk_len, s);
       if (L.algo != ALGO_LPA) launch_apply_moves(L.C[0], L.C[1], L.K, L.Sig, L.g.n, s);
       if (L.algo == ALGO_LPA)

@@ -68,6 +68,7 @@ static void check_params(const mgcd_params *p) {
   if (rl < 0 || rl > 64 || (rl & (rl - 1)) != 0)
     throw Error(MGCD_E_ARG, "row_lanes must be 0 or a power of two up to 64");
   if (p->direct_launch != 0 && p->direct_launch != 1) throw Error(MGCD_E_ARG, "direct_launch must be 0 or 1");
+  if (p->one_scan != 0 && p->one_scan != 1) throw Error(MGCD_E_ARG, "one_scan must be 0 or 1");
   if (p->exact_small < 0 || p->exact_lds < 0 || p->exact_lds_big < 0)
     throw Error(MGCD_E_ARG, "exact tier bounds must be >= 0");
   const SchedParams sp = sched_params(p);
@@ -173,6 +174,7 @@ static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Are
     LevelState h = run_sweeps(p->max_iterations, ls, st, &ct, s, [&](int, int j) {
       SweepArgs args{g, Ca, nullptr, K, nullptr, 0, 0, Cb, nullptr, ctr};
       args.halt = &ls->halt;
+      args.one_scan = p->one_scan;
       launch_sweep(args, sch, ALGO_LPA, p->mode, p->k, p->chunk_len, st, ct.ev[j]);
       launch_level_converge(ALGO_LPA, LevelRule{ctr, ls, g.nnz, n, p->tolerance, 0.0}, st);
       std::swap(Ca, Cb);  // a halted sweep copies C, so either buffer holds the result
@@ -194,6 +196,7 @@ static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Are
 static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Arena &a,
                        hipStream_t st, mgcd_stats *stats) {
   check_params(p);
+  if (p->one_scan) throw Error(MGCD_E_UNSUPPORTED, "one_scan is defined for LPA only");
   Graph g0 = view(gin);
   const int32_t n = g0.n;
   const int64_t nnz = g0.nnz;
@@ -477,6 +480,7 @@ int mgcd_move_sweep(const mgcd_csr *gin, const mgcd_params *p, int32_t algo, con
     build_schedule(g, sched_params(p), sch, a, st);
     launch_zero_u64(ctr, 3, st);
     SweepArgs args{g, C, nullptr, K, Sig, W, direction < 0 ? -1 : direction > 0 ? 1 : 0, C_new, gain, ctr};
+    args.one_scan = algo == MGCD_ALGO_LPA ? p->one_scan : 0;
     launch_sweep(args, sch, algo == MGCD_ALGO_LPA ? ALGO_LPA : ALGO_MOVE, p->mode, p->k, p->chunk_len, st);
     Counts c = read_counts(ctr, st);
     if (counters) {
@@ -547,6 +551,8 @@ static int run_batched_checked(int32_t algo, const mgcd_csr *graphs, int32_t cou
   return guarded([&] {
     if (!graphs || !outs || count < 0) throw Error(MGCD_E_ARG, "null argument");
     check_params(p);
+    if (p->one_scan && algo != MGCD_ALGO_LPA)
+      throw Error(MGCD_E_UNSUPPORTED, "one_scan is defined for LPA only");
     int64_t N = 0, E = 0;
     for (int32_t g = 0; g < count; ++g) {
       N += graphs[g].n;

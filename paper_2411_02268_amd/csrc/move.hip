@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
   if (f) flag_any = 1;
   bool lossy = tree_reduce<K>(sk, cb, nc, lds);
   lossy |= flag_any != 0;  // settled by the barriers inside tree_reduce
-  if (lossy) {
+  if (lossy && second_pass(a, ALGO)) {
     if (t < K) cand[(int64_t)m * K + t] = lds[t];
     if (t == 0) cflag[m] = 1;
     return;
@@ -529,7 +529,7 @@ __device__ inline void row_work(const SweepArgs &a, const Buckets &bk, int64_t L
   const uint64_t seg = P == 64 ? lm : (lm >> base_lane) & ((1ull << P) - 1);
   const int32_t d = valid ? community_of_self<ALGO>(a, i) : 0;
   uint32_t kd = 0;
-  const bool need2 = seg != 0;  // same for all lanes of a row
+  const bool need2 = seg != 0 && second_pass(a, ALGO);  // same for all lanes of a row
   if (!need2) {
 #pragma unroll
     for (int p = 0; p < K; ++p) kd += key[p] == (uint32_t)d ? ex[p] : 0u;
@@ -664,7 +664,7 @@ __global__ void __launch_bounds__(BLOCK)
     tree.result(ck, cv);
     lossy |= tree.lossy;
     uint32_t kd = 0;
-    if (!lossy) {
+    if (!lossy || !second_pass(a, ALGO)) {
       kd = wave_sum(ck == (uint32_t)d ? cv : 0u);
     } else {
       cv = 0;

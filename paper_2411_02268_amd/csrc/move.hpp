@@ -27,7 +27,13 @@ struct SweepArgs {
   // Single graph: a device flag; once set, every vertex keeps its community (the
   // sweep only copies C to C_new).  Null: always move.
   const uint32_t *halt = nullptr;
+  // LPA, the 1-scan variant (Section 4.3): every row decides from its sketch's values
+  // (treated as exact), so no row takes the second pass.
+  int32_t one_scan = 0;
 };
+
+// Whether a row whose sketch lost weight still needs the second pass.
+__device__ inline bool second_pass(const SweepArgs &a, int algo) { return !(algo == ALGO_LPA && a.one_scan); }
 
 // A single graph's level, kept on the device so that sweeps need no host round trip:
 // set `halt` when the level's stopping rule fires; count sweeps, streamed entries

@@ -329,3 +329,60 @@ def test_batched_many_graphs_dirty_workspace(mg, algo):
         assert np.array_equal(_np(lab), _np(solo))
         for key in ("iterations", "passes", "communities", "edges_scanned", "moved_last"):
             assert st[key] == sst[key], key
+
+
+# ---------------------------------------------------------------------------------
+# LPA, the 1-scan variant (Section 4.3): decisions from the sketch's values
+# ---------------------------------------------------------------------------------
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12"])
+@pytest.mark.parametrize("mode", ["alg1", "uncond", "std"])
+# L = 1 and 2 put the R-MAT hubs on the long-row path; k = 32 and 64 use the wave sketch
+@pytest.mark.parametrize("k,L", [(1, 128), (4, 7), (8, 2), (16, 5), (8, 1), (32, 128), (64, 16)])
+def test_lpa_one_scan_sweep_parity(mg, gname, mode, k, L):
+    g = graph(gname)
+    dg = mg.to_device(g)
+    rng = np.random.default_rng(zlib.crc32(f"1scan-{gname}-{mode}-{k}-{L}".encode()))
+    C = rng.integers(0, max(2, g.n // 5), size=g.n).astype(np.int32)
+    Cn, _, ctr = mg.move_sweep(dg, mg.ALGO_LPA, _t(C), 0, mode=MODES[mode], k=k, chunk_len=L,
+                               one_scan=1)
+    eC, _ = oracle.move_sweep(g, oracle.ALGO_LPA, C, mode=MODES[mode], k=k, chunk_len=L,
+                              one_scan=1)
+    assert np.array_equal(_np(Cn), eC)
+    assert ctr[0] == int((eC != C).sum())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("k,L", [(1, 128), (8, 128), (8, 4), (64, 16)])
+def test_lpa_one_scan_run_parity(mg, k, L):
+    for gname in ("rmat11", "planted", "cl12"):
+        g = graph(gname)
+        dg = mg.to_device(g)
+        lab, st = mg.lpa(dg, k=k, chunk_len=L, one_scan=1)
+        elab, est = oracle.lpa(g, k=k, chunk_len=L, one_scan=1)
+        assert np.array_equal(_np(lab), elab), gname
+        assert st["iterations"] == est.iterations and st["edges_scanned"] == est.edges_scanned
+    # batched runs take the same decisions
+    gs = _batch_graphs()
+    dgs = [mg.to_device(g) for g in gs]
+    labs, gst, _ = mg.run_batched(mg.ALGO_LPA, dgs, k=k, chunk_len=L, one_scan=1)
+    for g, lab in zip(gs, labs):
+        if g.n:
+            elab, _ = oracle.lpa(g, k=k, chunk_len=L, one_scan=1)
+            assert np.array_equal(_np(lab), elab)
+
+
+@pytest.mark.gpu
+def test_one_scan_is_lpa_only(mg):
+    dg = mg.to_device(graph("er200"))
+    for fn in (mg.louvain, mg.leiden):
+        with pytest.raises(mg.MgcdError) as ei:
+            fn(dg, one_scan=1)
+        assert ei.value.code == -6
+    with pytest.raises(mg.MgcdError) as ei:
+        mg.run_batched(mg.ALGO_LOUVAIN, [dg], one_scan=1)
+    assert ei.value.code == -6
+    with pytest.raises(mg.MgcdError) as ei:
+        mg.lpa(dg, one_scan=2)
+    assert ei.value.code == -1

@@ -102,6 +102,78 @@ def test_lpa_mg_step_uses_sketch_candidates():
         assert Cn[i] == min(c for c in sk if tot[c] == m)
 
 
+def _star(weights, labels):
+    """Vertex 0 joined to vertices 1..len(weights) with the given weights; C[j] =
+    labels[j - 1] for the leaves, C[0] = 0."""
+    n = 1 + len(weights) + 16
+    u = np.zeros(len(weights), dtype=np.int64)
+    v = np.arange(1, len(weights) + 1, dtype=np.int64)
+    g = synth.csr_from_undirected(n, u, v, w=np.asarray(weights, dtype=np.uint32))
+    C = np.arange(n, dtype=np.int32)
+    C[0] = 0
+    C[1:1 + len(labels)] = labels
+    return g, C
+
+
+def test_lpa_one_scan_hand_trace():
+    # Vertex 0's stream in CSR order: (a,5) (b,1) (c,5) (a,1) (b,3), k = 2.
+    # Algorithm 1: {a:5} -> {a:5, b:1} -> c misses a full sketch: a and b drop to 0
+    # and c is dropped -> a revived with 1 -> b revived with 3: sketch {a:1, b:3}.
+    # 1-scan (Section 4.3) takes the largest sketch value: b.  The second pass finds
+    # K_{0->a} = 6 > K_{0->b} = 4: a.
+    a, b, c = 10, 11, 12
+    g, C = _star([5, 1, 5, 1, 3], [a, b, c, a, b])
+    assert oracle.sketch_stream([a, b, c, a, b], [5, 1, 5, 1, 3], k=2) == {a: 1, b: 3}
+    one, _ = oracle.move_sweep(g, oracle.ALGO_LPA, C, mode=oracle.MODE_ALG1, k=2, one_scan=1)
+    two, _ = oracle.move_sweep(g, oracle.ALGO_LPA, C, mode=oracle.MODE_ALG1, k=2, one_scan=0)
+    assert one[0] == b and two[0] == a
+    # equal sketch values: the lower label
+    g, C = _star([2, 2], [b, a])
+    one, _ = oracle.move_sweep(g, oracle.ALGO_LPA, C, mode=oracle.MODE_ALG1, k=2, one_scan=1)
+    assert one[0] == a
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_ALG1, oracle.MODE_UNCOND, oracle.MODE_STD])
+def test_lpa_one_scan_takes_largest_sketch_value(mode):
+    # every vertex: the label of the largest value of its (pinned) merged sketch,
+    # lowest on ties; an empty sketch keeps the label
+    rng = np.random.default_rng(11)
+    g = synth.random_small(60, 0.3, 6, seed=11, loops=True)
+    C = rng.integers(0, 20, size=g.n).astype(np.int32)
+    k, L = 3, 5
+    Cn, _ = oracle.move_sweep(g, oracle.ALGO_LPA, C, mode=mode, k=k, chunk_len=L, one_scan=1)
+    for i in range(g.n):
+        lo, hi = g.offsets[i], g.offsets[i + 1]
+        js, ws = g.indices[lo:hi], g.weights[lo:hi]
+        sketches = []
+        for s0 in range(0, hi - lo, L):
+            kk = [int(C[j]) for j in js[s0:s0 + L] if j != i]
+            ww = [int(w) for j, w in zip(js[s0:s0 + L], ws[s0:s0 + L]) if j != i]
+            sketches.append(oracle.sketch_stream(kk, ww, mode=mode, k=k))
+        while len(sketches) > 1:
+            nxt = [oracle.mg_merge(sketches[x], sketches[x + 1], k)
+                   for x in range(0, len(sketches) - 1, 2)]
+            if len(sketches) % 2:
+                nxt.append(sketches[-1])
+            sketches = nxt
+        sk = sketches[0] if sketches else {}
+        if not sk:
+            assert Cn[i] == C[i]
+            continue
+        m = max(sk.values())
+        assert Cn[i] == min(c for c, v in sk.items() if v == m)
+
+
+def test_lpa_one_scan_equals_two_scan_when_sketch_is_exact():
+    # k covering every key: the sketch values are the exact weights (no subtraction)
+    g = synth.random_small(80, 0.2, 5, seed=3)
+    a, sa = oracle.lpa(g, one_scan=1, **BIGK)
+    b, sb = oracle.lpa(g, one_scan=0, **BIGK)
+    assert np.array_equal(a, b) and sa == sb
+    with pytest.raises(ValueError):
+        oracle.louvain(g, one_scan=1)
+
+
 def test_lpa_planted_finds_structure():
     g, truth = synth.planted_exact()
     for mode in (oracle.MODE_EXACT, oracle.MODE_ALG1):

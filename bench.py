@@ -23,6 +23,8 @@ import time
 
 import numpy as np
 
+from paper_2411_02268_amd.quality import nmi
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -192,13 +194,17 @@ def batched_leg(mg, torch, count: int, nmax: float, workers: int):
         t_plain = time.perf_counter() - a
         for x, y in zip(labs, plain_labels):
             same &= bool(torch.equal(x, y))
-        qs = [mg.modularity(g, lab) for g, lab in zip(sample, labs[:: max(1, count // 32)][:32])]
+        sample_labs = labs[:: max(1, count // 32)][:32]
+        qs = [mg.modularity(g, lab) for g, lab in zip(sample, sample_labs)]
+        nmis = [nmi(lab.cpu().numpy(), synth.planted_batch_truth(gi, nmax=nmax)[1])
+                for gi, lab in zip(range(0, count, max(1, count // 32)), sample_labs)]
         edges = sum(p["edges_scanned"] for p in per)
         out[name] = {"k": tuned["k"], "row_lanes": tuned["row_lanes"],
                      "quality_rule_met": tuned["report"]["quality_met"],
                      "batched_s": t_batch, "plain_s": t_plain, "speedup": t_plain / t_batch,
                      "batched_edges_per_s": edges / t_batch, "labels_identical_to_plain": same,
-                     "mean_Q_sample": float(np.mean(qs))}
+                     "mean_Q_sample": float(np.mean(qs)),
+                     "mean_nmi_sample_vs_planted": float(np.mean(nmis))}
         print(f"[bench] batched {name}: k={tuned['k']} batch {t_batch*1e3:.1f} ms vs plain "
               f"{t_plain*1e3:.1f} ms ({t_plain/t_batch:.2f}x), identical={same}",
               file=sys.stderr, flush=True)
@@ -207,22 +213,22 @@ def batched_leg(mg, torch, count: int, nmax: float, workers: int):
 
 
 WORKLOADS = {
-    # name: (algorithm, k, graph description, generator)
+    # name: (algorithm, k, graph description, generator -> (CSR, planted communities or None))
     "louvain-mg-k8-rmat20": (
         "louvain", 8, "R-MAT scale 20, edge factor 16, a/b/c=0.57/0.19/0.19, weights U[1,8], seed 2",
-        lambda synth: synth.rmat(scale=20, edge_factor=16, seed=2)),
+        lambda synth: (synth.rmat(scale=20, edge_factor=16, seed=2), None)),
     "leiden-mg-k16-cl24": (
         "leiden", 16, "Chung-Lu 2^24 vertices, mean degree 32, exponent 2.1, weights U[1,4], seed 3",
-        lambda synth: synth.chung_lu(n=1 << 24, avg_deg=32, seed=3)),
+        lambda synth: (synth.chung_lu(n=1 << 24, avg_deg=32, seed=3), None)),
     "leiden-mg-k64-cl24": (
         "leiden", 64, "Chung-Lu 2^24 vertices, mean degree 32, exponent 2.1, weights U[1,4], seed 3",
-        lambda synth: synth.chung_lu(n=1 << 24, avg_deg=32, seed=3)),
+        lambda synth: (synth.chung_lu(n=1 << 24, avg_deg=32, seed=3), None)),
     "louvain-mg-k64-rmat20": (
         "louvain", 64, "R-MAT scale 20, edge factor 16, a/b/c=0.57/0.19/0.19, weights U[1,8], seed 2",
-        lambda synth: synth.rmat(scale=20, edge_factor=16, seed=2)),
+        lambda synth: (synth.rmat(scale=20, edge_factor=16, seed=2), None)),
     "lpa-mg-k8-planted": (
         "lpa", 8, "planted partition 20 x 500, 12 intra + 4 inter edges per vertex, weight 1, seed 1",
-        lambda synth: synth.planted_exact(n_comm=20, comm_size=500, seed=1)[0]),
+        lambda synth: synth.planted_exact(n_comm=20, comm_size=500, seed=1)),
 }
 DEFAULT_WORKLOAD = "louvain-mg-k8-rmat20"
 
@@ -274,7 +280,7 @@ def main():
     L = 128
     fn = {"lpa": mg.lpa, "louvain": mg.louvain, "leiden": mg.leiden}[algo_name]
     t0 = time.time()
-    g = gen(synth)
+    g, truth = gen(synth)
     gen_s = time.time() - t0
     print(f"[bench] {args.workload}: graph n={g.n} nnz={g.nnz} W={g.total_weight()} generated in "
           f"{gen_s:.1f}s", file=sys.stderr, flush=True)
@@ -327,6 +333,13 @@ def main():
                  "ms_per_step": secs_x / args.exact_steps * 1e3}
         print(f"[bench] exact: {args.exact_steps} steps in {secs_x:.3f}s, "
               f"{edges_x/secs_x/1e9:.3f} G edges/s, Q={q_x:.6f}", file=sys.stderr, flush=True)
+
+    ground_truth = None
+    if truth is not None:  # planted partition: NMI of the labels against it
+        ground_truth = {"nmi_mg": nmi(lab.cpu().numpy(), truth)}
+        if args.exact_steps > 0:
+            ground_truth["nmi_exact"] = nmi(lab_x.cpu().numpy(), truth)
+        print(f"[bench] NMI vs planted partition: {ground_truth}", file=sys.stderr, flush=True)
 
     serving = None
     if args.serve_requests > 0:
@@ -389,6 +402,7 @@ def main():
         "config": {"workload": args.workload, "graph": graph_desc, "n": g.n, "nnz": g.nnz,
                    "k": k, "chunk_len": L, "algorithm": algo_name, "parallelism": "single-gpu"},
         "modularity": {"mg": q_mg, "exact": q_x, "ratio": q_mg / q_x if q_x else None},
+        "ground_truth": ground_truth,
         "exact": exact,
         "stats": {key: st_last[key] for key in ("iterations", "passes", "communities",
                                                  "ms_local_move", "ms_refine", "ms_aggregate",

@@ -37,7 +37,10 @@ enum {
   MGCD_MODE_EXACT = 0,  /* exact per-vertex table (the hashtable of Section 4, Fig. 1) */
   MGCD_MODE_ALG1 = 1,   /* Algorithm 1, conditional subtraction (Appendix A.1)       */
   MGCD_MODE_UNCOND = 2, /* unconditional subtraction (Section 4.1, first variant)    */
-  MGCD_MODE_STD = 3     /* textbook weighted MG (subtract min(w, smallest value))     */
+  MGCD_MODE_STD = 3,    /* textbook weighted MG (subtract min(w, smallest value))     */
+  MGCD_MODE_BM = 4      /* weighted Boyer-Moore (Section 4.1): Algorithm 1 with k = 1
+                           for local moving and refinement and k = 4 for aggregation;
+                           the k and k_aggregate fields are ignored                   */
 };
 
 enum { MGCD_ALGO_LPA = 0, MGCD_ALGO_LOUVAIN = 1, MGCD_ALGO_LEIDEN = 2 };

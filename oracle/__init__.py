@@ -19,6 +19,9 @@ SRC = os.path.join(HERE, "mgcd_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 MODE_EXACT, MODE_ALG1, MODE_UNCOND, MODE_STD = 0, 1, 2, 3
+# weighted Boyer-Moore (Section 4.1): Algorithm 1 with one slot for local moving and
+# refinement and four for aggregation (resolved in _params)
+MODE_BM = 4
 ALGO_LPA, ALGO_MOVE, ALGO_REFINE = 0, 1, 2
 
 
@@ -233,6 +236,8 @@ def _params(algo: str, **kw) -> _Params:
     o.update(kw)
     if o["k_aggregate"] is None:
         o["k_aggregate"] = o["k"]
+    if o["mode"] == MODE_BM:
+        o["mode"], o["k"], o["k_aggregate"] = MODE_ALG1, 1, 4
     if o["tolerance"] is None:
         o["tolerance"] = 0.05 if algo == "lpa" else 1e-2
     return _Params(o["mode"], o["k"], o["k_aggregate"], o["max_iterations"], o["max_passes"],

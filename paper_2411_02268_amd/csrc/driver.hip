@@ -359,6 +359,24 @@ static Arena make_arena(void *ws, size_t bytes) {
   return a;
 }
 
+// MGCD_MODE_BM is Algorithm 1 with one slot for local moving and refinement and four
+// for aggregation (the weighted Boyer-Moore variant of Section 4.1); every entry
+// point works on the resolved copy.
+static mgcd_params resolved(const mgcd_params *p) {
+  mgcd_params q{};
+  if (!p) return q;
+  q = *p;
+  if (q.mode == MGCD_MODE_BM) {
+    q.mode = MGCD_MODE_ALG1;
+    q.k = 1;
+    q.k_aggregate = 4;
+  }
+  return q;
+}
+#define MGCD_RESOLVE(p)                 \
+  const mgcd_params resolved_ = resolved(p); \
+  if (p) p = &resolved_
+
 extern "C" {
 
 void mgcd_default_params(int32_t algo, mgcd_params *p) {
@@ -377,6 +395,7 @@ void mgcd_default_params(int32_t algo, mgcd_params *p) {
 }
 
 size_t mgcd_workspace_bytes(int32_t algo, int32_t n, int64_t nnz, const mgcd_params *p) {
+  MGCD_RESOLVE(p);
   mgcd_params d;
   if (!p) {
     mgcd_default_params(algo, &d);
@@ -387,6 +406,7 @@ size_t mgcd_workspace_bytes(int32_t algo, int32_t n, int64_t nnz, const mgcd_par
 
 static int run_checked(int32_t algo, const mgcd_csr *g, const mgcd_params *p, int32_t *out, void *ws,
                        size_t ws_bytes, mgcd_stats *stats, void *stream) {
+  MGCD_RESOLVE(p);
   return guarded([&] {
     if (!g || !p) throw Error(MGCD_E_ARG, "null argument");
     if (g->n > 0 && !out) throw Error(MGCD_E_ARG, "communities_out is null");
@@ -461,6 +481,7 @@ int modularity(const mgcd_csr *gin, const int32_t *C, double *q, void *ws, size_
 int mgcd_move_sweep(const mgcd_csr *gin, const mgcd_params *p, int32_t algo, const int32_t *C,
                     int32_t direction, int32_t *C_new, int64_t *gain, int64_t *counters, void *ws,
                     size_t ws_bytes, void *stream) {
+  MGCD_RESOLVE(p);
   return guarded([&] {
     check_params(p);
     Graph g = view(gin);
@@ -493,6 +514,7 @@ int mgcd_move_sweep(const mgcd_csr *gin, const mgcd_params *p, int32_t algo, con
 
 int mgcd_refine(const mgcd_csr *gin, const mgcd_params *p, const int32_t *bound, int32_t *R, void *ws,
                 size_t ws_bytes, void *stream) {
+  MGCD_RESOLVE(p);
   return guarded([&] {
     check_params(p);
     Graph g = view(gin);
@@ -518,6 +540,7 @@ int mgcd_refine(const mgcd_csr *gin, const mgcd_params *p, const int32_t *bound,
 int mgcd_aggregate(const mgcd_csr *gin, const mgcd_params *p, const int32_t *D, int32_t m,
                    int32_t symmetric, int64_t *out_off, int32_t *out_idx, uint32_t *out_w,
                    int64_t *out_nnz, void *ws, size_t ws_bytes, void *stream) {
+  MGCD_RESOLVE(p);
   return guarded([&] {
     check_params(p);
     Graph g = view(gin);
@@ -536,6 +559,7 @@ int mgcd_aggregate(const mgcd_csr *gin, const mgcd_params *p, const int32_t *D, 
 
 size_t mgcd_workspace_bytes_batched(int32_t algo, int32_t count, int64_t total_n, int64_t total_nnz,
                                     const mgcd_params *p) {
+  MGCD_RESOLVE(p);
   mgcd_params d;
   if (!p) {
     mgcd_default_params(algo, &d);
@@ -548,6 +572,7 @@ size_t mgcd_workspace_bytes_batched(int32_t algo, int32_t count, int64_t total_n
 static int run_batched_checked(int32_t algo, const mgcd_csr *graphs, int32_t count, const mgcd_params *p,
                                int32_t *const *outs, void *ws, size_t ws_bytes, mgcd_graph_stats *gs,
                                mgcd_stats *total, void *stream) {
+  MGCD_RESOLVE(p);
   return guarded([&] {
     if (!graphs || !outs || count < 0) throw Error(MGCD_E_ARG, "null argument");
     check_params(p);

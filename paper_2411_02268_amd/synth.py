@@ -302,6 +302,15 @@ def _planted_one(args):
     return planted_uneven(n, cmin, cmax, 6, 4, rng)[0]
 
 
+def planted_batch_truth(g: int, nmin: float = 1e3, nmax: float = 2e5, cmin: int = 20,
+                        cmax: int = 2000, base_seed: int = 4000):
+    """Graph g of ``planted_batch`` (same arguments) with its planted communities:
+    (CSR, truth)."""
+    rng = np.random.default_rng(base_seed + g)
+    n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+    return planted_uneven(n, cmin, cmax, 6, 4, rng)
+
+
 def planted_batch(count: int = 4096, nmin: float = 1e3, nmax: float = 2e5, cmin: int = 20,
                   cmax: int = 2000, base_seed: int = 4000, workers: int = 1):
     """`count` planted graphs; graph g uses seed base_seed + g and has a vertex count

@@ -386,3 +386,18 @@ def test_one_scan_is_lpa_only(mg):
     with pytest.raises(mg.MgcdError) as ei:
         mg.lpa(dg, one_scan=2)
     assert ei.value.code == -1
+
+
+@pytest.mark.gpu
+def test_boyer_moore_mode(mg):
+    # MGCD_MODE_BM resolves to Algorithm 1 with k = 1 (moving, refinement) and
+    # k_aggregate = 4, on the device and in the oracle alike
+    for gname in ("rmat11", "planted"):
+        g = graph(gname)
+        dg = mg.to_device(g)
+        for algo in ("lpa", "louvain", "leiden"):
+            lab, st = getattr(mg, algo)(dg, mode=mg.MODE_BM, k=16, chunk_len=32)
+            same, sst = getattr(mg, algo)(dg, mode=mg.MODE_ALG1, k=1, k_aggregate=4, chunk_len=32)
+            elab, est = getattr(oracle, algo)(g, mode=oracle.MODE_BM, chunk_len=32)
+            assert np.array_equal(_np(lab), _np(same)) and np.array_equal(_np(lab), elab)
+            assert st["iterations"] == est.iterations and st["passes"] == est.passes

@@ -193,3 +193,31 @@ def test_merge_properties(a, b, k):
         assert m == dict(total)
     # the merge is symmetric in its arguments
     assert oracle.mg_merge(b, a, k) == m
+
+
+def boyer_moore(keys):
+    """Textbook Boyer-Moore majority vote: one candidate and a counter; the same key
+    raises the counter, another key lowers it, a zero counter takes the new key."""
+    cand, cnt = None, 0
+    for x in keys:
+        if cnt == 0:
+            cand, cnt = x, 1
+        elif x == cand:
+            cnt += 1
+        else:
+            cnt -= 1
+    return {cand: cnt} if cnt > 0 else {}
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_one_slot_unit_weights_is_boyer_moore(seed):
+    # Algorithm 1 with k = 1 on unit weights is the Boyer-Moore vote (the weighted BM
+    # of Section 4.1 reduces to it), so a key held by more than half of the stream
+    # is always the surviving candidate
+    rng = np.random.default_rng(seed)
+    for n in (1, 2, 7, 30, 101):
+        keys = rng.integers(0, 4, size=n).tolist()
+        assert oracle.sketch_stream(keys, [1] * n, k=1) == boyer_moore(keys)
+        maj = [5] * (n // 2 + 1) + rng.integers(0, 4, size=n - n // 2 - 1).tolist()
+        rng.shuffle(maj)
+        assert list(oracle.sketch_stream(maj, [1] * n, k=1)) == [5]

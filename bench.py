@@ -212,6 +212,46 @@ def batched_leg(mg, torch, count: int, nmax: float, workers: int):
     return out
 
 
+def k_sweep_leg(mg, torch, dg, repeats: int = 3, chunk_len: int = 128):
+    """Synthetic analogue of the paper's k sweeps (Figs. 4-6): for LPA, Louvain and
+    Leiden, each sketch variant (Algorithm 1, unconditional subtraction, LPA 1-scan)
+    at k = 1..64 and the weighted Boyer-Moore mode, the run time and modularity
+    relative to the exact table on the same graph (median of `repeats` runs)."""
+    def timed(fn, **kw):
+        lab, _ = fn(dg, chunk_len=chunk_len, **kw)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(repeats):
+            a = time.perf_counter()
+            lab, _ = fn(dg, chunk_len=chunk_len, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - a)
+        return float(np.median(ts)), mg.modularity(dg, lab)
+
+    out = {}
+    for name in ("lpa", "louvain", "leiden"):
+        fn = getattr(mg, name)
+        t_x, q_x = timed(fn, mode=mg.MODE_EXACT)
+        res = {"exact": {"ms": t_x * 1e3, "Q": q_x}}
+        variants = [("alg1", dict(mode=mg.MODE_ALG1)), ("uncond", dict(mode=mg.MODE_UNCOND))]
+        if name == "lpa":
+            variants.append(("alg1_1scan", dict(mode=mg.MODE_ALG1, one_scan=1)))
+        for vname, kw in variants:
+            res[vname] = {}
+            for k in (1, 2, 4, 8, 16, 32, 64):
+                t, q = timed(fn, k=k, **kw)
+                res[vname][str(k)] = {"rel_time": t / t_x, "rel_Q": q / q_x if q_x else None}
+        t, q = timed(fn, mode=mg.MODE_BM)
+        res["bm"] = {"rel_time": t / t_x, "rel_Q": q / q_x if q_x else None}
+        out[name] = res
+        best = min((v for v in res["alg1"].values() if v["rel_Q"] and v["rel_Q"] >= 0.99),
+                   key=lambda v: v["rel_time"], default=None)
+        print(f"[bench] k sweep {name}: exact {t_x*1e3:.2f} ms Q={q_x:.4f}; alg1 rel_Q by k "
+              + " ".join(f"{k}:{v['rel_Q']:.3f}" for k, v in res["alg1"].items())
+              + f"; fastest within 1 %: {best}", file=sys.stderr, flush=True)
+    return out
+
+
 WORKLOADS = {
     # name: (algorithm, k, graph description, generator -> (CSR, planted communities or None))
     "louvain-mg-k8-rmat20": (
@@ -256,6 +296,8 @@ def main():
                     help="graphs of the batched leg (0 skips it; default 1024 with the "
                          "default workload, else 0)")
     ap.add_argument("--batch-nmax", type=float, default=2e5)
+    ap.add_argument("--k-sweep", action="store_true",
+                    help="also run the k sweep of every sketch variant on the workload graph")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="finish with three 512 MiB device-to-device copies, the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -350,6 +392,8 @@ def main():
         batched = batched_leg(mg, torch, args.batch_graphs, args.batch_nmax,
                               min(16, host_threads()))
 
+    ksweep = k_sweep_leg(mg, torch, dg) if args.k_sweep else None
+
     if args.calibrate_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -403,6 +447,7 @@ def main():
                    "k": k, "chunk_len": L, "algorithm": algo_name, "parallelism": "single-gpu"},
         "modularity": {"mg": q_mg, "exact": q_x, "ratio": q_mg / q_x if q_x else None},
         "ground_truth": ground_truth,
+        "k_sweep": ksweep,
         "exact": exact,
         "stats": {key: st_last[key] for key in ("iterations", "passes", "communities",
                                                  "ms_local_move", "ms_refine", "ms_aggregate",

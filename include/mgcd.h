@@ -38,9 +38,15 @@ enum {
   MGCD_MODE_ALG1 = 1,   /* Algorithm 1, conditional subtraction (Appendix A.1)       */
   MGCD_MODE_UNCOND = 2, /* unconditional subtraction (Section 4.1, first variant)    */
   MGCD_MODE_STD = 3,    /* textbook weighted MG (subtract min(w, smallest value))     */
-  MGCD_MODE_BM = 4      /* weighted Boyer-Moore (Section 4.1): Algorithm 1 with k = 1
+  MGCD_MODE_BM = 4,     /* weighted Boyer-Moore (Section 4.1): Algorithm 1 with k = 1
                            for local moving and refinement and k = 4 for aggregation;
                            the k and k_aggregate fields are ignored                   */
+  MGCD_MODE_SMALL = 5   /* small mod-based table (Appendix A.2): k (1 .. 2^30) slots per
+                           vertex; key c counts in slot c mod k, a slot stands for the
+                           first key (in row order) that reached it with the summed
+                           weight of every key that did, and K_{i->d} is the sum in
+                           d's slot; no second pass; aggregation is exact (k_aggregate
+                           ignored)                                                   */
 };
 
 enum { MGCD_ALGO_LPA = 0, MGCD_ALGO_LOUVAIN = 1, MGCD_ALGO_LEIDEN = 2 };

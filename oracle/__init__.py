@@ -22,6 +22,8 @@ MODE_EXACT, MODE_ALG1, MODE_UNCOND, MODE_STD = 0, 1, 2, 3
 # weighted Boyer-Moore (Section 4.1): Algorithm 1 with one slot for local moving and
 # refinement and four for aggregation (resolved in _params)
 MODE_BM = 4
+# small mod-based table (Appendix A.2): k is the number of slots; aggregation is exact
+MODE_SMALL = 5
 ALGO_LPA, ALGO_MOVE, ALGO_REFINE = 0, 1, 2
 
 

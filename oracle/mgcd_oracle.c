@@ -280,6 +280,45 @@ static int exact_table(const uint32_t *key, const uint32_t *w, const uint8_t *us
   return (int)r;
 }
 
+/* The small mod-based table of Appendix A.2 with S slots: an entry with key c lands
+ * in slot c mod S; a slot keeps the first key that reached it (in stream order) and
+ * accumulates the weights of every key that reaches it, colliding or not.  out:
+ * the used slots as (first key, summed weight), ascending slot.  *vd: the sum in
+ * the slot of key d (0 if unused), the mod-based lookup of K_{i->d}. */
+typedef struct {
+  uint64_t slot;
+  int64_t pos;
+  uint32_t key, w;
+} slot_entry_t;
+
+static int cmp_slot_entry(const void *a, const void *b) {
+  const slot_entry_t *x = (const slot_entry_t *)a, *y = (const slot_entry_t *)b;
+  if (x->slot != y->slot) return x->slot < y->slot ? -1 : 1;
+  return x->pos < y->pos ? -1 : x->pos > y->pos;
+}
+
+static int small_table(const uint32_t *key, const uint32_t *w, const uint8_t *use, int64_t n,
+                       int64_t S, uint32_t d, pair_t *out, int64_t *vd) {
+  slot_entry_t *t = (slot_entry_t *)malloc(sizeof(slot_entry_t) * (size_t)(n > 0 ? n : 1));
+  int64_t m = 0;
+  for (int64_t e = 0; e < n; ++e)
+    if (use[e]) t[m++] = (slot_entry_t){(uint64_t)key[e] % (uint64_t)S, e, key[e], w[e]};
+  qsort(t, (size_t)m, sizeof(slot_entry_t), cmp_slot_entry);
+  const uint64_t sd = (uint64_t)d % (uint64_t)S;
+  int r = 0;
+  *vd = 0;
+  for (int64_t e = 0; e < m;) {
+    int64_t f = e;
+    uint64_t sum = 0;
+    while (f < m && t[f].slot == t[e].slot) sum += t[f++].w;
+    out[r++] = (pair_t){t[e].key, (uint32_t)sum};  /* t[e]: the slot's first entry */
+    if (t[e].slot == sd) *vd = (int64_t)sum;
+    e = f;
+  }
+  free(t);
+  return r;
+}
+
 /* exported for the sketch tests */
 int oracle_sketch_stream(const uint32_t *keys, const uint32_t *weights, int64_t n, int mode, int k,
                          int64_t chunk_len, uint32_t *out_keys, uint32_t *out_vals) {
@@ -407,8 +446,11 @@ static int32_t decide_vertex(const sweep_t *s, int32_t i, uint32_t *kbuf, uint32
     if (s->algo == OR_ALGO_REFINE && s->bound[j] != s->bound[i]) ubuf[e] = 0;
   }
   /* pass 1: candidate communities */
+  int64_t small_vd = 0;
   int nc = s->mode == OR_MODE_EXACT ? exact_table(kbuf, wbuf, ubuf, n, cbuf)
-                                    : stream_sketch(kbuf, wbuf, ubuf, n, s->mode, s->k, s->L, cbuf);
+           : s->mode == OR_MODE_SMALL
+               ? small_table(kbuf, wbuf, ubuf, n, s->k, (uint32_t)d, cbuf, &small_vd)
+               : stream_sketch(kbuf, wbuf, ubuf, n, s->mode, s->k, s->L, cbuf);
   if (nc == 0) return d;
   if (s->algo == OR_ALGO_LPA && s->one_scan) {
     /* The 1-scan variant of LPA (Section 4.3): no second pass; the label whose
@@ -425,16 +467,23 @@ static int32_t decide_vertex(const sweep_t *s, int32_t i, uint32_t *kbuf, uint32
     }
     return best;
   }
-  /* pass 2: exact linking weights K_{i->c} of the candidates and K_{i->d} */
   int64_t Kid = 0;
-  for (int x = 0; x < nc; ++x) cbuf[x].val = 0;
   int64_t *Kic = (int64_t *)malloc(sizeof(int64_t) * (size_t)nc);
-  for (int x = 0; x < nc; ++x) Kic[x] = 0;
-  for (int64_t e = 0; e < n; ++e) {
-    if (!ubuf[e]) continue;
-    for (int x = 0; x < nc; ++x)
-      if (cbuf[x].key == kbuf[e]) Kic[x] += wbuf[e];
-    if (kbuf[e] == (uint32_t)d) Kid += wbuf[e];
+  if (s->mode == OR_MODE_SMALL) {
+    /* the small table's values are the linking weights (no second pass), K_{i->d}
+     * by mod-based lookup */
+    for (int x = 0; x < nc; ++x) Kic[x] = cbuf[x].val;
+    Kid = small_vd;
+  } else {
+    /* pass 2: exact linking weights K_{i->c} of the candidates and K_{i->d} */
+    for (int x = 0; x < nc; ++x) cbuf[x].val = 0;
+    for (int x = 0; x < nc; ++x) Kic[x] = 0;
+    for (int64_t e = 0; e < n; ++e) {
+      if (!ubuf[e]) continue;
+      for (int x = 0; x < nc; ++x)
+        if (cbuf[x].key == kbuf[e]) Kic[x] += wbuf[e];
+      if (kbuf[e] == (uint32_t)d) Kid += wbuf[e];
+    }
   }
   int32_t best = -1;
   if (s->algo == OR_ALGO_LPA) {
@@ -512,7 +561,7 @@ int oracle_move_sweep(int32_t n, const int64_t *off, const int32_t *idx, const u
                       int mode, int k, int64_t chunk_len, const int32_t *C, const int32_t *bound,
                       const int64_t *K, const int64_t *Sigma, const int32_t *size, int64_t W,
                       int direction, int one_scan, int32_t *Cnew, int64_t *gain) {
-  if (k < 1 || k > KMAX || chunk_len < 1) return -1;
+  if (k < 1 || (k > KMAX && mode != OR_MODE_SMALL) || chunk_len < 1) return -1;
   graph_t g = {n, off[n], (int64_t *)off, (int32_t *)idx, (uint32_t *)w, 0};
   sweep_t s = {&g, algo, mode, k, chunk_len, C, bound, K, Sigma, size, W, one_scan};
   sweep(&s, Cnew, gain);
@@ -741,6 +790,10 @@ static void set_threads(const or_params *p) {
 }
 
 static int check_params(const or_params *p) {
+  if (p->mode == OR_MODE_SMALL) { /* k: slots of the small table; aggregation is exact */
+    if (p->k < 1) return -6;
+    return p->chunk_len < 1 ? -1 : 0;
+  }
   if (p->k < 1 || p->k > KMAX || p->k_aggregate < 1 || p->k_aggregate > KMAX) return -6;
   if (p->chunk_len < 1) return -1;
   return 0;
@@ -861,7 +914,8 @@ int oracle_louvain(int32_t n, const int64_t *off, const int32_t *idx, const uint
       int32_t *D = (int32_t *)malloc(sizeof(int32_t) * szl);
       for (int32_t i = 0; i < nl; ++i) D[i] = dense[C[i]];
       graph_t a;
-      aggregate(&g, D, m, p->mode, p->k_aggregate, p->chunk_len, 0, &a);
+      aggregate(&g, D, m, p->mode == OR_MODE_SMALL ? OR_MODE_EXACT : p->mode, p->k_aggregate,
+                p->chunk_len, 0, &a);
       int64_t *K2 = (int64_t *)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
       for (int32_t i = 0; i < nl; ++i) K2[D[i]] += K[i];
       free(K);
@@ -927,7 +981,8 @@ int oracle_leiden(int32_t n, const int64_t *off, const int32_t *idx, const uint3
     for (int32_t i = 0; i < nl; ++i) D[i] = denseR[R[i]];
     for (int32_t v = 0; v < n; ++v) top[v] = D[top[v]];
     graph_t a;
-    aggregate(&g, D, m, p->mode, p->k_aggregate, p->chunk_len, 1, &a);
+    aggregate(&g, D, m, p->mode == OR_MODE_SMALL ? OR_MODE_EXACT : p->mode, p->k_aggregate,
+              p->chunk_len, 1, &a);
     int64_t *K2 = (int64_t *)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
     int32_t *C2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
     for (int32_t i = 0; i < nl; ++i) {

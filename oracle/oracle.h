@@ -10,6 +10,7 @@
 #define OR_MODE_ALG1 1   /* Algorithm 1, conditional subtraction (the paper's MG)   */
 #define OR_MODE_UNCOND 2 /* unconditional subtraction (Section 4.1, variant 1)      */
 #define OR_MODE_STD 3    /* textbook weighted MG (min-decrement)                   */
+#define OR_MODE_SMALL 5  /* small mod-based table (Appendix A.2): k = its slot count  */
 
 #define OR_ALGO_LPA 0
 #define OR_ALGO_MOVE 1

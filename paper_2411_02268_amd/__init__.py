@@ -20,7 +20,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmgcd.so")
 
-MODE_EXACT, MODE_ALG1, MODE_UNCOND, MODE_STD, MODE_BM = 0, 1, 2, 3, 4
+MODE_EXACT, MODE_ALG1, MODE_UNCOND, MODE_STD, MODE_BM, MODE_SMALL = 0, 1, 2, 3, 4, 5
 ALGO_LPA, ALGO_LOUVAIN, ALGO_LEIDEN = 0, 1, 2
 ERRORS = {-1: "E_ARG", -2: "E_GRAPH", -3: "E_OVERFLOW", -4: "E_WORKSPACE", -5: "E_HIP",
           -6: "E_UNSUPPORTED"}

@@ -558,7 +558,7 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
       MGCD_HIP(hipMemcpyAsync(db.data(), nb_d, db.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
       MGCD_HIP(hipStreamSynchronize(st));
       auto &sl = slot[next_slot];
-      const int64_t nnz2 = aggregate(cur, D, m, p->mode, p->k_aggregate, p->chunk_len, 0, sl.off, sl.idx,
+      const int64_t nnz2 = aggregate(cur, D, m, agg_mode(p), p->k_aggregate, p->chunk_len, 0, sl.off, sl.idx,
                                      sl.w, a, st);
       launch_group_sums(D, K, Kbuf[1 - kcur], nl, m, st);
       // next level: graph g owns [db[g], db[g+1]) (empty when finished)
@@ -616,8 +616,8 @@ size_t batched_workspace_bytes(int32_t algo, int32_t count, int64_t N, int64_t E
   b += (size_t)(N + 1) * 8 + (size_t)E * 8;                 // union
   b += (size_t)N * 4 * 14 + (size_t)(N + 1) * 8;             // per-vertex state
   if (algo != MGCD_ALGO_LPA) b += 2 * ((size_t)(N + 1) * 8 + (size_t)E * 8);  // level slots
-  size_t sched = schedule_ws_bytes((int32_t)N, E, p->mode, p->k, L);
-  size_t agg = algo == MGCD_ALGO_LPA ? 0 : aggregate_ws_bytes((int32_t)N, E, p->mode, p->k_aggregate, L, false);
+  size_t sched = schedule_ws_bytes((int32_t)N, E, agg_mode(p), p->k, L);
+  size_t agg = algo == MGCD_ALGO_LPA ? 0 : aggregate_ws_bytes((int32_t)N, E, agg_mode(p), p->k_aggregate, L, false);
   size_t misc = (size_t)N * (4 + 4 + 8 + 8) + scan_ws_bytes(N + 1) + 64 * 1024;
   size_t phase = sched > agg ? sched : agg;
   phase = phase > degrees_ws_bytes(E) ? phase : degrees_ws_bytes(E);

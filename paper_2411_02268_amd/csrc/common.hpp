@@ -15,7 +15,7 @@ constexpr int WAVE = 64;                 // CDNA wavefront width
 constexpr int BLOCK = 256;               // four waves per workgroup
 
 enum Algo : int { ALGO_LPA = 0, ALGO_MOVE = 1, ALGO_REFINE = 2 };
-enum Mode : int { MODE_EXACT = 0, MODE_ALG1 = 1, MODE_UNCOND = 2, MODE_STD = 3 };
+enum Mode : int { MODE_EXACT = 0, MODE_ALG1 = 1, MODE_UNCOND = 2, MODE_STD = 3, MODE_SMALL = 5 };
 
 // A CSR graph in device memory (Section 3): rows are the out-entries of a vertex.
 struct Graph {

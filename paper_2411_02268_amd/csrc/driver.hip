@@ -56,10 +56,14 @@ struct ClassTimer {
 
 static void check_params(const mgcd_params *p) {
   if (!p) throw Error(MGCD_E_ARG, "params is null");
-  if (p->mode < 0 || p->mode > 3) throw Error(MGCD_E_UNSUPPORTED, "unknown sketch mode");
+  if (p->mode < 0 || (p->mode > 3 && p->mode != MGCD_MODE_SMALL))
+    throw Error(MGCD_E_UNSUPPORTED, "unknown sketch mode");
   auto okk = [](int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16 || k == 32 || k == 64; };
-  if (p->mode != MGCD_MODE_EXACT && (!okk(p->k) || !okk(p->k_aggregate)))
+  if (p->mode == MGCD_MODE_SMALL) {
+    if (p->k < 1 || p->k > (1 << 30)) throw Error(MGCD_E_UNSUPPORTED, "small-table slots k must be in [1, 2^30]");
+  } else if (p->mode != MGCD_MODE_EXACT && (!okk(p->k) || !okk(p->k_aggregate))) {
     throw Error(MGCD_E_UNSUPPORTED, "k and k_aggregate must be 1, 2, 4, 8, 16, 32 or 64");
+  }
   if (p->chunk_len < 1) throw Error(MGCD_E_ARG, "chunk_len must be >= 1");
   if (p->max_iterations < 1 || p->max_passes < 1) throw Error(MGCD_E_ARG, "iteration limits must be >= 1");
   if (!(p->tolerance >= 0.0) || !(p->tolerance_drop > 0.0) || !(p->aggregation_tolerance >= 0.0))
@@ -290,7 +294,7 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
       }
     }
     Slot &sl = slot[next_slot];
-    int64_t nnz2 = aggregate(cur, D, m, p->mode, p->k_aggregate, p->chunk_len, leiden ? 1 : 0, sl.off,
+    int64_t nnz2 = aggregate(cur, D, m, agg_mode(p), p->k_aggregate, p->chunk_len, leiden ? 1 : 0, sl.off,
                              sl.idx, sl.w, a, st);
     launch_group_sums(D, K, Kbuf[1 - kcur], nl, m, st);
     if (leiden) {
@@ -314,7 +318,7 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
 // ---- workspace ---------------------------------------------------------------------------
 
 static size_t workspace_bytes(int32_t algo, int32_t n, int64_t nnz, const mgcd_params *p) {
-  const int mode = p->mode;
+  const int mode = agg_mode(p);
   const int64_t L = p->chunk_len > 0 ? p->chunk_len : 1;
   size_t fixed = (size_t)n * 4 * 16 + 64 * 1024;
   if (algo != MGCD_ALGO_LPA) fixed += 2 * ((size_t)(n + 1) * 8 + (size_t)nnz * 8) + 4096;
@@ -546,12 +550,12 @@ int mgcd_aggregate(const mgcd_csr *gin, const mgcd_params *p, const int32_t *D, 
     Graph g = view(gin);
     if (m < 0 || m > g.n) throw Error(MGCD_E_ARG, "m out of range");
     if (!out_off || (g.nnz > 0 && (!out_idx || !out_w)) || !out_nnz) throw Error(MGCD_E_ARG, "null output");
-    size_t need = aggregate_ws_bytes(g.n, g.nnz, p->mode, p->k_aggregate, p->chunk_len, symmetric != 0) + 64 * 1024;
+    size_t need = aggregate_ws_bytes(g.n, g.nnz, agg_mode(p), p->k_aggregate, p->chunk_len, symmetric != 0) + 64 * 1024;
     if (ws_bytes < need) throw Error(MGCD_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
     Arena a = make_arena(ws, ws_bytes);
     hipStream_t st = (hipStream_t)stream;
     require_labels(D, g.n, m, a, st, "D");
-    *out_nnz = aggregate(g, D, m, p->mode, p->k_aggregate, p->chunk_len, symmetric ? 1 : 0, out_off,
+    *out_nnz = aggregate(g, D, m, agg_mode(p), p->k_aggregate, p->chunk_len, symmetric ? 1 : 0, out_off,
                          out_idx, out_w, a, st);
     MGCD_HIP(hipStreamSynchronize(st));
   });

@@ -730,9 +730,15 @@ __device__ inline void exact_row_regs(const SweepArgs &a, int32_t i, int32_t bi,
       c = (uint32_t)a.C[j];
     ks[t] = c | ((v && j != i) ? 0u : EMPTY);  // self-loops are skipped
   }
+  // table keys: the keys themselves, or their slots in the small table (a slot's
+  // first key stands for it, K_{i->d} is the sum in d's slot)
+  uint32_t ss[ES];
+#pragma unroll
+  for (int t = 0; t < ES; ++t) ss[t] = ks[t] != EMPTY ? slot_of(a, ks[t]) : EMPTY;
+  const uint32_t sd = slot_of(a, (uint32_t)d);
   uint32_t kd = 0;
 #pragma unroll
-  for (int t = 0; t < ES; ++t) kd += ks[t] == (uint32_t)d ? ws[t] : 0u;
+  for (int t = 0; t < ES; ++t) kd += ss[t] == sd ? ws[t] : 0u;
   int32_t best = -1;
   int64_t bestG = 0;
   const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
@@ -746,10 +752,10 @@ __device__ inline void exact_row_regs(const SweepArgs &a, int32_t i, int32_t bi,
     const uint32_t c = ks[t];
     bool first = c != EMPTY;
 #pragma unroll
-    for (int u = 0; u < t; ++u) first &= ks[u] != c;
+    for (int u = 0; u < t; ++u) first &= ss[u] != ss[t];
     uint32_t kc = 0;
 #pragma unroll
-    for (int u = t; u < ES; ++u) kc += ks[u] == c ? ws[u] : 0u;
+    for (int u = t; u < ES; ++u) kc += ss[u] == ss[t] ? ws[u] : 0u;
     consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)c, kc, sc[t], first, best, bestG);
   }
   finish<ALGO>(a, i, d, best, bestG, ct);
@@ -787,22 +793,28 @@ __global__ void __launch_bounds__(BLOCK)
   } else if (maxdeg <= 32) {
     if (live) exact_row_regs<ALGO, 32>(a, i, bi, lo, hi, d, ct);
   } else if (live) {
+    // table key of entry f (EMPTY when Algorithm 1's skips drop it)
+    auto tkey = [&](int64_t f) {
+      const uint32_t c = stream_key<ALGO>(a, i, a.g.idx[f], bi);
+      return c != EMPTY ? slot_of(a, c) : EMPTY;
+    };
+    const uint32_t sd = slot_of(a, (uint32_t)d);
     uint32_t kd = 0;
-    for (int64_t e = lo; e < hi; ++e)
-      kd += stream_key<ALGO>(a, i, a.g.idx[e], bi) == (uint32_t)d ? a.g.w[e] : 0u;
+    for (int64_t e = lo; e < hi; ++e) kd += tkey(e) == sd ? a.g.w[e] : 0u;
     int32_t best = -1;
     int64_t bestG = 0;
     const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
     const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
     const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
     for (int64_t e = lo; e < hi; ++e) {
-      uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
+      const uint32_t c = stream_key<ALGO>(a, i, a.g.idx[e], bi);
       if (c == EMPTY) continue;
+      const uint32_t se = slot_of(a, c);
       bool first = true;
-      for (int64_t f = lo; f < e && first; ++f) first = stream_key<ALGO>(a, i, a.g.idx[f], bi) != c;
+      for (int64_t f = lo; f < e && first; ++f) first = tkey(f) != se;
       if (!first) continue;
       uint32_t kc = 0;
-      for (int64_t f = e; f < hi; ++f) kc += stream_key<ALGO>(a, i, a.g.idx[f], bi) == c ? a.g.w[f] : 0u;
+      for (int64_t f = e; f < hi; ++f) kc += tkey(f) == se ? a.g.w[f] : 0u;
       consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)c, kc, best, bestG);
     }
     finish<ALGO>(a, i, d, best, bestG, ct);
@@ -829,11 +841,12 @@ __device__ inline Pair load_slot(Pair *p) {
 
 // Workgroup per vertex with an open-addressing table (linear probing) in LDS
 // (CAP slots) or, when GLOBAL, in this vertex's region of global memory.
-template <int ALGO, int CAP, bool GLOBAL>
+template <int ALGO, int CAP, bool GLOBAL, bool SMALL = false>
 __global__ void __launch_bounds__(BLOCK)
     k_exact_table(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
-                  Pair *htab) {
+                  Pair *htab, uint32_t *hpos) {
   __shared__ Pair ltab[GLOBAL ? 1 : CAP];
+  __shared__ uint32_t lpos[GLOBAL || !SMALL ? 1 : CAP];  // small table: first row position per slot
   __shared__ uint32_t kd_s;
   __shared__ int32_t bc[4];
   __shared__ int64_t bg[4];
@@ -845,15 +858,22 @@ __global__ void __launch_bounds__(BLOCK)
   }
   const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
   Pair *tab;
+  uint32_t *pos;
   uint32_t cap;
   if (GLOBAL) {
     tab = htab + hbase[blockIdx.x];
+    pos = hpos + hbase[blockIdx.x];
     cap = (uint32_t)(hbase[blockIdx.x + 1] - hbase[blockIdx.x]);
   } else {
     tab = ltab;
+    pos = lpos;
     cap = CAP;
   }
-  for (uint32_t x = t; x < cap; x += BLOCK) tab[x] = Pair{EMPTY, 0u};
+  constexpr bool small = SMALL;  // keys are small-table slots (a.small_slots of them)
+  for (uint32_t x = t; x < cap; x += BLOCK) {
+    tab[x] = Pair{EMPTY, 0u};
+    if (small) pos[x] = 0xFFFFFFFFu;
+  }
   if (t == 0) kd_s = 0;
   if (GLOBAL) __threadfence();
   __syncthreads();
@@ -880,13 +900,14 @@ __global__ void __launch_bounds__(BLOCK)
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t c = cs[u];
-      if (c == EMPTY) continue;
+      if (cs[u] == EMPTY) continue;
+      const uint32_t c = slot_of(a, cs[u]);  // the table key
       uint32_t h = hash_slot(c, mask);
       while (true) {
         uint32_t prev = atomicCAS(&tab[h].key, EMPTY, c);
         if (prev == EMPTY || prev == c) {
           atomicAdd(&tab[h].val, ws[u]);
+          if (small) atomicMin(&pos[h], (uint32_t)(e0 + (int64_t)u * BLOCK - lo));
           break;
         }
         h = (h + 1) & mask;
@@ -896,9 +917,10 @@ __global__ void __launch_bounds__(BLOCK)
   if (GLOBAL) __threadfence();
   __syncthreads();
   const int32_t d = community_of_self<ALGO>(a, i);
+  const uint32_t sd = slot_of(a, (uint32_t)d);
   for (uint32_t x = t; x < cap; x += BLOCK) {
     Pair p = load_slot<GLOBAL>(&tab[x]);
-    if (p.key == (uint32_t)d) kd_s = p.val;
+    if (p.key == sd) kd_s = p.val;
   }
   __syncthreads();
   const uint32_t kd = kd_s;
@@ -910,6 +932,12 @@ __global__ void __launch_bounds__(BLOCK)
   for (uint32_t x = t; x < cap; x += BLOCK) {
     Pair p = load_slot<GLOBAL>(&tab[x]);
     const bool present = p.key != EMPTY;
+    if (small && present) {
+      // the slot stands for its first key: the key of its earliest row entry
+      const uint32_t f = GLOBAL ? __hip_atomic_load(&pos[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                : pos[x];
+      p.key = stream_key<ALGO>(a, i, a.g.idx[lo + f], bi);
+    }
     const uint32_t sc = ALGO == ALGO_LPA ? 0u : a.Sig[present ? (int32_t)p.key : d];
     consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)p.key, p.val, sc, present, best, bestG);
   }
@@ -1055,7 +1083,7 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
   b += (size_t)n * 4 + 1024;                   // ordered list
   if (mode == MODE_EXACT) {
     b += (size_t)(n + 1) * 8 + scan_ws_bytes(n) + 1024;  // hash bases
-    b += (size_t)(4 * nnz + 64) * sizeof(Pair) + 1024;  // tables: cap <= 4*deg
+    b += (size_t)(4 * nnz + 64) * (sizeof(Pair) + 4) + 2048;  // tables (cap <= 4*deg), positions
   } else {
     // a long row has more than one chunk, so more than L entries: at most nnz / L
     // long rows, at most 2 nnz / L + 1 of their chunks, and groups of 64 chunks at
@@ -1119,6 +1147,7 @@ void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a
       MGCD_HIP(hipMemcpyAsync(&tot, s.hbase + c3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
       MGCD_HIP(hipStreamSynchronize(st));
       s.htab = a.take<Pair>(tot);
+      s.hpos = a.take<uint32_t>(tot);
     }
     return;
   }
@@ -1218,7 +1247,7 @@ static void sweep_mg(const SweepArgs &a, const Schedule &s, int64_t L, hipStream
   mark(ev, 3, st);
 }
 
-template <int ALGO>
+template <int ALGO, bool SMALL = false>
 static void sweep_exact(const SweepArgs &a, const Schedule &s, hipStream_t st, hipEvent_t *ev) {
   mark(ev, 0, st);
   if (s.ntier[0] > 0) {
@@ -1227,16 +1256,19 @@ static void sweep_exact(const SweepArgs &a, const Schedule &s, hipStream_t st, h
   }
   mark(ev, 1, st);
   if (s.ntier[1] > 0) {
-    k_exact_table<ALGO, 1024, false><<<(unsigned)s.ntier[1], BLOCK, 0, st>>>(a, s.tier[1], nullptr, nullptr);
+    k_exact_table<ALGO, 1024, false, SMALL><<<(unsigned)s.ntier[1], BLOCK, 0, st>>>(a, s.tier[1], nullptr, nullptr,
+                                                                              nullptr);
     MGCD_LAUNCHED();
   }
   if (s.ntier[2] > 0) {
-    k_exact_table<ALGO, 8192, false><<<(unsigned)s.ntier[2], BLOCK, 0, st>>>(a, s.tier[2], nullptr, nullptr);
+    k_exact_table<ALGO, 8192, false, SMALL><<<(unsigned)s.ntier[2], BLOCK, 0, st>>>(a, s.tier[2], nullptr, nullptr,
+                                                                              nullptr);
     MGCD_LAUNCHED();
   }
   mark(ev, 2, st);
   if (s.ntier[3] > 0) {
-    k_exact_table<ALGO, 1, true><<<(unsigned)s.ntier[3], BLOCK, 0, st>>>(a, s.tier[3], s.hbase, s.htab);
+    k_exact_table<ALGO, 1, true, SMALL><<<(unsigned)s.ntier[3], BLOCK, 0, st>>>(a, s.tier[3], s.hbase, s.htab,
+                                                                          s.hpos);
     MGCD_LAUNCHED();
   }
   mark(ev, 3, st);
@@ -1283,6 +1315,12 @@ static void sweep_algo(const SweepArgs &a, const Schedule &s, int mode, int k, i
                        hipStream_t st, hipEvent_t *ev) {
   switch (mode) {
     case MODE_EXACT: sweep_exact<ALGO>(a, s, st, ev); break;
+    case MODE_SMALL: {  // the exact kernels keyed by small-table slots (k of them)
+      SweepArgs b = a;
+      b.small_slots = k;
+      sweep_exact<ALGO, true>(b, s, st, ev);
+      break;
+    }
     case MODE_ALG1: sweep_k<ALGO, MODE_ALG1>(a, s, k, L, st, ev); break;
     case MODE_UNCOND: sweep_k<ALGO, MODE_UNCOND>(a, s, k, L, st, ev); break;
     case MODE_STD: sweep_k<ALGO, MODE_STD>(a, s, k, L, st, ev); break;

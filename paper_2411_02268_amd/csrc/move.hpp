@@ -30,7 +30,16 @@ struct SweepArgs {
   // LPA, the 1-scan variant (Section 4.3): every row decides from its sketch's values
   // (treated as exact), so no row takes the second pass.
   int32_t one_scan = 0;
+  // The small mod-based table of Appendix A.2 (exact kernels only): 0 = the exact
+  // table; S > 0 = key c counts in slot c mod S, whose first key (in stream order)
+  // stands for every key that lands there.
+  int32_t small_slots = 0;
 };
+
+// The table key of community (or vertex) c: itself, or its slot in the small table.
+__device__ inline uint32_t slot_of(const SweepArgs &a, uint32_t c) {
+  return a.small_slots > 0 ? c % (uint32_t)a.small_slots : c;
+}
 
 // Whether a row whose sketch lost weight still needs the second pass.
 __device__ inline bool second_pass(const SweepArgs &a, int algo) { return !(algo == ALGO_LPA && a.one_scan); }
@@ -104,6 +113,7 @@ struct Schedule {
   int64_t ntier[4] = {0, 0, 0, 0};
   int64_t *hbase = nullptr;   // [ntier[3]+1] global hash region of each tier-3 vertex
   Pair *htab = nullptr;
+  uint32_t *hpos = nullptr;   // small table: first row position of each global slot
 };
 
 // What a level's schedule depends on.  mode, k and L change results; the rest only
@@ -127,9 +137,15 @@ constexpr int64_t EXACT_T1_MAX = 512, EXACT_T2_MAX = 4096;
 void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a, hipStream_t st);
 
 // The schedule parameters of a call (0 in a schedule field selects its default).
+// The small table (MGCD_MODE_SMALL) runs on the exact kernels' schedule and
+// aggregates exactly: the mode that schedules and aggregation see.
+inline int agg_mode(const mgcd_params *p) {
+  return p->mode == MGCD_MODE_SMALL ? MGCD_MODE_EXACT : p->mode;
+}
+
 inline SchedParams sched_params(const mgcd_params *p) {
   SchedParams sp;
-  sp.mode = p->mode;
+  sp.mode = p->mode == MGCD_MODE_SMALL ? MGCD_MODE_EXACT : p->mode;  // small: exact tiers
   sp.k = p->k;
   sp.L = p->chunk_len;
   if (p->row_lanes > 0) {
@@ -142,7 +158,7 @@ inline SchedParams sched_params(const mgcd_params *p) {
   if (p->exact_lds_big > 0) sp.exact_t2 = p->exact_lds_big;
   if (sp.exact_t1 < sp.exact_t0) sp.exact_t1 = sp.exact_t0;
   if (sp.exact_t2 < sp.exact_t1) sp.exact_t2 = sp.exact_t1;
-  if (p->mode != MGCD_MODE_EXACT && p->k > 16) {
+  if (sp.mode != MGCD_MODE_EXACT && p->k > 16) {
     // a stream of at most 32 items cannot lose weight in a sketch of >= 32 slots under
     // Algorithm 1 or the textbook rule (a free slot is always left); the unconditional
     // rule subtracts on every miss, so it takes the sketch for every row

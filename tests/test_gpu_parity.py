@@ -401,3 +401,55 @@ def test_boyer_moore_mode(mg):
             elab, est = getattr(oracle, algo)(g, mode=oracle.MODE_BM, chunk_len=32)
             assert np.array_equal(_np(lab), _np(same)) and np.array_equal(_np(lab), elab)
             assert st["iterations"] == est.iterations and st["passes"] == est.passes
+
+
+# ---------------------------------------------------------------------------------
+# the small mod-based table (Appendix A.2)
+# ---------------------------------------------------------------------------------
+
+# exact_small / exact_lds / exact_lds_big of (2, 8, 24) put rows on every table tier
+# (registers, 1,024- and 8,192-slot LDS tables, global tables)
+TIERS = {"default": {}, "all_tiers": dict(exact_small=2, exact_lds=8, exact_lds_big=24)}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12"])
+@pytest.mark.parametrize("slots", [1, 3, 37, 1000, 1 << 20])
+@pytest.mark.parametrize("tiers", sorted(TIERS))
+def test_small_table_sweep_parity(mg, gname, slots, tiers):
+    g = graph(gname)
+    dg = mg.to_device(g)
+    rng = np.random.default_rng(zlib.crc32(f"small-{gname}-{slots}".encode()))
+    C = rng.integers(0, max(2, g.n // 5), size=g.n).astype(np.int32)
+    for algo, oalgo in ((mg.ALGO_LPA, oracle.ALGO_LPA), (mg.ALGO_LOUVAIN, oracle.ALGO_MOVE)):
+        Cn, gain, ctr = mg.move_sweep(dg, algo, _t(C), -1, mode=mg.MODE_SMALL, k=slots,
+                                      **TIERS[tiers])
+        eC, eg = oracle.move_sweep(g, oalgo, C, mode=oracle.MODE_SMALL, k=slots, direction=-1)
+        assert np.array_equal(_np(Cn), eC), algo
+        if algo == mg.ALGO_LOUVAIN:
+            assert np.array_equal(_np(gain), eg)
+    bound = rng.integers(0, 4, size=g.n).astype(np.int32)
+    R = mg.refine(dg, _t(bound), mode=mg.MODE_SMALL, k=slots, **TIERS[tiers])
+    eR = oracle.refine(g, bound, mode=oracle.MODE_SMALL, k=slots)
+    assert np.array_equal(_np(R), eR)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("slots", [2, 50, 1 << 16])
+def test_small_table_run_parity(mg, slots):
+    for gname in ("planted", "rmat11"):
+        g = graph(gname)
+        dg = mg.to_device(g)
+        for algo in ("lpa", "louvain", "leiden"):
+            lab, st = getattr(mg, algo)(dg, mode=mg.MODE_SMALL, k=slots)
+            elab, est = getattr(oracle, algo)(g, mode=oracle.MODE_SMALL, k=slots)
+            assert np.array_equal(_np(lab), elab), (gname, algo)
+            assert st["iterations"] == est.iterations and st["passes"] == est.passes
+    gs = _batch_graphs()
+    dgs = [mg.to_device(g) for g in gs]
+    for code, algo in ((mg.ALGO_LPA, "lpa"), (mg.ALGO_LOUVAIN, "louvain")):
+        labs, _, _ = mg.run_batched(code, dgs, mode=mg.MODE_SMALL, k=slots)
+        for g, lab in zip(gs, labs):
+            if g.n:
+                elab, _ = getattr(oracle, algo)(g, mode=oracle.MODE_SMALL, k=slots)
+                assert np.array_equal(_np(lab), elab)

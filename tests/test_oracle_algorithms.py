@@ -174,6 +174,48 @@ def test_lpa_one_scan_equals_two_scan_when_sketch_is_exact():
         oracle.louvain(g, one_scan=1)
 
 
+def test_small_table_hand_trace():
+    # Appendix A.2, 3 slots: keys 4, 7, 1 share slot 1 (first key 4), key 5 has slot 2.
+    # Vertex 0 sees 4 (w 2), 7 (w 2), 5 (w 3), 1 (w 2): the table holds 4 -> 6 and
+    # 5 -> 3, so LPA takes 4; the exact table has 5 as the heaviest single label.
+    g, C = _star([2, 2, 3, 2], [4, 7, 5, 1])
+    small, _ = oracle.move_sweep(g, oracle.ALGO_LPA, C, mode=oracle.MODE_SMALL, k=3)
+    exact, _ = oracle.move_sweep(g, oracle.ALGO_LPA, C, mode=oracle.MODE_EXACT)
+    assert small[0] == 4 and exact[0] == 5
+    # Louvain reads K_{0->d} from d's slot: with C[0] = 10 (slot 1) the current
+    # community already "holds" 6, so no move has a positive gain
+    C2 = C.copy()
+    C2[0] = 10
+    Cn, gain = oracle.move_sweep(g, oracle.ALGO_MOVE, C2, mode=oracle.MODE_SMALL, k=3)
+    W = int(np.asarray(g.weights).sum())
+    K0 = 9
+    Sig = np.bincount(C2, weights=oracle.weighted_degree(g), minlength=g.n)
+    # candidate 4 (slot 1, value 6): G = W (6 - 6) - K0 (K0 + Sig[4] - Sig[10])
+    g4 = W * 0 - K0 * (K0 + int(Sig[4]) - int(Sig[10]))
+    g5 = W * (3 - 6) - K0 * (K0 + int(Sig[5]) - int(Sig[10]))
+    assert max(g4, g5) <= 0 and Cn[0] == 10 and gain[0] == 0
+
+
+def test_small_table_one_slot_takes_first_neighbour():
+    # one slot: every key collides; the slot keeps the row's first (non-self) key
+    rng = np.random.default_rng(5)
+    g = synth.random_small(70, 0.1, 4, seed=5, loops=True)
+    C = rng.integers(0, 30, size=g.n).astype(np.int32)
+    Cn, _ = oracle.move_sweep(g, oracle.ALGO_LPA, C, mode=oracle.MODE_SMALL, k=1)
+    for i in range(g.n):
+        nb = [int(j) for j in g.indices[g.offsets[i]:g.offsets[i + 1]] if j != i]
+        assert Cn[i] == (C[nb[0]] if nb else C[i])
+
+
+def test_small_table_without_collisions_is_exact():
+    # more slots than labels: no two keys collide and the table is the exact one
+    g = synth.random_small(90, 0.15, 5, seed=8)
+    for fn in (oracle.lpa, oracle.louvain, oracle.leiden):
+        a, sa = fn(g, mode=oracle.MODE_SMALL, k=1 << 20)
+        b, sb = fn(g, mode=oracle.MODE_EXACT)
+        assert np.array_equal(a, b) and sa == sb
+
+
 def test_lpa_planted_finds_structure():
     g, truth = synth.planted_exact()
     for mode in (oracle.MODE_EXACT, oracle.MODE_ALG1):

@@ -216,7 +216,8 @@ def k_sweep_leg(mg, torch, dg, repeats: int = 3, chunk_len: int = 128):
     """Synthetic analogue of the paper's k sweeps (Figs. 4-6): for LPA, Louvain and
     Leiden, each sketch variant (Algorithm 1, unconditional subtraction, LPA 1-scan)
     at k = 1..64 and the weighted Boyer-Moore mode, the run time and modularity
-    relative to the exact table on the same graph (median of `repeats` runs)."""
+    relative to the exact table on the same graph (median of `repeats` runs); and the
+    small mod-based table at slot counts of 1e-5 .. 1e-1 of |V|."""
     def timed(fn, **kw):
         lab, _ = fn(dg, chunk_len=chunk_len, **kw)
         torch.cuda.synchronize()
@@ -243,6 +244,13 @@ def k_sweep_leg(mg, torch, dg, repeats: int = 3, chunk_len: int = 128):
                 res[vname][str(k)] = {"rel_time": t / t_x, "rel_Q": q / q_x if q_x else None}
         t, q = timed(fn, mode=mg.MODE_BM)
         res["bm"] = {"rel_time": t / t_x, "rel_Q": q / q_x if q_x else None}
+        # the small mod-based table (Appendix A.2) by slots fraction of |V|
+        res["small"] = {}
+        for frac in (1e-5, 1e-4, 3e-4, 1e-3, 1e-2, 1e-1):
+            slots = max(1, int(round(frac * dg.n)))
+            t, q = timed(fn, mode=mg.MODE_SMALL, k=slots)
+            res["small"][f"{frac:g}"] = {"slots": slots, "rel_time": t / t_x,
+                                         "rel_Q": q / q_x if q_x else None}
         out[name] = res
         best = min((v for v in res["alg1"].values() if v["rel_Q"] and v["rel_Q"] >= 0.99),
                    key=lambda v: v["rel_time"], default=None)

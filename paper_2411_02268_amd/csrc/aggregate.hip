@@ -559,7 +559,7 @@ __device__ inline void write_row(uint32_t (&k)[K], uint32_t (&v)[K], int32_t c, 
                                  uint32_t *rcount);
 
 template <int K, int MODE>
-__global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
+__global__ void __launch_bounds__(BLOCK) MGCD_ROWS_OCCUPANCY(K)
     k_agg_rows(AggStreams s, AggBuckets bk, int64_t L, Pair *rows, uint32_t *rcount) {
   __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
   const int lane = lane_id();
@@ -622,7 +622,7 @@ struct AggLong {
 // chunk within the group): the staged fold of each chunk, then the first six
 // levels of the fixed merge tree with shuffles; lane 0 writes the group's root.
 template <int K, int MODE>
-__global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
+__global__ void __launch_bounds__(BLOCK) MGCD_ROWS_OCCUPANCY(K)
     k_agg_chunks(AggStreams s, AggLong lg, int64_t L) {
   __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
   const int64_t w = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform

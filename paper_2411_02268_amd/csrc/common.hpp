@@ -56,6 +56,10 @@ inline thread_local bool in_capture = false;
 // Kernels that hold a K-slot sketch per lane in registers: at K = 16 two waves per
 // SIMD leave room for the sketch and its merge partner without spilling.
 #define MGCD_SKETCH_OCCUPANCY(K) __attribute__((amdgpu_waves_per_eu(1, (K) >= 16 ? 2 : 8)))
+// The row kernels of the sweep and of aggregation (LDS-staged windows) fit 128 VGPRs
+// at K = 16 without spilling their sketch: ask for the four waves per SIMD that their
+// LDS windows allow, for latency hiding.
+#define MGCD_ROWS_OCCUPANCY(K) __attribute__((amdgpu_waves_per_eu((K) >= 16 ? 4 : 1, 8)))
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

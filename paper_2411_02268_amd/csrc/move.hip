@@ -586,7 +586,7 @@ __device__ inline void row_work(const SweepArgs &a, const Buckets &bk, int64_t L
 // of long rows (their merge, pass 2 and decision follow in k_long_*), the rest
 // take the row buckets.
 template <int K, int ALGO, int MODE>
-__global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
+__global__ void __launch_bounds__(BLOCK) MGCD_ROWS_OCCUPANCY(K)
     k_move_rows(SweepArgs a, const Buckets *__restrict__ bkp, int64_t L, uint32_t *keybuf) {
   const Buckets &bk = *bkp;
   __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];

@@ -440,6 +440,10 @@ def main():
         cs = time.perf_counter() - a
         cpu = {"value": e_cpu / cs, "unit": "edges/s", "cores": threads, "kind": "oracle",
                "sample": f"{sample}, {reps} repetitions ({cs:.1f}s), OpenMP threads={threads}"}
+        if g.nnz <= 100_000_000:  # one run on one thread as well (same sample kind)
+            a1 = time.perf_counter()
+            _, est = ofn(g, mode=oracle.MODE_ALG1, k=k, chunk_len=L, threads=1)
+            cpu["value_1_thread"] = est.edges_scanned / (time.perf_counter() - a1)
         print(f"[bench] oracle: {reps} reps in {cs:.1f}s -> {e_cpu/cs/1e9:.3f} G edges/s",
               file=sys.stderr, flush=True)
 

@@ -455,10 +455,12 @@ struct AggStreams {
   const uint32_t *sw;     //             and weight of every position
 };
 
-// Stream position of every vertex's row (-1: the vertex is in no community).
-__global__ void k_row_pos(const uint32_t *mem, const int64_t *P, int32_t nmem, int64_t *rowpos) {
+// Stream position of every vertex's row (-1: the vertex is in no community); the
+// member count *nmem is read on the device (no host round trip).
+__global__ void k_row_pos(const uint32_t *mem, const int64_t *P, const int32_t *nmem, int32_t n,
+                          int64_t *rowpos) {
   int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (t < nmem) rowpos[mem[t]] = P[t];
+  if (t < n && t < *nmem) rowpos[mem[t]] = P[t];
 }
 
 // Rows of a tile of consecutive CSR entries [e0, e1) (non-empty): the rows meeting
@@ -903,13 +905,6 @@ static void agg_mg_k(int k, const AggStreams &s, const AggBuckets &bk, int64_t w
   }
 }
 
-static int32_t read_i32(const int32_t *p, hipStream_t st) {
-  int32_t h = 0;
-  MGCD_HIP(hipMemcpyAsync(&h, p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  MGCD_HIP(hipStreamSynchronize(st));
-  return h;
-}
-
 __global__ void k_fill_i64(int64_t *p, int64_t v, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1056,14 +1051,13 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   MGCD_LAUNCHED();
   int64_t *rowpos = a.take<int64_t>(n);
   launch_fill_i64(rowpos, -1, n, st);
-  const int32_t nmem = read_i32(mstart + m, st);
-  if (nmem > 0) {
-    k_row_pos<<<grid_for(nmem), BLOCK, 0, st>>>(mem, P, nmem, rowpos);
+  if (n > 0) {
+    k_row_pos<<<grid_for(n), BLOCK, 0, st>>>(mem, P, mstart + m, n, rowpos);
     MGCD_LAUNCHED();
   }
-  const int64_t npos = read_i64(P + n, st);  // positions of all streams
-  uint32_t *skey = a.take<uint32_t>(npos);
-  uint32_t *sw = a.take<uint32_t>(npos);
+  // the streams hold the members' rows: at most nnz positions
+  uint32_t *skey = a.take<uint32_t>(g.nnz);
+  uint32_t *sw = a.take<uint32_t>(g.nnz);
   if (g.nnz > 0) {
     k_agg_streamify<<<(unsigned)ceil_div(g.nnz, SF_TILE), BLOCK, 0, st>>>(g, D, rowpos, skey, sw);
     MGCD_LAUNCHED();

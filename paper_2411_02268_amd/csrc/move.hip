@@ -1169,18 +1169,18 @@ void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a
     k_chunk_counts<<<grid_for(s.nmulti), BLOCK, 0, st>>>(g.off, s.multi, s.nmulti, L, nch);
     MGCD_LAUNCHED();
     scan_i64(nch, s.cstart, s.nmulti, s.cstart + s.nmulti, a, st);
-    MGCD_HIP(hipMemcpyAsync(&s.nchunks, s.cstart + s.nmulti, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    MGCD_HIP(hipStreamSynchronize(st));
-    s.owner = a.take<int32_t>(s.nchunks);
-    k_chunk_owner<<<(unsigned)s.nmulti, BLOCK, 0, st>>>(s.cstart, s.nmulti, s.owner);
-    MGCD_LAUNCHED();
     int64_t *ng = a.take<int64_t>(s.nmulti);
     s.gstart = a.take<int64_t>(s.nmulti + 1);
     k_group_counts<<<grid_for(s.nmulti), BLOCK, 0, st>>>(s.cstart, s.nmulti, ng);
     MGCD_LAUNCHED();
     scan_i64(ng, s.gstart, s.nmulti, s.gstart + s.nmulti, a, st);
+    // chunk and group totals in one host round trip
+    MGCD_HIP(hipMemcpyAsync(&s.nchunks, s.cstart + s.nmulti, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     MGCD_HIP(hipMemcpyAsync(&s.ngroups, s.gstart + s.nmulti, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     MGCD_HIP(hipStreamSynchronize(st));
+    s.owner = a.take<int32_t>(s.nchunks);
+    k_chunk_owner<<<(unsigned)s.nmulti, BLOCK, 0, st>>>(s.cstart, s.nmulti, s.owner);
+    MGCD_LAUNCHED();
     s.gowner = a.take<int32_t>(s.ngroups);
     k_chunk_owner<<<(unsigned)s.nmulti, BLOCK, 0, st>>>(s.gstart, s.nmulti, s.gowner);
     MGCD_LAUNCHED();

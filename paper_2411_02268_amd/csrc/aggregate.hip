@@ -98,7 +98,6 @@ void launch_scatter_labels(const int32_t *map, const int32_t *val, int32_t *out,
   MGCD_LAUNCHED();
 }
 
-constexpr int ROW_BLOCKS = 2048;
 
 // K_i = sum of row i's weights (Section 3), W = their total.  A workgroup takes
 // DG_TILE consecutive entries: their weights are staged in LDS (coalesced loads) and
@@ -117,6 +116,47 @@ __device__ inline int32_t row_of_entry(const int64_t *off, int32_t lo, int32_t h
   }
   return lo;
 }
+
+// Rows of a tile of consecutive CSR entries [e0, e1) (non-empty): the rows meeting
+// it are r0 .. r1 (two binary searches); every row r0 < r <= r1 marks its first
+// position in an LDS count array, whose inclusive prefix sum then gives the entry
+// at tile position x the row r0 + starts[x] (no per-entry search).  Whole-workgroup
+// call; returns r0.
+constexpr int SF_ITEMS = 8, SF_TILE = BLOCK * SF_ITEMS;
+
+__device__ inline int32_t tile_rows(const Graph &g, int64_t e0, int64_t e1, uint32_t *starts) {
+  __shared__ uint32_t wsum[BLOCK / WAVE];
+  __shared__ int32_t sr[2];
+  const int t = threadIdx.x, w = t / WAVE;
+  for (int x = t; x < SF_TILE; x += BLOCK) starts[x] = 0;
+  if (t == 0) sr[0] = row_of_entry(g.off, 0, g.n - 1, e0);
+  if (t == 1) sr[1] = row_of_entry(g.off, 0, g.n - 1, e1 - 1);
+  __syncthreads();
+  const int32_t r0 = sr[0], r1 = sr[1];
+  // rows r0 < r <= r1 start inside the tile (off[r0 + 1] > e0, off[r1] <= e1 - 1)
+  for (int64_t r = (int64_t)r0 + 1 + t; r <= r1; r += BLOCK) atomicAdd(&starts[g.off[r] - e0], 1u);
+  __syncthreads();
+  // inclusive prefix sum of the counts: thread t owns positions SF_ITEMS*t ..
+  uint32_t v[SF_ITEMS], run = 0;
+#pragma unroll
+  for (int q = 0; q < SF_ITEMS; ++q) {
+    v[q] = starts[t * SF_ITEMS + q];
+    run += v[q];
+  }
+  const uint32_t incl = wave_inclusive_scan(run);
+  if (lane_id() == WAVE - 1) wsum[w] = incl;
+  __syncthreads();
+  uint32_t acc = incl - run;
+  for (int q = 0; q < w; ++q) acc += wsum[q];
+#pragma unroll
+  for (int q = 0; q < SF_ITEMS; ++q) {
+    acc += v[q];
+    starts[t * SF_ITEMS + q] = acc;
+  }
+  __syncthreads();
+  return r0;
+}
+
 
 __global__ void __launch_bounds__(BLOCK)
     k_row_weight_sums(Graph g, uint32_t *K, unsigned long long *Wpart) {
@@ -246,23 +286,36 @@ int32_t canonical(const int32_t *C, int32_t n, int32_t *out, Arena &a, hipStream
 
 // ---- modularity ------------------------------------------------------------------------
 
-// Grid-stride waves over vertices: weight of the intra-community entries.
+// Weight of the intra-community entries (sigma of Eq. 1 summed over communities):
+// SF_TILE consecutive entries per workgroup with their rows from tile_rows, every
+// entry's C[row] and C[j] gathered together; the workgroup total goes to one of SPREAD
+// copies of terms[0].
 __global__ void __launch_bounds__(BLOCK)
     k_intra(Graph g, const int32_t *C, unsigned long long *terms) {
-  __shared__ unsigned long long lw[4];
-  const int64_t waves = (int64_t)gridDim.x * 4;
-  uint64_t tot = 0;
-  for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE; i < g.n; i += waves) {
-    const int32_t ci = C[i];
-    uint64_t s = 0;
-    for (int64_t e = g.off[i] + lane_id(); e < g.off[i + 1]; e += WAVE)
-      s += C[g.idx[e]] == ci ? g.w[e] : 0u;
-    tot += s;
+  __shared__ uint32_t starts[SF_TILE];
+  __shared__ unsigned long long lw[BLOCK / WAVE];
+  const int t = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * SF_TILE;
+  const int64_t e1 = e0 + SF_TILE < g.nnz ? e0 + SF_TILE : g.nnz;
+  const int32_t r0 = tile_rows(g, e0, e1, starts);
+  unsigned long long tot = 0;
+#pragma unroll
+  for (int q = 0; q < SF_ITEMS; ++q) {
+    const int64_t x = (int64_t)q * BLOCK + t;
+    const bool v = e0 + x < e1;
+    const int64_t e = v ? e0 + x : e0;
+    const int32_t ci = C[r0 + (int32_t)starts[v ? x : 0]];
+    const int32_t cj = C[__builtin_nontemporal_load(g.idx + e)];
+    const uint32_t w = __builtin_nontemporal_load(g.w + e);
+    tot += (v && ci == cj) ? w : 0u;
   }
   tot = wave_sum(tot);
-  if (lane_id() == 0) lw[threadIdx.x / WAVE] = tot;
+  if (lane_id() == 0) lw[t / WAVE] = tot;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(&terms[2 * spread_copy()], lw[0] + lw[1] + lw[2] + lw[3]);
+  if (t == 0) {
+    const unsigned long long s = lw[0] + lw[1] + lw[2] + lw[3];
+    if (s) atomicAdd(&terms[2 * spread_copy()], s);
+  }
 }
 
 __global__ void k_comm_tot(const int32_t *C, const uint32_t *K, int32_t n, uint32_t *tot) {
@@ -286,9 +339,10 @@ void modularity_terms(const Graph &g, const int32_t *C, const uint32_t *K, unsig
   size_t mk = a.mark();
   uint32_t *tot = a.take<uint32_t>(g.n);
   zero_u32(tot, g.n, st);
-  int64_t rb = ceil_div(g.n, 4);
-  k_intra<<<(unsigned)(rb < ROW_BLOCKS ? rb : ROW_BLOCKS), BLOCK, 0, st>>>(g, C, terms);
-  MGCD_LAUNCHED();
+  if (g.nnz > 0) {
+    k_intra<<<(unsigned)ceil_div(g.nnz, SF_TILE), BLOCK, 0, st>>>(g, C, terms);
+    MGCD_LAUNCHED();
+  }
   k_comm_tot<<<grid_for(g.n), BLOCK, 0, st>>>(C, K, g.n, tot);
   MGCD_LAUNCHED();
   k_sum_squares<<<grid_for(g.n), BLOCK, 0, st>>>(tot, g.n, terms);
@@ -461,46 +515,6 @@ __global__ void k_row_pos(const uint32_t *mem, const int64_t *P, const int32_t *
                           int64_t *rowpos) {
   int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (t < n && t < *nmem) rowpos[mem[t]] = P[t];
-}
-
-// Rows of a tile of consecutive CSR entries [e0, e1) (non-empty): the rows meeting
-// it are r0 .. r1 (two binary searches); every row r0 < r <= r1 marks its first
-// position in an LDS count array, whose inclusive prefix sum then gives the entry
-// at tile position x the row r0 + starts[x] (no per-entry search).  Whole-workgroup
-// call; returns r0.
-constexpr int SF_ITEMS = 8, SF_TILE = BLOCK * SF_ITEMS;
-
-__device__ inline int32_t tile_rows(const Graph &g, int64_t e0, int64_t e1, uint32_t *starts) {
-  __shared__ uint32_t wsum[BLOCK / WAVE];
-  __shared__ int32_t sr[2];
-  const int t = threadIdx.x, w = t / WAVE;
-  for (int x = t; x < SF_TILE; x += BLOCK) starts[x] = 0;
-  if (t == 0) sr[0] = row_of_entry(g.off, 0, g.n - 1, e0);
-  if (t == 1) sr[1] = row_of_entry(g.off, 0, g.n - 1, e1 - 1);
-  __syncthreads();
-  const int32_t r0 = sr[0], r1 = sr[1];
-  // rows r0 < r <= r1 start inside the tile (off[r0 + 1] > e0, off[r1] <= e1 - 1)
-  for (int64_t r = (int64_t)r0 + 1 + t; r <= r1; r += BLOCK) atomicAdd(&starts[g.off[r] - e0], 1u);
-  __syncthreads();
-  // inclusive prefix sum of the counts: thread t owns positions SF_ITEMS*t ..
-  uint32_t v[SF_ITEMS], run = 0;
-#pragma unroll
-  for (int q = 0; q < SF_ITEMS; ++q) {
-    v[q] = starts[t * SF_ITEMS + q];
-    run += v[q];
-  }
-  const uint32_t incl = wave_inclusive_scan(run);
-  if (lane_id() == WAVE - 1) wsum[w] = incl;
-  __syncthreads();
-  uint32_t acc = incl - run;
-  for (int q = 0; q < w; ++q) acc += wsum[q];
-#pragma unroll
-  for (int q = 0; q < SF_ITEMS; ++q) {
-    acc += v[q];
-    starts[t * SF_ITEMS + q] = acc;
-  }
-  __syncthreads();
-  return r0;
 }
 
 // Lay the community streams out contiguously: entry e of row i goes to position

@@ -841,6 +841,85 @@ __device__ inline Pair load_slot(Pair *p) {
 
 // Workgroup per vertex with an open-addressing table (linear probing) in LDS
 // (CAP slots) or, when GLOBAL, in this vertex's region of global memory.
+// Exact mode, tier 1 (rows of up to EXACT_T1_MAX entries): one wave per row with an
+// LDS open-addressing table of its own, sized to the row (the smallest power of two
+// >= 2 * its length, 64 .. 1024 slots), so a block holds four rows instead of one.
+// Same table keys, sums, first positions (small table) and decision as k_exact_table.
+template <int ALGO, bool SMALL = false>
+__global__ void __launch_bounds__(BLOCK)
+    k_exact_wave(SweepArgs a, const int32_t *__restrict__ list, int64_t count) {
+  constexpr uint32_t CAPW = 2 * EXACT_T1_MAX;
+  __shared__ Pair wtab[BLOCK / WAVE][CAPW];
+  __shared__ uint32_t wpos[BLOCK / WAVE][SMALL ? CAPW : 1];
+  const int lane = lane_id(), w = threadIdx.x / WAVE;
+  const int64_t r = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
+  Counters ct;
+  if (r < count) {
+    const int32_t i = uniform(list[r]);
+    if (frozen(a, i)) {
+      if (lane == 0) a.Cnew[i] = community_of_self<ALGO>(a, i);
+    } else {
+      const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
+      uint32_t cap = 64;
+      while (cap < CAPW && (int64_t)cap < 2 * (hi - lo)) cap <<= 1;
+      Pair *tab = wtab[w];
+      uint32_t *pos = wpos[w];
+      for (uint32_t x = lane; x < cap; x += WAVE) {
+        tab[x] = Pair{EMPTY, 0u};
+        if (SMALL) pos[x] = 0xFFFFFFFFu;
+      }
+      wave_sync();
+      const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
+      const uint32_t mask = cap - 1;
+      for (int64_t e = lo + lane; e < hi; e += WAVE) {
+        const int32_t j = a.g.idx[e];
+        const uint32_t c0 = stream_key<ALGO>(a, i, j, bi);
+        if (c0 == EMPTY) continue;
+        const uint32_t c = slot_of(a, c0);
+        uint32_t h = hash_slot(c, mask);
+        while (true) {
+          const uint32_t prev = atomicCAS(&tab[h].key, EMPTY, c);
+          if (prev == EMPTY || prev == c) {
+            atomicAdd(&tab[h].val, a.g.w[e]);
+            if (SMALL) atomicMin(&pos[h], (uint32_t)(e - lo));
+            break;
+          }
+          h = (h + 1) & mask;
+        }
+      }
+      wave_sync();
+      const int32_t d = community_of_self<ALGO>(a, i);
+      const uint32_t sd = slot_of(a, (uint32_t)d);
+      uint32_t kd = 0;
+      for (uint32_t x = lane; x < cap; x += WAVE) kd += tab[x].key == sd ? tab[x].val : 0u;
+      kd = wave_sum(kd);
+      int32_t best = -1;
+      int64_t bestG = 0;
+      const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
+      const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+      const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+      for (uint32_t x = lane; x < cap; x += WAVE) {
+        Pair p = tab[x];
+        const bool present = p.key != EMPTY;
+        if (SMALL && present) p.key = stream_key<ALGO>(a, i, a.g.idx[lo + pos[x]], bi);
+        const uint32_t sc = ALGO == ALGO_LPA ? 0u : a.Sig[present ? (int32_t)p.key : d];
+        consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)p.key, p.val, sc, present, best, bestG);
+      }
+      // wave arg-max: larger gain first, then lower community id
+#pragma unroll
+      for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const int32_t ob = __shfl_xor(best, o);
+        const int64_t og = __shfl_xor(bestG, o);
+        const bool take = ob >= 0 && (best < 0 || og > bestG || (og == bestG && ob < best));
+        best = take ? ob : best;
+        bestG = take ? og : bestG;
+      }
+      if (lane == 0) finish<ALGO>(a, i, d, best, bestG, ct);
+    }
+  }
+  flush_counters(a, ct);
+}
+
 template <int ALGO, int CAP, bool GLOBAL, bool SMALL = false>
 __global__ void __launch_bounds__(BLOCK)
     k_exact_table(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
@@ -1256,8 +1335,8 @@ static void sweep_exact(const SweepArgs &a, const Schedule &s, hipStream_t st, h
   }
   mark(ev, 1, st);
   if (s.ntier[1] > 0) {
-    k_exact_table<ALGO, 1024, false, SMALL><<<(unsigned)s.ntier[1], BLOCK, 0, st>>>(a, s.tier[1], nullptr, nullptr,
-                                                                              nullptr);
+    k_exact_wave<ALGO, SMALL><<<(unsigned)ceil_div(s.ntier[1], BLOCK / WAVE), BLOCK, 0, st>>>(
+        a, s.tier[1], s.ntier[1]);
     MGCD_LAUNCHED();
   }
   if (s.ntier[2] > 0) {

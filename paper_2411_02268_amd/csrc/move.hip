@@ -704,6 +704,186 @@ __global__ void __launch_bounds__(BLOCK)
   flush_counters(a, ct);
 }
 
+// Rows of more than max(L, WAVE_SPLIT) entries when K is 32 or 64 ("split rows"): the
+// same sketch, merge tree and decision as k_wave_rows, with the work spread over waves
+// so that a hub row does not hold one wave for its whole length.
+//   k_wave_chunks: one wave per chunk: its Algorithm 1 sketch (keys written to the key
+//                  stream), finalised, into the chunk's node;
+//   k_wave_level:  one launch per tree level l: node x of a row (x a multiple of
+//                  2^(l+1)) takes in node x + 2^l if that exists, left operand first,
+//                  an odd last node is carried; after ceil(log2(chunks)) levels node 0
+//                  is the root, the same tree as WaveTree;
+//   k_wave_count:  pass 2 of lossy rows, one wave per chunk, integer sums added into
+//                  the row's counts (order-independent);
+//   k_wave_decide: one wave per row: scores and the decision, as in k_wave_rows.
+template <int K, int ALGO, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_wave_chunks(SweepArgs a, const int32_t *__restrict__ rows, const int64_t *__restrict__ cstart,
+                  const int32_t *__restrict__ owner, int64_t nchunks, int64_t L, uint32_t *keybuf,
+                  Pair *node, uint32_t *nflag, uint32_t *count) {
+  const int lane = lane_id();
+  const int64_t q = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
+  if (q >= nchunks) return;
+  const int32_t m = uniform(owner[q]);
+  const int32_t i = uniform(rows[m]);
+  if (q == cstart[m]) {  // the row's K + 1 pass-2 counts start at zero in every sweep
+    uint32_t *cm = count + (int64_t)m * (K + 1);
+    if (lane <= K) cm[lane] = 0u;                  // K < WAVE: slots 0..K
+    if (K == WAVE && lane == 0) cm[K] = 0u;        // K == WAVE: the last one
+  }
+  if (frozen(a, i)) return;
+  const int64_t rhi = uniform(a.g.off[i + 1]);
+  const int64_t lo = uniform(a.g.off[i]) + (q - cstart[m]) * L;
+  const int64_t hi = lo + L < rhi ? lo + L : rhi;
+  const int32_t bi = ALGO == ALGO_REFINE ? uniform(a.bound[i]) : 0;
+  WaveSketch<K, MODE> s;
+  s.reset();
+  for (int64_t e0 = lo; e0 < hi; e0 += WAVE) {
+    const int64_t e = e0 + lane;
+    const bool v = e < hi;
+    const int32_t j = v ? __builtin_nontemporal_load(a.g.idx + e) : 0;
+    const uint32_t w = v ? __builtin_nontemporal_load(a.g.w + e) : 0u;
+    uint32_t key = EMPTY;
+    if (v) {
+      key = stream_key<ALGO>(a, i, j, bi);
+      keybuf[e] = key;
+    }
+    const int nb = hi - e0 < WAVE ? (int)(hi - e0) : WAVE;
+    for (int t = 0; t < nb; ++t) {
+      const uint32_t c = lane_value(key, t);
+      if (c != EMPTY) s.update(c, lane_value(w, t));
+    }
+  }
+  s.finalize();
+  if (lane < K) node[q * K + lane] = Pair{s.key, s.val};
+  if (lane == 0) nflag[q] = s.lossy ? 1u : 0u;
+}
+
+template <int K>
+__global__ void __launch_bounds__(BLOCK)
+    k_wave_level(SweepArgs a, const int32_t *__restrict__ rows, const int64_t *__restrict__ cstart,
+                 const int32_t *__restrict__ owner, int64_t nchunks, int level, Pair *node,
+                 uint32_t *nflag) {
+  const int lane = lane_id();
+  const int64_t q = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
+  if (q >= nchunks) return;
+  const int32_t m = uniform(owner[q]);
+  const int64_t x = q - cstart[m], half = (int64_t)1 << level;
+  if ((x & (2 * half - 1)) != 0) return;  // not a left node of this level
+  const int64_t r = q + half;
+  if (r >= cstart[m + 1]) return;  // odd last node: carried up
+  if (frozen(a, rows[m])) return;
+  uint32_t ak = EMPTY, av = 0, bk = EMPTY, bv = 0;
+  if (lane < K) {
+    const Pair pa = node[q * K + lane], pb = node[r * K + lane];
+    ak = pa.key;
+    av = pa.val;
+    bk = pb.key;
+    bv = pb.val;
+  }
+  const bool lossy = wave_merge<K>(ak, av, bk, bv);
+  if (lane < K) node[q * K + lane] = Pair{ak, av};
+  if (lane == 0) nflag[q] = nflag[q] | nflag[r] | (lossy ? 1u : 0u);
+}
+
+// The root of split row m: keys of positive slots, other slots EMPTY.
+template <int K>
+__device__ inline void wave_root(const Pair *node, const int64_t *cstart, int32_t m, uint32_t &ck,
+                                 uint32_t &cv) {
+  const int lane = lane_id();
+  ck = EMPTY;
+  cv = 0;
+  if (lane < K) {
+    const Pair p = node[cstart[m] * K + lane];
+    ck = p.val > 0 ? p.key : EMPTY;
+    cv = p.val;
+  }
+}
+
+template <int K, int ALGO>
+__global__ void __launch_bounds__(BLOCK)
+    k_wave_count(SweepArgs a, const int32_t *__restrict__ rows, const int64_t *__restrict__ cstart,
+                 const int32_t *__restrict__ owner, int64_t nchunks, int64_t L,
+                 const uint32_t *__restrict__ keybuf, const Pair *__restrict__ node,
+                 const uint32_t *__restrict__ nflag, uint32_t *count) {
+  const int lane = lane_id();
+  const int64_t q = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
+  if (q >= nchunks) return;
+  const int32_t m = uniform(owner[q]);
+  const int32_t i = uniform(rows[m]);
+  if (frozen(a, i) || !nflag[cstart[m]]) return;
+  const int64_t rhi = uniform(a.g.off[i + 1]);
+  const int64_t lo = uniform(a.g.off[i]) + (q - cstart[m]) * L;
+  const int64_t hi = lo + L < rhi ? lo + L : rhi;
+  const uint32_t d = (uint32_t)uniform(community_of_self<ALGO>(a, i));
+  uint32_t ck, cv0;
+  wave_root<K>(node, cstart, m, ck, cv0);
+  uint32_t cv = 0, kd = 0;
+  for (int64_t e0 = lo; e0 < hi; e0 += WAVE) {
+    const int64_t e = e0 + lane;
+    const bool v = e < hi;
+    const uint32_t key = v ? __builtin_nontemporal_load(keybuf + e) : EMPTY;
+    const uint32_t w = v ? __builtin_nontemporal_load(a.g.w + e) : 0u;
+    kd += key == d ? w : 0u;
+    const int nb = hi - e0 < WAVE ? (int)(hi - e0) : WAVE;
+    for (int t = 0; t < nb; ++t) {
+      const uint32_t c = lane_value(key, t);
+      if (c != EMPTY && ck == c) cv += lane_value(w, t);
+    }
+  }
+  kd = wave_sum(kd);
+  uint32_t *cm = count + (int64_t)m * (K + 1);
+  if (lane < K && cv) atomicAdd(&cm[lane], cv);
+  if (lane == 0 && kd) atomicAdd(&cm[K], kd);
+}
+
+template <int K, int ALGO>
+__global__ void __launch_bounds__(BLOCK)
+    k_wave_decide(SweepArgs a, const int32_t *__restrict__ rows, const int64_t *__restrict__ cstart,
+                  int64_t nrows, const Pair *__restrict__ node, const uint32_t *__restrict__ nflag,
+                  const uint32_t *__restrict__ count) {
+  const int lane = lane_id();
+  const int64_t m = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
+  Counters ct;
+  if (m < nrows) {
+    const int32_t i = uniform(rows[m]);
+    if (frozen(a, i)) {
+      if (lane == 0) a.Cnew[i] = community_of_self<ALGO>(a, i);
+    } else {
+      const int32_t d = uniform(community_of_self<ALGO>(a, i));
+      uint32_t ck, cv;
+      wave_root<K>(node, cstart, (int32_t)m, ck, cv);
+      uint32_t kd;
+      if (!nflag[cstart[m]] || !second_pass(a, ALGO)) {
+        kd = wave_sum(ck == (uint32_t)d ? cv : 0u);
+      } else {
+        const uint32_t *cm = count + m * (K + 1);
+        cv = lane < K ? cm[lane] : 0u;
+        kd = cm[K];
+      }
+      int32_t best = -1;
+      int64_t bestG = 0;
+      if (ck != EMPTY) {
+        const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
+        const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+        const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+        consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)ck, cv, best, bestG);
+      }
+#pragma unroll
+      for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const int32_t b2 = __shfl_xor(best, o);
+        const int64_t g2 = __shfl_xor(bestG, o);
+        if (b2 >= 0 && (best < 0 || g2 > bestG || (g2 == bestG && b2 < best))) {
+          best = b2;
+          bestG = g2;
+        }
+      }
+      if (lane == 0) finish<ALGO>(a, i, d, best, bestG, ct);
+    }
+  }
+  flush_counters(a, ct);
+}
+
 // ---- exact mode ----------------------------------------------------------------------
 
 // A row of at most ES entries: keys and weights gathered once into registers, then
@@ -1054,6 +1234,8 @@ __global__ void __launch_bounds__(BLOCK)
 // (wave ballots, then one atomic per category and workgroup).
 //   MG:    0 = row fits one chunk (sort key: heavy first), 1 + b = a long row of at
 //          most 2^b <= 64 chunks (b = 1..6), 7 = longer rows;
+//   MG with K = 32 / 64: 0 = at most exact_t0 entries, 1 = one wave per row, 2 = split
+//          rows (more than max(L, WAVE_SPLIT) entries);
 //   exact: tiers 0..3 by degree.
 constexpr int NCAT = 8;
 
@@ -1077,8 +1259,8 @@ __global__ void __launch_bounds__(BLOCK)
     if (mode == MODE_EXACT) {
       cat = deg <= sp.exact_t0 ? 0 : deg <= sp.exact_t1 ? 1 : deg <= sp.exact_t2 ? 2 : 3;
       k = cat == 0 ? (uint64_t)(64 - b) : (uint64_t)(128 + cat);
-    } else if (sp.wave) {  // K = 32 / 64: short rows exact, the rest one wave each
-      cat = deg <= sp.exact_t0 ? 0 : 1;
+    } else if (sp.wave) {  // K = 32 / 64: short rows exact, split rows, the rest one wave each
+      cat = deg <= sp.exact_t0 ? 0 : (deg > L && deg > WAVE_SPLIT) ? 2 : 1;
       k = (uint64_t)(cat * 64 + 64 - b);  // heavy rows first in each tier
     } else if (deg <= L) {
       cat = 0;
@@ -1175,6 +1357,8 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
     b += (size_t)(nl + 1) * 8 * 2 + scan_ws_bytes(nl) + 2048;        // group counts, gstart
     b += (size_t)gl * (4 + (size_t)k * sizeof(Pair) + 4) + 4096;     // gowner, roots, flags
     b += (size_t)nl * ((size_t)k * sizeof(Pair) + 4) + 2048;         // candidates, flags
+    if (k > 16)  // split rows of the 32/64-slot sketch: chunk nodes, flags, pass-2 counts
+      b += (size_t)cl * ((size_t)k * sizeof(Pair) + 4) + (size_t)nl * (k + 1) * 4 + 4096;
   }
   return b + 64 * 1024;
 }
@@ -1206,6 +1390,23 @@ void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a
     s.tier[1] = order + h[0];
     s.ntier[1] = (int64_t)h[1];
     s.keybuf = a.take<uint32_t>(g.nnz);
+    s.multi = order + h[0] + h[1];
+    s.nmulti = (int64_t)h[2];
+    if (s.nmulti > 0) {
+      int64_t *nch = a.take<int64_t>(s.nmulti);
+      s.cstart = a.take<int64_t>(s.nmulti + 1);
+      k_chunk_counts<<<grid_for(s.nmulti), BLOCK, 0, st>>>(g.off, s.multi, s.nmulti, L, nch);
+      MGCD_LAUNCHED();
+      scan_i64(nch, s.cstart, s.nmulti, s.cstart + s.nmulti, a, st);
+      MGCD_HIP(hipMemcpyAsync(&s.nchunks, s.cstart + s.nmulti, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      MGCD_HIP(hipStreamSynchronize(st));
+      s.owner = a.take<int32_t>(s.nchunks);
+      k_chunk_owner<<<(unsigned)s.nmulti, BLOCK, 0, st>>>(s.cstart, s.nmulti, s.owner);
+      MGCD_LAUNCHED();
+      s.wnode = a.take<Pair>(s.nchunks * k);
+      s.wflag = a.take<uint32_t>(s.nchunks);
+      s.wcount = a.take<uint32_t>(s.nmulti * (k + 1));
+    }
     return;
   }
   if (mode == MODE_EXACT) {
@@ -1363,7 +1564,7 @@ static void sweep_wave(const SweepArgs &a, const Schedule &s, int64_t L, hipStre
   mark(ev, 1, st);
   if (s.ntier[1] > 0) {
     const unsigned grid = (unsigned)ceil_div(s.ntier[1], BLOCK / WAVE);
-    if (wave_depth_for(s.maxdeg, L) == WDEPTH_SHALLOW)
+    if (wave_depth_for(s.nmulti > 0 ? (L > WAVE_SPLIT ? L : WAVE_SPLIT) : s.maxdeg, L) == WDEPTH_SHALLOW)
       k_wave_rows<K, ALGO, MODE, WDEPTH_SHALLOW><<<grid, BLOCK, 0, st>>>(a, s.tier[1], s.ntier[1], L,
                                                                          s.keybuf);
     else
@@ -1371,6 +1572,26 @@ static void sweep_wave(const SweepArgs &a, const Schedule &s, int64_t L, hipStre
     MGCD_LAUNCHED();
   }
   mark(ev, 2, st);
+  if (s.nmulti > 0) {  // split rows
+    const unsigned cgrid = (unsigned)ceil_div(s.nchunks, BLOCK / WAVE);
+    k_wave_chunks<K, ALGO, MODE><<<cgrid, BLOCK, 0, st>>>(a, s.multi, s.cstart, s.owner, s.nchunks, L,
+                                                          s.keybuf, s.wnode, s.wflag, s.wcount);
+    MGCD_LAUNCHED();
+    const int64_t maxch = (s.maxdeg + L - 1) / L;
+    for (int l = 0; ((int64_t)1 << l) < maxch; ++l) {
+      k_wave_level<K><<<cgrid, BLOCK, 0, st>>>(a, s.multi, s.cstart, s.owner, s.nchunks, l, s.wnode,
+                                               s.wflag);
+      MGCD_LAUNCHED();
+    }
+    if (second_pass(a, ALGO)) {
+      k_wave_count<K, ALGO><<<cgrid, BLOCK, 0, st>>>(a, s.multi, s.cstart, s.owner, s.nchunks, L, s.keybuf,
+                                                     s.wnode, s.wflag, s.wcount);
+      MGCD_LAUNCHED();
+    }
+    k_wave_decide<K, ALGO><<<(unsigned)ceil_div(s.nmulti, BLOCK / WAVE), BLOCK, 0, st>>>(
+        a, s.multi, s.cstart, s.nmulti, s.wnode, s.wflag, s.wcount);
+    MGCD_LAUNCHED();
+  }
   mark(ev, 3, st);
 }
 

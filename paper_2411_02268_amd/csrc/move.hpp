@@ -42,7 +42,7 @@ __device__ inline uint32_t slot_of(const SweepArgs &a, uint32_t c) {
 }
 
 // Whether a row whose sketch lost weight still needs the second pass.
-__device__ inline bool second_pass(const SweepArgs &a, int algo) { return !(algo == ALGO_LPA && a.one_scan); }
+__host__ __device__ inline bool second_pass(const SweepArgs &a, int algo) { return !(algo == ALGO_LPA && a.one_scan); }
 
 // A single graph's level, kept on the device so that sweeps need no host round trip:
 // set `halt` when the level's stopping rule fires; count sweeps, streamed entries
@@ -108,6 +108,10 @@ struct Schedule {
   uint32_t *part = nullptr;   // [nchunks * (k+1)] pass-2 counts per chunk of a lossy long row
   Pair *cand = nullptr;       // [nmulti * k] merged candidates of each long row
   uint32_t *cflag = nullptr;  // [nmulti] 0 decided, 1 lossy, 2 frozen
+  // MG with K = 32 / 64: multi, cstart and owner list the split rows and their chunks
+  Pair *wnode = nullptr;      // [nchunks * k] chunk sketches, merged in place level by level
+  uint32_t *wflag = nullptr;  // [nchunks] the node's sketches or merges lost weight
+  uint32_t *wcount = nullptr; // [nmulti * (k+1)] pass-2 counts per candidate slot, then K_{i->d}
   // exact mode
   int32_t *tier[4] = {nullptr, nullptr, nullptr, nullptr};
   int64_t ntier[4] = {0, 0, 0, 0};
@@ -133,6 +137,9 @@ struct SchedParams {
                       // wave each
 };
 constexpr int64_t EXACT_T1_MAX = 512, EXACT_T2_MAX = 4096;
+// K = 32 / 64: rows of more than max(L, WAVE_SPLIT) entries are split over one wave per
+// chunk (schedule only: the merge tree and the results are those of one wave per row)
+constexpr int64_t WAVE_SPLIT = 512;
 
 void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a, hipStream_t st);
 

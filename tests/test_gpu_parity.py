@@ -310,6 +310,50 @@ def test_wave_sketch_deep_merge_tree(mg, k):
     assert np.array_equal(ww, e.weights)
 
 
+def _hub_graph(seed):
+    """6,000 vertices; five hubs of 5,000, 2,049, 1,300, 701 and 513 random neighbours
+    (chunk counts that are not powers of two) plus 8,000 random edges, weights 1..8."""
+    rng = np.random.default_rng(seed)
+    n = 6000
+    edges = []
+    for h, deg in enumerate((5000, 2049, 1300, 701, 513)):
+        edges += [(h, int(v)) for v in rng.choice(np.arange(5, n), size=deg, replace=False)]
+    edges += [(int(u), int(v)) for u, v in rng.integers(5, n, size=(8000, 2)) if u != v]
+    w = rng.integers(1, 9, size=len(edges)).astype(np.uint32)
+    return synth.from_edges(n, edges, w)
+
+
+@pytest.mark.parametrize("k", [32, 64])
+@pytest.mark.parametrize("mode", ["alg1", "uncond", "std"])
+@pytest.mark.parametrize("L", [1, 37, 128, 700])
+def test_wave_split_rows(mg, k, mode, L):
+    """At k = 32/64, rows of more than max(L, 512) entries are sketched one wave per
+    chunk and merged level by level on the device: labels, gains and counters equal the
+    oracle's for LPA, Louvain, 1-scan LPA and the refinement sweep, with neighbour
+    labels from 20 communities (loss-free hub sketches) and from 3,000 (lossy)."""
+    g = _hub_graph(77)
+    dg = mg.to_device(g)
+    rng = np.random.default_rng(zlib.crc32(f"split-{k}-{mode}-{L}".encode()))
+    for ncomm in (20, 3000):
+        C = rng.integers(0, ncomm, size=g.n).astype(np.int32)
+        for algo, oalgo in ((mg.ALGO_LPA, oracle.ALGO_LPA), (mg.ALGO_LOUVAIN, oracle.ALGO_MOVE)):
+            Cn, gain, ctr = mg.move_sweep(dg, algo, _t(C), 0, mode=MODES[mode], k=k, chunk_len=L)
+            eC, eg = oracle.move_sweep(g, oalgo, C, mode=MODES[mode], k=k, chunk_len=L)
+            assert np.array_equal(_np(Cn), eC), (algo, ncomm)
+            if algo == mg.ALGO_LOUVAIN:
+                assert np.array_equal(_np(gain), eg)
+                assert ctr == [int((eC != C).sum()), int((eg > 0).sum()), int(eg.sum())]
+        Cn, _, _ = mg.move_sweep(dg, mg.ALGO_LPA, _t(C), 0, mode=MODES[mode], k=k, chunk_len=L,
+                                 one_scan=1)
+        eC, _ = oracle.move_sweep(g, oracle.ALGO_LPA, C, mode=MODES[mode], k=k, chunk_len=L,
+                                  one_scan=1)
+        assert np.array_equal(_np(Cn), eC), ("1-scan", ncomm)
+    bound = rng.integers(0, 3, size=g.n).astype(np.int32)
+    R = mg.refine(dg, _t(bound), mode=MODES[mode], k=k, chunk_len=L)
+    eR = oracle.refine(g, bound, mode=MODES[mode], k=k, chunk_len=L)
+    assert np.array_equal(_np(R), eR)
+
+
 @pytest.mark.parametrize("algo", ["lpa", "louvain"])
 def test_batched_many_graphs_dirty_workspace(mg, algo):
     """More graphs than one wave of counters, in a workspace full of garbage: every

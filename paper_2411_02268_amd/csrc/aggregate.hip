@@ -422,10 +422,11 @@ __global__ void k_member_deg(const int64_t *off, const uint32_t *mem, int32_t n,
 }
 
 // Category of every community stream: b = log2 of the lanes it needs (0..6, at
-// most 64 chunks; sort key heavy first within b = 0) or 7 = longer.
+// most 64 chunks; sort key heavy first within b = 0) or 7 = longer.  With split > 0
+// (the 32/64-slot sketch): 0 = one wave, 7 = more than max(L, split) positions.
 __global__ void __launch_bounds__(BLOCK)
-    k_comm_keys(const int32_t *mstart, const int64_t *P, int32_t m, int64_t L, uint64_t *key,
-                uint32_t *val, unsigned long long *cnt) {
+    k_comm_keys(const int32_t *mstart, const int64_t *P, int32_t m, int64_t L, int64_t split,
+                uint64_t *key, uint32_t *val, unsigned long long *cnt) {
   __shared__ unsigned long long bc[8];
   if (threadIdx.x < 8) bc[threadIdx.x] = 0;
   __syncthreads();
@@ -435,7 +436,12 @@ __global__ void __launch_bounds__(BLOCK)
   if (c < m) {
     int64_t len = P[mstart[c + 1]] - P[mstart[c]];
     lmax = len;
-    if (len <= L) {
+    if (split > 0) {
+      cat = len > L && len > split ? 7 : 0;
+      int b = 0;
+      while (b < 63 && (len >> b) != 0) ++b;
+      key[c] = cat == 7 ? 207ull : (uint64_t)(64 - b);
+    } else if (len <= L) {
       int b = 0;
       while (b < 63 && (len >> b) != 0) ++b;
       cat = 0;
@@ -875,9 +881,103 @@ __global__ void __launch_bounds__(BLOCK)
   if (lane == 0) rcount[c] = (uint32_t)__popcll(pos);
 }
 
+// Streams of more than max(L, WAVE_SPLIT) positions at K = 32 / 64 ("split streams"):
+// the same chunk sketches, merge tree and row as k_agg_wave, spread over waves.
+struct AggSplit {
+  const int32_t *multi;   // [nmulti] split communities
+  int64_t nmulti;
+  const int64_t *cstart;  // [nmulti+1] first chunk of each
+  const int32_t *owner;   // [nchunks] index into multi of each chunk
+  int64_t nchunks;
+  Pair *node;             // [nchunks * K] chunk sketches, merged in place level by level
+};
+
+// One wave per chunk of a split stream: its sketch, finalised, into the chunk's node.
 template <int K, int MODE>
-static void agg_wave(const AggStreams &s, const int32_t *comms, int64_t ncomm, int64_t L, Pair *rows,
-                     uint32_t *rcount, int64_t max_len, hipStream_t st) {
+__global__ void __launch_bounds__(BLOCK) k_aggw_chunks(AggStreams s, AggSplit sp, int64_t L) {
+  const int lane = lane_id();
+  const int64_t q = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
+  if (q >= sp.nchunks) return;
+  const int32_t x = uniform(sp.owner[q]);
+  const int32_t c = uniform(sp.multi[x]);
+  const int64_t end = uniform(s.P[s.mstart[c + 1]]);
+  const int64_t p0 = uniform(s.P[s.mstart[c]]) + (q - sp.cstart[x]) * L;
+  const int64_t p1 = p0 + L < end ? p0 + L : end;
+  WaveSketch<K, MODE> sk;
+  sk.reset();
+  for (int64_t q0 = p0; q0 < p1; q0 += WAVE) {
+    const int64_t t = q0 + lane;
+    const bool v = t < p1;
+    const uint32_t key = v ? __builtin_nontemporal_load(s.skey + t) : EMPTY;
+    const uint32_t w = v ? __builtin_nontemporal_load(s.sw + t) : 0u;
+    const int nb = p1 - q0 < WAVE ? (int)(p1 - q0) : WAVE;
+    for (int u = 0; u < nb; ++u) sk.update(lane_value(key, u), lane_value(w, u));
+  }
+  sk.finalize();
+  if (lane < K) sp.node[q * K + lane] = Pair{sk.key, sk.val};
+}
+
+// Level `level` of the merge tree of every split stream (node x of a stream, x a
+// multiple of 2^(level+1), takes in node x + 2^level if that exists; an odd last node
+// is carried).
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_aggw_level(AggSplit sp, int level) {
+  const int lane = lane_id();
+  const int64_t q = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
+  if (q >= sp.nchunks) return;
+  const int32_t x = uniform(sp.owner[q]);
+  const int64_t half = (int64_t)1 << level;
+  if (((q - sp.cstart[x]) & (2 * half - 1)) != 0) return;
+  const int64_t r = q + half;
+  if (r >= sp.cstart[x + 1]) return;
+  uint32_t ak = EMPTY, av = 0, bk = EMPTY, bv = 0;
+  if (lane < K) {
+    const Pair pa = sp.node[q * K + lane], pb = sp.node[r * K + lane];
+    ak = pa.key;
+    av = pa.val;
+    bk = pb.key;
+    bv = pb.val;
+  }
+  wave_merge<K>(ak, av, bk, bv);
+  if (lane < K) sp.node[q * K + lane] = Pair{ak, av};
+}
+
+// The row of every split stream: the root's positive slots sorted by key.
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_aggw_rows(AggSplit sp, Pair *rows, uint32_t *rcount) {
+  const int lane = lane_id();
+  const int64_t x = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
+  if (x >= sp.nmulti) return;
+  const int32_t c = uniform(sp.multi[x]);
+  uint32_t ck = EMPTY, cv = 0;
+  if (lane < K) {
+    const Pair p = sp.node[sp.cstart[x] * K + lane];
+    cv = p.val;
+    ck = cv > 0 ? p.key : EMPTY;
+  }
+  uint32_t rank = 0;
+  for (int u = 0; u < WAVE; ++u) rank += lane_value(ck, u) < ck ? 1u : 0u;
+  const uint64_t pos = __ballot(cv > 0);
+  if (cv > 0) rows[(int64_t)c * K + rank] = Pair{ck, cv};
+  if (lane == 0) rcount[c] = (uint32_t)__popcll(pos);
+}
+
+template <int K, int MODE>
+static void agg_wave(const AggStreams &s, const int32_t *comms, int64_t ncomm, const AggSplit &sp,
+                     int64_t L, Pair *rows, uint32_t *rcount, int64_t max_len, hipStream_t st) {
+  if (sp.nmulti > 0) {
+    const unsigned cgrid = (unsigned)ceil_div(sp.nchunks, BLOCK / WAVE);
+    k_aggw_chunks<K, MODE><<<cgrid, BLOCK, 0, st>>>(s, sp, L);
+    MGCD_LAUNCHED();
+    const int64_t maxch = (max_len + L - 1) / L;
+    for (int l = 0; ((int64_t)1 << l) < maxch; ++l) {
+      k_aggw_level<K><<<cgrid, BLOCK, 0, st>>>(sp, l);
+      MGCD_LAUNCHED();
+    }
+    k_aggw_rows<K><<<(unsigned)ceil_div(sp.nmulti, BLOCK / WAVE), BLOCK, 0, st>>>(sp, rows, rcount);
+    MGCD_LAUNCHED();
+    max_len = L > WAVE_SPLIT ? L : WAVE_SPLIT;  // the longest stream left for one wave
+  }
   if (ncomm > 0) {
     const unsigned grid = (unsigned)ceil_div(ncomm, BLOCK / WAVE);
     if (wave_depth_for(max_len, L) == WDEPTH_SHALLOW)
@@ -905,11 +1005,11 @@ static void agg_mg(const AggStreams &s, const AggBuckets &bk, int64_t waves, con
 
 template <int MODE>
 static void agg_mg_k(int k, const AggStreams &s, const AggBuckets &bk, int64_t waves, const AggLong &lg,
-                     int64_t L, Pair *rows, uint32_t *rcount, const int32_t *all, int64_t m,
-                     int64_t max_len, hipStream_t st) {
+                     const AggSplit &sp, int64_t L, Pair *rows, uint32_t *rcount, const int32_t *one,
+                     int64_t none, int64_t max_len, hipStream_t st) {
   switch (k) {
-    case 32: agg_wave<32, MODE>(s, all, m, L, rows, rcount, max_len, st); break;
-    case 64: agg_wave<64, MODE>(s, all, m, L, rows, rcount, max_len, st); break;
+    case 32: agg_wave<32, MODE>(s, one, none, sp, L, rows, rcount, max_len, st); break;
+    case 64: agg_wave<64, MODE>(s, one, none, sp, L, rows, rcount, max_len, st); break;
     case 1: agg_mg<1, MODE>(s, bk, waves, lg, L, rows, rcount, st); break;
     case 2: agg_mg<2, MODE>(s, bk, waves, lg, L, rows, rcount, st); break;
     case 4: agg_mg<4, MODE>(s, bk, waves, lg, L, rows, rcount, st); break;
@@ -1013,7 +1113,8 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   launch_zero_u64(cnt, SPREAD * 9, st);
   uint64_t *ck0 = a.take<uint64_t>(m), *ck1 = a.take<uint64_t>(m);
   uint32_t *cv0 = a.take<uint32_t>(m), *cv1 = a.take<uint32_t>(m);
-  k_comm_keys<<<grid_for(m), BLOCK, 0, st>>>(mstart, P, m, L, ck0, cv0, cnt);
+  const bool wave = k > 16;  // the 32/64-slot sketch: one wave per stream, long ones split
+  k_comm_keys<<<grid_for(m), BLOCK, 0, st>>>(mstart, P, m, L, wave ? WAVE_SPLIT : 0, ck0, cv0, cnt);
   MGCD_LAUNCHED();
   bool cf = radix_sort_pairs(ck0, cv0, ck1, cv1, m, 8, a, st);
   int32_t *corder = a.take<int32_t>(m);
@@ -1040,12 +1141,21 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   int32_t *multi = corder + pos;
   int64_t *cstart = nullptr;
   AggLong lg{multi, nmulti, nullptr, nullptr, nullptr, 0, nullptr};
+  AggSplit sp{multi, 0, nullptr, nullptr, 0, nullptr};
   if (nmulti > 0) {
     int64_t *nch = a.take<int64_t>(nmulti);
     cstart = a.take<int64_t>(nmulti + 1);
     k_comm_chunks<<<grid_for(nmulti), BLOCK, 0, st>>>(mstart, P, multi, nmulti, L, nch);
     MGCD_LAUNCHED();
     scan_i64(nch, cstart, nmulti, cstart + nmulti, a, st);
+  }
+  if (wave && nmulti > 0) {  // chunks of the split streams
+    const int64_t nchunks = read_i64(cstart + nmulti, st);
+    int32_t *owner = a.take<int32_t>(nchunks);
+    k_comm_owner<<<(unsigned)nmulti, BLOCK, 0, st>>>(cstart, nmulti, owner);
+    MGCD_LAUNCHED();
+    sp = AggSplit{multi, nmulti, cstart, owner, nchunks, a.take<Pair>(nchunks * k)};
+  } else if (nmulti > 0) {
     // groups of 64 chunks per long stream
     int64_t *ng = a.take<int64_t>(nmulti);
     int64_t *gstart = a.take<int64_t>(nmulti + 1);
@@ -1078,9 +1188,9 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   }
   AggStreams s{g, D, mem, mstart, P, rs, skey, sw};
   switch (mode) {
-    case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, bk, waves, lg, L, rows, rcount, corder, m, (int64_t)hc[8], st); break;
-    case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, bk, waves, lg, L, rows, rcount, corder, m, (int64_t)hc[8], st); break;
-    case MODE_STD: agg_mg_k<MODE_STD>(k, s, bk, waves, lg, L, rows, rcount, corder, m, (int64_t)hc[8], st); break;
+    case MODE_ALG1: agg_mg_k<MODE_ALG1>(k, s, bk, waves, lg, sp, L, rows, rcount, corder, (int64_t)hc[0], (int64_t)hc[8], st); break;
+    case MODE_UNCOND: agg_mg_k<MODE_UNCOND>(k, s, bk, waves, lg, sp, L, rows, rcount, corder, (int64_t)hc[0], (int64_t)hc[8], st); break;
+    case MODE_STD: agg_mg_k<MODE_STD>(k, s, bk, waves, lg, sp, L, rows, rcount, corder, (int64_t)hc[0], (int64_t)hc[8], st); break;
     default: throw Error(-6, "unknown sketch mode");
   }
   int64_t total = 0;
@@ -1139,6 +1249,10 @@ size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L, bo
   const int64_t Lc = L > 0 ? L : 1;
   const int64_t nm = nnz / (64 * Lc) + 1, chunks = nnz / Lc + nm + 1;
   b += (size_t)(nm + 1) * 16 + scan_ws_bytes(nm) + (size_t)chunks * (4 + (size_t)k * sizeof(Pair)) + 8192;
+  if (k > 16) {  // split streams of the 32/64-slot sketch: more than max(L, WAVE_SPLIT) positions
+    const int64_t nw = nnz / (Lc > WAVE_SPLIT ? Lc : WAVE_SPLIT) + 1, cw = nnz / Lc + nw + 1;
+    b += (size_t)(nw + 1) * 16 + scan_ws_bytes(nw) + (size_t)cw * (4 + (size_t)k * sizeof(Pair)) + 8192;
+  }
   b += (size_t)n * k * sizeof(Pair) + (size_t)n * 4 + 4096;  // rows, rcount
   b += (size_t)nnz * 8 + (size_t)n * 8 + 4096;               // laid-out streams, row positions
   if (symmetric) {

@@ -330,7 +330,8 @@ def test_wave_split_rows(mg, k, mode, L):
     """At k = 32/64, rows of more than max(L, 512) entries are sketched one wave per
     chunk and merged level by level on the device: labels, gains and counters equal the
     oracle's for LPA, Louvain, 1-scan LPA and the refinement sweep, with neighbour
-    labels from 20 communities (loss-free hub sketches) and from 3,000 (lossy)."""
+    labels from 20 communities (loss-free hub sketches) and from 3,000 (lossy); the
+    aggregation of streams longer than max(L, 512) positions likewise."""
     g = _hub_graph(77)
     dg = mg.to_device(g)
     rng = np.random.default_rng(zlib.crc32(f"split-{k}-{mode}-{L}".encode()))
@@ -352,6 +353,16 @@ def test_wave_split_rows(mg, k, mode, L):
     R = mg.refine(dg, _t(bound), mode=MODES[mode], k=k, chunk_len=L)
     eR = oracle.refine(g, bound, mode=MODES[mode], k=k, chunk_len=L)
     assert np.array_equal(_np(R), eR)
+    # aggregation: community streams longer than max(L, 512) positions are split the same way
+    for ncomm in (5, 300):
+        u, D = np.unique(rng.integers(0, ncomm, size=g.n), return_inverse=True)
+        for symmetric in (False, True):
+            off, idx, ww = mg.aggregate(dg, _t(D), len(u), symmetric, mode=MODES[mode], k=k,
+                                        chunk_len=L)
+            e = oracle.aggregate(g, D.astype(np.int32), len(u), mode=MODES[mode], k=k,
+                                 chunk_len=L, symmetric=symmetric)
+            assert np.array_equal(off, e.offsets), (ncomm, symmetric)
+            assert np.array_equal(idx, e.indices) and np.array_equal(ww, e.weights)
 
 
 @pytest.mark.parametrize("algo", ["lpa", "louvain"])

@@ -241,12 +241,49 @@ void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, Arena &a
 
 // ---- canonical labels ----------------------------------------------------------------
 
-__global__ void k_min_member(const int32_t *C, int32_t n, int32_t *minv) {
-  int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (v < n) {
-    int32_t *m = &minv[C[v]];
-    if (*m > (int32_t)v) atomicMin(m, (int32_t)v);  // skip the atomic once a smaller id won
+// Per-workgroup combining of (key, value) updates before the global atomics: an LDS
+// open-addressing table of 2 * BLOCK slots (at most BLOCK keys, so probing ends), then
+// one global atomic per distinct key of the workgroup.  Without it, a community that
+// holds most vertices serialises its updates on one address.  MIN: minimum, else sum.
+// Every thread of the workgroup calls it (valid: the thread has an update).
+template <bool MIN>
+__device__ inline void block_combine(bool valid, uint32_t key, uint32_t val, uint32_t *out) {
+  constexpr uint32_t CAP = 2 * BLOCK;
+  __shared__ uint32_t tk[CAP], tv[CAP];
+  for (uint32_t x = threadIdx.x; x < CAP; x += BLOCK) {
+    tk[x] = 0xFFFFFFFFu;
+    tv[x] = MIN ? 0xFFFFFFFFu : 0u;
   }
+  __syncthreads();
+  if (valid) {
+    uint32_t h = (key * 2654435761u) & (CAP - 1);
+    while (true) {
+      const uint32_t prev = atomicCAS(&tk[h], 0xFFFFFFFFu, key);
+      if (prev == 0xFFFFFFFFu || prev == key) break;
+      h = (h + 1) & (CAP - 1);
+    }
+    if (MIN)
+      atomicMin(&tv[h], val);
+    else
+      atomicAdd(&tv[h], val);
+  }
+  __syncthreads();
+  for (uint32_t x = threadIdx.x; x < CAP; x += BLOCK) {
+    const uint32_t k = tk[x];
+    if (k == 0xFFFFFFFFu) continue;
+    if (MIN) {
+      if (out[k] > tv[x]) atomicMin(&out[k], tv[x]);  // skip once a smaller value won
+    } else if (tv[x]) {
+      atomicAdd(&out[k], tv[x]);
+    }
+  }
+}
+
+// Smallest member id of every community (ids are non-negative, so unsigned order).
+__global__ void __launch_bounds__(BLOCK) k_min_member(const int32_t *C, int32_t n, int32_t *minv) {
+  const int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const bool ok = v < n;
+  block_combine<true>(ok, ok ? (uint32_t)C[v] : 0u, (uint32_t)v, reinterpret_cast<uint32_t *>(minv));
 }
 __global__ void k_is_first(const int32_t *C, const int32_t *minv, int32_t n, uint32_t *first) {
   int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -318,9 +355,11 @@ __global__ void __launch_bounds__(BLOCK)
   }
 }
 
-__global__ void k_comm_tot(const int32_t *C, const uint32_t *K, int32_t n, uint32_t *tot) {
-  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i < n) atomicAdd(&tot[C[i]], K[i]);
+__global__ void __launch_bounds__(BLOCK)
+    k_comm_tot(const int32_t *C, const uint32_t *K, int32_t n, uint32_t *tot) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const bool ok = i < n;
+  block_combine<false>(ok, ok ? (uint32_t)C[i] : 0u, ok ? K[i] : 0u, tot);
 }
 
 __global__ void __launch_bounds__(BLOCK)
@@ -743,19 +782,39 @@ __global__ void k_heads(const uint64_t *ks, int64_t n, uint32_t *head) {
   if (e < n) head[e] = (e == 0 || ks[e - 1] != ks[e]) ? 1u : 0u;
 }
 
+// Add every row's number of run heads among this wave's lanes to rowcnt.  The keys
+// are sorted, so one row's lanes are consecutive: the first head of each row segment
+// adds the segment's count (one atomic per row and wave rather than one per head,
+// which serialised on the rows of hub communities).  Every lane of the wave calls it.
+__device__ inline void count_heads(bool head, uint32_t row, uint32_t *rowcnt) {
+  const int lane = lane_id();
+  const uint32_t prev = __shfl_up(row, 1);
+  const uint64_t seg_start = __ballot(lane == 0 || row != prev);  // bit 0 always set
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes 0..lane
+  const int s = 63 - __clzll(seg_start & upto);                     // this segment's start
+  const uint64_t later = seg_start & ~upto;                          // later segment starts
+  const uint64_t seg = (later ? ((1ull << __builtin_ctzll(later)) - 1) : ~0ull) & ~((1ull << s) - 1);
+  const uint64_t sh = heads & seg;
+  if (head && lane == __builtin_ctzll(sh)) atomicAdd(&rowcnt[row], (uint32_t)__popcll(sh));
+}
+
 // Runs have at most two entries (forward and reversed): keep the larger value.
 __global__ void k_dedupe_max(const uint64_t *ks, const uint32_t *vs, const uint32_t *head,
                              const int64_t *rid, int64_t n, int b, int32_t *idx, uint32_t *w,
                              uint32_t *rowcnt) {
-  int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (e >= n || !head[e]) return;
-  uint32_t v = vs[e];
-  if (e + 1 < n && ks[e + 1] == ks[e]) v = vs[e + 1] > v ? vs[e + 1] : v;
-  int64_t u = rid[e];
-  uint64_t mask = (b >= 64) ? ~0ull : ((1ull << b) - 1);
-  idx[u] = (int32_t)(ks[e] & mask);
-  w[u] = v;
-  atomicAdd(&rowcnt[(uint32_t)(ks[e] >> b)], 1u);
+  const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const bool h = e < n && head[e];
+  const uint64_t key = e < n ? ks[e] : ~0ull;  // every lane's row keeps a row's lanes together
+  if (h) {
+    uint32_t v = vs[e];
+    if (e + 1 < n && ks[e + 1] == key) v = vs[e + 1] > v ? vs[e + 1] : v;
+    const int64_t u = rid[e];
+    const uint64_t mask = (b >= 64) ? ~0ull : ((1ull << b) - 1);
+    idx[u] = (int32_t)(key & mask);
+    w[u] = v;
+  }
+  count_heads(h, (uint32_t)(key >> b), rowcnt);
 }
 
 // Exact aggregation: one key (D[i], D[j]) per CSR entry, SF_TILE entries per
@@ -825,10 +884,10 @@ __global__ void __launch_bounds__(BLOCK)
     if (head) {
       uint64_t mask = (1ull << b) - 1;
       idx[u] = (int32_t)(key & mask);
-      atomicAdd(&rowcnt[(uint32_t)(key >> b)], 1u);
     }
     if (next_head) atomicAdd(&w[u], (uint32_t)(incl - (start > 0 ? before : 0ull)));
   }
+  count_heads(head, (uint32_t)(key >> b), rowcnt);
 }
 
 // ---- aggregation driver -----------------------------------------------------------------

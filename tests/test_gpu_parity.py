@@ -201,10 +201,22 @@ def test_workspace_too_small(mg):
 
 
 @pytest.mark.parametrize("seed", range(4))
-def test_modularity_parity(mg, seed):
+@pytest.mark.parametrize("labels", ["50", "one", "giant", "distinct"])
+def test_modularity_parity(mg, seed, labels):
+    """Q against the oracle for 50 random communities, a single community, one giant
+    community (90 % of the vertices) among singletons, and all vertices apart (the
+    per-workgroup combining of community totals: one key, few keys, all distinct)."""
     g = synth.rmat(scale=12, edge_factor=8, seed=20 + seed)
     rng = np.random.default_rng(seed)
-    C = rng.integers(0, 50, size=g.n).astype(np.int32)
+    if labels == "50":
+        C = rng.integers(0, 50, size=g.n)
+    elif labels == "one":
+        C = np.zeros(g.n)
+    elif labels == "giant":
+        C = np.where(rng.random(g.n) < 0.9, 7, np.arange(g.n))
+    else:
+        C = rng.permutation(g.n)
+    C = C.astype(np.int32)
     q = mg.modularity(mg.to_device(g), _t(C))
     assert q_close(q, oracle.modularity(g, C))
 

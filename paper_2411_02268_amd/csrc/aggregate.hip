@@ -62,9 +62,49 @@ int32_t renumber(const int32_t *C, int32_t n, int32_t *D, Arena &a, hipStream_t 
   return (int32_t)m;
 }
 
-__global__ void k_group_sums(const int32_t *D, const uint32_t *K, uint32_t *Kout, int32_t n) {
-  int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i < n && D[i] >= 0) atomicAdd(&Kout[D[i]], K[i]);
+// Per-workgroup combining of (key, value) updates before the global atomics: an LDS
+// open-addressing table of 2 * BLOCK slots (at most BLOCK keys, so probing ends), then
+// one global atomic per distinct key of the workgroup.  Without it, a community that
+// holds most vertices serialises its updates on one address.  MIN: minimum, else sum.
+// Every thread of the workgroup calls it (valid: the thread has an update).
+template <bool MIN>
+__device__ inline void block_combine(bool valid, uint32_t key, uint32_t val, uint32_t *out) {
+  constexpr uint32_t CAP = 2 * BLOCK;
+  __shared__ uint32_t tk[CAP], tv[CAP];
+  for (uint32_t x = threadIdx.x; x < CAP; x += BLOCK) {
+    tk[x] = 0xFFFFFFFFu;
+    tv[x] = MIN ? 0xFFFFFFFFu : 0u;
+  }
+  __syncthreads();
+  if (valid) {
+    uint32_t h = (key * 2654435761u) & (CAP - 1);
+    while (true) {
+      const uint32_t prev = atomicCAS(&tk[h], 0xFFFFFFFFu, key);
+      if (prev == 0xFFFFFFFFu || prev == key) break;
+      h = (h + 1) & (CAP - 1);
+    }
+    if (MIN)
+      atomicMin(&tv[h], val);
+    else
+      atomicAdd(&tv[h], val);
+  }
+  __syncthreads();
+  for (uint32_t x = threadIdx.x; x < CAP; x += BLOCK) {
+    const uint32_t k = tk[x];
+    if (k == 0xFFFFFFFFu) continue;
+    if (MIN) {
+      if (out[k] > tv[x]) atomicMin(&out[k], tv[x]);  // skip once a smaller value won
+    } else if (tv[x]) {
+      atomicAdd(&out[k], tv[x]);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    k_group_sums(const int32_t *D, const uint32_t *K, uint32_t *Kout, int32_t n) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int32_t d = i < n ? D[i] : -1;
+  block_combine<false>(d >= 0, d >= 0 ? (uint32_t)d : 0u, d >= 0 ? K[i] : 0u, Kout);
 }
 
 void launch_group_sums(const int32_t *D, const uint32_t *K, uint32_t *Kout, int32_t n, int32_t m,
@@ -240,44 +280,6 @@ void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, Arena &a
 }
 
 // ---- canonical labels ----------------------------------------------------------------
-
-// Per-workgroup combining of (key, value) updates before the global atomics: an LDS
-// open-addressing table of 2 * BLOCK slots (at most BLOCK keys, so probing ends), then
-// one global atomic per distinct key of the workgroup.  Without it, a community that
-// holds most vertices serialises its updates on one address.  MIN: minimum, else sum.
-// Every thread of the workgroup calls it (valid: the thread has an update).
-template <bool MIN>
-__device__ inline void block_combine(bool valid, uint32_t key, uint32_t val, uint32_t *out) {
-  constexpr uint32_t CAP = 2 * BLOCK;
-  __shared__ uint32_t tk[CAP], tv[CAP];
-  for (uint32_t x = threadIdx.x; x < CAP; x += BLOCK) {
-    tk[x] = 0xFFFFFFFFu;
-    tv[x] = MIN ? 0xFFFFFFFFu : 0u;
-  }
-  __syncthreads();
-  if (valid) {
-    uint32_t h = (key * 2654435761u) & (CAP - 1);
-    while (true) {
-      const uint32_t prev = atomicCAS(&tk[h], 0xFFFFFFFFu, key);
-      if (prev == 0xFFFFFFFFu || prev == key) break;
-      h = (h + 1) & (CAP - 1);
-    }
-    if (MIN)
-      atomicMin(&tv[h], val);
-    else
-      atomicAdd(&tv[h], val);
-  }
-  __syncthreads();
-  for (uint32_t x = threadIdx.x; x < CAP; x += BLOCK) {
-    const uint32_t k = tk[x];
-    if (k == 0xFFFFFFFFu) continue;
-    if (MIN) {
-      if (out[k] > tv[x]) atomicMin(&out[k], tv[x]);  // skip once a smaller value won
-    } else if (tv[x]) {
-      atomicAdd(&out[k], tv[x]);
-    }
-  }
-}
 
 // Smallest member id of every community (ids are non-negative, so unsigned order).
 __global__ void __launch_bounds__(BLOCK) k_min_member(const int32_t *C, int32_t n, int32_t *minv) {

@@ -1006,21 +1006,6 @@ __device__ inline uint32_t hash_slot(uint32_t c, uint32_t mask) {
   return (c * 0x9E3779B1u) & mask;  // Fibonacci hashing, low bits
 }
 
-// A table slot filled by other threads' atomics: global tables are read at device
-// scope (past the CU's L1), LDS tables directly.
-template <bool GLOBAL>
-__device__ inline Pair load_slot(Pair *p) {
-  if constexpr (GLOBAL) {
-    uint32_t k = __hip_atomic_load(&p->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t v = __hip_atomic_load(&p->val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return Pair{k, v};
-  } else {
-    return *p;
-  }
-}
-
-// Workgroup per vertex with an open-addressing table (linear probing) in LDS
-// (CAP slots) or, when GLOBAL, in this vertex's region of global memory.
 // Exact mode, tier 1 (rows of up to EXACT_T1_MAX entries): one wave per row with an
 // LDS open-addressing table of its own, sized to the row (the smallest power of two
 // >= 2 * its length, 64 .. 1024 slots), so a block holds four rows instead of one.
@@ -1100,12 +1085,12 @@ __global__ void __launch_bounds__(BLOCK)
   flush_counters(a, ct);
 }
 
-template <int ALGO, int CAP, bool GLOBAL, bool SMALL = false>
-__global__ void __launch_bounds__(BLOCK)
-    k_exact_table(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
-                  Pair *htab, uint32_t *hpos) {
-  __shared__ Pair ltab[GLOBAL ? 1 : CAP];
-  __shared__ uint32_t lpos[GLOBAL || !SMALL ? 1 : CAP];  // small table: first row position per slot
+// Exact mode, tier 2: a workgroup per vertex with an open-addressing table (linear
+// probing) of CAP slots in LDS.
+template <int ALGO, int CAP, bool SMALL = false>
+__global__ void __launch_bounds__(BLOCK) k_exact_table(SweepArgs a, const int32_t *__restrict__ list) {
+  __shared__ Pair tab[CAP];
+  __shared__ uint32_t pos[SMALL ? CAP : 1];  // small table: first row position per slot
   __shared__ uint32_t kd_s;
   __shared__ int32_t bc[4];
   __shared__ int64_t bg[4];
@@ -1116,25 +1101,13 @@ __global__ void __launch_bounds__(BLOCK)
     return;
   }
   const int64_t lo = a.g.off[i], hi = a.g.off[i + 1];
-  Pair *tab;
-  uint32_t *pos;
-  uint32_t cap;
-  if (GLOBAL) {
-    tab = htab + hbase[blockIdx.x];
-    pos = hpos + hbase[blockIdx.x];
-    cap = (uint32_t)(hbase[blockIdx.x + 1] - hbase[blockIdx.x]);
-  } else {
-    tab = ltab;
-    pos = lpos;
-    cap = CAP;
-  }
+  constexpr uint32_t cap = CAP;
   constexpr bool small = SMALL;  // keys are small-table slots (a.small_slots of them)
   for (uint32_t x = t; x < cap; x += BLOCK) {
     tab[x] = Pair{EMPTY, 0u};
     if (small) pos[x] = 0xFFFFFFFFu;
   }
   if (t == 0) kd_s = 0;
-  if (GLOBAL) __threadfence();
   __syncthreads();
   const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
   const uint32_t mask = cap - 1;
@@ -1173,12 +1146,11 @@ __global__ void __launch_bounds__(BLOCK)
       }
     }
   }
-  if (GLOBAL) __threadfence();
   __syncthreads();
   const int32_t d = community_of_self<ALGO>(a, i);
   const uint32_t sd = slot_of(a, (uint32_t)d);
   for (uint32_t x = t; x < cap; x += BLOCK) {
-    Pair p = load_slot<GLOBAL>(&tab[x]);
+    Pair p = tab[x];
     if (p.key == sd) kd_s = p.val;
   }
   __syncthreads();
@@ -1189,12 +1161,11 @@ __global__ void __launch_bounds__(BLOCK)
   const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
   const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
   for (uint32_t x = t; x < cap; x += BLOCK) {
-    Pair p = load_slot<GLOBAL>(&tab[x]);
+    Pair p = tab[x];
     const bool present = p.key != EMPTY;
     if (small && present) {
       // the slot stands for its first key: the key of its earliest row entry
-      const uint32_t f = GLOBAL ? __hip_atomic_load(&pos[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                : pos[x];
+      const uint32_t f = pos[x];
       p.key = stream_key<ALGO>(a, i, a.g.idx[lo + f], bi);
     }
     const uint32_t sc = ALGO == ALGO_LPA ? 0u : a.Sig[present ? (int32_t)p.key : d];
@@ -1225,6 +1196,143 @@ __global__ void __launch_bounds__(BLOCK)
     if (ct.moved) atomicAdd(&a.ctr[0], (unsigned long long)ct.moved);
     if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
     if (ct.sumG) atomicAdd(&a.ctr[2], (unsigned long long)ct.sumG);
+  }
+}
+
+// Exact mode, rows of more than exact_t2 entries: a global open-addressing table per
+// row (hbase), filled by one workgroup per segment of GSEG entries (global atomics,
+// so the segments of one row insert concurrently), then one workgroup per row scores
+// the slots, decides and clears the table for the next sweep (the tables are cleared
+// once when the schedule is built).  Same keys, sums, positions and decision as
+// k_exact_table.
+template <int ALGO, bool SMALL>
+__global__ void __launch_bounds__(BLOCK)
+    k_gtab_insert(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
+                  const int64_t *__restrict__ sstart, const int32_t *__restrict__ sowner, Pair *htab,
+                  uint32_t *hpos) {
+  const int t = threadIdx.x;
+  const int64_t sg = blockIdx.x;
+  const int32_t r = sowner[sg];
+  const int32_t i = list[r];
+  if (frozen(a, i)) return;  // block-uniform
+  const int64_t rlo = a.g.off[i], rhi = a.g.off[i + 1];
+  const int64_t lo = rlo + (sg - sstart[r]) * GSEG;
+  const int64_t hi = lo + GSEG < rhi ? lo + GSEG : rhi;
+  Pair *tab = htab + hbase[r];
+  uint32_t *pos = hpos + hbase[r];
+  const uint32_t mask = (uint32_t)(hbase[r + 1] - hbase[r]) - 1;
+  const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
+  constexpr int U = 4;  // entries per thread and round, loads and gathers issued together
+  for (int64_t e0 = lo + t; e0 < hi; e0 += U * BLOCK) {
+    uint32_t cs[U], ws[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + (int64_t)u * BLOCK;
+      const bool v = e < hi;
+      const int64_t es = v ? e : lo;
+      const int32_t j = a.g.idx[es];
+      uint32_t c;
+      if (ALGO == ALGO_REFINE)
+        c = a.bound[j] == bi ? (uint32_t)j : EMPTY;
+      else
+        c = (uint32_t)a.C[j];
+      cs[u] = c | ((v && j != i) ? 0u : EMPTY);  // self-loops are skipped
+      ws[u] = a.g.w[es];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (cs[u] == EMPTY) continue;
+      const uint32_t c = slot_of(a, cs[u]);
+      uint32_t h = hash_slot(c, mask);
+      while (true) {
+        const uint32_t prev = atomicCAS(&tab[h].key, EMPTY, c);
+        if (prev == EMPTY || prev == c) {
+          atomicAdd(&tab[h].val, ws[u]);
+          if (SMALL) atomicMin(&pos[h], (uint32_t)(e0 + (int64_t)u * BLOCK - rlo));
+          break;
+        }
+        h = (h + 1) & mask;
+      }
+    }
+  }
+}
+
+template <int ALGO, bool SMALL>
+__global__ void __launch_bounds__(BLOCK)
+    k_gtab_decide(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
+                  Pair *htab, uint32_t *hpos) {
+  __shared__ uint32_t kd_s;
+  __shared__ int32_t bc[BLOCK / WAVE];
+  __shared__ int64_t bg[BLOCK / WAVE];
+  const int t = threadIdx.x;
+  const int32_t r = blockIdx.x;
+  const int32_t i = list[r];
+  if (frozen(a, i)) {  // block-uniform; the table was not filled
+    if (t == 0) a.Cnew[i] = community_of_self<ALGO>(a, i);
+    return;
+  }
+  const int64_t lo = a.g.off[i];
+  Pair *tab = htab + hbase[r];
+  uint32_t *pos = hpos + hbase[r];
+  const uint32_t cap = (uint32_t)(hbase[r + 1] - hbase[r]);
+  const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
+  const int32_t d = community_of_self<ALGO>(a, i);
+  const uint32_t sd = slot_of(a, (uint32_t)d);
+  if (t == 0) kd_s = 0;
+  __syncthreads();
+  for (uint32_t x = t; x < cap; x += BLOCK)
+    if (tab[x].key == sd) kd_s = tab[x].val;  // one slot holds sd
+  __syncthreads();
+  const uint32_t kd = kd_s;
+  int32_t best = -1;
+  int64_t bestG = 0;
+  const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
+  const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+  const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+  for (uint32_t x = t; x < cap; x += BLOCK) {
+    Pair p = tab[x];
+    const bool present = p.key != EMPTY;
+    if (SMALL && present) p.key = stream_key<ALGO>(a, i, a.g.idx[lo + pos[x]], bi);
+    const uint32_t sc = ALGO == ALGO_LPA ? 0u : a.Sig[present ? (int32_t)p.key : d];
+    consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)p.key, p.val, sc, present, best, bestG);
+  }
+  // block arg-max: larger gain first, then lower community id
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int32_t ob = __shfl_xor(best, o);
+    const int64_t og = __shfl_xor(bestG, o);
+    const bool take = ob >= 0 && (best < 0 || og > bestG || (og == bestG && ob < best));
+    best = take ? ob : best;
+    bestG = take ? og : bestG;
+  }
+  if (lane_id() == 0) {
+    bc[t / WAVE] = best;
+    bg[t / WAVE] = bestG;
+  }
+  __syncthreads();  // every slot has been read: clear the table for the next sweep
+  for (uint32_t x = t; x < cap; x += BLOCK) {
+    tab[x] = Pair{EMPTY, 0u};
+    if (SMALL) pos[x] = 0xFFFFFFFFu;
+  }
+  if (t == 0) {
+    for (int q = 1; q < BLOCK / WAVE; ++q) {
+      const bool take = bc[q] >= 0 && (best < 0 || bg[q] > bestG || (bg[q] == bestG && bc[q] < best));
+      best = take ? bc[q] : best;
+      bestG = take ? bg[q] : bestG;
+    }
+    Counters ct;
+    finish<ALGO>(a, i, d, best, bestG, ct);
+    if (ct.moved) atomicAdd(&a.ctr[0], (unsigned long long)ct.moved);
+    if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
+    if (ct.sumG) atomicAdd(&a.ctr[2], (unsigned long long)ct.sumG);
+  }
+}
+
+__global__ void k_gtab_clear(Pair *htab, uint32_t *hpos, int64_t n) {
+  const int64_t x = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (x < n) {
+    htab[x] = Pair{EMPTY, 0u};
+    hpos[x] = 0xFFFFFFFFu;
   }
 }
 
@@ -1345,6 +1453,8 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
   if (mode == MODE_EXACT) {
     b += (size_t)(n + 1) * 8 + scan_ws_bytes(n) + 1024;  // hash bases
     b += (size_t)(4 * nnz + 64) * (sizeof(Pair) + 4) + 2048;  // tables (cap <= 4*deg), positions
+    const int64_t sl = nnz / GSEG + 2;  // rows of more than GSEG entries, and their segments
+    b += (size_t)sl * (8 + 8 + 4) * 2 + scan_ws_bytes(sl) + 4096;     // counts, starts, owners
   } else {
     // a long row has more than one chunk, so more than L entries: at most nnz / L
     // long rows, at most 2 nnz / L + 1 of their chunks, and groups of 64 chunks at
@@ -1423,11 +1533,22 @@ void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a
       k_hash_caps<<<grid_for(c3), BLOCK, 0, st>>>(g.off, s.tier[3], c3, caps);
       MGCD_LAUNCHED();
       scan_i64(caps, s.hbase, c3, s.hbase + c3, a, st);
-      int64_t tot = 0;
+      int64_t *nseg = a.take<int64_t>(c3);
+      s.sstart = a.take<int64_t>(c3 + 1);
+      k_chunk_counts<<<grid_for(c3), BLOCK, 0, st>>>(g.off, s.tier[3], c3, GSEG, nseg);
+      MGCD_LAUNCHED();
+      scan_i64(nseg, s.sstart, c3, s.sstart + c3, a, st);
+      int64_t tot = 0;  // table slots and segments in one host round trip
       MGCD_HIP(hipMemcpyAsync(&tot, s.hbase + c3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      MGCD_HIP(hipMemcpyAsync(&s.nseg, s.sstart + c3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
       MGCD_HIP(hipStreamSynchronize(st));
+      s.sowner = a.take<int32_t>(s.nseg);
+      k_chunk_owner<<<(unsigned)c3, BLOCK, 0, st>>>(s.sstart, c3, s.sowner);
+      MGCD_LAUNCHED();
       s.htab = a.take<Pair>(tot);
       s.hpos = a.take<uint32_t>(tot);
+      k_gtab_clear<<<grid_for(tot), BLOCK, 0, st>>>(s.htab, s.hpos, tot);
+      MGCD_LAUNCHED();
     }
     return;
   }
@@ -1541,14 +1662,15 @@ static void sweep_exact(const SweepArgs &a, const Schedule &s, hipStream_t st, h
     MGCD_LAUNCHED();
   }
   if (s.ntier[2] > 0) {
-    k_exact_table<ALGO, 8192, false, SMALL><<<(unsigned)s.ntier[2], BLOCK, 0, st>>>(a, s.tier[2], nullptr, nullptr,
-                                                                              nullptr);
+    k_exact_table<ALGO, 8192, SMALL><<<(unsigned)s.ntier[2], BLOCK, 0, st>>>(a, s.tier[2]);
     MGCD_LAUNCHED();
   }
   mark(ev, 2, st);
   if (s.ntier[3] > 0) {
-    k_exact_table<ALGO, 1, true, SMALL><<<(unsigned)s.ntier[3], BLOCK, 0, st>>>(a, s.tier[3], s.hbase, s.htab,
-                                                                          s.hpos);
+    k_gtab_insert<ALGO, SMALL><<<(unsigned)s.nseg, BLOCK, 0, st>>>(a, s.tier[3], s.hbase, s.sstart, s.sowner,
+                                                                  s.htab, s.hpos);
+    MGCD_LAUNCHED();
+    k_gtab_decide<ALGO, SMALL><<<(unsigned)s.ntier[3], BLOCK, 0, st>>>(a, s.tier[3], s.hbase, s.htab, s.hpos);
     MGCD_LAUNCHED();
   }
   mark(ev, 3, st);

@@ -118,6 +118,9 @@ struct Schedule {
   int64_t *hbase = nullptr;   // [ntier[3]+1] global hash region of each tier-3 vertex
   Pair *htab = nullptr;
   uint32_t *hpos = nullptr;   // small table: first row position of each global slot
+  int64_t *sstart = nullptr;  // [ntier[3]+1] first insert segment (GSEG entries) of each row
+  int32_t *sowner = nullptr;  // [nseg] tier-3 index of each segment
+  int64_t nseg = 0;
 };
 
 // What a level's schedule depends on.  mode, k and L change results; the rest only
@@ -137,6 +140,8 @@ struct SchedParams {
                       // wave each
 };
 constexpr int64_t EXACT_T1_MAX = 512, EXACT_T2_MAX = 4096;
+// exact mode, global tables: entries inserted by one workgroup
+constexpr int64_t GSEG = 4096;
 // K = 32 / 64: rows of more than max(L, WAVE_SPLIT) entries are split over one wave per
 // chunk (schedule only: the merge tree and the results are those of one wave per row)
 constexpr int64_t WAVE_SPLIT = 512;

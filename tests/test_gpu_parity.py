@@ -322,6 +322,11 @@ def test_wave_sketch_deep_merge_tree(mg, k):
     assert np.array_equal(ww, e.weights)
 
 
+# exact_small / exact_lds / exact_lds_big of (2, 8, 24) put rows on every table tier
+# (registers, 1,024- and 8,192-slot LDS tables, global tables)
+TIERS = {"default": {}, "all_tiers": dict(exact_small=2, exact_lds=8, exact_lds_big=24)}
+
+
 def _hub_graph(seed):
     """6,000 vertices; five hubs of 5,000, 2,049, 1,300, 701 and 513 random neighbours
     (chunk counts that are not powers of two) plus 8,000 random edges, weights 1..8."""
@@ -375,6 +380,37 @@ def test_wave_split_rows(mg, k, mode, L):
                                  chunk_len=L, symmetric=symmetric)
             assert np.array_equal(off, e.offsets), (ncomm, symmetric)
             assert np.array_equal(idx, e.indices) and np.array_equal(ww, e.weights)
+
+
+@pytest.mark.parametrize("mode,k", [("exact", 8), ("small", 3), ("small", 4096)])
+@pytest.mark.parametrize("tiers", sorted(TIERS))
+def test_exact_segmented_rows(mg, mode, k, tiers):
+    """Exact and small-table modes with rows of more than 4,096 entries: a row's global
+    table filled by several workgroups (segments of 4,096 entries) and decided by one.
+    Sweeps, the refinement sweep and whole Louvain, Leiden and LPA runs (a level's
+    sweeps reuse the tables, which each decision clears) equal the oracle's."""
+    g = _hub_graph(78)
+    dg = mg.to_device(g)
+    gm = mg.MODE_EXACT if mode == "exact" else mg.MODE_SMALL
+    om = oracle.MODE_EXACT if mode == "exact" else oracle.MODE_SMALL
+    rng = np.random.default_rng(zlib.crc32(f"gseg-{mode}-{k}-{tiers}".encode()))
+    for ncomm in (20, 3000):
+        C = rng.integers(0, ncomm, size=g.n).astype(np.int32)
+        for algo, oalgo in ((mg.ALGO_LPA, oracle.ALGO_LPA), (mg.ALGO_LOUVAIN, oracle.ALGO_MOVE)):
+            Cn, gain, ctr = mg.move_sweep(dg, algo, _t(C), 0, mode=gm, k=k, **TIERS[tiers])
+            eC, eg = oracle.move_sweep(g, oalgo, C, mode=om, k=k)
+            assert np.array_equal(_np(Cn), eC), (algo, ncomm)
+            if algo == mg.ALGO_LOUVAIN:
+                assert np.array_equal(_np(gain), eg)
+                assert ctr == [int((eC != C).sum()), int((eg > 0).sum()), int(eg.sum())]
+    bound = rng.integers(0, 3, size=g.n).astype(np.int32)
+    R = mg.refine(dg, _t(bound), mode=gm, k=k, **TIERS[tiers])
+    assert np.array_equal(_np(R), oracle.refine(g, bound, mode=om, k=k))
+    for algo in ("louvain", "leiden", "lpa"):
+        lab, st = getattr(mg, algo)(dg, mode=gm, k=k, **TIERS[tiers])
+        elab, est = getattr(oracle, algo)(g, mode=om, k=k)
+        assert np.array_equal(_np(lab), elab), algo
+        assert st["iterations"] == est.iterations
 
 
 @pytest.mark.parametrize("algo", ["lpa", "louvain"])
@@ -473,10 +509,6 @@ def test_boyer_moore_mode(mg):
 # ---------------------------------------------------------------------------------
 # the small mod-based table (Appendix A.2)
 # ---------------------------------------------------------------------------------
-
-# exact_small / exact_lds / exact_lds_big of (2, 8, 24) put rows on every table tier
-# (registers, 1,024- and 8,192-slot LDS tables, global tables)
-TIERS = {"default": {}, "all_tiers": dict(exact_small=2, exact_lds=8, exact_lds_big=24)}
 
 
 @pytest.mark.gpu

@@ -1201,10 +1201,11 @@ __global__ void __launch_bounds__(BLOCK) k_exact_table(SweepArgs a, const int32_
 
 // Exact mode, rows of more than exact_t2 entries: a global open-addressing table per
 // row (hbase), filled by one workgroup per segment of GSEG entries (global atomics,
-// so the segments of one row insert concurrently), then one workgroup per row scores
-// the slots, decides and clears the table for the next sweep (the tables are cleared
-// once when the schedule is built).  Same keys, sums, positions and decision as
-// k_exact_table.
+// so the segments of one row insert concurrently); then K_{i->d} by a probe, one
+// workgroup per TSEG table slots scores them and clears them for the next sweep (the
+// tables are cleared once when the schedule is built), and one thread per row
+// combines the segments' best (the rule is associative) and decides.  Same keys,
+// sums, positions and decision as k_exact_table.
 template <int ALGO, bool SMALL>
 __global__ void __launch_bounds__(BLOCK)
     k_gtab_insert(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
@@ -1257,46 +1258,65 @@ __global__ void __launch_bounds__(BLOCK)
   }
 }
 
+// K_{i->d} of every global-table row, by probing its table for d's key (before any
+// workgroup of k_gtab_scan clears a segment of the table).
+template <int ALGO>
+__global__ void __launch_bounds__(BLOCK)
+    k_gtab_kd(SweepArgs a, const int32_t *__restrict__ list, int64_t count, const int64_t *__restrict__ hbase,
+              const Pair *__restrict__ htab, uint32_t *kdout) {
+  const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= count) return;
+  const int32_t i = list[r];
+  if (frozen(a, i)) return;
+  const Pair *tab = htab + hbase[r];
+  const uint32_t mask = (uint32_t)(hbase[r + 1] - hbase[r]) - 1;
+  const uint32_t sd = slot_of(a, (uint32_t)community_of_self<ALGO>(a, i));
+  uint32_t h = hash_slot(sd, mask), kd = 0;
+  while (true) {  // the table is at most half full, so an EMPTY slot ends the probe
+    const Pair p = tab[h];
+    if (p.key == sd) {
+      kd = p.val;
+      break;
+    }
+    if (p.key == EMPTY) break;
+    h = (h + 1) & mask;
+  }
+  kdout[r] = kd;
+}
+
+// One workgroup per TSEG slots of a row's table: the best candidate among them
+// (larger gain, then lower id) into part[], then the slots are cleared for the next
+// sweep.
 template <int ALGO, bool SMALL>
 __global__ void __launch_bounds__(BLOCK)
-    k_gtab_decide(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
-                  Pair *htab, uint32_t *hpos) {
-  __shared__ uint32_t kd_s;
+    k_gtab_scan(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
+                const int64_t *__restrict__ tstart, const int32_t *__restrict__ towner, Pair *htab,
+                uint32_t *hpos, const uint32_t *__restrict__ kdin, int32_t *pbest, int64_t *pgain) {
   __shared__ int32_t bc[BLOCK / WAVE];
   __shared__ int64_t bg[BLOCK / WAVE];
   const int t = threadIdx.x;
-  const int32_t r = blockIdx.x;
+  const int64_t sg = blockIdx.x;
+  const int32_t r = towner[sg];
   const int32_t i = list[r];
-  if (frozen(a, i)) {  // block-uniform; the table was not filled
-    if (t == 0) a.Cnew[i] = community_of_self<ALGO>(a, i);
-    return;
-  }
+  if (frozen(a, i)) return;  // block-uniform; the table was not filled
   const int64_t lo = a.g.off[i];
-  Pair *tab = htab + hbase[r];
-  uint32_t *pos = hpos + hbase[r];
-  const uint32_t cap = (uint32_t)(hbase[r + 1] - hbase[r]);
+  const int64_t x0 = hbase[r] + (sg - tstart[r]) * TSEG;
+  const int64_t x1 = x0 + TSEG < hbase[r + 1] ? x0 + TSEG : hbase[r + 1];
   const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
   const int32_t d = community_of_self<ALGO>(a, i);
-  const uint32_t sd = slot_of(a, (uint32_t)d);
-  if (t == 0) kd_s = 0;
-  __syncthreads();
-  for (uint32_t x = t; x < cap; x += BLOCK)
-    if (tab[x].key == sd) kd_s = tab[x].val;  // one slot holds sd
-  __syncthreads();
-  const uint32_t kd = kd_s;
+  const uint32_t kd = kdin[r];
   int32_t best = -1;
   int64_t bestG = 0;
   const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
   const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
   const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
-  for (uint32_t x = t; x < cap; x += BLOCK) {
-    Pair p = tab[x];
+  for (int64_t x = x0 + t; x < x1; x += BLOCK) {
+    Pair p = htab[x];
     const bool present = p.key != EMPTY;
-    if (SMALL && present) p.key = stream_key<ALGO>(a, i, a.g.idx[lo + pos[x]], bi);
+    if (SMALL && present) p.key = stream_key<ALGO>(a, i, a.g.idx[lo + hpos[x]], bi);
     const uint32_t sc = ALGO == ALGO_LPA ? 0u : a.Sig[present ? (int32_t)p.key : d];
     consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)p.key, p.val, sc, present, best, bestG);
   }
-  // block arg-max: larger gain first, then lower community id
 #pragma unroll
   for (int o = WAVE / 2; o > 0; o >>= 1) {
     const int32_t ob = __shfl_xor(best, o);
@@ -1309,10 +1329,10 @@ __global__ void __launch_bounds__(BLOCK)
     bc[t / WAVE] = best;
     bg[t / WAVE] = bestG;
   }
-  __syncthreads();  // every slot has been read: clear the table for the next sweep
-  for (uint32_t x = t; x < cap; x += BLOCK) {
-    tab[x] = Pair{EMPTY, 0u};
-    if (SMALL) pos[x] = 0xFFFFFFFFu;
+  __syncthreads();  // every slot of the segment has been read: clear them
+  for (int64_t x = x0 + t; x < x1; x += BLOCK) {
+    htab[x] = Pair{EMPTY, 0u};
+    if (SMALL) hpos[x] = 0xFFFFFFFFu;
   }
   if (t == 0) {
     for (int q = 1; q < BLOCK / WAVE; ++q) {
@@ -1320,12 +1340,36 @@ __global__ void __launch_bounds__(BLOCK)
       best = take ? bc[q] : best;
       bestG = take ? bg[q] : bestG;
     }
-    Counters ct;
-    finish<ALGO>(a, i, d, best, bestG, ct);
-    if (ct.moved) atomicAdd(&a.ctr[0], (unsigned long long)ct.moved);
-    if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
-    if (ct.sumG) atomicAdd(&a.ctr[2], (unsigned long long)ct.sumG);
+    pbest[sg] = best;
+    pgain[sg] = bestG;
   }
+}
+
+// One thread per global-table row: the best over its segments, then the decision.
+template <int ALGO>
+__global__ void __launch_bounds__(BLOCK)
+    k_gtab_finish(SweepArgs a, const int32_t *__restrict__ list, int64_t count,
+                  const int64_t *__restrict__ tstart, const int32_t *__restrict__ pbest,
+                  const int64_t *__restrict__ pgain) {
+  const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  Counters ct;
+  if (r < count) {
+    const int32_t i = list[r];
+    const int32_t d = community_of_self<ALGO>(a, i);
+    if (frozen(a, i)) {
+      a.Cnew[i] = d;
+    } else {
+      int32_t best = -1;
+      int64_t bestG = 0;
+      for (int64_t q = tstart[r]; q < tstart[r + 1]; ++q) {
+        const bool take = pbest[q] >= 0 && (best < 0 || pgain[q] > bestG || (pgain[q] == bestG && pbest[q] < best));
+        best = take ? pbest[q] : best;
+        bestG = take ? pgain[q] : bestG;
+      }
+      finish<ALGO>(a, i, d, best, bestG, ct);
+    }
+  }
+  flush_counters(a, ct);
 }
 
 __global__ void k_gtab_clear(Pair *htab, uint32_t *hpos, int64_t n) {
@@ -1428,6 +1472,11 @@ __global__ void k_chunk_owner(const int64_t *cstart, int64_t nmulti, int32_t *ow
   for (int64_t q = cstart[m] + threadIdx.x; q < cstart[m + 1]; q += BLOCK) owner[q] = (int32_t)m;
 }
 
+__global__ void k_table_segs(const int64_t *hbase, int64_t count, int64_t *nt) {
+  const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (r < count) nt[r] = (hbase[r + 1] - hbase[r] + TSEG - 1) / TSEG;
+}
+
 __global__ void k_hash_caps(const int64_t *off, const int32_t *list, int64_t count, int64_t *cap) {
   int64_t m = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (m >= count) return;
@@ -1455,6 +1504,9 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
     b += (size_t)(4 * nnz + 64) * (sizeof(Pair) + 4) + 2048;  // tables (cap <= 4*deg), positions
     const int64_t sl = nnz / GSEG + 2;  // rows of more than GSEG entries, and their segments
     b += (size_t)sl * (8 + 8 + 4) * 2 + scan_ws_bytes(sl) + 4096;     // counts, starts, owners
+    // table segments (at most table slots / TSEG + rows), their bests; probes per row
+    const int64_t tl = (4 * nnz + 64) / TSEG + (nnz > 0 ? nnz : 1) + 2;
+    b += (size_t)tl * (4 + 4 + 8) + (size_t)(nnz + 2) * (8 + 8 + 4) + scan_ws_bytes(nnz + 2) + 8192;
   } else {
     // a long row has more than one chunk, so more than L entries: at most nnz / L
     // long rows, at most 2 nnz / L + 1 of their chunks, and groups of 64 chunks at
@@ -1538,13 +1590,25 @@ void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a
       k_chunk_counts<<<grid_for(c3), BLOCK, 0, st>>>(g.off, s.tier[3], c3, GSEG, nseg);
       MGCD_LAUNCHED();
       scan_i64(nseg, s.sstart, c3, s.sstart + c3, a, st);
-      int64_t tot = 0;  // table slots and segments in one host round trip
+      int64_t *ntab = a.take<int64_t>(c3);
+      s.tstart = a.take<int64_t>(c3 + 1);
+      k_table_segs<<<grid_for(c3), BLOCK, 0, st>>>(s.hbase, c3, ntab);
+      MGCD_LAUNCHED();
+      scan_i64(ntab, s.tstart, c3, s.tstart + c3, a, st);
+      int64_t tot = 0;  // table slots, insert and scan segments in one host round trip
       MGCD_HIP(hipMemcpyAsync(&tot, s.hbase + c3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
       MGCD_HIP(hipMemcpyAsync(&s.nseg, s.sstart + c3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      MGCD_HIP(hipMemcpyAsync(&s.ntseg, s.tstart + c3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
       MGCD_HIP(hipStreamSynchronize(st));
       s.sowner = a.take<int32_t>(s.nseg);
       k_chunk_owner<<<(unsigned)c3, BLOCK, 0, st>>>(s.sstart, c3, s.sowner);
       MGCD_LAUNCHED();
+      s.towner = a.take<int32_t>(s.ntseg);
+      k_chunk_owner<<<(unsigned)c3, BLOCK, 0, st>>>(s.tstart, c3, s.towner);
+      MGCD_LAUNCHED();
+      s.gkd = a.take<uint32_t>(c3);
+      s.pbest = a.take<int32_t>(s.ntseg);
+      s.pgain = a.take<int64_t>(s.ntseg);
       s.htab = a.take<Pair>(tot);
       s.hpos = a.take<uint32_t>(tot);
       k_gtab_clear<<<grid_for(tot), BLOCK, 0, st>>>(s.htab, s.hpos, tot);
@@ -1670,7 +1734,13 @@ static void sweep_exact(const SweepArgs &a, const Schedule &s, hipStream_t st, h
     k_gtab_insert<ALGO, SMALL><<<(unsigned)s.nseg, BLOCK, 0, st>>>(a, s.tier[3], s.hbase, s.sstart, s.sowner,
                                                                   s.htab, s.hpos);
     MGCD_LAUNCHED();
-    k_gtab_decide<ALGO, SMALL><<<(unsigned)s.ntier[3], BLOCK, 0, st>>>(a, s.tier[3], s.hbase, s.htab, s.hpos);
+    k_gtab_kd<ALGO><<<grid_for(s.ntier[3]), BLOCK, 0, st>>>(a, s.tier[3], s.ntier[3], s.hbase, s.htab, s.gkd);
+    MGCD_LAUNCHED();
+    k_gtab_scan<ALGO, SMALL><<<(unsigned)s.ntseg, BLOCK, 0, st>>>(a, s.tier[3], s.hbase, s.tstart, s.towner,
+                                                                 s.htab, s.hpos, s.gkd, s.pbest, s.pgain);
+    MGCD_LAUNCHED();
+    k_gtab_finish<ALGO><<<grid_for(s.ntier[3]), BLOCK, 0, st>>>(a, s.tier[3], s.ntier[3], s.tstart, s.pbest,
+                                                                s.pgain);
     MGCD_LAUNCHED();
   }
   mark(ev, 3, st);

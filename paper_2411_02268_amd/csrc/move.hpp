@@ -121,6 +121,12 @@ struct Schedule {
   int64_t *sstart = nullptr;  // [ntier[3]+1] first insert segment (GSEG entries) of each row
   int32_t *sowner = nullptr;  // [nseg] tier-3 index of each segment
   int64_t nseg = 0;
+  int64_t *tstart = nullptr;  // [ntier[3]+1] first scan segment (TSEG table slots) of each row
+  int32_t *towner = nullptr;  // [ntseg] tier-3 index of each scan segment
+  int64_t ntseg = 0;
+  uint32_t *gkd = nullptr;    // [ntier[3]] K_{i->d} of each row
+  int32_t *pbest = nullptr;   // [ntseg] best candidate of each scan segment
+  int64_t *pgain = nullptr;   // [ntseg] its gain
 };
 
 // What a level's schedule depends on.  mode, k and L change results; the rest only
@@ -140,8 +146,8 @@ struct SchedParams {
                       // wave each
 };
 constexpr int64_t EXACT_T1_MAX = 512, EXACT_T2_MAX = 4096;
-// exact mode, global tables: entries inserted by one workgroup
-constexpr int64_t GSEG = 4096;
+// exact mode, global tables: entries inserted by one workgroup, slots scored by one
+constexpr int64_t GSEG = 4096, TSEG = 8192;
 // K = 32 / 64: rows of more than max(L, WAVE_SPLIT) entries are split over one wave per
 // chunk (schedule only: the merge tree and the results are those of one wave per row)
 constexpr int64_t WAVE_SPLIT = 512;

@@ -1211,6 +1211,14 @@ __global__ void __launch_bounds__(BLOCK)
     k_gtab_insert(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
                   const int64_t *__restrict__ sstart, const int32_t *__restrict__ sowner, Pair *htab,
                   uint32_t *hpos) {
+  // Each round's U * BLOCK entries are first combined in an LDS table (at most U * BLOCK
+  // keys in 2 * U * BLOCK slots), then every distinct key goes to the global table
+  // once: the entries of a hub row concentrate on a few communities, whose slots
+  // would otherwise serialise the global atomics of all the row's workgroups.
+  constexpr int U = 4;  // entries per thread and round, loads and gathers issued together
+  constexpr uint32_t LCAP = 2 * U * BLOCK;
+  __shared__ uint32_t lk[LCAP], lv[LCAP];
+  __shared__ uint32_t lp[SMALL ? LCAP : 1];
   const int t = threadIdx.x;
   const int64_t sg = blockIdx.x;
   const int32_t r = sowner[sg];
@@ -1223,12 +1231,17 @@ __global__ void __launch_bounds__(BLOCK)
   uint32_t *pos = hpos + hbase[r];
   const uint32_t mask = (uint32_t)(hbase[r + 1] - hbase[r]) - 1;
   const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
-  constexpr int U = 4;  // entries per thread and round, loads and gathers issued together
-  for (int64_t e0 = lo + t; e0 < hi; e0 += U * BLOCK) {
+  for (int64_t b0 = lo; b0 < hi; b0 += U * BLOCK) {  // block-uniform rounds
+    for (uint32_t x = t; x < LCAP; x += BLOCK) {
+      lk[x] = EMPTY;
+      lv[x] = 0u;
+      if (SMALL) lp[x] = 0xFFFFFFFFu;
+    }
+    __syncthreads();
     uint32_t cs[U], ws[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t e = e0 + (int64_t)u * BLOCK;
+      const int64_t e = b0 + t + (int64_t)u * BLOCK;
       const bool v = e < hi;
       const int64_t es = v ? e : lo;
       const int32_t j = a.g.idx[es];
@@ -1244,17 +1257,29 @@ __global__ void __launch_bounds__(BLOCK)
     for (int u = 0; u < U; ++u) {
       if (cs[u] == EMPTY) continue;
       const uint32_t c = slot_of(a, cs[u]);
+      uint32_t h = hash_slot(c, LCAP - 1);
+      while (true) {
+        const uint32_t prev = atomicCAS(&lk[h], EMPTY, c);
+        if (prev == EMPTY || prev == c) break;
+        h = (h + 1) & (LCAP - 1);
+      }
+      atomicAdd(&lv[h], ws[u]);
+      if (SMALL) atomicMin(&lp[h], (uint32_t)(b0 + t + (int64_t)u * BLOCK - rlo));
+    }
+    __syncthreads();
+    for (uint32_t x = t; x < LCAP; x += BLOCK) {
+      const uint32_t c = lk[x];
+      if (c == EMPTY) continue;
       uint32_t h = hash_slot(c, mask);
       while (true) {
         const uint32_t prev = atomicCAS(&tab[h].key, EMPTY, c);
-        if (prev == EMPTY || prev == c) {
-          atomicAdd(&tab[h].val, ws[u]);
-          if (SMALL) atomicMin(&pos[h], (uint32_t)(e0 + (int64_t)u * BLOCK - rlo));
-          break;
-        }
+        if (prev == EMPTY || prev == c) break;
         h = (h + 1) & mask;
       }
+      atomicAdd(&tab[h].val, lv[x]);
+      if (SMALL) atomicMin(&pos[h], lp[x]);
     }
+    __syncthreads();  // the flush has read the table before the next round clears it
   }
 }
 

@@ -1525,13 +1525,15 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
   b += radix_sort_ws_bytes(n) + 4096;
   b += (size_t)n * 4 + 1024;                   // ordered list
   if (mode == MODE_EXACT) {
-    b += (size_t)(n + 1) * 8 + scan_ws_bytes(n) + 1024;  // hash bases
+    // rows on global tables: at most min(n, nnz) (each has an entry)
+    const int64_t c3 = n < nnz ? n : nnz;
+    // per row: table capacity and base, insert-segment count and start, scan-segment
+    // count and start (8 B each), K_{i->d} (4 B); three scans
+    b += (size_t)(c3 + 2) * (6 * 8 + 4) + 3 * scan_ws_bytes(c3 + 1) + 8192;
     b += (size_t)(4 * nnz + 64) * (sizeof(Pair) + 4) + 2048;  // tables (cap <= 4*deg), positions
-    const int64_t sl = nnz / GSEG + 2;  // rows of more than GSEG entries, and their segments
-    b += (size_t)sl * (8 + 8 + 4) * 2 + scan_ws_bytes(sl) + 4096;     // counts, starts, owners
-    // table segments (at most table slots / TSEG + rows), their bests; probes per row
-    const int64_t tl = (4 * nnz + 64) / TSEG + (nnz > 0 ? nnz : 1) + 2;
-    b += (size_t)tl * (4 + 4 + 8) + (size_t)(nnz + 2) * (8 + 8 + 4) + scan_ws_bytes(nnz + 2) + 8192;
+    // insert segments (owner) and scan segments (owner, best, gain)
+    const int64_t ns = nnz / GSEG + c3 + 2, nt = (4 * nnz + 64) / TSEG + c3 + 2;
+    b += (size_t)ns * 4 + (size_t)nt * (4 + 4 + 8) + 4096;
   } else {
     // a long row has more than one chunk, so more than L entries: at most nnz / L
     // long rows, at most 2 nnz / L + 1 of their chunks, and groups of 64 chunks at

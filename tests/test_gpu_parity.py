@@ -413,6 +413,27 @@ def test_exact_segmented_rows(mg, mode, k, tiers):
         assert st["iterations"] == est.iterations
 
 
+@pytest.mark.parametrize("gname", ["er120dense", "rmat11"])
+@pytest.mark.parametrize("mode,k", [("exact", 8), ("small", 5)])
+def test_exact_every_row_on_global_tables(mg, gname, mode, k):
+    """Tier thresholds of 1 put every row of two or more entries on a global table (as
+    many table rows as vertices): the workspace the library reports suffices, and
+    sweeps and whole runs equal the oracle's."""
+    g = graph(gname)
+    dg = mg.to_device(g)
+    gm = mg.MODE_EXACT if mode == "exact" else mg.MODE_SMALL
+    om = oracle.MODE_EXACT if mode == "exact" else oracle.MODE_SMALL
+    kw = dict(exact_small=1, exact_lds=1, exact_lds_big=1)
+    C = np.random.default_rng(3).integers(0, max(2, g.n // 4), size=g.n).astype(np.int32)
+    Cn, gain, _ = mg.move_sweep(dg, mg.ALGO_LOUVAIN, _t(C), 0, mode=gm, k=k, **kw)
+    eC, eg = oracle.move_sweep(g, oracle.ALGO_MOVE, C, mode=om, k=k)
+    assert np.array_equal(_np(Cn), eC) and np.array_equal(_np(gain), eg)
+    for algo in ("louvain", "leiden", "lpa"):
+        lab, _ = getattr(mg, algo)(dg, mode=gm, k=k, **kw)
+        elab, _ = getattr(oracle, algo)(g, mode=om, k=k)
+        assert np.array_equal(_np(lab), elab), algo
+
+
 @pytest.mark.parametrize("algo", ["lpa", "louvain"])
 def test_batched_many_graphs_dirty_workspace(mg, algo):
     """More graphs than one wave of counters, in a workspace full of garbage: every

@@ -435,6 +435,29 @@ def test_exact_every_row_on_global_tables(mg, gname, mode, k):
 
 
 @pytest.mark.parametrize("algo", ["lpa", "louvain"])
+@pytest.mark.parametrize("mode,k,L", [("alg1", 64, 128), ("alg1", 32, 37), ("std", 64, 1),
+                                      ("exact", 8, 128)])
+def test_batched_with_hub_rows(mg, algo, mode, k, L):
+    """Batched runs where two graphs have hub rows of 513 to 5,000 entries (split rows of
+    the 32/64-slot sketch, segmented global tables of the exact mode) next to small
+    graphs that converge first, so the hub graphs' long rows are swept while other
+    graphs are frozen and vice versa: every graph equals its plain run and the oracle."""
+    gs = _batch_graphs() + [_hub_graph(90), _hub_graph(91)]
+    dgs = [mg.to_device(g) for g in gs]
+    kw = dict(mode=MODES[mode], k=k, chunk_len=L)
+    code = mg.ALGO_LPA if algo == "lpa" else mg.ALGO_LOUVAIN
+    labs, gst, _ = mg.run_batched(code, dgs, **kw)
+    for g, dg, lab, st in zip(gs, dgs, labs, gst):
+        if g.n == 0:
+            continue
+        solo, sst = getattr(mg, algo)(dg, **kw)
+        assert np.array_equal(_np(lab), _np(solo))
+        assert st["iterations"] == sst["iterations"] and st["edges_scanned"] == sst["edges_scanned"]
+        elab, _ = getattr(oracle, algo)(g, **kw)
+        assert np.array_equal(_np(lab), elab)
+
+
+@pytest.mark.parametrize("algo", ["lpa", "louvain"])
 def test_batched_many_graphs_dirty_workspace(mg, algo):
     """More graphs than one wave of counters, in a workspace full of garbage: every
     per-graph counter and statistic must start from zero (regression: a clear that

@@ -323,7 +323,7 @@ def test_wave_sketch_deep_merge_tree(mg, k):
 
 
 # exact_small / exact_lds / exact_lds_big of (2, 8, 24) put rows on every table tier
-# (registers, 1,024- and 8,192-slot LDS tables, global tables)
+# (registers, row-sized and 8,192-slot LDS tables, global tables)
 TIERS = {"default": {}, "all_tiers": dict(exact_small=2, exact_lds=8, exact_lds_big=24)}
 
 

@@ -1036,16 +1036,34 @@ __global__ void __launch_bounds__(BLOCK)
       wave_sync();
       const int32_t bi = ALGO == ALGO_REFINE ? a.bound[i] : 0;
       const uint32_t mask = cap - 1;
-      for (int64_t e = lo + lane; e < hi; e += WAVE) {
-        const int32_t j = a.g.idx[e];
-        const uint32_t c0 = stream_key<ALGO>(a, i, j, bi);
-        if (c0 == EMPTY) continue;
-        const uint32_t c = slot_of(a, c0);
+      for (int64_t e0 = lo; e0 < hi; e0 += WAVE) {  // wave-uniform rounds
+        const int64_t e = e0 + lane;
+        const bool v = e < hi;
+        uint32_t c = v ? stream_key<ALGO>(a, i, a.g.idx[e], bi) : EMPTY;
+        if (c != EMPTY) c = slot_of(a, c);
+        uint32_t w = v ? a.g.w[e] : 0u;
+        // the lanes holding the first live lane's key add their weights into that lane
+        // (one table update instead of one per lane, which serialise on the slot of a
+        // community that many neighbours share; the lane is the group's first position)
+        const uint64_t lm = __ballot(c != EMPTY);
+        if (lm) {
+          const int ld = __builtin_ctzll(lm);
+          const uint32_t ck = lane_value(c, ld);
+          const bool m = c == ck;
+          if (__popcll(__ballot(m)) > 1) {
+            const uint32_t sum = wave_sum(m ? w : 0u);
+            if (lane == ld)
+              w = sum;
+            else if (m)
+              c = EMPTY;
+          }
+        }
+        if (c == EMPTY) continue;
         uint32_t h = hash_slot(c, mask);
         while (true) {
           const uint32_t prev = atomicCAS(&tab[h].key, EMPTY, c);
           if (prev == EMPTY || prev == c) {
-            atomicAdd(&tab[h].val, a.g.w[e]);
+            atomicAdd(&tab[h].val, w);
             if (SMALL) atomicMin(&pos[h], (uint32_t)(e - lo));
             break;
           }

@@ -77,22 +77,23 @@ typedef struct {
 /* Sketch update rules                                                              */
 /* ------------------------------------------------------------------------------ */
 
-/* Algorithm 1 (conditional subtraction), in slot form: add w to every slot holding
- * c; stop if c is present; else put (c, w) into the last slot whose value is 0;
- * else subtract w from every slot, clamping at 0.  The new item is then dropped. */
+/* Algorithm 1 (conditional subtraction, Appendix A.1).  Keys are unique in the
+ * sketch, and a key whose value fell to 0 keeps its slot until it is overwritten:
+ * an arriving item with that key revives it instead of being inserted.  One scan
+ * finds the slot of c, if any, and the highest-index slot of value 0.  A key in
+ * the sketch takes w; otherwise c goes into that free slot; with no free slot every
+ * value loses w (clamped at 0) and the item is dropped (the conditional rule). */
 static void populate_alg1(uint32_t *Sk, uint32_t *Sv, int k, uint32_t c, uint32_t w) {
-  for (int p = 0; p < k; ++p)
-    if (Sk[p] == c) Sv[p] += w;
-  int has = 0;
-  for (int p = 0; p < k; ++p)
-    if (Sk[p] == c) has = 1;
-  if (has) return;
-  int e = -1;
-  for (int p = 0; p < k; ++p)
-    if (Sv[p] == 0) e = p;
-  if (e >= 0) {
-    Sk[e] = c;
-    Sv[e] = w;
+  int at = -1, free_slot = -1;
+  for (int p = 0; p < k; ++p) {
+    if (Sk[p] == c) at = p;
+    else if (Sv[p] == 0) free_slot = p;
+  }
+  if (at >= 0) {
+    Sv[at] += w;
+  } else if (free_slot >= 0) {
+    Sk[free_slot] = c;
+    Sv[free_slot] = w;
   } else {
     for (int p = 0; p < k; ++p) Sv[p] = Sv[p] > w ? Sv[p] - w : 0;
   }

@@ -162,6 +162,21 @@ size_t mgcd_modularity_workspace_bytes(int32_t n, int64_t nnz);
 int modularity(const mgcd_csr *g, const int32_t *communities, double *q, void *ws,
                size_t ws_bytes, void *stream);
 
+/* Largest vertex count modularity_noalloc accepts. */
+#define MGCD_NOALLOC_MAX_VERTICES (1 << 22)
+
+/* modularity() for callers that cannot allocate device memory or pass a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, result and synchronisation as modularity(), minus
+ * the workspace: the library works in a fixed device scratch array of its own,
+ * 64 MiB + 128 KiB per device, set aside when the library is loaded on that device
+ * and held until the process ends.  Graphs of more than MGCD_NOALLOC_MAX_VERTICES
+ * vertices return MGCD_E_WORKSPACE before any device work.  The call allocates
+ * nothing.  All calls on one device share its scratch: calls that overlap on one
+ * device (other threads, other streams) race and must not be made; consecutive calls
+ * are independent (each writes what it reads first). */
+int modularity_noalloc(const mgcd_csr *g, const int32_t *communities, double *q, void *stream);
+
 /* One synchronous local-moving sweep (the hot path on its own, for iteration-level
  * checks).  algo: MGCD_ALGO_LPA or MGCD_ALGO_LOUVAIN.  C: device int32[n], the
  * current membership (values in [0, n)).  C_new: device int32[n] receives the

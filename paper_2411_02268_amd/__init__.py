@@ -94,6 +94,8 @@ def lib():
         L.mgcd_modularity_workspace_bytes.restype = sz
         L.modularity.argtypes = [ct.POINTER(CSRDesc), P, ct.POINTER(ct.c_double), P, sz, P]
         L.modularity.restype = ct.c_int
+        L.modularity_noalloc.argtypes = [ct.POINTER(CSRDesc), P, ct.POINTER(ct.c_double), P]
+        L.modularity_noalloc.restype = ct.c_int
         L.mgcd_move_sweep.argtypes = [ct.POINTER(CSRDesc), ct.POINTER(Params), i32, P, i32, P, P, P,
                                       P, sz, P]
         L.mgcd_move_sweep.restype = ct.c_int
@@ -222,6 +224,20 @@ def modularity(g: DeviceGraph, labels) -> float:
     _check(lib().modularity(ct.byref(d), labels.data_ptr(), ct.byref(q), ws.data_ptr(),
                             ws.numel(), _stream()))
     return q.value
+
+
+def modularity_noalloc(g: DeviceGraph, labels) -> float:
+    """modularity() without a workspace: the library's own fixed device scratch
+    (graphs of up to NOALLOC_MAX_VERTICES vertices; overlapping calls on one device
+    race)."""
+    q = ct.c_double()
+    d = g.desc()
+    _check(lib().modularity_noalloc(ct.byref(d), labels.data_ptr() if g.n else None,
+                                    ct.byref(q), _stream()))
+    return q.value
+
+
+NOALLOC_MAX_VERTICES = 1 << 22
 
 
 def move_sweep(g: DeviceGraph, algo: int, C, direction: int = 0, **kw):

@@ -12,6 +12,7 @@
 // symmetrically and starts the next pass from the (renumbered) communities.
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/mgcd.h"
@@ -363,6 +364,75 @@ static Arena make_arena(void *ws, size_t bytes) {
   return a;
 }
 
+// Modularity (Section 3.2, Eq. 1) of membership C with a workspace of ws_bytes >=
+// mgcd_modularity_workspace_bytes(g.n, g.nnz) at ws; everything it reads from the
+// workspace it first writes there.  Synchronises st.
+static void modularity_in(const Graph &g, const int32_t *C, double *q, void *ws, size_t ws_bytes,
+                        hipStream_t st) {
+  if (g.n == 0) {
+    *q = 0.0;
+    return;
+  }
+  Arena a = make_arena(ws, ws_bytes);
+  require_labels(C, g.n, g.n, a, st, "communities");
+  uint32_t *K = a.take<uint32_t>(g.n);
+  unsigned long long *Wd = a.take<unsigned long long>(1);
+  unsigned long long *terms = a.take<unsigned long long>(2 * SPREAD);
+  launch_degrees(g, K, Wd, a, st);
+  modularity_terms(g, C, K, terms, a, st);
+  unsigned long long ht[2 * SPREAD], h[2] = {0, 0};
+  MGCD_HIP(hipMemcpyAsync(ht, terms, sizeof(ht), hipMemcpyDeviceToHost, st));
+  uint64_t W = read_dev(Wd, st);
+  for (int c = 0; c < SPREAD; ++c) {
+    h[0] += ht[2 * c];
+    h[1] += ht[2 * c + 1];
+  }
+  if (W == 0) {
+    *q = 0.0;
+    return;
+  }
+  const double Wd_ = (double)W;
+  *q = (double)h[0] / Wd_ - (double)h[1] / (Wd_ * Wd_);
+}
+
+
+// ---- device scratch of modularity_noalloc ---------------------------------------------
+//
+// One array per device, set aside when the library's code object is loaded there and
+// held until the process ends.  Its device address is looked up once per device
+// (hipGetSymbolAddress with that device current) and kept; host code uses only that
+// address, never the array's name.  Every modularity_noalloc call on a device uses
+// the same memory: calls that overlap on one device race.
+constexpr size_t NOALLOC_SCRATCH_BYTES = ((size_t)64 << 20) + ((size_t)128 << 10);
+static_assert((size_t)MGCD_NOALLOC_MAX_VERTICES * 16 + SPREAD * 8 + 4096 + 64 * 1024 <= NOALLOC_SCRATCH_BYTES,
+              "the scratch must hold the modularity workspace of the largest accepted graph");
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+// The device address of `scratch` on the device of stream st (the current device for
+// the null stream).
+static void *scratch_of_stream(hipStream_t st) {
+  int cur = 0, dev = 0;
+  MGCD_HIP(hipGetDevice(&cur));
+  dev = cur;
+  if (st) MGCD_HIP(hipStreamGetDevice(st, &dev));
+  if (dev < 0 || dev >= SCRATCH_DEVICES) throw Error(MGCD_E_ARG, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    if (dev != cur) MGCD_HIP(hipSetDevice(dev));
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (dev != cur) MGCD_HIP(hipSetDevice(cur));
+    if (e != hipSuccess || !ptr)
+      throw Error(MGCD_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 // MGCD_MODE_BM is Algorithm 1 with one slot for local moving and refinement and four
 // for aggregation (the weighted Boyer-Moore variant of Section 4.1); every entry
 // point works on the resolved copy.
@@ -454,33 +524,26 @@ int modularity(const mgcd_csr *gin, const int32_t *C, double *q, void *ws, size_
     if (g.n > 0 && !C) throw Error(MGCD_E_ARG, "communities is null");
     size_t need = mgcd_modularity_workspace_bytes(g.n, g.nnz);
     if (ws_bytes < need) throw Error(MGCD_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
-    if (g.n == 0) {
-      *q = 0.0;
-      return;
-    }
-    Arena a = make_arena(ws, ws_bytes);
-    hipStream_t st = (hipStream_t)stream;
-    require_labels(C, g.n, g.n, a, st, "communities");
-    uint32_t *K = a.take<uint32_t>(g.n);
-    unsigned long long *Wd = a.take<unsigned long long>(1);
-    unsigned long long *terms = a.take<unsigned long long>(2 * SPREAD);
-    launch_degrees(g, K, Wd, a, st);
-    modularity_terms(g, C, K, terms, a, st);
-    unsigned long long ht[2 * SPREAD], h[2] = {0, 0};
-    MGCD_HIP(hipMemcpyAsync(ht, terms, sizeof(ht), hipMemcpyDeviceToHost, st));
-    uint64_t W = read_dev(Wd, st);
-    for (int c = 0; c < SPREAD; ++c) {
-      h[0] += ht[2 * c];
-      h[1] += ht[2 * c + 1];
-    }
-    if (W == 0) {
-      *q = 0.0;
-      return;
-    }
-    const double Wd_ = (double)W;
-    *q = (double)h[0] / Wd_ - (double)h[1] / (Wd_ * Wd_);
+    modularity_in(g, C, q, ws, ws_bytes, (hipStream_t)stream);
   });
 }
+
+int modularity_noalloc(const mgcd_csr *gin, const int32_t *C, double *q, void *stream) {
+  return guarded([&] {
+    if (!q) throw Error(MGCD_E_ARG, "q is null");
+    Graph g = view(gin);
+    if (g.n > 0 && !C) throw Error(MGCD_E_ARG, "communities is null");
+    size_t need = mgcd_modularity_workspace_bytes(g.n, g.nnz);
+    if (g.n > MGCD_NOALLOC_MAX_VERTICES || need > NOALLOC_SCRATCH_BYTES)
+      throw Error(MGCD_E_WORKSPACE, "modularity_noalloc handles at most " +
+                                        std::to_string(MGCD_NOALLOC_MAX_VERTICES) + " vertices (this graph needs " +
+                                        std::to_string(need) + " bytes of its " +
+                                        std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte device scratch)");
+    hipStream_t st = (hipStream_t)stream;
+    modularity_in(g, C, q, scratch_of_stream(st), NOALLOC_SCRATCH_BYTES, st);
+  });
+}
+
 
 int mgcd_move_sweep(const mgcd_csr *gin, const mgcd_params *p, int32_t algo, const int32_t *C,
                     int32_t direction, int32_t *C_new, int64_t *gain, int64_t *counters, void *ws,

@@ -51,12 +51,14 @@ def sources_sha256() -> str:
     return h.hexdigest()
 
 
-def class_bytes(g, L: int, k: int):
+def class_bytes(g, L: int, k: int, cands: float = 0.0):
     """Algorithmic bytes of one level-0 MG sweep per kernel class (reads and writes
     the method must make; a second pass over a row of at most 64 chunks counts as
     on-chip, a second pass over a longer row re-reads its keys and weights):
       per CSR entry 12 B (index 4, weight 4, gathered C[j] 4);
       per decided vertex 28 B (list 4, offsets 8, C 4, C_new 4, K 4, Sigma_d 4);
+      per candidate community c != d scored by class 0, 4 B (its total Sigma_c;
+      `cands` = candidates per launch, counted on the device);
       rows of more than 64 chunks: one sketch of 8k + 4 B per group of 64 chunks,
       written by class 0 and read by class 1; class 1 re-reads their entries'
       keys and weights (8 B) and writes and reads 4 (k + 1) B of counts per chunk.
@@ -66,7 +68,7 @@ def class_bytes(g, L: int, k: int):
     nch = (deg + L - 1) // L
     big = nch > 64
     groups = int(((nch[big] + 63) // 64).sum())
-    c0 = 12 * int(deg.sum()) + 28 * g.n + (8 * k + 4) * groups
+    c0 = 12 * int(deg.sum()) + 28 * g.n + (8 * k + 4) * groups + int(round(4 * cands))
     c1 = (8 * k + 4) * groups + 8 * int(deg[big].sum()) + 2 * 4 * (k + 1) * int(nch[big].sum())
     return [c0, c1, 0]
 
@@ -362,7 +364,8 @@ def main():
     for s in stats:
         ms += np.array(s["ms_l0_kernel"])
         sweeps += s["l0_sweeps"]
-    cb = class_bytes(g, L, k)
+    cands = sum(s["l0_candidates"] for s in stats) / max(sweeps, 1)
+    cb = class_bytes(g, L, k, cands)
     dom = int(np.argmax(ms))
     names = ["k_move_rows (every row: staged sketch, merge tree, second pass, decision; "
              "chunk sketches of rows longer than 64 chunks)",

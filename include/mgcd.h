@@ -68,8 +68,9 @@ typedef struct {
 
 typedef struct {
   int32_t mode;           /* MGCD_MODE_*                                              */
-  int32_t k;              /* sketch slots for moving/refinement: 1, 2, 4, 8 or 16     */
-  int32_t k_aggregate;    /* sketch slots for aggregation: 1, 2, 4, 8 or 16           */
+  int32_t k;              /* sketch slots for moving/refinement: 1, 2, 4, 8, 16, 32
+                             or 64 (MGCD_MODE_SMALL: the table's slots, 1 .. 2^30)    */
+  int32_t k_aggregate;    /* sketch slots for aggregation: 1, 2, 4, 8, 16, 32 or 64  */
   int32_t max_iterations; /* synchronous sweeps per pass (LPA: in total)              */
   int32_t max_passes;     /* Louvain/Leiden passes (levels)                            */
   int32_t validate;       /* 1: check the CSR on the device first (MGCD_E_GRAPH)      */
@@ -123,6 +124,9 @@ typedef struct {
   int32_t reserved2;
   float ms_l0_kernel[3];
   float reserved3;
+  /* Louvain/Leiden, level-0 sweeps: candidate communities c != d scored by the main
+     sweep kernel (each needs its community total Sigma_c), summed over the sweeps. */
+  int64_t l0_candidates;
 } mgcd_stats;
 
 /* Defaults for an algorithm: MG Algorithm 1, k = 8 (LPA, Louvain) or 16 (Leiden),

@@ -49,7 +49,8 @@ class Stats(ct.Structure):
                 ("moved_last", ct.c_int64), ("ms_local_move", ct.c_float),
                 ("ms_refine", ct.c_float), ("ms_aggregate", ct.c_float), ("ms_total", ct.c_float),
                 ("l0_sweeps", ct.c_int32), ("reserved2", ct.c_int32),
-                ("ms_l0_kernel", ct.c_float * 3), ("reserved3", ct.c_float)]
+                ("ms_l0_kernel", ct.c_float * 3), ("reserved3", ct.c_float),
+                ("l0_candidates", ct.c_int64)]
 
     def asdict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("reserved")}

@@ -34,11 +34,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 4) -> str:
-    """Compile all sources and link libmgcd.so; always rebuilds."""
+def _stale(src: str) -> bool:
+    """An object is stale when its source, or any header it may include, is newer."""
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)]
+    deps += [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")]
+    deps += [os.path.join(ROOT, "include", h) for h in os.listdir(os.path.join(ROOT, "include"))]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(jobs: int = 4, incremental: bool = False) -> str:
+    """Compile the sources and link libmgcd.so.  By default every source is compiled;
+    incremental=True recompiles only objects older than their source or any header."""
     os.makedirs(BUILD, exist_ok=True)
+    todo = [s for s in SOURCES if not incremental or _stale(s)]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,4 +64,5 @@ def build(jobs: int = 4) -> str:
 
 
 if __name__ == "__main__":
-    print(build(int(sys.argv[1]) if len(sys.argv) > 1 else 4))
+    args = [a for a in sys.argv[1:] if a != "--incremental"]
+    print(build(int(args[0]) if args else 4, incremental="--incremental" in sys.argv))

@@ -425,6 +425,7 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
 
   if (algo == MGCD_ALGO_LPA) {
     launch_iota(Ca, N, st);
+    launch_iota(Cb, N, st);  // rows without entries are in no sweep: both buffers hold them
     Schedule sch;
     build_schedule(U, sched_params(p), sch, a, st);
     for (int32_t g = 0; g < count; ++g) active[g] = !finished[g];
@@ -489,6 +490,7 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
       Schedule sch;
       build_schedule(cur, sched_params(p), sch, a, st);
       launch_iota(Ca, nl, st);
+      launch_iota(Cb, nl, st);  // rows without entries are in no sweep
       launch_community_totals(Ca, K, Sig, nl, st);
       ms_lm += tm.stop();
       for (int32_t g = 0; g < count; ++g) {

@@ -167,13 +167,14 @@ static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Are
   int32_t *Ca = a.take<int32_t>(n), *Cb = a.take<int32_t>(n);
   unsigned long long *ctr = a.take<unsigned long long>(4);
   launch_iota(Ca, n, st);
+  launch_iota(Cb, n, st);  // rows without entries are in no sweep: both buffers hold them
   Schedule sch;
   build_schedule(g, sched_params(p), sch, a, st);
   LevelState *ls = a.take<LevelState>(1);
   mgcd_stats s{};
   ClassTimer ct;
   lm.start();
-  launch_zero_u64(ctr, 3, st);
+  launch_zero_u64(ctr, 4, st);
   launch_zero_state(ls, st);
   if (n > 0) {
     LevelState h = run_sweeps(p->max_iterations, ls, st, &ct, s, [&](int, int j) {
@@ -246,8 +247,10 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
     tm.start();
     build_schedule(cur, sched_params(p), sch, a, st);
     if (!leiden) launch_iota(Ca, nl, st);
+    // rows without entries are in no sweep: both label buffers start equal
+    if (nl > 0) MGCD_HIP(hipMemcpyAsync(Cb, Ca, (size_t)nl * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     launch_community_totals(Ca, K, Sig, nl, st);
-    launch_zero_u64(ctr, 3, st);
+    launch_zero_u64(ctr, 4, st);
     launch_zero_state(ls, st);
     LevelState h = run_sweeps(p->max_iterations, ls, st, pass == 0 ? &ct : nullptr, s, [&](int it, int j) {
       SweepArgs args{cur, Ca, nullptr, K, Sig, W, (it % 2 == 0) ? -1 : 1, Cb, nullptr, ctr};
@@ -260,6 +263,7 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
       std::swap(Ca, Cb);
     });
     ms_lm += tm.stop();
+    if (pass == 0) s.l0_candidates = (int64_t)h.cands;
     s.iterations += h.sweeps;
     s.edges_scanned += (int64_t)h.edges;
     s.moved_last = (int64_t)h.moved_last;
@@ -268,7 +272,8 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
     if (leiden) {
       tm.start();
       SweepArgs r{cur, nullptr, Ca, K, K, W, 0, prop, nullptr, ctr};
-      launch_zero_u64(ctr, 3, st);
+      launch_iota(prop, nl, st);  // a row without entries proposes itself
+      launch_zero_u64(ctr, 4, st);
       launch_sweep(r, sch, ALGO_REFINE, p->mode, p->k, p->chunk_len, st);
       launch_refine_accept(prop, nprop, from, Cb, nl, st);  // Cb <- refined R
       ms_ref += tm.stop();
@@ -566,7 +571,10 @@ int mgcd_move_sweep(const mgcd_csr *gin, const mgcd_params *p, int32_t algo, con
     launch_community_totals(C, K, Sig, g.n, st);
     Schedule sch;
     build_schedule(g, sched_params(p), sch, a, st);
-    launch_zero_u64(ctr, 3, st);
+    launch_zero_u64(ctr, 4, st);
+    // rows without entries are in no sweep: they keep their community and gain 0
+    if (g.n > 0) MGCD_HIP(hipMemcpyAsync(C_new, C, (size_t)g.n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (gain) launch_zero_u64(reinterpret_cast<unsigned long long *>(gain), g.n, st);
     SweepArgs args{g, C, nullptr, K, Sig, W, direction < 0 ? -1 : direction > 0 ? 1 : 0, C_new, gain, ctr};
     args.one_scan = algo == MGCD_ALGO_LPA ? p->one_scan : 0;
     launch_sweep(args, sch, algo == MGCD_ALGO_LPA ? ALGO_LPA : ALGO_MOVE, p->mode, p->k, p->chunk_len, st);
@@ -596,7 +604,8 @@ int mgcd_refine(const mgcd_csr *gin, const mgcd_params *p, const int32_t *bound,
     unsigned long long *ctr = a.take<unsigned long long>(4);
     Schedule sch;
     build_schedule(g, sched_params(p), sch, a, st);
-    launch_zero_u64(ctr, 3, st);
+    launch_zero_u64(ctr, 4, st);
+    launch_iota(prop, g.n, st);  // a row without entries proposes itself
     SweepArgs r{g, nullptr, bound, K, K, W, 0, prop, nullptr, ctr};
     launch_sweep(r, sch, ALGO_REFINE, p->mode, p->k, p->chunk_len, st);
     launch_refine_accept(prop, nprop, from, R, g.n, st);

@@ -31,7 +31,7 @@ namespace mgcd {
 // ---- decision ---------------------------------------------------------------------
 
 struct Counters {
-  uint32_t moved = 0, prop = 0;
+  uint32_t moved = 0, prop = 0, cand = 0;
   uint64_t sumG = 0;
 };
 
@@ -122,18 +122,20 @@ __device__ inline void finish(const SweepArgs &a, int32_t i, int32_t d, int32_t 
 }
 
 __device__ inline void flush_counters(const SweepArgs &a, Counters ct) {
-  __shared__ unsigned long long red[3][4];
+  __shared__ unsigned long long red[4][4];
   unsigned long long m = wave_sum((unsigned long long)ct.moved);
   unsigned long long p = wave_sum((unsigned long long)ct.prop);
   unsigned long long g = wave_sum((unsigned long long)ct.sumG);
+  unsigned long long c = wave_sum((unsigned long long)ct.cand);
   int w = threadIdx.x / WAVE;
   if (lane_id() == 0) {
     red[0][w] = m;
     red[1][w] = p;
     red[2][w] = g;
+    red[3][w] = c;
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < 4) {
     unsigned long long s = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] +
                            red[threadIdx.x][3];
     if (s) atomicAdd(&a.ctr[threadIdx.x], s);
@@ -578,6 +580,10 @@ __device__ inline void row_work(const SweepArgs &a, const Buckets &bk, int64_t L
     const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
     const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
     consider_slots<K, ALGO>(a, W, d, Ki, Sd, kd, key, ex, best, bestG);
+    if (ALGO != ALGO_LPA) {
+#pragma unroll
+      for (int p = 0; p < K; ++p) ct.cand += key[p] != EMPTY && key[p] != (uint32_t)d;
+    }
     finish<ALGO>(a, i, d, best, bestG, ct);
   }
 }
@@ -1432,7 +1438,11 @@ __global__ void k_gtab_clear(Pair *htab, uint32_t *hpos, int64_t n) {
 //   MG with K = 32 / 64: 0 = at most exact_t0 entries, 1 = one wave per row, 2 = split
 //          rows (more than max(L, WAVE_SPLIT) entries);
 //   exact: tiers 0..3 by degree.
-constexpr int NCAT = 8;
+//   every mode: rows without entries (category 8) are sorted last and listed in no
+//          kernel's work: their label can never change, so no sweep writes it, and
+//          callers keep both label buffers equal for them.
+constexpr int NCAT = 9;
+constexpr int CAT_EMPTY = 8;
 
 __global__ void __launch_bounds__(BLOCK)
     k_schedule_keys(const int64_t *off, int32_t n, SchedParams sp, uint64_t *key, uint32_t *val,
@@ -1451,7 +1461,10 @@ __global__ void __launch_bounds__(BLOCK)
     int b = 0;
     while (b < 63 && (deg >> b) != 0) ++b;  // bits of deg
     uint64_t k;
-    if (mode == MODE_EXACT) {
+    if (deg == 0) {
+      cat = CAT_EMPTY;
+      k = 255;  // after every other key of every mode
+    } else if (mode == MODE_EXACT) {
       cat = deg <= sp.exact_t0 ? 0 : deg <= sp.exact_t1 ? 1 : deg <= sp.exact_t2 ? 2 : 3;
       k = cat == 0 ? (uint64_t)(64 - b) : (uint64_t)(128 + cat);
     } else if (sp.wave) {  // K = 32 / 64: short rows exact, split rows, the rest one wave each
@@ -1882,9 +1895,10 @@ __device__ inline void level_converge(int algo, const LevelRule &r) {
   // become a scalar load, which a following vector store of 0 can overtake.
   unsigned long long *ctr = r.ctr;
   const unsigned long long moved = atomicExch(&ctr[0], 0ull), prop = atomicExch(&ctr[1], 0ull),
-                           sumG = atomicExch(&ctr[2], 0ull);
+                           sumG = atomicExch(&ctr[2], 0ull), cands = atomicExch(&ctr[3], 0ull);
   LevelState *ls = r.ls;
   if (ls->halt) return;
+  ls->cands += cands;
   ls->sweeps += 1;
   ls->edges += (unsigned long long)r.nnz;
   ls->moved_last = moved;
@@ -1977,7 +1991,7 @@ void launch_level_converge(int algo, const LevelRule &r, hipStream_t st) {
   MGCD_LAUNCHED();
 }
 
-__global__ void k_zero_state(LevelState *ls) { *ls = LevelState{0, 0, 0, 0}; }
+__global__ void k_zero_state(LevelState *ls) { *ls = LevelState{0, 0, 0, 0, 0}; }
 
 void launch_zero_state(LevelState *ls, hipStream_t st) {
   k_zero_state<<<1, 1, 0, st>>>(ls);

@@ -16,7 +16,7 @@ struct SweepArgs {
   int32_t dir;           // -1 lower ids only, +1 higher ids only, 0 any
   int32_t *Cnew;         // new membership (refinement: proposed target)
   int64_t *gain;         // optional: gain of each vertex's best move
-  unsigned long long *ctr;  // [moved, proposals, sum of gains] (device)
+  unsigned long long *ctr;  // [moved, proposals, sum of gains, candidates] (device)
   // Batched runs (many graphs as one disjoint union): graph of every vertex, its
   // graph's total weight, whether that graph still moves, per-graph counters
   // [3 * graph + {moved, proposals, sum of gains}].  Null for a single graph.
@@ -45,17 +45,20 @@ __device__ inline uint32_t slot_of(const SweepArgs &a, uint32_t c) {
 __host__ __device__ inline bool second_pass(const SweepArgs &a, int algo) { return !(algo == ALGO_LPA && a.one_scan); }
 
 // A single graph's level, kept on the device so that sweeps need no host round trip:
-// set `halt` when the level's stopping rule fires; count sweeps, streamed entries
-// and the last sweep's movers.
+// set `halt` when the level's stopping rule fires; count sweeps, streamed entries,
+// the last sweep's movers and the candidate communities (c != d) whose totals the
+// main sweep kernel read (Louvain/Leiden; a measurement figure only).
 struct LevelState {
   uint32_t halt;
   uint32_t sweeps;
   unsigned long long edges;
   unsigned long long moved_last;
+  unsigned long long cands;
 };
 // A level's stopping rule: LPA stops when movers <= tol * n, Louvain local moving
 // when no vertex has a positive move or 2 * summed gain <= tol * W^2 (WW = W^2).
-// The sweep counters ctr [moved, proposals, sum of gains] are read and cleared.
+// The sweep counters ctr [moved, proposals, sum of gains, candidates] are read and
+// cleared.
 struct LevelRule {
   unsigned long long *ctr = nullptr;
   LevelState *ls = nullptr;

@@ -47,6 +47,24 @@ __global__ void k_pack(const DevDesc *d, int32_t y0, int64_t *off, int32_t *idx,
 
 __global__ void k_set_last_offset(int64_t *off, int64_t n, int64_t E) { off[n] = E; }
 
+// Validation of every graph against its own sizes (validate = 1), before packing:
+// offsets[0] = 0, offsets[n_g] = nnz_g, offsets non-decreasing, every index in
+// [0, n_g) and every weight >= 1.  *bad receives the smallest failing graph index.
+__global__ void k_validate_each(const DevDesc *d, int32_t y0, int32_t *bad) {
+  const int32_t gi = y0 + (int32_t)blockIdx.y;
+  const DevDesc g = d[gi];
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  bool ok = true;
+  const int64_t t0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (t0 == 0) ok &= g.off[0] == 0 && g.off[g.n] == g.nnz;
+  for (int64_t v = t0; v < g.n; v += stride) ok &= g.off[v + 1] >= g.off[v];
+  for (int64_t e = t0; e < g.nnz; e += stride) {
+    const int32_t j = g.idx[e];
+    ok &= j >= 0 && (int64_t)j < g.n && g.w[e] >= 1u;
+  }
+  if (!ok) atomicMin(bad, gi);
+}
+
 // Per-graph sums of K (vertices of one graph are contiguous: a wave whose lanes all
 // belong to one graph adds once).
 __global__ void k_graph_weights(const uint32_t *K, const int32_t *gid, int64_t n, unsigned long long *Wg) {
@@ -121,6 +139,13 @@ struct Batch {
   int32_t *gid0;
   uint8_t *sel_d;
 };
+
+static unsigned long long read_u64(const unsigned long long *p, hipStream_t st) {
+  unsigned long long h = 0;
+  MGCD_HIP(hipMemcpyAsync(&h, p, sizeof(h), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  return h;
+}
 
 static void copy_h2d(void *dst, const void *src, size_t bytes, hipStream_t st) {
   MGCD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
@@ -340,6 +365,20 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
   }
   b.ddesc = a.take<DevDesc>(count);
   copy_h2d(b.ddesc, hd.data(), hd.size() * sizeof(DevDesc), st);
+  if (p->validate) {
+    int32_t *bad = a.take<int32_t>(1);
+    launch_fill_i32(bad, count, 1, st);
+    for (int32_t y0 = 0; y0 < count; y0 += 65535) {
+      const int32_t ny = std::min<int32_t>(65535, count - y0);
+      dim3 grid((unsigned)std::min<int64_t>(ceil_div(max_items + 1, BLOCK), 4096), (unsigned)ny);
+      k_validate_each<<<grid, BLOCK, 0, st>>>(b.ddesc, y0, bad);
+      MGCD_LAUNCHED();
+    }
+    int32_t hb = count;
+    MGCD_HIP(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+    if (hb < count) throw Error(MGCD_E_GRAPH, "graph " + std::to_string(hb) + " failed validation");
+  }
   b.gid0 = a.take<int32_t>(N);
   b.sel_d = a.take<uint8_t>(count);
   uint8_t *active_d = a.take<uint8_t>(count);
@@ -358,29 +397,26 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
   k_set_last_offset<<<1, 1, 0, st>>>(uoff, N, E);
   MGCD_LAUNCHED();
   Graph U{N, E, uoff, uidx, uw};
-  if (p->validate) {
-    unsigned long long *flag = a.take<unsigned long long>(1);
-    launch_zero_u64(flag, 1, st);
-    launch_validate(U, flag, st);
-    unsigned long long hf = 0;
-    MGCD_HIP(hipMemcpyAsync(&hf, flag, sizeof(hf), hipMemcpyDeviceToHost, st));
-    MGCD_HIP(hipStreamSynchronize(st));
-    if (hf) throw Error(MGCD_E_GRAPH, "a CSR failed validation");
-  }
   uint32_t *Kbuf[2] = {a.take<uint32_t>(N), a.take<uint32_t>(N)};
   {
     unsigned long long *Wtot = a.take<unsigned long long>(1);
     launch_degrees(U, Kbuf[0], Wtot, a, st);
-    MGCD_HIP(hipMemsetAsync(Wg64, 0, count * sizeof(unsigned long long), st));
+    launch_zero_u64(Wg64, count, st);
     if (N > 0) {
       k_graph_weights<<<grid_for(N), BLOCK, 0, st>>>(Kbuf[0], b.gid0, N, Wg64);
       MGCD_LAUNCHED();
     }
     std::vector<unsigned long long> hw(count);
     MGCD_HIP(hipMemcpyAsync(hw.data(), Wg64, count * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    MGCD_HIP(hipStreamSynchronize(st));
-    for (int32_t g = 0; g < count; ++g)
+    const unsigned long long wall = read_u64(Wtot, st);
+    // W_g sums the rows' K, which are 32-bit: a row of 2^32 or more would wrap and
+    // drop below its true weight, so the W_g must add up to the exact (64-bit) total
+    unsigned long long wsum = 0;
+    for (int32_t g = 0; g < count; ++g) {
       if (hw[g] >= (1ull << 31)) throw Error(MGCD_E_OVERFLOW, "graph " + std::to_string(g) + ": total edge weight must be below 2^31");
+      wsum += hw[g];
+    }
+    if (wsum != wall) throw Error(MGCD_E_OVERFLOW, "a graph's total edge weight must be below 2^31");
     k_u64_to_u32<<<grid_for(count), BLOCK, 0, st>>>(Wg64, Wg, count);
     MGCD_LAUNCHED();
   }

@@ -306,6 +306,9 @@ def main():
                     help="graphs of the batched leg (0 skips it; default 1024 with the "
                          "default workload, else 0)")
     ap.add_argument("--batch-nmax", type=float, default=2e5)
+    ap.add_argument("--no-quality-split", dest="quality_split", action="store_false",
+                    help="skip the modularity of L = 4096 and of aggregation decoupled "
+                         "from local moving")
     ap.add_argument("--k-sweep", action="store_true",
                     help="also run the k sweep of every sketch variant on the workload graph")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -387,6 +390,24 @@ def main():
         print(f"[bench] exact: {args.exact_steps} steps in {secs_x:.3f}s, "
               f"{edges_x/secs_x/1e9:.3f} G edges/s, Q={q_x:.6f}", file=sys.stderr, flush=True)
 
+    # where a sketch's modularity loss comes from (Louvain/Leiden, when the exact run
+    # is there): the chunk length L = 4096 against the default, and aggregation
+    # decoupled from local moving (sketch moving with exact rows; exact moving with
+    # sketch rows of k slots)
+    split = None
+    if q_x and algo_name != "lpa" and args.quality_split:
+        split = {}
+        for key, kw in (("L4096", dict(mode=mg.MODE_ALG1, k=k, chunk_len=4096)),
+                        ("mg_move_exact_agg", dict(mode=mg.MODE_ALG1, k=k, chunk_len=L,
+                                                   aggregation=1)),
+                        ("exact_move_mg_agg", dict(mode=mg.MODE_EXACT, k_aggregate=k,
+                                                   chunk_len=L, aggregation=2))):
+            lab_s, _ = fn(dg, **kw)
+            qs = mg.modularity(dg, lab_s)
+            split[key] = {"Q": qs, "ratio": qs / q_x}
+        print(f"[bench] quality split: " + ", ".join(f"{a} {b['ratio']:.3f}" for a, b in split.items()),
+              file=sys.stderr, flush=True)
+
     ground_truth = None
     if truth is not None:  # planted partition: NMI of the labels against it
         ground_truth = {"nmi_mg": nmi(lab.cpu().numpy(), truth)}
@@ -460,7 +481,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": args.workload, "graph": graph_desc, "n": g.n, "nnz": g.nnz,
                    "k": k, "chunk_len": L, "algorithm": algo_name, "parallelism": "single-gpu"},
-        "modularity": {"mg": q_mg, "exact": q_x, "ratio": q_mg / q_x if q_x else None},
+        "modularity": {"mg": q_mg, "exact": q_x, "ratio": q_mg / q_x if q_x else None,
+                       "split": split},
         "ground_truth": ground_truth,
         "k_sweep": ksweep,
         "exact": exact,

@@ -51,6 +51,15 @@ enum {
 
 enum { MGCD_ALGO_LPA = 0, MGCD_ALGO_LOUVAIN = 1, MGCD_ALGO_LEIDEN = 2 };
 
+/* How aggregation builds a super-vertex's row (mgcd_params.aggregation). */
+enum {
+  MGCD_AGG_AS_MODE = 0, /* as `mode` says (the method of Section 4.1: the same sketch as
+                           local moving, k_aggregate slots; exact in the exact and
+                           small-table modes)                                        */
+  MGCD_AGG_EXACT = 1,   /* exact rows (every linked community with its full weight)  */
+  MGCD_AGG_SKETCH = 2   /* Algorithm 1 with k_aggregate slots, whatever `mode` is     */
+};
+
 /* An undirected graph G = (V, E, w) (Section 3).  Every undirected edge {i, j}
  * appears as the entries i->j and j->i with equal weight; a self-loop appears once.
  * Layout: offsets[n+1] int64 (offsets[0] = 0, non-decreasing, offsets[n] = nnz);
@@ -102,6 +111,10 @@ typedef struct {
                              no second pass; 0 (default) runs the second pass.
                              Louvain/Leiden calls with 1 return MGCD_E_UNSUPPORTED;
                              the exact mode is unaffected (its table is exact).     */
+  int32_t aggregation;    /* MGCD_AGG_*: 0 (default) aggregates as `mode` says; 1 and
+                             2 decouple aggregation from local moving, to measure
+                             how much of a sketch's modularity loss each phase
+                             causes                                                 */
 } mgcd_params;
 
 typedef struct {

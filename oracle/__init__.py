@@ -43,7 +43,7 @@ class _Params(ct.Structure):
                 ("threads", ct.c_int32), ("chunk_len", ct.c_int64),
                 ("tolerance", ct.c_double), ("tolerance_drop", ct.c_double),
                 ("aggregation_tolerance", ct.c_double), ("one_scan", ct.c_int32),
-                ("reserved", ct.c_int32)]
+                ("aggregation", ct.c_int32)]
 
 
 class _Stats(ct.Structure):
@@ -230,7 +230,7 @@ def modularity(g, C) -> float:
 
 DEFAULTS = dict(mode=MODE_ALG1, k=8, k_aggregate=None, chunk_len=128, max_iterations=20,
                 max_passes=10, tolerance=None, tolerance_drop=10.0, aggregation_tolerance=0.8,
-                threads=0, one_scan=0)
+                threads=0, one_scan=0, aggregation=0)
 
 
 def _params(algo: str, **kw) -> _Params:
@@ -244,7 +244,7 @@ def _params(algo: str, **kw) -> _Params:
         o["tolerance"] = 0.05 if algo == "lpa" else 1e-2
     return _Params(o["mode"], o["k"], o["k_aggregate"], o["max_iterations"], o["max_passes"],
                    o["threads"], o["chunk_len"], o["tolerance"], o["tolerance_drop"],
-                   o["aggregation_tolerance"], o["one_scan"], 0)
+                   o["aggregation_tolerance"], o["one_scan"], o["aggregation"])
 
 
 def _run(name: str, g, **kw):

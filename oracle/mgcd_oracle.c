@@ -790,13 +790,25 @@ static void set_threads(const or_params *p) {
 #endif
 }
 
+/* The rows of aggregation: as the moving mode says (Section 4.1: the same sketch;
+ * the small table of Appendix A.2 aggregates exactly), or decoupled from it, exact or
+ * Algorithm 1 with k_aggregate slots, to measure each phase's share of a sketch's
+ * modularity loss. */
+static int agg_mode_of(const or_params *p) {
+  if (p->aggregation == 1) return OR_MODE_EXACT;
+  if (p->aggregation == 2) return OR_MODE_ALG1;
+  return p->mode == OR_MODE_SMALL ? OR_MODE_EXACT : p->mode;
+}
+
 static int check_params(const or_params *p) {
-  if (p->mode == OR_MODE_SMALL) { /* k: slots of the small table; aggregation is exact */
-    if (p->k < 1) return -6;
-    return p->chunk_len < 1 ? -1 : 0;
-  }
-  if (p->k < 1 || p->k > KMAX || p->k_aggregate < 1 || p->k_aggregate > KMAX) return -6;
+  if (p->aggregation < 0 || p->aggregation > 2) return -1;
   if (p->chunk_len < 1) return -1;
+  if (p->mode == OR_MODE_SMALL) { /* k: slots of the small table */
+    if (p->k < 1) return -6;
+  } else if (p->k < 1 || p->k > KMAX) {
+    return -6;
+  }
+  if (agg_mode_of(p) != OR_MODE_EXACT && (p->k_aggregate < 1 || p->k_aggregate > KMAX)) return -6;
   return 0;
 }
 
@@ -915,8 +927,7 @@ int oracle_louvain(int32_t n, const int64_t *off, const int32_t *idx, const uint
       int32_t *D = (int32_t *)malloc(sizeof(int32_t) * szl);
       for (int32_t i = 0; i < nl; ++i) D[i] = dense[C[i]];
       graph_t a;
-      aggregate(&g, D, m, p->mode == OR_MODE_SMALL ? OR_MODE_EXACT : p->mode, p->k_aggregate,
-                p->chunk_len, 0, &a);
+      aggregate(&g, D, m, agg_mode_of(p), p->k_aggregate, p->chunk_len, 0, &a);
       int64_t *K2 = (int64_t *)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
       for (int32_t i = 0; i < nl; ++i) K2[D[i]] += K[i];
       free(K);
@@ -982,8 +993,7 @@ int oracle_leiden(int32_t n, const int64_t *off, const int32_t *idx, const uint3
     for (int32_t i = 0; i < nl; ++i) D[i] = denseR[R[i]];
     for (int32_t v = 0; v < n; ++v) top[v] = D[top[v]];
     graph_t a;
-    aggregate(&g, D, m, p->mode == OR_MODE_SMALL ? OR_MODE_EXACT : p->mode, p->k_aggregate,
-              p->chunk_len, 1, &a);
+    aggregate(&g, D, m, agg_mode_of(p), p->k_aggregate, p->chunk_len, 1, &a);
     int64_t *K2 = (int64_t *)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
     int32_t *C2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
     for (int32_t i = 0; i < nl; ++i) {

@@ -28,7 +28,7 @@ typedef struct {
   double tolerance_drop;
   double aggregation_tolerance;
   int32_t one_scan; /* LPA only: 1 = the 1-scan variant (Section 4.3) */
-  int32_t reserved;
+  int32_t aggregation; /* 0: as mode; 1: exact rows; 2: Algorithm 1, k_aggregate slots */
 } or_params;
 
 typedef struct {

@@ -654,7 +654,7 @@ size_t batched_workspace_bytes(int32_t algo, int32_t count, int64_t N, int64_t E
   b += (size_t)(N + 1) * 8 + (size_t)E * 8;                 // union
   b += (size_t)N * 4 * 14 + (size_t)(N + 1) * 8;             // per-vertex state
   if (algo != MGCD_ALGO_LPA) b += 2 * ((size_t)(N + 1) * 8 + (size_t)E * 8);  // level slots
-  size_t sched = schedule_ws_bytes((int32_t)N, E, agg_mode(p), p->k, L);
+  size_t sched = schedule_ws_bytes((int32_t)N, E, sched_mode(p), p->k, L);
   size_t agg = algo == MGCD_ALGO_LPA ? 0 : aggregate_ws_bytes((int32_t)N, E, agg_mode(p), p->k_aggregate, L, false);
   size_t misc = (size_t)N * (4 + 4 + 8 + 8) + scan_ws_bytes(N + 1) + 64 * 1024;
   size_t phase = sched > agg ? sched : agg;

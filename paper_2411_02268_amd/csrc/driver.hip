@@ -62,9 +62,12 @@ static void check_params(const mgcd_params *p) {
   auto okk = [](int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16 || k == 32 || k == 64; };
   if (p->mode == MGCD_MODE_SMALL) {
     if (p->k < 1 || p->k > (1 << 30)) throw Error(MGCD_E_UNSUPPORTED, "small-table slots k must be in [1, 2^30]");
-  } else if (p->mode != MGCD_MODE_EXACT && (!okk(p->k) || !okk(p->k_aggregate))) {
-    throw Error(MGCD_E_UNSUPPORTED, "k and k_aggregate must be 1, 2, 4, 8, 16, 32 or 64");
+  } else if (p->mode != MGCD_MODE_EXACT && !okk(p->k)) {
+    throw Error(MGCD_E_UNSUPPORTED, "k must be 1, 2, 4, 8, 16, 32 or 64");
   }
+  if (p->aggregation < 0 || p->aggregation > 2) throw Error(MGCD_E_ARG, "aggregation must be 0, 1 or 2");
+  if (agg_mode(p) != MGCD_MODE_EXACT && !okk(p->k_aggregate))
+    throw Error(MGCD_E_UNSUPPORTED, "k_aggregate must be 1, 2, 4, 8, 16, 32 or 64");
   if (p->chunk_len < 1) throw Error(MGCD_E_ARG, "chunk_len must be >= 1");
   if (p->max_iterations < 1 || p->max_passes < 1) throw Error(MGCD_E_ARG, "iteration limits must be >= 1");
   if (!(p->tolerance >= 0.0) || !(p->tolerance_drop > 0.0) || !(p->aggregation_tolerance >= 0.0))
@@ -324,12 +327,11 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
 // ---- workspace ---------------------------------------------------------------------------
 
 static size_t workspace_bytes(int32_t algo, int32_t n, int64_t nnz, const mgcd_params *p) {
-  const int mode = agg_mode(p);
   const int64_t L = p->chunk_len > 0 ? p->chunk_len : 1;
   size_t fixed = (size_t)n * 4 * 16 + 64 * 1024;
   if (algo != MGCD_ALGO_LPA) fixed += 2 * ((size_t)(n + 1) * 8 + (size_t)nnz * 8) + 4096;
-  size_t sched = schedule_ws_bytes(n, nnz, mode, p->k, L);
-  size_t agg = algo == MGCD_ALGO_LPA ? 0 : aggregate_ws_bytes(n, nnz, mode, p->k_aggregate, L, algo == MGCD_ALGO_LEIDEN);
+  size_t sched = schedule_ws_bytes(n, nnz, sched_mode(p), p->k, L);
+  size_t agg = algo == MGCD_ALGO_LPA ? 0 : aggregate_ws_bytes(n, nnz, agg_mode(p), p->k_aggregate, L, algo == MGCD_ALGO_LEIDEN);
   size_t misc = (size_t)n * (4 + 4 + 8 + 8) + scan_ws_bytes((int64_t)n + 1) + 16 * 1024;
   size_t degrees = degrees_ws_bytes(nnz);
   size_t phase = sched > agg ? sched : agg;

@@ -158,10 +158,17 @@ constexpr int64_t WAVE_SPLIT = 512;
 void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a, hipStream_t st);
 
 // The schedule parameters of a call (0 in a schedule field selects its default).
-// The small table (MGCD_MODE_SMALL) runs on the exact kernels' schedule and
-// aggregates exactly: the mode that schedules and aggregation see.
-inline int agg_mode(const mgcd_params *p) {
+// The small table (MGCD_MODE_SMALL) runs on the exact kernels' schedule: the mode
+// that local-moving schedules see.
+inline int sched_mode(const mgcd_params *p) {
   return p->mode == MGCD_MODE_SMALL ? MGCD_MODE_EXACT : p->mode;
+}
+// The mode of aggregation: as the moving mode (the small table aggregates exactly),
+// or the exact rows / Algorithm 1 sketch that `aggregation` asks for.
+inline int agg_mode(const mgcd_params *p) {
+  if (p->aggregation == MGCD_AGG_EXACT) return MGCD_MODE_EXACT;
+  if (p->aggregation == MGCD_AGG_SKETCH) return MGCD_MODE_ALG1;
+  return sched_mode(p);
 }
 
 inline SchedParams sched_params(const mgcd_params *p) {

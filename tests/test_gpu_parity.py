@@ -596,3 +596,19 @@ def test_small_table_run_parity(mg, slots):
             if g.n:
                 elab, _ = getattr(oracle, algo)(g, mode=oracle.MODE_SMALL, k=slots)
                 assert np.array_equal(_np(lab), elab)
+
+
+@pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12"])
+@pytest.mark.parametrize("algo", ["louvain", "leiden"])
+@pytest.mark.parametrize("cfg", [dict(mode=1, k=4, aggregation=1),
+                                 dict(mode=0, k_aggregate=4, aggregation=2),
+                                 dict(mode=1, k=32, k_aggregate=2, aggregation=2, chunk_len=37)],
+                         ids=["mg-move-exact-agg", "exact-move-mg-agg", "k32-move-k2-agg"])
+def test_decoupled_aggregation(mg, gname, algo, cfg):
+    """Aggregation decoupled from local moving (the measurement of each phase's share
+    of a sketch's modularity loss): whole runs equal to the oracle."""
+    g = graph(gname)
+    lab, st = getattr(mg, algo)(mg.to_device(g), **cfg)
+    elab, est = getattr(oracle, algo)(g, **cfg)
+    assert np.array_equal(_np(lab), elab)
+    assert st["iterations"] == est.iterations and st["passes"] == est.passes

@@ -281,7 +281,10 @@ def leiden_recomposed(g0, passes, mode, k, L, tol=1e-2, start_in_bound=True):
     return oracle.canonical(top), its
 
 
-def louvain_recomposed(g0, passes, mode, k, L, tol=1e-2):
+def louvain_recomposed(g0, passes, mode, k, L, tol=1e-2, agg=None, kagg=None):
+    """agg / kagg: the aggregation's mode and slots when they differ from moving's."""
+    agg = mode if agg is None else agg
+    kagg = k if kagg is None else kagg
     K = oracle.weighted_degree(g0)
     W = int(K.sum())
     g, top = g0, np.arange(g0.n)
@@ -293,7 +296,7 @@ def louvain_recomposed(g0, passes, mode, k, L, tol=1e-2):
         top = D[top]
         if p == passes - 1 or m > 0.8 * g.n:
             break
-        a = oracle.aggregate(g, D, m, mode=mode, k=k, chunk_len=L)
+        a = oracle.aggregate(g, D, m, mode=agg, k=kagg, chunk_len=L)
         g = synth.CSR(a.offsets, a.indices, a.weights)
         K = np.bincount(D, weights=K, minlength=m).astype(np.int64)
         tol /= 10
@@ -322,6 +325,24 @@ def test_louvain_equals_recomposed_phases(seed, mode, k, L):
         want, its = louvain_recomposed(g, passes, mode, k, L)
         got, st = oracle.louvain(g, mode=mode, k=k, chunk_len=L, max_passes=passes)
         assert np.array_equal(got, want) and st.iterations == its
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_louvain_aggregation_decoupled_from_moving(seed):
+    # aggregation = 1: sketch moving, exact rows; aggregation = 2: exact moving, rows
+    # from Algorithm 1 with k_aggregate slots (the measurement of each phase's loss)
+    g = _driver_case(seed)
+    want, its = louvain_recomposed(g, 10, oracle.MODE_ALG1, 2, 5, agg=oracle.MODE_EXACT)
+    got, st = oracle.louvain(g, mode=oracle.MODE_ALG1, k=2, chunk_len=5, aggregation=1)
+    assert np.array_equal(got, want) and st.iterations == its
+    want, its = louvain_recomposed(g, 10, oracle.MODE_EXACT, 8, 5, agg=oracle.MODE_ALG1, kagg=2)
+    got, st = oracle.louvain(g, mode=oracle.MODE_EXACT, k=8, k_aggregate=2, chunk_len=5,
+                             aggregation=2)
+    assert np.array_equal(got, want) and st.iterations == its
+    # the split is not vacuous on these inputs
+    full, _ = oracle.louvain(g, mode=oracle.MODE_ALG1, k=2, chunk_len=5)
+    ex, _ = oracle.louvain(g, mode=oracle.MODE_EXACT)
+    assert not (np.array_equal(full, got) and np.array_equal(ex, got))
 
 
 def test_leiden_start_witness():

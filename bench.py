@@ -303,7 +303,7 @@ def main():
                          "default workload, else 0)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--batch-graphs", type=int, default=None,
-                    help="graphs of the batched leg (0 skips it; default 1024 with the "
+                    help="graphs of the batched leg (0 skips it; default 4096 with the "
                          "default workload, else 0)")
     ap.add_argument("--batch-nmax", type=float, default=2e5)
     ap.add_argument("--no-quality-split", dest="quality_split", action="store_false",
@@ -323,7 +323,7 @@ def main():
     if args.serve_requests is None:
         args.serve_requests = 2000 if default else 0
     if args.batch_graphs is None:
-        args.batch_graphs = 1024 if default else 0
+        args.batch_graphs = 4096 if default else 0
 
     import torch
     import paper_2411_02268_amd as mg

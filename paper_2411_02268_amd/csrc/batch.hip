@@ -191,44 +191,67 @@ static void write_selected(Batch &b, const int32_t *lab, const std::vector<uint8
   a.release(mk);
 }
 
-// After a sweep, per graph on the device: a graph still moving counts the sweep
-// (stat = {sweeps, entries streamed, movers of its last sweep}) and stops when its
-// rule says so -- LPA: movers <= tol * n_g; Louvain: no positive move, or
-// 2 * (summed gain) <= tol * W_g^2 -- and its counters are cleared for the next sweep.
-// The same double-precision tests the single-graph driver makes on the host.
+// After a sweep, per graph on the device (one workgroup, graphs strided over its
+// threads): a graph still moving counts the sweep (stat = {sweeps, entries streamed,
+// movers of its last sweep}) and stops when its rule says so -- LPA: movers <=
+// tol * n_g; Louvain: no positive move, or 2 * (summed gain) <= tol * W_g^2 -- and
+// its counters are cleared for the next sweep (the same double-precision tests the
+// single-graph driver makes on the host).  Then lv[0] = graphs still moving (0: every
+// later sweep of the level does nothing), lv[1] counts the sweeps in which some graph
+// moved, and the persistent sweep kernel's work counter is cleared.
 template <int ALGO>
-__global__ void k_batch_converge(unsigned long long *gctr, uint8_t *active, long long *stat,
-                                 const int64_t *nent, const int64_t *nvert,
-                                 const unsigned long long *Wg64, double tol, int32_t count) {
-  const int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (g >= count) return;
-  unsigned long long *c = gctr + 3 * g;
-  const unsigned long long moved = atomicExch(&c[0], 0ull), prop = atomicExch(&c[1], 0ull),
-                           sumG = atomicExch(&c[2], 0ull);
-  if (!active[g]) return;
-  stat[3 * g] += 1;
-  stat[3 * g + 1] += nent[g];
-  stat[3 * g + 2] = (long long)moved;
-  bool stop;
-  if (ALGO == ALGO_LPA) {
-    stop = (double)moved <= tol * (double)nvert[g];
-  } else {
-    const double WW = (double)Wg64[g] * (double)Wg64[g];
-    stop = prop == 0 || 2.0 * (double)sumG <= tol * WW;
+__global__ void __launch_bounds__(BLOCK)
+    k_batch_converge(unsigned long long *gctr, uint8_t *active, long long *stat, const int64_t *nent,
+                     const int64_t *nvert, const unsigned long long *Wg64, double tol, int32_t count,
+                     uint32_t *lv, unsigned long long *queue) {
+  __shared__ uint32_t red[BLOCK / WAVE];
+  const uint32_t was = lv[0];
+  uint32_t still = 0;
+  for (int64_t g = threadIdx.x; g < count; g += BLOCK) {
+    unsigned long long *c = gctr + 3 * g;
+    const unsigned long long moved = atomicExch(&c[0], 0ull), prop = atomicExch(&c[1], 0ull),
+                             sumG = atomicExch(&c[2], 0ull);
+    if (!active[g]) continue;
+    stat[3 * g] += 1;
+    stat[3 * g + 1] += nent[g];
+    stat[3 * g + 2] = (long long)moved;
+    bool stop;
+    if (ALGO == ALGO_LPA) {
+      stop = (double)moved <= tol * (double)nvert[g];
+    } else {
+      const double WW = (double)Wg64[g] * (double)Wg64[g];
+      stop = prop == 0 || 2.0 * (double)sumG <= tol * WW;
+    }
+    if (stop)
+      active[g] = 0;
+    else
+      still += 1;
   }
-  if (stop) active[g] = 0;
+  still = block_sum(still, red);
+  if (threadIdx.x == 0) {
+    lv[0] = still;
+    lv[1] += was > 0 ? 1u : 0u;
+    *queue = 0;
+  }
 }
 
-// One level's local-moving sweeps for every graph of the batch, each sweep followed
-// by the per-graph bookkeeping on the device, so no sweep waits for the host.  The
-// sweeps are issued in segments of SEG (even, so the two label buffers and the sweep
-// directions repeat); by default one segment is captured as a HIP graph and that
-// graph is launched again for every segment.  Between segments the host reads the
-// per-graph flags once and stops when no graph is still moving; a graph that has
-// stopped stays frozen (its vertices keep their labels) in the rest of its segment.
-// Returns with the caller's stream synchronised; C[0] then holds the labels.
-constexpr int SEG = 4;
+// Start of a level: lv = {graphs moving, sweeps with moves so far = 0}, queue empty.
+__global__ void k_level_start(uint32_t *lv, uint32_t moving, unsigned long long *queue) {
+  lv[0] = moving;
+  lv[1] = 0;
+  *queue = 0;
+}
 
+// One level's local-moving sweeps for every graph of the batch, as one device-driven
+// launch: all max_iterations sweeps (each followed by its Sigma update and the
+// per-graph stopping rules of k_batch_converge) are captured as one HIP graph and
+// launched once, or issued one by one (direct_launch), and the host waits once, at
+// the end.  Within a sweep the main sweep kernel is persistent: its waves take row
+// tiles of all graphs from a device work counter.  A graph that has stopped keeps its
+// labels (its rows copy C to C_new) while others move; once no graph moves, every
+// remaining sweep kernel returns at once, so the labels stay in the buffer the last
+// real sweep wrote, found from the device's count of real sweeps.  On return the
+// stream is synchronised and C[0] holds the labels.
 struct LevelSweeps {
   int algo;             // ALGO_LPA or ALGO_MOVE
   Graph g;
@@ -243,6 +266,9 @@ struct LevelSweeps {
   const int64_t *nent, *nvert;
   int32_t count;
   double tol;
+  uint32_t *lv;               // [graphs moving, sweeps with moves]
+  unsigned long long *queue;  // work counter of the persistent sweep kernel
+  uint32_t moving;            // graphs moving at the start of the level
 };
 
 // A stream of the library's own to record graphs on (the caller's stream may be the
@@ -260,46 +286,45 @@ struct CaptureStream {
 
 static void level_sweeps(LevelSweeps &L, const mgcd_params *p, const Schedule &sch,
                          CaptureStream *capture, hipStream_t st) {
-  // sweeps it0 .. it0+n-1 on stream s (label buffers swapped after each)
-  auto issue = [&](int it0, int n, hipStream_t s) {
-    for (int it = it0; it < it0 + n; ++it) {
+  const int total = p->max_iterations;
+  // every sweep of the level on stream s (label buffers swapped after each)
+  auto issue = [&](hipStream_t s) {
+    int32_t *C[2] = {L.C[0], L.C[1]};
+    for (int it = 0; it < total; ++it) {
       const int dir = L.algo == ALGO_LPA ? 0 : (it % 2 == 0 ? -1 : 1);
-      SweepArgs args{L.g, L.C[0], nullptr, L.K, L.Sig, 0, dir, L.C[1], nullptr, L.gctr};
+      SweepArgs args{L.g, C[0], nullptr, L.K, L.Sig, 0, dir, C[1], nullptr, L.gctr};
       args.gid = L.gid;
       args.Wg = L.Wg;
       args.active = L.active;
       args.gctr = L.gctr;
+      args.live = L.lv;
+      args.queue = L.queue;
       args.one_scan = L.algo == ALGO_LPA ? p->one_scan : 0;
       launch_sweep(args, sch, L.algo, p->mode, p->k, p->chunk_len, s);
-      if (L.algo != ALGO_LPA) launch_apply_moves(L.C[0], L.C[1], L.K, L.Sig, L.g.n, s);
+      if (L.algo != ALGO_LPA) {
+        LevelRule r;
+        r.live = L.lv;
+        launch_apply_moves(C[0], C[1], L.K, L.Sig, L.g.n, s, &r);
+      }
       if (L.algo == ALGO_LPA)
-        k_batch_converge<ALGO_LPA><<<grid_for(L.count), BLOCK, 0, s>>>(
-            L.gctr, L.active, L.stat, L.nent, L.nvert, L.Wg64, L.tol, L.count);
+        k_batch_converge<ALGO_LPA><<<1, BLOCK, 0, s>>>(L.gctr, L.active, L.stat, L.nent, L.nvert, L.Wg64,
+                                                      L.tol, L.count, L.lv, L.queue);
       else
-        k_batch_converge<ALGO_MOVE><<<grid_for(L.count), BLOCK, 0, s>>>(
-            L.gctr, L.active, L.stat, L.nent, L.nvert, L.Wg64, L.tol, L.count);
+        k_batch_converge<ALGO_MOVE><<<1, BLOCK, 0, s>>>(L.gctr, L.active, L.stat, L.nent, L.nvert, L.Wg64,
+                                                       L.tol, L.count, L.lv, L.queue);
       MGCD_LAUNCHED();
-      std::swap(L.C[0], L.C[1]);
+      std::swap(C[0], C[1]);
     }
   };
-  std::vector<uint8_t> flags(L.count);
-  auto any_moving = [&]() {
-    MGCD_HIP(hipMemcpyAsync(flags.data(), L.active, L.count, hipMemcpyDeviceToHost, st));
-    MGCD_HIP(hipStreamSynchronize(st));
-    for (uint8_t f : flags)
-      if (f) return true;
-    return false;
-  };
-  const int total = p->max_iterations;
-  int done = 0;
-  bool moving = true;
-  if (capture && total >= SEG) {
+  k_level_start<<<1, 1, 0, st>>>(L.lv, L.moving, L.queue);
+  MGCD_LAUNCHED();
+  if (capture && total > 0) {
     hipStream_t cs = capture->get();
     hipGraph_t graph = nullptr;
     MGCD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     in_capture = true;
     try {
-      issue(0, SEG, cs);
+      issue(cs);
     } catch (...) {
       in_capture = false;
       (void)hipStreamEndCapture(cs, &graph);
@@ -310,22 +335,18 @@ static void level_sweeps(LevelSweeps &L, const mgcd_params *p, const Schedule &s
     MGCD_HIP(hipStreamEndCapture(cs, &graph));
     hipGraphExec_t exec = nullptr;
     hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    while (e == hipSuccess && moving && done + SEG <= total) {
-      e = hipGraphLaunch(exec, st);  // on the caller's stream, after its earlier work
-      done += SEG;
-      if (e == hipSuccess) moving = any_moving();
-    }
+    if (e == hipSuccess) e = hipGraphLaunch(exec, st);  // on the caller's stream, after its work
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (exec) (void)hipGraphExecDestroy(exec);
     (void)hipGraphDestroy(graph);
     MGCD_HIP(e);
+  } else {
+    issue(st);
   }
-  while (moving && done < total) {
-    const int n = std::min(SEG, total - done);
-    issue(done, n, st);
-    done += n;
-    moving = any_moving();
-  }
+  uint32_t h[2] = {0, 0};
+  MGCD_HIP(hipMemcpyAsync(h, L.lv, sizeof(h), hipMemcpyDeviceToHost, st));
   MGCD_HIP(hipStreamSynchronize(st));
+  if (h[1] % 2 == 1) std::swap(L.C[0], L.C[1]);  // an odd count of real sweeps ends in C[1]
 }
 
 void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_params *p,
@@ -440,6 +461,13 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
   CaptureStream cstream;
   CaptureStream *capture = p->direct_launch == 0 ? &cstream : nullptr;
   long long *stat = a.take<long long>(3 * (int64_t)count);
+  uint32_t *lvd = a.take<uint32_t>(2);
+  unsigned long long *queue = a.take<unsigned long long>(1);
+  auto moving = [&]() {
+    uint32_t c = 0;
+    for (uint8_t f : active) c += f ? 1u : 0u;
+    return c;
+  };
   int64_t *nent_d = a.take<int64_t>(count);
   int64_t *nvert_d = a.take<int64_t>(count);
   // per-level stats from the device: sweeps, entries, movers per graph
@@ -472,7 +500,8 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
     launch_zero_u64(gctr, 3 * count, st);
     if (N > 0 && p->max_iterations > 0) {
       LevelSweeps lv{ALGO_LPA, U, {Ca, Cb}, Kbuf[0], nullptr, b.gid0, Wg, Wg64,
-                     active_d, gctr, stat, nent_d, nvert_d, count, p->tolerance};
+                     active_d, gctr, stat, nent_d, nvert_d, count, p->tolerance,
+                     lvd, queue, moving()};
       tm.start();
       level_sweeps(lv, p, sch, capture, st);
       ms_lm += tm.stop();
@@ -540,7 +569,8 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
       launch_zero_u64(gctr, 3 * count, st);
       {
         LevelSweeps lv{ALGO_MOVE, cur, {Ca, Cb}, K, Sig, gid_cur, Wg, Wg64,
-                       active_d, gctr, stat, nent_d, nvert_d, count, tol};
+                       active_d, gctr, stat, nent_d, nvert_d, count, tol,
+                       lvd, queue, moving()};
         tm.start();
         level_sweeps(lv, p, sch, capture, st);
         ms_lm += tm.stop();

@@ -51,6 +51,11 @@ __device__ inline bool frozen(const SweepArgs &a, int32_t i) {
   return (a.halt && *a.halt) || (a.gid && !a.active[a.gid[i]]);
 }
 
+// Batched runs: no graph moves any more (set after the previous sweep), so this sweep
+// does nothing at all and the labels stay in the buffer the last real sweep wrote.
+// Wave-uniform (written before the kernel started).
+__device__ inline bool level_over(const SweepArgs &a) { return a.live && *a.live == 0; }
+
 // Evaluate candidate c (present: it exists) with exact linking weight kc and
 // community total sc; keep the best.  Branch-free, so gathers feeding sc are issued
 // together rather than each inside a branch of its own.
@@ -339,6 +344,7 @@ template <int K, int ALGO>
 __global__ void __launch_bounds__(BLOCK) MGCD_SKETCH_OCCUPANCY(K)
     k_long_merge(SweepArgs a, const int32_t *__restrict__ multi, const int64_t *__restrict__ gstart,
                  Pair *sk, const uint32_t *__restrict__ skflag, Pair *cand, uint32_t *cflag) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   __shared__ Pair lds[BLOCK * K];
   __shared__ int flag_any;
   const int t = threadIdx.x;
@@ -389,6 +395,7 @@ __global__ void __launch_bounds__(BLOCK)
                  const int64_t *__restrict__ cstart, int64_t nchunks, int64_t L,
                  const Pair *__restrict__ cand, const uint32_t *__restrict__ cflag,
                  const uint32_t *__restrict__ keybuf, uint32_t *part) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   const int64_t q = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
   if (q >= nchunks) return;
   const int32_t m = owner[q];
@@ -437,6 +444,7 @@ __global__ void __launch_bounds__(BLOCK)
     k_long_decide(SweepArgs a, const int32_t *__restrict__ multi, const int64_t *__restrict__ cstart,
                   const Pair *__restrict__ cand, const uint32_t *__restrict__ cflag,
                   const uint32_t *__restrict__ part) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   __shared__ uint32_t red[K + 1][BLOCK / WAVE];
   const int32_t m = blockIdx.x;
   if (cflag[m] != 1) return;  // block-uniform
@@ -594,15 +602,32 @@ __device__ inline void row_work(const SweepArgs &a, const Buckets &bk, int64_t L
 template <int K, int ALGO, int MODE>
 __global__ void __launch_bounds__(BLOCK) MGCD_ROWS_OCCUPANCY(K)
     k_move_rows(SweepArgs a, const Buckets *__restrict__ bkp, int64_t L, uint32_t *keybuf) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   const Buckets &bk = *bkp;
   __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
   uint32_t *const win = swin[threadIdx.x / WAVE];
-  const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
   Counters ct;
-  if (wave < bk.ngroups)
-    long_group<K, ALGO, MODE>(a, bk, L, keybuf, win, wave);
-  else
-    row_work<K, ALGO, MODE>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
+  if (a.queue) {
+    // persistent: every wave takes work items from the device counter, in the grid's
+    // order (long-row groups, then the row buckets heaviest first), until none is left
+    const int64_t total = bk.ngroups + bk.wave_end[0];
+    for (;;) {
+      unsigned long long w0 = 0;
+      if (lane_id() == 0) w0 = atomicAdd(a.queue, 1ull);
+      const int64_t wave = uniform((int64_t)__shfl(w0, 0));
+      if (wave >= total) break;
+      if (wave < bk.ngroups)
+        long_group<K, ALGO, MODE>(a, bk, L, keybuf, win, wave);
+      else
+        row_work<K, ALGO, MODE>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
+    }
+  } else {
+    const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
+    if (wave < bk.ngroups)
+      long_group<K, ALGO, MODE>(a, bk, L, keybuf, win, wave);
+    else
+      row_work<K, ALGO, MODE>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
+  }
   flush_counters(a, ct);
 }
 
@@ -621,6 +646,7 @@ template <int K, int ALGO, int MODE, int DEPTH>
 __global__ void __launch_bounds__(BLOCK)
     k_wave_rows(SweepArgs a, const int32_t *__restrict__ rows, int64_t nrows, int64_t L,
                 uint32_t *keybuf) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   __shared__ uint32_t sstack[BLOCK / WAVE][DEPTH * 2 * WAVE];
   const int lane = lane_id();
   const int64_t r = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
@@ -727,6 +753,7 @@ __global__ void __launch_bounds__(BLOCK)
     k_wave_chunks(SweepArgs a, const int32_t *__restrict__ rows, const int64_t *__restrict__ cstart,
                   const int32_t *__restrict__ owner, int64_t nchunks, int64_t L, uint32_t *keybuf,
                   Pair *node, uint32_t *nflag, uint32_t *count) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   const int lane = lane_id();
   const int64_t q = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
   if (q >= nchunks) return;
@@ -770,6 +797,7 @@ __global__ void __launch_bounds__(BLOCK)
     k_wave_level(SweepArgs a, const int32_t *__restrict__ rows, const int64_t *__restrict__ cstart,
                  const int32_t *__restrict__ owner, int64_t nchunks, int level, Pair *node,
                  uint32_t *nflag) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   const int lane = lane_id();
   const int64_t q = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
   if (q >= nchunks) return;
@@ -812,6 +840,7 @@ __global__ void __launch_bounds__(BLOCK)
                  const int32_t *__restrict__ owner, int64_t nchunks, int64_t L,
                  const uint32_t *__restrict__ keybuf, const Pair *__restrict__ node,
                  const uint32_t *__restrict__ nflag, uint32_t *count) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   const int lane = lane_id();
   const int64_t q = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
   if (q >= nchunks) return;
@@ -848,6 +877,7 @@ __global__ void __launch_bounds__(BLOCK)
     k_wave_decide(SweepArgs a, const int32_t *__restrict__ rows, const int64_t *__restrict__ cstart,
                   int64_t nrows, const Pair *__restrict__ node, const uint32_t *__restrict__ nflag,
                   const uint32_t *__restrict__ count) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   const int lane = lane_id();
   const int64_t m = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
   Counters ct;
@@ -954,6 +984,7 @@ __device__ inline void exact_row_regs(const SweepArgs &a, int32_t i, int32_t bi,
 template <int ALGO>
 __global__ void __launch_bounds__(BLOCK)
     k_exact_small(SweepArgs a, const int32_t *__restrict__ list, int64_t count) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   Counters ct;
   int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const bool listed = t < count;
@@ -1019,6 +1050,7 @@ __device__ inline uint32_t hash_slot(uint32_t c, uint32_t mask) {
 template <int ALGO, bool SMALL = false>
 __global__ void __launch_bounds__(BLOCK)
     k_exact_wave(SweepArgs a, const int32_t *__restrict__ list, int64_t count) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   constexpr uint32_t CAPW = 2 * EXACT_T1_MAX;
   __shared__ Pair wtab[BLOCK / WAVE][CAPW];
   __shared__ uint32_t wpos[BLOCK / WAVE][SMALL ? CAPW : 1];
@@ -1113,6 +1145,7 @@ __global__ void __launch_bounds__(BLOCK)
 // probing) of CAP slots in LDS.
 template <int ALGO, int CAP, bool SMALL = false>
 __global__ void __launch_bounds__(BLOCK) k_exact_table(SweepArgs a, const int32_t *__restrict__ list) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   __shared__ Pair tab[CAP];
   __shared__ uint32_t pos[SMALL ? CAP : 1];  // small table: first row position per slot
   __shared__ uint32_t kd_s;
@@ -1235,6 +1268,7 @@ __global__ void __launch_bounds__(BLOCK)
     k_gtab_insert(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
                   const int64_t *__restrict__ sstart, const int32_t *__restrict__ sowner, Pair *htab,
                   uint32_t *hpos) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   // Each round's U * BLOCK entries are first combined in an LDS table (at most U * BLOCK
   // keys in 2 * U * BLOCK slots), then every distinct key goes to the global table
   // once: the entries of a hub row concentrate on a few communities, whose slots
@@ -1313,6 +1347,7 @@ template <int ALGO>
 __global__ void __launch_bounds__(BLOCK)
     k_gtab_kd(SweepArgs a, const int32_t *__restrict__ list, int64_t count, const int64_t *__restrict__ hbase,
               const Pair *__restrict__ htab, uint32_t *kdout) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (r >= count) return;
   const int32_t i = list[r];
@@ -1341,6 +1376,7 @@ __global__ void __launch_bounds__(BLOCK)
     k_gtab_scan(SweepArgs a, const int32_t *__restrict__ list, const int64_t *__restrict__ hbase,
                 const int64_t *__restrict__ tstart, const int32_t *__restrict__ towner, Pair *htab,
                 uint32_t *hpos, const uint32_t *__restrict__ kdin, int32_t *pbest, int64_t *pgain) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   __shared__ int32_t bc[BLOCK / WAVE];
   __shared__ int64_t bg[BLOCK / WAVE];
   const int t = threadIdx.x;
@@ -1400,6 +1436,7 @@ __global__ void __launch_bounds__(BLOCK)
     k_gtab_finish(SweepArgs a, const int32_t *__restrict__ list, int64_t count,
                   const int64_t *__restrict__ tstart, const int32_t *__restrict__ pbest,
                   const int64_t *__restrict__ pgain) {
+  if (level_over(a)) return;  // batched: every graph has stopped
   const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   Counters ct;
   if (r < count) {
@@ -1744,13 +1781,25 @@ static inline void mark(hipEvent_t *ev, int i, hipStream_t st) {
   if (ev) MGCD_HIP(hipEventRecord(ev[i], st));
 }
 
+// Workgroups of the main sweep kernel resident at once on the current device: its LDS
+// windows (36 KiB per workgroup) leave room for four per compute unit.
+static int64_t resident_blocks() {
+  int dev = 0, cus = 0;
+  MGCD_HIP(hipGetDevice(&dev));
+  MGCD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  return 4 * (int64_t)(cus > 0 ? cus : 1);
+}
+
 template <int K, int ALGO, int MODE>
 static void sweep_mg(const SweepArgs &a, const Schedule &s, int64_t L, hipStream_t st, hipEvent_t *ev) {
   mark(ev, 0, st);
   const int64_t waves = s.ngroups + s.row_waves;
   if (waves > 0) {
-    k_move_rows<K, ALGO, MODE><<<(unsigned)ceil_div(waves, BLOCK / WAVE), BLOCK, 0, st>>>(
-        a, s.buckets, L, s.keybuf);
+    // persistent (a.queue): as many workgroups as stay resident at once, each pulling
+    // work until the queue is empty
+    int64_t blocks = ceil_div(waves, BLOCK / WAVE);
+    if (a.queue) blocks = std::min<int64_t>(blocks, (int64_t)resident_blocks());
+    k_move_rows<K, ALGO, MODE><<<(unsigned)blocks, BLOCK, 0, st>>>(a, s.buckets, L, s.keybuf);
     MGCD_LAUNCHED();
   }
   mark(ev, 1, st);
@@ -1910,6 +1959,7 @@ __device__ inline void level_converge(int algo, const LevelRule &r) {
 __global__ void k_apply_moves(const int32_t *Cold, const int32_t *Cnew, const uint32_t *K, uint32_t *Sig,
                               int32_t n, LevelRule rule) {
   int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (rule.live && *rule.live == 0) return;  // batched: the sweep did nothing
   if (rule.ls && i == 0) level_converge(ALGO_MOVE, rule);  // the sweep's counters are final
   if (i >= n) return;
   int32_t d = Cold[i], c = Cnew[i];

@@ -24,6 +24,11 @@ struct SweepArgs {
   const uint32_t *Wg = nullptr;
   const uint8_t *active = nullptr;
   unsigned long long *gctr = nullptr;
+  // Batched runs: graphs still moving after the previous sweep (device); at 0 every
+  // sweep kernel returns at once.  queue: work counter of the persistent main sweep
+  // kernel (zero before the sweep); null launches it with one wave per work item.
+  const uint32_t *live = nullptr;
+  unsigned long long *queue = nullptr;
   // Single graph: a device flag; once set, every vertex keeps its community (the
   // sweep only copies C to C_new).  Null: always move.
   const uint32_t *halt = nullptr;
@@ -65,6 +70,7 @@ struct LevelRule {
   int64_t nnz = 0;  // entries streamed per sweep
   int32_t n = 0;
   double tol = 0, WW = 0;
+  const uint32_t *live = nullptr;  // batched: 0 graphs moving -> no Sigma update
 };
 // After a sweep: apply the rule to the sweep's counters and update the state.
 void launch_level_converge(int algo, const LevelRule &r, hipStream_t st);

@@ -231,15 +231,17 @@ __global__ void __launch_bounds__(BLOCK)
   if (threadIdx.x == 0) {
     lv[0] = still;
     lv[1] += was > 0 ? 1u : 0u;
-    *queue = 0;
   }
+  if (threadIdx.x < QLANES) queue[threadIdx.x * QSTRIDE] = 0;
 }
 
 // Start of a level: lv = {graphs moving, sweeps with moves so far = 0}, queue empty.
 __global__ void k_level_start(uint32_t *lv, uint32_t moving, unsigned long long *queue) {
-  lv[0] = moving;
-  lv[1] = 0;
-  *queue = 0;
+  if (threadIdx.x == 0) {
+    lv[0] = moving;
+    lv[1] = 0;
+  }
+  if (threadIdx.x < QLANES) queue[threadIdx.x * QSTRIDE] = 0;
 }
 
 // One level's local-moving sweeps for every graph of the batch, as one device-driven
@@ -316,7 +318,7 @@ static void level_sweeps(LevelSweeps &L, const mgcd_params *p, const Schedule &s
       std::swap(C[0], C[1]);
     }
   };
-  k_level_start<<<1, 1, 0, st>>>(L.lv, L.moving, L.queue);
+  k_level_start<<<1, QLANES, 0, st>>>(L.lv, L.moving, L.queue);
   MGCD_LAUNCHED();
   if (capture && total > 0) {
     hipStream_t cs = capture->get();
@@ -462,7 +464,7 @@ void run_batched(int algo, const mgcd_csr *graphs, int32_t count, const mgcd_par
   CaptureStream *capture = p->direct_launch == 0 ? &cstream : nullptr;
   long long *stat = a.take<long long>(3 * (int64_t)count);
   uint32_t *lvd = a.take<uint32_t>(2);
-  unsigned long long *queue = a.take<unsigned long long>(1);
+  unsigned long long *queue = a.take<unsigned long long>((int64_t)QLANES * QSTRIDE);
   auto moving = [&]() {
     uint32_t c = 0;
     for (uint8_t f : active) c += f ? 1u : 0u;

@@ -608,18 +608,25 @@ __global__ void __launch_bounds__(BLOCK) MGCD_ROWS_OCCUPANCY(K)
   uint32_t *const win = swin[threadIdx.x / WAVE];
   Counters ct;
   if (a.queue) {
-    // persistent: every wave takes work items from the device counter, in the grid's
-    // order (long-row groups, then the row buckets heaviest first), until none is left
+    // persistent: every wave takes work items from its counter of the queue (the
+    // items of the grid's order -- long-row groups, then the row buckets heaviest
+    // first -- whose index is c mod QLANES), QGRAB at a time, until none is left
     const int64_t total = bk.ngroups + bk.wave_end[0];
+    const int c = (int)(((int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE) % QLANES);
+    unsigned long long *q = a.queue + (int64_t)c * QSTRIDE;
     for (;;) {
-      unsigned long long w0 = 0;
-      if (lane_id() == 0) w0 = atomicAdd(a.queue, 1ull);
-      const int64_t wave = uniform((int64_t)__shfl(w0, 0));
-      if (wave >= total) break;
-      if (wave < bk.ngroups)
-        long_group<K, ALGO, MODE>(a, bk, L, keybuf, win, wave);
-      else
-        row_work<K, ALGO, MODE>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
+      unsigned long long j0 = 0;
+      if (lane_id() == 0) j0 = atomicAdd(q, (unsigned long long)QGRAB);
+      const int64_t j = uniform((int64_t)__shfl(j0, 0));
+      if (c + j * QLANES >= total) break;
+      for (int t = 0; t < QGRAB; ++t) {
+        const int64_t wave = c + (j + t) * QLANES;  // wave-uniform
+        if (wave >= total) break;
+        if (wave < bk.ngroups)
+          long_group<K, ALGO, MODE>(a, bk, L, keybuf, win, wave);
+        else
+          row_work<K, ALGO, MODE>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
+      }
     }
   } else {
     const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform

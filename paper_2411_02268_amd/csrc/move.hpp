@@ -25,8 +25,9 @@ struct SweepArgs {
   const uint8_t *active = nullptr;
   unsigned long long *gctr = nullptr;
   // Batched runs: graphs still moving after the previous sweep (device); at 0 every
-  // sweep kernel returns at once.  queue: work counter of the persistent main sweep
-  // kernel (zero before the sweep); null launches it with one wave per work item.
+  // sweep kernel returns at once.  queue: the QLANES work counters of the persistent
+  // main sweep kernel (QSTRIDE apart, zero before the sweep); null launches it with
+  // one wave per work item.
   const uint32_t *live = nullptr;
   unsigned long long *queue = nullptr;
   // Single graph: a device flag; once set, every vertex keeps its community (the
@@ -75,6 +76,12 @@ struct LevelRule {
 // After a sweep: apply the rule to the sweep's counters and update the state.
 void launch_level_converge(int algo, const LevelRule &r, hipStream_t st);
 void launch_zero_state(LevelState *ls, hipStream_t st);
+
+// The persistent main sweep kernel's work queue: QLANES counters, each on a cache line
+// of its own (QSTRIDE u64 apart); counter c hands out work items c, c + QLANES, ...
+// (an interleaved share of the heaviest-first order), QGRAB at a time, so that the
+// waves' atomics spread over QLANES addresses and a grab serves many items.
+constexpr int QLANES = 64, QSTRIDE = 16, QGRAB = 16;
 
 // Row buckets of the main sweep kernel: rows needing 2^b lanes (b = 0..6).
 // The grid of the main sweep kernel: first one wave per group of 64 chunks of the

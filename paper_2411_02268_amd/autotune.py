@@ -14,7 +14,7 @@ import time
 
 import numpy as np
 
-SKETCH_K = (1, 2, 4, 8, 16)
+SKETCH_K = (1, 2, 4, 8, 16, 32, 64)
 ROW_LANES = (8, 16, 32, 64)
 EXACT_TIERS = ((32, 512, 4096), (16, 256, 4096), (64, 512, 4096), (32, 128, 2048))
 

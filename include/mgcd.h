@@ -115,6 +115,12 @@ typedef struct {
                              2 decouple aggregation from local moving, to measure
                              how much of a sketch's modularity loss each phase
                              causes                                                 */
+  /* Schedule only (never changes results): */
+  int32_t storage_order;  /* level-0 local moving on a copy of the input with vertices
+                             in descending degree (rows, their order and every
+                             community id unchanged; the neighbours' labels that
+                             sweeps gather share cache lines): 0 (default) when the
+                             input has at least 2^26 entries, 1 never, 2 always      */
 } mgcd_params;
 
 typedef struct {

@@ -40,7 +40,8 @@ class Params(ct.Structure):
                 ("aggregation_tolerance", ct.c_double), ("row_lanes", ct.c_int32),
                 ("exact_small", ct.c_int32), ("exact_lds", ct.c_int32),
                 ("exact_lds_big", ct.c_int32), ("direct_launch", ct.c_int32),
-                ("one_scan", ct.c_int32), ("aggregation", ct.c_int32)]
+                ("one_scan", ct.c_int32), ("aggregation", ct.c_int32),
+                ("storage_order", ct.c_int32)]
 
 
 class Stats(ct.Structure):

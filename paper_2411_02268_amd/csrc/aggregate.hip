@@ -601,6 +601,76 @@ __global__ void __launch_bounds__(BLOCK)
   }
 }
 
+// ---- storage copy in degree order ---------------------------------------------------
+
+__global__ void k_degree_keys(const int64_t *off, int32_t n, int64_t nnz, uint64_t *key, uint32_t *val) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  key[i] = (uint64_t)(nnz - (off[i + 1] - off[i]));  // descending degree; stable sort: ascending id
+  val[i] = (uint32_t)i;
+}
+
+__global__ void k_place(const uint32_t *perm, const int64_t *off, const uint32_t *K, int32_t n, int32_t *pos,
+                        int64_t *deg, uint32_t *Kp) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t v = perm[p];
+  pos[v] = (int32_t)p;
+  deg[p] = off[v + 1] - off[v];
+  Kp[p] = K[v];
+}
+
+__global__ void k_row_places(const int32_t *pos, const int64_t *offp, int32_t n, int64_t *rowpos) {
+  const int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v < n) rowpos[v] = offp[pos[v]];
+}
+
+size_t storage_ws_bytes(int32_t n, int64_t nnz) {
+  size_t b = (size_t)(n + 1) * 8 + (size_t)nnz * 8 + 4096;       // offsets, indices, weights
+  b += (size_t)n * (4 + 4 + 4) + 4096;                            // perm, pos, K
+  b += (size_t)n * (8 + 4) * 2 + radix_sort_ws_bytes(n) + 4096;   // degree sort (released)
+  b += (size_t)n * 8 * 2 + scan_ws_bytes((int64_t)n + 1) + 8192;  // degrees, row places (released)
+  return b;
+}
+
+StorageCopy storage_copy(const Graph &g, const uint32_t *K, Arena &a, hipStream_t st) {
+  const int32_t n = g.n;
+  StorageCopy s{};
+  int64_t *offp = a.take<int64_t>((int64_t)n + 1);
+  int32_t *idxp = a.take<int32_t>(g.nnz);
+  uint32_t *wp = a.take<uint32_t>(g.nnz);
+  uint32_t *perm = a.take<uint32_t>(n);
+  s.pos = a.take<int32_t>(n);
+  s.Kp = a.take<uint32_t>(n);
+  s.perm = reinterpret_cast<int32_t *>(perm);
+  s.g = Graph{n, g.nnz, offp, idxp, wp};
+  if (n == 0) {
+    launch_zero_u64(reinterpret_cast<unsigned long long *>(offp), 1, st);
+    return s;
+  }
+  const size_t mk = a.mark();
+  uint64_t *k0 = a.take<uint64_t>(n), *k1 = a.take<uint64_t>(n);
+  uint32_t *v0 = a.take<uint32_t>(n), *v1 = a.take<uint32_t>(n);
+  k_degree_keys<<<grid_for(n), BLOCK, 0, st>>>(g.off, n, g.nnz, k0, v0);
+  MGCD_LAUNCHED();
+  const bool flip = radix_sort_pairs(k0, v0, k1, v1, n, bits_for((uint64_t)g.nnz), a, st);
+  MGCD_HIP(hipMemcpyAsync(perm, flip ? v1 : v0, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  int64_t *deg = a.take<int64_t>(n);
+  k_place<<<grid_for(n), BLOCK, 0, st>>>(perm, g.off, K, n, s.pos, deg, s.Kp);
+  MGCD_LAUNCHED();
+  scan_i64(deg, offp, n, offp + n, a, st);
+  int64_t *rowpos = a.take<int64_t>(n);
+  k_row_places<<<grid_for(n), BLOCK, 0, st>>>(s.pos, offp, n, rowpos);
+  MGCD_LAUNCHED();
+  if (g.nnz > 0) {  // entries in source order (coalesced reads), written at their new places
+    k_agg_streamify<<<(unsigned)ceil_div(g.nnz, SF_TILE), BLOCK, 0, st>>>(
+        g, s.pos, rowpos, reinterpret_cast<uint32_t *>(idxp), wp);
+    MGCD_LAUNCHED();
+  }
+  a.release(mk);
+  return s;
+}
+
 __global__ void k_row_starts(const int64_t *off, const uint32_t *mem, int32_t n, int64_t *rs) {
   int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (t < n) rs[t] = off[mem[t]];

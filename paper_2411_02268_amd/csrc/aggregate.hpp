@@ -37,6 +37,18 @@ void launch_scatter_labels(const int32_t *map, const int32_t *val, int32_t *out,
 void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, Arena &a, hipStream_t st);
 size_t degrees_ws_bytes(int64_t nnz);
 
+// Storage copy of a graph for local moving: vertices laid out in descending degree
+// (ties: ascending id), each row's entries unchanged and in their order, indices
+// translated to positions.  perm[p] = vertex at position p, pos[v] = position of v,
+// Kp[p] = K[perm[p]].  Arrays are taken from `a` (storage_ws_bytes of them).
+struct StorageCopy {
+  Graph g;
+  int32_t *perm, *pos;
+  uint32_t *Kp;
+};
+StorageCopy storage_copy(const Graph &g, const uint32_t *K, Arena &a, hipStream_t st);
+size_t storage_ws_bytes(int32_t n, int64_t nnz);
+
 // Canonical labels: communities numbered in order of their smallest vertex.
 // Returns the number of communities (synchronises the stream).
 int32_t canonical(const int32_t *C, int32_t n, int32_t *out, Arena &a, hipStream_t st);

@@ -66,6 +66,7 @@ static void check_params(const mgcd_params *p) {
     throw Error(MGCD_E_UNSUPPORTED, "k must be 1, 2, 4, 8, 16, 32 or 64");
   }
   if (p->aggregation < 0 || p->aggregation > 2) throw Error(MGCD_E_ARG, "aggregation must be 0, 1 or 2");
+  if (p->storage_order < 0 || p->storage_order > 2) throw Error(MGCD_E_ARG, "storage_order must be 0, 1 or 2");
   if (agg_mode(p) != MGCD_MODE_EXACT && !okk(p->k_aggregate))
     throw Error(MGCD_E_UNSUPPORTED, "k_aggregate must be 1, 2, 4, 8, 16, 32 or 64");
   if (p->chunk_len < 1) throw Error(MGCD_E_ARG, "chunk_len must be >= 1");
@@ -82,6 +83,16 @@ static void check_params(const mgcd_params *p) {
   const SchedParams sp = sched_params(p);
   if (sp.exact_t1 > EXACT_T1_MAX || sp.exact_t2 > EXACT_T2_MAX)
     throw Error(MGCD_E_ARG, "exact tier bounds must be at most 512 (exact_lds) and 4096 (exact_lds_big)");
+}
+
+// Level-0 local moving on the degree-ordered storage copy (schedule only): asked for,
+// or by default when the input is large enough for the label gathers to miss the
+// caches (the copy costs about one sweep's traffic; measured on R-MAT 2^20, 3.1e7
+// entries, it saved less than it cost over the four level-0 sweeps, on Chung-Lu
+// 2^24, 5.4e8 entries, a third of every sweep).
+constexpr int64_t STORAGE_AUTO_NNZ = (int64_t)1 << 26;
+static bool use_storage(const mgcd_params *p, int64_t nnz) {
+  return p->storage_order == 2 || (p->storage_order == 0 && nnz >= STORAGE_AUTO_NNZ);
 }
 
 static Graph view(const mgcd_csr *g) {
@@ -170,9 +181,23 @@ static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Are
   int32_t *Ca = a.take<int32_t>(n), *Cb = a.take<int32_t>(n);
   unsigned long long *ctr = a.take<unsigned long long>(4);
   launch_iota(Ca, n, st);
-  launch_iota(Cb, n, st);  // rows without entries are in no sweep: both buffers hold them
+  // sweeps on the degree-ordered copy (labels by position, values the communities'
+  // own ids), or on the input
+  const bool sto = use_storage(p, g.nnz);
+  StorageCopy sc{};
+  Graph gs = g;
+  uint32_t *Ks = K;
+  int32_t *Ck = Ca;  // the labels the caller sees, by vertex
+  if (sto) {
+    sc = storage_copy(g, K, a, st);
+    gs = sc.g;
+    Ks = sc.Kp;
+    Ca = a.take<int32_t>(n);
+    launch_compose(sc.perm, Ck, Ca, n, st);  // Ca[p] = C[perm[p]]
+  }
+  if (n > 0) MGCD_HIP(hipMemcpyAsync(Cb, Ca, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
   Schedule sch;
-  build_schedule(g, sched_params(p), sch, a, st);
+  build_schedule(gs, sched_params(p), sch, a, st);
   LevelState *ls = a.take<LevelState>(1);
   mgcd_stats s{};
   ClassTimer ct;
@@ -181,7 +206,7 @@ static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Are
   launch_zero_state(ls, st);
   if (n > 0) {
     LevelState h = run_sweeps(p->max_iterations, ls, st, &ct, s, [&](int, int j) {
-      SweepArgs args{g, Ca, nullptr, K, nullptr, 0, 0, Cb, nullptr, ctr};
+      SweepArgs args{gs, Ca, nullptr, Ks, nullptr, 0, 0, Cb, nullptr, ctr};
       args.halt = &ls->halt;
       args.one_scan = p->one_scan;
       launch_sweep(args, sch, ALGO_LPA, p->mode, p->k, p->chunk_len, st, ct.ev[j]);
@@ -191,6 +216,10 @@ static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Are
     s.iterations = h.sweeps;
     s.edges_scanned = (int64_t)h.edges;
     s.moved_last = (int64_t)h.moved_last;
+  }
+  if (sto) {  // back to vertices: C[v] = Ca[pos[v]]
+    launch_compose(sc.pos, Ca, Ck, n, st);
+    Ca = Ck;
   }
   const float ms_lm = lm.stop();
   s.communities = canonical(Ca, n, out, a, st);
@@ -248,23 +277,44 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
     size_t mark = a.mark();
     Schedule sch;
     tm.start();
-    build_schedule(cur, sched_params(p), sch, a, st);
     if (!leiden) launch_iota(Ca, nl, st);
+    // level 0 may move on the degree-ordered copy: labels by position whose values are
+    // the communities' own ids (keys, ties, directions and Sigma unchanged)
+    const bool sto = pass == 0 && use_storage(p, cur.nnz);
+    StorageCopy sc{};
+    Graph gm = cur;
+    uint32_t *Km = K;
+    int32_t *Cv = Ca, *Cw = Cb;  // the vertex-space buffers
+    if (sto) {
+      sc = storage_copy(cur, K, a, st);
+      gm = sc.g;
+      Km = sc.Kp;
+      Ca = a.take<int32_t>(nl);
+      Cb = a.take<int32_t>(nl);
+      launch_compose(sc.perm, Cv, Ca, nl, st);  // Ca[p] = C[perm[p]]
+    }
+    build_schedule(gm, sched_params(p), sch, a, st);
     // rows without entries are in no sweep: both label buffers start equal
     if (nl > 0) MGCD_HIP(hipMemcpyAsync(Cb, Ca, (size_t)nl * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-    launch_community_totals(Ca, K, Sig, nl, st);
+    launch_community_totals(Ca, Km, Sig, nl, st);
     launch_zero_u64(ctr, 4, st);
     launch_zero_state(ls, st);
     LevelState h = run_sweeps(p->max_iterations, ls, st, pass == 0 ? &ct : nullptr, s, [&](int it, int j) {
-      SweepArgs args{cur, Ca, nullptr, K, Sig, W, (it % 2 == 0) ? -1 : 1, Cb, nullptr, ctr};
+      SweepArgs args{gm, Ca, nullptr, Km, Sig, W, (it % 2 == 0) ? -1 : 1, Cb, nullptr, ctr};
       args.halt = &ls->halt;
       launch_sweep(args, sch, ALGO_MOVE, p->mode, p->k, p->chunk_len, st, pass == 0 ? ct.ev[j] : nullptr);
       // a sweep without positive moves, or a halted one, leaves C_new equal to C; the
       // same launch applies the stopping rule to this sweep's counters
       const LevelRule rule{ctr, ls, cur.nnz, nl, tol, WW};
-      launch_apply_moves(Ca, Cb, K, Sig, nl, st, &rule);
+      launch_apply_moves(Ca, Cb, Km, Sig, nl, st, &rule);
       std::swap(Ca, Cb);
     });
+    if (sto) {  // back to vertices: C[v] = Ca[pos[v]]; refinement needs the input's schedule
+      launch_compose(sc.pos, Ca, Cv, nl, st);
+      Ca = Cv;
+      Cb = Cw;
+      if (leiden) build_schedule(cur, sched_params(p), sch, a, st);
+    }
     ms_lm += tm.stop();
     if (pass == 0) s.l0_candidates = (int64_t)h.cands;
     s.iterations += h.sweeps;
@@ -331,6 +381,10 @@ static size_t workspace_bytes(int32_t algo, int32_t n, int64_t nnz, const mgcd_p
   size_t fixed = (size_t)n * 4 * 16 + 64 * 1024;
   if (algo != MGCD_ALGO_LPA) fixed += 2 * ((size_t)(n + 1) * 8 + (size_t)nnz * 8) + 4096;
   size_t sched = schedule_ws_bytes(n, nnz, sched_mode(p), p->k, L);
+  // level 0 on the storage copy: the copy and two label buffers by position beside the
+  // schedule of the copy (Leiden: and of the input, for the refinement)
+  if (use_storage(p, nnz))
+    sched = storage_ws_bytes(n, nnz) + (size_t)n * 8 + 8192 + sched * (algo == MGCD_ALGO_LEIDEN ? 2 : 1);
   size_t agg = algo == MGCD_ALGO_LPA ? 0 : aggregate_ws_bytes(n, nnz, agg_mode(p), p->k_aggregate, L, algo == MGCD_ALGO_LEIDEN);
   size_t misc = (size_t)n * (4 + 4 + 8 + 8) + scan_ws_bytes((int64_t)n + 1) + 16 * 1024;
   size_t degrees = degrees_ws_bytes(nnz);

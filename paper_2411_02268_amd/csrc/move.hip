@@ -280,7 +280,7 @@ __device__ inline LongChunk long_chunk(const SweepArgs &a, const int32_t *multi,
 // and written to the key stream), then the first six levels of the fixed merge
 // tree with cross-lane shuffles; lane 0 writes the group's root.
 template <int K, int ALGO, int MODE>
-__device__ inline void long_group(const SweepArgs &a, const Buckets &bk, int64_t L,
+__device__ __attribute__((always_inline)) inline void long_group(const SweepArgs &a, const Buckets &bk, int64_t L,
                                   uint32_t *keybuf, uint32_t *win, int64_t w) {
   const int lane = lane_id();
   const int32_t m = bk.gowner[w];
@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(BLOCK)
 //           chunk, then xor-shuffles inside the row's aligned segment;
 //   lane 0 of the segment decides.
 template <int K, int ALGO, int MODE>
-__device__ inline void row_work(const SweepArgs &a, const Buckets &bk, int64_t L, uint32_t *keybuf,
+__device__ __attribute__((always_inline)) inline void row_work(const SweepArgs &a, const Buckets &bk, int64_t L, uint32_t *keybuf,
                                 uint32_t *win, int64_t wave, Counters &ct) {
   const int lane = lane_id();
   // buckets are laid out in the grid from b = 6 down to b = 0 (wave-uniform)
@@ -599,18 +599,27 @@ __device__ inline void row_work(const SweepArgs &a, const Buckets &bk, int64_t L
 // The main sweep kernel: the first bk.ngroups waves sketch the groups of 64 chunks
 // of long rows (their merge, pass 2 and decision follow in k_long_*), the rest
 // take the row buckets.
-template <int K, int ALGO, int MODE>
+template <int K, int ALGO, int MODE, bool PERSIST>
 __global__ void __launch_bounds__(BLOCK) MGCD_ROWS_OCCUPANCY(K)
     k_move_rows(SweepArgs a, const Buckets *__restrict__ bkp, int64_t L, uint32_t *keybuf) {
-  if (level_over(a)) return;  // batched: every graph has stopped
   const Buckets &bk = *bkp;
   __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
   uint32_t *const win = swin[threadIdx.x / WAVE];
-  Counters ct;
-  if (a.queue) {
-    // persistent: every wave takes work items from its counter of the queue (the
-    // items of the grid's order -- long-row groups, then the row buckets heaviest
-    // first -- whose index is c mod QLANES), QGRAB at a time, until none is left
+  if constexpr (!PERSIST) {
+    const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
+    Counters ct;
+    if (wave < bk.ngroups)
+      long_group<K, ALGO, MODE>(a, bk, L, keybuf, win, wave);
+    else
+      row_work<K, ALGO, MODE>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
+    flush_counters(a, ct);
+  } else {
+    // persistent (batched runs): every wave takes work items from its counter of the
+    // queue (the items of the grid's order -- long-row groups, then the row buckets
+    // heaviest first -- whose index is c mod QLANES), QGRAB at a time, until none is
+    // left; nothing at all once every graph has stopped
+    if (level_over(a)) return;
+    Counters ct;
     const int64_t total = bk.ngroups + bk.wave_end[0];
     const int c = (int)(((int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE) % QLANES);
     unsigned long long *q = a.queue + (int64_t)c * QSTRIDE;
@@ -619,6 +628,7 @@ __global__ void __launch_bounds__(BLOCK) MGCD_ROWS_OCCUPANCY(K)
       if (lane_id() == 0) j0 = atomicAdd(q, (unsigned long long)QGRAB);
       const int64_t j = uniform((int64_t)__shfl(j0, 0));
       if (c + j * QLANES >= total) break;
+#pragma unroll 1
       for (int t = 0; t < QGRAB; ++t) {
         const int64_t wave = c + (j + t) * QLANES;  // wave-uniform
         if (wave >= total) break;
@@ -628,14 +638,8 @@ __global__ void __launch_bounds__(BLOCK) MGCD_ROWS_OCCUPANCY(K)
           row_work<K, ALGO, MODE>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
       }
     }
-  } else {
-    const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;  // wave-uniform
-    if (wave < bk.ngroups)
-      long_group<K, ALGO, MODE>(a, bk, L, keybuf, win, wave);
-    else
-      row_work<K, ALGO, MODE>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
+    flush_counters(a, ct);
   }
-  flush_counters(a, ct);
 }
 
 // ---- MG with K = 32 or 64: one wave per row -------------------------------------------
@@ -1804,9 +1808,12 @@ static void sweep_mg(const SweepArgs &a, const Schedule &s, int64_t L, hipStream
   if (waves > 0) {
     // persistent (a.queue): as many workgroups as stay resident at once, each pulling
     // work until the queue is empty
-    int64_t blocks = ceil_div(waves, BLOCK / WAVE);
-    if (a.queue) blocks = std::min<int64_t>(blocks, (int64_t)resident_blocks());
-    k_move_rows<K, ALGO, MODE><<<(unsigned)blocks, BLOCK, 0, st>>>(a, s.buckets, L, s.keybuf);
+    const int64_t blocks = ceil_div(waves, BLOCK / WAVE);
+    if (a.queue)
+      k_move_rows<K, ALGO, MODE, true><<<(unsigned)std::min<int64_t>(blocks, resident_blocks()), BLOCK, 0, st>>>(
+          a, s.buckets, L, s.keybuf);
+    else
+      k_move_rows<K, ALGO, MODE, false><<<(unsigned)blocks, BLOCK, 0, st>>>(a, s.buckets, L, s.keybuf);
     MGCD_LAUNCHED();
   }
   mark(ev, 1, st);

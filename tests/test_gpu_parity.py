@@ -612,3 +612,34 @@ def test_decoupled_aggregation(mg, gname, algo, cfg):
     elab, est = getattr(oracle, algo)(g, **cfg)
     assert np.array_equal(_np(lab), elab)
     assert st["iterations"] == est.iterations and st["passes"] == est.passes
+
+
+@pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12", "planted"])
+@pytest.mark.parametrize("algo", ["lpa", "louvain", "leiden"])
+@pytest.mark.parametrize("cfg", [dict(mode=1, k=8), dict(mode=1, k=2, chunk_len=5),
+                                 dict(mode=0), dict(mode=1, k=64, chunk_len=37),
+                                 dict(mode=5, k=7), dict(mode=3, k=16, chunk_len=3)],
+                         ids=["alg1-k8", "alg1-k2-L5", "exact", "alg1-k64-L37", "small-7", "std-k16-L3"])
+def test_storage_order_changes_nothing(mg, gname, algo, cfg):
+    """Level 0 on the degree-ordered storage copy (forced on): labels and counters equal
+    to the oracle's (and so to the input-order run's)."""
+    g = graph(gname)
+    lab, st = getattr(mg, algo)(mg.to_device(g), storage_order=2, **cfg)
+    elab, est = getattr(oracle, algo)(g, **cfg)
+    assert np.array_equal(_np(lab), elab)
+    assert st["iterations"] == est.iterations and st["passes"] == est.passes
+
+
+def test_storage_order_on_rmat16(mg):
+    """A larger power-law graph with isolated vertices and hub rows on the long-row
+    path: the storage copy gives the input order's labels and statistics."""
+    g = synth.rmat(scale=16, edge_factor=16, seed=44)
+    dg = mg.to_device(g)
+    for algo in ("lpa", "louvain", "leiden"):
+        a, sa = getattr(mg, algo)(dg, storage_order=2)
+        b, sb = getattr(mg, algo)(dg, storage_order=1)
+        assert bool((a == b).all())
+        for key in ("iterations", "passes", "communities", "edges_scanned", "l0_candidates"):
+            assert sa[key] == sb[key], key
+    elab, _ = oracle.louvain(g)
+    assert np.array_equal(_np(mg.louvain(dg, storage_order=2)[0]), elab)

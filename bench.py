@@ -264,18 +264,19 @@ def k_sweep_leg(mg, torch, dg, repeats: int = 3, chunk_len: int = 128):
 
 WORKLOADS = {
     # name: (algorithm, k, graph description, generator -> (CSR, planted communities or None))
+    # (the large graphs sort their edge samples on the GPU: the same CSR as on the host)
     "louvain-mg-k8-rmat20": (
         "louvain", 8, "R-MAT scale 20, edge factor 16, a/b/c=0.57/0.19/0.19, weights U[1,8], seed 2",
-        lambda synth: (synth.rmat(scale=20, edge_factor=16, seed=2), None)),
+        lambda synth: (synth.rmat(scale=20, edge_factor=16, seed=2, device="cuda"), None)),
     "leiden-mg-k16-cl24": (
         "leiden", 16, "Chung-Lu 2^24 vertices, mean degree 32, exponent 2.1, weights U[1,4], seed 3",
-        lambda synth: (synth.chung_lu(n=1 << 24, avg_deg=32, seed=3), None)),
+        lambda synth: (synth.chung_lu(n=1 << 24, avg_deg=32, seed=3, device="cuda"), None)),
     "leiden-mg-k64-cl24": (
         "leiden", 64, "Chung-Lu 2^24 vertices, mean degree 32, exponent 2.1, weights U[1,4], seed 3",
-        lambda synth: (synth.chung_lu(n=1 << 24, avg_deg=32, seed=3), None)),
+        lambda synth: (synth.chung_lu(n=1 << 24, avg_deg=32, seed=3, device="cuda"), None)),
     "louvain-mg-k64-rmat20": (
         "louvain", 64, "R-MAT scale 20, edge factor 16, a/b/c=0.57/0.19/0.19, weights U[1,8], seed 2",
-        lambda synth: (synth.rmat(scale=20, edge_factor=16, seed=2), None)),
+        lambda synth: (synth.rmat(scale=20, edge_factor=16, seed=2, device="cuda"), None)),
     "lpa-mg-k8-planted": (
         "lpa", 8, "planted partition 20 x 500, 12 intra + 4 inter edges per vertex, weight 1, seed 1",
         lambda synth: synth.planted_exact(n_comm=20, comm_size=500, seed=1)),
@@ -306,6 +307,9 @@ def main():
                     help="graphs of the batched leg (0 skips it; default 4096 with the "
                          "default workload, else 0)")
     ap.add_argument("--batch-nmax", type=float, default=2e5)
+    ap.add_argument("--storage-order", type=int, default=0, choices=(0, 1, 2),
+                    help="level-0 storage copy in degree order: 0 by size (default), 1 off, 2 on "
+                         "(schedule only: results are the same)")
     ap.add_argument("--no-quality-split", dest="quality_split", action="store_false",
                     help="skip the modularity of L = 4096 and of aggregation decoupled "
                          "from local moving")
@@ -342,13 +346,14 @@ def main():
     dg = mg.to_device(g)
 
     def run(mode, steps, warm):
+        so = args.storage_order
         for _ in range(warm):
-            fn(dg, mode=mode, k=k, chunk_len=L)
+            fn(dg, mode=mode, k=k, chunk_len=L, storage_order=so)
         torch.cuda.synchronize()
         stats = []
         a = time.perf_counter()
         for _ in range(steps):
-            lab, st = fn(dg, mode=mode, k=k, chunk_len=L)
+            lab, st = fn(dg, mode=mode, k=k, chunk_len=L, storage_order=so)
             stats.append(st)
         torch.cuda.synchronize()
         b = time.perf_counter()
@@ -480,7 +485,10 @@ def main():
         "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": args.workload, "graph": graph_desc, "n": g.n, "nnz": g.nnz,
-                   "k": k, "chunk_len": L, "algorithm": algo_name, "parallelism": "single-gpu"},
+                   "k": k, "chunk_len": L, "algorithm": algo_name, "parallelism": "single-gpu",
+                   "storage_order": args.storage_order,
+                   "level0_storage_copy": args.storage_order == 2 or
+                                          (args.storage_order == 0 and g.nnz >= (1 << 26))},
         "modularity": {"mg": q_mg, "exact": q_x, "ratio": q_mg / q_x if q_x else None,
                        "split": split},
         "ground_truth": ground_truth,

@@ -31,15 +31,18 @@ sys.path.insert(0, ROOT)
 METRIC = "local-move edges/s (sketch vs exact), batched p99 latency, equal modularity"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 
-# HBM bytes of one level-0 k_move_rows launch on this workload, from FETCH_SIZE and
-# WRITE_SIZE (rocprofv3 --pmc, one counter per run) scaled by what the counters read
-# for a 512 MiB device copy (FETCH x 2.0, WRITE x 1.0); the commands and figures are in
-# profiles/k_move_rows_rmat20_counters.md.  Valid only for the kernel sources they were
-# taken on: SOURCES_SHA256 is checked at run time, and traffic is reported as null when
-# the sources differ.
-TRAFFIC_BYTES = 2432803647
+# HBM bytes of one level-0 launch of the main sweep kernel, per workload and whether
+# level 0 ran on the storage copy, from FETCH_SIZE and WRITE_SIZE (rocprofv3 --pmc, one
+# counter per run) scaled by what the counters read for a 512 MiB device copy (FETCH
+# x 2.0, WRITE x 1.0); commands and figures in profiles/k_move_rows_rmat20_counters.md
+# and profiles/k_move_rows_cl24_leiden_counters.md.  Valid only for the kernel sources
+# they were taken on: SOURCES_SHA256 is checked at run time, and traffic is reported as
+# null when the sources differ.
+TRAFFIC_BYTES = {("louvain-mg-k8-rmat20", False): 2406600565,
+                 ("leiden-mg-k16-cl24", False): 106665441721,
+                 ("leiden-mg-k16-cl24", True): 80185015294}
 TRAFFIC_SOURCES = ["csrc/move.hip", "csrc/move.hpp", "csrc/sketch.hpp", "csrc/common.hpp", "csrc/staging.hpp"]
-TRAFFIC_SOURCES_SHA256 = "785c556d8280c4cbc8c5a9359b87a68656b76a8813d371271ad5113411069408"
+TRAFFIC_SOURCES_SHA256 = "d2c8510b53b4aeb0947d3e8e235fe1cc9e2ad5d67bc494276227cd87f031c8b8"
 
 
 def sources_sha256() -> str:
@@ -477,8 +480,9 @@ def main():
               file=sys.stderr, flush=True)
 
     traffic = None
-    if default and dom == 0 and sources_sha256() == TRAFFIC_SOURCES_SHA256:
-        traffic = TRAFFIC_BYTES
+    used_copy = args.storage_order == 2 or (args.storage_order == 0 and g.nnz >= (1 << 26))
+    if dom == 0 and sources_sha256() == TRAFFIC_SOURCES_SHA256:
+        traffic = TRAFFIC_BYTES.get((args.workload, used_copy))
     st_last = stats[-1]
     out = {
         "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,

@@ -220,7 +220,7 @@ def batched_leg(mg, torch, count: int, nmax: float, workers: int):
 def k_sweep_leg(mg, torch, dg, repeats: int = 3, chunk_len: int = 128):
     """Synthetic analogue of the paper's k sweeps (Figs. 4-6): for LPA, Louvain and
     Leiden, each sketch variant (Algorithm 1, unconditional subtraction, LPA 1-scan)
-    at k = 1..64 and the weighted Boyer-Moore mode, the run time and modularity
+    at k = 1..256 and the weighted Boyer-Moore mode, the run time and modularity
     relative to the exact table on the same graph (median of `repeats` runs); and the
     small mod-based table at slot counts of 1e-5 .. 1e-1 of |V|."""
     def timed(fn, **kw):
@@ -244,7 +244,7 @@ def k_sweep_leg(mg, torch, dg, repeats: int = 3, chunk_len: int = 128):
             variants.append(("alg1_1scan", dict(mode=mg.MODE_ALG1, one_scan=1)))
         for vname, kw in variants:
             res[vname] = {}
-            for k in (1, 2, 4, 8, 16, 32, 64):
+            for k in (1, 2, 4, 8, 16, 32, 64, 128, 256):
                 t, q = timed(fn, k=k, **kw)
                 res[vname][str(k)] = {"rel_time": t / t_x, "rel_Q": q / q_x if q_x else None}
         t, q = timed(fn, mode=mg.MODE_BM)

@@ -77,9 +77,11 @@ typedef struct {
 
 typedef struct {
   int32_t mode;           /* MGCD_MODE_*                                              */
-  int32_t k;              /* sketch slots for moving/refinement: 1, 2, 4, 8, 16, 32
-                             or 64 (MGCD_MODE_SMALL: the table's slots, 1 .. 2^30)    */
-  int32_t k_aggregate;    /* sketch slots for aggregation: 1, 2, 4, 8, 16, 32 or 64  */
+  int32_t k;              /* sketch slots for moving/refinement: 1, 2, 4, 8, 16, 32,
+                             64, 128 or 256 (MGCD_MODE_SMALL: the table's slots,
+                             1 .. 2^30)                                               */
+  int32_t k_aggregate;    /* sketch slots for aggregation: 1, 2, 4, 8, 16, 32, 64,
+                             128 or 256                                               */
   int32_t max_iterations; /* synchronous sweeps per pass (LPA: in total)              */
   int32_t max_passes;     /* Louvain/Leiden passes (levels)                            */
   int32_t validate;       /* 1: check the CSR on the device first (MGCD_E_GRAPH)      */

@@ -477,8 +477,8 @@ __global__ void __launch_bounds__(BLOCK)
   if (c < m) {
     int64_t len = P[mstart[c + 1]] - P[mstart[c]];
     lmax = len;
-    if (split > 0) {
-      cat = len > L && len > split ? 7 : 0;
+    if (split != 0) {  // wave sketch: split streams (split < 0: every non-empty one)
+      cat = (split < 0 ? len > 0 : (len > L && len > split)) ? 7 : 0;
       int b = 0;
       while (b < 63 && (len >> b) != 0) ++b;
       key[c] = cat == 7 ? 207ull : (uint64_t)(64 - b);
@@ -973,6 +973,7 @@ template <int K, int MODE, int DEPTH>
 __global__ void __launch_bounds__(BLOCK)
     k_agg_wave(AggStreams s, const int32_t *__restrict__ comms, int64_t ncomm, int64_t L,
                Pair *rows, uint32_t *rcount) {
+  static_assert(K <= WAVE, "one slot per lane; larger sketches split every stream");
   __shared__ uint32_t sstack[BLOCK / WAVE][DEPTH * 2 * WAVE];
   const int lane = lane_id();
   const int64_t r = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
@@ -993,7 +994,7 @@ __global__ void __launch_bounds__(BLOCK)
       sk.update(lane_value(key, u), lane_value(w, u));
       if (--left == 0) {  // end of a chunk
         sk.finalize();
-        tree.push(sk.key, sk.val);
+        tree.push(sk.key[0], sk.val[0]);
         sk.reset();
         left = L;
       }
@@ -1001,7 +1002,7 @@ __global__ void __launch_bounds__(BLOCK)
   }
   if (left != L) {  // the last, partial chunk
     sk.finalize();
-    tree.push(sk.key, sk.val);
+    tree.push(sk.key[0], sk.val[0]);
   }
   uint32_t ck, cv;
   tree.result(ck, cv);
@@ -1045,7 +1046,9 @@ __global__ void __launch_bounds__(BLOCK) k_aggw_chunks(AggStreams s, AggSplit sp
     for (int u = 0; u < nb; ++u) sk.update(lane_value(key, u), lane_value(w, u));
   }
   sk.finalize();
-  if (lane < K) sp.node[q * K + lane] = Pair{sk.key, sk.val};
+#pragma unroll
+  for (int r = 0; r < WaveSlots<K>::S; ++r)
+    if (r * WAVE + lane < K) sp.node[q * K + r * WAVE + lane] = Pair{sk.key[r], sk.val[r]};
 }
 
 // Level `level` of the merge tree of every split stream (node x of a stream, x a
@@ -1061,16 +1064,27 @@ __global__ void __launch_bounds__(BLOCK) k_aggw_level(AggSplit sp, int level) {
   if (((q - sp.cstart[x]) & (2 * half - 1)) != 0) return;
   const int64_t r = q + half;
   if (r >= sp.cstart[x + 1]) return;
-  uint32_t ak = EMPTY, av = 0, bk = EMPTY, bv = 0;
-  if (lane < K) {
-    const Pair pa = sp.node[q * K + lane], pb = sp.node[r * K + lane];
-    ak = pa.key;
-    av = pa.val;
-    bk = pb.key;
-    bv = pb.val;
+  constexpr int S = WaveSlots<K>::S;
+  uint32_t ak[S], av[S], bk[S], bv[S];
+#pragma unroll
+  for (int u = 0; u < S; ++u) {
+    const int p = u * WAVE + lane;
+    ak[u] = EMPTY;
+    av[u] = 0;
+    bk[u] = EMPTY;
+    bv[u] = 0;
+    if (p < K) {
+      const Pair pa = sp.node[q * K + p], pb = sp.node[r * K + p];
+      ak[u] = pa.key;
+      av[u] = pa.val;
+      bk[u] = pb.key;
+      bv[u] = pb.val;
+    }
   }
   wave_merge<K>(ak, av, bk, bv);
-  if (lane < K) sp.node[q * K + lane] = Pair{ak, av};
+#pragma unroll
+  for (int u = 0; u < S; ++u)
+    if (u * WAVE + lane < K) sp.node[q * K + u * WAVE + lane] = Pair{ak[u], av[u]};
 }
 
 // The row of every split stream: the root's positive slots sorted by key.
@@ -1080,17 +1094,38 @@ __global__ void __launch_bounds__(BLOCK) k_aggw_rows(AggSplit sp, Pair *rows, ui
   const int64_t x = uniform(((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE);
   if (x >= sp.nmulti) return;
   const int32_t c = uniform(sp.multi[x]);
-  uint32_t ck = EMPTY, cv = 0;
-  if (lane < K) {
-    const Pair p = sp.node[sp.cstart[x] * K + lane];
-    cv = p.val;
-    ck = cv > 0 ? p.key : EMPTY;
+  constexpr int S = WaveSlots<K>::S;
+  uint32_t ck[S], cv[S];
+#pragma unroll
+  for (int u = 0; u < S; ++u) {
+    ck[u] = EMPTY;
+    cv[u] = 0;
+    if (u * WAVE + lane < K) {
+      const Pair p = sp.node[sp.cstart[x] * K + u * WAVE + lane];
+      cv[u] = p.val;
+      ck[u] = cv[u] > 0 ? p.key : EMPTY;
+    }
   }
-  uint32_t rank = 0;
-  for (int u = 0; u < WAVE; ++u) rank += lane_value(ck, u) < ck ? 1u : 0u;
-  const uint64_t pos = __ballot(cv > 0);
-  if (cv > 0) rows[(int64_t)c * K + rank] = Pair{ck, cv};
-  if (lane == 0) rcount[c] = (uint32_t)__popcll(pos);
+  // the row is the positive slots sorted by key: a slot's place is the number of
+  // smaller keys among all slots (EMPTY, the largest value, for the others)
+  int npos = 0;
+#pragma unroll
+  for (int u = 0; u < S; ++u) {
+    uint32_t rank = 0;
+#pragma unroll
+    for (int v = 0; v < S; ++v)
+      for (int t = 0; t < WAVE; ++t) rank += lane_value(ck[v], t) < ck[u] ? 1u : 0u;
+    if (cv[u] > 0) rows[(int64_t)c * K + rank] = Pair{ck[u], cv[u]};
+    npos += __popcll(__ballot(cv[u] > 0));
+  }
+  if (lane == 0) rcount[c] = (uint32_t)npos;
+}
+
+// Streams the split path does not take when every non-empty stream is split (K = 128,
+// 256): empty ones, whose row is empty.
+__global__ void k_empty_rows(const int32_t *comms, int64_t n, uint32_t *rcount) {
+  const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (t < n) rcount[comms[t]] = 0;
 }
 
 template <int K, int MODE>
@@ -1110,11 +1145,15 @@ static void agg_wave(const AggStreams &s, const int32_t *comms, int64_t ncomm, c
     max_len = L > WAVE_SPLIT ? L : WAVE_SPLIT;  // the longest stream left for one wave
   }
   if (ncomm > 0) {
-    const unsigned grid = (unsigned)ceil_div(ncomm, BLOCK / WAVE);
-    if (wave_depth_for(max_len, L) == WDEPTH_SHALLOW)
-      k_agg_wave<K, MODE, WDEPTH_SHALLOW><<<grid, BLOCK, 0, st>>>(s, comms, ncomm, L, rows, rcount);
-    else
-      k_agg_wave<K, MODE, WDEPTH><<<grid, BLOCK, 0, st>>>(s, comms, ncomm, L, rows, rcount);
+    if constexpr (K <= WAVE) {
+      const unsigned grid = (unsigned)ceil_div(ncomm, BLOCK / WAVE);
+      if (wave_depth_for(max_len, L) == WDEPTH_SHALLOW)
+        k_agg_wave<K, MODE, WDEPTH_SHALLOW><<<grid, BLOCK, 0, st>>>(s, comms, ncomm, L, rows, rcount);
+      else
+        k_agg_wave<K, MODE, WDEPTH><<<grid, BLOCK, 0, st>>>(s, comms, ncomm, L, rows, rcount);
+    } else {
+      k_empty_rows<<<grid_for(ncomm), BLOCK, 0, st>>>(comms, ncomm, rcount);
+    }
     MGCD_LAUNCHED();
   }
 }
@@ -1141,6 +1180,8 @@ static void agg_mg_k(int k, const AggStreams &s, const AggBuckets &bk, int64_t w
   switch (k) {
     case 32: agg_wave<32, MODE>(s, one, none, sp, L, rows, rcount, max_len, st); break;
     case 64: agg_wave<64, MODE>(s, one, none, sp, L, rows, rcount, max_len, st); break;
+    case 128: agg_wave<128, MODE>(s, one, none, sp, L, rows, rcount, max_len, st); break;
+    case 256: agg_wave<256, MODE>(s, one, none, sp, L, rows, rcount, max_len, st); break;
     case 1: agg_mg<1, MODE>(s, bk, waves, lg, L, rows, rcount, st); break;
     case 2: agg_mg<2, MODE>(s, bk, waves, lg, L, rows, rcount, st); break;
     case 4: agg_mg<4, MODE>(s, bk, waves, lg, L, rows, rcount, st); break;
@@ -1244,8 +1285,10 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   launch_zero_u64(cnt, SPREAD * 9, st);
   uint64_t *ck0 = a.take<uint64_t>(m), *ck1 = a.take<uint64_t>(m);
   uint32_t *cv0 = a.take<uint32_t>(m), *cv1 = a.take<uint32_t>(m);
-  const bool wave = k > 16;  // the 32/64-slot sketch: one wave per stream, long ones split
-  k_comm_keys<<<grid_for(m), BLOCK, 0, st>>>(mstart, P, m, L, wave ? WAVE_SPLIT : 0, ck0, cv0, cnt);
+  const bool wave = k > 16;  // the 32/64-slot sketch: one wave per stream, long ones split;
+                            // 128/256 slots: every non-empty stream split
+  k_comm_keys<<<grid_for(m), BLOCK, 0, st>>>(mstart, P, m, L, !wave ? 0 : k > WAVE ? -1 : WAVE_SPLIT, ck0,
+                                             cv0, cnt);
   MGCD_LAUNCHED();
   bool cf = radix_sort_pairs(ck0, cv0, ck1, cv1, m, 8, a, st);
   int32_t *corder = a.take<int32_t>(m);
@@ -1380,8 +1423,10 @@ size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L, bo
   const int64_t Lc = L > 0 ? L : 1;
   const int64_t nm = nnz / (64 * Lc) + 1, chunks = nnz / Lc + nm + 1;
   b += (size_t)(nm + 1) * 16 + scan_ws_bytes(nm) + (size_t)chunks * (4 + (size_t)k * sizeof(Pair)) + 8192;
-  if (k > 16) {  // split streams of the 32/64-slot sketch: more than max(L, WAVE_SPLIT) positions
-    const int64_t nw = nnz / (Lc > WAVE_SPLIT ? Lc : WAVE_SPLIT) + 1, cw = nnz / Lc + nw + 1;
+  if (k > 16) {  // split streams of the 32/64-slot sketch: more than max(L, WAVE_SPLIT)
+    // positions; of the 128/256-slot sketch: every non-empty stream (at most min(n, nnz))
+    const int64_t nw = k > WAVE ? (n < nnz ? (int64_t)n : nnz) + 1 : nnz / (Lc > WAVE_SPLIT ? Lc : WAVE_SPLIT) + 1;
+    const int64_t cw = nnz / Lc + nw + 1;
     b += (size_t)(nw + 1) * 16 + scan_ws_bytes(nw) + (size_t)cw * (4 + (size_t)k * sizeof(Pair)) + 8192;
   }
   b += (size_t)n * k * sizeof(Pair) + (size_t)n * 4 + 4096;  // rows, rcount

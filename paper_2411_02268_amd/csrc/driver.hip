@@ -59,16 +59,18 @@ static void check_params(const mgcd_params *p) {
   if (!p) throw Error(MGCD_E_ARG, "params is null");
   if (p->mode < 0 || (p->mode > 3 && p->mode != MGCD_MODE_SMALL))
     throw Error(MGCD_E_UNSUPPORTED, "unknown sketch mode");
-  auto okk = [](int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16 || k == 32 || k == 64; };
+  auto okk = [](int k) {
+    return k == 1 || k == 2 || k == 4 || k == 8 || k == 16 || k == 32 || k == 64 || k == 128 || k == 256;
+  };
   if (p->mode == MGCD_MODE_SMALL) {
     if (p->k < 1 || p->k > (1 << 30)) throw Error(MGCD_E_UNSUPPORTED, "small-table slots k must be in [1, 2^30]");
   } else if (p->mode != MGCD_MODE_EXACT && !okk(p->k)) {
-    throw Error(MGCD_E_UNSUPPORTED, "k must be 1, 2, 4, 8, 16, 32 or 64");
+    throw Error(MGCD_E_UNSUPPORTED, "k must be 1, 2, 4, 8, 16, 32, 64, 128 or 256");
   }
   if (p->aggregation < 0 || p->aggregation > 2) throw Error(MGCD_E_ARG, "aggregation must be 0, 1 or 2");
   if (p->storage_order < 0 || p->storage_order > 2) throw Error(MGCD_E_ARG, "storage_order must be 0, 1 or 2");
   if (agg_mode(p) != MGCD_MODE_EXACT && !okk(p->k_aggregate))
-    throw Error(MGCD_E_UNSUPPORTED, "k_aggregate must be 1, 2, 4, 8, 16, 32 or 64");
+    throw Error(MGCD_E_UNSUPPORTED, "k_aggregate must be 1, 2, 4, 8, 16, 32, 64, 128 or 256");
   if (p->chunk_len < 1) throw Error(MGCD_E_ARG, "chunk_len must be >= 1");
   if (p->max_iterations < 1 || p->max_passes < 1) throw Error(MGCD_E_ARG, "iteration limits must be >= 1");
   if (!(p->tolerance >= 0.0) || !(p->tolerance_drop > 0.0) || !(p->aggregation_tolerance >= 0.0))

@@ -657,6 +657,7 @@ template <int K, int ALGO, int MODE, int DEPTH>
 __global__ void __launch_bounds__(BLOCK)
     k_wave_rows(SweepArgs a, const int32_t *__restrict__ rows, int64_t nrows, int64_t L,
                 uint32_t *keybuf) {
+  static_assert(K <= WAVE, "one slot per lane; larger sketches take the split rows");
   if (level_over(a)) return;  // batched: every graph has stopped
   __shared__ uint32_t sstack[BLOCK / WAVE][DEPTH * 2 * WAVE];
   const int lane = lane_id();
@@ -692,7 +693,7 @@ __global__ void __launch_bounds__(BLOCK)
         if (--left == 0) {  // end of a chunk
           lossy |= s.lossy;
           s.finalize();
-          tree.push(s.key, s.val);
+          tree.push(s.key[0], s.val[0]);
           s.reset();
           left = L;
         }
@@ -701,7 +702,7 @@ __global__ void __launch_bounds__(BLOCK)
     if (left != L) {  // the last, partial chunk
       lossy |= s.lossy;
       s.finalize();
-      tree.push(s.key, s.val);
+      tree.push(s.key[0], s.val[0]);
     }
     uint32_t ck, cv;
     tree.result(ck, cv);
@@ -772,8 +773,7 @@ __global__ void __launch_bounds__(BLOCK)
   const int32_t i = uniform(rows[m]);
   if (q == cstart[m]) {  // the row's K + 1 pass-2 counts start at zero in every sweep
     uint32_t *cm = count + (int64_t)m * (K + 1);
-    if (lane <= K) cm[lane] = 0u;                  // K < WAVE: slots 0..K
-    if (K == WAVE && lane == 0) cm[K] = 0u;        // K == WAVE: the last one
+    for (int p = lane; p <= K; p += WAVE) cm[p] = 0u;
   }
   if (frozen(a, i)) return;
   const int64_t rhi = uniform(a.g.off[i + 1]);
@@ -799,7 +799,9 @@ __global__ void __launch_bounds__(BLOCK)
     }
   }
   s.finalize();
-  if (lane < K) node[q * K + lane] = Pair{s.key, s.val};
+#pragma unroll
+  for (int r = 0; r < WaveSlots<K>::S; ++r)
+    if (r * WAVE + lane < K) node[q * K + r * WAVE + lane] = Pair{s.key[r], s.val[r]};
   if (lane == 0) nflag[q] = s.lossy ? 1u : 0u;
 }
 
@@ -818,30 +820,44 @@ __global__ void __launch_bounds__(BLOCK)
   const int64_t r = q + half;
   if (r >= cstart[m + 1]) return;  // odd last node: carried up
   if (frozen(a, rows[m])) return;
-  uint32_t ak = EMPTY, av = 0, bk = EMPTY, bv = 0;
-  if (lane < K) {
-    const Pair pa = node[q * K + lane], pb = node[r * K + lane];
-    ak = pa.key;
-    av = pa.val;
-    bk = pb.key;
-    bv = pb.val;
+  constexpr int S = WaveSlots<K>::S;
+  uint32_t ak[S], av[S], bk[S], bv[S];
+#pragma unroll
+  for (int u = 0; u < S; ++u) {
+    const int p = u * WAVE + lane;
+    ak[u] = EMPTY;
+    av[u] = 0;
+    bk[u] = EMPTY;
+    bv[u] = 0;
+    if (p < K) {
+      const Pair pa = node[q * K + p], pb = node[r * K + p];
+      ak[u] = pa.key;
+      av[u] = pa.val;
+      bk[u] = pb.key;
+      bv[u] = pb.val;
+    }
   }
   const bool lossy = wave_merge<K>(ak, av, bk, bv);
-  if (lane < K) node[q * K + lane] = Pair{ak, av};
+#pragma unroll
+  for (int u = 0; u < S; ++u)
+    if (u * WAVE + lane < K) node[q * K + u * WAVE + lane] = Pair{ak[u], av[u]};
   if (lane == 0) nflag[q] = nflag[q] | nflag[r] | (lossy ? 1u : 0u);
 }
 
 // The root of split row m: keys of positive slots, other slots EMPTY.
-template <int K>
-__device__ inline void wave_root(const Pair *node, const int64_t *cstart, int32_t m, uint32_t &ck,
-                                 uint32_t &cv) {
+template <int K, int S = WaveSlots<K>::S>
+__device__ inline void wave_root(const Pair *node, const int64_t *cstart, int32_t m, uint32_t (&ck)[S],
+                                 uint32_t (&cv)[S]) {
   const int lane = lane_id();
-  ck = EMPTY;
-  cv = 0;
-  if (lane < K) {
-    const Pair p = node[cstart[m] * K + lane];
-    ck = p.val > 0 ? p.key : EMPTY;
-    cv = p.val;
+#pragma unroll
+  for (int u = 0; u < S; ++u) {
+    ck[u] = EMPTY;
+    cv[u] = 0;
+    if (u * WAVE + lane < K) {
+      const Pair p = node[cstart[m] * K + u * WAVE + lane];
+      ck[u] = p.val > 0 ? p.key : EMPTY;
+      cv[u] = p.val;
+    }
   }
 }
 
@@ -862,9 +878,12 @@ __global__ void __launch_bounds__(BLOCK)
   const int64_t lo = uniform(a.g.off[i]) + (q - cstart[m]) * L;
   const int64_t hi = lo + L < rhi ? lo + L : rhi;
   const uint32_t d = (uint32_t)uniform(community_of_self<ALGO>(a, i));
-  uint32_t ck, cv0;
+  constexpr int S = WaveSlots<K>::S;
+  uint32_t ck[S], cv0[S], cv[S];
   wave_root<K>(node, cstart, m, ck, cv0);
-  uint32_t cv = 0, kd = 0;
+#pragma unroll
+  for (int u = 0; u < S; ++u) cv[u] = 0;
+  uint32_t kd = 0;
   for (int64_t e0 = lo; e0 < hi; e0 += WAVE) {
     const int64_t e = e0 + lane;
     const bool v = e < hi;
@@ -874,12 +893,17 @@ __global__ void __launch_bounds__(BLOCK)
     const int nb = hi - e0 < WAVE ? (int)(hi - e0) : WAVE;
     for (int t = 0; t < nb; ++t) {
       const uint32_t c = lane_value(key, t);
-      if (c != EMPTY && ck == c) cv += lane_value(w, t);
+      const uint32_t wt = lane_value(w, t);
+#pragma unroll
+      for (int u = 0; u < S; ++u)
+        if (c != EMPTY && ck[u] == c) cv[u] += wt;
     }
   }
   kd = wave_sum(kd);
   uint32_t *cm = count + (int64_t)m * (K + 1);
-  if (lane < K && cv) atomicAdd(&cm[lane], cv);
+#pragma unroll
+  for (int u = 0; u < S; ++u)
+    if (u * WAVE + lane < K && cv[u]) atomicAdd(&cm[u * WAVE + lane], cv[u]);
   if (lane == 0 && kd) atomicAdd(&cm[K], kd);
 }
 
@@ -898,24 +922,29 @@ __global__ void __launch_bounds__(BLOCK)
       if (lane == 0) a.Cnew[i] = community_of_self<ALGO>(a, i);
     } else {
       const int32_t d = uniform(community_of_self<ALGO>(a, i));
-      uint32_t ck, cv;
+      constexpr int S = WaveSlots<K>::S;
+      uint32_t ck[S], cv[S];
       wave_root<K>(node, cstart, (int32_t)m, ck, cv);
       uint32_t kd;
       if (!nflag[cstart[m]] || !second_pass(a, ALGO)) {
-        kd = wave_sum(ck == (uint32_t)d ? cv : 0u);
+        uint32_t own = 0;
+#pragma unroll
+        for (int u = 0; u < S; ++u) own += ck[u] == (uint32_t)d ? cv[u] : 0u;
+        kd = wave_sum(own);
       } else {
         const uint32_t *cm = count + m * (K + 1);
-        cv = lane < K ? cm[lane] : 0u;
+#pragma unroll
+        for (int u = 0; u < S; ++u) cv[u] = u * WAVE + lane < K ? cm[u * WAVE + lane] : 0u;
         kd = cm[K];
       }
       int32_t best = -1;
       int64_t bestG = 0;
-      if (ck != EMPTY) {
-        const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
-        const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
-        const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
-        consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)ck, cv, best, bestG);
-      }
+      const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
+      const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
+      const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
+#pragma unroll
+      for (int u = 0; u < S; ++u)
+        if (ck[u] != EMPTY) consider<ALGO>(a, W, d, Ki, Sd, kd, (int32_t)ck[u], cv[u], best, bestG);
 #pragma unroll
       for (int o = WAVE / 2; o > 0; o >>= 1) {
         const int32_t b2 = __shfl_xor(best, o);
@@ -1515,8 +1544,9 @@ __global__ void __launch_bounds__(BLOCK)
     } else if (mode == MODE_EXACT) {
       cat = deg <= sp.exact_t0 ? 0 : deg <= sp.exact_t1 ? 1 : deg <= sp.exact_t2 ? 2 : 3;
       k = cat == 0 ? (uint64_t)(64 - b) : (uint64_t)(128 + cat);
-    } else if (sp.wave) {  // K = 32 / 64: short rows exact, split rows, the rest one wave each
-      cat = deg <= sp.exact_t0 ? 0 : (deg > L && deg > WAVE_SPLIT) ? 2 : 1;
+    } else if (sp.wave) {  // K >= 32: short rows exact, split rows, the rest one wave each
+      // (K = 128 / 256: every other row is a split row, one wave per chunk)
+      cat = deg <= sp.exact_t0 ? 0 : (sp.k > WAVE || (deg > L && deg > WAVE_SPLIT)) ? 2 : 1;
       k = (uint64_t)(cat * 64 + 64 - b);  // heavy rows first in each tier
     } else if (deg <= L) {
       cat = 0;
@@ -1627,6 +1657,12 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
     b += (size_t)nl * ((size_t)k * sizeof(Pair) + 4) + 2048;         // candidates, flags
     if (k > 16)  // split rows of the 32/64-slot sketch: chunk nodes, flags, pass-2 counts
       b += (size_t)cl * ((size_t)k * sizeof(Pair) + 4) + (size_t)nl * (k + 1) * 4 + 4096;
+    if (k > WAVE) {  // 128/256 slots: every row of more than 32 (or, unconditional, 0)
+      // entries is split: at most min(n, nnz) rows and nnz / L + that many chunks
+      const int64_t rs = (n < nnz ? (int64_t)n : nnz) + 1, cs = nnz / Lc + rs + 1;
+      b += (size_t)(rs + 1) * 8 * 2 + scan_ws_bytes(rs) + (size_t)cs * 4 + 4096;  // counts, cstart, owner
+      b += (size_t)cs * ((size_t)k * sizeof(Pair) + 4) + (size_t)rs * (k + 1) * 4 + 4096;
+    }
   }
   return b + 64 * 1024;
 }
@@ -1875,14 +1911,16 @@ static void sweep_wave(const SweepArgs &a, const Schedule &s, int64_t L, hipStre
     MGCD_LAUNCHED();
   }
   mark(ev, 1, st);
-  if (s.ntier[1] > 0) {
-    const unsigned grid = (unsigned)ceil_div(s.ntier[1], BLOCK / WAVE);
-    if (wave_depth_for(s.nmulti > 0 ? (L > WAVE_SPLIT ? L : WAVE_SPLIT) : s.maxdeg, L) == WDEPTH_SHALLOW)
-      k_wave_rows<K, ALGO, MODE, WDEPTH_SHALLOW><<<grid, BLOCK, 0, st>>>(a, s.tier[1], s.ntier[1], L,
-                                                                         s.keybuf);
-    else
-      k_wave_rows<K, ALGO, MODE, WDEPTH><<<grid, BLOCK, 0, st>>>(a, s.tier[1], s.ntier[1], L, s.keybuf);
-    MGCD_LAUNCHED();
+  if constexpr (K <= WAVE) {  // K = 128 / 256: every row the sketch takes is a split row
+    if (s.ntier[1] > 0) {
+      const unsigned grid = (unsigned)ceil_div(s.ntier[1], BLOCK / WAVE);
+      if (wave_depth_for(s.nmulti > 0 ? (L > WAVE_SPLIT ? L : WAVE_SPLIT) : s.maxdeg, L) == WDEPTH_SHALLOW)
+        k_wave_rows<K, ALGO, MODE, WDEPTH_SHALLOW><<<grid, BLOCK, 0, st>>>(a, s.tier[1], s.ntier[1], L,
+                                                                           s.keybuf);
+      else
+        k_wave_rows<K, ALGO, MODE, WDEPTH><<<grid, BLOCK, 0, st>>>(a, s.tier[1], s.ntier[1], L, s.keybuf);
+      MGCD_LAUNCHED();
+    }
   }
   mark(ev, 2, st);
   if (s.nmulti > 0) {  // split rows
@@ -1914,6 +1952,8 @@ static void sweep_k(const SweepArgs &a, const Schedule &s, int k, int64_t L, hip
   switch (k) {
     case 32: sweep_wave<32, ALGO, MODE>(a, s, L, st, ev); break;
     case 64: sweep_wave<64, ALGO, MODE>(a, s, L, st, ev); break;
+    case 128: sweep_wave<128, ALGO, MODE>(a, s, L, st, ev); break;
+    case 256: sweep_wave<256, ALGO, MODE>(a, s, L, st, ev); break;
     case 1: sweep_mg<1, ALGO, MODE>(a, s, L, st, ev); break;
     case 2: sweep_mg<2, ALGO, MODE>(a, s, L, st, ev); break;
     case 4: sweep_mg<4, ALGO, MODE>(a, s, L, st, ev); break;

@@ -1,8 +1,9 @@
-// The weighted Misra-Gries sketch spread over a wavefront, for K = 32 or 64 slots
-// (Appendix A.1, Algorithm 1, and its variants): slot p lives in lane p.  Stream
-// items arrive wave-uniform (the same (c, w) in every lane); matching a key is one
-// compare per lane plus a ballot, and the free slot that takes a new key is the
-// lowest free lane (slot placement does not change the sketch's positive entries).
+// The weighted Misra-Gries sketch spread over a wavefront, for K = 32, 64, 128 or 256
+// slots (Appendix A.1, Algorithm 1, and its variants): slot p lives in lane p mod 64,
+// register p / 64.  Stream items arrive wave-uniform (the same (c, w) in every lane);
+// matching a key is one compare per slot register plus a ballot, and the free slot
+// that takes a new key is the first free one (slot placement does not change the
+// sketch's positive entries).
 #pragma once
 #include "common.hpp"
 
@@ -15,17 +16,62 @@ __device__ inline T lane_value(T v, int lane) {  // v of `lane` (wave-uniform la
   return (T)__builtin_amdgcn_readlane((int)v, lane);
 }
 
+// Slots per lane of a K-slot wave sketch: one for K <= 64, K / 64 for 128 and 256
+// (slot p = s * 64 + lane lives in lane `lane`, register s).
+template <int K>
+struct WaveSlots {
+  static_assert(K == 32 || K == 64 || K == 128 || K == 256, "wave sketch sizes");
+  static constexpr int S = K <= WAVE ? 1 : K / WAVE;
+  // lanes whose slot s exists (all lanes unless K < 64)
+  static constexpr uint64_t VALID = K >= WAVE ? ~0ull : ((1ull << K) - 1);
+};
+
 template <int K, int MODE>
 struct WaveSketch {
-  static_assert(K == 32 || K == 64, "one slot per lane");
-  static constexpr uint64_t VALID = K == 64 ? ~0ull : ((1ull << K) - 1);
-  uint32_t key, val;  // this lane's slot (lanes >= K stay empty)
-  bool lossy;         // wave-uniform
+  static constexpr int S = WaveSlots<K>::S;
+  static constexpr uint64_t VALID = WaveSlots<K>::VALID;
+  uint32_t key[S], val[S];  // this lane's slots (lanes >= K stay empty)
+  bool lossy;               // wave-uniform
 
   __device__ inline void reset() {
-    key = EMPTY;
-    val = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      key[s] = EMPTY;
+      val[s] = 0;
+    }
     lossy = false;
+  }
+
+  // The first free slot (value 0; register-major, then lowest lane) takes (c, w);
+  // returns false (wave-uniform) when every slot is in use.
+  __device__ inline bool insert(uint32_t c, uint32_t w) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint64_t fr = __ballot(val[s] == 0) & VALID;
+      if (fr) {
+        if (lane == first_lane(fr)) {
+          key[s] = c;
+          val[s] = w;
+        }
+        return true;
+      }
+    }
+    return false;
+  }
+
+  // Add w to the slot whose key is c (present: value positive, or any value for
+  // Algorithm 1, whose stale keys revive); false (wave-uniform) when c has none.
+  __device__ inline bool add(uint32_t c, uint32_t w, bool positive_only) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const bool m = key[s] == c && (!positive_only || val[s] > 0);
+      if (__ballot(m) & VALID) {
+        if (m) val[s] += w;
+        return true;
+      }
+    }
+    return false;
   }
 
   // Add (c, w) (wave-uniform, c != EMPTY).
@@ -34,94 +80,85 @@ struct WaveSketch {
     if constexpr (MODE == MODE_ALG1) {
       // accumulate into the slot holding c (a stale key revives); else the first free
       // slot; else subtract w from every slot (clamped at 0) and drop the item
-      const bool m = key == c;
-      if (__ballot(m) & VALID) {
-        if (m) val += w;
-        return;
-      }
-      const uint64_t fr = __ballot(val == 0) & VALID;
-      if (fr) {
-        if (lane == first_lane(fr)) {
-          key = c;
-          val = w;
-        }
-        return;
-      }
+      if (add(c, w, false)) return;
+      if (insert(c, w)) return;
       lossy = true;
-      val = val > w ? val - w : 0u;
+#pragma unroll
+      for (int s = 0; s < S; ++s) val[s] = val[s] > w ? val[s] - w : 0u;
     } else if constexpr (MODE == MODE_UNCOND) {
       // present = positive; on a miss subtract w from every slot, then insert
-      const bool m = key == c && val > 0;
-      if (__ballot(m) & VALID) {
-        if (m) val += w;
-        return;
+      if (add(c, w, true)) return;
+      bool any = false;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        any |= (__ballot(val[s] > 0) & VALID) != 0;
+        val[s] = val[s] > w ? val[s] - w : 0u;
       }
-      const bool any = (__ballot(val > 0) & VALID) != 0;
-      val = val > w ? val - w : 0u;
-      const uint64_t fr = __ballot(val == 0) & VALID;
-      if (fr && lane == first_lane(fr)) {
-        key = c;
-        val = w;
-      }
-      lossy |= any || !fr;
+      const bool put = insert(c, w);
+      lossy |= any || !put;
     } else {  // MODE_STD: textbook weighted MG
-      const bool m = key == c && val > 0;
-      if (__ballot(m) & VALID) {
-        if (m) val += w;
-        return;
-      }
-      uint64_t fr = __ballot(val == 0) & VALID;
-      if (fr) {
-        if (lane == first_lane(fr)) {
-          key = c;
-          val = w;
-        }
-        return;
-      }
+      if (add(c, w, true)) return;
+      if (insert(c, w)) return;
       lossy = true;
-      uint32_t d = lane < K ? val : ~0u;
+      uint32_t d = ~0u;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const uint32_t x = lane < K ? val[s] : ~0u;
+        d = x < d ? x : d;
+      }
 #pragma unroll
       for (int o = WAVE / 2; o > 0; o >>= 1) {
         const uint32_t x = __shfl_xor(d, o);
         d = x < d ? x : d;
       }
       d = d < w ? d : w;
-      if (lane < K) val -= d;
-      const uint32_t rest = w - d;
-      if (rest > 0) {
-        fr = __ballot(val == 0) & VALID;
-        if (lane == first_lane(fr)) {
-          key = c;
-          val = rest;
-        }
+      if (lane < K) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) val[s] -= d;
       }
+      const uint32_t rest = w - d;
+      if (rest > 0) insert(c, rest);
     }
   }
 
   // Keep only the candidates (positive slots); other keys become EMPTY.
-  __device__ inline void finalize() { key = val > 0 ? key : EMPTY; }
+  __device__ inline void finalize() {
+#pragma unroll
+    for (int s = 0; s < S; ++s) key[s] = val[s] > 0 ? key[s] : EMPTY;
+  }
 };
 
 // Merge sketch (bk, bv) into (ak, av) (mergeable summaries, Agarwal et al. 2012): add
 // the values of equal keys; if more than K keys are positive, subtract the (K+1)-th
 // largest value from all and keep the positive ones.  Returns true (wave-uniform)
-// when the threshold step removed weight.
-template <int K>
-__device__ inline bool wave_merge(uint32_t &ak, uint32_t &av, uint32_t bk, uint32_t bv) {
-  constexpr uint64_t VALID = WaveSketch<K, MODE_ALG1>::VALID;
+// when the threshold step removed weight.  S slots per lane as in WaveSketch.
+template <int K, int S = WaveSlots<K>::S>
+__device__ inline bool wave_merge(uint32_t (&ak)[S], uint32_t (&av)[S], uint32_t (&bk)[S],
+                                  uint32_t (&bv)[S]) {
+  constexpr uint64_t VALID = WaveSlots<K>::VALID;
   const int lane = lane_id();
-  uint64_t bpos = __ballot(bv > 0) & VALID;
-  while (bpos) {
-    const int q = first_lane(bpos);
-    bpos &= bpos - 1;
-    const uint32_t kq = lane_value(bk, q), vq = lane_value(bv, q);
-    const bool m = av > 0 && ak == kq;
-    if (__ballot(m) & VALID) {
-      if (m) av += vq;
-      if (lane == q) bv = 0;
+#pragma unroll
+  for (int sb = 0; sb < S; ++sb) {
+    uint64_t bpos = __ballot(bv[sb] > 0) & VALID;
+    while (bpos) {
+      const int q = first_lane(bpos);
+      bpos &= bpos - 1;
+      const uint32_t kq = lane_value(bk[sb], q), vq = lane_value(bv[sb], q);
+#pragma unroll
+      for (int sa = 0; sa < S; ++sa) {
+        const bool m = av[sa] > 0 && ak[sa] == kq;
+        if (__ballot(m) & VALID) {
+          if (m) av[sa] += vq;
+          if (lane == q) bv[sb] = 0;
+          break;
+        }
+      }
     }
   }
-  const int cnt = __popcll(__ballot(av > 0) & VALID) + __popcll(__ballot(bv > 0) & VALID);
+  int cnt = 0;
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+    cnt += __popcll(__ballot(av[s] > 0) & VALID) + __popcll(__ballot(bv[s] > 0) & VALID);
   bool lossy = false;
   if (cnt > K) {
     lossy = true;
@@ -129,24 +166,49 @@ __device__ inline bool wave_merge(uint32_t &ak, uint32_t &av, uint32_t bk, uint3
     uint32_t t = 0;
     for (int bit = 31; bit >= 0; --bit) {
       const uint32_t cand = t | (1u << bit);
-      const int ge = __popcll(__ballot(av >= cand) & VALID) + __popcll(__ballot(bv >= cand) & VALID);
+      int ge = 0;
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        ge += __popcll(__ballot(av[s] >= cand) & VALID) + __popcll(__ballot(bv[s] >= cand) & VALID);
       if (ge >= K + 1) t = cand;
     }
-    av = av > t ? av - t : 0u;
-    bv = bv > t ? bv - t : 0u;
-  }
-  // move the survivors of b into the free slots of a (at most K survive in total)
-  bpos = __ballot(bv > 0) & VALID;
-  while (bpos) {
-    const int q = first_lane(bpos);
-    bpos &= bpos - 1;
-    const uint32_t kq = lane_value(bk, q), vq = lane_value(bv, q);
-    const uint64_t fr = __ballot(av == 0) & VALID;
-    if (lane == first_lane(fr)) {
-      ak = kq;
-      av = vq;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      av[s] = av[s] > t ? av[s] - t : 0u;
+      bv[s] = bv[s] > t ? bv[s] - t : 0u;
     }
   }
+  // move the survivors of b into the free slots of a (at most K survive in total)
+#pragma unroll
+  for (int sb = 0; sb < S; ++sb) {
+    uint64_t bpos = __ballot(bv[sb] > 0) & VALID;
+    while (bpos) {
+      const int q = first_lane(bpos);
+      bpos &= bpos - 1;
+      const uint32_t kq = lane_value(bk[sb], q), vq = lane_value(bv[sb], q);
+#pragma unroll
+      for (int sa = 0; sa < S; ++sa) {
+        const uint64_t fr = __ballot(av[sa] == 0) & VALID;
+        if (fr) {
+          if (lane == first_lane(fr)) {
+            ak[sa] = kq;
+            av[sa] = vq;
+          }
+          break;
+        }
+      }
+    }
+  }
+  return lossy;
+}
+
+// One slot per lane (K = 32, 64): the merge on scalars.
+template <int K>
+__device__ inline bool wave_merge(uint32_t &ak, uint32_t &av, uint32_t bk, uint32_t bv) {
+  uint32_t a1[1] = {ak}, v1[1] = {av}, b1[1] = {bk}, w1[1] = {bv};
+  const bool lossy = wave_merge<K, 1>(a1, v1, b1, w1);
+  ak = a1[0];
+  av = v1[0];
   return lossy;
 }
 

@@ -61,7 +61,8 @@ def graph(name):
 @pytest.mark.parametrize("mode", ["exact", "alg1", "uncond", "std"])
 # L = 1 and 2 give rows of several aligned groups of 64 chunks on the R-MAT graph
 @pytest.mark.parametrize("k,L", [(1, 128), (4, 7), (8, 128), (8, 16), (16, 5), (8, 2), (4, 1),
-                                 (32, 128), (64, 16), (64, 3), (32, 1)])
+                                 (32, 128), (64, 16), (64, 3), (32, 1), (128, 128), (128, 2),
+                                 (256, 3), (256, 1)])
 def test_sweep_parity(mg, gname, mode, k, L):
     g = graph(gname)
     dg = mg.to_device(g)
@@ -84,7 +85,8 @@ def test_sweep_parity(mg, gname, mode, k, L):
 @pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12"])
 @pytest.mark.parametrize("mode,k,L", [("exact", 8, 128), ("alg1", 2, 9), ("alg1", 16, 128),
                                       ("std", 4, 6), ("alg1", 64, 128), ("std", 32, 7),
-                                      ("uncond", 64, 20)])
+                                      ("uncond", 64, 20), ("alg1", 128, 3), ("std", 256, 1),
+                                      ("uncond", 128, 64)])
 def test_refine_parity(mg, gname, mode, k, L):
     g = graph(gname)
     dg = mg.to_device(g)
@@ -99,7 +101,9 @@ def test_refine_parity(mg, gname, mode, k, L):
 @pytest.mark.parametrize("mode,k,L", [("exact", 8, 128), ("alg1", 1, 128), ("alg1", 4, 11),
                                       ("alg1", 8, 128), ("alg1", 16, 40), ("uncond", 8, 64),
                                       ("alg1", 64, 128), ("alg1", 32, 5), ("std", 64, 9),
-                                      ("uncond", 32, 64), ("alg1", 8, 1), ("std", 4, 2)])
+                                      ("uncond", 32, 64), ("alg1", 8, 1), ("std", 4, 2),
+                                      ("alg1", 128, 128), ("alg1", 256, 2), ("std", 128, 9),
+                                      ("uncond", 256, 4)])
 @pytest.mark.parametrize("symmetric", [False, True])
 def test_aggregate_parity(mg, gname, mode, k, L, symmetric):
     g = graph(gname)
@@ -128,6 +132,8 @@ RUNS = [
     ("leiden", "std", 4, 128),
     ("leiden", "alg1", 64, 128), ("louvain", "alg1", 32, 16), ("lpa", "alg1", 64, 5),
     ("leiden", "uncond", 32, 128), ("louvain", "std", 64, 128),
+    ("leiden", "alg1", 128, 128), ("louvain", "alg1", 256, 16), ("lpa", "std", 128, 5),
+    ("louvain", "uncond", 256, 128), ("leiden", "alg1", 256, 3),
 ]
 
 
@@ -298,7 +304,7 @@ def test_batched_equals_solo(mg, algo, mode, k, L, direct):
         assert np.array_equal(_np(lab), elab)
 
 
-@pytest.mark.parametrize("k", [8, 16, 32, 64])
+@pytest.mark.parametrize("k", [8, 16, 32, 64, 128, 256])
 def test_wave_sketch_deep_merge_tree(mg, k):
     """A hub row of 6,000 entries with L = 1: a merge tree of more than 4,096 chunk
     sketches (the deep stack of the wave sketch at k >= 32; about 94 groups of 64
@@ -340,7 +346,7 @@ def _hub_graph(seed):
     return synth.from_edges(n, edges, w)
 
 
-@pytest.mark.parametrize("k", [32, 64])
+@pytest.mark.parametrize("k", [32, 64, 128, 256])
 @pytest.mark.parametrize("mode", ["alg1", "uncond", "std"])
 @pytest.mark.parametrize("L", [1, 37, 128, 700])
 def test_wave_split_rows(mg, k, mode, L):

@@ -301,6 +301,36 @@ int mgcd_server_info(mgcd_server *s, int64_t *waiting, int64_t *running, size_t 
                      size_t *peak_bytes);
 int mgcd_server_destroy(mgcd_server *s);
 
+/* ---- serving by steps (Section 3.2 sweeps as the unit of scheduling) --------------
+ *
+ * A stepped server keeps every resident request's state on the device and advances
+ * all of them together: one step is one local-moving sweep (LPA: one propagation
+ * sweep) over the disjoint union of the resident requests' current level graphs,
+ * each graph under its own stopping rule, sweep direction, tolerance and total weight
+ * W.  A request whose level ended takes its phase transition on its own between steps
+ * (Louvain: renumbering and aggregation, Section 3.3; Leiden: refinement first,
+ * Section 4.2; LPA: its final labels), and requests that arrived join at the next
+ * step.  Each request's labels and the stats fields iterations, passes, communities,
+ * edges_scanned and moved_last are identical to those of the same call made alone;
+ * ms_total is the host time from admission to completion and the other times are 0.
+ *
+ * mgcd_server_create_stepped: arena as for mgcd_server_create.  Its first
+ *   shared_bytes (0: 45% of the arena) hold the union during steps and the phase work
+ *   between them; the rest holds each resident request's own block (its labels,
+ *   degrees and aggregated levels; first fit).  A request is admitted in arrival
+ *   order once fewer than max_resident (1..65536) requests are resident, its block
+ *   fits and the union of the resident requests with it (sized at their input sizes)
+ *   fits the shared region.  One scheduler thread and one HIP stream (default
+ *   priority) on the device current at creation.  params are checked at creation
+ *   (MGCD_E_ARG / MGCD_E_UNSUPPORTED as the calls return them).  Submission, poll,
+ *   wait, info (bytes_in_use and the peak count the blocks; the shared region is
+ *   reserved) and destroy are those of mgcd_server_*.  mgcd_server_submit returns
+ *   MGCD_E_WORKSPACE when the request alone exceeds the blocks' part or the shared
+ *   region.  Graph errors (validation when params ask for it, MGCD_E_OVERFLOW) fail
+ *   that request alone; a device error fails every resident request. */
+int mgcd_server_create_stepped(void *arena, size_t arena_bytes, size_t shared_bytes, int32_t max_resident,
+                               int32_t algo, const mgcd_params *p, mgcd_server **out);
+
 /* Message of the last error on this thread ("" if none). */
 const char *mgcd_last_error(void);
 

@@ -115,6 +115,8 @@ def lib():
             f.restype = ct.c_int
         L.mgcd_server_create.argtypes = [P, sz, i32, i32, ct.POINTER(Params), ct.POINTER(P)]
         L.mgcd_server_create.restype = ct.c_int
+        L.mgcd_server_create_stepped.argtypes = [P, sz, sz, i32, i32, ct.POINTER(Params), ct.POINTER(P)]
+        L.mgcd_server_create_stepped.restype = ct.c_int
         L.mgcd_server_submit.argtypes = [P, ct.POINTER(CSRDesc), P, ct.POINTER(i64)]
         L.mgcd_server_submit.restype = ct.c_int
         L.mgcd_server_poll.argtypes = [P, i64, ct.POINTER(i32)]
@@ -321,12 +323,16 @@ def run_batched(algo: int, graphs, workspace=None, **kw):
 
 
 class Server:
-    """Continuous-batching server over the library's mgcd_server_* calls: `slots`
-    worker streams run whole calls of `algo` for submitted graphs, each in a block of
-    one device arena of `arena_bytes`.  submit() returns a ticket; wait() returns
-    (labels, stats, (t_submit, t_start, t_end)) with times in seconds since creation."""
+    """Continuous-batching server over the library's mgcd_server_* calls, in one device
+    arena of `arena_bytes`.  stepped=False: `slots` worker streams run whole calls of
+    `algo`, each in a block of the arena.  stepped=True: up to `slots` resident
+    requests advance together one sweep per step (mgcd_server_create_stepped;
+    shared_bytes as there, 0 = its default).  submit() returns a ticket; wait()
+    returns (labels, stats, (t_submit, t_start, t_end)) with times in seconds since
+    creation."""
 
-    def __init__(self, algo: int, arena_bytes: int, slots: int = 4, device: str = "cuda", **kw):
+    def __init__(self, algo: int, arena_bytes: int, slots: int = 4, device: str = "cuda",
+                 stepped: bool = False, shared_bytes: int = 0, **kw):
         import torch
         self.algo = algo
         self.p = params(algo, **kw)
@@ -334,8 +340,13 @@ class Server:
         self.device = self.arena.device
         self._h = ct.c_void_p()
         self._held = {}
-        _check(lib().mgcd_server_create(self.arena.data_ptr(), int(arena_bytes), int(slots), algo,
-                                        ct.byref(self.p), ct.byref(self._h)))
+        torch.cuda.current_stream().synchronize()  # the arena exists before the server uses it
+        if stepped:
+            _check(lib().mgcd_server_create_stepped(self.arena.data_ptr(), int(arena_bytes), int(shared_bytes),
+                                                    int(slots), algo, ct.byref(self.p), ct.byref(self._h)))
+        else:
+            _check(lib().mgcd_server_create(self.arena.data_ptr(), int(arena_bytes), int(slots), algo,
+                                            ct.byref(self.p), ct.byref(self._h)))
 
     def submit(self, g: DeviceGraph) -> int:
         import torch

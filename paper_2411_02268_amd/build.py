@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmgcd.so")
-SOURCES = ["primitives.hip", "move.hip", "aggregate.hip", "batch.hip", "driver.hip", "server.hip"]
+SOURCES = ["primitives.hip", "move.hip", "aggregate.hip", "batch.hip", "driver.hip", "server.hip", "stepped.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -20,6 +20,7 @@
 #include "batch.hpp"
 #include "move.hpp"
 #include "primitives.hpp"
+#include "stepped.hpp"
 
 namespace mgcd {
 
@@ -510,6 +511,13 @@ static mgcd_params resolved(const mgcd_params *p) {
   }
   return q;
 }
+mgcd_params mgcd::checked_params(const mgcd_params *p) {
+  if (!p) throw Error(MGCD_E_ARG, "params is null");
+  const mgcd_params q = resolved(p);
+  check_params(&q);
+  return q;
+}
+
 #define MGCD_RESOLVE(p)                 \
   const mgcd_params resolved_ = resolved(p); \
   if (p) p = &resolved_

@@ -108,7 +108,8 @@ __device__ inline void finish(const SweepArgs &a, int32_t i, int32_t d, int32_t 
       ct.prop += 1;
       ct.sumG += (uint64_t)bestG;
     }
-    bool ok = a.dir == 0 || (a.dir < 0 ? best < d : best > d);
+    const int dir = a.gdir ? (int)a.gdir[a.gid[i]] : a.dir;
+    bool ok = dir == 0 || (dir < 0 ? best < d : best > d);
     if (ok) target = best;
   }
   a.Cnew[i] = target;

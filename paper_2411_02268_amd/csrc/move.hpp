@@ -30,6 +30,9 @@ struct SweepArgs {
   // one wave per work item.
   const uint32_t *live = nullptr;
   unsigned long long *queue = nullptr;
+  // Graphs at different sweeps of their own levels (serving): each graph's direction
+  // (-1, +1 or 0), by graph; null: every vertex takes `dir`.
+  const int8_t *gdir = nullptr;
   // Single graph: a device flag; once set, every vertex keeps its community (the
   // sweep only copies C to C_new).  Null: always move.
   const uint32_t *halt = nullptr;

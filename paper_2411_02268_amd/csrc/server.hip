@@ -1,5 +1,8 @@
-// Serving (continuous batching): worker threads with their own streams run whole
-// calls for a queue of requests, each in a block of one caller-provided arena.
+// Serving (continuous batching), in two forms over one caller-provided arena:
+// whole calls -- worker threads with their own streams each run one request's call at
+// a time in a block of the arena; or steps -- one scheduler thread advances every
+// resident request together, one sweep per step, through the step engine
+// (stepped.hip), admitting new requests between steps.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -9,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -16,6 +20,7 @@
 
 #include "common.hpp"
 #include "mgcd.h"
+#include "stepped.hpp"
 
 namespace {
 
@@ -31,6 +36,8 @@ struct Request {
   std::string err;
   mgcd_stats stats{};
   double t_submit = 0, t_start = 0, t_end = 0;
+  size_t off = 0;       // its block in the arena
+  mgcd::StepJob job;    // step-level serving
 };
 
 // First-fit allocator over [0, cap) with coalescing of free neighbours.
@@ -98,6 +105,15 @@ struct mgcd_server {
   int64_t next_ticket = 1;
   int64_t running = 0;
   bool stopping = false;
+  // step-level serving: the shared region [0, shared) of the arena, blocks after it
+  bool stepped = false;
+  int64_t max_resident = 0;
+  size_t shared = 0;
+  std::unique_ptr<mgcd::StepEngine> engine;
+  std::unordered_map<Request *, std::shared_ptr<Request>> resident;
+  int64_t res_N = 0, res_E = 0;
+  std::multiset<int32_t> res_n;
+  std::multiset<int64_t> res_nnz;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
   double now() const {
@@ -134,6 +150,101 @@ struct mgcd_server {
       --running;
       cv_done.notify_all();
       cv_admit.notify_all();  // freed memory may admit the next request
+    }
+  }
+
+  // Step-level serving: the oldest waiting requests join while a resident place is
+  // free, the shared region holds the union with them and their block fits (in
+  // arrival order; a request that does not fit waits for earlier ones to finish).
+  void admit_waiting(std::vector<std::shared_ptr<Request>> &adm) {
+    while (!waiting.empty() && (int64_t)resident.size() < max_resident) {
+      std::shared_ptr<Request> r = waiting.front();
+      const int32_t n = (int32_t)r->g.n;
+      const int64_t nnz = r->g.nnz;
+      const int32_t mx_n = std::max(n, res_n.empty() ? 0 : *res_n.rbegin());
+      const int64_t mx_e = std::max(nnz, res_nnz.empty() ? (int64_t)0 : *res_nnz.rbegin());
+      const size_t need = mgcd::StepEngine::shared_need(algo, params, (int64_t)resident.size() + 1, res_N + n,
+                                                        res_E + nnz, mx_n, mx_e);
+      size_t off = 0;
+      if (need > shared || !blocks.take(r->need, &off)) break;
+      waiting.pop_front();
+      r->off = off;
+      r->job.g = r->g;
+      r->job.out = r->out;
+      r->job.block = arena + shared + off;
+      r->job.user = r.get();
+      r->state = 1;
+      r->t_start = now();
+      resident[r.get()] = r;
+      res_N += n;
+      res_E += nnz;
+      res_n.insert(n);
+      res_nnz.insert(nnz);
+      ++running;
+      adm.push_back(r);
+    }
+  }
+
+  void complete(Request *r) {
+    blocks.give(r->off, r->need);
+    res_N -= r->g.n;
+    res_E -= r->g.nnz;
+    res_n.erase(res_n.find((int32_t)r->g.n));
+    res_nnz.erase(res_nnz.find(r->g.nnz));
+    r->rc = r->job.rc;
+    r->err = r->job.err;
+    r->stats = r->job.stats;
+    r->t_end = now();
+    r->state = 2;
+    --running;
+    resident.erase(r);
+  }
+
+  void run_steps() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      std::vector<std::shared_ptr<Request>> adm;
+      admit_waiting(adm);
+      if (adm.empty() && resident.empty()) {
+        if (waiting.empty()) {
+          if (stopping) break;
+          cv_admit.wait(lk, [&] { return stopping || !waiting.empty(); });
+          continue;
+        }
+        // nothing resident and the oldest request still does not fit: it never will
+        std::shared_ptr<Request> r = waiting.front();
+        waiting.pop_front();
+        r->rc = MGCD_E_WORKSPACE;
+        r->err = "request does not fit the server's arena";
+        r->t_start = r->t_end = now();
+        r->state = 2;
+        cv_done.notify_all();
+        continue;
+      }
+      lk.unlock();
+      std::vector<mgcd::StepJob *> fin;
+      auto fail = [&](int code, const std::string &msg) {
+        engine->fail_all(code, msg, fin);
+        for (auto &r : adm)
+          if (!r->job.done) {
+            r->job.rc = code;
+            r->job.err = msg;
+            r->job.done = true;
+            fin.push_back(&r->job);
+          }
+      };
+      try {
+        for (auto &r : adm) engine->admit(&r->job, fin);
+        engine->step(fin);
+      } catch (const mgcd::Error &e) {
+        fail(e.code, e.what());
+      } catch (const std::exception &e) {
+        fail(MGCD_E_ARG, e.what());
+      }
+      lk.lock();
+      for (mgcd::StepJob *j : fin) complete((Request *)j->user);
+      if (!fin.empty()) cv_done.notify_all();
     }
   }
 };
@@ -176,6 +287,49 @@ int mgcd_server_create(void *arena, size_t arena_bytes, int32_t slots, int32_t a
   return MGCD_OK;
 }
 
+int mgcd_server_create_stepped(void *arena, size_t arena_bytes, size_t shared_bytes, int32_t max_resident,
+                               int32_t algo, const mgcd_params *p, mgcd_server **out) {
+  if (!out) return fail(MGCD_E_ARG, "out is null");
+  *out = nullptr;
+  if (!arena || arena_bytes == 0) return fail(MGCD_E_ARG, "arena is empty");
+  if (((uintptr_t)arena % ALIGN) != 0) return fail(MGCD_E_ARG, "arena must be 256-byte aligned");
+  if (max_resident < 1 || max_resident > (1 << 16)) return fail(MGCD_E_ARG, "max_resident must be in [1, 65536]");
+  if (algo < MGCD_ALGO_LPA || algo > MGCD_ALGO_LEIDEN) return fail(MGCD_E_UNSUPPORTED, "unknown algorithm");
+  const size_t cap = arena_bytes / ALIGN * ALIGN;
+  if (shared_bytes == 0) shared_bytes = cap / 20 * 9;  // 45%
+  shared_bytes = shared_bytes / ALIGN * ALIGN;
+  if (shared_bytes == 0 || shared_bytes >= cap) return fail(MGCD_E_ARG, "shared_bytes must leave room for blocks");
+  auto s = std::make_unique<mgcd_server>();
+  s->arena = (char *)arena;
+  s->algo = algo;
+  try {
+    mgcd_params d;
+    if (!p) {
+      mgcd_default_params(algo, &d);
+      p = &d;
+    }
+    s->params = mgcd::checked_params(p);
+    if (algo != MGCD_ALGO_LPA && s->params.one_scan)
+      throw mgcd::Error(MGCD_E_UNSUPPORTED, "one_scan is defined for LPA only");
+  } catch (const mgcd::Error &e) {
+    return fail(e.code, e.what());
+  }
+  s->stepped = true;
+  s->max_resident = max_resident;
+  s->shared = shared_bytes;
+  s->blocks = BlockAllocator(cap - shared_bytes);
+  if (hipGetDevice(&s->device) != hipSuccess) return fail(MGCD_E_HIP, "hipGetDevice failed");
+  mgcd::set_last_error("");
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+    return fail(MGCD_E_HIP, "hipStreamCreateWithFlags failed");
+  s->streams.push_back(st);
+  s->engine = std::make_unique<mgcd::StepEngine>(algo, s->params, s->arena, shared_bytes, st);
+  s->workers.emplace_back([srv = s.get()] { srv->run_steps(); });
+  *out = s.release();
+  return MGCD_OK;
+}
+
 int mgcd_server_submit(mgcd_server *s, const mgcd_csr *g, int32_t *communities_out,
                        int64_t *ticket) {
   if (!s || !g || !ticket) return fail(MGCD_E_ARG, "null argument");
@@ -184,13 +338,17 @@ int mgcd_server_submit(mgcd_server *s, const mgcd_csr *g, int32_t *communities_o
   auto r = std::make_shared<Request>();
   r->g = *g;
   r->out = communities_out;
-  const size_t need = mgcd_workspace_bytes(s->algo, g->n, g->nnz, &s->params);
+  const size_t need = s->stepped ? mgcd::StepEngine::block_bytes(s->algo, s->params, g->n, g->nnz)
+                                 : mgcd_workspace_bytes(s->algo, g->n, g->nnz, &s->params);
   r->need = need < ALIGN ? ALIGN : (need + ALIGN - 1) / ALIGN * ALIGN;
   std::lock_guard<std::mutex> lk(s->mu);
   size_t cap = 0;
   for (auto &b : s->blocks.free_) cap += b.second;
   cap += s->blocks.used;
   if (r->need > cap) return fail(MGCD_E_WORKSPACE, "request needs more than the whole arena");
+  if (s->stepped &&
+      mgcd::StepEngine::shared_need(s->algo, s->params, 1, g->n, g->nnz, (int32_t)g->n, g->nnz) > s->shared)
+    return fail(MGCD_E_WORKSPACE, "request needs more than the server's shared region");
   if (s->stopping) return fail(MGCD_E_ARG, "server is shutting down");
   r->ticket = s->next_ticket++;
   r->t_submit = s->now();

@@ -76,49 +76,58 @@ def class_bytes(g, L: int, k: int, cands: float = 0.0):
     return [c0, c1, 0]
 
 
-def serving_leg(mg, torch, requests: int, slots: int, budget_gb: float, seed: int = 5):
-    """Louvain MG k=8 requests on R-MAT graphs of 2^14..2^21 vertices (scale uniform,
-    average degree 16, weights [1, 8]) arriving as a Poisson stream, served by
-    mg.Server under a device-memory budget.  One graph per scale (seed 500 + scale) is
-    generated once and every request of that scale reuses it.  Capacities are measured
-    closed-loop (all requests queued at once): mu_plain with one slot (a FIFO of plain
-    per-graph launches), mu_batched with `slots` slots.  Latency = completion minus
-    submission (server clock).  Every served result is compared with the plain launch's
-    labels on the device (bit-identical, hence equal modularity)."""
+def serving_leg(mg, torch, requests: int, slots: int, resident: int, sweeps: int, budget_gb: float,
+                seed: int = 5):
+    """Louvain MG k=8 requests from synth.serving_stream: every request is its own
+    R-MAT graph (2^s vertices, s uniform in [14, 21], 8 * 2^s edge samples, weights
+    [1, 8]; drawn on the GPU by synth.rmat_torch from the request's seed), arriving as
+    a Poisson stream.  Three ways to serve it, each in a device arena of budget_gb:
+      plain -- one whole call at a time (the server with one slot: a FIFO of plain
+               launches),
+      calls -- `slots` worker streams, each running whole calls,
+      steps -- up to `resident` requests advancing together, up to `sweeps` sweeps per
+               step (0: each step takes every resident level to its end).
+    Capacities are measured closed-loop (all requests queued at once); latencies
+    open-loop at 0.8 * mu_plain for all three, and at 0.8 * mu of each server.
+    Latency = completion minus submission (server clock).  Every served result is
+    compared on the device with the request's own plain call (labels, bit-identical,
+    hence equal modularity)."""
     import threading
     from paper_2411_02268_amd import synth
-    scales = list(range(14, 22))
+    reqs = synth.serving_stream(count=requests, smin=14, smax=21, deg=16, rate_hz=1.0, seed=seed)
     t0 = time.time()
-    pool = {s: mg.to_device(synth.rmat(scale=s, edge_factor=8, seed=500 + s)) for s in scales}
-    print(f"[bench] serving pool generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    solo, svc, q = {}, {}, {}
-    for s, dg in pool.items():
-        mg.louvain(dg)
+    graphs = [mg.DeviceGraph(*synth.rmat_torch(s, 8, seed=gs)) for _, s, gs in reqs]
+    torch.cuda.synchronize()
+    nnz = np.array([g.nnz for g in graphs], dtype=np.int64)
+    print(f"[bench] serving: {requests} distinct R-MAT requests ({int(nnz.sum())} entries) generated "
+          f"in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    mg.louvain(graphs[0])
+    solo, svc = [], np.zeros(requests)
+    for i, g in enumerate(graphs):
         torch.cuda.synchronize()
         a = time.perf_counter()
-        lab, st = mg.louvain(dg)
+        lab, st = mg.louvain(g)
         torch.cuda.synchronize()
-        svc[s] = time.perf_counter() - a
-        solo[s] = (lab, st)
-        q[s] = mg.modularity(dg, lab)
-    rng = np.random.default_rng(seed)
-    req_scales = rng.integers(14, 22, size=requests)
-    unit_gaps = rng.exponential(1.0, size=requests)
+        svc[i] = time.perf_counter() - a
+        solo.append(lab)
+    scales = np.array([s for _, s, _ in reqs])
+    unit = np.array([t for t, _, _ in reqs])  # arrival times at one request per second
     budget = int(budget_gb * (1 << 30))
     same = [True]
 
-    def run(nslots, rate):
-        arrivals = np.zeros(requests) if rate is None else np.cumsum(unit_gaps / rate)
+    def run(kind, rate):
+        arrivals = np.zeros(requests) if rate is None else unit / rate
         tickets = [None] * requests
         ready = threading.Semaphore(0)
         out = [None] * requests
-        with mg.Server(mg.ALGO_LOUVAIN, budget, slots=nslots) as srv:
+        nsl = {"plain": 1, "calls": slots, "steps": resident}[kind]
+        with mg.Server(mg.ALGO_LOUVAIN, budget, slots=nsl, stepped=kind == "steps",
+                       sweeps_per_step=sweeps) as srv:
             def waiter():
                 for k in range(requests):
                     ready.acquire()
                     lab, st, tm = srv.wait(tickets[k])
-                    ok = bool(torch.equal(lab, solo[int(req_scales[k])][0]))
-                    out[k] = (tm, st["edges_scanned"], ok)
+                    out[k] = (tm, st["edges_scanned"], bool(torch.equal(lab, solo[k])))
             th = threading.Thread(target=waiter)
             th.start()
             start = time.perf_counter()
@@ -126,7 +135,7 @@ def serving_leg(mg, torch, requests: int, slots: int, budget_gb: float, seed: in
                 delay = start + arrivals[k] - time.perf_counter()
                 if delay > 0:
                     time.sleep(delay)
-                tickets[k] = srv.submit(pool[int(req_scales[k])])
+                tickets[k] = srv.submit(graphs[k])
                 ready.release()
             th.join()
             peak = srv.info()["peak_bytes"]
@@ -135,28 +144,31 @@ def serving_leg(mg, torch, requests: int, slots: int, budget_gb: float, seed: in
         t_last = max(o[0][2] for o in out)
         edges = sum(o[1] for o in out)
         same[0] &= all(o[2] for o in out)
-        return {"slots": nslots, "rate_rps": rate, "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
-                "throughput_rps": requests / (t_last - t_first),
-                "edges_per_s": edges / (t_last - t_first), "peak_arena_GB": peak / 2**30}
+        r = {"kind": kind, "slots": nsl, "rate_rps": rate, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+             "throughput_rps": requests / (t_last - t_first),
+             "edges_per_s": edges / (t_last - t_first), "peak_blocks_GB": peak / 2**30}
+        print(f"[bench] serving {kind} rate {'closed' if rate is None else f'{rate:.1f}/s'}: "
+              f"{r['throughput_rps']:.1f} req/s, p50 {r['p50_ms']:.2f} ms, p99 {r['p99_ms']:.2f} ms",
+              file=sys.stderr, flush=True)
+        return r
 
-    cap_plain = run(1, None)
-    cap_batched = run(slots, None)
-    mu_p, mu_b = cap_plain["throughput_rps"], cap_batched["throughput_rps"]
+    kinds = ("plain", "calls", "steps")
+    cap = {kd: run(kd, None) for kd in kinds}
+    mu_p = cap["plain"]["throughput_rps"]
     res = {
         "requests": requests, "algorithm": "louvain", "k": 8, "budget_GB": budget_gb,
-        "scales": "2^14..2^21 vertices, uniform in the exponent; one pooled graph per scale",
-        "modularity_by_scale": {str(s): q[s] for s in scales},
-        "plain_service_ms_by_scale": {str(s): svc[s] * 1e3 for s in scales},
-        "capacity": {"plain": cap_plain, "batched": cap_batched},
-        "at_0.8_mu_plain": {"plain": run(1, 0.8 * mu_p), "batched": run(slots, 0.8 * mu_p)},
-        "at_0.8_mu_batched": {"batched": run(slots, 0.8 * mu_b)},
+        "calls_slots": slots, "steps_resident": resident, "steps_sweeps_per_step": sweeps,
+        "workload": "synth.serving_stream: distinct R-MAT graphs, 2^14..2^21 vertices (scale "
+                    "uniform), 8 * 2^s edge samples, weights [1, 8], Poisson arrivals",
+        "entries_total": int(nnz.sum()),
+        "plain_service_ms_by_scale": {str(s): float(svc[scales == s].mean() * 1e3)
+                                      for s in sorted(set(scales.tolist()))},
+        "capacity": cap,
+        "at_0.8_mu_plain": {kd: run(kd, 0.8 * mu_p) for kd in kinds},
+        "at_0.8_own_mu": {kd: run(kd, 0.8 * cap[kd]["throughput_rps"]) for kd in ("calls", "steps")},
     }
     res["labels_identical_to_plain"] = same[0]
-    for key in ("at_0.8_mu_plain", "at_0.8_mu_batched"):
-        for mode, r in res[key].items():
-            print(f"[bench] serving {key} {mode}: rate {r['rate_rps']:.1f}/s p50 {r['p50_ms']:.2f} ms "
-                  f"p99 {r['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
     return res
 
 
@@ -303,9 +315,13 @@ def main():
     ap.add_argument("--exact-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=None,
-                    help="requests of the serving leg (0 skips it; default 2000 with the "
+                    help="requests of the serving leg (0 skips it; default 1000 with the "
                          "default workload, else 0)")
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=4, help="worker streams of the whole-call server")
+    ap.add_argument("--serve-resident", type=int, default=32,
+                    help="resident requests of the step-level server")
+    ap.add_argument("--serve-sweeps", type=int, default=0,
+                    help="sweeps per step of the step-level server (0: a whole level per step)")
     ap.add_argument("--batch-graphs", type=int, default=None,
                     help="graphs of the batched leg (0 skips it; default 4096 with the "
                          "default workload, else 0)")
@@ -328,7 +344,7 @@ def main():
         sys.exit(2)
     default = args.workload == DEFAULT_WORKLOAD
     if args.serve_requests is None:
-        args.serve_requests = 2000 if default else 0
+        args.serve_requests = 1000 if default else 0
     if args.batch_graphs is None:
         args.batch_graphs = 4096 if default else 0
 
@@ -425,7 +441,8 @@ def main():
 
     serving = None
     if args.serve_requests > 0:
-        serving = serving_leg(mg, torch, args.serve_requests, args.serve_slots, 64.0)
+        serving = serving_leg(mg, torch, args.serve_requests, args.serve_slots, args.serve_resident,
+                              args.serve_sweeps, 64.0)
 
     batched = None
     if args.batch_graphs > 0:

@@ -304,20 +304,23 @@ int mgcd_server_destroy(mgcd_server *s);
 /* ---- serving by steps (Section 3.2 sweeps as the unit of scheduling) --------------
  *
  * A stepped server keeps every resident request's state on the device and advances
- * all of them together: one step is one local-moving sweep (LPA: one propagation
- * sweep) over the disjoint union of the resident requests' current level graphs,
- * each graph under its own stopping rule, sweep direction, tolerance and total weight
- * W.  A request whose level ended takes its phase transition on its own between steps
- * (Louvain: renumbering and aggregation, Section 3.3; Leiden: refinement first,
- * Section 4.2; LPA: its final labels), and requests that arrived join at the next
- * step.  Each request's labels and the stats fields iterations, passes, communities,
+ * all of them together: one step is up to sweeps_per_step local-moving sweeps (LPA:
+ * propagation sweeps) over the disjoint union of the resident requests' current level
+ * graphs, each graph under its own stopping rule, sweep direction, tolerance and
+ * total weight W; a graph whose level ends within the step stays frozen for the rest
+ * of it, and the step ends early once no graph moves.  A request whose level ended
+ * takes its phase transition on its own between steps (Louvain: renumbering and
+ * aggregation, Section 3.3; Leiden: refinement first, Section 4.2; LPA: its final
+ * labels), and requests that arrived join at the next step.  Each request's labels and the stats fields iterations, passes, communities,
  * edges_scanned and moved_last are identical to those of the same call made alone;
  * ms_total is the host time from admission to completion and the other times are 0.
  *
  * mgcd_server_create_stepped: arena as for mgcd_server_create.  Its first
  *   shared_bytes (0: 45% of the arena) hold the union during steps and the phase work
  *   between them; the rest holds each resident request's own block (its labels,
- *   degrees and aggregated levels; first fit).  A request is admitted in arrival
+ *   degrees and aggregated levels; first fit).  sweeps_per_step >= 1, or 0 for
+ *   max_iterations (each step takes every resident level to its end).  A request is
+ *   admitted in arrival
  *   order once fewer than max_resident (1..65536) requests are resident, its block
  *   fits and the union of the resident requests with it (sized at their input sizes)
  *   fits the shared region.  One scheduler thread and one HIP stream (default
@@ -329,7 +332,22 @@ int mgcd_server_destroy(mgcd_server *s);
  *   region.  Graph errors (validation when params ask for it, MGCD_E_OVERFLOW) fail
  *   that request alone; a device error fails every resident request. */
 int mgcd_server_create_stepped(void *arena, size_t arena_bytes, size_t shared_bytes, int32_t max_resident,
-                               int32_t algo, const mgcd_params *p, mgcd_server **out);
+                               int32_t sweeps_per_step, int32_t algo, const mgcd_params *p,
+                               mgcd_server **out);
+
+/* Where a stepped server's time went (host clock; zero for a whole-call server):
+ * steps and sweeps issued, sweeps in which some graph moved, unions packed, phase
+ * transitions; rows_swept = union rows summed over the sweeps in which some graph
+ * moved and rows_moving = the rows of the graphs that moved in them (their ratio is
+ * the share of swept rows that were not frozen); seconds spent packing unions and
+ * building their schedules, in sweeps and their read-back, and in phase work
+ * (admissions, transitions, final labels).  Counters since creation. */
+typedef struct {
+  int64_t steps, sweeps, sweeps_moving, packs, transitions;
+  int64_t rows_swept, rows_moving;
+  double s_pack, s_sweep, s_phase;
+} mgcd_step_stats;
+int mgcd_server_step_stats(mgcd_server *s, mgcd_step_stats *out);
 
 /* Message of the last error on this thread ("" if none). */
 const char *mgcd_last_error(void);

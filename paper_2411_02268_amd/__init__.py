@@ -67,6 +67,15 @@ class GraphStats(ct.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class StepStats(ct.Structure):
+    _fields_ = [(f, ct.c_int64) for f in ("steps", "sweeps", "sweeps_moving", "packs", "transitions",
+                                          "rows_swept", "rows_moving")] + \
+               [(f, ct.c_double) for f in ("s_pack", "s_sweep", "s_phase")]
+
+    def asdict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class CSRDesc(ct.Structure):
     _fields_ = [("n", ct.c_int32), ("reserved", ct.c_int32), ("nnz", ct.c_int64),
                 ("offsets", ct.c_void_p), ("indices", ct.c_void_p), ("weights", ct.c_void_p)]
@@ -115,8 +124,10 @@ def lib():
             f.restype = ct.c_int
         L.mgcd_server_create.argtypes = [P, sz, i32, i32, ct.POINTER(Params), ct.POINTER(P)]
         L.mgcd_server_create.restype = ct.c_int
-        L.mgcd_server_create_stepped.argtypes = [P, sz, sz, i32, i32, ct.POINTER(Params), ct.POINTER(P)]
+        L.mgcd_server_create_stepped.argtypes = [P, sz, sz, i32, i32, i32, ct.POINTER(Params), ct.POINTER(P)]
         L.mgcd_server_create_stepped.restype = ct.c_int
+        L.mgcd_server_step_stats.argtypes = [P, ct.POINTER(StepStats)]
+        L.mgcd_server_step_stats.restype = ct.c_int
         L.mgcd_server_submit.argtypes = [P, ct.POINTER(CSRDesc), P, ct.POINTER(i64)]
         L.mgcd_server_submit.restype = ct.c_int
         L.mgcd_server_poll.argtypes = [P, i64, ct.POINTER(i32)]
@@ -326,13 +337,14 @@ class Server:
     """Continuous-batching server over the library's mgcd_server_* calls, in one device
     arena of `arena_bytes`.  stepped=False: `slots` worker streams run whole calls of
     `algo`, each in a block of the arena.  stepped=True: up to `slots` resident
-    requests advance together one sweep per step (mgcd_server_create_stepped;
-    shared_bytes as there, 0 = its default).  submit() returns a ticket; wait()
+    requests advance together, up to `sweeps_per_step` sweeps per step
+    (mgcd_server_create_stepped; shared_bytes and sweeps_per_step as there, 0 = their
+    defaults).  submit() returns a ticket; wait()
     returns (labels, stats, (t_submit, t_start, t_end)) with times in seconds since
     creation."""
 
     def __init__(self, algo: int, arena_bytes: int, slots: int = 4, device: str = "cuda",
-                 stepped: bool = False, shared_bytes: int = 0, **kw):
+                 stepped: bool = False, shared_bytes: int = 0, sweeps_per_step: int = 0, **kw):
         import torch
         self.algo = algo
         self.p = params(algo, **kw)
@@ -343,7 +355,8 @@ class Server:
         torch.cuda.current_stream().synchronize()  # the arena exists before the server uses it
         if stepped:
             _check(lib().mgcd_server_create_stepped(self.arena.data_ptr(), int(arena_bytes), int(shared_bytes),
-                                                    int(slots), algo, ct.byref(self.p), ct.byref(self._h)))
+                                                    int(slots), int(sweeps_per_step), algo, ct.byref(self.p),
+                                                    ct.byref(self._h)))
         else:
             _check(lib().mgcd_server_create(self.arena.data_ptr(), int(arena_bytes), int(slots), algo,
                                             ct.byref(self.p), ct.byref(self._h)))
@@ -376,6 +389,11 @@ class Server:
         u, pk = ct.c_size_t(), ct.c_size_t()
         _check(lib().mgcd_server_info(self._h, ct.byref(w), ct.byref(r), ct.byref(u), ct.byref(pk)))
         return {"waiting": w.value, "running": r.value, "bytes_in_use": u.value, "peak_bytes": pk.value}
+
+    def step_stats(self) -> dict:
+        st = StepStats()
+        _check(lib().mgcd_server_step_stats(self._h, ct.byref(st)))
+        return st.asdict()
 
     def close(self):
         if self._h:

@@ -32,6 +32,7 @@ namespace mgcd {
 
 struct Counters {
   uint32_t moved = 0, prop = 0, cand = 0;
+  int32_t g = 0;  // batched: the graph of the rows counted (one row per lane per flush)
   uint64_t sumG = 0;
 };
 
@@ -104,30 +105,55 @@ __device__ inline void finish(const SweepArgs &a, int32_t i, int32_t d, int32_t 
   if (ALGO == ALGO_LPA) {
     if (best >= 0) target = best;
   } else if (best >= 0) {
-    if (!a.gctr) {
-      ct.prop += 1;
-      ct.sumG += (uint64_t)bestG;
-    }
+    ct.prop += 1;
+    ct.sumG += (uint64_t)bestG;
     const int dir = a.gdir ? (int)a.gdir[a.gid[i]] : a.dir;
     bool ok = dir == 0 || (dir < 0 ? best < d : best > d);
     if (ok) target = best;
   }
   a.Cnew[i] = target;
   if (ALGO != ALGO_LPA && a.gain) a.gain[i] = best >= 0 ? bestG : 0;
-  if (a.gctr) {  // batched: per-graph counters (the block counters stay zero)
-    unsigned long long *gc = a.gctr + 3 * (int64_t)a.gid[i];
-    if (target != d) atomicAdd(&gc[0], 1ull);
-    if (ALGO != ALGO_LPA && best >= 0) {
-      atomicAdd(&gc[1], 1ull);
-      atomicAdd(&gc[2], (unsigned long long)bestG);
-    }
-    ct = Counters{};
-    return;
-  }
   ct.moved += target != d;
+  if (a.gctr) ct.g = a.gid[i];  // batched: added to the graph's counters when flushed
+}
+
+// Batched runs (all lanes of the wave): the lanes' counts go to their graphs'
+// counters, one atomic per graph and counter for the whole wave (lanes grouped by
+// graph, each group summed across the wave), then the counts restart.
+__device__ inline void flush_graph_counters(const SweepArgs &a, Counters &ct) {
+  const int lane = lane_id();
+  uint64_t todo = __ballot(ct.moved != 0 || ct.prop != 0);  // a gain comes with a proposal
+  while (todo) {  // wave-uniform
+    const int leader = __builtin_ctzll(todo);
+    const int32_t g = __shfl(ct.g, leader);
+    const bool mine = ((todo >> lane) & 1ull) != 0 && ct.g == g;
+    const unsigned long long m = wave_sum((unsigned long long)(mine ? ct.moved : 0u));
+    const unsigned long long p = wave_sum((unsigned long long)(mine ? ct.prop : 0u));
+    const unsigned long long sg = wave_sum((unsigned long long)(mine ? ct.sumG : 0ull));
+    if (lane == leader) {
+      unsigned long long *c = a.gctr + 3 * (int64_t)g;
+      if (m) atomicAdd(&c[0], m);
+      if (p) atomicAdd(&c[1], p);
+      if (sg) atomicAdd(&c[2], sg);
+    }
+    todo &= ~__ballot(mine);
+  }
+  ct = Counters{};
+}
+
+// One thread's counts of one row, to its graph's counters (batched) or the sweep's.
+__device__ inline void commit_counters(const SweepArgs &a, const Counters &ct) {
+  unsigned long long *c = a.gctr ? a.gctr + 3 * (int64_t)ct.g : a.ctr;
+  if (ct.moved) atomicAdd(&c[0], (unsigned long long)ct.moved);
+  if (ct.prop) atomicAdd(&c[1], (unsigned long long)ct.prop);
+  if (ct.sumG) atomicAdd(&c[2], (unsigned long long)ct.sumG);
 }
 
 __device__ inline void flush_counters(const SweepArgs &a, Counters ct) {
+  if (a.gctr) {  // batched (kernel-uniform): per graph, per wave
+    flush_graph_counters(a, ct);
+    return;
+  }
   __shared__ unsigned long long red[4][4];
   unsigned long long m = wave_sum((unsigned long long)ct.moved);
   unsigned long long p = wave_sum((unsigned long long)ct.prop);
@@ -335,9 +361,7 @@ __device__ inline void decide_long(const SweepArgs &a, int32_t i, int32_t d, con
   const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
   consider_slots<K, ALGO>(a, W, d, Ki, Sd, kd, key, ex, best, bestG);
   finish<ALGO>(a, i, d, best, bestG, ct);
-  if (ct.moved) atomicAdd(&a.ctr[0], (unsigned long long)ct.moved);
-  if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
-  if (ct.sumG) atomicAdd(&a.ctr[2], (unsigned long long)ct.sumG);
+  commit_counters(a, ct);
 }
 
 // cflag[m]: 0 decided here (exact sketch), 1 lossy (candidates in cand), 2 frozen.
@@ -633,10 +657,12 @@ __global__ void __launch_bounds__(BLOCK) MGCD_ROWS_OCCUPANCY(K)
       for (int t = 0; t < QGRAB; ++t) {
         const int64_t wave = c + (j + t) * QLANES;  // wave-uniform
         if (wave >= total) break;
-        if (wave < bk.ngroups)
+        if (wave < bk.ngroups) {
           long_group<K, ALGO, MODE>(a, bk, L, keybuf, win, wave);
-        else
+        } else {
           row_work<K, ALGO, MODE>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
+          if (a.gctr) flush_graph_counters(a, ct);  // the next item's rows may be another graph's
+        }
       }
     }
     flush_counters(a, ct);
@@ -1291,9 +1317,7 @@ __global__ void __launch_bounds__(BLOCK) k_exact_table(SweepArgs a, const int32_
     }
     Counters ct;
     finish<ALGO>(a, i, d, best, bestG, ct);
-    if (ct.moved) atomicAdd(&a.ctr[0], (unsigned long long)ct.moved);
-    if (ct.prop) atomicAdd(&a.ctr[1], (unsigned long long)ct.prop);
-    if (ct.sumG) atomicAdd(&a.ctr[2], (unsigned long long)ct.sumG);
+    commit_counters(a, ct);
   }
 }
 

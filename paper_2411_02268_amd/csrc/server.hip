@@ -25,6 +25,8 @@
 namespace {
 
 constexpr size_t ALIGN = 256;
+// Streams on which a stepped server runs the phase work of many requests at once.
+constexpr int STEP_PHASE_LANES = 4;
 
 struct Request {
   int64_t ticket = 0;
@@ -114,6 +116,7 @@ struct mgcd_server {
   int64_t res_N = 0, res_E = 0;
   std::multiset<int32_t> res_n;
   std::multiset<int64_t> res_nnz;
+  mgcd_step_stats step_stats{};  // the engine's counters, copied under the lock
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
   double now() const {
@@ -235,7 +238,9 @@ struct mgcd_server {
           }
       };
       try {
-        for (auto &r : adm) engine->admit(&r->job, fin);
+        std::vector<mgcd::StepJob *> js;
+        for (auto &r : adm) js.push_back(&r->job);
+        engine->admit(js, fin);
         engine->step(fin);
       } catch (const mgcd::Error &e) {
         fail(e.code, e.what());
@@ -243,6 +248,7 @@ struct mgcd_server {
         fail(MGCD_E_ARG, e.what());
       }
       lk.lock();
+      step_stats = engine->counters();
       for (mgcd::StepJob *j : fin) complete((Request *)j->user);
       if (!fin.empty()) cv_done.notify_all();
     }
@@ -288,12 +294,13 @@ int mgcd_server_create(void *arena, size_t arena_bytes, int32_t slots, int32_t a
 }
 
 int mgcd_server_create_stepped(void *arena, size_t arena_bytes, size_t shared_bytes, int32_t max_resident,
-                               int32_t algo, const mgcd_params *p, mgcd_server **out) {
+                               int32_t sweeps_per_step, int32_t algo, const mgcd_params *p, mgcd_server **out) {
   if (!out) return fail(MGCD_E_ARG, "out is null");
   *out = nullptr;
   if (!arena || arena_bytes == 0) return fail(MGCD_E_ARG, "arena is empty");
   if (((uintptr_t)arena % ALIGN) != 0) return fail(MGCD_E_ARG, "arena must be 256-byte aligned");
   if (max_resident < 1 || max_resident > (1 << 16)) return fail(MGCD_E_ARG, "max_resident must be in [1, 65536]");
+  if (sweeps_per_step < 0) return fail(MGCD_E_ARG, "sweeps_per_step must be >= 0");
   if (algo < MGCD_ALGO_LPA || algo > MGCD_ALGO_LEIDEN) return fail(MGCD_E_UNSUPPORTED, "unknown algorithm");
   const size_t cap = arena_bytes / ALIGN * ALIGN;
   if (shared_bytes == 0) shared_bytes = cap / 20 * 9;  // 45%
@@ -324,7 +331,13 @@ int mgcd_server_create_stepped(void *arena, size_t arena_bytes, size_t shared_by
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
     return fail(MGCD_E_HIP, "hipStreamCreateWithFlags failed");
   s->streams.push_back(st);
-  s->engine = std::make_unique<mgcd::StepEngine>(algo, s->params, s->arena, shared_bytes, st);
+  try {
+    s->engine = std::make_unique<mgcd::StepEngine>(algo, s->params, sweeps_per_step, s->arena, shared_bytes, st,
+                                                   STEP_PHASE_LANES);
+  } catch (const mgcd::Error &e) {
+    (void)hipStreamDestroy(st);
+    return fail(e.code, e.what());
+  }
   s->workers.emplace_back([srv = s.get()] { srv->run_steps(); });
   *out = s.release();
   return MGCD_OK;
@@ -394,6 +407,13 @@ int mgcd_server_info(mgcd_server *s, int64_t *waiting, int64_t *running, size_t 
   if (running) *running = s->running;
   if (bytes_in_use) *bytes_in_use = s->blocks.used;
   if (peak_bytes) *peak_bytes = s->blocks.peak;
+  return MGCD_OK;
+}
+
+int mgcd_server_step_stats(mgcd_server *s, mgcd_step_stats *out) {
+  if (!s || !out) return fail(MGCD_E_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->step_stats;
   return MGCD_OK;
 }
 

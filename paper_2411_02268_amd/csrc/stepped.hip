@@ -1,21 +1,26 @@
-// Step-level serving: one local-moving sweep per step over every resident request.
+// Step-level serving: every resident request advances together, sweep by sweep.
 //
 // While the resident set and their levels stay the same, their current level graphs
 // live packed as one disjoint union in the shared region (vertex and entry ids shifted
-// by each graph's base), with the union's labels, community totals and schedule; a
-// step is one sweep of Louvain's local moving (or LPA) over the union, the Sigma
-// update, and each graph's own stopping rule (Section 3.2, its own W, sweep direction
-// and tolerance), read back in one copy.  When some graph's level ends, or requests
-// join, the union is dissolved: labels and community totals go back to each request's
+// by each graph's base), with the union's labels, community totals and schedule.  A
+// step is up to S sweeps of Louvain's local moving (or LPA) over the union, each
+// followed by the Sigma update and each graph's own stopping rule (Section 3.2, with
+// its own W, sweep direction and tolerance) on the device: a graph whose level ended
+// is frozen for the rest of the step (its rows copy their labels), and once none moves
+// the step's remaining kernels return at once; the host reads the outcome once per
+// step.  When some graph's level ended, or requests join, the union is dissolved: labels and community totals go back to each request's
 // own block, the graphs whose level ended take their phase transition alone (Leiden
 // refinement, renumbering and aggregation, Section 3.3; or their final labels), and
 // the next step packs the union anew.  Because a graph's sweeps read only its own
 // rows, labels and totals, and every rule is per graph, each request's labels equal
 // those of its own call.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
+#include <exception>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "aggregate.hpp"
@@ -45,11 +50,12 @@ struct PackDesc {
   int64_t n, nnz, vbase, ebase;
 };
 
-// A graph's outcome of one sweep.
+// A graph's outcome of one step: movers of its last sweep, sweeps made, whether its
+// level ended.
 struct StepResult {
   unsigned long long moved;
-  uint32_t stop;
-  uint32_t pad;
+  uint32_t sweeps;
+  uint32_t ended;
 };
 
 // Graph y0 + blockIdx.y into the union: its rows (offsets, ids shifted by its bases),
@@ -89,32 +95,65 @@ __global__ void k_step_unpack(const PackDesc *d, const int32_t *gid, const int32
   if (Sig) g.Sig[v] = Sig[u];
 }
 
-// After a sweep, per graph: its counters (read and cleared), its stopping rule --
-// LPA: movers <= tol * n_g; Louvain: no positive move, or 2 * (summed gain) <= tol *
-// W_g^2, the tests of a call's own level -- and the direction of its next sweep
-// (lower ids first, then alternating).
-template <int ALGO>
-__global__ void k_step_converge(unsigned long long *gctr, const unsigned long long *Wg64, const int64_t *nvert,
-                                const double *gtol, int32_t *git, int8_t *gdir, int32_t count,
-                                StepResult *res) {
-  const int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (g >= count) return;
-  unsigned long long *c = gctr + 3 * g;
-  // read and clear in one atomic step (a plain load could be served by the scalar
-  // cache and be overtaken by the store of 0)
-  const unsigned long long moved = atomicExch(&c[0], 0ull), prop = atomicExch(&c[1], 0ull),
-                           sumG = atomicExch(&c[2], 0ull);
-  bool stop;
-  if (ALGO == ALGO_LPA) {
-    stop = (double)moved <= gtol[g] * (double)nvert[g];
-  } else {
-    const double WW = (double)Wg64[g] * (double)Wg64[g];
-    stop = prop == 0 || 2.0 * (double)sumG <= gtol[g] * WW;
+// Start of a step: every graph of the union moves (lv = {graphs moving, sweeps in
+// which some graph moved}), no outcome yet.
+__global__ void k_step_begin(uint32_t *lv, int32_t count, StepResult *res) {
+  for (int64_t g = threadIdx.x; g < count; g += BLOCK) res[g] = StepResult{0ull, 0u, 0u};
+  if (threadIdx.x == 0) {
+    lv[0] = (uint32_t)count;
+    lv[1] = 0;
   }
-  const int32_t it = git[g] + 1;
-  git[g] = it;
-  if (gdir) gdir[g] = it % 2 == 0 ? (int8_t)-1 : (int8_t)1;
-  res[g] = StepResult{moved, stop ? 1u : 0u, 0u};
+}
+
+// After a sweep, per graph (one workgroup, graphs strided over its threads): its
+// counters are read and cleared; a graph still moving counts the sweep and ends its
+// level when its stopping rule fires -- LPA: movers <= tol * n_g; Louvain: no positive
+// move, or 2 * (summed gain) <= tol * W_g^2, the tests of a call's own level -- or at
+// max_it sweeps; its next sweep alternates direction (lower ids first).  A graph whose
+// level ended is frozen for the rest of the step.  lv[0] = graphs still moving (0:
+// every later sweep kernel of the step returns at once), lv[1] counts the sweeps in
+// which some graph moved.
+template <int ALGO>
+__global__ void __launch_bounds__(BLOCK)
+    k_step_converge(unsigned long long *gctr, const unsigned long long *Wg64, const int64_t *nvert,
+                    const double *gtol, int32_t *git, int8_t *gdir, uint8_t *active, int32_t max_it,
+                    int32_t count, StepResult *res, uint32_t *lv) {
+  __shared__ uint32_t red[BLOCK / WAVE];
+  const uint32_t was = lv[0];
+  uint32_t still = 0;
+  for (int64_t g = threadIdx.x; g < count; g += BLOCK) {
+    unsigned long long *c = gctr + 3 * g;
+    // read and clear in one atomic step (a plain load could be served by the scalar
+    // cache and be overtaken by the store of 0)
+    const unsigned long long moved = atomicExch(&c[0], 0ull), prop = atomicExch(&c[1], 0ull),
+                             sumG = atomicExch(&c[2], 0ull);
+    if (!active[g]) continue;
+    bool stop;
+    if (ALGO == ALGO_LPA) {
+      stop = (double)moved <= gtol[g] * (double)nvert[g];
+    } else {
+      const double WW = (double)Wg64[g] * (double)Wg64[g];
+      stop = prop == 0 || 2.0 * (double)sumG <= gtol[g] * WW;
+    }
+    const int32_t it = git[g] + 1;
+    git[g] = it;
+    if (gdir) gdir[g] = it % 2 == 0 ? (int8_t)-1 : (int8_t)1;
+    StepResult r = res[g];
+    r.moved = moved;
+    r.sweeps += 1;
+    if (stop || it >= max_it) {
+      r.ended = 1;
+      active[g] = 0;
+    } else {
+      still += 1;
+    }
+    res[g] = r;
+  }
+  still = block_sum(still, red);
+  if (threadIdx.x == 0) {
+    lv[0] = still;
+    lv[1] += was > 0 ? 1u : 0u;
+  }
 }
 
 size_t up(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -162,14 +201,33 @@ struct StepEngine::Union {
   int8_t *gdir = nullptr;
   unsigned long long *gctr = nullptr, *ctr = nullptr;
   StepResult *res = nullptr;
+  uint32_t *lv = nullptr;
   Schedule sch;
   std::vector<StepResult> hres;
 };
 
-StepEngine::StepEngine(int algo, const mgcd_params &p, char *shared, size_t shared_bytes, hipStream_t st)
-    : algo_(algo), p_(p), shared_(shared), shared_bytes_(shared_bytes), st_(st), u_(new Union) {}
+StepEngine::StepEngine(int algo, const mgcd_params &p, int sweeps_per_step, char *shared, size_t shared_bytes,
+                       hipStream_t st, int phase_lanes)
+    : algo_(algo),
+      p_(p),
+      sweeps_(sweeps_per_step > 0 ? sweeps_per_step : p.max_iterations),
+      shared_(shared),
+      shared_bytes_(shared_bytes),
+      st_(st),
+      u_(new Union) {
+  MGCD_HIP(hipGetDevice(&device_));
+  lanes_.push_back(st_);
+  for (int t = 1; t < phase_lanes; ++t) {
+    hipStream_t x = nullptr;
+    MGCD_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    lanes_.push_back(x);
+  }
+}
 
-StepEngine::~StepEngine() { delete u_; }
+StepEngine::~StepEngine() {
+  for (size_t t = 1; t < lanes_.size(); ++t) (void)hipStreamDestroy(lanes_[t]);
+  delete u_;
+}
 
 // A job's block: degrees, labels and (Louvain / Leiden) the level maps and the two
 // slots of aggregated level graphs, as in a call of its own.
@@ -204,6 +262,19 @@ size_t StepEngine::block_bytes(int algo, const mgcd_params &, int32_t n, int64_t
   return up(a.peak) + 4096;
 }
 
+// The phase work of one job: admission (degrees, validation), Leiden refinement (its
+// schedule and proposal arrays), renumbering, aggregation, final labels.
+size_t StepEngine::phase_bytes(int algo, const mgcd_params &p, int32_t n, int64_t nnz) {
+  const int64_t L = p.chunk_len > 0 ? p.chunk_len : 1;
+  size_t ph = degrees_ws_bytes(nnz);
+  if (algo != MGCD_ALGO_LPA) {
+    ph = std::max(ph, aggregate_ws_bytes(n, nnz, agg_mode(&p), p.k_aggregate, L, algo == MGCD_ALGO_LEIDEN));
+    if (algo == MGCD_ALGO_LEIDEN)
+      ph = std::max(ph, schedule_ws_bytes(n, nnz, sched_mode(&p), p.k, L) + (size_t)n * 12 + 8192);
+  }
+  return ph + (size_t)n * (4 + 4 + 8 + 8) + scan_ws_bytes((int64_t)n + 1) + 64 * 1024 + (1u << 20);
+}
+
 size_t StepEngine::shared_need(int algo, const mgcd_params &p, int64_t count, int64_t N, int64_t E,
                                int32_t max_n, int64_t max_nnz) {
   const int64_t L = p.chunk_len > 0 ? p.chunk_len : 1;
@@ -211,34 +282,47 @@ size_t StepEngine::shared_need(int algo, const mgcd_params &p, int64_t count, in
   size_t un = up((size_t)(N + 1) * 8) + up((size_t)E * 4) * 2 + up((size_t)N * 4) * 5;
   un += TableLayout(count).total + up((size_t)count * 24) + up((size_t)count * sizeof(StepResult)) + 4096;
   un += schedule_ws_bytes((int32_t)std::min<int64_t>(N, INT32_MAX), E, sched_mode(&p), p.k, L);
-  un += 64 * 1024;
-  // the phase work of one job: admission (degrees, validation), Leiden refinement (its
-  // schedule and proposal arrays), renumbering, aggregation, final labels
-  size_t ph = degrees_ws_bytes(max_nnz);
-  if (algo != MGCD_ALGO_LPA) {
-    ph = std::max(ph, aggregate_ws_bytes(max_n, max_nnz, agg_mode(&p), p.k_aggregate, L,
-                                         algo == MGCD_ALGO_LEIDEN));
-    if (algo == MGCD_ALGO_LEIDEN)
-      ph = std::max(ph, schedule_ws_bytes(max_n, max_nnz, sched_mode(&p), p.k, L) + (size_t)max_n * 12 + 8192);
-  }
-  ph += (size_t)max_n * (4 + 4 + 8 + 8) + scan_ws_bytes((int64_t)max_n + 1) + 64 * 1024;
-  return std::max(un, ph) + (1u << 20);
+  un += 64 * 1024 + (1u << 20);
+  return std::max(un, phase_bytes(algo, p, max_n, max_nnz));
 }
 
-Arena StepEngine::phase_arena() {
+// Phase work of many jobs over the phase lanes: each lane has its own stream and an
+// equal slice of the shared region (as many lanes as slices that hold the largest
+// job's phase work), takes the next job until none is left and drains its stream.
+// Runs while the union is dissolved, after the main stream's work.
+template <typename F>
+void StepEngine::in_lanes(const std::vector<StepJob *> &js, F &&f) {
   if (u_->live) throw Error(MGCD_E_ARG, "internal: phase work while the union is packed");
-  Arena a;
-  a.base = shared_;
-  a.cap = shared_bytes_;
-  return a;
+  if (js.empty()) return;
+  MGCD_HIP(hipStreamSynchronize(st_));
+  size_t need = 0;
+  for (StepJob *j : js) need = std::max(need, phase_bytes(algo_, p_, j->g.n, j->g.nnz));  // the input bounds every level
+  int T = (int)std::min<size_t>(lanes_.size(), js.size());
+  while (T > 1 && shared_bytes_ / (size_t)T / 256 * 256 < need) --T;
+  const size_t slice = T > 1 ? shared_bytes_ / (size_t)T / 256 * 256 : shared_bytes_;
+  std::atomic<size_t> next{0};
+  std::vector<std::exception_ptr> err((size_t)T);
+  auto work = [&](int t) {
+    try {
+      MGCD_HIP(hipSetDevice(device_));
+      const Lane l{lanes_[(size_t)t], shared_ + (size_t)t * slice, slice};
+      for (size_t q; (q = next.fetch_add(1)) < js.size();) f(js[q], l);
+      MGCD_HIP(hipStreamSynchronize(l.st));
+    } catch (...) {
+      err[(size_t)t] = std::current_exception();
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto &x : th) x.join();
+  for (auto &e : err)
+    if (e) std::rethrow_exception(e);
 }
 
-void StepEngine::admit(StepJob *j, std::vector<StepJob *> &finished) {
-  dissolve();
-  j->t_admit = host_seconds();
-  j->done = false;
-  j->rc = MGCD_OK;
-  j->stats = mgcd_stats{};
+// Host checks, degrees and W of a job; false when it finished here (an error, or no
+// vertices).
+bool StepEngine::prepare(StepJob *j, const Lane &l) {
   const mgcd_csr &c = j->g;
   try {
     if (c.n < 0 || c.nnz < 0) throw Error(MGCD_E_ARG, "negative graph size");
@@ -249,27 +333,26 @@ void StepEngine::admit(StepJob *j, std::vector<StepJob *> &finished) {
     if (c.n == 0) {  // nothing to move: the call's own result
       j->stats.passes = algo_ == MGCD_ALGO_LPA ? 1 : 0;
       j->done = true;
-      finished.push_back(j);
-      return;
+      return false;
     }
     Arena b;
     b.base = j->block;
     b.cap = block_bytes(algo_, p_, c.n, c.nnz);
     block_layout(algo_, j, b);
     const Graph g{c.n, c.nnz, c.offsets, c.indices, c.weights};
-    Arena a = phase_arena();
+    Arena a = l.arena();
     unsigned long long *scr = a.take<unsigned long long>(2);
     unsigned long long h = 0;
     if (p_.validate) {  // before anything reads the rows
-      launch_zero_u64(scr, 2, st_);
-      launch_validate(g, scr, st_);
-      MGCD_HIP(hipMemcpyAsync(&h, scr, sizeof(h), hipMemcpyDeviceToHost, st_));
-      MGCD_HIP(hipStreamSynchronize(st_));
+      launch_zero_u64(scr, 2, l.st);
+      launch_validate(g, scr, l.st);
+      MGCD_HIP(hipMemcpyAsync(&h, scr, sizeof(h), hipMemcpyDeviceToHost, l.st));
+      MGCD_HIP(hipStreamSynchronize(l.st));
       if (h != 0) throw Error(MGCD_E_GRAPH, "CSR failed validation");
     }
-    launch_degrees(g, j->K[0], scr + 1, a, st_);
-    MGCD_HIP(hipMemcpyAsync(&h, scr + 1, sizeof(h), hipMemcpyDeviceToHost, st_));
-    MGCD_HIP(hipStreamSynchronize(st_));
+    launch_degrees(g, j->K[0], scr + 1, a, l.st);
+    MGCD_HIP(hipMemcpyAsync(&h, scr + 1, sizeof(h), hipMemcpyDeviceToHost, l.st));
+    MGCD_HIP(hipStreamSynchronize(l.st));
     if (h >= (1ull << 31)) throw Error(MGCD_E_OVERFLOW, "total edge weight must be below 2^31");
     j->W = h;
     j->cur = g;
@@ -277,94 +360,118 @@ void StepEngine::admit(StepJob *j, std::vector<StepJob *> &finished) {
     j->next_slot = 0;
     j->pass = 0;
     j->tol = p_.tolerance;
-    if (algo_ != MGCD_ALGO_LPA) launch_iota(j->top, c.n, st_);
+    if (algo_ != MGCD_ALGO_LPA) launch_iota(j->top, c.n, l.st);
   } catch (const Error &e) {
     if (e.code == MGCD_E_HIP) throw;
     j->rc = e.code;
     j->err = e.what();
     j->done = true;
-    finished.push_back(j);
-    return;
+    return false;
   }
-  jobs_.push_back(j);
-  enter_level(j, true, finished);
+  enter_level(j, true, l);
+  return true;
+}
+
+void StepEngine::admit(const std::vector<StepJob *> &js, std::vector<StepJob *> &finished) {
+  if (js.empty()) return;
+  dissolve();
+  const double t0 = host_seconds();
+  for (StepJob *j : js) {
+    j->t_admit = t0;
+    j->done = false;
+    j->rc = MGCD_OK;
+    j->stats = mgcd_stats{};
+    j->cur = Graph{};
+  }
+  try {
+    in_lanes(js, [&](StepJob *j, const Lane &l) { prepare(j, l); });
+  } catch (...) {
+    ctr_.s_phase += host_seconds() - t0;
+    throw;
+  }
+  for (StepJob *j : js) {  // in arrival order
+    if (j->done)
+      finished.push_back(j);
+    else
+      jobs_.push_back(j);
+  }
+  ctr_.s_phase += host_seconds() - t0;
 }
 
 // A level starts: labels (every vertex alone, or Leiden's carried-over start) and their
 // community totals.
-void StepEngine::enter_level(StepJob *j, bool reset, std::vector<StepJob *> &) {
+void StepEngine::enter_level(StepJob *j, bool reset, const Lane &l) {
   const int32_t nl = j->cur.n;
   j->stats.passes += 1;
   j->it = 0;
-  if (reset) launch_iota(j->C, nl, st_);
-  if (algo_ != MGCD_ALGO_LPA) launch_community_totals(j->C, j->K[j->kcur], j->Sig, nl, st_);
+  if (reset) launch_iota(j->C, nl, l.st);
+  if (algo_ != MGCD_ALGO_LPA) launch_community_totals(j->C, j->K[j->kcur], j->Sig, nl, l.st);
 }
 
-void StepEngine::finish(StepJob *j, const int32_t *labels, std::vector<StepJob *> &finished) {
-  Arena a = phase_arena();
-  j->stats.communities = canonical(labels, j->g.n, j->out, a, st_);
+void StepEngine::finish(StepJob *j, const int32_t *labels, const Lane &l) {
+  Arena a = l.arena();
+  j->stats.communities = canonical(labels, j->g.n, j->out, a, l.st);
   j->stats.ms_total = (float)((host_seconds() - j->t_admit) * 1e3);
   j->done = true;
-  jobs_.erase(std::find(jobs_.begin(), jobs_.end(), j));
-  finished.push_back(j);
 }
 
 // The phase transition after a level's sweeps, as a call makes it: LPA ends; Louvain
 // renumbers, stops or aggregates (Section 3.3); Leiden first refines within the moving
 // communities (Section 4.2) and aggregates by the refined ones, each super-vertex
-// starting in its moving community.
-void StepEngine::end_level(StepJob *j, std::vector<StepJob *> &finished) {
+// starting in its moving community.  Sets done when the job finished.
+void StepEngine::end_level(StepJob *j, const Lane &l) {
   if (algo_ == MGCD_ALGO_LPA) {
-    finish(j, j->C, finished);
+    finish(j, j->C, l);
     return;
   }
   const bool leiden = algo_ == MGCD_ALGO_LEIDEN;
   const int32_t n = j->g.n;
   const int32_t nl = j->cur.n;
   uint32_t *K = j->K[j->kcur];
-  Arena a = phase_arena();
+  hipStream_t st = l.st;
+  Arena a = l.arena();
   int32_t m;
   if (leiden) {
     size_t mk = a.mark();
     Schedule sch;
-    build_schedule(j->cur, sched_params(&p_), sch, a, st_);
+    build_schedule(j->cur, sched_params(&p_), sch, a, st);
     int32_t *prop = a.take<int32_t>(nl), *nprop = a.take<int32_t>(nl), *from = a.take<int32_t>(nl);
     unsigned long long *ctr = a.take<unsigned long long>(4);
     SweepArgs r{j->cur, nullptr, j->C, K, K, j->W, 0, prop, nullptr, ctr};
-    launch_iota(prop, nl, st_);  // a row without entries proposes itself
-    launch_zero_u64(ctr, 4, st_);
-    launch_sweep(r, sch, ALGO_REFINE, p_.mode, p_.k, p_.chunk_len, st_);
-    launch_refine_accept(prop, nprop, from, j->R, nl, st_);
+    launch_iota(prop, nl, st);  // a row without entries proposes itself
+    launch_zero_u64(ctr, 4, st);
+    launch_sweep(r, sch, ALGO_REFINE, p_.mode, p_.k, p_.chunk_len, st);
+    launch_refine_accept(prop, nprop, from, j->R, nl, st);
     a.release(mk);
-    m = renumber(j->R, nl, j->D, a, st_);
+    m = renumber(j->R, nl, j->D, a, st);
     const bool last = j->pass == p_.max_passes - 1 || (double)m > p_.aggregation_tolerance * (double)nl;
     if (last) {
-      launch_compose(j->top, j->C, j->top, n, st_);
-      finish(j, j->top, finished);
+      launch_compose(j->top, j->C, j->top, n, st);
+      finish(j, j->top, l);
       return;
     }
-    renumber(j->C, nl, j->Dc, a, st_);
-    launch_compose(j->top, j->D, j->top, n, st_);
+    renumber(j->C, nl, j->Dc, a, st);
+    launch_compose(j->top, j->D, j->top, n, st);
   } else {
-    m = renumber(j->C, nl, j->D, a, st_);
-    launch_compose(j->top, j->D, j->top, n, st_);
+    m = renumber(j->C, nl, j->D, a, st);
+    launch_compose(j->top, j->D, j->top, n, st);
     const bool last = j->pass == p_.max_passes - 1 || (double)m > p_.aggregation_tolerance * (double)nl;
     if (last) {
-      finish(j, j->top, finished);
+      finish(j, j->top, l);
       return;
     }
   }
   const int q = j->next_slot;
   const int64_t nnz2 = aggregate(j->cur, j->D, m, agg_mode(&p_), p_.k_aggregate, p_.chunk_len, leiden ? 1 : 0,
-                                 j->soff[q], j->sidx[q], j->sw[q], a, st_);
-  launch_group_sums(j->D, K, j->K[1 - j->kcur], nl, m, st_);
-  if (leiden) launch_scatter_labels(j->D, j->Dc, j->C, nl, st_);  // super-vertex starts in its community
+                                 j->soff[q], j->sidx[q], j->sw[q], a, st);
+  launch_group_sums(j->D, K, j->K[1 - j->kcur], nl, m, st);
+  if (leiden) launch_scatter_labels(j->D, j->Dc, j->C, nl, st);  // super-vertex starts in its community
   j->cur = Graph{m, nnz2, j->soff[q], j->sidx[q], j->sw[q]};
   j->next_slot = 1 - q;
   j->kcur = 1 - j->kcur;
   j->tol /= p_.tolerance_drop;
   j->pass += 1;
-  enter_level(j, !leiden, finished);
+  enter_level(j, !leiden, l);
 }
 
 void StepEngine::dissolve() {
@@ -379,6 +486,8 @@ void StepEngine::dissolve() {
 
 void StepEngine::repack() {
   Union &u = *u_;
+  const double t0 = host_seconds();
+  ctr_.packs += 1;
   const int32_t count = (int32_t)jobs_.size();
   std::vector<PackDesc> hd(count);
   int64_t N = 0, E = 0, maxi = 1;
@@ -390,7 +499,9 @@ void StepEngine::repack() {
     maxi = std::max<int64_t>(maxi, std::max<int64_t>(j->cur.n, j->cur.nnz));
   }
   if (N >= (1ll << 31)) throw Error(MGCD_E_WORKSPACE, "resident vertices must stay below 2^31");
-  u.a = phase_arena();
+  u.a = Arena{};
+  u.a.base = shared_;
+  u.a.cap = shared_bytes_;
   Arena &a = u.a;
   const bool lpa = algo_ == MGCD_ALGO_LPA;
   u.count = count;
@@ -434,6 +545,7 @@ void StepEngine::repack() {
   u.gctr = a.take<unsigned long long>(3 * (int64_t)count);
   u.ctr = a.take<unsigned long long>(4);
   u.res = a.take<StepResult>(count);
+  u.lv = a.take<uint32_t>(2);
   MGCD_HIP(hipMemcpyAsync(u.table, ht.data(), tl.total, hipMemcpyHostToDevice, st_));
   launch_zero_u64(u.gctr, 3 * (int64_t)count, st_);
   launch_zero_u64(u.ctr, 4, st_);
@@ -450,44 +562,79 @@ void StepEngine::repack() {
   build_schedule(u.g, sched_params(&p_), u.sch, a, st_);
   u.hres.resize(count);
   u.live = true;
+  MGCD_HIP(hipStreamSynchronize(st_));
+  ctr_.s_pack += host_seconds() - t0;
 }
 
 void StepEngine::step(std::vector<StepJob *> &finished) {
   if (jobs_.empty()) return;
   Union &u = *u_;
   if (!u.live) repack();
+  const double t0 = host_seconds();
+  ctr_.steps += 1;
+  ctr_.sweeps += sweeps_;
   const bool lpa = algo_ == MGCD_ALGO_LPA;
-  SweepArgs args{u.g, u.C[0], nullptr, u.K, u.Sig, 0, 0, u.C[1], nullptr, u.ctr};
-  args.gid = u.gid;
-  args.Wg = u.Wg;
-  args.active = u.active;
-  args.gctr = u.gctr;
-  args.gdir = lpa ? nullptr : u.gdir;
-  args.one_scan = lpa ? p_.one_scan : 0;
-  launch_sweep(args, u.sch, lpa ? ALGO_LPA : ALGO_MOVE, p_.mode, p_.k, p_.chunk_len, st_);
-  if (!lpa) launch_apply_moves(u.C[0], u.C[1], u.K, u.Sig, u.g.n, st_);
-  if (lpa)
-    k_step_converge<ALGO_LPA><<<grid_of(u.count), BLOCK, 0, st_>>>(u.gctr, u.Wg64, u.nvert, u.gtol, u.git,
-                                                                   nullptr, u.count, u.res);
-  else
-    k_step_converge<ALGO_MOVE><<<grid_of(u.count), BLOCK, 0, st_>>>(u.gctr, u.Wg64, u.nvert, u.gtol, u.git,
-                                                                    u.gdir, u.count, u.res);
+  k_step_begin<<<1, BLOCK, 0, st_>>>(u.lv, u.count, u.res);
   MGCD_LAUNCHED();
+  // up to sweeps_ sweeps; once no graph moves, the remaining kernels return at once
+  int32_t *C[2] = {u.C[0], u.C[1]};
+  for (int s = 0; s < sweeps_; ++s) {
+    SweepArgs args{u.g, C[0], nullptr, u.K, u.Sig, 0, 0, C[1], nullptr, u.ctr};
+    args.gid = u.gid;
+    args.Wg = u.Wg;
+    args.active = u.active;
+    args.gctr = u.gctr;
+    args.live = u.lv;
+    args.gdir = lpa ? nullptr : u.gdir;
+    args.one_scan = lpa ? p_.one_scan : 0;
+    launch_sweep(args, u.sch, lpa ? ALGO_LPA : ALGO_MOVE, p_.mode, p_.k, p_.chunk_len, st_);
+    if (!lpa) {
+      LevelRule r;
+      r.live = u.lv;
+      launch_apply_moves(C[0], C[1], u.K, u.Sig, u.g.n, st_, &r);
+    }
+    if (lpa)
+      k_step_converge<ALGO_LPA><<<1, BLOCK, 0, st_>>>(u.gctr, u.Wg64, u.nvert, u.gtol, u.git, nullptr, u.active,
+                                                      p_.max_iterations, u.count, u.res, u.lv);
+    else
+      k_step_converge<ALGO_MOVE><<<1, BLOCK, 0, st_>>>(u.gctr, u.Wg64, u.nvert, u.gtol, u.git, u.gdir, u.active,
+                                                       p_.max_iterations, u.count, u.res, u.lv);
+    MGCD_LAUNCHED();
+    std::swap(C[0], C[1]);
+  }
+  uint32_t lv[2] = {0, 0};
   MGCD_HIP(hipMemcpyAsync(u.hres.data(), u.res, (size_t)u.count * sizeof(StepResult), hipMemcpyDeviceToHost, st_));
+  MGCD_HIP(hipMemcpyAsync(lv, u.lv, sizeof(lv), hipMemcpyDeviceToHost, st_));
   MGCD_HIP(hipStreamSynchronize(st_));
-  std::swap(u.C[0], u.C[1]);
+  // the labels are in the buffer the last sweep in which some graph moved wrote
+  if (lv[1] % 2 == 1) std::swap(u.C[0], u.C[1]);
+  ctr_.sweeps_moving += lv[1];
+  ctr_.rows_swept += (int64_t)lv[1] * u.g.n;
+  ctr_.s_sweep += host_seconds() - t0;
+  const double t1 = host_seconds();
   std::vector<StepJob *> ended;
   for (int32_t g = 0; g < u.count; ++g) {
     StepJob *j = jobs_[g];
-    j->it += 1;
-    j->stats.iterations += 1;
-    j->stats.edges_scanned += j->cur.nnz;
-    j->stats.moved_last = (int64_t)u.hres[g].moved;
-    if (u.hres[g].stop || j->it >= p_.max_iterations) ended.push_back(j);
+    const StepResult &r = u.hres[g];
+    ctr_.rows_moving += (int64_t)r.sweeps * j->cur.n;
+    if (r.sweeps == 0) continue;
+    j->it += (int)r.sweeps;
+    j->stats.iterations += (int32_t)r.sweeps;
+    j->stats.edges_scanned += (int64_t)r.sweeps * j->cur.nnz;
+    j->stats.moved_last = (int64_t)r.moved;
+    if (r.ended) ended.push_back(j);
   }
-  if (ended.empty()) return;
-  dissolve();
-  for (StepJob *j : ended) end_level(j, finished);
+  if (!ended.empty()) {
+    ctr_.transitions += (int64_t)ended.size();
+    dissolve();
+    in_lanes(ended, [&](StepJob *j, const Lane &l) { end_level(j, l); });
+    for (StepJob *j : ended)
+      if (j->done) {
+        jobs_.erase(std::find(jobs_.begin(), jobs_.end(), j));
+        finished.push_back(j);
+      }
+  }
+  ctr_.s_phase += host_seconds() - t1;
 }
 
 void StepEngine::fail_all(int code, const std::string &msg, std::vector<StepJob *> &finished) {

@@ -48,9 +48,13 @@ struct StepJob {
 
 class StepEngine {
  public:
-  // algo: MGCD_ALGO_*; p: checked (checked_params); the shared region holds the union
-  // during steps and the phase work between them.
-  StepEngine(int algo, const mgcd_params &p, char *shared, size_t shared_bytes, hipStream_t st);
+  // algo: MGCD_ALGO_*; p: checked (checked_params); a step makes up to
+  // sweeps_per_step sweeps (<= 0: max_iterations, every level to its end); the shared
+  // region holds the union during steps and the phase work between them; phase work
+  // runs on up to phase_lanes streams at once (st and streams of the engine's own), on
+  // the device current at construction.
+  StepEngine(int algo, const mgcd_params &p, int sweeps_per_step, char *shared, size_t shared_bytes,
+             hipStream_t st, int phase_lanes);
   ~StepEngine();
   StepEngine(const StepEngine &) = delete;
   StepEngine &operator=(const StepEngine &) = delete;
@@ -60,32 +64,52 @@ class StepEngine {
   static size_t block_bytes(int algo, const mgcd_params &p, int32_t n, int64_t nnz);
   static size_t shared_need(int algo, const mgcd_params &p, int64_t count, int64_t N, int64_t E,
                             int32_t max_n, int64_t max_nnz);
+  static size_t phase_bytes(int algo, const mgcd_params &p, int32_t n, int64_t nnz);
 
-  // Takes a job in (it joins the union at the next step).  A job that fails its checks
+  // Takes jobs in (they join the union at the next step).  A job that fails its checks
   // or has nothing to move finishes at once and is appended to `finished`.
-  void admit(StepJob *j, std::vector<StepJob *> &finished);
-  // One step: a sweep over every resident job, then the phase transitions of the jobs
+  void admit(const std::vector<StepJob *> &js, std::vector<StepJob *> &finished);
+  // One step: up to sweeps_per_step sweeps over every resident job (a job whose level
+  // ends stays frozen for the rest of the step), then the phase transitions of the jobs
   // whose level ended; jobs that finished are appended to `finished`.
   void step(std::vector<StepJob *> &finished);
   // After an error the engine cannot recover from: every resident job fails.
   void fail_all(int code, const std::string &msg, std::vector<StepJob *> &finished);
   size_t resident() const { return jobs_.size(); }
+  const mgcd_step_stats &counters() const { return ctr_; }
 
  private:
   struct Union;
+  struct Lane {  // a stream and its slice of the shared region for phase work
+    hipStream_t st;
+    char *base;
+    size_t cap;
+    Arena arena() const {
+      Arena a;
+      a.base = base;
+      a.cap = cap;
+      return a;
+    }
+  };
   void dissolve();
   void repack();
-  void enter_level(StepJob *j, bool reset, std::vector<StepJob *> &finished);
-  void end_level(StepJob *j, std::vector<StepJob *> &finished);
-  void finish(StepJob *j, const int32_t *labels, std::vector<StepJob *> &finished);
-  Arena phase_arena();
+  template <typename F>
+  void in_lanes(const std::vector<StepJob *> &js, F &&f);
+  bool prepare(StepJob *j, const Lane &l);
+  void enter_level(StepJob *j, bool reset, const Lane &l);
+  void end_level(StepJob *j, const Lane &l);
+  void finish(StepJob *j, const int32_t *labels, const Lane &l);
 
   int algo_;
   mgcd_params p_;
+  int sweeps_;
   char *shared_;
   size_t shared_bytes_;
   hipStream_t st_;
+  int device_ = 0;
+  std::vector<hipStream_t> lanes_;  // lanes_[0] = st_
   std::vector<StepJob *> jobs_;  // resident, in admission order
+  mgcd_step_stats ctr_{};
   Union *u_;
 };
 

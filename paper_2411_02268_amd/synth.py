@@ -358,6 +358,47 @@ def planted_batch(count: int = 4096, nmin: float = 1e3, nmax: float = 2e5, cmin:
 # serving stream
 # ----------------------------------------------------------------------------------
 
+def rmat_torch(scale: int, edge_factor: int = 8, seed: int = 2, wmax: int = 8, a: float = 0.57,
+               b: float = 0.19, c: float = 0.19, device: str = "cuda"):
+    """R-MAT built entirely with torch on `device` (for streams of many distinct
+    graphs): the recipe of rmat() -- edge_factor * 2**scale samples, quadrant
+    probabilities a, b, c, d, a seeded relabel, self-loops dropped, duplicates
+    collapsed, weights uniform in [1, wmax] per pair -- drawn from torch's seeded
+    generator (a different random stream from rmat's).  Returns device tensors
+    (offsets int64[n+1], indices int32[nnz], weights int32[nnz] holding uint32 bits),
+    rows sorted by column."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    n = 1 << scale
+    m = edge_factor * n
+    u = torch.zeros(m, dtype=torch.int64, device=device)
+    v = torch.zeros(m, dtype=torch.int64, device=device)
+    ab, abc = a + b, a + b + c
+    for bit in range(scale):
+        r = torch.rand(m, generator=gen, device=device)
+        u |= (r >= ab).to(torch.int64) << bit
+        v |= (((r >= a) & (r < ab)) | (r >= abc)).to(torch.int64) << bit
+        del r
+    perm = torch.randperm(n, generator=gen, device=device)
+    u, v = perm[u], perm[v]
+    keep = u != v
+    lo, hi = torch.minimum(u, v)[keep], torch.maximum(u, v)[keep]
+    del u, v, keep, perm
+    key = torch.unique(lo * n + hi)
+    del lo, hi
+    w = torch.randint(1, wmax + 1, (key.numel(),), generator=gen, device=device, dtype=torch.int64)
+    both = torch.cat([key, (key % n) * n + key // n])
+    wt = torch.cat([w, w])
+    del key, w
+    both, order = torch.sort(both)
+    wt = wt[order].to(torch.int32)
+    off = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    off[1:] = torch.cumsum(torch.bincount(both // n, minlength=n), 0)
+    idx = (both % n).to(torch.int32)
+    return off, idx, wt
+
+
 def serving_stream(count: int = 2000, smin: int = 14, smax: int = 21, deg: int = 16,
                    rate_hz: float = 100.0, seed: int = 5):
     """Poisson arrivals (exponential gaps at ``rate_hz``) of R-MAT requests with

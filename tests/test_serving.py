@@ -97,6 +97,17 @@ def test_stepped_all_resident(mg, pool, algo_name, kw):
         _check_same(mg, algo, pool, srv, order, kw, stepped=True)
 
 
+@pytest.mark.parametrize("sweeps", [1, 2, 5])
+@pytest.mark.parametrize("algo_name", ALGOS)
+def test_stepped_sweeps_per_step(mg, pool, algo_name, sweeps):
+    """Steps of one, two or five sweeps: levels end inside or across steps, graphs
+    freeze within a step and resume in the next, joining and ending at any point."""
+    algo = _algo(mg, algo_name)
+    order = [4, 0, 5, 3, 1, 7, 2, 6, 4, 4, 0]
+    with mg.Server(algo, 1 << 30, slots=5, stepped=True, sweeps_per_step=sweeps) as srv:
+        _check_same(mg, algo, pool, srv, order, {}, stepped=True)
+
+
 def test_stepped_lpa_one_scan(mg, pool):
     kw = dict(one_scan=1, k=2)
     with mg.Server(mg.ALGO_LPA, 1 << 30, slots=8, stepped=True, **kw) as srv:

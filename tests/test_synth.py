@@ -19,3 +19,25 @@ def test_torch_sorted_build_equals_numpy(make):
     for i in range(0, a.n, 97):
         row = a.indices[a.offsets[i]:a.offsets[i + 1]]
         assert np.all(np.diff(row) > 0) and not np.any(row == i)
+
+
+def test_rmat_torch_is_a_valid_undirected_csr():
+    """The torch-drawn R-MAT of the serving stream: symmetric entries with equal
+    weights, rows sorted without duplicates or self-loops, weights in [1, 8], and the
+    same graph for the same seed (different for another)."""
+    import torch
+    off, idx, w = synth.rmat_torch(11, 8, seed=7, device="cpu")
+    o, ii, ww = off.numpy(), idx.numpy(), w.numpy().view(np.uint32)
+    n = o.shape[0] - 1
+    assert n == 2048 and o[0] == 0 and o[-1] == ii.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(o))
+    assert not np.any(rows == ii)
+    for i in range(n):
+        assert np.all(np.diff(ii[o[i]:o[i + 1]]) > 0)
+    assert ww.min() >= 1 and ww.max() <= 8
+    fwd = set(zip(rows.tolist(), ii.tolist(), ww.tolist()))
+    assert fwd == set(zip(ii.tolist(), rows.tolist(), ww.tolist()))
+    off2, idx2, w2 = synth.rmat_torch(11, 8, seed=7, device="cpu")
+    assert torch.equal(off, off2) and torch.equal(idx, idx2) and torch.equal(w, w2)
+    _, idx3, _ = synth.rmat_torch(11, 8, seed=8, device="cpu")
+    assert idx3.shape != idx.shape or not torch.equal(idx3, idx)

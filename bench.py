@@ -38,11 +38,11 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 # and profiles/k_move_rows_cl24_leiden_counters.md.  Valid only for the kernel sources
 # they were taken on: SOURCES_SHA256 is checked at run time, and traffic is reported as
 # null when the sources differ.
-TRAFFIC_BYTES = {("louvain-mg-k8-rmat20", False): 2406600565,
-                 ("leiden-mg-k16-cl24", False): 106665441721,
-                 ("leiden-mg-k16-cl24", True): 80185015294}
+TRAFFIC_BYTES = {("louvain-mg-k8-rmat20", False): 2380722024,
+                 ("leiden-mg-k16-cl24", False): 106706025376,
+                 ("leiden-mg-k16-cl24", True): 80207006440}
 TRAFFIC_SOURCES = ["csrc/move.hip", "csrc/move.hpp", "csrc/sketch.hpp", "csrc/common.hpp", "csrc/staging.hpp"]
-TRAFFIC_SOURCES_SHA256 = "d2c8510b53b4aeb0947d3e8e235fe1cc9e2ad5d67bc494276227cd87f031c8b8"
+TRAFFIC_SOURCES_SHA256 = "cc52825819b5cf5515cca2cdf18ce3e9dec6b31a7d82fb397b87a63e05b477cf"
 
 
 def sources_sha256() -> str:

@@ -38,9 +38,9 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 # and profiles/k_move_rows_cl24_leiden_counters.md.  Valid only for the kernel sources
 # they were taken on: SOURCES_SHA256 is checked at run time, and traffic is reported as
 # null when the sources differ.
-TRAFFIC_BYTES = {("louvain-mg-k8-rmat20", False): 2380722024,
-                 ("leiden-mg-k16-cl24", False): 106706025376,
-                 ("leiden-mg-k16-cl24", True): 80207006440}
+TRAFFIC_BYTES = {("louvain-mg-k8-rmat20", False, 0): 2380722024,
+                 ("leiden-mg-k16-cl24", False, 0): 106706025376,
+                 ("leiden-mg-k16-cl24", True, 0): 80207006440}
 TRAFFIC_SOURCES = ["csrc/move.hip", "csrc/move.hpp", "csrc/sketch.hpp", "csrc/common.hpp", "csrc/staging.hpp"]
 TRAFFIC_SOURCES_SHA256 = "cc52825819b5cf5515cca2cdf18ce3e9dec6b31a7d82fb397b87a63e05b477cf"
 
@@ -54,7 +54,7 @@ def sources_sha256() -> str:
     return h.hexdigest()
 
 
-def class_bytes(g, L: int, k: int, cands: float = 0.0):
+def class_bytes(g, L: int, k: int, cands: float = 0.0, short: int = 0):
     """Algorithmic bytes of one level-0 MG sweep per kernel class (reads and writes
     the method must make; a second pass over a row of at most 64 chunks counts as
     on-chip, a second pass over a longer row re-reads its keys and weights):
@@ -66,14 +66,18 @@ def class_bytes(g, L: int, k: int, cands: float = 0.0):
       written by class 0 and read by class 1; class 1 re-reads their entries'
       keys and weights (8 B) and writes and reads 4 (k + 1) B of counts per chunk.
     Class 0: the main sweep kernel (k_move_rows).  Class 1: long-row merge, second
-    pass and decision (k_long_merge, k_long_count, k_long_decide).  Class 2: 0."""
+    pass and decision (k_long_merge, k_long_count, k_long_decide).  Class 2: rows of
+    1..short entries on the exact one-lane kernel (12 B per entry, 28 B per vertex;
+    their candidates' totals are not counted)."""
     deg = np.diff(g.offsets)
     nch = (deg + L - 1) // L
     big = nch > 64
+    sh = (deg >= 1) & (deg <= short)
     groups = int(((nch[big] + 63) // 64).sum())
-    c0 = 12 * int(deg.sum()) + 28 * g.n + (8 * k + 4) * groups + int(round(4 * cands))
+    c0 = 12 * int(deg[~sh].sum()) + 28 * int((~sh).sum()) + (8 * k + 4) * groups + int(round(4 * cands))
     c1 = (8 * k + 4) * groups + 8 * int(deg[big].sum()) + 2 * 4 * (k + 1) * int(nch[big].sum())
-    return [c0, c1, 0]
+    c2 = 12 * int(deg[sh].sum()) + 28 * int(sh.sum())
+    return [c0, c1, c2]
 
 
 def serving_leg(mg, torch, requests: int, slots: int, resident: int, sweeps: int, budget_gb: float,
@@ -292,6 +296,14 @@ WORKLOADS = {
     "louvain-mg-k64-rmat20": (
         "louvain", 64, "R-MAT scale 20, edge factor 16, a/b/c=0.57/0.19/0.19, weights U[1,8], seed 2",
         lambda synth: (synth.rmat(scale=20, edge_factor=16, seed=2, device="cuda"), None)),
+    "louvain-mg-k8-road": (
+        "louvain", 8, "road-network stand-in: 1,620^2 grid intersections, segments kept with p 0.6, "
+        "0..6 points per segment, unit weights, seed 4 (about 12 M vertices, 2.09 entries per vertex)",
+        lambda synth: (synth.road_like(side=1620, seed=4, device="cuda"), None)),
+    "louvain-mg-k8-kmer": (
+        "louvain", 8, "k-mer stand-in: 2^24 vertices in chains of mean length 16, ends joined "
+        "with p 0.9, unit weights, seed 5 (about 2.1 entries per vertex)",
+        lambda synth: (synth.kmer_like(n=1 << 24, seed=5, device="cuda"), None)),
     "lpa-mg-k8-planted": (
         "lpa", 8, "planted partition 20 x 500, 12 intra + 4 inter edges per vertex, weight 1, seed 1",
         lambda synth: synth.planted_exact(n_comm=20, comm_size=500, seed=1)),
@@ -328,6 +340,10 @@ def main():
     ap.add_argument("--batch-nmax", type=float, default=2e5)
     ap.add_argument("--storage-order", type=int, default=0, choices=(0, 1, 2),
                     help="level-0 storage copy in degree order: 0 by size (default), 1 off, 2 on "
+                         "(schedule only: results are the same)")
+    ap.add_argument("--short-rows", type=int, default=0, choices=(0, 1, 2),
+                    help="MG rows of at most k entries on the exact one-lane kernel: 0 (default) "
+                         "when the average row has at most k entries, 1 never, 2 always "
                          "(schedule only: results are the same)")
     ap.add_argument("--no-quality-split", dest="quality_split", action="store_false",
                     help="skip the modularity of L = 4096 and of aggregation decoupled "
@@ -367,12 +383,12 @@ def main():
     def run(mode, steps, warm):
         so = args.storage_order
         for _ in range(warm):
-            fn(dg, mode=mode, k=k, chunk_len=L, storage_order=so)
+            fn(dg, mode=mode, k=k, chunk_len=L, storage_order=so, short_rows=args.short_rows)
         torch.cuda.synchronize()
         stats = []
         a = time.perf_counter()
         for _ in range(steps):
-            lab, st = fn(dg, mode=mode, k=k, chunk_len=L, storage_order=so)
+            lab, st = fn(dg, mode=mode, k=k, chunk_len=L, storage_order=so, short_rows=args.short_rows)
             stats.append(st)
         torch.cuda.synchronize()
         b = time.perf_counter()
@@ -392,12 +408,14 @@ def main():
         ms += np.array(s["ms_l0_kernel"])
         sweeps += s["l0_sweeps"]
     cands = sum(s["l0_candidates"] for s in stats) / max(sweeps, 1)
-    cb = class_bytes(g, L, k, cands)
+    # MG Algorithm 1 here: rows of at most k entries on the exact kernel (level 0)
+    short = k if (k <= 16 and (args.short_rows == 2 or (args.short_rows == 0 and g.nnz <= k * g.n))) else 0
+    cb = class_bytes(g, L, k, cands, short)
     dom = int(np.argmax(ms))
-    names = ["k_move_rows (every row: staged sketch, merge tree, second pass, decision; "
-             "chunk sketches of rows longer than 64 chunks)",
+    names = ["k_move_rows (every row of more than k entries: staged sketch, merge tree, second "
+             "pass, decision; chunk sketches of rows longer than 64 chunks)",
              "k_long_merge + k_long_count + k_long_decide (rows longer than 64 chunks)",
-             "unused"]
+             "k_exact_small (rows of at most k entries: their sketch is their exact table)"]
     per_launch_ms = ms[dom] / max(sweeps, 1)
     achieved = cb[dom] / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     sweep_ms = ms.sum() / max(sweeps, 1)
@@ -499,7 +517,7 @@ def main():
     traffic = None
     used_copy = args.storage_order == 2 or (args.storage_order == 0 and g.nnz >= (1 << 26))
     if dom == 0 and sources_sha256() == TRAFFIC_SOURCES_SHA256:
-        traffic = TRAFFIC_BYTES.get((args.workload, used_copy))
+        traffic = TRAFFIC_BYTES.get((args.workload, used_copy, args.short_rows))
     st_last = stats[-1]
     out = {
         "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
@@ -507,7 +525,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": args.workload, "graph": graph_desc, "n": g.n, "nnz": g.nnz,
                    "k": k, "chunk_len": L, "algorithm": algo_name, "parallelism": "single-gpu",
-                   "storage_order": args.storage_order,
+                   "storage_order": args.storage_order, "short_rows": args.short_rows,
                    "level0_storage_copy": args.storage_order == 2 or
                                           (args.storage_order == 0 and g.nnz >= (1 << 26))},
         "modularity": {"mg": q_mg, "exact": q_x, "ratio": q_mg / q_x if q_x else None,

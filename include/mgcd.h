@@ -123,6 +123,12 @@ typedef struct {
                              community id unchanged; the neighbours' labels that
                              sweeps gather share cache lines): 0 (default) when the
                              input has at least 2^26 entries, 1 never, 2 always      */
+  int32_t short_rows;     /* MGCD_MODE_ALG1 / _STD with k <= 16: a row of at most k
+                             entries holds at most k distinct keys, so its sketch never
+                             loses weight and equals its exact table.  Such rows are
+                             decided on the exact one-lane kernel: 0 (default) when the
+                             level's average row has at most k entries, 1 never (the
+                             sketch kernels take them), 2 always                     */
 } mgcd_params;
 
 typedef struct {
@@ -137,10 +143,12 @@ typedef struct {
   float ms_aggregate;     /* device time in renumbering and aggregation               */
   float ms_total;         /* device time of the whole call                            */
   /* Level-0 local-moving sweeps, device time per kernel class (HIP events on the
-     call's stream).  MG: [0] the main sweep kernel (every row, plus the chunk
+     call's stream).  MG: [0] the main sweep kernel (every row the sketch takes:
+     all rows but those that short_rows sends to the exact kernel, plus the chunk
      sketches of rows longer than 64 chunks), [1] the merge, second pass and
-     decision of those long rows, [2] unused.  Exact: [0] rows of at most 32
-     entries, [1] LDS hash tables, [2] global hash tables. */
+     decision of those long rows, [2] rows of at most k entries on the exact
+     one-lane kernel (short_rows).  Exact: [0] rows of at most 32 entries, [1] LDS hash tables,
+     [2] global hash tables. */
   int32_t l0_sweeps;
   int32_t reserved2;
   float ms_l0_kernel[3];

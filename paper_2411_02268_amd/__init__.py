@@ -41,7 +41,7 @@ class Params(ct.Structure):
                 ("exact_small", ct.c_int32), ("exact_lds", ct.c_int32),
                 ("exact_lds_big", ct.c_int32), ("direct_launch", ct.c_int32),
                 ("one_scan", ct.c_int32), ("aggregation", ct.c_int32),
-                ("storage_order", ct.c_int32)]
+                ("storage_order", ct.c_int32), ("short_rows", ct.c_int32)]
 
 
 class Stats(ct.Structure):

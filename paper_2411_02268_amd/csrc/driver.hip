@@ -70,6 +70,7 @@ static void check_params(const mgcd_params *p) {
   }
   if (p->aggregation < 0 || p->aggregation > 2) throw Error(MGCD_E_ARG, "aggregation must be 0, 1 or 2");
   if (p->storage_order < 0 || p->storage_order > 2) throw Error(MGCD_E_ARG, "storage_order must be 0, 1 or 2");
+  if (p->short_rows < 0 || p->short_rows > 2) throw Error(MGCD_E_ARG, "short_rows must be 0, 1 or 2");
   if (agg_mode(p) != MGCD_MODE_EXACT && !okk(p->k_aggregate))
     throw Error(MGCD_E_UNSUPPORTED, "k_aggregate must be 1, 2, 4, 8, 16, 32, 64, 128 or 256");
   if (p->chunk_len < 1) throw Error(MGCD_E_ARG, "chunk_len must be >= 1");

@@ -1543,8 +1543,9 @@ __global__ void k_gtab_clear(Pair *htab, uint32_t *hpos, int64_t n) {
 //   every mode: rows without entries (category 8) are sorted last and listed in no
 //          kernel's work: their label can never change, so no sweep writes it, and
 //          callers keep both label buffers equal for them.
-constexpr int NCAT = 9;
+constexpr int NCAT = 10;
 constexpr int CAT_EMPTY = 8;
+constexpr int CAT_SHORT = 9;  // MG: rows whose sketch cannot lose weight (exact one-lane kernel)
 
 __global__ void __launch_bounds__(BLOCK)
     k_schedule_keys(const int64_t *off, int32_t n, SchedParams sp, uint64_t *key, uint32_t *val,
@@ -1573,6 +1574,9 @@ __global__ void __launch_bounds__(BLOCK)
       // (K = 128 / 256: every other row is a split row, one wave per chunk)
       cat = deg <= sp.exact_t0 ? 0 : (sp.k > WAVE || (deg > L && deg > WAVE_SPLIT)) ? 2 : 1;
       k = (uint64_t)(cat * 64 + 64 - b);  // heavy rows first in each tier
+    } else if (deg <= sp.mg_short) {  // after the single-chunk rows, heavy rows first
+      cat = CAT_SHORT;
+      k = (uint64_t)(128 + 64 - b);
     } else if (deg <= L) {
       cat = 0;
       k = (uint64_t)(64 - b);  // heavy rows first
@@ -1692,7 +1696,9 @@ size_t schedule_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L) {
   return b + 64 * 1024;
 }
 
-void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a, hipStream_t st) {
+void build_schedule(const Graph &g, const SchedParams &sp_in, Schedule &s, Arena &a, hipStream_t st) {
+  SchedParams sp = sp_in;
+  if (sp.short_auto && g.nnz > sp.mg_short * (int64_t)g.n) sp.mg_short = 0;
   const int mode = sp.mode, k = sp.k;
   const int64_t L = sp.L;
   const int32_t n = g.n;
@@ -1788,6 +1794,9 @@ void build_schedule(const Graph &g, const SchedParams &sp, Schedule &s, Arena &a
   s.single = order;
   s.nsingle = (int64_t)h[0];
   pos = s.nsingle;
+  s.tier[0] = order + pos;  // short rows
+  s.ntier[0] = (int64_t)h[CAT_SHORT];
+  pos += s.ntier[0];
   for (int b = 1; b <= 6; ++b) {
     s.packed[b] = order + pos;
     s.npacked[b] = (int64_t)h[b];
@@ -1891,6 +1900,10 @@ static void sweep_mg(const SweepArgs &a, const Schedule &s, int64_t L, hipStream
     MGCD_LAUNCHED();
   }
   mark(ev, 2, st);
+  if (s.ntier[0] > 0) {  // rows whose sketch is their exact table: the exact one-lane kernel
+    k_exact_small<ALGO><<<grid_for(s.ntier[0]), BLOCK, 0, st>>>(a, s.tier[0], s.ntier[0]);
+    MGCD_LAUNCHED();
+  }
   mark(ev, 3, st);
 }
 
@@ -1984,7 +1997,7 @@ static void sweep_k(const SweepArgs &a, const Schedule &s, int k, int64_t L, hip
     case 4: sweep_mg<4, ALGO, MODE>(a, s, L, st, ev); break;
     case 8: sweep_mg<8, ALGO, MODE>(a, s, L, st, ev); break;
     case 16: sweep_mg<16, ALGO, MODE>(a, s, L, st, ev); break;
-    default: throw Error(-6, "k must be 1, 2, 4, 8, 16, 32 or 64");
+    default: throw Error(-6, "k must be 1, 2, 4, 8, 16, 32, 64, 128 or 256");
   }
 }
 

@@ -163,6 +163,13 @@ struct SchedParams {
   int64_t exact_t0 = 32, exact_t1 = 512, exact_t2 = 4096;
   bool wave = false;  // K = 32 / 64: rows of at most exact_t0 entries exact, the rest one
                       // wave each
+  // K <= 16, Algorithm 1 or the textbook rule: rows of at most mg_short entries hold at
+  // most K distinct keys, so no update or merge ever removes weight and the sketch is
+  // the row's exact table; they take the exact one-lane kernel (0: none).  short_auto:
+  // only when the graph's average row has at most mg_short entries (most rows are
+  // short; on skewed graphs the extra launch costs more than the rows it takes over)
+  int64_t mg_short = 0;
+  bool short_auto = false;
 };
 constexpr int64_t EXACT_T1_MAX = 512, EXACT_T2_MAX = 4096;
 // exact mode, global tables: entries inserted by one workgroup, slots scored by one
@@ -202,6 +209,10 @@ inline SchedParams sched_params(const mgcd_params *p) {
   if (p->exact_lds_big > 0) sp.exact_t2 = p->exact_lds_big;
   if (sp.exact_t1 < sp.exact_t0) sp.exact_t1 = sp.exact_t0;
   if (sp.exact_t2 < sp.exact_t1) sp.exact_t2 = sp.exact_t1;
+  if ((p->mode == MGCD_MODE_ALG1 || p->mode == MGCD_MODE_STD) && p->k <= 16 && p->short_rows != 1) {
+    sp.mg_short = p->k;
+    sp.short_auto = p->short_rows == 0;
+  }
   if (sp.mode != MGCD_MODE_EXACT && p->k > 16) {
     // a stream of at most 32 items cannot lose weight in a sketch of >= 32 slots under
     // Algorithm 1 or the textbook rule (a free slot is always left); the unconditional

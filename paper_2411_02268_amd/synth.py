@@ -14,7 +14,9 @@ available here.  These generators stand in for them:
 * ``rmat``            R-MAT (Graph500 style) skewed graph, social-network-like;
 * ``chung_lu``        power-law expected degrees (exponent 2.1), web-like;
 * ``planted_batch``   thousands of small planted graphs of uneven size;
-* ``serving_stream``  a Poisson request stream of R-MAT graphs.
+* ``serving_stream``  a Poisson request stream of R-MAT graphs;
+* ``road_like``, ``kmer_like``  the low-degree classes (road networks, k-mer graphs:
+                      about 2.1 CSR entries per vertex, unit weights).
 """
 from __future__ import annotations
 
@@ -411,6 +413,70 @@ def serving_stream(count: int = 2000, smin: int = 14, smax: int = 21, deg: int =
     scales = rng.integers(smin, smax + 1, size=count)
     seeds = rng.integers(1, 2**31 - 1, size=count)
     return [(float(t[i]), int(scales[i]), int(seeds[i])) for i in range(count)]
+
+
+# ----------------------------------------------------------------------------------
+# low-degree classes: road networks and k-mer graphs (about 2.1 CSR entries per vertex)
+# ----------------------------------------------------------------------------------
+
+def road_like(side: int = 1024, p_keep: float = 0.6, max_sub: int = 6, seed: int = 4,
+              device: str | None = None) -> CSR:
+    """A road-network stand-in: a side x side grid of intersections whose street
+    segments (grid edges) are kept with probability p_keep, each kept segment drawn as
+    a chain through a uniform 0..max_sub intermediate points of degree 2.  Unit
+    weights.  Ids keep the geometry's locality, as map data does: intersections in
+    row-major order, then every segment's points in segment order.  With the defaults
+    about 4.6 vertices per intersection and 2.09 CSR entries per vertex."""
+    rng = np.random.default_rng(seed)
+    S = side * side
+    r, c = np.divmod(np.arange(S, dtype=np.int64), side)
+    right = np.nonzero(c < side - 1)[0]
+    down = np.nonzero(r < side - 1)[0]
+    a = np.concatenate([right, down])
+    b = np.concatenate([right + 1, down + side])
+    keep = rng.random(a.shape[0]) < p_keep
+    a, b = a[keep], b[keep]
+    order = np.argsort(a * S + b, kind="stable")
+    a, b = a[order], b[order]
+    ksub = rng.integers(0, max_sub + 1, size=a.shape[0])
+    first = S + np.concatenate([[0], np.cumsum(ksub)[:-1]])  # id of each segment's first point
+    n = S + int(ksub.sum())
+    # segment e is the path a_e, first_e, ..., first_e + k_e - 1, b_e
+    seg = np.repeat(np.arange(a.shape[0]), ksub + 1)
+    pos = np.arange(seg.shape[0]) - np.repeat(np.cumsum(ksub + 1) - (ksub + 1), ksub + 1)
+    u = np.where(pos == 0, a[seg], first[seg] + pos - 1)
+    v = np.where(pos == ksub[seg], b[seg], first[seg] + pos)
+    return csr_from_undirected(n, u, v, seed=seed, wmax=1, device=device)
+
+
+def kmer_like(n: int = 1 << 20, mean_len: float = 16.0, p_branch: float = 0.9, seed: int = 5,
+              device: str | None = None) -> CSR:
+    """A k-mer graph stand-in (de Bruijn graphs of sequences are mostly unbranched
+    paths): the vertices, in random order, cut into chains of geometric length (mean
+    mean_len), each chain end joined with probability p_branch to a uniformly random
+    vertex (a branch point).  Unit weights; ids random, as k-mer hashes are.  With
+    the defaults about 2.1 CSR entries per vertex."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n).astype(np.int64)
+    lens = []
+    total = 0
+    while total < n:
+        x = rng.geometric(1.0 / mean_len, size=max(16, int(1.2 * (n - total) / mean_len)))
+        lens.append(x)
+        total += int(x.sum())
+    lens = np.concatenate(lens)
+    ends = np.minimum(np.cumsum(lens), n)
+    ends = ends[: int(np.searchsorted(ends, n)) + 1]
+    starts = np.concatenate([[0], ends[:-1]])
+    inner = np.ones(n, dtype=bool)  # position p joins p + 1 unless a chain ends at p
+    inner[ends - 1] = False
+    pidx = np.nonzero(inner[:-1])[0]
+    u, v = [perm[pidx]], [perm[pidx + 1]]
+    for e in (starts, ends - 1):
+        join = rng.random(e.shape[0]) < p_branch
+        u.append(perm[e[join]])
+        v.append(rng.integers(0, n, size=int(join.sum())))
+    return csr_from_undirected(n, np.concatenate(u), np.concatenate(v), seed=seed, wmax=1, device=device)
 
 
 # ----------------------------------------------------------------------------------

@@ -43,6 +43,8 @@ GRAPHS = {
     "rmat11": lambda: synth.rmat(scale=11, edge_factor=8, seed=3),
     "cl12": lambda: synth.chung_lu(n=1 << 12, avg_deg=24, seed=4),
     "planted": lambda: synth.planted_exact(n_comm=8, comm_size=60, seed=5)[0],
+    "road": lambda: synth.road_like(40, seed=6),
+    "kmer": lambda: synth.kmer_like(3000, seed=7),
 }
 _cache = {}
 
@@ -137,7 +139,7 @@ RUNS = [
 ]
 
 
-@pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12", "planted"])
+@pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12", "planted", "road", "kmer"])
 @pytest.mark.parametrize("algo,mode,k,L", RUNS)
 def test_run_parity(mg, gname, algo, mode, k, L):
     g = graph(gname)
@@ -240,6 +242,45 @@ def test_planted_lpa_config(mg):
         elab, est = oracle.lpa(g, mode=mode, k=8)
         assert np.array_equal(_np(lab), elab)
         assert st["iterations"] == est.iterations <= 20
+
+
+@pytest.mark.parametrize("gname", ["er200", "rmat11", "cl12", "road", "kmer"])
+@pytest.mark.parametrize("algo,mode,k,L", [("lpa", "alg1", 8, 128), ("louvain", "alg1", 1, 128),
+                                           ("louvain", "std", 4, 2), ("leiden", "alg1", 16, 128),
+                                           ("leiden", "std", 8, 5), ("louvain", "uncond", 4, 128)])
+def test_short_rows_schedule_only(mg, gname, algo, mode, k, L):
+    """Rows of at most k entries on the exact one-lane kernel (short_rows = 2), on the
+    sketch kernels (1) or by the graph's average row (0): the same labels and counts,
+    equal to the oracle's."""
+    g = graph(gname)
+    dg = mg.to_device(g)
+    kw = dict(mode=MODES[mode], k=k, chunk_len=L)
+    elab, est = getattr(oracle, algo)(g, **kw)
+    runs = [getattr(mg, algo)(dg, short_rows=sr, **kw) for sr in (0, 1, 2)]
+    for lab, st in runs:
+        assert np.array_equal(_np(lab), elab)
+        for key in ("iterations", "passes", "edges_scanned", "moved_last"):
+            assert st[key] == runs[0][1][key]
+
+
+@pytest.mark.parametrize("cls", ["road", "kmer"])
+@pytest.mark.parametrize("algo,mode,k", [("lpa", "alg1", 8), ("louvain", "alg1", 8), ("leiden", "alg1", 16),
+                                         ("louvain", "exact", 8), ("lpa", "exact", 8)])
+def test_low_degree_class_config(mg, cls, algo, mode, k):
+    """The road and k-mer stand-ins at a million vertices (about 2.1 entries per
+    vertex): whole runs equal the oracle's labels and counts."""
+    key = cls + "_big"
+    if key not in _cache:
+        _cache[key] = (synth.road_like(480, seed=4, device="cuda") if cls == "road"
+                       else synth.kmer_like(1 << 20, seed=5, device="cuda"))
+    g = _cache[key]
+    dg = mg.to_device(g)
+    kw = dict(mode=MODES[mode], k=k, chunk_len=128)
+    lab, st = getattr(mg, algo)(dg, **kw)
+    elab, est = getattr(oracle, algo)(g, **kw)
+    assert np.array_equal(_np(lab), elab)
+    assert st["iterations"] == est.iterations and st["passes"] == est.passes
+    assert st["edges_scanned"] == est.edges_scanned
 
 
 def test_rmat20_louvain_config(mg):

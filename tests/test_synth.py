@@ -41,3 +41,32 @@ def test_rmat_torch_is_a_valid_undirected_csr():
     assert torch.equal(off, off2) and torch.equal(idx, idx2) and torch.equal(w, w2)
     _, idx3, _ = synth.rmat_torch(11, 8, seed=8, device="cpu")
     assert idx3.shape != idx.shape or not torch.equal(idx3, idx)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: synth.road_like(96, seed=4),
+    lambda: synth.kmer_like(20000, seed=5),
+])
+def test_low_degree_classes(make):
+    """Road- and k-mer-like stand-ins: symmetric unit-weight CSRs, rows sorted without
+    self-loops or duplicates, about 2.1 entries per vertex (the |E|/|V| of the paper's
+    road and k-mer graphs), mostly degree-2 vertices."""
+    g = make()
+    o, ii, ww = g.offsets, g.indices, g.weights
+    n = g.n
+    rows = np.repeat(np.arange(n), np.diff(o))
+    assert not np.any(rows == ii)
+    assert np.all(ww == 1)
+    key = rows.astype(np.int64) * n + ii
+    assert np.all(np.diff(key) > 0)  # sorted rows, no duplicates
+    rev = ii.astype(np.int64) * n + rows
+    assert np.array_equal(np.sort(rev), key)  # symmetric
+    assert 2.0 <= g.nnz / n <= 2.25
+    deg = np.diff(o)
+    assert np.mean(deg == 2) > 0.6
+
+
+def test_road_like_device_sort_equals_host():
+    a, b = synth.road_like(80, seed=9), synth.road_like(80, seed=9, device="cpu")
+    assert np.array_equal(a.offsets, b.offsets) and np.array_equal(a.indices, b.indices)
+    assert np.array_equal(a.weights, b.weights)

@@ -31,18 +31,19 @@ sys.path.insert(0, ROOT)
 METRIC = "local-move edges/s (sketch vs exact), batched p99 latency, equal modularity"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 
-# HBM bytes of one level-0 launch of the main sweep kernel, per workload and whether
-# level 0 ran on the storage copy, from FETCH_SIZE and WRITE_SIZE (rocprofv3 --pmc, one
+# HBM bytes of one level-0 launch of the main sweep kernel, per (workload, level 0 on
+# the storage copy, short_rows), from FETCH_SIZE and WRITE_SIZE (rocprofv3 --pmc, one
 # counter per run) scaled by what the counters read for a 512 MiB device copy (FETCH
 # x 2.0, WRITE x 1.0); commands and figures in profiles/k_move_rows_rmat20_counters.md
-# and profiles/k_move_rows_cl24_leiden_counters.md.  Valid only for the kernel sources
-# they were taken on: SOURCES_SHA256 is checked at run time, and traffic is reported as
-# null when the sources differ.
-TRAFFIC_BYTES = {("louvain-mg-k8-rmat20", False, 0): 2380722024,
-                 ("leiden-mg-k16-cl24", False, 0): 106706025376,
-                 ("leiden-mg-k16-cl24", True, 0): 80207006440}
+# and profiles/k_move_rows_cl24_leiden_counters.md.  Each figure is valid only for the
+# kernel sources it was taken on (the SHA-256 of TRAFFIC_SOURCES beside it, checked at
+# run time); traffic is reported as null when the sources differ.
+TRAFFIC_BYTES = {
+    ("louvain-mg-k8-rmat20", False, 0): (2381658808, "a0c76fd4e61102f14c50288fae36bafad204b906239b9e8e0fa0b8a19a3dd93e"),
+    ("leiden-mg-k16-cl24", False, 0): (106706025376, "cc52825819b5cf5515cca2cdf18ce3e9dec6b31a7d82fb397b87a63e05b477cf"),
+    ("leiden-mg-k16-cl24", True, 0): (80207006440, "cc52825819b5cf5515cca2cdf18ce3e9dec6b31a7d82fb397b87a63e05b477cf"),
+}
 TRAFFIC_SOURCES = ["csrc/move.hip", "csrc/move.hpp", "csrc/sketch.hpp", "csrc/common.hpp", "csrc/staging.hpp"]
-TRAFFIC_SOURCES_SHA256 = "cc52825819b5cf5515cca2cdf18ce3e9dec6b31a7d82fb397b87a63e05b477cf"
 
 
 def sources_sha256() -> str:
@@ -516,8 +517,9 @@ def main():
 
     traffic = None
     used_copy = args.storage_order == 2 or (args.storage_order == 0 and g.nnz >= (1 << 26))
-    if dom == 0 and sources_sha256() == TRAFFIC_SOURCES_SHA256:
-        traffic = TRAFFIC_BYTES.get((args.workload, used_copy, args.short_rows))
+    known = TRAFFIC_BYTES.get((args.workload, used_copy, args.short_rows))
+    if dom == 0 and known and sources_sha256() == known[1]:
+        traffic = known[0]
     st_last = stats[-1]
     out = {
         "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,

@@ -3,7 +3,8 @@
 k is semantic (it changes labels): it is chosen on a calibration sample by the
 paper's quality rule (Section 4.1: the smallest sketch whose modularity stays within
 1 % of the exact table), taking the fastest k that meets it.  The schedule knobs
-(row_lanes, exact tier bounds) never change results: they are chosen by time, and
+(row_lanes, where rows of at most k entries go, exact tier bounds) never change
+results: they are chosen by time, and
 the tuner checks that every candidate reproduces the default's labels exactly.
 The chosen values are written to a JSON params file.
 """
@@ -16,6 +17,7 @@ import numpy as np
 
 SKETCH_K = (1, 2, 4, 8, 16, 32, 64)
 ROW_LANES = (8, 16, 32, 64)
+SHORT_ROWS = (0, 1, 2)
 EXACT_TIERS = ((32, 512, 4096), (16, 256, 4096), (64, 512, 4096), (32, 128, 2048))
 
 
@@ -94,23 +96,35 @@ def tune(mg, sample, algo: int, ks=SKETCH_K, quality: float = 0.99, repeats: int
             raise RuntimeError(f"row_lanes={rl} changed the labels")
         lane_t[rl] = sec
     rl = choose_fastest(lane_t)
+    # where rows of at most k entries go (k <= 16; schedule only): by the level's average
+    # row, never or always to the exact one-lane kernel
+    short_t = {}
+    if k <= 16:
+        for sr in SHORT_ROWS:
+            sec, labels = _timed(mg, run, sample, repeats, **dict(base, k=k, row_lanes=rl, short_rows=sr))
+            labels = [lab.cpu().numpy() for lab in labels]
+            if any(not np.array_equal(a, b) for a, b in zip(ref_k, labels)):
+                raise RuntimeError(f"short_rows={sr} changed the labels")
+            short_t[sr] = sec
+    sr = choose_fastest(short_t) if short_t else 0
     return {
         "algo": int(algo), "mode": int(mg.MODE_ALG1), "k": int(k), "k_aggregate": int(k),
-        "chunk_len": int(chunk_len), "row_lanes": int(rl),
+        "chunk_len": int(chunk_len), "row_lanes": int(rl), "short_rows": int(sr),
         "exact_small": tiers[0], "exact_lds": tiers[1], "exact_lds_big": tiers[2],
         "report": {
             "quality_rule": quality, "quality_met": met, "batched": batched,
             "sample": [[g.n, g.nnz] for g in sample],
             "k_table": {str(kk): {"worst_Q_ratio": r, "seconds": s} for kk, (r, s) in table.items()},
             "row_lanes_seconds": {str(c): s for c, s in lane_t.items()},
+            "short_rows_seconds": {str(c): s for c, s in short_t.items()},
             "exact_tier_seconds": {str(c): s for c, s in tier_t.items()},
             "Q_exact": q_exact,
         },
     }
 
 
-PARAM_KEYS = ("mode", "k", "k_aggregate", "chunk_len", "row_lanes", "exact_small", "exact_lds",
-              "exact_lds_big")
+PARAM_KEYS = ("mode", "k", "k_aggregate", "chunk_len", "row_lanes", "short_rows", "exact_small",
+              "exact_lds", "exact_lds_big")
 
 
 def save(tuned: dict, path: str):
@@ -129,4 +143,5 @@ def run_kwargs(tuned: dict, exact: bool = False) -> dict:
     kw = {k: tuned[k] for k in PARAM_KEYS if k in tuned}
     if exact:
         kw["mode"] = 0
+        kw.pop("short_rows", None)
     return kw

@@ -24,12 +24,13 @@ def test_choose_fastest():
 
 def test_params_file_roundtrip(tmp_path):
     tuned = {"algo": 1, "mode": 1, "k": 4, "k_aggregate": 4, "chunk_len": 128, "row_lanes": 16,
-             "exact_small": 32, "exact_lds": 512, "exact_lds_big": 4096, "report": {}}
+             "short_rows": 2, "exact_small": 32, "exact_lds": 512, "exact_lds_big": 4096, "report": {}}
     path = str(tmp_path / "p.json")
     autotune.save(tuned, path)
     back = autotune.load(path)
     assert autotune.run_kwargs(back) == {k: tuned[k] for k in autotune.PARAM_KEYS}
-    assert autotune.run_kwargs(back, exact=True)["mode"] == 0
+    ex = autotune.run_kwargs(back, exact=True)
+    assert ex["mode"] == 0 and "short_rows" not in ex
 
 
 @pytest.fixture(scope="module")

@@ -144,6 +144,7 @@ def serving_leg(mg, torch, requests: int, slots: int, resident: int, sweeps: int
                 ready.release()
             th.join()
             peak = srv.info()["peak_bytes"]
+            step_stats = srv.step_stats() if kind == "steps" else None
         lat = np.array([o[0][2] - o[0][0] for o in out])
         t_first = min(o[0][0] for o in out)
         t_last = max(o[0][2] for o in out)
@@ -153,6 +154,8 @@ def serving_leg(mg, torch, requests: int, slots: int, resident: int, sweeps: int
              "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
              "throughput_rps": requests / (t_last - t_first),
              "edges_per_s": edges / (t_last - t_first), "peak_blocks_GB": peak / 2**30}
+        if step_stats:
+            r["step_stats"] = step_stats
         print(f"[bench] serving {kind} rate {'closed' if rate is None else f'{rate:.1f}/s'}: "
               f"{r['throughput_rps']:.1f} req/s, p50 {r['p50_ms']:.2f} ms, p99 {r['p99_ms']:.2f} ms",
               file=sys.stderr, flush=True)

@@ -235,3 +235,22 @@ def test_stepped_serving_stream(mg):
             lab, st, _ = srv.wait(t)
             np.testing.assert_array_equal(lab.cpu().numpy(), want[0])
             assert st["iterations"] == want[1]["iterations"]
+
+
+def test_stepped_step_stats(mg, pool):
+    """The engine's counters: steps, sweeps and transitions happened; frozen rows are
+    never more than the swept ones; a whole-call server reports zeros."""
+    with mg.Server(mg.ALGO_LOUVAIN, 1 << 30, slots=8, stepped=True, sweeps_per_step=3) as srv:
+        ts = [srv.submit(pool[i]) for i in (0, 1, 2, 3, 4, 5)]
+        passes = 0
+        for t in ts:
+            _, st, _ = srv.wait(t)
+            passes += st["passes"]
+        c = srv.step_stats()
+    assert c["steps"] >= 1 and c["packs"] >= 1
+    assert c["sweeps"] == 3 * c["steps"] and c["sweeps_moving"] <= c["sweeps"]
+    assert 0 < c["rows_moving"] <= c["rows_swept"]
+    assert c["transitions"] == passes  # every level of every request ends once
+    assert min(c["s_pack"], c["s_sweep"], c["s_phase"]) >= 0.0
+    with mg.Server(mg.ALGO_LOUVAIN, 1 << 28, slots=2) as srv:
+        assert all(v == 0 for v in srv.step_stats().values())

@@ -334,7 +334,7 @@ def main():
                     help="requests of the serving leg (0 skips it; default 1000 with the "
                          "default workload, else 0)")
     ap.add_argument("--serve-slots", type=int, default=4, help="worker streams of the whole-call server")
-    ap.add_argument("--serve-resident", type=int, default=32,
+    ap.add_argument("--serve-resident", type=int, default=64,
                     help="resident requests of the step-level server")
     ap.add_argument("--serve-sweeps", type=int, default=0,
                     help="sweeps per step of the step-level server (0: a whole level per step)")

@@ -331,8 +331,10 @@ int mgcd_server_destroy(mgcd_server *s);
  *   admitted in arrival
  *   order once fewer than max_resident (1..65536) requests are resident, its block
  *   fits and the union of the resident requests with it (sized at their input sizes)
- *   fits the shared region.  One scheduler thread and one HIP stream (default
- *   priority) on the device current at creation.  params are checked at creation
+ *   fits its engine's share of the shared region.  Two step engines (one when
+ *   max_resident is 1), each with half the resident places and half the shared region,
+ *   a scheduler thread and a HIP stream (default priority) of its own on the device
+ *   current at creation, so that one engine's sweeps overlap the other's phase work.  params are checked at creation
  *   (MGCD_E_ARG / MGCD_E_UNSUPPORTED as the calls return them).  Submission, poll,
  *   wait, info (bytes_in_use and the peak count the blocks; the shared region is
  *   reserved) and destroy are those of mgcd_server_*.  mgcd_server_submit returns

@@ -1,8 +1,8 @@
 // Serving (continuous batching), in two forms over one caller-provided arena:
 // whole calls -- worker threads with their own streams each run one request's call at
-// a time in a block of the arena; or steps -- one scheduler thread advances every
-// resident request together, one sweep per step, through the step engine
-// (stepped.hip), admitting new requests between steps.
+// a time in a block of the arena; or steps -- step engines (stepped.hip), each with a
+// scheduler thread and stream of its own, advance their resident requests together,
+// sweep by sweep, admitting new requests between steps.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -25,8 +25,13 @@
 namespace {
 
 constexpr size_t ALIGN = 256;
-// Streams on which a stepped server runs the phase work of many requests at once.
+// Streams on which a stepped server's engine runs the phase work of many requests at
+// once.
 constexpr int STEP_PHASE_LANES = 4;
+// Step engines of a stepped server: each takes half the resident places and half the
+// shared region and runs on a stream and scheduler thread of its own, so that one
+// engine's sweeps overlap the other's phase work (host round trips).
+constexpr int STEP_ENGINES = 2;
 
 struct Request {
   int64_t ticket = 0;
@@ -40,6 +45,20 @@ struct Request {
   double t_submit = 0, t_start = 0, t_end = 0;
   size_t off = 0;       // its block in the arena
   mgcd::StepJob job;    // step-level serving
+  int eng = 0;          // step-level serving: its engine
+};
+
+// One step engine of a stepped server and the requests resident in it.
+struct EngineSlot {
+  std::unique_ptr<mgcd::StepEngine> engine;
+  char *shared = nullptr;  // its slice of the shared region
+  size_t shared_bytes = 0;
+  int64_t max_resident = 0;
+  std::unordered_map<Request *, std::shared_ptr<Request>> resident;
+  int64_t res_N = 0, res_E = 0;
+  std::multiset<int32_t> res_n;
+  std::multiset<int64_t> res_nnz;
+  mgcd_step_stats stats{};  // the engine's counters, copied under the server's lock
 };
 
 // First-fit allocator over [0, cap) with coalescing of free neighbours.
@@ -107,16 +126,12 @@ struct mgcd_server {
   int64_t next_ticket = 1;
   int64_t running = 0;
   bool stopping = false;
-  // step-level serving: the shared region [0, shared) of the arena, blocks after it
+  // step-level serving: the shared region [0, shared) of the arena (one slice per
+  // engine), blocks after it
   bool stepped = false;
-  int64_t max_resident = 0;
   size_t shared = 0;
-  std::unique_ptr<mgcd::StepEngine> engine;
-  std::unordered_map<Request *, std::shared_ptr<Request>> resident;
-  int64_t res_N = 0, res_E = 0;
-  std::multiset<int32_t> res_n;
-  std::multiset<int64_t> res_nnz;
-  mgcd_step_stats step_stats{};  // the engine's counters, copied under the lock
+  std::vector<EngineSlot> engs;
+  uint64_t admit_gen = 0;  // changes whenever a request arrives or a block is freed
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
   double now() const {
@@ -156,79 +171,97 @@ struct mgcd_server {
     }
   }
 
-  // Step-level serving: the oldest waiting requests join while a resident place is
-  // free, the shared region holds the union with them and their block fits (in
-  // arrival order; a request that does not fit waits for earlier ones to finish).
-  void admit_waiting(std::vector<std::shared_ptr<Request>> &adm) {
-    while (!waiting.empty() && (int64_t)resident.size() < max_resident) {
+  // Step-level serving: the oldest waiting requests join engine e while it has a
+  // resident place, its shared slice holds its union with them and their block fits
+  // (in arrival order; a request that does not fit waits for others to finish).
+  void admit_waiting(int e, std::vector<std::shared_ptr<Request>> &adm) {
+    EngineSlot &E = engs[(size_t)e];
+    while (!waiting.empty() && (int64_t)E.resident.size() < E.max_resident) {
       std::shared_ptr<Request> r = waiting.front();
       const int32_t n = (int32_t)r->g.n;
       const int64_t nnz = r->g.nnz;
-      const int32_t mx_n = std::max(n, res_n.empty() ? 0 : *res_n.rbegin());
-      const int64_t mx_e = std::max(nnz, res_nnz.empty() ? (int64_t)0 : *res_nnz.rbegin());
-      const size_t need = mgcd::StepEngine::shared_need(algo, params, (int64_t)resident.size() + 1, res_N + n,
-                                                        res_E + nnz, mx_n, mx_e);
+      const int32_t mx_n = std::max(n, E.res_n.empty() ? 0 : *E.res_n.rbegin());
+      const int64_t mx_e = std::max(nnz, E.res_nnz.empty() ? (int64_t)0 : *E.res_nnz.rbegin());
+      const size_t need = mgcd::StepEngine::shared_need(algo, params, (int64_t)E.resident.size() + 1,
+                                                        E.res_N + n, E.res_E + nnz, mx_n, mx_e);
       size_t off = 0;
-      if (need > shared || !blocks.take(r->need, &off)) break;
+      if (need > E.shared_bytes || !blocks.take(r->need, &off)) break;
       waiting.pop_front();
       r->off = off;
+      r->eng = e;
       r->job.g = r->g;
       r->job.out = r->out;
       r->job.block = arena + shared + off;
       r->job.user = r.get();
       r->state = 1;
       r->t_start = now();
-      resident[r.get()] = r;
-      res_N += n;
-      res_E += nnz;
-      res_n.insert(n);
-      res_nnz.insert(nnz);
+      E.resident[r.get()] = r;
+      E.res_N += n;
+      E.res_E += nnz;
+      E.res_n.insert(n);
+      E.res_nnz.insert(nnz);
       ++running;
       adm.push_back(r);
     }
   }
 
   void complete(Request *r) {
+    EngineSlot &E = engs[(size_t)r->eng];
     blocks.give(r->off, r->need);
-    res_N -= r->g.n;
-    res_E -= r->g.nnz;
-    res_n.erase(res_n.find((int32_t)r->g.n));
-    res_nnz.erase(res_nnz.find(r->g.nnz));
+    ++admit_gen;
+    E.res_N -= r->g.n;
+    E.res_E -= r->g.nnz;
+    E.res_n.erase(E.res_n.find((int32_t)r->g.n));
+    E.res_nnz.erase(E.res_nnz.find(r->g.nnz));
     r->rc = r->job.rc;
     r->err = r->job.err;
     r->stats = r->job.stats;
     r->t_end = now();
     r->state = 2;
     --running;
-    resident.erase(r);
+    E.resident.erase(r);
   }
 
-  void run_steps() {
+  bool all_idle() const {
+    for (const EngineSlot &E : engs)
+      if (!E.resident.empty()) return false;
+    return true;
+  }
+
+  void run_steps(int e) {
     (void)hipSetDevice(device);
+    EngineSlot &E = engs[(size_t)e];
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
       std::vector<std::shared_ptr<Request>> adm;
-      admit_waiting(adm);
-      if (adm.empty() && resident.empty()) {
+      const uint64_t gen = admit_gen;
+      admit_waiting(e, adm);
+      if (adm.empty() && E.resident.empty()) {
         if (waiting.empty()) {
           if (stopping) break;
           cv_admit.wait(lk, [&] { return stopping || !waiting.empty(); });
           continue;
         }
-        // nothing resident and the oldest request still does not fit: it never will
-        std::shared_ptr<Request> r = waiting.front();
-        waiting.pop_front();
-        r->rc = MGCD_E_WORKSPACE;
-        r->err = "request does not fit the server's arena";
-        r->t_start = r->t_end = now();
-        r->state = 2;
-        cv_done.notify_all();
+        if (all_idle() && blocks.used == 0) {
+          // nothing resident anywhere and the oldest request does not fit: it never will
+          std::shared_ptr<Request> r = waiting.front();
+          waiting.pop_front();
+          r->rc = MGCD_E_WORKSPACE;
+          r->err = "request does not fit the server's arena";
+          r->t_start = r->t_end = now();
+          r->state = 2;
+          cv_done.notify_all();
+          continue;
+        }
+        // the other engine holds the memory the oldest request needs: wait until a
+        // request arrives or a block is freed (also when stopping: the queue drains)
+        cv_admit.wait(lk, [&] { return admit_gen != gen; });
         continue;
       }
       lk.unlock();
       std::vector<mgcd::StepJob *> fin;
       auto fail = [&](int code, const std::string &msg) {
-        engine->fail_all(code, msg, fin);
+        E.engine->fail_all(code, msg, fin);
         for (auto &r : adm)
           if (!r->job.done) {
             r->job.rc = code;
@@ -240,17 +273,20 @@ struct mgcd_server {
       try {
         std::vector<mgcd::StepJob *> js;
         for (auto &r : adm) js.push_back(&r->job);
-        engine->admit(js, fin);
-        engine->step(fin);
-      } catch (const mgcd::Error &e) {
-        fail(e.code, e.what());
-      } catch (const std::exception &e) {
-        fail(MGCD_E_ARG, e.what());
+        E.engine->admit(js, fin);
+        E.engine->step(fin);
+      } catch (const mgcd::Error &ex) {
+        fail(ex.code, ex.what());
+      } catch (const std::exception &ex) {
+        fail(MGCD_E_ARG, ex.what());
       }
       lk.lock();
-      step_stats = engine->counters();
+      E.stats = E.engine->counters();
       for (mgcd::StepJob *j : fin) complete((Request *)j->user);
-      if (!fin.empty()) cv_done.notify_all();
+      if (!fin.empty()) {
+        cv_done.notify_all();
+        cv_admit.notify_all();  // freed memory may admit requests into the other engine
+      }
     }
   }
 };
@@ -322,23 +358,34 @@ int mgcd_server_create_stepped(void *arena, size_t arena_bytes, size_t shared_by
     return fail(e.code, e.what());
   }
   s->stepped = true;
-  s->max_resident = max_resident;
   s->shared = shared_bytes;
   s->blocks = BlockAllocator(cap - shared_bytes);
   if (hipGetDevice(&s->device) != hipSuccess) return fail(MGCD_E_HIP, "hipGetDevice failed");
   mgcd::set_last_error("");
-  hipStream_t st = nullptr;
-  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
-    return fail(MGCD_E_HIP, "hipStreamCreateWithFlags failed");
-  s->streams.push_back(st);
-  try {
-    s->engine = std::make_unique<mgcd::StepEngine>(algo, s->params, sweeps_per_step, s->arena, shared_bytes, st,
-                                                   STEP_PHASE_LANES);
-  } catch (const mgcd::Error &e) {
-    (void)hipStreamDestroy(st);
-    return fail(e.code, e.what());
+  const int ne = max_resident < STEP_ENGINES ? max_resident : STEP_ENGINES;
+  const size_t slice = shared_bytes / (size_t)ne / ALIGN * ALIGN;
+  s->engs.resize((size_t)ne);
+  for (int e = 0; e < ne; ++e) {
+    EngineSlot &E = s->engs[(size_t)e];
+    E.shared = s->arena + (size_t)e * slice;
+    E.shared_bytes = slice;
+    E.max_resident = max_resident / ne + (e < max_resident % ne ? 1 : 0);
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+      return fail(MGCD_E_HIP, "hipStreamCreateWithFlags failed");
+    }
+    s->streams.push_back(st);
+    try {
+      E.engine = std::make_unique<mgcd::StepEngine>(algo, s->params, sweeps_per_step, E.shared, slice, st,
+                                                    STEP_PHASE_LANES);
+    } catch (const mgcd::Error &ex) {
+      s->engs.clear();
+      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+      return fail(ex.code, ex.what());
+    }
   }
-  s->workers.emplace_back([srv = s.get()] { srv->run_steps(); });
+  for (int e = 0; e < ne; ++e) s->workers.emplace_back([srv = s.get(), e] { srv->run_steps(e); });
   *out = s.release();
   return MGCD_OK;
 }
@@ -360,10 +407,12 @@ int mgcd_server_submit(mgcd_server *s, const mgcd_csr *g, int32_t *communities_o
   cap += s->blocks.used;
   if (r->need > cap) return fail(MGCD_E_WORKSPACE, "request needs more than the whole arena");
   if (s->stepped &&
-      mgcd::StepEngine::shared_need(s->algo, s->params, 1, g->n, g->nnz, (int32_t)g->n, g->nnz) > s->shared)
-    return fail(MGCD_E_WORKSPACE, "request needs more than the server's shared region");
+      mgcd::StepEngine::shared_need(s->algo, s->params, 1, g->n, g->nnz, (int32_t)g->n, g->nnz) >
+          s->engs[0].shared_bytes)
+    return fail(MGCD_E_WORKSPACE, "request needs more than a step engine's share of the shared region");
   if (s->stopping) return fail(MGCD_E_ARG, "server is shutting down");
   r->ticket = s->next_ticket++;
+  ++s->admit_gen;
   r->t_submit = s->now();
   s->tickets[r->ticket] = r;
   s->waiting.push_back(r);
@@ -413,7 +462,20 @@ int mgcd_server_info(mgcd_server *s, int64_t *waiting, int64_t *running, size_t 
 int mgcd_server_step_stats(mgcd_server *s, mgcd_step_stats *out) {
   if (!s || !out) return fail(MGCD_E_ARG, "null argument");
   std::lock_guard<std::mutex> lk(s->mu);
-  *out = s->step_stats;
+  mgcd_step_stats t{};
+  for (const EngineSlot &E : s->engs) {
+    t.steps += E.stats.steps;
+    t.sweeps += E.stats.sweeps;
+    t.sweeps_moving += E.stats.sweeps_moving;
+    t.packs += E.stats.packs;
+    t.transitions += E.stats.transitions;
+    t.rows_swept += E.stats.rows_swept;
+    t.rows_moving += E.stats.rows_moving;
+    t.s_pack += E.stats.s_pack;
+    t.s_sweep += E.stats.s_sweep;
+    t.s_phase += E.stats.s_phase;
+  }
+  *out = t;
   return MGCD_OK;
 }
 

@@ -1046,8 +1046,8 @@ __device__ inline void exact_row_regs(const SweepArgs &a, int32_t i, int32_t bi,
 
 // Exact mode, the shortest rows (tier 0): one lane per vertex; K_{i->c} of each
 // distinct key, summed at its first occurrence in the row.  Rows of at most 32
-// entries keep the row in registers (the unroll depth follows the longest row of
-// the wave); longer tier-0 rows (a raised exact_small) re-read the row.
+// entries keep the row in registers (the unroll depth, 2 to 32, follows the longest
+// row of the wave); longer tier-0 rows (a raised exact_small) re-read the row.
 template <int ALGO>
 __global__ void __launch_bounds__(BLOCK)
     k_exact_small(SweepArgs a, const int32_t *__restrict__ list, int64_t count) {
@@ -1070,6 +1070,10 @@ __global__ void __launch_bounds__(BLOCK)
   const int32_t d = live ? community_of_self<ALGO>(a, i) : 0;
   if (maxdeg == 0) {
     if (live) finish<ALGO>(a, i, d, -1, 0, ct);  // no neighbours: stay
+  } else if (maxdeg <= 2) {
+    if (live) exact_row_regs<ALGO, 2>(a, i, bi, lo, hi, d, ct);
+  } else if (maxdeg <= 4) {
+    if (live) exact_row_regs<ALGO, 4>(a, i, bi, lo, hi, d, ct);
   } else if (maxdeg <= 8) {
     if (live) exact_row_regs<ALGO, 8>(a, i, bi, lo, hi, d, ct);
   } else if (maxdeg <= 16) {

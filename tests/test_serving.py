@@ -254,3 +254,30 @@ def test_stepped_step_stats(mg, pool):
     assert min(c["s_pack"], c["s_sweep"], c["s_phase"]) >= 0.0
     with mg.Server(mg.ALGO_LOUVAIN, 1 << 28, slots=2) as srv:
         assert all(v == 0 for v in srv.step_stats().values())
+
+
+@pytest.mark.parametrize("stepped", [False, True], ids=["calls", "steps"])
+def test_destroy_drains(mg, pool, stepped):
+    """Destroying a server with requests still queued or running runs them to
+    completion first (their outputs are written) and returns."""
+    import torch
+    want = _solo(mg, mg.ALGO_LOUVAIN, pool[4], {})[0]
+    srv = mg.Server(mg.ALGO_LOUVAIN, 1 << 30, slots=2, stepped=stepped)
+    ts = [srv.submit(pool[4]) for _ in range(5)]
+    outs = [srv._held[t][1] for t in ts]
+    srv.close()
+    torch.cuda.synchronize()
+    for o in outs:
+        np.testing.assert_array_equal(o[:pool[4].n].cpu().numpy(), want)
+
+
+def test_stepped_rejects_bad_params(mg):
+    with pytest.raises(mg.MgcdError) as e:
+        mg.Server(mg.ALGO_LOUVAIN, 1 << 24, slots=4, stepped=True, k=3)
+    assert e.value.code == -6
+    with pytest.raises(mg.MgcdError) as e:
+        mg.Server(mg.ALGO_LOUVAIN, 1 << 24, slots=4, stepped=True, one_scan=1)
+    assert e.value.code == -6
+    with pytest.raises(mg.MgcdError) as e:
+        mg.Server(mg.ALGO_LPA, 1 << 24, slots=0, stepped=True)
+    assert e.value.code == -1

@@ -157,24 +157,58 @@ __device__ inline int32_t row_of_entry(const int64_t *off, int32_t lo, int32_t h
   return lo;
 }
 
-// Rows of a tile of consecutive CSR entries [e0, e1) (non-empty): the rows meeting
-// it are r0 .. r1 (two binary searches); every row r0 < r <= r1 marks its first
-// position in an LDS count array, whose inclusive prefix sum then gives the entry
-// at tile position x the row r0 + starts[x] (no per-entry search).  Whole-workgroup
-// call; returns r0.
 constexpr int SF_ITEMS = 8, SF_TILE = BLOCK * SF_ITEMS;
 
-__device__ inline int32_t tile_rows(const Graph &g, int64_t e0, int64_t e1, uint32_t *starts) {
+// The first row of every tile of SF_TILE consecutive CSR entries: first[t] = the row
+// holding entry t * SF_TILE (t < ntiles) and first[ntiles] = n - 1, so that a tile's
+// rows lie in first[t] .. first[t + 1] (an upper bound: rows after the tile's last
+// entry are recognised by their offsets).  One thread per row marks the tile starts
+// inside its row; each entry lies in exactly one row, so each slot has one writer.
+// This replaces two binary searches over the offsets per workgroup, whose chains of
+// dependent loads set the time of the tiled kernels.
+__global__ void k_tile_first_rows(const int64_t *off, int32_t n, int64_t ntiles, int32_t *first) {
+  const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (r == 0) first[ntiles] = n - 1;
+  if (r >= n) return;
+  const int64_t lo = off[r], hi = off[r + 1];
+  for (int64_t b = (lo + SF_TILE - 1) / SF_TILE; b * SF_TILE < hi; ++b) first[b] = (int32_t)r;
+}
+
+size_t tile_table_bytes(int64_t nnz) { return (size_t)(ceil_div(nnz > 0 ? nnz : 0, SF_TILE) + 1) * 4 + 256; }
+
+// The table of a graph with entries (taken from `a`).
+static int32_t *tile_first_rows(const Graph &g, Arena &a, hipStream_t st) {
+  const int64_t nt = ceil_div(g.nnz, SF_TILE);
+  int32_t *first = a.take<int32_t>(nt + 1);
+  k_tile_first_rows<<<(unsigned)ceil_div(g.n > 0 ? g.n : 1, BLOCK), BLOCK, 0, st>>>(g.off, g.n, nt, first);
+  MGCD_LAUNCHED();
+  return first;
+}
+
+// Rows of a tile of consecutive CSR entries [e0, e1) (non-empty): the rows meeting it
+// lie in r0 .. r1 (from the tile table, or two binary searches when first is null);
+// every row r0 < r <= r1 that starts inside the tile marks its first position in an
+// LDS count array, whose inclusive prefix sum then gives the entry at tile position x
+// the row r0 + starts[x] (no per-entry search).  Whole-workgroup call; returns r0.
+__device__ inline int32_t tile_rows(const Graph &g, int64_t e0, int64_t e1, uint32_t *starts,
+                                    const int32_t *first) {
   __shared__ uint32_t wsum[BLOCK / WAVE];
   __shared__ int32_t sr[2];
   const int t = threadIdx.x, w = t / WAVE;
   for (int x = t; x < SF_TILE; x += BLOCK) starts[x] = 0;
-  if (t == 0) sr[0] = row_of_entry(g.off, 0, g.n - 1, e0);
-  if (t == 1) sr[1] = row_of_entry(g.off, 0, g.n - 1, e1 - 1);
+  if (first) {
+    if (t < 2) sr[t] = first[blockIdx.x + t];
+  } else {
+    if (t == 0) sr[0] = row_of_entry(g.off, 0, g.n - 1, e0);
+    if (t == 1) sr[1] = row_of_entry(g.off, 0, g.n - 1, e1 - 1);
+  }
   __syncthreads();
   const int32_t r0 = sr[0], r1 = sr[1];
-  // rows r0 < r <= r1 start inside the tile (off[r0 + 1] > e0, off[r1] <= e1 - 1)
-  for (int64_t r = (int64_t)r0 + 1 + t; r <= r1; r += BLOCK) atomicAdd(&starts[g.off[r] - e0], 1u);
+  // rows r0 < r <= r1 starting before e1 start inside the tile (off[r0 + 1] > e0)
+  for (int64_t r = (int64_t)r0 + 1 + t; r <= r1; r += BLOCK) {
+    const int64_t p = g.off[r] - e0;
+    if (p < e1 - e0) atomicAdd(&starts[p], 1u);
+  }
   __syncthreads();
   // inclusive prefix sum of the counts: thread t owns positions SF_ITEMS*t ..
   uint32_t v[SF_ITEMS], run = 0;
@@ -199,7 +233,7 @@ __device__ inline int32_t tile_rows(const Graph &g, int64_t e0, int64_t e1, uint
 
 
 __global__ void __launch_bounds__(BLOCK)
-    k_row_weight_sums(Graph g, uint32_t *K, unsigned long long *Wpart) {
+    k_row_weight_sums(Graph g, const int32_t *first, uint32_t *K, unsigned long long *Wpart) {
   __shared__ uint32_t ex[DG_TILE + 1];
   __shared__ uint32_t wsum[BLOCK / WAVE];
   __shared__ unsigned long long wtot[BLOCK / WAVE];
@@ -207,8 +241,13 @@ __global__ void __launch_bounds__(BLOCK)
   const int t = threadIdx.x, w = t / WAVE;
   const int64_t e0 = (int64_t)blockIdx.x * DG_TILE;
   const int64_t e1 = e0 + DG_TILE < g.nnz ? e0 + DG_TILE : g.nnz;
-  if (t == 0) sr[0] = row_of_entry(g.off, 0, g.n - 1, e0);
-  if (t == 1) sr[1] = row_of_entry(g.off, 0, g.n - 1, e1 - 1);
+  static_assert(DG_TILE == SF_TILE, "one tile table");
+  if (first) {  // rows meeting the tile lie in sr[0] .. sr[1]
+    if (t < 2) sr[t] = first[blockIdx.x + t];
+  } else {
+    if (t == 0) sr[0] = row_of_entry(g.off, 0, g.n - 1, e0);
+    if (t == 1) sr[1] = row_of_entry(g.off, 0, g.n - 1, e1 - 1);
+  }
   unsigned long long tsum = 0;
 #pragma unroll
   for (int q = 0; q < DG_ITEMS; ++q) {
@@ -262,7 +301,7 @@ __global__ void k_fold_total(const unsigned long long *part, unsigned long long 
   if (lane_id() == 0) *W = s;
 }
 
-size_t degrees_ws_bytes(int64_t) { return (size_t)SPREAD * 8 + 4096; }
+size_t degrees_ws_bytes(int64_t nnz) { return (size_t)SPREAD * 8 + 4096 + tile_table_bytes(nnz); }
 
 void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, Arena &a, hipStream_t st) {
   static_assert(SPREAD == WAVE, "k_fold_total folds one copy per lane");
@@ -271,7 +310,11 @@ void launch_degrees(const Graph &g, uint32_t *K, unsigned long long *W, Arena &a
   launch_zero_u64(part, SPREAD, st);
   if (g.n > 0) zero_u32(K, g.n, st);
   if (g.nnz > 0) {
-    k_row_weight_sums<<<(unsigned)ceil_div(g.nnz, DG_TILE), BLOCK, 0, st>>>(g, K, part);
+    // the tile table when the workspace holds it (a fixed scratch may not): else each
+    // workgroup finds its rows by binary search
+    const size_t tb = (size_t)(ceil_div(g.nnz, SF_TILE) + 1) * 4;
+    const int32_t *first = ((a.used + 255) & ~(size_t)255) + tb <= a.cap ? tile_first_rows(g, a, st) : nullptr;
+    k_row_weight_sums<<<(unsigned)ceil_div(g.nnz, DG_TILE), BLOCK, 0, st>>>(g, first, K, part);
     MGCD_LAUNCHED();
   }
   k_fold_total<<<1, WAVE, 0, st>>>(part, W);
@@ -336,7 +379,7 @@ __global__ void __launch_bounds__(BLOCK)
   const int t = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * SF_TILE;
   const int64_t e1 = e0 + SF_TILE < g.nnz ? e0 + SF_TILE : g.nnz;
-  const int32_t r0 = tile_rows(g, e0, e1, starts);
+  const int32_t r0 = tile_rows(g, e0, e1, starts, nullptr);
   unsigned long long tot = 0;
 #pragma unroll
   for (int q = 0; q < SF_ITEMS; ++q) {
@@ -569,12 +612,13 @@ __global__ void k_row_pos(const uint32_t *mem, const int64_t *P, const int32_t *
 // consecutive entries (balanced whatever the row lengths), finds their rows with
 // tile_rows and reads and writes the entries in coalesced order.
 __global__ void __launch_bounds__(BLOCK)
-    k_agg_streamify(Graph g, const int32_t *D, const int64_t *rowpos, uint32_t *skey, uint32_t *sw) {
+    k_agg_streamify(Graph g, const int32_t *first, const int32_t *D, const int64_t *rowpos, uint32_t *skey,
+                    uint32_t *sw) {
   __shared__ uint32_t starts[SF_TILE];
   const int t = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * SF_TILE;
   const int64_t e1 = e0 + SF_TILE < g.nnz ? e0 + SF_TILE : g.nnz;
-  const int32_t r0 = tile_rows(g, e0, e1, starts);
+  const int32_t r0 = tile_rows(g, e0, e1, starts, first);
   // all loads and gathers are issued first (a position past the end reads entry e0),
   // then the stores, so the gathers of the SF_ITEMS rounds are in flight together
   int64_t pos[SF_ITEMS];
@@ -630,6 +674,7 @@ size_t storage_ws_bytes(int32_t n, int64_t nnz) {
   b += (size_t)n * (4 + 4 + 4) + 4096;                            // perm, pos, K
   b += (size_t)n * (8 + 4) * 2 + radix_sort_ws_bytes(n) + 4096;   // degree sort (released)
   b += (size_t)n * 8 * 2 + scan_ws_bytes((int64_t)n + 1) + 8192;  // degrees, row places (released)
+  b += tile_table_bytes(nnz);                                     // tile first rows (released)
   return b;
 }
 
@@ -663,8 +708,9 @@ StorageCopy storage_copy(const Graph &g, const uint32_t *K, Arena &a, hipStream_
   k_row_places<<<grid_for(n), BLOCK, 0, st>>>(s.pos, offp, n, rowpos);
   MGCD_LAUNCHED();
   if (g.nnz > 0) {  // entries in source order (coalesced reads), written at their new places
+    const int32_t *first = tile_first_rows(g, a, st);
     k_agg_streamify<<<(unsigned)ceil_div(g.nnz, SF_TILE), BLOCK, 0, st>>>(
-        g, s.pos, rowpos, reinterpret_cast<uint32_t *>(idxp), wp);
+        g, first, s.pos, rowpos, reinterpret_cast<uint32_t *>(idxp), wp);
     MGCD_LAUNCHED();
   }
   a.release(mk);
@@ -894,14 +940,14 @@ __global__ void k_dedupe_max(const uint64_t *ks, const uint32_t *vs, const uint3
 // the key 2^(2b) - 1, sorted past every real key, and are not counted in kept
 // (SPREAD copies, by workgroup).
 __global__ void __launch_bounds__(BLOCK)
-    k_exact_keys(Graph g, const int32_t *D, int b, uint64_t *key, uint32_t *val,
+    k_exact_keys(Graph g, const int32_t *first, const int32_t *D, int b, uint64_t *key, uint32_t *val,
                  unsigned long long *kept) {
   __shared__ uint32_t starts[SF_TILE];
   __shared__ unsigned long long bk[BLOCK / WAVE];
   const int t = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * SF_TILE;
   const int64_t e1 = e0 + SF_TILE < g.nnz ? e0 + SF_TILE : g.nnz;
-  const int32_t r0 = tile_rows(g, e0, e1, starts);
+  const int32_t r0 = tile_rows(g, e0, e1, starts, first);
   const uint64_t left_out = (1ull << (2 * b)) - 1;
   uint64_t ks[SF_ITEMS];
   uint32_t vs[SF_ITEMS];
@@ -1231,7 +1277,8 @@ static int64_t aggregate_exact(const Graph &g, const int32_t *D, int32_t m, int6
   int64_t *rid = a.take<int64_t>(E0 + 1);
   unsigned long long *kept = a.take<unsigned long long>(2 * SPREAD);
   launch_zero_u64(kept, 2 * SPREAD, st);
-  k_exact_keys<<<(unsigned)ceil_div(E0, SF_TILE), BLOCK, 0, st>>>(g, D, b, k0, v0, kept);
+  const int32_t *first = tile_first_rows(g, a, st);
+  k_exact_keys<<<(unsigned)ceil_div(E0, SF_TILE), BLOCK, 0, st>>>(g, first, D, b, k0, v0, kept);
   MGCD_LAUNCHED();
   bool flip = radix_sort_pairs(k0, v0, k1, v1, E0, 2 * b, a, st);
   unsigned long long hk[2];
@@ -1357,7 +1404,8 @@ int64_t aggregate(const Graph &g, const int32_t *D, int32_t m, int mode, int k, 
   uint32_t *skey = a.take<uint32_t>(g.nnz);
   uint32_t *sw = a.take<uint32_t>(g.nnz);
   if (g.nnz > 0) {
-    k_agg_streamify<<<(unsigned)ceil_div(g.nnz, SF_TILE), BLOCK, 0, st>>>(g, D, rowpos, skey, sw);
+    const int32_t *first = tile_first_rows(g, a, st);
+    k_agg_streamify<<<(unsigned)ceil_div(g.nnz, SF_TILE), BLOCK, 0, st>>>(g, first, D, rowpos, skey, sw);
     MGCD_LAUNCHED();
   }
   AggStreams s{g, D, mem, mstart, P, rs, skey, sw};
@@ -1411,7 +1459,7 @@ size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L, bo
   if (mode == MODE_EXACT) {
     b += (size_t)nnz * (8 + 8 + 4 + 4 + 4 + 8) + 8192;
     b += radix_sort_ws_bytes(nnz) + scan_ws_bytes(nnz) + (size_t)n * 4 + 4096;
-    return b + 64 * 1024;
+    return b + tile_table_bytes(nnz) + 64 * 1024;
   }
   b += (size_t)n * (8 + 8 + 4 + 4) + 4096;          // member sort buffers
   b += radix_sort_ws_bytes(n) + 4096;
@@ -1431,6 +1479,7 @@ size_t aggregate_ws_bytes(int32_t n, int64_t nnz, int mode, int k, int64_t L, bo
   }
   b += (size_t)n * k * sizeof(Pair) + (size_t)n * 4 + 4096;  // rows, rcount
   b += (size_t)nnz * 8 + (size_t)n * 8 + 4096;               // laid-out streams, row positions
+  b += tile_table_bytes(nnz);                                // tile first rows
   if (symmetric) {
     // emit buffers (rows hold at most their stream: <= 2 min(k n, nnz) entries), sort, heads
     int64_t e2 = 2 * ((int64_t)n * k < nnz ? (int64_t)n * k : nnz);

@@ -156,6 +156,84 @@ __global__ void __launch_bounds__(BLOCK)
   }
 }
 
+// ---- phase transitions of many graphs at once (LPA, Louvain) --------------------------
+
+// out[q] = src[pos[q]].
+__global__ void k_step_gather(const int64_t *src, const int64_t *pos, int64_t *out, int32_t count) {
+  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (q < count) out[q] = src[pos[q]];
+}
+
+// A graph's level map into the union's renumbering: top[v] = D[vbase + top[v]] - db
+// (D: dense ids over the graphs renumbered together; the graph's are db, db + 1, ...).
+struct ComposeDesc {
+  int32_t *top;
+  int64_t n, vbase, db;
+};
+__global__ void k_step_compose(const ComposeDesc *d, int32_t y0, const int32_t *D) {
+  const ComposeDesc c = d[y0 + (int32_t)blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < c.n; v += stride)
+    c.top[v] = (int32_t)(D[c.vbase + c.top[v]] - c.db);
+}
+
+// Canonical labels of many graphs at once: graph f's labels lab[0, n) (values < n)
+// and vertices take the global places off .. off + n - 1; a community is numbered by
+// the rank of its smallest vertex among the communities of its graph.
+struct CanonDesc {
+  const int32_t *lab;
+  int32_t *out;
+  int64_t n, off;
+};
+__global__ void k_canon_min(const CanonDesc *d, int32_t y0, int32_t *minv) {
+  const CanonDesc c = d[y0 + (int32_t)blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < c.n; v += stride)
+    atomicMin(&minv[c.off + c.lab[v]], (int32_t)(c.off + v));
+}
+__global__ void k_canon_first(const CanonDesc *d, int32_t y0, const int32_t *minv, uint32_t *first) {
+  const CanonDesc c = d[y0 + (int32_t)blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < c.n; v += stride)
+    first[c.off + v] = minv[c.off + c.lab[v]] == (int32_t)(c.off + v) ? 1u : 0u;
+}
+__global__ void k_canon_write(const CanonDesc *d, int32_t y0, const int32_t *minv, const int64_t *rank) {
+  const CanonDesc c = d[y0 + (int32_t)blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < c.n; v += stride)
+    c.out[v] = (int32_t)(rank[minv[c.off + c.lab[v]]] - rank[c.off]);
+}
+
+// The next level of a graph out of the union's aggregation: its rows are db .. db + m - 1
+// and its entries eb .. ee - 1 of (off, idx, w), ids shifted down by db; its degrees K'
+// and the start of its next level (every vertex alone: C = iota, Sigma = K').
+struct OutDesc {
+  int64_t *off;
+  int32_t *idx;
+  uint32_t *w;
+  uint32_t *K, *Sig;
+  int32_t *C;
+  int64_t db, m, eb, ee;
+};
+__global__ void k_step_copy_out(const OutDesc *d, int32_t y0, const int64_t *off, const int32_t *idx,
+                                const uint32_t *w, const uint32_t *K) {
+  const OutDesc o = d[y0 + (int32_t)blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r <= o.m; r += stride) {
+    o.off[r] = off[o.db + r] - o.eb;
+    if (r < o.m) {
+      const uint32_t k = K[o.db + r];
+      o.K[r] = k;
+      o.Sig[r] = k;
+      o.C[r] = (int32_t)r;
+    }
+  }
+  for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < o.ee - o.eb; e += stride) {
+    o.idx[e] = (int32_t)(idx[o.eb + e] - o.db);
+    o.w[e] = w[o.eb + e];
+  }
+}
+
 size_t up(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Per-graph table of the union (one upload): its parts at these byte offsets.
@@ -202,6 +280,8 @@ struct StepEngine::Union {
   unsigned long long *gctr = nullptr, *ctr = nullptr;
   StepResult *res = nullptr;
   uint32_t *lv = nullptr;
+  size_t mark_sched = 0;        // u.a before the schedule (released by batched transitions)
+  std::vector<PackDesc> hd;     // host copy of the graphs' places
   Schedule sch;
   std::vector<StepResult> hres;
 };
@@ -281,8 +361,17 @@ size_t StepEngine::shared_need(int algo, const mgcd_params &p, int64_t count, in
   // the union: rows, entries, per-vertex state, per-graph table, counters, schedule
   size_t un = up((size_t)(N + 1) * 8) + up((size_t)E * 4) * 2 + up((size_t)N * 4) * 5;
   un += TableLayout(count).total + up((size_t)count * 24) + up((size_t)count * sizeof(StepResult)) + 4096;
-  un += schedule_ws_bytes((int32_t)std::min<int64_t>(N, INT32_MAX), E, sched_mode(&p), p.k, L);
-  un += 64 * 1024 + (1u << 20);
+  const int32_t n32 = (int32_t)std::min<int64_t>(N, INT32_MAX);
+  // after the arrays: the schedule, or (LPA, Louvain) the transitions made together in
+  // its place (two renumberings, canonical labels, the aggregated union and its degrees,
+  // small tables)
+  size_t after = schedule_ws_bytes(n32, E, sched_mode(&p), p.k, L);
+  if (algo != MGCD_ALGO_LEIDEN) {
+    size_t b = (size_t)count * 512 + (size_t)N * 96 + (size_t)E * 8 + 2 * scan_ws_bytes(N + 1) + 256 * 1024;
+    if (algo == MGCD_ALGO_LOUVAIN) b += aggregate_ws_bytes(n32, E, agg_mode(&p), p.k_aggregate, L, false);
+    after = std::max(after, b);
+  }
+  un += after + 64 * 1024 + (1u << 20);
   return std::max(un, phase_bytes(algo, p, max_n, max_nnz));
 }
 
@@ -558,7 +647,9 @@ void StepEngine::repack() {
   k_step_last_offset<<<1, 1, 0, st_>>>(off, N, E);
   MGCD_LAUNCHED();
   MGCD_HIP(hipStreamSynchronize(st_));  // the host table may go
+  u.hd = hd;
   u.sch = Schedule{};
+  u.mark_sched = a.mark();
   build_schedule(u.g, sched_params(&p_), u.sch, a, st_);
   u.hres.resize(count);
   u.live = true;
@@ -626,8 +717,15 @@ void StepEngine::step(std::vector<StepJob *> &finished) {
   }
   if (!ended.empty()) {
     ctr_.transitions += (int64_t)ended.size();
-    dissolve();
-    in_lanes(ended, [&](StepJob *j, const Lane &l) { end_level(j, l); });
+    if (algo_ == MGCD_ALGO_LEIDEN) {  // refinement first, graph by graph
+      dissolve();
+      in_lanes(ended, [&](StepJob *j, const Lane &l) { end_level(j, l); });
+    } else {
+      std::vector<int32_t> eg;
+      for (int32_t g = 0; g < u.count; ++g)
+        if (u.hres[(size_t)g].ended) eg.push_back(g);
+      batched_end(eg);
+    }
     for (StepJob *j : ended)
       if (j->done) {
         jobs_.erase(std::find(jobs_.begin(), jobs_.end(), j));
@@ -635,6 +733,197 @@ void StepEngine::step(std::vector<StepJob *> &finished) {
       }
   }
   ctr_.s_phase += host_seconds() - t1;
+}
+
+// Host -> device copy of a small table (the stream is synchronised before it returns,
+// so the host buffer may go).
+template <typename T>
+static T *upload(Arena &a, const std::vector<T> &h, hipStream_t st) {
+  T *d = a.take<T>((int64_t)h.size());
+  if (!h.empty()) {
+    MGCD_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+  }
+  return d;
+}
+
+// src[pos[q]] for the host positions pos, read back to the host.
+static std::vector<int64_t> gather(Arena &a, const int64_t *src, const std::vector<int64_t> &pos,
+                                   hipStream_t st) {
+  std::vector<int64_t> h(pos.size(), 0);
+  if (pos.empty()) return h;
+  const size_t mk = a.mark();
+  const int64_t *pd = upload(a, pos, st);
+  int64_t *od = a.take<int64_t>((int64_t)pos.size());
+  k_step_gather<<<grid_of((int64_t)pos.size()), BLOCK, 0, st>>>(src, pd, od, (int32_t)pos.size());
+  MGCD_LAUNCHED();
+  MGCD_HIP(hipMemcpyAsync(h.data(), od, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  a.release(mk);
+  return h;
+}
+
+// Launch `kernel` with grid y over the table's entries (65,535 at a time) and x over the
+// longest entry's `len` items.
+template <typename D, typename F>
+static void per_graph(const D *dd, int32_t count, int64_t len, hipStream_t st, F &&launch) {
+  for (int32_t y0 = 0; y0 < count; y0 += 65535) {
+    const int32_t ny = std::min<int32_t>(65535, count - y0);
+    dim3 grid((unsigned)std::min<int64_t>(ceil_div(len > 0 ? len : 1, BLOCK), 4096), (unsigned)ny);
+    launch(grid, y0);
+    MGCD_LAUNCHED();
+  }
+  (void)dd;
+}
+
+// The phase transitions of the LPA / Louvain graphs eg (places in the union) whose
+// level ended in the last step, made together while the union's memory is still
+// intact, as run_batched makes them for a batch: every graph's labels and totals go
+// back to its block; Louvain renumbers the ended graphs together, composes their level
+// maps and decides which stop (Section 3.3); the graphs that stop get their canonical
+// labels together; the others are aggregated together, each taking its rows of the
+// aggregated union as its next level.  Each graph's result is that of its own call:
+// renumbering keeps every graph's ids in order, and a community's stream holds only
+// its own graph's rows.
+void StepEngine::batched_end(const std::vector<int32_t> &eg) {
+  Union &u = *u_;
+  const int32_t N = u.g.n;
+  hipStream_t st = st_;
+  if (N > 0) {
+    k_step_unpack<<<grid_of(N), BLOCK, 0, st>>>(u.desc, u.gid, u.C[0], u.Sig, N);
+    MGCD_LAUNCHED();
+  }
+  u.live = false;
+  Arena &a = u.a;  // after the union's arrays (the schedule's memory is reused)
+  a.release(u.mark_sched);
+  const bool lpa = algo_ == MGCD_ALGO_LPA;
+  const int32_t q = (int32_t)eg.size();
+  std::vector<StepJob *> J((size_t)q);
+  for (int32_t i = 0; i < q; ++i) J[(size_t)i] = jobs_[(size_t)eg[(size_t)i]];
+  std::vector<uint8_t> last((size_t)q, 1);
+  std::vector<int64_t> m((size_t)q, 0);
+  if (!lpa) {
+    // renumber the ended graphs together; graph g's communities are db[g] .. db[g] + m[g] - 1
+    std::vector<uint8_t> keep((size_t)u.count, 0);
+    for (int32_t g : eg) keep[(size_t)g] = 1;
+    const uint8_t *keep_d = upload(a, keep, st);
+    int32_t *D1 = a.take<int32_t>(N);
+    int64_t *dense1 = a.take<int64_t>((int64_t)N + 1);
+    renumber(u.C[0], N, D1, a, st, u.gid, keep_d, dense1);
+    std::vector<int64_t> pos(2 * (size_t)q);
+    for (int32_t i = 0; i < q; ++i) {
+      const PackDesc &h = u.hd[(size_t)eg[(size_t)i]];
+      pos[2 * (size_t)i] = h.vbase;
+      pos[2 * (size_t)i + 1] = h.vbase + h.n;
+    }
+    const std::vector<int64_t> db = gather(a, dense1, pos, st);
+    std::vector<ComposeDesc> cd((size_t)q);
+    int64_t n0max = 0;
+    for (int32_t i = 0; i < q; ++i) {
+      StepJob *j = J[(size_t)i];
+      m[(size_t)i] = db[2 * (size_t)i + 1] - db[2 * (size_t)i];
+      last[(size_t)i] = j->pass == p_.max_passes - 1 ||
+                        (double)m[(size_t)i] > p_.aggregation_tolerance * (double)j->cur.n;
+      cd[(size_t)i] = ComposeDesc{j->top, j->g.n, u.hd[(size_t)eg[(size_t)i]].vbase, db[2 * (size_t)i]};
+      n0max = std::max<int64_t>(n0max, j->g.n);
+    }
+    const ComposeDesc *cdd = upload(a, cd, st);
+    per_graph(cdd, q, n0max, st, [&](dim3 grid, int32_t y0) { k_step_compose<<<grid, BLOCK, 0, st>>>(cdd, y0, D1); });
+  }
+  // graphs that stop: canonical labels, all together
+  {
+    std::vector<CanonDesc> fd;
+    std::vector<int32_t> fi;
+    int64_t X = 0, nmax = 0;
+    for (int32_t i = 0; i < q; ++i) {
+      if (!last[(size_t)i]) continue;
+      StepJob *j = J[(size_t)i];
+      fd.push_back(CanonDesc{lpa ? j->C : j->top, j->out, j->g.n, X});
+      fi.push_back(i);
+      X += j->g.n;
+      nmax = std::max<int64_t>(nmax, j->g.n);
+    }
+    if (!fd.empty()) {
+      const size_t mk = a.mark();
+      const int32_t nf = (int32_t)fd.size();
+      const CanonDesc *fdd = upload(a, fd, st);
+      int32_t *minv = a.take<int32_t>(X);
+      uint32_t *first = a.take<uint32_t>(X);
+      int64_t *rank = a.take<int64_t>(X + 1);
+      launch_fill_i32(minv, 0x7FFFFFFF, X, st);
+      per_graph(fdd, nf, nmax, st, [&](dim3 grid, int32_t y0) { k_canon_min<<<grid, BLOCK, 0, st>>>(fdd, y0, minv); });
+      per_graph(fdd, nf, nmax, st,
+                [&](dim3 grid, int32_t y0) { k_canon_first<<<grid, BLOCK, 0, st>>>(fdd, y0, minv, first); });
+      scan_u32_i64(first, rank, X, rank + X, a, st);
+      per_graph(fdd, nf, nmax, st,
+                [&](dim3 grid, int32_t y0) { k_canon_write<<<grid, BLOCK, 0, st>>>(fdd, y0, minv, rank); });
+      std::vector<int64_t> pos((size_t)nf + 1);
+      for (int32_t f = 0; f < nf; ++f) pos[(size_t)f] = fd[(size_t)f].off;
+      pos[(size_t)nf] = X;
+      const std::vector<int64_t> rk = gather(a, rank, pos, st);
+      const double now = host_seconds();
+      for (int32_t f = 0; f < nf; ++f) {
+        StepJob *j = J[(size_t)fi[(size_t)f]];
+        j->stats.communities = (int32_t)(rk[(size_t)f + 1] - rk[(size_t)f]);
+        j->stats.ms_total = (float)((now - j->t_admit) * 1e3);
+        j->done = true;
+      }
+      a.release(mk);
+    }
+  }
+  if (lpa) return;
+  // the others: aggregated together, each graph's rows of the result its next level
+  std::vector<int32_t> ci;
+  for (int32_t i = 0; i < q; ++i)
+    if (!last[(size_t)i]) ci.push_back(i);
+  if (ci.empty()) return;
+  std::vector<uint8_t> keep2((size_t)u.count, 0);
+  for (int32_t i : ci) keep2[(size_t)eg[(size_t)i]] = 1;
+  const uint8_t *keep2_d = upload(a, keep2, st);
+  int32_t *D2 = a.take<int32_t>(N);
+  int64_t *dense2 = a.take<int64_t>((int64_t)N + 1);
+  const int32_t m2 = renumber(u.C[0], N, D2, a, st, u.gid, keep2_d, dense2);
+  std::vector<int64_t> pos(ci.size());
+  for (size_t c = 0; c < ci.size(); ++c) pos[c] = u.hd[(size_t)eg[(size_t)ci[c]]].vbase;
+  const std::vector<int64_t> db2 = gather(a, dense2, pos, st);
+  int64_t *off2 = a.take<int64_t>((int64_t)m2 + 1);
+  int32_t *idx2 = a.take<int32_t>(u.g.nnz);
+  uint32_t *w2 = a.take<uint32_t>(u.g.nnz);
+  aggregate(u.g, D2, m2, agg_mode(&p_), p_.k_aggregate, p_.chunk_len, 0, off2, idx2, w2, a, st);
+  uint32_t *Kn = a.take<uint32_t>(m2);
+  launch_group_sums(D2, u.K, Kn, N, m2, st);
+  std::vector<int64_t> epos(2 * ci.size());
+  for (size_t c = 0; c < ci.size(); ++c) {
+    epos[2 * c] = db2[c];
+    epos[2 * c + 1] = db2[c] + m[(size_t)ci[c]];
+  }
+  const std::vector<int64_t> eb = gather(a, off2, epos, st);
+  std::vector<OutDesc> od(ci.size());
+  int64_t len = 1;
+  for (size_t c = 0; c < ci.size(); ++c) {
+    StepJob *j = J[(size_t)ci[c]];
+    const int qs = j->next_slot;
+    const int64_t mc = m[(size_t)ci[c]];
+    od[c] = OutDesc{j->soff[qs], j->sidx[qs], j->sw[qs], j->K[1 - j->kcur], j->Sig, j->C, db2[c], mc,
+                    eb[2 * c], eb[2 * c + 1]};
+    len = std::max<int64_t>(len, std::max<int64_t>(mc + 1, eb[2 * c + 1] - eb[2 * c]));
+  }
+  const OutDesc *odd = upload(a, od, st);
+  per_graph(odd, (int32_t)od.size(), len, st, [&](dim3 grid, int32_t y0) {
+    k_step_copy_out<<<grid, BLOCK, 0, st>>>(odd, y0, off2, idx2, w2, Kn);
+  });
+  MGCD_HIP(hipStreamSynchronize(st));
+  for (size_t c = 0; c < ci.size(); ++c) {
+    StepJob *j = J[(size_t)ci[c]];
+    const int qs = j->next_slot;
+    j->cur = Graph{(int32_t)m[(size_t)ci[c]], eb[2 * c + 1] - eb[2 * c], j->soff[qs], j->sidx[qs], j->sw[qs]};
+    j->next_slot = 1 - qs;
+    j->kcur = 1 - j->kcur;
+    j->tol /= p_.tolerance_drop;
+    j->pass += 1;
+    j->stats.passes += 1;  // the next level (its labels and totals are set: C = iota, Sigma = K)
+    j->it = 0;
+  }
 }
 
 void StepEngine::fail_all(int code, const std::string &msg, std::vector<StepJob *> &finished) {

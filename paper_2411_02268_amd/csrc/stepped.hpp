@@ -93,6 +93,7 @@ class StepEngine {
   };
   void dissolve();
   void repack();
+  void batched_end(const std::vector<int32_t> &eg);
   template <typename F>
   void in_lanes(const std::vector<StepJob *> &js, F &&f);
   bool prepare(StepJob *j, const Lane &l);

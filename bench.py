@@ -331,7 +331,7 @@ def main():
     ap.add_argument("--exact-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=None,
-                    help="requests of the serving leg (0 skips it; default 1000 with the "
+                    help="requests of the serving leg (0 skips it; default 2000 with the "
                          "default workload, else 0)")
     ap.add_argument("--serve-slots", type=int, default=4, help="worker streams of the whole-call server")
     ap.add_argument("--serve-resident", type=int, default=64,
@@ -364,7 +364,7 @@ def main():
         sys.exit(2)
     default = args.workload == DEFAULT_WORKLOAD
     if args.serve_requests is None:
-        args.serve_requests = 1000 if default else 0
+        args.serve_requests = 2000 if default else 0
     if args.batch_graphs is None:
         args.batch_graphs = 4096 if default else 0
 

@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 # run time); traffic is reported as null when the sources differ.
 TRAFFIC_BYTES = {
     ("louvain-mg-k8-rmat20", False, 0): (2381066085, "4b706a6b193f31b23af55e7f9a8caa32620a8e9214b829d003303eae3640857e"),
-    ("leiden-mg-k16-cl24", False, 0): (106706025376, "cc52825819b5cf5515cca2cdf18ce3e9dec6b31a7d82fb397b87a63e05b477cf"),
-    ("leiden-mg-k16-cl24", True, 0): (80207006440, "cc52825819b5cf5515cca2cdf18ce3e9dec6b31a7d82fb397b87a63e05b477cf"),
+    ("leiden-mg-k16-cl24", False, 0): (106669676216, "4b706a6b193f31b23af55e7f9a8caa32620a8e9214b829d003303eae3640857e"),
+    ("leiden-mg-k16-cl24", True, 0): (80185205416, "4b706a6b193f31b23af55e7f9a8caa32620a8e9214b829d003303eae3640857e"),
 }
 TRAFFIC_SOURCES = ["csrc/move.hip", "csrc/move.hpp", "csrc/sketch.hpp", "csrc/common.hpp", "csrc/staging.hpp"]
 

@@ -350,12 +350,13 @@ int mgcd_server_create_stepped(void *arena, size_t arena_bytes, size_t shared_by
  * transitions; rows_swept = union rows summed over the sweeps in which some graph
  * moved and rows_moving = the rows of the graphs that moved in them (their ratio is
  * the share of swept rows that were not frozen); seconds spent packing unions and
- * building their schedules, in sweeps and their read-back, and in phase work
- * (admissions, transitions, final labels).  Counters since creation. */
+ * building their schedules, in sweeps and their read-back, in phase transitions
+ * (with final labels) and in admissions.  Counters since creation, summed over the
+ * server's engines. */
 typedef struct {
   int64_t steps, sweeps, sweeps_moving, packs, transitions;
   int64_t rows_swept, rows_moving;
-  double s_pack, s_sweep, s_phase;
+  double s_pack, s_sweep, s_phase, s_admit;
 } mgcd_step_stats;
 int mgcd_server_step_stats(mgcd_server *s, mgcd_step_stats *out);
 

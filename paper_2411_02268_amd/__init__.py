@@ -70,7 +70,7 @@ class GraphStats(ct.Structure):
 class StepStats(ct.Structure):
     _fields_ = [(f, ct.c_int64) for f in ("steps", "sweeps", "sweeps_moving", "packs", "transitions",
                                           "rows_swept", "rows_moving")] + \
-               [(f, ct.c_double) for f in ("s_pack", "s_sweep", "s_phase")]
+               [(f, ct.c_double) for f in ("s_pack", "s_sweep", "s_phase", "s_admit")]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

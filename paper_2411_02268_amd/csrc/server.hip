@@ -474,6 +474,7 @@ int mgcd_server_step_stats(mgcd_server *s, mgcd_step_stats *out) {
     t.s_pack += E.stats.s_pack;
     t.s_sweep += E.stats.s_sweep;
     t.s_phase += E.stats.s_phase;
+    t.s_admit += E.stats.s_admit;
   }
   *out = t;
   return MGCD_OK;

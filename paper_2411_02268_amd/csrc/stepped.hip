@@ -234,6 +234,24 @@ __global__ void k_step_copy_out(const OutDesc *d, int32_t y0, const int64_t *off
   }
 }
 
+// Level 0 of admitted graphs: every vertex alone (C = iota, top = iota) and the
+// community totals of that membership (Sigma = K).
+struct StartDesc {
+  int32_t *C, *top;  // top: null for LPA
+  uint32_t *Sig;     // null for LPA
+  const uint32_t *K;
+  int64_t n;
+};
+__global__ void k_admit_start(const StartDesc *d, int32_t y0) {
+  const StartDesc s = d[y0 + (int32_t)blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < s.n; v += stride) {
+    s.C[v] = (int32_t)v;
+    if (s.top) s.top[v] = (int32_t)v;
+    if (s.Sig) s.Sig[v] = s.K[v];
+  }
+}
+
 size_t up(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Per-graph table of the union (one upload): its parts at these byte offsets.
@@ -461,6 +479,47 @@ bool StepEngine::prepare(StepJob *j, const Lane &l) {
   return true;
 }
 
+// Host -> device copy of a small table (the stream is synchronised before it returns,
+// so the host buffer may go).
+template <typename T>
+static T *upload(Arena &a, const std::vector<T> &h, hipStream_t st) {
+  T *d = a.take<T>((int64_t)h.size());
+  if (!h.empty()) {
+    MGCD_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    MGCD_HIP(hipStreamSynchronize(st));
+  }
+  return d;
+}
+
+// src[pos[q]] for the host positions pos, read back to the host.
+static std::vector<int64_t> gather(Arena &a, const int64_t *src, const std::vector<int64_t> &pos,
+                                   hipStream_t st) {
+  std::vector<int64_t> h(pos.size(), 0);
+  if (pos.empty()) return h;
+  const size_t mk = a.mark();
+  const int64_t *pd = upload(a, pos, st);
+  int64_t *od = a.take<int64_t>((int64_t)pos.size());
+  k_step_gather<<<grid_of((int64_t)pos.size()), BLOCK, 0, st>>>(src, pd, od, (int32_t)pos.size());
+  MGCD_LAUNCHED();
+  MGCD_HIP(hipMemcpyAsync(h.data(), od, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  a.release(mk);
+  return h;
+}
+
+// Launch `kernel` with grid y over the table's entries (65,535 at a time) and x over the
+// longest entry's `len` items.
+template <typename D, typename F>
+static void per_graph(const D *dd, int32_t count, int64_t len, hipStream_t st, F &&launch) {
+  for (int32_t y0 = 0; y0 < count; y0 += 65535) {
+    const int32_t ny = std::min<int32_t>(65535, count - y0);
+    dim3 grid((unsigned)std::min<int64_t>(ceil_div(len > 0 ? len : 1, BLOCK), 4096), (unsigned)ny);
+    launch(grid, y0);
+    MGCD_LAUNCHED();
+  }
+  (void)dd;
+}
+
 void StepEngine::admit(const std::vector<StepJob *> &js, std::vector<StepJob *> &finished) {
   if (js.empty()) return;
   dissolve();
@@ -473,9 +532,12 @@ void StepEngine::admit(const std::vector<StepJob *> &js, std::vector<StepJob *> 
     j->cur = Graph{};
   }
   try {
-    in_lanes(js, [&](StepJob *j, const Lane &l) { prepare(j, l); });
+    if (p_.validate)  // each graph checked before anything reads its rows
+      in_lanes(js, [&](StepJob *j, const Lane &l) { prepare(j, l); });
+    else
+      admit_together(js);
   } catch (...) {
-    ctr_.s_phase += host_seconds() - t0;
+    ctr_.s_admit += host_seconds() - t0;
     throw;
   }
   for (StepJob *j : js) {  // in arrival order
@@ -484,7 +546,79 @@ void StepEngine::admit(const std::vector<StepJob *> &js, std::vector<StepJob *> 
     else
       jobs_.push_back(j);
   }
-  ctr_.s_phase += host_seconds() - t0;
+  ctr_.s_admit += host_seconds() - t0;
+}
+
+// Admission of many graphs without validation: every graph's degrees and W issued on
+// the main stream one after the other with no host round trip between them, the W
+// read back once, then every level 0 started by one launch.  A graph whose W does not
+// fit 32 bits finishes with MGCD_E_OVERFLOW.
+void StepEngine::admit_together(const std::vector<StepJob *> &js) {
+  hipStream_t st = st_;
+  Arena a = Lane{st, shared_, shared_bytes_}.arena();
+  std::vector<StepJob *> ok;
+  for (StepJob *j : js) {
+    const mgcd_csr &c = j->g;
+    try {
+      if (c.n < 0 || c.nnz < 0) throw Error(MGCD_E_ARG, "negative graph size");
+      if (c.n > 0 && (!c.offsets || !j->out)) throw Error(MGCD_E_ARG, "offsets or communities_out is null");
+      if (c.nnz > 0 && (!c.indices || !c.weights)) throw Error(MGCD_E_ARG, "indices/weights null");
+      if ((((uintptr_t)c.indices) | ((uintptr_t)c.weights)) & 15)
+        throw Error(MGCD_E_ARG, "indices and weights must be 16-byte aligned");
+    } catch (const Error &e) {
+      j->rc = e.code;
+      j->err = e.what();
+      j->done = true;
+      continue;
+    }
+    if (c.n == 0) {  // nothing to move: the call's own result
+      j->stats.passes = algo_ == MGCD_ALGO_LPA ? 1 : 0;
+      j->done = true;
+      continue;
+    }
+    Arena b;
+    b.base = j->block;
+    b.cap = block_bytes(algo_, p_, c.n, c.nnz);
+    block_layout(algo_, j, b);
+    ok.push_back(j);
+  }
+  if (ok.empty()) return;
+  unsigned long long *Wd = a.take<unsigned long long>((int64_t)ok.size());
+  for (size_t q = 0; q < ok.size(); ++q) {
+    const mgcd_csr &c = ok[q]->g;
+    launch_degrees(Graph{c.n, c.nnz, c.offsets, c.indices, c.weights}, ok[q]->K[0], Wd + q, a, st);
+  }
+  std::vector<unsigned long long> W(ok.size());
+  MGCD_HIP(hipMemcpyAsync(W.data(), Wd, W.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  MGCD_HIP(hipStreamSynchronize(st));
+  std::vector<StartDesc> sd;
+  int64_t nmax = 1;
+  for (size_t q = 0; q < ok.size(); ++q) {
+    StepJob *j = ok[q];
+    if (W[q] >= (1ull << 31)) {
+      j->rc = MGCD_E_OVERFLOW;
+      j->err = "total edge weight must be below 2^31";
+      j->done = true;
+      continue;
+    }
+    const mgcd_csr &c = j->g;
+    j->W = W[q];
+    j->cur = Graph{c.n, c.nnz, c.offsets, c.indices, c.weights};
+    j->kcur = 0;
+    j->next_slot = 0;
+    j->pass = 0;
+    j->tol = p_.tolerance;
+    j->stats.passes += 1;  // level 0
+    j->it = 0;
+    const bool lpa = algo_ == MGCD_ALGO_LPA;
+    sd.push_back(StartDesc{j->C, lpa ? nullptr : j->top, lpa ? nullptr : j->Sig, j->K[0], (int64_t)c.n});
+    nmax = std::max<int64_t>(nmax, c.n);
+  }
+  if (sd.empty()) return;
+  const StartDesc *sdd = upload(a, sd, st);
+  per_graph(sdd, (int32_t)sd.size(), nmax, st,
+            [&](dim3 grid, int32_t y0) { k_admit_start<<<grid, BLOCK, 0, st>>>(sdd, y0); });
+  MGCD_HIP(hipStreamSynchronize(st));  // the table's host copy and the blocks are ready
 }
 
 // A level starts: labels (every vertex alone, or Leiden's carried-over start) and their
@@ -733,47 +867,6 @@ void StepEngine::step(std::vector<StepJob *> &finished) {
       }
   }
   ctr_.s_phase += host_seconds() - t1;
-}
-
-// Host -> device copy of a small table (the stream is synchronised before it returns,
-// so the host buffer may go).
-template <typename T>
-static T *upload(Arena &a, const std::vector<T> &h, hipStream_t st) {
-  T *d = a.take<T>((int64_t)h.size());
-  if (!h.empty()) {
-    MGCD_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
-    MGCD_HIP(hipStreamSynchronize(st));
-  }
-  return d;
-}
-
-// src[pos[q]] for the host positions pos, read back to the host.
-static std::vector<int64_t> gather(Arena &a, const int64_t *src, const std::vector<int64_t> &pos,
-                                   hipStream_t st) {
-  std::vector<int64_t> h(pos.size(), 0);
-  if (pos.empty()) return h;
-  const size_t mk = a.mark();
-  const int64_t *pd = upload(a, pos, st);
-  int64_t *od = a.take<int64_t>((int64_t)pos.size());
-  k_step_gather<<<grid_of((int64_t)pos.size()), BLOCK, 0, st>>>(src, pd, od, (int32_t)pos.size());
-  MGCD_LAUNCHED();
-  MGCD_HIP(hipMemcpyAsync(h.data(), od, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  MGCD_HIP(hipStreamSynchronize(st));
-  a.release(mk);
-  return h;
-}
-
-// Launch `kernel` with grid y over the table's entries (65,535 at a time) and x over the
-// longest entry's `len` items.
-template <typename D, typename F>
-static void per_graph(const D *dd, int32_t count, int64_t len, hipStream_t st, F &&launch) {
-  for (int32_t y0 = 0; y0 < count; y0 += 65535) {
-    const int32_t ny = std::min<int32_t>(65535, count - y0);
-    dim3 grid((unsigned)std::min<int64_t>(ceil_div(len > 0 ? len : 1, BLOCK), 4096), (unsigned)ny);
-    launch(grid, y0);
-    MGCD_LAUNCHED();
-  }
-  (void)dd;
 }
 
 // The phase transitions of the LPA / Louvain graphs eg (places in the union) whose

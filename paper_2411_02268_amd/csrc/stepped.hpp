@@ -97,6 +97,7 @@ class StepEngine {
   template <typename F>
   void in_lanes(const std::vector<StepJob *> &js, F &&f);
   bool prepare(StepJob *j, const Lane &l);
+  void admit_together(const std::vector<StepJob *> &js);
   void enter_level(StepJob *j, bool reset, const Lane &l);
   void end_level(StepJob *j, const Lane &l);
   void finish(StepJob *j, const int32_t *labels, const Lane &l);

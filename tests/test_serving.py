@@ -251,7 +251,7 @@ def test_stepped_step_stats(mg, pool):
     assert c["sweeps"] == 3 * c["steps"] and c["sweeps_moving"] <= c["sweeps"]
     assert 0 < c["rows_moving"] <= c["rows_swept"]
     assert c["transitions"] == passes  # every level of every request ends once
-    assert min(c["s_pack"], c["s_sweep"], c["s_phase"]) >= 0.0
+    assert min(c["s_pack"], c["s_sweep"], c["s_phase"], c["s_admit"]) >= 0.0 and c["s_admit"] > 0.0
     with mg.Server(mg.ALGO_LOUVAIN, 1 << 28, slots=2) as srv:
         assert all(v == 0 for v in srv.step_stats().values())
 

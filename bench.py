@@ -55,11 +55,12 @@ def sources_sha256() -> str:
     return h.hexdigest()
 
 
-def class_bytes(g, L: int, k: int, cands: float = 0.0, short: int = 0):
+def class_bytes(g, L: int, k: int, cands: float = 0.0, short: int = 0, label: int = 4):
     """Algorithmic bytes of one level-0 MG sweep per kernel class (reads and writes
     the method must make; a second pass over a row of at most 64 chunks counts as
     on-chip, a second pass over a longer row re-reads its keys and weights):
-      per CSR entry 12 B (index 4, weight 4, gathered C[j] 4);
+      per CSR entry 12 B (index 4, weight 4, gathered C[j] 4; `label` = 0 for the
+      first sweep from singletons, where C[j] = j is not read);
       per decided vertex 28 B (list 4, offsets 8, C 4, C_new 4, K 4, Sigma_d 4);
       per candidate community c != d scored by class 0, 4 B (its total Sigma_c;
       `cands` = candidates per launch, counted on the device);
@@ -75,9 +76,10 @@ def class_bytes(g, L: int, k: int, cands: float = 0.0, short: int = 0):
     big = nch > 64
     sh = (deg >= 1) & (deg <= short)
     groups = int(((nch[big] + 63) // 64).sum())
-    c0 = 12 * int(deg[~sh].sum()) + 28 * int((~sh).sum()) + (8 * k + 4) * groups + int(round(4 * cands))
+    per_entry = 8 + label
+    c0 = per_entry * int(deg[~sh].sum()) + 28 * int((~sh).sum()) + (8 * k + 4) * groups + int(round(4 * cands))
     c1 = (8 * k + 4) * groups + 8 * int(deg[big].sum()) + 2 * 4 * (k + 1) * int(nch[big].sum())
-    c2 = 12 * int(deg[sh].sum()) + 28 * int(sh.sum())
+    c2 = per_entry * int(deg[sh].sum()) + 28 * int(sh.sum())
     return [c0, c1, c2]
 
 
@@ -415,6 +417,13 @@ def main():
     # MG Algorithm 1 here: rows of at most k entries on the exact kernel (level 0)
     short = k if (k <= 16 and (args.short_rows == 2 or (args.short_rows == 0 and g.nnz <= k * g.n))) else 0
     cb = class_bytes(g, L, k, cands, short)
+    used_copy = args.storage_order == 2 or (args.storage_order == 0 and g.nnz >= (1 << 26))
+    if not used_copy:
+        # the first level-0 sweep of every run starts from singletons and reads no
+        # labels: average the bytes over the same launches as the time
+        per_run = sweeps / max(len(stats), 1)
+        cb1 = class_bytes(g, L, k, cands, short, label=0)
+        cb = [int(round((c1 + (per_run - 1) * c) / per_run)) for c1, c in zip(cb1, cb)]
     dom = int(np.argmax(ms))
     names = ["k_move_rows (every row of more than k entries: staged sketch, merge tree, second "
              "pass, decision; chunk sketches of rows longer than 64 chunks)",
@@ -519,7 +528,6 @@ def main():
               file=sys.stderr, flush=True)
 
     traffic = None
-    used_copy = args.storage_order == 2 or (args.storage_order == 0 and g.nnz >= (1 << 26))
     known = TRAFFIC_BYTES.get((args.workload, used_copy, args.short_rows))
     if dom == 0 and known and sources_sha256() == known[1]:
         traffic = known[0]

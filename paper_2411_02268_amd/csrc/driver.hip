@@ -209,10 +209,11 @@ static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Are
   launch_zero_u64(ctr, 4, st);
   launch_zero_state(ls, st);
   if (n > 0) {
-    LevelState h = run_sweeps(p->max_iterations, ls, st, &ct, s, [&](int, int j) {
+    LevelState h = run_sweeps(p->max_iterations, ls, st, &ct, s, [&](int it, int j) {
       SweepArgs args{gs, Ca, nullptr, Ks, nullptr, 0, 0, Cb, nullptr, ctr};
       args.halt = &ls->halt;
       args.one_scan = p->one_scan;
+      args.ident = !sto && it == 0;  // every vertex starts alone (on the copy: C = perm)
       launch_sweep(args, sch, ALGO_LPA, p->mode, p->k, p->chunk_len, st, ct.ev[j]);
       launch_level_converge(ALGO_LPA, LevelRule{ctr, ls, g.nnz, n, p->tolerance, 0.0}, st);
       std::swap(Ca, Cb);  // a halted sweep copies C, so either buffer holds the result
@@ -306,6 +307,9 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
     LevelState h = run_sweeps(p->max_iterations, ls, st, pass == 0 ? &ct : nullptr, s, [&](int it, int j) {
       SweepArgs args{gm, Ca, nullptr, Km, Sig, W, (it % 2 == 0) ? -1 : 1, Cb, nullptr, ctr};
       args.halt = &ls->halt;
+      // a level starts from singletons (Leiden after its first: from the refined
+      // partition's communities); on the copy C holds perm, not positions
+      args.ident = !sto && it == 0 && (!leiden || pass == 0);
       launch_sweep(args, sch, ALGO_MOVE, p->mode, p->k, p->chunk_len, st, pass == 0 ? ct.ev[j] : nullptr);
       // a sweep without positive moves, or a halted one, leaves C_new equal to C; the
       // same launch applies the stopping rule to this sweep's counters

@@ -180,7 +180,25 @@ template <int ALGO>
 __device__ inline uint32_t stream_key(const SweepArgs &a, int32_t i, int32_t j, int32_t bi) {
   if (j == i) return EMPTY;
   if (ALGO == ALGO_REFINE) return a.bound[j] == bi ? (uint32_t)j : EMPTY;
-  return (uint32_t)a.C[j];
+  return a.ident ? (uint32_t)j : (uint32_t)a.C[j];
+}
+
+// Keys of U neighbours j (any valid ids): their communities C[j], or j itself when C is
+// the identity; refinement keys are j when it shares the row's bound b[u], else EMPTY.
+// One wave-uniform branch around all U reads keeps them in flight together.
+template <int ALGO, int U>
+__device__ inline void neighbour_keys(const SweepArgs &a, const int32_t (&j)[U], const int32_t (&b)[U],
+                                      uint32_t (&c)[U]) {
+  if (ALGO == ALGO_REFINE) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = a.bound[j[u]] == b[u] ? (uint32_t)j[u] : EMPTY;
+  } else if (a.ident) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = (uint32_t)j[u];
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = (uint32_t)a.C[j[u]];
+  }
 }
 
 // ---- MG: long rows -----------------------------------------------------------------
@@ -213,22 +231,24 @@ __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i
       ww[r] = __builtin_nontemporal_load(a.g.w + es);
     }
     {
+      int32_t jj[G], bb[G];
+      uint32_t c[G];
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const int src = (g0 + r) * SPR + lane / WIN;
+        jj[r] = ((ok >> r) & 1u) ? (int32_t)kk[r] : 0;
+        bb[r] = ALGO == ALGO_REFINE ? __shfl(bi, src) : 0;
+      }
+      neighbour_keys<ALGO, G>(a, jj, bb, c);
 #pragma unroll
       for (int r = 0; r < G; ++r) {
         const int src = (g0 + r) * SPR + lane / WIN;
         const int32_t ii = __shfl(i, src);
-        const int32_t bb = __shfl(bi, src);
         const bool v = (ok >> r) & 1u;
-        const int32_t j = v ? (int32_t)kk[r] : 0;
-        uint32_t c;
-        if (ALGO == ALGO_REFINE)
-          c = a.bound[j] == bb ? (uint32_t)j : EMPTY;
-        else
-          c = (uint32_t)a.C[j];
         // self-loops are skipped.  The gathered value is used on every lane (OR with
         // an all-ones mask instead of a select), so the compiler keeps the gathers of
         // all rounds in flight instead of sinking each into a branch of its own.
-        kk[r] = c | ((v && j != ii) ? 0u : EMPTY);
+        kk[r] = c[r] | ((v && jj[r] != ii) ? 0u : EMPTY);
       }
 #pragma unroll
       for (int r = 0; r < G; ++r) {
@@ -999,20 +1019,19 @@ __device__ inline void exact_row_regs(const SweepArgs &a, int32_t i, int32_t bi,
   // its value masked afterwards, so the loads and gathers of all positions are in
   // flight together.
   uint32_t ks[ES], ws[ES];
+  int32_t js[ES], bs[ES];
   const int64_t safe = hi > lo ? lo : 0;
 #pragma unroll
   for (int t = 0; t < ES; ++t) {
     const bool v = lo + t < hi;
     const int64_t e = v ? lo + t : safe;
-    const int32_t j = a.g.idx[e];
+    js[t] = a.g.idx[e];
+    bs[t] = bi;
     ws[t] = a.g.w[e] & (v ? ~0u : 0u);
-    uint32_t c;
-    if (ALGO == ALGO_REFINE)
-      c = a.bound[j] == bi ? (uint32_t)j : EMPTY;
-    else
-      c = (uint32_t)a.C[j];
-    ks[t] = c | ((v && j != i) ? 0u : EMPTY);  // self-loops are skipped
   }
+  neighbour_keys<ALGO, ES>(a, js, bs, ks);
+#pragma unroll
+  for (int t = 0; t < ES; ++t) ks[t] |= (lo + t < hi && js[t] != i) ? 0u : EMPTY;  // self-loops are skipped
   // table keys: the keys themselves, or their slots in the small table (a slot's
   // first key stands for it, K_{i->d} is the sum in d's slot)
   uint32_t ss[ES];
@@ -1244,20 +1263,20 @@ __global__ void __launch_bounds__(BLOCK) k_exact_table(SweepArgs a, const int32_
   constexpr int U = 4;
   for (int64_t e0 = lo + t; e0 < hi; e0 += U * BLOCK) {
     uint32_t cs[U], ws[U];
+    int32_t js[U], bs[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = e0 + (int64_t)u * BLOCK;
       const bool v = e < hi;
       const int64_t es = v ? e : lo;
-      const int32_t j = a.g.idx[es];
-      uint32_t c;
-      if (ALGO == ALGO_REFINE)
-        c = a.bound[j] == bi ? (uint32_t)j : EMPTY;
-      else
-        c = (uint32_t)a.C[j];
-      cs[u] = c | ((v && j != i) ? 0u : EMPTY);  // self-loops are skipped
+      js[u] = a.g.idx[es];
+      bs[u] = bi;
       ws[u] = a.g.w[es];
     }
+    neighbour_keys<ALGO, U>(a, js, bs, cs);
+#pragma unroll
+    for (int u = 0; u < U; ++u)  // self-loops are skipped
+      cs[u] |= ((e0 + (int64_t)u * BLOCK) < hi && js[u] != i) ? 0u : EMPTY;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (cs[u] == EMPTY) continue;
@@ -1366,20 +1385,20 @@ __global__ void __launch_bounds__(BLOCK)
     }
     __syncthreads();
     uint32_t cs[U], ws[U];
+    int32_t js[U], bs[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = b0 + t + (int64_t)u * BLOCK;
       const bool v = e < hi;
       const int64_t es = v ? e : lo;
-      const int32_t j = a.g.idx[es];
-      uint32_t c;
-      if (ALGO == ALGO_REFINE)
-        c = a.bound[j] == bi ? (uint32_t)j : EMPTY;
-      else
-        c = (uint32_t)a.C[j];
-      cs[u] = c | ((v && j != i) ? 0u : EMPTY);  // self-loops are skipped
+      js[u] = a.g.idx[es];
+      bs[u] = bi;
       ws[u] = a.g.w[es];
     }
+    neighbour_keys<ALGO, U>(a, js, bs, cs);
+#pragma unroll
+    for (int u = 0; u < U; ++u)  // self-loops are skipped
+      cs[u] |= ((b0 + t + (int64_t)u * BLOCK) < hi && js[u] != i) ? 0u : EMPTY;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (cs[u] == EMPTY) continue;

@@ -43,6 +43,10 @@ struct SweepArgs {
   // table; S > 0 = key c counts in slot c mod S, whose first key (in stream order)
   // stands for every key that lands there.
   int32_t small_slots = 0;
+  // C is the identity (every vertex alone, C[j] = j: the first sweep of a level that
+  // starts from singletons): the kernels may take a neighbour's community as j without
+  // reading C, which must still hold the identity.
+  int32_t ident = 0;
 };
 
 // The table key of community (or vertex) c: itself, or its slot in the small table.

@@ -646,8 +646,7 @@ __device__ __attribute__((always_inline)) inline void row_work(const SweepArgs &
 // take the row buckets.
 template <int K, int ALGO, int MODE, bool PERSIST>
 __global__ void __launch_bounds__(BLOCK) MGCD_ROWS_OCCUPANCY(K)
-    k_move_rows(SweepArgs a, const Buckets *__restrict__ bkp, int64_t L, uint32_t *keybuf) {
-  const Buckets &bk = *bkp;
+    k_move_rows(SweepArgs a, const Buckets bk, int64_t L, uint32_t *keybuf) {
   __shared__ __attribute__((aligned(16))) uint32_t swin[BLOCK / WAVE][WAVE * WROW];
   uint32_t *const win = swin[threadIdx.x / WAVE];
   if constexpr (!PERSIST) {
@@ -1873,9 +1872,7 @@ void build_schedule(const Graph &g, const SchedParams &sp_in, Schedule &s, Arena
     bk.cstart = s.cstart;
     bk.sk = s.sk;
     bk.skflag = s.skflag;
-    s.buckets = a.take<Buckets>(1);
-    MGCD_HIP(hipMemcpyAsync(s.buckets, &bk, sizeof(bk), hipMemcpyHostToDevice, st));
-    MGCD_HIP(hipStreamSynchronize(st));
+    s.buckets = bk;  // a kernel argument: no upload, no host round trip
   }
 }
 

@@ -120,7 +120,7 @@ struct Schedule {
   int32_t *owner = nullptr;   // [nchunks] multi index of each chunk
   int64_t nchunks = 0;
   int64_t maxdeg = 0;          // longest row
-  Buckets *buckets = nullptr; // device copy of the bucket table
+  Buckets buckets{};           // bucket table of k_move_rows (passed by value)
   int64_t row_waves = 0;
   uint32_t *keybuf = nullptr; // [nnz] keys C[j] gathered in pass 1, read by pass 2
   int64_t *gstart = nullptr;  // [nmulti+1] first group of 64 chunks of each multi vertex

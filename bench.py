@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 # kernel sources it was taken on (the SHA-256 of TRAFFIC_SOURCES beside it, checked at
 # run time); traffic is reported as null when the sources differ.
 TRAFFIC_BYTES = {
-    ("louvain-mg-k8-rmat20", False, 0): (2381066085, "4b706a6b193f31b23af55e7f9a8caa32620a8e9214b829d003303eae3640857e"),
+    ("louvain-mg-k8-rmat20", False, 0): (2276541846, "5bdb13cc73e48bbb5a6ea0300256941c811d3b5407d5984c946236529686d6a1"),
     ("leiden-mg-k16-cl24", False, 0): (106669676216, "4b706a6b193f31b23af55e7f9a8caa32620a8e9214b829d003303eae3640857e"),
     ("leiden-mg-k16-cl24", True, 0): (80185205416, "4b706a6b193f31b23af55e7f9a8caa32620a8e9214b829d003303eae3640857e"),
 }

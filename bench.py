@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 # run time); traffic is reported as null when the sources differ.
 TRAFFIC_BYTES = {
     ("louvain-mg-k8-rmat20", False, 0): (2276541846, "5bdb13cc73e48bbb5a6ea0300256941c811d3b5407d5984c946236529686d6a1"),
-    ("leiden-mg-k16-cl24", False, 0): (106669676216, "4b706a6b193f31b23af55e7f9a8caa32620a8e9214b829d003303eae3640857e"),
-    ("leiden-mg-k16-cl24", True, 0): (80185205416, "4b706a6b193f31b23af55e7f9a8caa32620a8e9214b829d003303eae3640857e"),
+    ("leiden-mg-k16-cl24", False, 0): (91133474248, "5bdb13cc73e48bbb5a6ea0300256941c811d3b5407d5984c946236529686d6a1"),
+    ("leiden-mg-k16-cl24", True, 0): (80246333624, "5bdb13cc73e48bbb5a6ea0300256941c811d3b5407d5984c946236529686d6a1"),
 }
 TRAFFIC_SOURCES = ["csrc/move.hip", "csrc/move.hpp", "csrc/sketch.hpp", "csrc/common.hpp", "csrc/staging.hpp"]
 

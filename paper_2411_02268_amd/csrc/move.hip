@@ -206,8 +206,13 @@ __device__ inline void neighbour_keys(const SweepArgs &a, const int32_t (&j)[U],
 // Stage positions s0 .. s0+WIN-1 of every lane's chunk [clo, chi) of row i into the
 // wave's LDS window (staging.hpp).  GATHER: the keys are C[j] (with Algorithm 1's
 // skips), gathered with the loads of 8 rounds in flight, and are also written to the
-// key stream; otherwise they are read from the key stream.
-template <int ALGO, bool GATHER>
+// key stream; otherwise they are read from the key stream.  FUSED: each round reads its
+// labels in its own step and ignores a.ident (the persistent batched kernel, whose
+// graphs never start a sweep from the identity: measured 6 % faster there); otherwise
+// the label reads of a group sit behind one branch on a.ident (the single-graph kernel,
+// where this form also needs fewer registers: four waves per SIMD at k = 8 instead of
+// three).
+template <int ALGO, bool GATHER, bool FUSED = false>
 __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i, int32_t bi,
                                     int64_t clo, int64_t chi, int64_t s0, uint32_t *keybuf) {
   if constexpr (!GATHER) {
@@ -230,7 +235,25 @@ __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i
       kk[r] = (uint32_t)__builtin_nontemporal_load(a.g.idx + es);
       ww[r] = __builtin_nontemporal_load(a.g.w + es);
     }
-    {
+    if constexpr (FUSED) {
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const int src = (g0 + r) * SPR + lane / WIN;
+        const int32_t ii = __shfl(i, src);
+        const int32_t bb = __shfl(bi, src);
+        const bool v = (ok >> r) & 1u;
+        const int32_t j = v ? (int32_t)kk[r] : 0;
+        uint32_t c;
+        if (ALGO == ALGO_REFINE)
+          c = a.bound[j] == bb ? (uint32_t)j : EMPTY;
+        else
+          c = (uint32_t)a.C[j];
+        // self-loops are skipped.  The gathered value is used on every lane (OR with
+        // an all-ones mask instead of a select), so the compiler keeps the gathers of
+        // all rounds in flight instead of sinking each into a branch of its own.
+        kk[r] = c | ((v && j != ii) ? 0u : EMPTY);
+      }
+    } else {
       int32_t jj[G], bb[G];
       uint32_t c[G];
 #pragma unroll
@@ -245,11 +268,10 @@ __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i
         const int src = (g0 + r) * SPR + lane / WIN;
         const int32_t ii = __shfl(i, src);
         const bool v = (ok >> r) & 1u;
-        // self-loops are skipped.  The gathered value is used on every lane (OR with
-        // an all-ones mask instead of a select), so the compiler keeps the gathers of
-        // all rounds in flight instead of sinking each into a branch of its own.
-        kk[r] = c[r] | ((v && jj[r] != ii) ? 0u : EMPTY);
+        kk[r] = c[r] | ((v && jj[r] != ii) ? 0u : EMPTY);  // self-loops are skipped
       }
+    }
+    {
 #pragma unroll
       for (int r = 0; r < G; ++r) {
         const int src = (g0 + r) * SPR + lane / WIN;
@@ -269,7 +291,7 @@ __device__ inline void stage_window(const SweepArgs &a, uint32_t *win, int32_t i
 // by stage_window, then every lane folds its own 16 staged entries into its VGPR
 // sketch.  Every lane of the wave must call this; an idle lane passes an empty
 // chunk.
-template <int K, int ALGO, int MODE, bool GATHER = true>
+template <int K, int ALGO, int MODE, bool GATHER = true, bool FUSED = false>
 __device__ inline void staged_sketch(const SweepArgs &a, RegSketch<K, MODE> &s, uint32_t *win,
                                      int32_t i, int32_t bi, int64_t clo, int64_t chi,
                                      uint32_t *keybuf) {
@@ -280,7 +302,7 @@ __device__ inline void staged_sketch(const SweepArgs &a, RegSketch<K, MODE> &s, 
     maxlen = x > maxlen ? x : maxlen;
   }
   for (int64_t s0 = 0; s0 < maxlen; s0 += WIN) {
-    stage_window<ALGO, GATHER>(a, win, i, bi, clo, chi, s0, keybuf);
+    stage_window<ALGO, GATHER, FUSED>(a, win, i, bi, clo, chi, s0, keybuf);
     wave_sync();
     uint32_t kk[WIN], ww[WIN];
     read_window(win, kk, ww);
@@ -326,7 +348,7 @@ __device__ inline LongChunk long_chunk(const SweepArgs &a, const int32_t *multi,
 // = chunk within the group): Algorithm 1 over the staged entries (keys gathered
 // and written to the key stream), then the first six levels of the fixed merge
 // tree with cross-lane shuffles; lane 0 writes the group's root.
-template <int K, int ALGO, int MODE>
+template <int K, int ALGO, int MODE, bool FUSED = false>
 __device__ __attribute__((always_inline)) inline void long_group(const SweepArgs &a, const Buckets &bk, int64_t L,
                                   uint32_t *keybuf, uint32_t *win, int64_t w) {
   const int lane = lane_id();
@@ -344,7 +366,7 @@ __device__ __attribute__((always_inline)) inline void long_group(const SweepArgs
   const int32_t bi = (ALGO == ALGO_REFINE && active) ? a.bound[i] : 0;
   RegSketch<K, MODE> s;
   s.reset();
-  staged_sketch<K, ALGO, MODE>(a, s, win, i, bi, lo, hi, keybuf);
+  staged_sketch<K, ALGO, MODE, true, FUSED>(a, s, win, i, bi, lo, hi, keybuf);
   s.finalize();
   bool lossy = s.lossy;
 #pragma unroll 1
@@ -533,7 +555,7 @@ __global__ void __launch_bounds__(BLOCK)
 //           stream (no second gather) and the weights, each lane counting its own
 //           chunk, then xor-shuffles inside the row's aligned segment;
 //   lane 0 of the segment decides.
-template <int K, int ALGO, int MODE>
+template <int K, int ALGO, int MODE, bool FUSED = false>
 __device__ __attribute__((always_inline)) inline void row_work(const SweepArgs &a, const Buckets &bk, int64_t L, uint32_t *keybuf,
                                 uint32_t *win, int64_t wave, Counters &ct) {
   const int lane = lane_id();
@@ -557,7 +579,7 @@ __device__ __attribute__((always_inline)) inline void row_work(const SweepArgs &
   const int64_t chi = q < nc ? (clo + L < hi ? clo + L : hi) : clo;
   RegSketch<K, MODE> s;
   s.reset();
-  staged_sketch<K, ALGO, MODE>(a, s, win, i, bi, clo, chi, keybuf);
+  staged_sketch<K, ALGO, MODE, true, FUSED>(a, s, win, i, bi, clo, chi, keybuf);
   s.finalize();
   bool lossy = s.lossy;
   for (int l = 0; l < logp; ++l) {
@@ -677,9 +699,9 @@ __global__ void __launch_bounds__(BLOCK) MGCD_ROWS_OCCUPANCY(K)
         const int64_t wave = c + (j + t) * QLANES;  // wave-uniform
         if (wave >= total) break;
         if (wave < bk.ngroups) {
-          long_group<K, ALGO, MODE>(a, bk, L, keybuf, win, wave);
+          long_group<K, ALGO, MODE, true>(a, bk, L, keybuf, win, wave);
         } else {
-          row_work<K, ALGO, MODE>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
+          row_work<K, ALGO, MODE, true>(a, bk, L, keybuf, win, wave - bk.ngroups, ct);
           if (a.gctr) flush_graph_counters(a, ct);  // the next item's rows may be another graph's
         }
       }
@@ -1018,19 +1040,20 @@ __device__ inline void exact_row_regs(const SweepArgs &a, int32_t i, int32_t bi,
   // its value masked afterwards, so the loads and gathers of all positions are in
   // flight together.
   uint32_t ks[ES], ws[ES];
-  int32_t js[ES], bs[ES];
   const int64_t safe = hi > lo ? lo : 0;
 #pragma unroll
   for (int t = 0; t < ES; ++t) {
     const bool v = lo + t < hi;
     const int64_t e = v ? lo + t : safe;
-    js[t] = a.g.idx[e];
-    bs[t] = bi;
+    const int32_t j = a.g.idx[e];
     ws[t] = a.g.w[e] & (v ? ~0u : 0u);
+    uint32_t c;
+    if (ALGO == ALGO_REFINE)
+      c = a.bound[j] == bi ? (uint32_t)j : EMPTY;
+    else
+      c = (uint32_t)a.C[j];
+    ks[t] = c | ((v && j != i) ? 0u : EMPTY);  // self-loops are skipped
   }
-  neighbour_keys<ALGO, ES>(a, js, bs, ks);
-#pragma unroll
-  for (int t = 0; t < ES; ++t) ks[t] |= (lo + t < hi && js[t] != i) ? 0u : EMPTY;  // self-loops are skipped
   // table keys: the keys themselves, or their slots in the small table (a slot's
   // first key stands for it, K_{i->d} is the sum in d's slot)
   uint32_t ss[ES];

@@ -154,12 +154,19 @@ static Counts read_counts(const unsigned long long *ctr, hipStream_t st) {
   return Counts{h[0], h[1], h[2]};
 }
 
+// grow: a segment that ends with the level still moving is followed by one twice as
+// long.  The callers ask for it on aggregated levels of at most GROW_MAX_N vertices:
+// such a level tends to run on (often to max_it), and there a sweep issued after the
+// rule fired costs a few microseconds of launches and label copies, less than the host
+// round trip it saves.
+constexpr int32_t GROW_MAX_N = 1 << 21;
 template <typename F>
 static LevelState run_sweeps(int max_it, LevelState *ls, hipStream_t st, ClassTimer *ct, mgcd_stats &s,
-                             F &&sweep) {
+                             bool grow, F &&sweep) {
   LevelState h{};
+  int len = SEG;
   for (int it = 0; it < max_it;) {
-    const int seg = max_it - it < SEG ? max_it - it : SEG;
+    const int seg = max_it - it < len ? max_it - it : len;
     for (int j = 0; j < seg; ++j) sweep(it + j, j);
     const uint32_t before = h.sweeps;
     h = read_dev(ls, st);
@@ -167,6 +174,7 @@ static LevelState run_sweeps(int max_it, LevelState *ls, hipStream_t st, ClassTi
       for (uint32_t j = 0; j < h.sweeps - before; ++j) ct->add(s, (int)j);
     it += seg;
     if (h.halt) break;
+    if (grow && !ct) len *= 2;
   }
   return h;
 }
@@ -209,7 +217,7 @@ static void run_lpa(const mgcd_csr *gin, const mgcd_params *p, int32_t *out, Are
   launch_zero_u64(ctr, 4, st);
   launch_zero_state(ls, st);
   if (n > 0) {
-    LevelState h = run_sweeps(p->max_iterations, ls, st, &ct, s, [&](int it, int j) {
+    LevelState h = run_sweeps(p->max_iterations, ls, st, &ct, s, false, [&](int it, int j) {
       SweepArgs args{gs, Ca, nullptr, Ks, nullptr, 0, 0, Cb, nullptr, ctr};
       args.halt = &ls->halt;
       args.one_scan = p->one_scan;
@@ -304,7 +312,8 @@ static void run_levels(bool leiden, const mgcd_csr *gin, const mgcd_params *p, i
     launch_community_totals(Ca, Km, Sig, nl, st);
     launch_zero_u64(ctr, 4, st);
     launch_zero_state(ls, st);
-    LevelState h = run_sweeps(p->max_iterations, ls, st, pass == 0 ? &ct : nullptr, s, [&](int it, int j) {
+    LevelState h = run_sweeps(p->max_iterations, ls, st, pass == 0 ? &ct : nullptr, s,
+                              pass > 0 && nl <= GROW_MAX_N, [&](int it, int j) {
       SweepArgs args{gm, Ca, nullptr, Km, Sig, W, (it % 2 == 0) ? -1 : 1, Cb, nullptr, ctr};
       args.halt = &ls->halt;
       // a level starts from singletons (Leiden after its first: from the refined

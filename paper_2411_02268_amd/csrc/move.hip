@@ -84,18 +84,54 @@ __device__ inline void consider(const SweepArgs &a, int64_t W, int32_t d, int64_
   consider_v<ALGO>(W, d, Ki, Sd, kd, c, kc, sc, true, best, bestG);
 }
 
-// The best of K candidate slots (EMPTY: no candidate): the community totals of all
-// slots are gathered first (an absent slot reads Sigma_d), then scored.
+// The best of K candidate slots (EMPTY: no candidate).  LPA scores the linking weights
+// alone.  Louvain and Leiden also need each candidate's total Sigma_c, a random read.
+// The gain W (k_c - k_d) - K_i (K_i + Sigma_c - Sigma_d) is at most its value at
+// Sigma_c = 0, so the heaviest candidate is scored first, and another candidate's total
+// is read only when that bound can still beat the best so far (or tie it with a lower
+// id); a slot that cannot reads Sigma_d instead (cached; the reads stay branch-free and
+// in flight together) and is not scored.  The best gain only grows, so a skipped slot
+// could neither win nor tie: the result equals scoring every slot.  Returns the number
+// of candidates' totals read.
 template <int K, int ALGO>
-__device__ inline void consider_slots(const SweepArgs &a, int64_t W, int32_t d, int64_t Ki, int64_t Sd,
-                                      uint32_t kd, const uint32_t (&key)[K], const uint32_t (&ex)[K],
-                                      int32_t &best, int64_t &bestG) {
-  uint32_t sc[K];
+__device__ inline int consider_slots(const SweepArgs &a, int64_t W, int32_t d, int64_t Ki, int64_t Sd,
+                                     uint32_t kd, const uint32_t (&key)[K], const uint32_t (&ex)[K],
+                                     int32_t &best, int64_t &bestG) {
+  if constexpr (ALGO == ALGO_LPA) {
 #pragma unroll
-  for (int p = 0; p < K; ++p) sc[p] = ALGO == ALGO_LPA ? 0u : a.Sig[key[p] != EMPTY ? (int32_t)key[p] : d];
+    for (int p = 0; p < K; ++p)
+      consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)key[p], ex[p], 0u, key[p] != EMPTY, best, bestG);
+    return 0;
+  } else {
+    const uint32_t ud = (uint32_t)d;
+    uint32_t c0 = EMPTY, x0 = 0;  // the heaviest candidate other than d (ties: first slot)
 #pragma unroll
-  for (int p = 0; p < K; ++p)
-    consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)key[p], ex[p], sc[p], key[p] != EMPTY, best, bestG);
+    for (int p = 0; p < K; ++p) {
+      const bool take = key[p] != EMPTY && key[p] != ud && (c0 == EMPTY || ex[p] > x0);
+      c0 = take ? key[p] : c0;
+      x0 = take ? ex[p] : x0;
+    }
+    const uint32_t s0 = a.Sig[c0 != EMPTY ? (int32_t)c0 : d];
+    consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)c0, x0, s0, c0 != EMPTY, best, bestG);
+    const int64_t rest = Sd - Ki;  // Sigma_d without i: U(c) = W (k_c - k_d) + K_i (Sigma_d - K_i)
+    bool live[K];
+    uint32_t sc[K];
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      const int64_t U = W * ((int64_t)ex[p] - (int64_t)kd) + Ki * rest;
+      const int32_t c = (int32_t)key[p];
+      live[p] = key[p] != EMPTY && key[p] != ud && key[p] != c0 && U > 0 &&
+                (best < 0 || U > bestG || (U == bestG && c < best));
+      sc[p] = a.Sig[live[p] ? c : d];
+    }
+    int reads = c0 != EMPTY;
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      consider_v<ALGO>(W, d, Ki, Sd, kd, (int32_t)key[p], ex[p], sc[p], live[p], best, bestG);
+      reads += live[p];
+    }
+    return reads;
+  }
 }
 
 template <int ALGO>
@@ -654,11 +690,7 @@ __device__ __attribute__((always_inline)) inline void row_work(const SweepArgs &
     const int64_t W = ALGO == ALGO_LPA ? 0 : (int64_t)weight_of(a, i);
     const int64_t Ki = ALGO == ALGO_LPA ? 0 : (int64_t)a.K[i];
     const int64_t Sd = ALGO == ALGO_LPA ? 0 : (int64_t)a.Sig[d];
-    consider_slots<K, ALGO>(a, W, d, Ki, Sd, kd, key, ex, best, bestG);
-    if (ALGO != ALGO_LPA) {
-#pragma unroll
-      for (int p = 0; p < K; ++p) ct.cand += key[p] != EMPTY && key[p] != (uint32_t)d;
-    }
+    ct.cand += consider_slots<K, ALGO>(a, W, d, Ki, Sd, kd, key, ex, best, bestG);
     finish<ALGO>(a, i, d, best, bestG, ct);
   }
 }

@@ -39,9 +39,9 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 # kernel sources it was taken on (the SHA-256 of TRAFFIC_SOURCES beside it, checked at
 # run time); traffic is reported as null when the sources differ.
 TRAFFIC_BYTES = {
-    ("louvain-mg-k8-rmat20", False, 0): (2276408832, "78056ebed55c302164b2dc6d1506ab0e7373f973f53c5418a6fdaf607d7a562b"),
-    ("leiden-mg-k16-cl24", False, 0): (91126146016, "78056ebed55c302164b2dc6d1506ab0e7373f973f53c5418a6fdaf607d7a562b"),
-    ("leiden-mg-k16-cl24", True, 0): (80244325168, "78056ebed55c302164b2dc6d1506ab0e7373f973f53c5418a6fdaf607d7a562b"),
+    ("louvain-mg-k8-rmat20", False, 0): (2223564784, "14135e926398dd07a7f2c1975aa01f1d5d0505a6324d9e01db2eb465472917e9"),
+    ("leiden-mg-k16-cl24", False, 0): (79392629096, "14135e926398dd07a7f2c1975aa01f1d5d0505a6324d9e01db2eb465472917e9"),
+    ("leiden-mg-k16-cl24", True, 0): (67723806128, "14135e926398dd07a7f2c1975aa01f1d5d0505a6324d9e01db2eb465472917e9"),
 }
 TRAFFIC_SOURCES = ["csrc/move.hip", "csrc/move.hpp", "csrc/sketch.hpp", "csrc/common.hpp", "csrc/staging.hpp"]
 

@@ -201,7 +201,7 @@ def batched_leg(mg, torch, count: int, nmax: float, workers: int):
     sample = dgs[:: max(1, count // 32)][:32]
     out = {"graphs": count, "n": N, "nnz": E, "nmax": nmax}
     for name, algo, fn in (("lpa", mg.ALGO_LPA, mg.lpa), ("louvain", mg.ALGO_LOUVAIN, mg.louvain)):
-        tuned = autotune.tune(mg, sample, algo, repeats=1, batched=True)
+        tuned = autotune.tune(mg, sample, algo, repeats=3, batched=True)  # median of 3 per config
         kw = autotune.run_kwargs(tuned)
         mg.run_batched(algo, dgs, **kw)  # warm-up
         torch.cuda.synchronize()
